@@ -1,0 +1,501 @@
+/*
+ * k-clique densest subgraph search -- CPU ORACLE (test infrastructure only).
+ *
+ * This file is the plain, slow, obviously correct definition of what the
+ * GPU path computes.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it; no product code links it or calls it.  It shares
+ * no source with the GPU library: it never builds a clique tree and enumerates
+ * every k-clique explicitly.
+ *
+ * What it computes (paper: Sec. 2 "Convex programming CP(G)" and Algorithm 1,
+ * the Frank-Wolfe framework; Sec. 3.2 Algorithm 2 for the iteration/extraction
+ * skeleton):
+ *
+ *   r_0 = r0 (zero by default)
+ *   for t = 1..T (synchronous: every clique reads r_{t-1}):
+ *       d_t(u) = #{ C in C_k(V) : u = argmin_{v in C} (r_{t-1}(v), v) }
+ *       r_t    = r_{t-1} + d_t
+ *   pi  = nodes sorted by r_T non-increasing, ties by ascending id
+ *   K_i = |C_k(pi[0..i))|,  i* = the largest i maximising K_i / i
+ *   result: loads r_T, density K_{i*}/i*, node set pi[0..i*),
+ *           upper bound max_u (r_T(u) - r0(u)) / T.
+ *
+ * Readings of points the paper leaves open (argmin ties go to the lowest id
+ * where Algorithm 1 says "break ties arbitrarily"; synchronous updates; sort
+ * direction and the largest-prefix tie rule from Definition 1) are listed with
+ * their reasons in the design notes.  Loads are kept as unsigned 128-bit
+ * integers so nothing here can overflow for any graph it can enumerate.
+ *
+ * Pins: the test suite checks this oracle against the paper's printed example
+ * (Example 1: 9 triangles on 7 nodes, density 9/7, densest set {u1..u6} at
+ * 4/3; Example 2's clique tree determines the graph), closed forms on complete
+ * and disjoint-union graphs, Lemma 6 (sum of loads equals t * |C_k|), the
+ * bound density <= rho* <= upper bound from brute force over all subsets on
+ * graphs of at most 14 nodes, and a brute-force Frank-Wolfe over all k-subsets.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef unsigned __int128 u128;
+
+enum {
+    KOR_OK = 0,
+    KOR_EINVAL = -1,      /* bad argument (k < 2, T == 0 for solve, null pointer) */
+    KOR_EGRAPH = -2,      /* CSR is not a simple undirected graph */
+    KOR_ENOMEM = -7,
+};
+
+typedef struct {
+    uint32_t n;
+    const uint64_t *row_ptr;
+    const uint32_t *col;
+} graph_t;
+
+typedef struct {
+    uint64_t c_k_lo, c_k_hi;      /* |C_k(V)| */
+    uint32_t T;                   /* iterations run */
+    uint32_t size;                /* i* */
+    uint64_t dens_num;            /* K_{i*} */
+    uint64_t ub_num_lo, ub_num_hi;/* max (r_T - r0); denominator T */
+    double enum_seconds;          /* listing all k-cliques once */
+    double iter_seconds;          /* the T Frank-Wolfe iterations */
+    double extract_seconds;       /* final extraction */
+    int threads;                  /* OpenMP threads used */
+    int streamed;                 /* 1 if cliques were re-listed each iteration */
+} kor_result;
+
+typedef struct {                  /* one row per iteration when a trace is asked for */
+    uint32_t t, size;
+    uint64_t dens_num;
+    uint64_t ub_num_lo, ub_num_hi;
+} kor_trace_row;
+
+static double now_s(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* ---- graph validation: simple, undirected, rows sorted (Sec. 2 problem statement) ---- */
+
+static int has_edge(const graph_t *g, uint32_t u, uint32_t v) {
+    uint64_t lo = g->row_ptr[u], hi = g->row_ptr[u + 1];
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (g->col[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo < g->row_ptr[u + 1] && g->col[lo] == v;
+}
+
+int kor_validate(uint32_t n, uint64_t nnz, const uint64_t *row_ptr, const uint32_t *col) {
+    if (!row_ptr || (nnz && !col)) return KOR_EINVAL;
+    if (row_ptr[0] != 0 || row_ptr[n] != nnz) return KOR_EGRAPH;
+    graph_t g = {n, row_ptr, col};
+    for (uint32_t u = 0; u < n; ++u) {
+        if (row_ptr[u + 1] < row_ptr[u]) return KOR_EGRAPH;
+        for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            uint32_t v = col[e];
+            if (v >= n || v == u) return KOR_EGRAPH;                 /* range, self-loop */
+            if (e > row_ptr[u] && col[e - 1] >= v) return KOR_EGRAPH; /* unsorted or repeated */
+            if (!has_edge(&g, v, u)) return KOR_EGRAPH;               /* asymmetric */
+        }
+    }
+    return KOR_OK;
+}
+
+/* ---- k-clique listing: every clique once, as ids c[0] < c[1] < ... < c[k-1] ---- */
+
+typedef void (*clique_fn)(const uint32_t *c, int k, void *ctx);
+
+typedef struct {
+    const graph_t *g;
+    int k;
+    uint32_t *clique;     /* k entries */
+    uint32_t *cand;       /* k levels x maxdeg */
+    uint64_t maxdeg;
+    clique_fn fn;
+    void *ctx;
+} lister_t;
+
+/* cand (ncand ids, ascending) are the common neighbours of clique[0..depth)
+ * that exceed clique[depth-1].  Extend by each of them in turn. */
+static void list_rec(lister_t *L, int depth, const uint32_t *cand, uint64_t ncand) {
+    for (uint64_t i = 0; i < ncand; ++i) {
+        uint32_t v = cand[i];
+        L->clique[depth] = v;
+        if (depth + 1 == L->k) {
+            L->fn(L->clique, L->k, L->ctx);
+            continue;
+        }
+        /* next = cand[i+1..] intersected with N(v) */
+        uint32_t *next = L->cand + (uint64_t)(depth + 1) * L->maxdeg;
+        uint64_t nn = 0;
+        uint64_t a = i + 1, b = L->g->row_ptr[v], be = L->g->row_ptr[v + 1];
+        while (a < ncand && b < be) {
+            uint32_t x = cand[a], y = L->g->col[b];
+            if (x < y) ++a;
+            else if (y < x) ++b;
+            else { next[nn++] = x; ++a; ++b; }
+        }
+        if ((uint64_t)(depth + 1) + nn >= (uint64_t)L->k) list_rec(L, depth + 1, next, nn);
+    }
+}
+
+static uint64_t max_degree(const graph_t *g) {
+    uint64_t d = 0;
+    for (uint32_t u = 0; u < g->n; ++u) {
+        uint64_t x = g->row_ptr[u + 1] - g->row_ptr[u];
+        if (x > d) d = x;
+    }
+    return d;
+}
+
+/* List every k-clique whose smallest id is u. */
+static void list_from(lister_t *L, uint32_t u) {
+    const graph_t *g = L->g;
+    uint64_t b = g->row_ptr[u], e = g->row_ptr[u + 1];
+    while (b < e && g->col[b] < u) ++b;      /* neighbours greater than u */
+    L->clique[0] = u;
+    if ((uint64_t)1 + (e - b) >= (uint64_t)L->k) list_rec(L, 1, g->col + b, e - b);
+}
+
+static int lister_init(lister_t *L, const graph_t *g, int k, clique_fn fn, void *ctx, uint64_t maxdeg) {
+    L->g = g; L->k = k; L->fn = fn; L->ctx = ctx; L->maxdeg = maxdeg ? maxdeg : 1;
+    L->clique = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)k);
+    L->cand = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)k * (size_t)L->maxdeg);
+    return (L->clique && L->cand) ? KOR_OK : KOR_ENOMEM;
+}
+
+static void lister_free(lister_t *L) { free(L->clique); free(L->cand); }
+
+/* ---- counting and explicit listing (used by tests of the clique tree) ---- */
+
+static void count_fn(const uint32_t *c, int k, void *ctx) { (void)c; (void)k; ++*(uint64_t *)ctx; }
+
+static int set_threads(int threads) {
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+    return omp_get_max_threads();
+#else
+    (void)threads;
+    return 1;
+#endif
+}
+
+int kor_count(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k, int threads,
+              uint64_t *count_lo, uint64_t *count_hi) {
+    if (k < 1 || !row_ptr || !count_lo || !count_hi) return KOR_EINVAL;
+    graph_t g = {n, row_ptr, col};
+    uint64_t maxdeg = max_degree(&g);
+    u128 total = 0;
+    int err = KOR_OK;
+    set_threads(threads);
+    if (k == 1) { *count_lo = n; *count_hi = 0; return KOR_OK; }
+#pragma omp parallel reduction(+ : total)
+    {
+        lister_t L;
+        uint64_t local = 0;
+        if (lister_init(&L, &g, k, count_fn, &local, maxdeg) != KOR_OK) {
+#pragma omp atomic write
+            err = KOR_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t u = 0; u < (int64_t)n; ++u) {
+                list_from(&L, (uint32_t)u);
+                total += local;
+                local = 0;
+            }
+        }
+        lister_free(&L);
+    }
+    *count_lo = (uint64_t)total;
+    *count_hi = (uint64_t)(total >> 64);
+    return err;
+}
+
+typedef struct { uint32_t *out; uint64_t cap, used; } fill_ctx;
+
+static void fill_fn(const uint32_t *c, int k, void *ctx) {
+    fill_ctx *f = (fill_ctx *)ctx;
+    if (f->used < f->cap) memcpy(f->out + f->used * (uint64_t)k, c, sizeof(uint32_t) * (size_t)k);
+    ++f->used;
+}
+
+/* Write all k-cliques (sorted ids, lexicographic order) into out[cap * k].
+ * *count receives the total; KOR_ENOMEM if it exceeds cap. Single-threaded. */
+int kor_list(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k,
+             uint32_t *out, uint64_t cap, uint64_t *count) {
+    if (k < 2 || !row_ptr || !count) return KOR_EINVAL;
+    graph_t g = {n, row_ptr, col};
+    fill_ctx f = {out, cap, 0};
+    lister_t L;
+    if (lister_init(&L, &g, k, fill_fn, &f, max_degree(&g)) != KOR_OK) { lister_free(&L); return KOR_ENOMEM; }
+    for (uint32_t u = 0; u < n; ++u) list_from(&L, u);
+    lister_free(&L);
+    *count = f.used;
+    return f.used <= cap ? KOR_OK : KOR_ENOMEM;
+}
+
+/* ---- synchronous Frank-Wolfe (Alg. 1, FW-2: each clique credits its minimum-load node) ---- */
+
+typedef struct { const u128 *r; uint64_t *delta; } fw_ctx;
+
+/* Ids in c are ascending, so a strict '<' keeps the lowest id among equal loads. */
+static uint32_t argmin_load(const uint32_t *c, int k, const u128 *r) {
+    uint32_t best = c[0];
+    for (int i = 1; i < k; ++i)
+        if (r[c[i]] < r[best]) best = c[i];
+    return best;
+}
+
+static void fw_fn(const uint32_t *c, int k, void *ctx) {
+    fw_ctx *f = (fw_ctx *)ctx;
+    f->delta[argmin_load(c, k, f->r)] += 1;
+}
+
+/* ---- extraction (Alg. 1 / Alg. 2 tail: sort by load, best prefix density) ---- */
+
+static const u128 *g_sort_r;   /* qsort has no context argument; the sort is single-threaded */
+
+static int cmp_desc_load(const void *a, const void *b) {
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    if (g_sort_r[x] != g_sort_r[y]) return g_sort_r[x] > g_sort_r[y] ? -1 : 1;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+typedef struct { const uint32_t *pos; uint64_t *hist; } pre_ctx;
+
+static void prefix_fn(const uint32_t *c, int k, void *ctx) {
+    pre_ctx *p = (pre_ctx *)ctx;
+    uint32_t last = 0;
+    for (int i = 0; i < k; ++i)
+        if (p->pos[c[i]] > last) last = p->pos[c[i]];
+    p->hist[last] += 1;   /* the clique lies in every prefix V_i with i > last */
+}
+
+typedef struct {
+    const graph_t *g;
+    int k;
+    int stored;
+    uint32_t *cliques;    /* c_k * k ids when stored */
+    uint64_t nclq;
+    uint64_t maxdeg;
+    int nthreads;
+} run_t;
+
+/* Apply fn with per-thread context ctxs[thread] to every k-clique. */
+static int for_each_clique(run_t *R, clique_fn fn, void **ctxs) {
+    int err = KOR_OK;
+    if (R->stored) {
+#pragma omp parallel
+        {
+#ifdef _OPENMP
+            void *ctx = ctxs[omp_get_thread_num()];
+#else
+            void *ctx = ctxs[0];
+#endif
+#pragma omp for schedule(static)
+            for (int64_t i = 0; i < (int64_t)R->nclq; ++i)
+                fn(R->cliques + (uint64_t)i * (uint64_t)R->k, R->k, ctx);
+        }
+        return KOR_OK;
+    }
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+        void *ctx = ctxs[omp_get_thread_num()];
+#else
+        void *ctx = ctxs[0];
+#endif
+        lister_t L;
+        if (lister_init(&L, R->g, R->k, fn, ctx, R->maxdeg) != KOR_OK) {
+#pragma omp atomic write
+            err = KOR_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t u = 0; u < (int64_t)R->g->n; ++u) list_from(&L, (uint32_t)u);
+        }
+        lister_free(&L);
+    }
+    return err;
+}
+
+/* Extraction on loads r: writes order[n], returns (i*, K_{i*}). */
+static int extract(run_t *R, const u128 *r, uint32_t *order, uint32_t *size, uint64_t *dens_num,
+                   uint64_t **hist_t, uint32_t *pos) {
+    uint32_t n = R->g->n;
+    for (uint32_t i = 0; i < n; ++i) order[i] = i;
+    g_sort_r = r;
+    qsort(order, n, sizeof(uint32_t), cmp_desc_load);
+    for (uint32_t i = 0; i < n; ++i) pos[order[i]] = i;
+
+    void *ctxs[1024];
+    pre_ctx pc[1024];
+    for (int t = 0; t < R->nthreads; ++t) {
+        memset(hist_t[t], 0, sizeof(uint64_t) * (size_t)n);
+        pc[t].pos = pos;
+        pc[t].hist = hist_t[t];
+        ctxs[t] = &pc[t];
+    }
+    int err = for_each_clique(R, prefix_fn, ctxs);
+    if (err) return err;
+
+    /* K_i = number of cliques inside the first i nodes; best ratio, ties -> larger i */
+    uint64_t K = 0, bestK = 0;
+    uint32_t best_i = 0;
+    for (uint32_t i = 1; i <= n; ++i) {
+        for (int t = 0; t < R->nthreads; ++t) K += hist_t[t][i - 1];
+        if (K == 0) continue;
+        if (best_i == 0 || (u128)K * best_i >= (u128)bestK * i) { bestK = K; best_i = i; }
+    }
+    *size = best_i;
+    *dens_num = bestK;
+    return KOR_OK;
+}
+
+static u128 upper_bound_num(const u128 *r, const uint64_t *r0, uint32_t n) {
+    u128 best = 0;
+    for (uint32_t u = 0; u < n; ++u) {
+        u128 x = r[u] - (r0 ? (u128)r0[u] : 0);
+        if (x > best) best = x;
+    }
+    return best;
+}
+
+/*
+ * Full solve.  r_out_lo / r_out_hi receive the low and high 64 bits of r_T,
+ * order_out the extraction order pi (its first result->size entries are the
+ * node set).  trace (nullable) receives T rows: the extraction after every
+ * iteration.  max_store_bytes bounds the memory used to keep the clique list;
+ * above it cliques are listed again on every pass.
+ */
+int kor_solve(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k, uint32_t T,
+              const uint64_t *r0, int threads, uint64_t max_store_bytes,
+              uint64_t *r_out_lo, uint64_t *r_out_hi, uint32_t *order_out,
+              kor_result *res, kor_trace_row *trace) {
+    if (k < 2 || T == 0 || !row_ptr || !r_out_lo || !r_out_hi || !order_out || !res) return KOR_EINVAL;
+    memset(res, 0, sizeof(*res));
+    graph_t g = {n, row_ptr, col};
+    run_t R;
+    memset(&R, 0, sizeof(R));
+    R.g = &g;
+    R.k = k;
+    R.maxdeg = max_degree(&g);
+    R.nthreads = set_threads(threads);
+    if (R.nthreads > 1024) return KOR_EINVAL;
+    res->threads = R.nthreads;
+    int err = KOR_OK;
+
+    double t0 = now_s();
+    uint64_t c_lo = 0, c_hi = 0;
+    err = kor_count(n, row_ptr, col, k, threads, &c_lo, &c_hi);
+    if (err) return err;
+    u128 c_k = ((u128)c_hi << 64) | c_lo;
+    res->c_k_lo = c_lo;
+    res->c_k_hi = c_hi;
+    if (c_hi == 0 && c_lo * (u128)k * 4u <= (u128)max_store_bytes) {
+        R.stored = 1;
+        R.nclq = c_lo;
+        R.cliques = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(c_lo ? c_lo : 1) * (size_t)k);
+        if (!R.cliques) return KOR_ENOMEM;
+        uint64_t got = 0;
+        err = kor_list(n, row_ptr, col, k, R.cliques, c_lo, &got);
+        if (err || got != c_lo) { free(R.cliques); return err ? err : KOR_EGRAPH; }
+    }
+    res->streamed = !R.stored;
+    res->enum_seconds = now_s() - t0;
+
+    u128 *r = (u128 *)malloc(sizeof(u128) * (size_t)(n ? n : 1));
+    uint64_t **delta_t = (uint64_t **)calloc((size_t)R.nthreads, sizeof(uint64_t *));
+    uint32_t *pos = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    int ok = r && delta_t && pos;
+    for (int t = 0; ok && t < R.nthreads; ++t) {
+        delta_t[t] = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+        ok = delta_t[t] != NULL;
+    }
+    if (!ok) { err = KOR_ENOMEM; goto done; }
+    for (uint32_t u = 0; u < n; ++u) r[u] = r0 ? (u128)r0[u] : 0;
+
+    double t1 = now_s(), t_extract_in_loop = 0.0;
+    for (uint32_t it = 1; it <= T; ++it) {
+        void *ctxs[1024];
+        fw_ctx fc[1024];
+        for (int t = 0; t < R.nthreads; ++t) {
+            memset(delta_t[t], 0, sizeof(uint64_t) * (size_t)n);
+            fc[t].r = r;
+            fc[t].delta = delta_t[t];
+            ctxs[t] = &fc[t];
+        }
+        err = for_each_clique(&R, fw_fn, ctxs);     /* every clique reads r_{t-1} */
+        if (err) goto done;
+        for (uint32_t u = 0; u < n; ++u)            /* then r_t = r_{t-1} + d_t */
+            for (int t = 0; t < R.nthreads; ++t) r[u] += delta_t[t][u];
+        if (trace) {
+            double te = now_s();
+            kor_trace_row *row = &trace[it - 1];
+            row->t = it;
+            err = extract(&R, r, order_out, &row->size, &row->dens_num, delta_t, pos);
+            if (err) goto done;
+            u128 ub = upper_bound_num(r, r0, n);
+            row->ub_num_lo = (uint64_t)ub;
+            row->ub_num_hi = (uint64_t)(ub >> 64);
+            t_extract_in_loop += now_s() - te;
+        }
+    }
+    res->iter_seconds = now_s() - t1 - t_extract_in_loop;
+
+    double t2 = now_s();
+    res->T = T;
+    if (c_k == 0) {
+        for (uint32_t i = 0; i < n; ++i) order_out[i] = i;
+        g_sort_r = r;
+        qsort(order_out, n, sizeof(uint32_t), cmp_desc_load);
+        res->size = 0;
+        res->dens_num = 0;
+    } else {
+        err = extract(&R, r, order_out, &res->size, &res->dens_num, delta_t, pos);
+        if (err) goto done;
+    }
+    u128 ub = upper_bound_num(r, r0, n);
+    res->ub_num_lo = (uint64_t)ub;
+    res->ub_num_hi = (uint64_t)(ub >> 64);
+    res->extract_seconds = now_s() - t2;
+    for (uint32_t u = 0; u < n; ++u) {
+        r_out_lo[u] = (uint64_t)r[u];
+        r_out_hi[u] = (uint64_t)(r[u] >> 64);
+    }
+
+done:
+    if (delta_t)
+        for (int t = 0; t < R.nthreads; ++t) free(delta_t[t]);
+    free(delta_t);
+    free(pos);
+    free(r);
+    free(R.cliques);
+    return err;
+}
+
+/* Frank-Wolfe credits of one iteration from loads r (u64), for tests of the first step. */
+int kor_credits(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k,
+                const uint64_t *r, uint64_t *d_out) {
+    if (k < 2 || !row_ptr || !r || !d_out) return KOR_EINVAL;
+    graph_t g = {n, row_ptr, col};
+    u128 *rr = (u128 *)malloc(sizeof(u128) * (size_t)(n ? n : 1));
+    if (!rr) return KOR_ENOMEM;
+    for (uint32_t u = 0; u < n; ++u) { rr[u] = r[u]; d_out[u] = 0; }
+    fw_ctx fc = {rr, d_out};
+    lister_t L;
+    int err = lister_init(&L, &g, k, fw_fn, &fc, max_degree(&g));
+    if (!err)
+        for (uint32_t u = 0; u < n; ++u) list_from(&L, u);
+    lister_free(&L);
+    free(rr);
+    return err;
+}
+
+int kor_threads(int threads) { return set_threads(threads); }

@@ -1,0 +1,153 @@
+"""Python access to the CPU oracle (test infrastructure only).
+
+The oracle lists every k-clique explicitly and runs synchronous Frank-Wolfe on
+the convex program CP(G) (paper Sec. 2, Algorithm 1), then extracts the best
+prefix by k-clique density (Algorithm 2's final steps).  It is the yardstick of
+the GPU path and is loaded only by tests, the smoke check and the benchmark's
+CPU-baseline leg.  It imports nothing from the GPU package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "kdss_oracle.c")
+LIB = os.path.join(HERE, "libkdss_oracle.so")
+
+
+class Result(C.Structure):
+    _fields_ = [("c_k_lo", C.c_uint64), ("c_k_hi", C.c_uint64), ("T", C.c_uint32),
+                ("size", C.c_uint32), ("dens_num", C.c_uint64), ("ub_num_lo", C.c_uint64),
+                ("ub_num_hi", C.c_uint64), ("enum_seconds", C.c_double),
+                ("iter_seconds", C.c_double), ("extract_seconds", C.c_double),
+                ("threads", C.c_int), ("streamed", C.c_int)]
+
+
+class TraceRow(C.Structure):
+    _fields_ = [("t", C.c_uint32), ("size", C.c_uint32), ("dens_num", C.c_uint64),
+                ("ub_num_lo", C.c_uint64), ("ub_num_hi", C.c_uint64)]
+
+
+def build(force: bool = False, src: str = SRC, out: str = LIB) -> str:
+    """Compile the oracle (or a copy of its source) with gcc: plain C, OpenMP."""
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wextra", "-o", tmp, src])
+        os.replace(tmp, out)
+    return out
+
+
+_libs = {}
+
+
+def lib(path: str | None = None):
+    """The oracle library at ``path`` (default: the built oracle)."""
+    path = path or LIB
+    if path not in _libs:
+        if path == LIB and not os.path.exists(LIB):
+            build()
+        L = C.CDLL(path)
+        p64 = C.POINTER(C.c_uint64)
+        p32 = C.POINTER(C.c_uint32)
+        L.kor_validate.argtypes = [C.c_uint32, C.c_uint64, p64, p32]
+        L.kor_count.argtypes = [C.c_uint32, p64, p32, C.c_int, C.c_int, p64, p64]
+        L.kor_list.argtypes = [C.c_uint32, p64, p32, C.c_int, p32, C.c_uint64, p64]
+        L.kor_solve.argtypes = [C.c_uint32, p64, p32, C.c_int, C.c_uint32, p64, C.c_int,
+                                C.c_uint64, p64, p64, p32, C.POINTER(Result),
+                                C.POINTER(TraceRow)]
+        L.kor_credits.argtypes = [C.c_uint32, p64, p32, C.c_int, p64, p64]
+        L.kor_threads.argtypes = [C.c_int]
+        _libs[path] = L
+    return _libs[path]
+
+
+def _p64(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint64)) if a is not None else None
+
+
+def _p32(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint32)) if a is not None else None
+
+
+def _csr(row_ptr, col):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.uint64)
+    cl = np.ascontiguousarray(col, dtype=np.uint32)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.uint32)
+    return rp, cl
+
+
+def validate(n, row_ptr, col, libpath=None) -> int:
+    rp, cl = _csr(row_ptr, col)
+    return lib(libpath).kor_validate(n, int(rp[n]) if rp.size > n else 0, _p64(rp), _p32(cl))
+
+
+def count(n, row_ptr, col, k, threads=0, libpath=None) -> int:
+    rp, cl = _csr(row_ptr, col)
+    lo, hi = C.c_uint64(0), C.c_uint64(0)
+    err = lib(libpath).kor_count(n, _p64(rp), _p32(cl), k, threads, C.byref(lo), C.byref(hi))
+    if err:
+        raise RuntimeError(f"kor_count failed: {err}")
+    return (hi.value << 64) | lo.value
+
+
+def list_cliques(n, row_ptr, col, k, libpath=None) -> np.ndarray:
+    """All k-cliques as rows of ascending ids (lexicographic order)."""
+    c = count(n, row_ptr, col, k, libpath=libpath)
+    rp, cl = _csr(row_ptr, col)
+    out = np.zeros(max(c, 1) * k, dtype=np.uint32)
+    got = C.c_uint64(0)
+    err = lib(libpath).kor_list(n, _p64(rp), _p32(cl), k, _p32(out), c, C.byref(got))
+    if err:
+        raise RuntimeError(f"kor_list failed: {err}")
+    return out[: c * k].reshape(c, k)
+
+
+def credits(n, row_ptr, col, k, r, libpath=None) -> np.ndarray:
+    """Frank-Wolfe credits d(u) of one synchronous iteration at loads r."""
+    rp, cl = _csr(row_ptr, col)
+    rr = np.ascontiguousarray(r, dtype=np.uint64)
+    d = np.zeros(max(n, 1), dtype=np.uint64)
+    err = lib(libpath).kor_credits(n, _p64(rp), _p32(cl), k, _p64(rr), _p64(d))
+    if err:
+        raise RuntimeError(f"kor_credits failed: {err}")
+    return d[:n]
+
+
+def solve(n, row_ptr, col, k, T, r0=None, trace=False, threads=0,
+          max_store_bytes=8 << 30, libpath=None) -> dict:
+    """Synchronous Frank-Wolfe + extraction.  Returns a dict with
+    r (uint64 when every load fits, else Python ints), order (uint32[n]),
+    size (i*), dens_num (K_{i*}), ub_num (max r_T - r0), T, c_k, timings and,
+    when asked, the per-iteration trace."""
+    rp, cl = _csr(row_ptr, col)
+    nn = max(n, 1)
+    r_lo = np.zeros(nn, dtype=np.uint64)
+    r_hi = np.zeros(nn, dtype=np.uint64)
+    order = np.zeros(nn, dtype=np.uint32)
+    r0a = None if r0 is None else np.ascontiguousarray(r0, dtype=np.uint64)
+    res = Result()
+    rows = (TraceRow * T)() if trace else None
+    err = lib(libpath).kor_solve(n, _p64(rp), _p32(cl), k, T, _p64(r0a), threads, max_store_bytes,
+                          _p64(r_lo), _p64(r_hi), _p32(order), C.byref(res),
+                          C.cast(rows, C.POINTER(TraceRow)) if trace else None)
+    if err:
+        raise RuntimeError(f"kor_solve failed: {err}")
+    if np.any(r_hi[:n]):
+        r = [(int(h) << 64) | int(l) for l, h in zip(r_lo[:n], r_hi[:n])]
+    else:
+        r = r_lo[:n].copy()
+    out = dict(r=r, order=order[:n].copy(), size=res.size, dens_num=res.dens_num,
+               ub_num=(res.ub_num_hi << 64) | res.ub_num_lo, T=res.T,
+               c_k=(res.c_k_hi << 64) | res.c_k_lo, enum_seconds=res.enum_seconds,
+               iter_seconds=res.iter_seconds, extract_seconds=res.extract_seconds,
+               threads=res.threads, streamed=bool(res.streamed))
+    if trace:
+        out["trace"] = [dict(t=rw.t, size=rw.size, dens_num=rw.dens_num,
+                             ub_num=(rw.ub_num_hi << 64) | rw.ub_num_lo) for rw in rows]
+    return out
