@@ -1,0 +1,208 @@
+/*
+ * kdss -- k-clique densest subgraph search on MI355X (gfx950).
+ *
+ * The library runs the hot path of PSCTL (paper: Sec. 3, Algorithm 2) with the
+ * Frank-Wolfe step of the convex program CP(G) (Sec. 2, Algorithm 1), batched
+ * through the succinct clique tree (SCT, Sec. 2, Lemmas 3-5):
+ *
+ *   1. build the k-pruned SCT of the graph on the host (timed separately);
+ *   2. T synchronous Frank-Wolfe iterations on the GPU: every leaf (hold set H,
+ *      pivot set P) credits each member u with the exact number of the leaf's
+ *      k-cliques whose minimum-load member is u (loads compared as (r(u), id(u)),
+ *      lower id first on equal loads), and the credits are added to r;
+ *   3. order the nodes by r non-increasing (ties: lower id first), count the
+ *      k-cliques inside every prefix, and return the prefix with the highest
+ *      k-clique density |C_k(S)|/|S| (Sec. 2), the longest one on ties.
+ *
+ * Every count is an exact integer; results do not depend on the SCT's shape
+ * or on the order in which leaves are processed.
+ *
+ * Conventions for every entry point:
+ *  - Return value: KDSS_OK (0) or a negative status below; kdss_last_error()
+ *    then gives a thread-local message.  No call aborts or throws.
+ *  - Host pointers are marked "host", device pointers "device".  The caller
+ *    owns every buffer it passes; the library owns only the opaque handles it
+ *    returns, which *_free releases (NULL is accepted).
+ *  - The library allocates no device memory: the caller passes one device
+ *    workspace of the size kdss_plan_info() reports.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *    enqueued on it in order; a call that fills a host result synchronises
+ *    that stream before returning.
+ *  - Handles are not safe for concurrent use from several threads.
+ *  - Node ids are 32-bit; loads are u64, or u128 (two u64 per node: low word
+ *    first) when a run could exceed 2^64 - 1.
+ */
+#ifndef KDSS_H
+#define KDSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KDSS_OK 0
+#define KDSS_EINVAL (-1)      /* bad argument: null pointer, k < 2, T == 0, ... */
+#define KDSS_EGRAPH (-2)      /* the CSR is not a simple undirected graph      */
+#define KDSS_ERANGE (-3)      /* a size exceeds a documented limit            */
+#define KDSS_EOVERFLOW (-4)   /* an exact count would not fit its integer     */
+#define KDSS_EWORKSPACE (-5)  /* workspace too small or not the uploaded one  */
+#define KDSS_EHIP (-6)        /* a HIP runtime call failed                    */
+#define KDSS_ENOMEM (-7)      /* host allocation failed                       */
+#define KDSS_EUNSUPPORTED (-8)/* a case this build does not handle            */
+
+typedef struct kdss_sct kdss_sct;     /* host clique tree (owned by the library) */
+typedef struct kdss_plan kdss_plan;   /* device layout of one tree               */
+
+/* Simple undirected graph G(V, E) (Sec. 2): n nodes, symmetric adjacency with
+ * rows sorted ascending, no self-loops, no repeated neighbours.  Host arrays:
+ * row_ptr[n + 1] (row_ptr[0] = 0, row_ptr[n] = nnz = 2|E|), col[nnz]. */
+typedef struct {
+    uint32_t n;
+    uint64_t nnz;
+    const uint64_t *row_ptr;
+    const uint32_t *col;
+} kdss_csr;
+
+typedef struct { uint64_t lo, hi; } kdss_u128;
+
+typedef struct {
+    uint32_t k, n;
+    uint64_t leaves;          /* |P_k|: leaves with h <= k <= h + p (Lemma 4)   */
+    uint64_t members;         /* sum over those leaves of h + p                 */
+    uint32_t s_max;           /* largest h + p                                  */
+    uint32_t degeneracy;      /* delta of Sec. 2                                */
+    kdss_u128 c_k;            /* |C_k(V)| = sum of C(p, k - h) (Lemma 5)        */
+    double build_seconds;     /* host SCT construction, wall clock              */
+} kdss_tree_stats;
+
+typedef struct {
+    int width;                /* 0: choose; 64 or 128: force the load width     */
+    int use_graph;            /* 1: replay the iterations as a hipGraph         */
+    uint32_t extract_every;   /* 0: extract after iteration T only; e > 0: also
+                                 after every e-th iteration, into the trace     */
+    int time_kernels;         /* 1: bracket every leaf-credit and load-update
+                                 launch of kdss_run with hipEvents (plain
+                                 launches, no graph); see kdss_plan_timing    */
+} kdss_opts;
+
+typedef struct {              /* accumulated by kdss_run when time_kernels = 1  */
+    uint64_t leaf_launches;   /* Frank-Wolfe leaf-credit launches timed         */
+    double leaf_ms;           /* their summed durations (hipEvent elapsed time) */
+    uint64_t apply_launches;
+    double apply_ms;
+} kdss_timing;
+
+typedef struct {
+    uint64_t workspace_bytes; /* device workspace that kdss_plan_upload/run need */
+    uint64_t stream_bytes;    /* leaf stream: members + headers + tile table     */
+    int width;                /* load width of runs with this plan: 64 or 128   */
+    int key_mode;             /* 0: packed 64-bit keys (r << id_bits | id);
+                                 1: full (r, id) keys                           */
+    uint32_t id_bits;
+    uint32_t T_max;
+    uint64_t tiles[5];        /* per size class: s <= 8, 16, 32, 64, > 64       */
+    uint64_t leaves[5];
+    uint64_t members[5];
+} kdss_plan_stats;
+
+typedef struct {
+    uint32_t T;               /* iterations run                                 */
+    uint32_t size;            /* i*: the node set is order[0 .. size)           */
+    uint32_t n;
+    int width;                /* load width used: 64 or 128                     */
+    kdss_u128 dens_num;       /* K_{i*} = |C_k(order[0 .. i*))|                 */
+    kdss_u128 ub_num;         /* max_u (r_T(u) - r0(u)); the bound is ub_num/T  */
+    kdss_u128 c_k;
+    double density;           /* dens_num / size (0 when size == 0)             */
+    double upper_bound;       /* ub_num / T                                     */
+} kdss_result;
+
+typedef struct {              /* one extraction during a run                    */
+    uint32_t t, size;
+    kdss_u128 dens_num;
+    kdss_u128 ub_num;
+} kdss_trace_row;
+
+/* Name of a status code, and the detail of the calling thread's last error. */
+const char *kdss_status_string(int status);
+const char *kdss_last_error(void);
+
+/* Checks that g is a simple undirected graph in the form described above.
+ * KDSS_OK, KDSS_EINVAL (null arrays) or KDSS_EGRAPH. Host only. */
+int kdss_csr_validate(const kdss_csr *g);
+
+/* Builds the k-pruned succinct clique tree of g (Sec. 2 "Succinct Clique Tree",
+ * Lemmas 3-5) on the host with up to `threads` threads (0: all cores).  Only
+ * leaves with h <= k <= h + p are kept (Lemma 4).  Every k-clique of g lies in
+ * exactly one kept leaf.  g's arrays are read during the call only.
+ * Errors: KDSS_EINVAL (k < 2, null), KDSS_EGRAPH, KDSS_ERANGE (k > 31),
+ * KDSS_EOVERFLOW (|C_k| >= 2^128), KDSS_ENOMEM. */
+int kdss_sct_build(const kdss_csr *g, uint32_t k, uint32_t threads, kdss_sct **out);
+
+int kdss_sct_info(const kdss_sct *s, kdss_tree_stats *out);
+
+/* Copies the kept leaves to host arrays: h[i], p[i] per leaf and the members
+ * (leaf by leaf, its h hold nodes first, then its p pivot nodes).
+ * KDSS_ERANGE if a capacity is too small. */
+int kdss_sct_export(const kdss_sct *s, uint32_t *h, uint32_t *p, uint32_t *members,
+                    uint64_t leaf_cap, uint64_t member_cap);
+
+/* Core number of every node (a by-product of the degeneracy order); core[n]. */
+int kdss_sct_core_numbers(const kdss_sct *s, uint32_t *core, uint32_t n);
+
+void kdss_sct_free(kdss_sct *s);
+
+/* Lays out s for the GPU, for runs of at most T_max iterations whose start
+ * loads r0 are all <= r0_max.  Chooses the load width (u64 when
+ * r0_max + T_max * |C_k| < 2^64, else u128) and the key mode.  opts may be NULL.
+ * Errors: KDSS_EINVAL, KDSS_EOVERFLOW (|C_k| >= 2^64, or u128 needed but
+ * width 64 forced), KDSS_EUNSUPPORTED (a leaf larger than 4096 members, or
+ * more than 2^31 nodes). */
+int kdss_plan_create(const kdss_sct *s, uint32_t T_max, uint64_t r0_max, const kdss_opts *opts,
+                     kdss_plan **out);
+int kdss_plan_info(const kdss_plan *p, kdss_plan_stats *out);
+
+/* Kernel durations gathered by kdss_run with opts.time_kernels = 1 since the
+ * plan was created or the last reset (reset != 0 clears them after copying). */
+int kdss_plan_timing(kdss_plan *p, kdss_timing *out, int reset);
+void kdss_plan_free(kdss_plan *p);
+
+/* Copies the leaf stream, tile table and binomial table into the device
+ * workspace d_ws (ws_bytes >= workspace_bytes) on `stream`.  Must precede
+ * kdss_run on that workspace.  Errors: KDSS_EWORKSPACE, KDSS_EHIP. */
+int kdss_plan_upload(kdss_plan *p, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Runs T (1 <= T <= T_max) synchronous Frank-Wolfe iterations (Algorithm 2's
+ * loop with Algorithm 1's per-clique step) from loads d_r0 (device u64[n];
+ * NULL = all zero; every entry must be <= r0_max), then the extraction.
+ * Outputs (device, caller-owned): d_r receives r_T (u64[n], or u128[n] as
+ * 2n u64 when the plan's width is 128); d_order receives the order pi (u32[n]),
+ * whose first h_res->size entries are the node set.  h_trace (host, nullable)
+ * receives one row per extraction when opts->extract_every > 0, at most
+ * trace_cap rows.  h_res (host) is filled after the stream is synchronised.
+ * Errors: KDSS_EINVAL, KDSS_EWORKSPACE, KDSS_EOVERFLOW (an r0 entry exceeded
+ * r0_max: results are invalid), KDSS_EHIP. */
+int kdss_run(kdss_plan *p, void *d_ws, size_t ws_bytes, uint32_t T, const uint64_t *d_r0,
+             void *d_r, uint32_t *d_order, kdss_trace_row *h_trace, uint32_t trace_cap,
+             kdss_result *h_res, void *stream);
+
+/* One leaf-credit pass (Algorithm 1's per-clique step, batched by Lemma 5) at loads
+ * d_r (device, the plan's width): d_out[u] (device u64[n], overwritten) =
+ * the number of k-cliques whose minimum (r, id) member is u.  Enqueued only. */
+int kdss_leaf_credit(kdss_plan *p, void *d_ws, size_t ws_bytes, const void *d_r,
+                     uint64_t *d_out, void *stream);
+
+/* The extraction alone (Algorithm 2, last three lines) at loads d_r after T
+ * iterations from d_r0 (nullable): order into d_order (device u32[n]), result
+ * into h_res (host; synchronises the stream). */
+int kdss_extract(kdss_plan *p, void *d_ws, size_t ws_bytes, const void *d_r,
+                 const uint64_t *d_r0, uint32_t T, uint32_t *d_order, kdss_result *h_res,
+                 void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDSS_H */

@@ -226,19 +226,58 @@ static void fill_fn(const uint32_t *c, int k, void *ctx) {
     ++f->used;
 }
 
-/* Write all k-cliques (sorted ids, lexicographic order) into out[cap * k].
- * *count receives the total; KOR_ENOMEM if it exceeds cap. Single-threaded. */
+/* Write all k-cliques (sorted ids; ordered by smallest id, then lexicographically)
+ * into out[cap * k].  *count receives the total; KOR_ENOMEM if it exceeds cap.
+ * Two passes over the roots: count the cliques of every root, then let each
+ * root write at its prefix offset. */
 int kor_list(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k,
              uint32_t *out, uint64_t cap, uint64_t *count) {
     if (k < 2 || !row_ptr || !count) return KOR_EINVAL;
     graph_t g = {n, row_ptr, col};
-    fill_ctx f = {out, cap, 0};
-    lister_t L;
-    if (lister_init(&L, &g, k, fill_fn, &f, max_degree(&g)) != KOR_OK) { lister_free(&L); return KOR_ENOMEM; }
-    for (uint32_t u = 0; u < n; ++u) list_from(&L, u);
-    lister_free(&L);
-    *count = f.used;
-    return f.used <= cap ? KOR_OK : KOR_ENOMEM;
+    uint64_t maxdeg = max_degree(&g);
+    uint64_t *start = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+    if (!start) return KOR_ENOMEM;
+    int err = KOR_OK;
+#pragma omp parallel
+    {
+        lister_t L;
+        uint64_t local = 0;
+        if (lister_init(&L, &g, k, count_fn, &local, maxdeg) != KOR_OK) {
+#pragma omp atomic write
+            err = KOR_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t u = 0; u < (int64_t)n; ++u) {
+                local = 0;
+                list_from(&L, (uint32_t)u);
+                start[u + 1] = local;
+            }
+        }
+        lister_free(&L);
+    }
+    for (uint32_t u = 0; u < n; ++u) start[u + 1] += start[u];
+    *count = start[n];
+    if (err || start[n] > cap) { free(start); return err ? err : KOR_ENOMEM; }
+#pragma omp parallel
+    {
+        fill_ctx f = {NULL, 0, 0};
+        lister_t L;
+        if (lister_init(&L, &g, k, fill_fn, &f, maxdeg) != KOR_OK) {
+#pragma omp atomic write
+            err = KOR_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t u = 0; u < (int64_t)n; ++u) {
+                f.out = out + start[u] * (uint64_t)k;
+                f.cap = start[u + 1] - start[u];
+                f.used = 0;
+                list_from(&L, (uint32_t)u);
+            }
+        }
+        lister_free(&L);
+    }
+    free(start);
+    return err;
 }
 
 /* ---- synchronous Frank-Wolfe (Alg. 1, FW-2: each clique credits its minimum-load node) ---- */

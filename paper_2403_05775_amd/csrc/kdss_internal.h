@@ -1,0 +1,138 @@
+// Internal declarations shared by the host sources of the kdss library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/kdss.h"
+
+namespace kdss {
+
+using u128 = unsigned __int128;
+
+// Records a detail message for kdss_last_error() and returns status.
+int fail(int status, const std::string& msg);
+
+// ---- graph checks and degeneracy order (host) ----
+int validate_csr(const kdss_csr* g);
+
+struct Degeneracy {
+  std::vector<uint32_t> order;   // nodes in peeling order
+  std::vector<uint32_t> rank;    // rank[v] = position of v in order
+  std::vector<uint32_t> core;    // core number of every node
+  uint32_t degeneracy = 0;
+};
+void degeneracy_order(const kdss_csr* g, Degeneracy* out);
+
+// ---- the k-pruned succinct clique tree, flattened to its leaves ----
+// Leaf i owns members[off[i] .. off[i] + h[i] + p[i]): first its h hold nodes
+// (every clique of the leaf contains them), then its p pivot nodes (any subset
+// of them may be added).  Only leaves with h <= k <= h + p are kept (Lemma 4).
+struct Sct {
+  uint32_t n = 0, k = 0;
+  std::vector<uint32_t> members;
+  std::vector<uint64_t> off;     // leaves + 1 entries
+  std::vector<uint8_t> h;
+  std::vector<uint32_t> p;
+  u128 c_k = 0;                  // sum over leaves of C(p, k - h)
+  uint32_t s_max = 0;
+  double build_seconds = 0.0;
+  Degeneracy deg;
+  uint64_t leaves() const { return h.size(); }
+};
+
+int build_sct(const kdss_csr* g, uint32_t k, uint32_t threads, Sct* out);
+
+// Binomial coefficient C(a, b) in 128 bits, saturating at 2^128 - 1.
+u128 binom128(uint64_t a, uint64_t b);
+
+// ---- device layout ----
+// Leaves with at most 64 members are processed one leaf per lane: a "lane
+// tile" is one round of up to 64 leaves of similar size, whose members are
+// stored column-major (member x of the tile's leaf i at mbase + 64 x + i, short
+// leaves padded), so every member load of a wavefront is one contiguous row.
+// Leaves are grouped by size (kLaneBounds) and keep the tree's depth-first
+// order inside a group, so neighbouring lanes usually share the leaf's root.
+// Larger leaves ("big") are processed one per wavefront, members contiguous.
+// Statistics are reported for the size buckets s <= 8, 16, 32, 64 and > 64.
+constexpr int kNumClasses = 5;
+constexpr int kBigClass = 4;
+constexpr uint32_t kTileLane = 0, kTileBig = 4;
+constexpr uint32_t kMaxBigLeaf = 4096;     // largest leaf the planner accepts
+constexpr uint32_t kMaxK = 31;
+constexpr uint32_t kLaneBounds[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64};
+constexpr int kNumLaneGroups = sizeof(kLaneBounds) / sizeof(kLaneBounds[0]);
+
+// One tile = the work of one wavefront.
+struct Tile {
+  uint64_t mbase;    // first member of the tile
+  uint32_t lbase;    // first leaf (index into the header array)
+  uint32_t info;     // kind (3 bits: kTileLane / kTileBig) | leaf count (13 bits) << 3
+                     // | largest leaf (16 bits) << 16
+};
+static_assert(sizeof(Tile) == 16, "tile descriptor is 16 bytes");
+
+// Launch geometry shared by the planner (workspace sizes) and the kernels.
+constexpr uint32_t kSortThreads = 256, kSortItems = 8, kSortTile = kSortThreads * kSortItems;
+constexpr uint32_t kScanThreads = 256, kScanItems = 4, kScanTile = kScanThreads * kScanItems;
+constexpr uint32_t kRedThreads = 256, kRedTile = 4096;
+constexpr uint32_t kBinomLds = 512;              // binomial tables up to this size live in LDS
+// Hot nodes: the nodes that occur in the most leaves.  Their member ids carry
+// kHotFlag | index into the hot table; every workgroup keeps their keys and
+// credits in LDS and writes its credit totals to a scratch row at its end.
+constexpr uint32_t kHotMax = 512;
+constexpr uint32_t kHotMinOccurrences = 32;
+constexpr uint32_t kHotFlag = 0x80000000u;
+constexpr uint32_t kLeafBlocksMax = 1024;        // persistent leaf-credit grid
+
+// Device-side result of an extraction.
+struct DevResult {
+  uint64_t dens_num;      // K_{i*}
+  uint32_t size;          // i*
+  uint32_t pad0;
+  uint64_t ub_lo, ub_hi;  // max (r - r0)
+  uint64_t r0max;         // largest start load seen
+  uint64_t pad1[3];
+};
+static_assert(sizeof(DevResult) == 64, "device result is 64 bytes");
+
+// Leaf header: h (5 bits), p (27 bits).
+inline uint32_t pack_leaf(uint32_t h, uint32_t p) { return h | (p << 5); }
+inline uint32_t pack_tile_info(uint32_t kind, uint32_t leaves, uint32_t smax) {
+  return kind | (leaves << 3) | (smax << 16);
+}
+
+}  // namespace kdss
+
+// The device plan of one clique tree (opaque to callers as kdss_plan).
+struct kdss_plan {
+  uint32_t n = 0, k = 0, T_max = 0, id_bits = 0, s_max = 0;
+  int width = 64;          // load width
+  int key_mode = 0;        // 0 packed, 1 full
+  uint64_t r0_max = 0;
+  kdss::u128 c_k = 0;
+  kdss_opts opts{};
+  std::vector<uint32_t> members;      // class-major, tile order
+  std::vector<uint32_t> hdr;          // one per leaf
+  std::vector<kdss::Tile> tiles;
+  std::vector<uint64_t> binom;        // C(a, b), a <= s_max, b <= k, row length k + 1
+  uint64_t class_tiles[kdss::kNumClasses] = {}, class_leaves[kdss::kNumClasses] = {},
+           class_members[kdss::kNumClasses] = {};
+  // workspace layout (byte offsets)
+  size_t off_members = 0, off_hdr = 0, off_tiles = 0, off_binom = 0, off_delta = 0, off_key = 0,
+         off_cnt = 0, off_kw[2][2] = {}, off_perm[2] = {}, off_keyp = 0, off_hist = 0, off_bsum = 0,
+         off_bbest = 0, off_red = 0, off_dres = 0, ws_bytes = 0;
+  uint32_t sort_blocks = 0, scan_blocks = 0, red_blocks = 0;
+  uint32_t leaf_blocks = 0;            // persistent grid of the leaf-credit kernel
+  std::vector<uint32_t> hot;           // original ids of the hot nodes
+  size_t off_hot = 0, off_scratch = 0, off_dbase = 0;
+  // state of the device side
+  void* uploaded_ws = nullptr;
+  void* graph_exec = nullptr;          // hipGraphExec_t of one iteration
+  void* graph_ws = nullptr;
+  void* graph_r = nullptr;
+  void* capture_stream = nullptr;
+  std::vector<void*> events;           // hipEvent_t pool for kernel timing
+  kdss_timing timing{};
+};

@@ -1,0 +1,1211 @@
+// Device side of kdss for gfx950 (CDNA4, 64-lane wavefronts): the leaf-credit
+// pass, the load update, and the extraction (radix sort, prefix clique counts,
+// exact best-prefix search), plus the C-ABI entry points that launch them.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "kdss_internal.h"
+
+using namespace kdss;
+
+namespace {
+
+// ----------------------------------------------------------------------------
+// Cross-lane helpers on 64-bit values (two 32-bit lane operations each).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int lane) {
+  uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, lane);
+  uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int mask) {
+  uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask);
+  uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t shfl32(uint32_t v, int lane) { return (uint32_t)__shfl((int)v, lane); }
+__device__ __forceinline__ uint32_t shfl_xor32(uint32_t v, int mask) { return (uint32_t)__shfl_xor((int)v, mask); }
+__device__ __forceinline__ uint32_t readlane32(uint32_t v, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// ----------------------------------------------------------------------------
+// Keys.  A leaf orders its members by (load, node id); the minimum of a clique
+// is the member with the smallest key.  Four encodings:
+//   KPacked: load << id_bits | id in one u64 (precomputed per iteration);
+//   KFull:   (u64 load, id);  KWide: (u128 load, id);
+//   KRank:   a unique u32 (the extraction's n - 1 - position).
+// ----------------------------------------------------------------------------
+struct KeySrc {
+  const uint64_t* key;    // packed keys
+  const uint64_t* r;      // loads (u64, or u128 as lo/hi pairs)
+  const uint32_t* rank;   // extraction keys
+};
+
+struct KPacked {
+  uint64_t v;
+  __device__ static KPacked mx() { return {~0ull}; }
+  __device__ static KPacked load(const KeySrc& s, uint32_t u) { return {s.key[u]}; }
+  __device__ bool lt(const KPacked& o) const { return v < o.v; }
+  __device__ bool eq(const KPacked& o) const { return v == o.v; }
+  __device__ KPacked sx(int m) const { return {shfl_xor64(v, m)}; }
+  __device__ KPacked sl(int l) const { return {shfl64(v, l)}; }
+  __device__ KPacked rl(int l) const { return {readlane64(v, l)}; }
+};
+
+struct KFull {
+  uint64_t r;
+  uint32_t id;
+  __device__ static KFull mx() { return {~0ull, ~0u}; }
+  __device__ static KFull load(const KeySrc& s, uint32_t u) { return {s.r[u], u}; }
+  __device__ bool lt(const KFull& o) const { return r < o.r || (r == o.r && id < o.id); }
+  __device__ bool eq(const KFull& o) const { return r == o.r && id == o.id; }
+  __device__ KFull sx(int m) const { return {shfl_xor64(r, m), shfl_xor32(id, m)}; }
+  __device__ KFull sl(int l) const { return {shfl64(r, l), shfl32(id, l)}; }
+  __device__ KFull rl(int l) const { return {readlane64(r, l), readlane32(id, l)}; }
+};
+
+struct KWide {
+  uint64_t hi, lo;
+  uint32_t id;
+  __device__ static KWide mx() { return {~0ull, ~0ull, ~0u}; }
+  __device__ static KWide load(const KeySrc& s, uint32_t u) { return {s.r[2ull * u + 1], s.r[2ull * u], u}; }
+  __device__ bool lt(const KWide& o) const {
+    return hi < o.hi || (hi == o.hi && (lo < o.lo || (lo == o.lo && id < o.id)));
+  }
+  __device__ bool eq(const KWide& o) const { return hi == o.hi && lo == o.lo && id == o.id; }
+  __device__ KWide sx(int m) const { return {shfl_xor64(hi, m), shfl_xor64(lo, m), shfl_xor32(id, m)}; }
+  __device__ KWide sl(int l) const { return {shfl64(hi, l), shfl64(lo, l), shfl32(id, l)}; }
+  __device__ KWide rl(int l) const { return {readlane64(hi, l), readlane64(lo, l), readlane32(id, l)}; }
+};
+
+struct KRank {
+  uint32_t v;
+  __device__ static KRank mx() { return {~0u}; }
+  __device__ static KRank load(const KeySrc& s, uint32_t u) { return {s.rank[u]}; }
+  __device__ bool lt(const KRank& o) const { return v < o.v; }
+  __device__ bool eq(const KRank& o) const { return v == o.v; }
+  __device__ KRank sx(int m) const { return {shfl_xor32(v, m)}; }
+  __device__ KRank sl(int l) const { return {shfl32(v, l)}; }
+  __device__ KRank rl(int l) const { return {readlane32(v, l)}; }
+};
+
+// Where a lane's credits go.  Hot nodes (member id kHotFlag | index) add into
+// the workgroup's LDS counters; other nodes go through one pending
+// (node, credit) pair per lane, which absorbs repeated credits to the same node
+// (a leaf's root is usually its minimum, and a lane sees leaf after leaf of the
+// same root), before a global atomic.
+struct Sink {
+  unsigned long long* hcnt;
+  uint64_t* out;
+  uint32_t pu;
+  uint64_t pc;
+  __device__ __forceinline__ void flush() {
+    if (pc) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(out + pu), (unsigned long long)pc);
+      pc = 0;
+    }
+  }
+  __device__ __forceinline__ void add(uint32_t raw, uint64_t c) {
+    if (raw & kHotFlag) {
+      atomicAdd(&hcnt[raw & ~kHotFlag], (unsigned long long)c);
+    } else if (raw == pu) {
+      pc += c;
+    } else {
+      flush();
+      pu = raw;
+      pc = c;
+    }
+  }
+};
+
+template <class KT>
+__device__ __forceinline__ KT member_key(const KeySrc& src, const KT* hkey, uint32_t raw) {
+  return (raw & kHotFlag) ? hkey[raw & ~kHotFlag] : KT::load(src, raw);
+}
+
+// Branch-free form for batched loads: both the LDS slot and the global key are
+// read (the hot index is also a valid node id, and the LDS index is masked into
+// the table), then one is selected, so a batch of these issues back to back.
+template <class KT>
+__device__ __forceinline__ KT member_key_nb(const KeySrc& src, const KT* hkey, uint32_t raw) {
+  const KT a = hkey[raw & (kHotMax - 1)];
+  const KT b = KT::load(src, raw & ~kHotFlag);
+  return (raw & kHotFlag) ? a : b;
+}
+
+// ----------------------------------------------------------------------------
+// Leaf credit (paper: Algorithm 1's per-clique minimum-load step, batched per
+// SCT leaf with the counts of Lemma 5).
+//
+// A leaf (H, P) with h = |H|, p = |P|, j = k - h holds the k-cliques H + C',
+// C' a j-subset of P.  Let m be the hold member with the smallest key.  The
+// minimum of H + C' is m unless C' holds a pivot member below m; then it is
+// the smallest such member u of C'.  With a(x) = the number of pivot members
+// whose key exceeds x's:
+//   pivot u below m gets C(a(u), j - 1);   m gets C(a(m), j);   others get 0.
+// Pivot members below m are the "low" ones; a(u) = p - 1 - (number of low
+// members below u), and a(m) = p - (number of low members).
+// ----------------------------------------------------------------------------
+
+// Adds (key, val) of every lane to the sink after combining runs of adjacent
+// lanes with the same key (a segmented inclusive scan over the wavefront): only
+// the last lane of a run adds the run's total.  Lanes with val == 0 add nothing.
+__device__ __forceinline__ void combine_add(Sink& sink, uint32_t key, uint64_t val) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const uint32_t kp = shfl32(key, lane > 0 ? lane - 1 : 0);
+  const uint32_t head = (lane == 0 || kp != key) ? 1u : 0u;
+  uint32_t f = head;
+  uint64_t v = val;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int src = lane >= d ? lane - d : lane;
+    const uint64_t vu = shfl64(v, src);
+    const uint32_t fu = shfl32(f, src);
+    if (lane >= d && !f) {
+      v += vu;
+      f |= fu;
+    }
+  }
+  const uint32_t next_head = shfl32(head, lane < 63 ? lane + 1 : 63);
+  const bool run_end = lane == 63 || next_head;
+  if (run_end && v) sink.add(key, v);
+}
+
+// Lane tile: one leaf per lane; member x of the lane's leaf is the row-x word
+// of the column-major tile, so every load below is one contiguous 256-byte row.
+// A single pass over the rows finds the hold minimum m (hold members come first
+// in every leaf) and counts the pivot members below m.  Lanes that have such
+// "low" members rank them: up to four are kept in registers, more (frequent only
+// while many loads tie, e.g. from all-zero start loads) are ranked by a rescan.
+template <class KT>
+__device__ __forceinline__ void tile_lane(const Tile& t, const uint32_t* __restrict__ members,
+                                          const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k,
+                                          const KeySrc& src, const KT* hkey, Sink& sink) {
+  constexpr uint32_t U = 8;   // rows loaded per batch
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t nl = (t.info >> 3) & 0x1FFFu, smax = t.info >> 16;
+  const uint32_t k1 = k + 1;
+  const uint32_t hd = lane < nl ? hdr[t.lbase + lane] : 0u;   // a missing leaf reads as empty
+  const uint32_t h = hd & 31u, p = hd >> 5, s = h + p;
+  const uint32_t j = k - h;
+  const uint32_t* __restrict__ col = members + t.mbase + lane;
+  KT km = KT::mx();
+  uint32_t mraw = 0, nlow = 0;
+  for (uint32_t x0 = 0; x0 < smax; x0 += U) {
+    uint32_t raw[U];
+    KT key[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) raw[u] = col[(size_t)min(x0 + u, smax - 1) * 64];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) key[u] = member_key_nb<KT>(src, hkey, raw[u]);
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      const uint32_t x = x0 + u;
+      const bool hold = x < h, piv = x >= h && x < s;
+      const bool better = hold && key[u].lt(km);
+      km = better ? key[u] : km;
+      mraw = better ? raw[u] : mraw;
+      nlow += (piv && key[u].lt(km)) ? 1u : 0u;
+    }
+  }
+  if (nlow) {
+    if (nlow <= 4) {
+      KT l0 = KT::mx(), l1 = KT::mx(), l2 = KT::mx(), l3 = KT::mx();
+      uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0, c = 0;
+      for (uint32_t x0 = 0; x0 < smax; x0 += U) {
+        uint32_t raw[U];
+        KT key[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) raw[u] = col[(size_t)min(x0 + u, smax - 1) * 64];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) key[u] = member_key_nb<KT>(src, hkey, raw[u]);
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+          const uint32_t x = x0 + u;
+          if (x >= h && x < s && key[u].lt(km)) {
+            if (c == 0) { l0 = key[u]; r0 = raw[u]; }
+            else if (c == 1) { l1 = key[u]; r1 = raw[u]; }
+            else if (c == 2) { l2 = key[u]; r2 = raw[u]; }
+            else { l3 = key[u]; r3 = raw[u]; }
+            ++c;
+          }
+        }
+      }
+      // rank of each low member among the low members (unused slots hold the maximum key)
+      const uint32_t b0 = (l1.lt(l0) ? 1u : 0u) + (l2.lt(l0) ? 1u : 0u) + (l3.lt(l0) ? 1u : 0u);
+      const uint32_t b1 = (l0.lt(l1) ? 1u : 0u) + (l2.lt(l1) ? 1u : 0u) + (l3.lt(l1) ? 1u : 0u);
+      const uint32_t b2 = (l0.lt(l2) ? 1u : 0u) + (l1.lt(l2) ? 1u : 0u) + (l3.lt(l2) ? 1u : 0u);
+      const uint32_t b3 = (l0.lt(l3) ? 1u : 0u) + (l1.lt(l3) ? 1u : 0u) + (l2.lt(l3) ? 1u : 0u);
+      if (j >= 1) {
+        const uint64_t* row = binom + (j - 1);
+        sink.add(r0, row[(size_t)(p - 1 - b0) * k1]);
+        if (nlow > 1) sink.add(r1, row[(size_t)(p - 1 - b1) * k1]);
+        if (nlow > 2) sink.add(r2, row[(size_t)(p - 1 - b2) * k1]);
+        if (nlow > 3) sink.add(r3, row[(size_t)(p - 1 - b3) * k1]);
+      }
+    }
+  }
+  // Leaves with more than four low members: the whole wavefront takes them one
+  // at a time, one member per lane (lane tiles hold at most 64 members).
+  uint64_t heavy = __ballot(nlow > 4);
+  while (heavy) {
+    const int L = __ffsll((unsigned long long)heavy) - 1;
+    heavy &= heavy - 1;
+    const uint32_t hL = (uint32_t)__builtin_amdgcn_readlane((int)h, L);
+    const uint32_t sL = (uint32_t)__builtin_amdgcn_readlane((int)s, L);
+    const uint32_t pL = sL - hL, jL = k - hL;
+    const KT kmL = km.rl(L);
+    const bool va = lane < sL;
+    const uint32_t ra = va ? members[t.mbase + (size_t)lane * 64 + (uint32_t)L] : 0u;
+    const KT ka = va ? member_key<KT>(src, hkey, ra) : KT::mx();
+    const bool low = va && lane >= hL && ka.lt(kmL);
+    uint64_t bm = __ballot(low);
+    uint32_t below = 0;
+    while (bm) {
+      const int tl = __ffsll((unsigned long long)bm) - 1;
+      bm &= bm - 1;
+      below += (low && ka.rl(tl).lt(ka)) ? 1u : 0u;
+    }
+    if (low && jL >= 1) {
+      const uint64_t c = binom[(size_t)(pL - 1 - below) * k1 + (jL - 1)];
+      if (c) sink.add(ra, c);
+    }
+  }
+  const uint64_t cm = h ? binom[(size_t)(p - nlow) * k1 + j] : 0ull;
+  combine_add(sink, cm ? mraw : 0xFFFFFFFFu, cm);
+}
+
+// Big tile: one leaf of more than 64 members per wavefront, in chunks of 64.
+template <class KT>
+__device__ __forceinline__ void tile_big(const Tile& t, const uint32_t* __restrict__ members,
+                                         const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ binom,
+                                         uint32_t k, const KeySrc& src, const KT* hkey, Sink& sink) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t hd = hdr[t.lbase];
+  const uint32_t h = hd & 31u, p = hd >> 5, s = h + p;
+  const uint32_t j = k - h, k1 = k + 1;
+  const uint32_t* __restrict__ mem = members + t.mbase;
+  // the hold members all sit in the first chunk (h <= 31)
+  const uint32_t r0 = lane < s ? mem[lane] : 0u;
+  const KT k0 = lane < s ? member_key<KT>(src, hkey, r0) : KT::mx();
+  KT kh = lane < h ? k0 : KT::mx();
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const KT o = kh.sx(d);
+    if (o.lt(kh)) kh = o;
+  }
+  uint32_t nlow = 0;
+  for (uint32_t a0 = 0; a0 < s; a0 += 64) {
+    const uint32_t ia = a0 + lane;
+    const bool va = ia < s;
+    const uint32_t ra = va ? mem[ia] : 0u;
+    const KT ka = va ? member_key<KT>(src, hkey, ra) : KT::mx();
+    const bool low = va && ia >= h && ka.lt(kh);
+    const uint64_t lm = __ballot(low);
+    nlow += (uint32_t)__popcll(lm);
+    if (!lm) continue;
+    uint32_t below = 0;
+    for (uint32_t b0 = 0; b0 < s; b0 += 64) {
+      const uint32_t ib = b0 + lane;
+      const bool vb = ib < s && ib >= h;
+      const KT kb = vb ? member_key<KT>(src, hkey, mem[ib]) : KT::mx();
+      uint64_t bm = __ballot(vb && kb.lt(kh));   // low members of this chunk
+      while (bm) {
+        const int tl = __ffsll((unsigned long long)bm) - 1;
+        const KT kt = kb.rl(tl);
+        below += (low && kt.lt(ka)) ? 1u : 0u;
+        bm &= bm - 1;
+      }
+    }
+    if (low && j >= 1) {
+      const uint64_t c = binom[(size_t)(p - 1 - below) * k1 + (j - 1)];
+      if (c) sink.add(ra, c);
+    }
+  }
+  if (lane < h && k0.eq(kh)) {
+    const uint64_t c = binom[(size_t)(p - nlow) * k1 + j];
+    if (c) sink.add(r0, c);
+  }
+}
+
+// Persistent grid: wave w of the grid takes tiles w, w + 4 * gridDim.x, ...
+// Each workgroup writes its hot-node credit totals to scratch[blockIdx.x][*].
+template <class KT>
+__global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict__ tiles, uint32_t ntiles,
+                                                          const uint32_t* __restrict__ members,
+                                                          const uint32_t* __restrict__ hdr,
+                                                          const uint64_t* __restrict__ binom, uint32_t nbinom,
+                                                          uint32_t k, KeySrc src, uint64_t* __restrict__ out,
+                                                          const uint32_t* __restrict__ hot, uint32_t nhot,
+                                                          uint64_t* __restrict__ scratch) {
+  __shared__ KT hkey[kHotMax];
+  __shared__ unsigned long long hcnt[kHotMax];
+  __shared__ uint64_t sbinom[kBinomLds];
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
+    hkey[i] = KT::load(src, hot[i]);
+    hcnt[i] = 0;
+  }
+  const bool lds_binom = nbinom <= kBinomLds;
+  if (lds_binom)
+    for (uint32_t i = threadIdx.x; i < nbinom; i += blockDim.x) sbinom[i] = binom[i];
+  __syncthreads();
+  const uint64_t* bt = lds_binom ? sbinom : binom;
+  Sink sink{hcnt, out, 0u, 0ull};
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t stride = gridDim.x * 4u;
+  for (uint32_t tile = blockIdx.x * 4u + w; tile < ntiles; tile += stride) {
+    const Tile t = tiles[tile];
+    if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k, src, hkey, sink);
+    else tile_lane<KT>(t, members, hdr, bt, k, src, hkey, sink);
+  }
+  sink.flush();
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) scratch[(size_t)blockIdx.x * nhot + i] = hcnt[i];
+}
+
+// Hot-node totals: out[hot[i]] += sum over workgroups b of scratch[b][i].  A
+// block sums 64 hot nodes over a band of kHotRowsPerBlock rows (4 waves, each
+// a quarter of the band) and adds its partial sums with one atomic per node.
+constexpr uint32_t kHotRowsPerBlock = 64;
+
+__global__ __launch_bounds__(256) void hot_reduce_kernel(const uint64_t* __restrict__ scratch, uint32_t blocks,
+                                                         const uint32_t* __restrict__ hot, uint32_t nhot,
+                                                         uint64_t* __restrict__ out) {
+  __shared__ uint64_t part[4][64];
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t i = blockIdx.x * 64u + lane;
+  const uint32_t b0 = blockIdx.y * kHotRowsPerBlock;
+  const uint32_t b1 = min(blocks, b0 + kHotRowsPerBlock);
+  uint64_t s = 0;
+  if (i < nhot) {
+#pragma unroll 4
+    for (uint32_t b = b0 + w; b < b1; b += 4) s += scratch[(size_t)b * nhot + i];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && i < nhot) {
+    const uint64_t t = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    if (t) atomicAdd(reinterpret_cast<unsigned long long*>(out + hot[i]), (unsigned long long)t);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Load update r_t = r_{t-1} + d_t (Algorithm 1's unit increments summed over
+// the iteration), and its start.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fill_u64_kernel(uint64_t* a, uint64_t v, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+__global__ void reset_result_kernel(DevResult* d) {
+  if (threadIdx.x == 0) {
+    d->dens_num = 0;
+    d->size = 0;
+    d->pad0 = 0;
+    d->ub_lo = d->ub_hi = 0;
+    d->r0max = 0;
+    d->pad1[0] = d->pad1[1] = d->pad1[2] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void init_loads_kernel(const uint64_t* __restrict__ r0, uint64_t* __restrict__ r,
+                                                         uint64_t* __restrict__ delta, uint64_t* __restrict__ key,
+                                                         uint32_t n, uint32_t id_bits, int packed, int wide,
+                                                         DevResult* dres) {
+  uint64_t mx = 0;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const uint64_t x = r0 ? r0[u] : 0ull;
+    mx = x > mx ? x : mx;
+    if (wide) {
+      r[2ull * u] = x;
+      r[2ull * u + 1] = 0;
+    } else {
+      r[u] = x;
+    }
+    delta[u] = 0;
+    if (packed) key[u] = (x << id_bits) | u;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t o = shfl_xor64(mx, d);
+    mx = o > mx ? o : mx;
+  }
+  if ((threadIdx.x & 63u) == 0 && mx) atomicMax(reinterpret_cast<unsigned long long*>(&dres->r0max), (unsigned long long)mx);
+}
+
+__global__ __launch_bounds__(256) void apply64_kernel(uint64_t* __restrict__ r, uint64_t* __restrict__ delta,
+                                                      uint64_t* __restrict__ key, uint32_t n, uint32_t id_bits,
+                                                      int packed) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const uint64_t x = r[u] + delta[u];
+    r[u] = x;
+    delta[u] = 0;
+    if (packed) key[u] = (x << id_bits) | u;
+  }
+}
+
+__global__ __launch_bounds__(256) void apply128_kernel(uint64_t* __restrict__ r, uint64_t* __restrict__ delta,
+                                                       uint32_t n) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const uint64_t d = delta[u];
+    const uint64_t lo = r[2ull * u] + d;
+    r[2ull * u] = lo;
+    r[2ull * u + 1] += (lo < d) ? 1ull : 0ull;
+    delta[u] = 0;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Maxima: max_u (r(u) - sub(u)) as a 128-bit value (sub may be null).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ bool gt128(uint64_t ah, uint64_t al, uint64_t bh, uint64_t bl) {
+  return ah > bh || (ah == bh && al > bl);
+}
+
+__global__ __launch_bounds__(256) void max_partial_kernel(const uint64_t* __restrict__ r, const uint64_t* __restrict__ sub,
+                                                          uint32_t n, int wide, uint64_t* __restrict__ red) {
+  __shared__ uint64_t sh[4], sl[4];
+  uint64_t bh = 0, bl = 0;
+  const uint32_t base = blockIdx.x * kRedTile;
+  for (uint32_t i = threadIdx.x; i < kRedTile; i += blockDim.x) {
+    const uint32_t u = base + i;
+    if (u >= n) break;
+    uint64_t lo = wide ? r[2ull * u] : r[u];
+    uint64_t hi = wide ? r[2ull * u + 1] : 0ull;
+    if (sub) {
+      const uint64_t s = sub[u];
+      hi -= (lo < s) ? 1ull : 0ull;
+      lo -= s;
+    }
+    if (gt128(hi, lo, bh, bl)) { bh = hi; bl = lo; }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t oh = shfl_xor64(bh, d), ol = shfl_xor64(bl, d);
+    if (gt128(oh, ol, bh, bl)) { bh = oh; bl = ol; }
+  }
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0) { sh[w] = bh; sl[w] = bl; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t x = 1; x < blockDim.x / 64; ++x)
+      if (gt128(sh[x], sl[x], bh, bl)) { bh = sh[x]; bl = sl[x]; }
+    red[2ull * blockIdx.x] = bl;
+    red[2ull * blockIdx.x + 1] = bh;
+  }
+}
+
+__global__ __launch_bounds__(256) void max_final_kernel(const uint64_t* __restrict__ red, uint32_t nb,
+                                                        uint64_t* out_lo, uint64_t* out_hi) {
+  __shared__ uint64_t sh[4], sl[4];
+  uint64_t bh = 0, bl = 0;
+  for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
+    if (gt128(red[2ull * i + 1], red[2ull * i], bh, bl)) { bh = red[2ull * i + 1]; bl = red[2ull * i]; }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t oh = shfl_xor64(bh, d), ol = shfl_xor64(bl, d);
+    if (gt128(oh, ol, bh, bl)) { bh = oh; bl = ol; }
+  }
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0) { sh[w] = bh; sl[w] = bl; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t x = 1; x < blockDim.x / 64; ++x)
+      if (gt128(sh[x], sl[x], bh, bl)) { bh = sh[x]; bl = sl[x]; }
+    *out_lo = bl;
+    *out_hi = bh;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Extraction order (Algorithm 2: sort V by r): stable LSD radix sort of
+// d(u) = B - r(u) (B >= every load), starting from ascending ids, so the
+// result is r non-increasing with ties in ascending id.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void sort_init_kernel(const uint64_t* __restrict__ r, uint32_t n, int wide,
+                                                        uint64_t b_lo, uint64_t b_hi, uint64_t* __restrict__ kw_lo,
+                                                        uint64_t* __restrict__ kw_hi, uint32_t* __restrict__ perm) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const uint64_t lo = wide ? r[2ull * u] : r[u];
+    const uint64_t hi = wide ? r[2ull * u + 1] : 0ull;
+    kw_lo[u] = b_lo - lo;
+    if (wide) kw_hi[u] = b_hi - hi - ((b_lo < lo) ? 1ull : 0ull);
+    perm[u] = u;
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint64_t* __restrict__ kw, uint32_t n,
+                                                                  uint32_t shift, uint32_t* __restrict__ hist,
+                                                                  uint32_t nblocks) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kSortTile;
+  for (uint32_t j = 0; j < kSortItems; ++j) {
+    const uint32_t i = base + j * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(uint32_t)(kw[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void scan_exclusive_single_kernel(T* a, uint32_t count) {
+  __shared__ T part[1024];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (count + 1023u) / 1024u;
+  const uint32_t b = min(count, tid * per), e = min(count, b + per);
+  T s = 0;
+  for (uint32_t i = b; i < e; ++i) s += a[i];
+  part[tid] = s;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024; off <<= 1) {
+    const T v = tid >= off ? part[tid - off] : (T)0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  T run = tid ? part[tid - 1] : (T)0;
+  for (uint32_t i = b; i < e; ++i) {
+    const T x = a[i];
+    a[i] = run;
+    run += x;
+  }
+}
+
+// Exclusive scan of a u32 value over a 256-thread block; returns the exclusive
+// prefix of this thread and sets *total to the block sum.
+__device__ __forceinline__ uint32_t block_exclusive_scan256(uint32_t v, uint32_t* total, uint32_t* sh) {
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = shfl32(inc, (int)lane >= d ? (int)lane - d : (int)lane);
+    if ((int)lane >= d) inc += o;
+  }
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, sum = 0;
+  for (uint32_t x = 0; x < 4; ++x) {
+    if (x < w) before += sh[x];
+    sum += sh[x];
+  }
+  __syncthreads();
+  *total = sum;
+  return before + inc - v;
+}
+
+// Digit offsets, step 1: block d scans row d of the digit-major histogram in
+// place (exclusive) and records the row total.
+__global__ __launch_bounds__(256) void radix_rowscan_kernel(uint32_t* __restrict__ hist, uint32_t nblocks,
+                                                            uint32_t* __restrict__ rowtot) {
+  __shared__ uint32_t sh[4];
+  uint32_t* row = hist + (size_t)blockIdx.x * nblocks;
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < nblocks; b0 += 256) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint32_t v = b < nblocks ? row[b] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan256(v, &total, sh);
+    if (b < nblocks) row[b] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) rowtot[blockIdx.x] = carry;
+}
+
+// Digit offsets, step 2: exclusive scan of the 256 row totals (one block).
+__global__ __launch_bounds__(256) void radix_digitscan_kernel(uint32_t* __restrict__ rowtot) {
+  __shared__ uint32_t sh[4];
+  uint32_t total;
+  const uint32_t ex = block_exclusive_scan256(rowtot[threadIdx.x], &total, sh);
+  rowtot[threadIdx.x] = ex;
+}
+
+// Stable scatter of one 8-bit digit: elements of a tile keep their relative order.
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+    const uint64_t* __restrict__ klo, const uint64_t* __restrict__ khi, const uint32_t* __restrict__ pin,
+    uint64_t* __restrict__ olo, uint64_t* __restrict__ ohi, uint32_t* __restrict__ pout, uint32_t n,
+    uint32_t shift, int use_hi, int wide, const uint32_t* __restrict__ hist, uint32_t nblocks,
+    const uint32_t* __restrict__ dbase) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[4][256];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  base[tid] = dbase[tid] + hist[(size_t)tid * nblocks + blockIdx.x];
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  for (uint32_t j = 0; j < kSortItems; ++j) {
+    const uint32_t i = blockIdx.x * kSortTile + j * kSortThreads + tid;
+    const bool valid = i < n;
+    const uint64_t vlo = valid ? klo[i] : 0ull;
+    const uint64_t vhi = (valid && wide) ? khi[i] : 0ull;
+    const uint32_t d = (uint32_t)((use_hi ? vhi : vlo) >> shift) & 255u;
+    wcnt[0][tid] = 0;
+    wcnt[1][tid] = 0;
+    wcnt[2][tid] = 0;
+    wcnt[3][tid] = 0;
+    __syncthreads();
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(valid && bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
+    __syncthreads();
+    wcnt[0][tid] = 0;
+    wcnt[1][tid] = c0;
+    wcnt[2][tid] = c0 + c1;
+    wcnt[3][tid] = c0 + c1 + c2;
+    __syncthreads();
+    if (valid) {
+      const uint32_t dst = base[d] + wcnt[w][d] + rank;
+      olo[dst] = vlo;
+      if (wide) ohi[dst] = vhi;
+      pout[dst] = pin[i];
+    }
+    __syncthreads();
+    base[tid] += c0 + c1 + c2 + c3;
+    __syncthreads();
+  }
+}
+
+// extraction key n - 1 - position (smallest key = latest position), and zeroed counts
+__global__ __launch_bounds__(256) void rank_keys_kernel(const uint32_t* __restrict__ perm, uint32_t n,
+                                                        uint32_t* __restrict__ rank, uint64_t* __restrict__ cnt) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    rank[perm[i]] = n - 1 - i;
+    cnt[i] = 0;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Prefix clique counts K_i and the best prefix (Algorithm 2: argmax_i rho_k(V_i)).
+// cnt[u] holds the number of cliques whose latest-positioned member is u, so
+// K_i = sum of cnt[order[0 .. i)).  Ratios are compared exactly:
+// K_a / a > K_b / b  iff  K_a * b > K_b * a (96-bit products); ties -> larger i.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ bool better(uint64_t Ka, uint32_t ia, uint64_t Kb, uint32_t ib) {
+  if (Ka == 0) return false;
+  if (Kb == 0) return true;
+  const uint64_t xl = Ka * (uint64_t)ib, xh = __umul64hi(Ka, (uint64_t)ib);
+  const uint64_t yl = Kb * (uint64_t)ia, yh = __umul64hi(Kb, (uint64_t)ia);
+  if (xh != yh) return xh > yh;
+  if (xl != yl) return xl > yl;
+  return ia > ib;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_blocksum_kernel(const uint64_t* __restrict__ cnt,
+                                                                     const uint32_t* __restrict__ perm, uint32_t n,
+                                                                     uint64_t* __restrict__ bsum) {
+  __shared__ uint64_t ws[kScanThreads / 64];
+  uint64_t s = 0;
+  const uint32_t base = blockIdx.x * kScanTile;
+  for (uint32_t j = 0; j < kScanItems; ++j) {
+    const uint32_t i = base + j * kScanThreads + threadIdx.x;
+    if (i < n) s += cnt[perm[i]];
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) s += shfl_xor64(s, d);
+  if ((threadIdx.x & 63u) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (uint32_t x = 0; x < kScanThreads / 64; ++x) t += ws[x];
+    bsum[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_argmax_kernel(const uint64_t* __restrict__ cnt,
+                                                                   const uint32_t* __restrict__ perm, uint32_t n,
+                                                                   const uint64_t* __restrict__ bsum,
+                                                                   uint64_t* __restrict__ bbest) {
+  __shared__ uint64_t wsum[kScanThreads / 64];
+  __shared__ uint64_t bk[kScanThreads / 64];
+  __shared__ uint32_t bi[kScanThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  // thread t owns positions base + t*items .. + items - 1 (consecutive)
+  const uint32_t first = blockIdx.x * kScanTile + tid * kScanItems;
+  uint64_t v[kScanItems];
+  uint64_t tsum = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kScanItems; ++j) {
+    const uint32_t i = first + j;
+    v[j] = i < n ? cnt[perm[i]] : 0ull;
+    tsum += v[j];
+  }
+  // inclusive scan of thread sums within the wave
+  uint64_t inc = tsum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t o = shfl64(inc, (int)lane - d < 0 ? (int)lane : (int)lane - d);
+    if ((int)lane - d >= 0) inc += o;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint64_t before = bsum[blockIdx.x];
+  for (uint32_t x = 0; x < w; ++x) before += wsum[x];
+  uint64_t K = before + inc - tsum;
+  uint64_t bestK = 0;
+  uint32_t besti = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kScanItems; ++j) {
+    const uint32_t i = first + j;
+    K += v[j];
+    if (i < n && better(K, i + 1, bestK, besti)) { bestK = K; besti = i + 1; }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t ok = shfl_xor64(bestK, d);
+    const uint32_t oi = shfl_xor32(besti, d);
+    if (better(ok, oi, bestK, besti)) { bestK = ok; besti = oi; }
+  }
+  if (lane == 0) { bk[w] = bestK; bi[w] = besti; }
+  __syncthreads();
+  if (tid == 0) {
+    for (uint32_t x = 1; x < kScanThreads / 64; ++x)
+      if (better(bk[x], bi[x], bestK, besti)) { bestK = bk[x]; besti = bi[x]; }
+    bbest[2ull * blockIdx.x] = bestK;
+    bbest[2ull * blockIdx.x + 1] = besti;
+  }
+}
+
+__global__ __launch_bounds__(256) void argmax_final_kernel(const uint64_t* __restrict__ bbest, uint32_t nb,
+                                                           DevResult* dres) {
+  __shared__ uint64_t bk[4];
+  __shared__ uint32_t bi[4];
+  uint64_t bestK = 0;
+  uint32_t besti = 0;
+  for (uint32_t x = threadIdx.x; x < nb; x += blockDim.x) {
+    const uint64_t K = bbest[2ull * x];
+    const uint32_t i = (uint32_t)bbest[2ull * x + 1];
+    if (better(K, i, bestK, besti)) { bestK = K; besti = i; }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t ok = shfl_xor64(bestK, d);
+    const uint32_t oi = shfl_xor32(besti, d);
+    if (better(ok, oi, bestK, besti)) { bestK = ok; besti = oi; }
+  }
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0) { bk[w] = bestK; bi[w] = besti; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t x = 1; x < blockDim.x / 64; ++x)
+      if (better(bk[x], bi[x], bestK, besti)) { bestK = bk[x]; besti = bi[x]; }
+    dres->dens_num = bestK;
+    dres->size = besti;
+  }
+}
+
+__global__ __launch_bounds__(256) void copy_u32_kernel(const uint32_t* __restrict__ a, uint32_t* __restrict__ b,
+                                                       uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+// ----------------------------------------------------------------------------
+// Host-side launch helpers.
+// ----------------------------------------------------------------------------
+int hip_fail(hipError_t e, const char* what) {
+  return fail(KDSS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                 \
+  do {                                      \
+    hipError_t e_ = (call);                 \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+uint32_t grid_for(size_t n, uint32_t threads = 256, uint32_t cap = 16384) {
+  size_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (uint32_t)b;
+}
+
+uint32_t bit_length128(u128 x) {
+  uint32_t b = 0;
+  while (x) { ++b; x >>= 1; }
+  return b;
+}
+
+struct WsView {
+  char* base;
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
+};
+
+// mode: 0 packed FW keys, 1 full u64 loads, 2 full u128 loads, 3 extraction ranks
+int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& src, uint64_t* out,
+                hipStream_t st) {
+  const uint32_t ntiles = (uint32_t)P->tiles.size();
+  if (ntiles == 0) return KDSS_OK;
+  const uint32_t blocks = P->leaf_blocks;
+  const Tile* tiles = ws.at<Tile>(P->off_tiles);
+  const uint32_t* members = ws.at<uint32_t>(P->off_members);
+  const uint32_t* hdr = ws.at<uint32_t>(P->off_hdr);
+  const uint64_t* binom = ws.at<uint64_t>(P->off_binom);
+  const uint32_t* hot = ws.at<uint32_t>(P->off_hot);
+  const uint32_t nhot = (uint32_t)P->hot.size();
+  uint64_t* scratch = ws.at<uint64_t>(P->off_scratch);
+#define KDSS_LEAF(KT) \
+  leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, (uint32_t)P->binom.size(), \
+                                                 P->k, src, out, hot, nhot, scratch)
+  switch (mode) {
+    case 0: KDSS_LEAF(KPacked); break;
+    case 1: KDSS_LEAF(KFull); break;
+    case 2: KDSS_LEAF(KWide); break;
+    default: KDSS_LEAF(KRank); break;
+  }
+#undef KDSS_LEAF
+  HIP_TRY(hipGetLastError(), "leaf credit launch");
+  if (nhot) {
+    const dim3 grid((nhot + 63) / 64, (blocks + kHotRowsPerBlock - 1) / kHotRowsPerBlock);
+    hot_reduce_kernel<<<grid, 256, 0, st>>>(scratch, blocks, hot, nhot, out);
+    HIP_TRY(hipGetLastError(), "hot reduce launch");
+  }
+  return KDSS_OK;
+}
+
+int fw_mode(const kdss_plan* P) { return P->width == 128 ? 2 : (P->key_mode == 0 ? 0 : 1); }
+
+KeySrc fw_src(const kdss_plan* P, const WsView& ws, const void* d_r) {
+  KeySrc s{};
+  s.key = ws.at<uint64_t>(P->off_key);
+  s.r = static_cast<const uint64_t*>(d_r);
+  s.rank = nullptr;
+  return s;
+}
+
+// One Frank-Wolfe iteration: credits at r_{t-1} into delta, then r_t = r_{t-1} + delta.
+int launch_iteration(const kdss_plan* P, const WsView& ws, void* d_r, hipStream_t st) {
+  uint64_t* delta = ws.at<uint64_t>(P->off_delta);
+  int rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st);
+  if (rc) return rc;
+  if (P->width == 128) {
+    apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
+  } else {
+    apply64_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, ws.at<uint64_t>(P->off_key),
+                                                    P->n, P->id_bits, P->key_mode == 0 ? 1 : 0);
+  }
+  HIP_TRY(hipGetLastError(), "apply launch");
+  return KDSS_OK;
+}
+
+// Extraction at loads d_r; every load is <= bound.  The order lands in d_order
+// and the best prefix and upper bound in the device result.
+int launch_extract(const kdss_plan* P, const WsView& ws, const void* d_r, const uint64_t* d_r0, u128 bound,
+                   uint32_t* d_order, hipStream_t st) {
+  const uint32_t n = P->n;
+  const int wide = P->width == 128 ? 1 : 0;
+  const uint64_t* r = static_cast<const uint64_t*>(d_r);
+  DevResult* dres = ws.at<DevResult>(P->off_dres);
+  uint64_t* red = ws.at<uint64_t>(P->off_red);
+  // upper bound numerator max (r - r0)
+  max_partial_kernel<<<P->red_blocks, 256, 0, st>>>(r, d_r0, n, wide, red);
+  max_final_kernel<<<1, 256, 0, st>>>(red, P->red_blocks, &dres->ub_lo, &dres->ub_hi);
+  HIP_TRY(hipGetLastError(), "upper bound launch");
+  // order: sort B - r ascending, stable over ascending ids
+  int cur = 0;
+  uint64_t* kw[2][2] = {{ws.at<uint64_t>(P->off_kw[0][0]), ws.at<uint64_t>(P->off_kw[0][1])},
+                        {ws.at<uint64_t>(P->off_kw[1][0]), ws.at<uint64_t>(P->off_kw[1][1])}};
+  uint32_t* perm[2] = {ws.at<uint32_t>(P->off_perm[0]), ws.at<uint32_t>(P->off_perm[1])};
+  uint32_t* hist = ws.at<uint32_t>(P->off_hist);
+  uint32_t* dbase = ws.at<uint32_t>(P->off_dbase);
+  sort_init_kernel<<<grid_for(n), 256, 0, st>>>(r, n, wide, (uint64_t)bound, (uint64_t)(bound >> 64), kw[0][0],
+                                                kw[0][1], perm[0]);
+  HIP_TRY(hipGetLastError(), "sort init launch");
+  const uint32_t nbits = bit_length128(bound);
+  for (uint32_t sh = 0; sh < nbits; sh += 8) {
+    const int use_hi = sh >= 64 ? 1 : 0;
+    const uint64_t* src = use_hi ? kw[cur][1] : kw[cur][0];
+    radix_hist_kernel<<<P->sort_blocks, kSortThreads, 0, st>>>(src, n, sh & 63u, hist, P->sort_blocks);
+    radix_rowscan_kernel<<<256, 256, 0, st>>>(hist, P->sort_blocks, dbase);
+    radix_digitscan_kernel<<<1, 256, 0, st>>>(dbase);
+    radix_scatter_kernel<<<P->sort_blocks, kSortThreads, 0, st>>>(kw[cur][0], kw[cur][1], perm[cur], kw[cur ^ 1][0],
+                                                                  kw[cur ^ 1][1], perm[cur ^ 1], n, sh & 63u, use_hi,
+                                                                  wide, hist, P->sort_blocks, dbase);
+    HIP_TRY(hipGetLastError(), "radix pass launch");
+    cur ^= 1;
+  }
+  // prefix clique counts via the leaf pass on position keys
+  uint32_t* rank = ws.at<uint32_t>(P->off_keyp);
+  uint64_t* cnt = ws.at<uint64_t>(P->off_cnt);
+  rank_keys_kernel<<<grid_for(n), 256, 0, st>>>(perm[cur], n, rank, cnt);
+  HIP_TRY(hipGetLastError(), "rank keys launch");
+  KeySrc ks{};
+  ks.rank = rank;
+  int rc = launch_leaf(P, ws, 3, ks, cnt, st);
+  if (rc) return rc;
+  uint64_t* bsum = ws.at<uint64_t>(P->off_bsum);
+  uint64_t* bbest = ws.at<uint64_t>(P->off_bbest);
+  scan_blocksum_kernel<<<P->scan_blocks, kScanThreads, 0, st>>>(cnt, perm[cur], n, bsum);
+  scan_exclusive_single_kernel<uint64_t><<<1, 1024, 0, st>>>(bsum, P->scan_blocks);
+  scan_argmax_kernel<<<P->scan_blocks, kScanThreads, 0, st>>>(cnt, perm[cur], n, bsum, bbest);
+  argmax_final_kernel<<<1, 256, 0, st>>>(bbest, P->scan_blocks, dres);
+  copy_u32_kernel<<<grid_for(n), 256, 0, st>>>(perm[cur], d_order, n);
+  HIP_TRY(hipGetLastError(), "prefix count launch");
+  return KDSS_OK;
+}
+
+void fill_result(const kdss_plan* P, const DevResult& d, uint32_t T, kdss_result* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->T = T;
+  out->n = P->n;
+  out->size = d.size;
+  out->width = P->width;
+  out->dens_num.lo = d.dens_num;
+  out->dens_num.hi = 0;
+  out->ub_num.lo = d.ub_lo;
+  out->ub_num.hi = d.ub_hi;
+  out->c_k.lo = (uint64_t)P->c_k;
+  out->c_k.hi = (uint64_t)(P->c_k >> 64);
+  out->density = d.size ? (double)d.dens_num / (double)d.size : 0.0;
+  const double ub = (double)d.ub_hi * 18446744073709551616.0 + (double)d.ub_lo;
+  out->upper_bound = T ? ub / (double)T : 0.0;
+}
+
+int check_ws(const kdss_plan* P, void* d_ws, size_t ws_bytes) {
+  if (!d_ws) return fail(KDSS_EINVAL, "null workspace");
+  if (ws_bytes < P->ws_bytes) return fail(KDSS_EWORKSPACE, "workspace smaller than kdss_plan_info().workspace_bytes");
+  if (P->uploaded_ws != d_ws) return fail(KDSS_EWORKSPACE, "workspace was not filled by kdss_plan_upload");
+  return KDSS_OK;
+}
+
+int read_result(const kdss_plan* P, const WsView& ws, hipStream_t st, DevResult* h) {
+  HIP_TRY(hipMemcpyAsync(h, ws.at<DevResult>(P->off_dres), sizeof(DevResult), hipMemcpyDeviceToHost, st),
+          "result copy");
+  HIP_TRY(hipStreamSynchronize(st), "stream synchronize");
+  return KDSS_OK;
+}
+
+void drop_graph(kdss_plan* P) {
+  if (P->graph_exec) hipGraphExecDestroy(static_cast<hipGraphExec_t>(P->graph_exec));
+  P->graph_exec = nullptr;
+  P->graph_ws = nullptr;
+  P->graph_r = nullptr;
+}
+
+// Captures one iteration into a graph on a private stream (the caller's
+// stream may be the null stream, which cannot be captured).
+int ensure_graph(kdss_plan* P, const WsView& ws, void* d_r) {
+  if (P->graph_exec && P->graph_ws == ws.base && P->graph_r == d_r) return KDSS_OK;
+  drop_graph(P);
+  if (!P->capture_stream) {
+    hipStream_t s;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "capture stream");
+    P->capture_stream = s;
+  }
+  hipStream_t cs = static_cast<hipStream_t>(P->capture_stream);
+  HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+  int rc = launch_iteration(P, ws, d_r, cs);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+  P->graph_exec = ex;
+  P->graph_ws = ws.base;
+  P->graph_r = d_r;
+  return KDSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void kdss_plan_free(kdss_plan* P) {
+  if (!P) return;
+  drop_graph(P);
+  for (void* e : P->events) hipEventDestroy(static_cast<hipEvent_t>(e));
+  if (P->capture_stream) hipStreamDestroy(static_cast<hipStream_t>(P->capture_stream));
+  delete P;
+}
+
+int kdss_plan_upload(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!P || !d_ws) return fail(KDSS_EINVAL, "null argument");
+  if (ws_bytes < P->ws_bytes) return fail(KDSS_EWORKSPACE, "workspace smaller than kdss_plan_info().workspace_bytes");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WsView ws{static_cast<char*>(d_ws)};
+  if (!P->members.empty())
+    HIP_TRY(hipMemcpyAsync(ws.at<uint32_t>(P->off_members), P->members.data(), P->members.size() * 4,
+                           hipMemcpyHostToDevice, st), "upload members");
+  if (!P->hdr.empty())
+    HIP_TRY(hipMemcpyAsync(ws.at<uint32_t>(P->off_hdr), P->hdr.data(), P->hdr.size() * 4, hipMemcpyHostToDevice, st),
+            "upload headers");
+  if (!P->tiles.empty())
+    HIP_TRY(hipMemcpyAsync(ws.at<Tile>(P->off_tiles), P->tiles.data(), P->tiles.size() * sizeof(Tile),
+                           hipMemcpyHostToDevice, st), "upload tiles");
+  HIP_TRY(hipMemcpyAsync(ws.at<uint64_t>(P->off_binom), P->binom.data(), P->binom.size() * 8, hipMemcpyHostToDevice,
+                         st), "upload binomials");
+  if (!P->hot.empty())
+    HIP_TRY(hipMemcpyAsync(ws.at<uint32_t>(P->off_hot), P->hot.data(), P->hot.size() * 4, hipMemcpyHostToDevice, st),
+            "upload hot nodes");
+  HIP_TRY(hipStreamSynchronize(st), "upload synchronize");
+  P->uploaded_ws = d_ws;
+  return KDSS_OK;
+}
+
+int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64_t* d_r0, void* d_r,
+             uint32_t* d_order, kdss_trace_row* h_trace, uint32_t trace_cap, kdss_result* h_res, void* stream) {
+  if (!P || !d_r || !d_order || !h_res) return fail(KDSS_EINVAL, "null argument");
+  if (T == 0 || T > P->T_max) return fail(KDSS_EINVAL, "T must be in 1..T_max");
+  int rc = check_ws(P, d_ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WsView ws{static_cast<char*>(d_ws)};
+  DevResult* dres = ws.at<DevResult>(P->off_dres);
+  reset_result_kernel<<<1, 64, 0, st>>>(dres);
+  init_loads_kernel<<<grid_for(P->n), 256, 0, st>>>(d_r0, static_cast<uint64_t*>(d_r), ws.at<uint64_t>(P->off_delta),
+                                                    ws.at<uint64_t>(P->off_key), P->n, P->id_bits,
+                                                    P->key_mode == 0 ? 1 : 0, P->width == 128 ? 1 : 0, dres);
+  HIP_TRY(hipGetLastError(), "init launch");
+  const uint32_t every = P->opts.extract_every;
+  const bool timed = P->opts.time_kernels != 0;
+  if (timed) {
+    while (P->events.size() < 3ull * T) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e), "event create");
+      P->events.push_back(e);
+    }
+  }
+  uint32_t rows = 0;
+  for (uint32_t t = 1; t <= T; ++t) {
+    if (timed) {
+      hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data()) + 3ull * (t - 1);
+      uint64_t* delta = ws.at<uint64_t>(P->off_delta);
+      HIP_TRY(hipEventRecord(ev[0], st), "event record");
+      rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st);
+      if (rc) return rc;
+      HIP_TRY(hipEventRecord(ev[1], st), "event record");
+      if (P->width == 128) {
+        apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
+      } else {
+        apply64_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta,
+                                                        ws.at<uint64_t>(P->off_key), P->n, P->id_bits,
+                                                        P->key_mode == 0 ? 1 : 0);
+      }
+      HIP_TRY(hipGetLastError(), "apply launch");
+      HIP_TRY(hipEventRecord(ev[2], st), "event record");
+    } else if (P->opts.use_graph) {
+      rc = ensure_graph(P, ws, d_r);
+      if (rc) return rc;
+      HIP_TRY(hipGraphLaunch(static_cast<hipGraphExec_t>(P->graph_exec), st), "graph launch");
+    } else {
+      rc = launch_iteration(P, ws, d_r, st);
+      if (rc) return rc;
+    }
+    if (every && t % every == 0 && t < T && h_trace && rows < trace_cap) {
+      const u128 bound = (u128)P->r0_max + (u128)t * P->c_k;
+      rc = launch_extract(P, ws, d_r, d_r0, bound, d_order, st);
+      if (rc) return rc;
+      DevResult h;
+      rc = read_result(P, ws, st, &h);
+      if (rc) return rc;
+      kdss_trace_row& row = h_trace[rows++];
+      row.t = t;
+      row.size = h.size;
+      row.dens_num.lo = h.dens_num;
+      row.dens_num.hi = 0;
+      row.ub_num.lo = h.ub_lo;
+      row.ub_num.hi = h.ub_hi;
+    }
+  }
+  const u128 bound = (u128)P->r0_max + (u128)T * P->c_k;
+  rc = launch_extract(P, ws, d_r, d_r0, bound, d_order, st);
+  if (rc) return rc;
+  DevResult h;
+  rc = read_result(P, ws, st, &h);
+  if (rc) return rc;
+  if (h.r0max > P->r0_max) return fail(KDSS_EOVERFLOW, "a start load exceeds the plan's r0_max");
+  if (timed) {
+    hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data());
+    for (uint32_t t = 0; t < T; ++t) {
+      float a = 0.f, b = 0.f;
+      HIP_TRY(hipEventElapsedTime(&a, ev[3 * t], ev[3 * t + 1]), "event elapsed");
+      HIP_TRY(hipEventElapsedTime(&b, ev[3 * t + 1], ev[3 * t + 2]), "event elapsed");
+      P->timing.leaf_ms += a;
+      P->timing.apply_ms += b;
+    }
+    P->timing.leaf_launches += T;
+    P->timing.apply_launches += T;
+  }
+  fill_result(P, h, T, h_res);
+  if (every && h_trace && rows < trace_cap) {
+    kdss_trace_row& row = h_trace[rows++];
+    row.t = T;
+    row.size = h.size;
+    row.dens_num = h_res->dens_num;
+    row.ub_num = h_res->ub_num;
+  }
+  return KDSS_OK;
+}
+
+int kdss_plan_timing(kdss_plan* P, kdss_timing* out, int reset) {
+  if (!P || !out) return fail(KDSS_EINVAL, "null argument");
+  *out = P->timing;
+  if (reset) P->timing = kdss_timing{};
+  return KDSS_OK;
+}
+
+int kdss_leaf_credit(kdss_plan* P, void* d_ws, size_t ws_bytes, const void* d_r, uint64_t* d_out, void* stream) {
+  if (!P || !d_r || !d_out) return fail(KDSS_EINVAL, "null argument");
+  int rc = check_ws(P, d_ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WsView ws{static_cast<char*>(d_ws)};
+  fill_u64_kernel<<<grid_for(P->n), 256, 0, st>>>(d_out, 0ull, P->n);
+  int mode = P->width == 128 ? 2 : 1;   // loads given directly: full keys
+  KeySrc s{};
+  s.r = static_cast<const uint64_t*>(d_r);
+  rc = launch_leaf(P, ws, mode, s, d_out, st);
+  if (rc) return rc;
+  HIP_TRY(hipGetLastError(), "leaf credit launch");
+  return KDSS_OK;
+}
+
+int kdss_extract(kdss_plan* P, void* d_ws, size_t ws_bytes, const void* d_r, const uint64_t* d_r0, uint32_t T,
+                 uint32_t* d_order, kdss_result* h_res, void* stream) {
+  if (!P || !d_r || !d_order || !h_res) return fail(KDSS_EINVAL, "null argument");
+  if (T == 0) return fail(KDSS_EINVAL, "T must be at least 1");
+  int rc = check_ws(P, d_ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WsView ws{static_cast<char*>(d_ws)};
+  DevResult* dres = ws.at<DevResult>(P->off_dres);
+  reset_result_kernel<<<1, 64, 0, st>>>(dres);
+  // the sort needs a bound on the loads: their maximum
+  uint64_t* red = ws.at<uint64_t>(P->off_red);
+  max_partial_kernel<<<P->red_blocks, 256, 0, st>>>(static_cast<const uint64_t*>(d_r), nullptr, P->n,
+                                                    P->width == 128 ? 1 : 0, red);
+  max_final_kernel<<<1, 256, 0, st>>>(red, P->red_blocks, &dres->pad1[0], &dres->pad1[1]);
+  HIP_TRY(hipGetLastError(), "max launch");
+  DevResult h;
+  rc = read_result(P, ws, st, &h);
+  if (rc) return rc;
+  const u128 bound = ((u128)h.pad1[1] << 64) | h.pad1[0];
+  rc = launch_extract(P, ws, d_r, d_r0, bound, d_order, st);
+  if (rc) return rc;
+  rc = read_result(P, ws, st, &h);
+  if (rc) return rc;
+  fill_result(P, h, T, h_res);
+  return KDSS_OK;
+}
+
+}  // extern "C"

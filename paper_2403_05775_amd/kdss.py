@@ -1,0 +1,314 @@
+"""Python binding of the kdss C-ABI (argument marshalling only).
+
+Every step of the method runs in libkdss.so: the clique tree is built by its
+host code and every iteration and extraction runs in its HIP kernels.  PyTorch
+only provides device memory and the stream.  The library must have been built
+(``__graft_entry__.build()``); a missing library is an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkdss.so")
+
+OK, EINVAL, EGRAPH, ERANGE, EOVERFLOW, EWORKSPACE, EHIP, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
+
+
+class KdssError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("nnz", C.c_uint64), ("row_ptr", C.POINTER(C.c_uint64)),
+                ("col", C.POINTER(C.c_uint32))]
+
+
+class U128(C.Structure):
+    _fields_ = [("lo", C.c_uint64), ("hi", C.c_uint64)]
+
+    @property
+    def value(self) -> int:
+        return (self.hi << 64) | self.lo
+
+
+class TreeStats(C.Structure):
+    _fields_ = [("k", C.c_uint32), ("n", C.c_uint32), ("leaves", C.c_uint64), ("members", C.c_uint64),
+                ("s_max", C.c_uint32), ("degeneracy", C.c_uint32), ("c_k", U128),
+                ("build_seconds", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("width", C.c_int), ("use_graph", C.c_int), ("extract_every", C.c_uint32),
+                ("time_kernels", C.c_int)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("leaf_launches", C.c_uint64), ("leaf_ms", C.c_double), ("apply_launches", C.c_uint64),
+                ("apply_ms", C.c_double)]
+
+
+class PlanStats(C.Structure):
+    _fields_ = [("workspace_bytes", C.c_uint64), ("stream_bytes", C.c_uint64), ("width", C.c_int),
+                ("key_mode", C.c_int), ("id_bits", C.c_uint32), ("T_max", C.c_uint32),
+                ("tiles", C.c_uint64 * 5), ("leaves", C.c_uint64 * 5), ("members", C.c_uint64 * 5)]
+
+
+class Result(C.Structure):
+    _fields_ = [("T", C.c_uint32), ("size", C.c_uint32), ("n", C.c_uint32), ("width", C.c_int),
+                ("dens_num", U128), ("ub_num", U128), ("c_k", U128), ("density", C.c_double),
+                ("upper_bound", C.c_double)]
+
+
+class TraceRow(C.Structure):
+    _fields_ = [("t", C.c_uint32), ("size", C.c_uint32), ("dens_num", U128), ("ub_num", U128)]
+
+
+EXPORTS = [
+    "kdss_status_string", "kdss_last_error", "kdss_csr_validate", "kdss_sct_build", "kdss_sct_info",
+    "kdss_sct_export", "kdss_sct_core_numbers", "kdss_sct_free", "kdss_plan_create", "kdss_plan_info",
+    "kdss_plan_free", "kdss_plan_upload", "kdss_run", "kdss_leaf_credit", "kdss_extract", "kdss_plan_timing",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libkdss.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    L = C.CDLL(LIB_PATH)
+    vp, p64, p32 = C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)
+    L.kdss_status_string.restype = C.c_char_p
+    L.kdss_status_string.argtypes = [C.c_int]
+    L.kdss_last_error.restype = C.c_char_p
+    L.kdss_csr_validate.argtypes = [C.POINTER(Csr)]
+    L.kdss_sct_build.argtypes = [C.POINTER(Csr), C.c_uint32, C.c_uint32, C.POINTER(vp)]
+    L.kdss_sct_info.argtypes = [vp, C.POINTER(TreeStats)]
+    L.kdss_sct_export.argtypes = [vp, p32, p32, p32, C.c_uint64, C.c_uint64]
+    L.kdss_sct_core_numbers.argtypes = [vp, p32, C.c_uint32]
+    L.kdss_sct_free.argtypes = [vp]
+    L.kdss_sct_free.restype = None
+    L.kdss_plan_create.argtypes = [vp, C.c_uint32, C.c_uint64, C.POINTER(Opts), C.POINTER(vp)]
+    L.kdss_plan_info.argtypes = [vp, C.POINTER(PlanStats)]
+    L.kdss_plan_free.argtypes = [vp]
+    L.kdss_plan_free.restype = None
+    L.kdss_plan_upload.argtypes = [vp, vp, C.c_size_t, vp]
+    L.kdss_plan_timing.argtypes = [vp, C.POINTER(Timing), C.c_int]
+    L.kdss_run.argtypes = [vp, vp, C.c_size_t, C.c_uint32, vp, vp, vp, C.POINTER(TraceRow), C.c_uint32,
+                           C.POINTER(Result), vp]
+    L.kdss_leaf_credit.argtypes = [vp, vp, C.c_size_t, vp, vp, vp]
+    L.kdss_extract.argtypes = [vp, vp, C.c_size_t, vp, vp, C.c_uint32, vp, C.POINTER(Result), vp]
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        detail = lib().kdss_last_error().decode(errors="replace")
+        raise KdssError(status, where, detail or lib().kdss_status_string(status).decode())
+
+
+def _csr(graph):
+    rp = np.ascontiguousarray(graph.row_ptr, dtype=np.uint64)
+    col = np.ascontiguousarray(graph.col, dtype=np.uint32)
+    if col.size == 0:
+        col = np.zeros(1, dtype=np.uint32)
+    c = Csr(graph.n, int(rp[graph.n]), rp.ctypes.data_as(C.POINTER(C.c_uint64)),
+            col.ctypes.data_as(C.POINTER(C.c_uint32)))
+    return c, (rp, col)
+
+
+def validate(graph) -> int:
+    c, keep = _csr(graph)
+    return lib().kdss_csr_validate(C.byref(c))
+
+
+class Tree:
+    """The k-pruned succinct clique tree of a graph, built by the library's host code."""
+
+    def __init__(self, graph, k: int, threads: int = 0):
+        c, keep = _csr(graph)
+        h = C.c_void_p()
+        _check(lib().kdss_sct_build(C.byref(c), k, threads, C.byref(h)), "kdss_sct_build")
+        self._h = h
+        self.n, self.k = graph.n, k
+
+    def stats(self) -> TreeStats:
+        s = TreeStats()
+        _check(lib().kdss_sct_info(self._h, C.byref(s)), "kdss_sct_info")
+        return s
+
+    def export(self):
+        """(h, p, members) of the kept leaves."""
+        s = self.stats()
+        h = np.zeros(max(s.leaves, 1), dtype=np.uint32)
+        p = np.zeros(max(s.leaves, 1), dtype=np.uint32)
+        m = np.zeros(max(s.members, 1), dtype=np.uint32)
+        P32 = C.POINTER(C.c_uint32)
+        _check(lib().kdss_sct_export(self._h, h.ctypes.data_as(P32), p.ctypes.data_as(P32), m.ctypes.data_as(P32),
+                                     h.size, m.size), "kdss_sct_export")
+        return h[: s.leaves], p[: s.leaves], m[: s.members]
+
+    def core_numbers(self) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.uint32)
+        _check(lib().kdss_sct_core_numbers(self._h, out.ctypes.data_as(C.POINTER(C.c_uint32)), self.n),
+               "kdss_sct_core_numbers")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kdss_sct_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Plan:
+    """Device layout of a tree; owns nothing on the device."""
+
+    def __init__(self, tree: Tree, T_max: int, r0_max: int = 0, width: int = 0, use_graph: bool = False,
+                 extract_every: int = 0, time_kernels: bool = False):
+        o = Opts(width, 1 if use_graph else 0, extract_every, 1 if time_kernels else 0)
+        h = C.c_void_p()
+        _check(lib().kdss_plan_create(tree._h, T_max, r0_max, C.byref(o), C.byref(h)), "kdss_plan_create")
+        self._h = h
+        self.n, self.k, self.T_max = tree.n, tree.k, T_max
+        self.extract_every = extract_every
+        st = self.stats()
+        self.width = st.width
+        self.workspace_bytes = st.workspace_bytes
+
+    def stats(self) -> PlanStats:
+        s = PlanStats()
+        _check(lib().kdss_plan_info(self._h, C.byref(s)), "kdss_plan_info")
+        return s
+
+    def timing(self, reset: bool = False) -> Timing:
+        t = Timing()
+        _check(lib().kdss_plan_timing(self._h, C.byref(t), 1 if reset else 0), "kdss_plan_timing")
+        return t
+
+    def alloc_workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def alloc_loads(self, device="cuda"):
+        import torch
+        words = self.n * (2 if self.width == 128 else 1)
+        return torch.empty(max(words, 1), dtype=torch.int64, device=device)
+
+    def upload(self, ws, stream=None):
+        _check(lib().kdss_plan_upload(self._h, _ptr(ws), ws.numel(), _stream(stream)), "kdss_plan_upload")
+
+    def run(self, ws, T: int, r, order, r0=None, trace_cap: int = 0, stream=None):
+        res = Result()
+        rows = (TraceRow * trace_cap)() if trace_cap else None
+        _check(lib().kdss_run(self._h, _ptr(ws), ws.numel(), T, _ptr(r0), _ptr(r), _ptr(order),
+                              C.cast(rows, C.POINTER(TraceRow)) if rows is not None else None, trace_cap,
+                              C.byref(res), _stream(stream)), "kdss_run")
+        trace = None
+        if rows is not None:
+            trace = [dict(t=x.t, size=x.size, dens_num=x.dens_num.value, ub_num=x.ub_num.value)
+                     for x in rows if x.t]
+        return res, trace
+
+    def leaf_credit(self, ws, r, out, stream=None):
+        _check(lib().kdss_leaf_credit(self._h, _ptr(ws), ws.numel(), _ptr(r), _ptr(out), _stream(stream)),
+               "kdss_leaf_credit")
+
+    def extract(self, ws, r, order, T: int, r0=None, stream=None) -> Result:
+        res = Result()
+        _check(lib().kdss_extract(self._h, _ptr(ws), ws.numel(), _ptr(r), _ptr(r0), T, _ptr(order),
+                                  C.byref(res), _stream(stream)), "kdss_extract")
+        return res
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kdss_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def loads_to_numpy(r_tensor, n: int, width: int):
+    """Device loads -> numpy uint64 (width 64) or a list of Python ints (width 128)."""
+    a = r_tensor.cpu().numpy().view(np.uint64)
+    if width == 64:
+        return a[:n].copy()
+    lo, hi = a[0: 2 * n: 2], a[1: 2 * n: 2]
+    if not np.any(hi):
+        return lo.copy()
+    return [(int(h) << 64) | int(l) for l, h in zip(lo, hi)]
+
+
+@dataclass
+class Solution:
+    r: object                 # numpy uint64[n] or list of ints
+    order: np.ndarray         # uint32[n]
+    size: int
+    dens_num: int
+    ub_num: int
+    T: int
+    c_k: int
+    width: int
+    trace: list | None
+    tree_stats: TreeStats
+    plan_stats: PlanStats
+
+    @property
+    def nodes(self) -> np.ndarray:
+        return self.order[: self.size]
+
+
+def solve(graph, k: int, T: int, r0=None, width: int = 0, use_graph: bool = False, extract_every: int = 0,
+          threads: int = 0, device="cuda") -> Solution:
+    """Build the tree, lay it out, run T iterations and the extraction on the GPU."""
+    import torch
+    tree = Tree(graph, k, threads)
+    r0_max = 0 if r0 is None else int(np.max(np.asarray(r0, dtype=np.uint64))) if graph.n else 0
+    plan = Plan(tree, T, r0_max, width=width, use_graph=use_graph, extract_every=extract_every)
+    ws = plan.alloc_workspace(device)
+    plan.upload(ws)
+    r = plan.alloc_loads(device)
+    order = torch.empty(max(graph.n, 1), dtype=torch.int32, device=device)
+    r0_t = None
+    if r0 is not None:
+        r0_t = torch.from_numpy(np.asarray(r0, dtype=np.uint64).view(np.int64).copy()).to(device)
+    cap = (T // extract_every + 1) if extract_every else 0
+    res, trace = plan.run(ws, T, r, order, r0=r0_t, trace_cap=cap)
+    torch.cuda.synchronize()
+    out = Solution(r=loads_to_numpy(r, graph.n, plan.width),
+                   order=order.cpu().numpy().view(np.uint32)[: graph.n].copy(), size=res.size,
+                   dens_num=res.dens_num.value, ub_num=res.ub_num.value, T=res.T, c_k=res.c_k.value,
+                   width=res.width, trace=trace, tree_stats=tree.stats(), plan_stats=plan.stats())
+    plan.close()
+    tree.close()
+    return out

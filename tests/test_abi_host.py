@@ -1,0 +1,188 @@
+"""Host-side tests of the C-ABI library: exports, graph checks, the clique tree
+builder and the planner.  No GPU call is made here."""
+from __future__ import annotations
+
+import ctypes as C
+import itertools
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2403_05775_amd import kdss, synth
+from tests.test_oracle_pins import example_graph
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "kdss.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kdss_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = kdss.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(kdss.EXPORTS) | (set(names) - set(kdss.EXPORTS))
+    for name in kdss.EXPORTS:
+        assert name in names
+
+
+def test_status_strings():
+    L = kdss.lib()
+    for code in range(0, -9, -1):
+        assert L.kdss_status_string(code)
+    assert L.kdss_status_string(0) == b"ok"
+
+
+def test_validate_codes():
+    good = synth.from_edge_list(4, [(0, 1), (1, 2), (2, 3)])
+    assert kdss.validate(good) == kdss.OK
+    bad = synth.Graph(n=4, row_ptr=good.row_ptr.copy(), col=np.array([1, 2, 0, 1, 3, 2], np.uint32))
+    assert kdss.validate(bad) == kdss.EGRAPH
+    bad2 = synth.Graph(n=4, row_ptr=np.array([0, 0, 2, 4, 5], np.uint64), col=np.array([0, 2, 1, 3, 2], np.uint32))
+    assert kdss.validate(bad2) == kdss.EGRAPH
+    with pytest.raises(kdss.KdssError) as e:
+        kdss.Tree(bad, 3)
+    assert e.value.status == kdss.EGRAPH
+
+
+def test_tree_argument_errors():
+    g = synth.complete_graph(6)
+    for k, code in [(1, kdss.EINVAL), (0, kdss.EINVAL), (32, kdss.ERANGE)]:
+        with pytest.raises(kdss.KdssError) as e:
+            kdss.Tree(g, k)
+        assert e.value.status == code
+
+
+def expand(h, p, m, k):
+    out, off = [], 0
+    for hh, pp in zip(h, p):
+        H = [int(x) for x in m[off: off + hh]]
+        P = [int(x) for x in m[off + hh: off + hh + pp]]
+        off += hh + pp
+        for c in itertools.combinations(P, k - hh):
+            out.append(tuple(sorted(H + list(c))))
+    return out
+
+
+def test_example_tree_matches_paper_pairs():
+    """Example 2 prints five pairs, each with one hold node; the library's tree of
+    the same graph has the same number of leaves and the same pair sizes, and for
+    k = 3 (Lemma 5) encodes the 9 triangles of Example 1."""
+    g, pairs, vals = example_graph()
+    t = kdss.Tree(g, 3)
+    h, p, m = t.export()
+    assert len(h) == len(pairs)
+    assert sorted(zip(h.tolist(), p.tolist())) == sorted((len(a), len(b)) for a, b in pairs)
+    assert t.stats().c_k.value == vals["triangles"][0]
+    assert len(set(expand(h, p, m, 3))) == 9
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_tree_expansion_equals_enumeration(oracle_mod, seed):
+    """Lemma 4: the kept leaves partition C_k(V); every leaf is a clique; h <= k <= h + p."""
+    rs = synth.Stream(seed, 51)
+    n = int(rs.integers(20, 45)[0])
+    g = synth.erdos_renyi(n, 0.35, seed=seed, planted_clique=int(rs.integers(0, 12)[0]))
+    A = set()
+    rp = g.row_ptr.astype(np.int64)
+    for u in range(n):
+        for e in range(rp[u], rp[u + 1]):
+            A.add((u, int(g.col[e])))
+    for k in range(2, 9):
+        t = kdss.Tree(g, k)
+        h, p, m = t.export()
+        assert np.all(h <= k) and np.all(h + p >= k)
+        off = 0
+        for hh, pp in zip(h, p):
+            leaf = [int(x) for x in m[off: off + hh + pp]]
+            off += hh + pp
+            assert all((a, b) in A for a, b in itertools.combinations(leaf, 2))
+        got = expand(h, p, m, k)
+        ref = {tuple(int(x) for x in c) for c in oracle_mod.list_cliques(g.n, g.row_ptr, g.col, k)}
+        assert len(got) == len(set(got)) == len(ref)
+        assert set(got) == ref
+        assert t.stats().c_k.value == len(ref)
+        assert t.stats().members == int(np.sum(h + p))
+
+
+def test_tree_power_law_counts(oracle_mod):
+    g = synth.chung_lu(3000, 30000, 2.3, seed=4, planted=25)
+    for k in (3, 5, 7):
+        t = kdss.Tree(g, k)
+        assert t.stats().c_k.value == oracle_mod.count(g.n, g.row_ptr, g.col, k)
+
+
+def test_tree_independent_of_threads():
+    g = synth.chung_lu(5000, 40000, 2.4, seed=2)
+    a = kdss.Tree(g, 4, threads=1).export()
+    b = kdss.Tree(g, 4, threads=7).export()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_core_numbers_match_peeling():
+    g = synth.chung_lu(500, 3000, 2.3, seed=3)
+    core = kdss.Tree(g, 3).core_numbers()
+    # peeling by repeatedly removing a minimum-degree node (quadratic, tiny n)
+    adj = [set() for _ in range(g.n)]
+    rp = g.row_ptr.astype(np.int64)
+    for u in range(g.n):
+        for e in range(rp[u], rp[u + 1]):
+            adj[u].add(int(g.col[e]))
+    alive = set(range(g.n))
+    deg = {u: len(adj[u]) for u in alive}
+    ref = np.zeros(g.n, dtype=np.int64)
+    cur = 0
+    while alive:
+        u = min(alive, key=lambda x: (deg[x], x))
+        cur = max(cur, deg[u])
+        ref[u] = cur
+        alive.remove(u)
+        for v in adj[u]:
+            if v in alive:
+                deg[v] -= 1
+    assert np.array_equal(core.astype(np.int64), ref)
+
+
+def test_plan_layout_and_errors():
+    g = synth.chung_lu(2000, 20000, 2.3, seed=5, planted=30)
+    t = kdss.Tree(g, 4)
+    ts = t.stats()
+    p = kdss.Plan(t, 50)
+    s = p.stats()
+    assert sum(s.leaves) == ts.leaves and sum(s.members) == ts.members
+    assert s.width == 64 and s.workspace_bytes > s.stream_bytes
+    with pytest.raises(kdss.KdssError) as e:
+        kdss.Plan(t, 0)
+    assert e.value.status == kdss.EINVAL
+    with pytest.raises(kdss.KdssError) as e:
+        kdss.Plan(t, 10, r0_max=2**64 - 2, width=64)
+    assert e.value.status == kdss.EOVERFLOW
+    assert kdss.Plan(t, 10, r0_max=2**64 - 2).stats().width == 128
+    assert kdss.Plan(t, 10, width=128).stats().width == 128
+    assert kdss.Plan(t, 10, r0_max=2**60).stats().key_mode == 1
+
+
+def test_run_rejects_bad_arguments_before_device_work():
+    g = synth.complete_graph(8)
+    t = kdss.Tree(g, 3)
+    p = kdss.Plan(t, 5)
+    L = kdss.lib()
+    res = kdss.Result()
+    # null workspace / not uploaded workspace / T out of range: host checks only
+    assert L.kdss_run(p._h, None, 0, 3, None, C.c_void_p(8), C.c_void_p(8), None, 0, C.byref(res), None) == kdss.EINVAL
+    assert L.kdss_run(p._h, C.c_void_p(256), p.workspace_bytes, 3, None, C.c_void_p(8), C.c_void_p(8), None, 0,
+                      C.byref(res), None) == kdss.EWORKSPACE
+    assert L.kdss_run(p._h, C.c_void_p(256), p.workspace_bytes, 9, None, C.c_void_p(8), C.c_void_p(8), None, 0,
+                      C.byref(res), None) == kdss.EINVAL
+    assert L.kdss_run(p._h, C.c_void_p(256), 16, 3, None, C.c_void_p(8), C.c_void_p(8), None, 0,
+                      C.byref(res), None) == kdss.EWORKSPACE
+    assert b"workspace" in L.kdss_last_error()

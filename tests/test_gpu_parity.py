@@ -1,0 +1,179 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Loads, order, node set, density and upper bound must be bit-exact: every count
+is an integer and the synchronous update does not depend on leaf order."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2403_05775_amd import synth
+from tests.test_oracle_pins import example_graph
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_05775_amd import kdss
+    kdss.lib()
+    return kdss
+
+
+def ref(O, g, k, T, r0=None, trace=False):
+    return O.solve(g.n, g.row_ptr, g.col, k, T, r0=r0, trace=trace)
+
+
+def assert_same(sol, res, T, label=""):
+    r_gpu = sol.r if isinstance(sol.r, list) else sol.r.tolist()
+    r_ref = res["r"] if isinstance(res["r"], list) else res["r"].tolist()
+    assert [int(x) for x in r_gpu] == [int(x) for x in r_ref], f"loads differ {label}"
+    assert sol.c_k == res["c_k"], label
+    assert np.array_equal(sol.order, res["order"]), f"order differs {label}"
+    assert (sol.size, sol.dens_num, sol.ub_num) == (res["size"], res["dens_num"], res["ub_num"]), label
+    assert sol.T == T
+
+
+def test_example_graph(K, oracle_mod):
+    g, _, vals = example_graph()
+    for T in (1, 2, 5, 64):
+        print(f"example graph k=3 T={T}", flush=True)
+        sol = K.solve(g, 3, T)
+        assert_same(sol, ref(oracle_mod, g, 3, T), T, f"T={T}")
+    sol = K.solve(g, 3, 64)
+    assert sorted(sol.nodes.tolist()) == vals["densest_set"]
+
+
+def test_er_planted_trace(K, oracle_mod):
+    """ER G(200, 0.08) seed 0 + planted 12-clique, k = 3, T = 64, extraction after every iteration."""
+    g = synth.erdos_renyi(200, 0.08, seed=0, planted_clique=12)
+    print("er200 k=3 T=64 trace", flush=True)
+    sol = K.solve(g, 3, 64, extract_every=1)
+    res = ref(oracle_mod, g, 3, 64, trace=True)
+    assert_same(sol, res, 64)
+    assert len(sol.trace) == 64
+    for a, b in zip(sol.trace, res["trace"]):
+        assert (a["t"], a["size"], a["dens_num"], a["ub_num"]) == (b["t"], b["size"], b["dens_num"], b["ub_num"])
+    # the planted 12-clique is the densest subgraph here: density C(12,3)/12 = 55/3
+    assert sol.size == 12 and sol.dens_num == 220
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_graphs(K, oracle_mod, seed):
+    rs = synth.Stream(seed, 61)
+    n = int(rs.integers(30, 400)[0])
+    m = int(rs.integers(n, 6 * n)[0])
+    beta = 2.1 + 0.8 * float(rs.uniform(1)[0])
+    planted = int(rs.integers(0, 20)[0])
+    g = synth.chung_lu(n, m, beta, seed=seed, planted=planted)
+    k = int(rs.integers(2, 8)[0])
+    T = int(rs.integers(1, 40)[0])
+    r0 = None
+    if seed % 3 == 1:
+        r0 = (rs.u64(n) % np.uint64(4)).astype(np.uint64)       # many ties
+    elif seed % 3 == 2:
+        r0 = (rs.u64(n) % np.uint64(1000)).astype(np.uint64)
+    print(f"random seed={seed} n={n} m={m} k={k} T={T} r0={'yes' if r0 is not None else 'no'}", flush=True)
+    sol = K.solve(g, k, T, r0=r0)
+    assert_same(sol, ref(oracle_mod, g, k, T, r0=r0), T, f"seed={seed}")
+
+
+@pytest.mark.parametrize("k,planted", [(2, 70), (3, 70), (4, 70), (5, 30), (6, 30), (8, 30)])
+def test_every_size_class(K, oracle_mod, k, planted):
+    """Leaves of 2..64 members, and above 64 with a planted 70-clique (kept small
+    enough for the oracle to list every k-clique)."""
+    g = synth.erdos_renyi(260, 0.12, seed=7, planted_clique=planted)
+    T = 6
+    print(f"size classes k={k} planted={planted}", flush=True)
+    sol = K.solve(g, k, T)
+    if planted > 64:
+        assert sol.plan_stats.leaves[4] > 0
+    assert_same(sol, ref(oracle_mod, g, k, T), T, f"k={k}")
+
+
+def test_graph_replay_and_determinism(K, oracle_mod):
+    g = synth.chung_lu(3000, 20000, 2.3, seed=11, planted=25)
+    print("graph replay k=4 T=30", flush=True)
+    a = K.solve(g, 4, 30, use_graph=True)
+    b = K.solve(g, 4, 30)
+    c = K.solve(g, 4, 30)
+    assert_same(a, ref(oracle_mod, g, 4, 30), 30)
+    for x in (b, c):
+        assert np.array_equal(a.r, x.r) and np.array_equal(a.order, x.order) and a.size == x.size
+
+
+def test_full_keys_and_wide_loads(K, oracle_mod):
+    """Start loads near 2^62 force full (load, id) keys; near 2^64 force 128-bit loads."""
+    g = synth.chung_lu(600, 5000, 2.3, seed=12, planted=15)
+    rs = synth.Stream(12, 71)
+    base = np.uint64(2**62)
+    r0 = base + (rs.u64(g.n) % np.uint64(3)).astype(np.uint64)
+    print("full keys", flush=True)
+    sol = K.solve(g, 4, 7, r0=r0)
+    assert sol.plan_stats.key_mode == 1 and sol.width == 64
+    assert_same(sol, ref(oracle_mod, g, 4, 7, r0=r0), 7)
+    r0w = np.uint64(2**64 - 50) + (rs.u64(g.n) % np.uint64(5)).astype(np.uint64)
+    print("wide loads", flush=True)
+    sol = K.solve(g, 4, 7, r0=r0w)
+    assert sol.width == 128
+    res = ref(oracle_mod, g, 4, 7, r0=r0w)
+    assert isinstance(res["r"], list)
+    assert_same(sol, res, 7)
+    print("forced width 128", flush=True)
+    sol = K.solve(g, 3, 5, width=128)
+    assert sol.width == 128
+    assert_same(sol, ref(oracle_mod, g, 3, 5), 5)
+
+
+def test_leaf_credit_with_forced_ties(K, oracle_mod):
+    """One credit pass at arbitrary loads with many equal values (ties by id)."""
+    from paper_2403_05775_amd import kdss
+    g = synth.chung_lu(2000, 16000, 2.2, seed=13, planted=30)
+    for k in (3, 5):
+        tree = kdss.Tree(g, k)
+        plan = kdss.Plan(tree, 1)
+        ws = plan.alloc_workspace()
+        plan.upload(ws)
+        for trial in range(3):
+            rs = synth.Stream(100 + trial, 81)
+            r = (rs.u64(g.n) % np.uint64(3 + 7 * trial)).astype(np.uint64)
+            rt = torch.from_numpy(r.view(np.int64).copy()).cuda()
+            out = torch.empty(g.n, dtype=torch.int64, device="cuda")
+            print(f"leaf credit k={k} trial={trial}", flush=True)
+            plan.leaf_credit(ws, rt, out)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy().view(np.uint64)
+            want = oracle_mod.credits(g.n, g.row_ptr, g.col, k, r)
+            assert np.array_equal(got, want)
+        plan.close()
+        tree.close()
+
+
+def test_extract_alone(K, oracle_mod):
+    """The extraction at the oracle's own loads gives the oracle's answer."""
+    from paper_2403_05775_amd import kdss
+    g = synth.chung_lu(1500, 12000, 2.4, seed=14, planted=20)
+    res = ref(oracle_mod, g, 4, 9)
+    tree = kdss.Tree(g, 4)
+    plan = kdss.Plan(tree, 9)
+    ws = plan.alloc_workspace()
+    plan.upload(ws)
+    rt = torch.from_numpy(res["r"].view(np.int64).copy()).cuda()
+    order = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    print("extract alone", flush=True)
+    out = plan.extract(ws, rt, order, 9)
+    assert (out.size, out.dens_num.value, out.ub_num.value) == (res["size"], res["dens_num"], res["ub_num"])
+    assert np.array_equal(order.cpu().numpy().view(np.uint32), res["order"])
+
+
+def test_no_cliques(K, oracle_mod):
+    g = synth.complete_graph(6)
+    print("k above clique number", flush=True)
+    sol = K.solve(g, 7, 3)
+    assert sol.c_k == 0 and sol.size == 0 and sol.dens_num == 0 and sol.ub_num == 0
+    assert np.all(sol.r == 0)
+    assert_same(sol, ref(oracle_mod, g, 7, 3), 3)
