@@ -235,6 +235,10 @@ int kdss_plan_create(const kdss_sct* s, uint32_t T_max, uint64_t r0_max, const k
         P->class_tiles[size_bucket(smax)]++;
       }
     }
+    if (P->tiles.size() >= (1ull << 26)) {
+      delete P;
+      return fail(KDSS_ERANGE, "more than 2^26 tiles");
+    }
     if (P->hdr.size() > 0xFFFFFFFFull) {
       delete P;
       return fail(KDSS_ERANGE, "more than 2^32 - 1 leaves");
@@ -282,7 +286,13 @@ int kdss_plan_create(const kdss_sct* s, uint32_t T_max, uint64_t r0_max, const k
     P->off_dres = take(sizeof(DevResult));
     P->leaf_blocks = (uint32_t)std::min<uint64_t>(kLeafBlocksMax, std::max<uint64_t>(1, (P->tiles.size() + 3) / 4));
     P->off_hot = take(P->hot.size() * 4);
-    P->off_scratch = take((size_t)P->leaf_blocks * P->hot.size() * 8);
+    P->heavy_blocks = kHeavyBlocks;
+    P->off_scratch = take((size_t)(P->leaf_blocks + P->heavy_blocks) * P->hot.size() * 8);
+    P->lane_leaves = 0;
+    for (const Tile& tl : P->tiles)
+      if ((tl.info & 7u) == kTileLane) P->lane_leaves += (tl.info >> 3) & 0x1FFFu;
+    P->off_queue = take(P->lane_leaves * 4);
+    P->off_qcount = take(64);
     P->ws_bytes = o;
   } catch (const std::bad_alloc&) {
     delete P;

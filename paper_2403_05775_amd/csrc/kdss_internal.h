@@ -85,6 +85,7 @@ constexpr uint32_t kHotMax = 512;
 constexpr uint32_t kHotMinOccurrences = 32;
 constexpr uint32_t kHotFlag = 0x80000000u;
 constexpr uint32_t kLeafBlocksMax = 1024;        // persistent leaf-credit grid
+constexpr uint32_t kHeavyBlocks = 512;           // grid of the heavy-leaf kernel
 
 // Device-side result of an extraction.
 struct DevResult {
@@ -126,7 +127,9 @@ struct kdss_plan {
   uint32_t sort_blocks = 0, scan_blocks = 0, red_blocks = 0;
   uint32_t leaf_blocks = 0;            // persistent grid of the leaf-credit kernel
   std::vector<uint32_t> hot;           // original ids of the hot nodes
-  size_t off_hot = 0, off_scratch = 0, off_dbase = 0;
+  size_t off_hot = 0, off_scratch = 0, off_dbase = 0, off_queue = 0, off_qcount = 0;
+  uint32_t heavy_blocks = 0;           // grid of the heavy-leaf kernel
+  uint64_t lane_leaves = 0;            // leaves in lane tiles (queue capacity)
   // state of the device side
   void* uploaded_ws = nullptr;
   void* graph_exec = nullptr;          // hipGraphExec_t of one iteration

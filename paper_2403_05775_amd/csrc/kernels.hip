@@ -185,9 +185,10 @@ __device__ __forceinline__ void combine_add(Sink& sink, uint32_t key, uint64_t v
 // "low" members rank them: up to four are kept in registers, more (frequent only
 // while many loads tie, e.g. from all-zero start loads) are ranked by a rescan.
 template <class KT>
-__device__ __forceinline__ void tile_lane(const Tile& t, const uint32_t* __restrict__ members,
+__device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, const uint32_t* __restrict__ members,
                                           const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k,
-                                          const KeySrc& src, const KT* hkey, Sink& sink) {
+                                          const KeySrc& src, const KT* hkey, Sink& sink, uint32_t* __restrict__ queue,
+                                          uint32_t* __restrict__ qcount) {
   constexpr uint32_t U = 8;   // rows loaded per batch
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nl = (t.info >> 3) & 0x1FFFu, smax = t.info >> 16;
@@ -198,6 +199,10 @@ __device__ __forceinline__ void tile_lane(const Tile& t, const uint32_t* __restr
   const uint32_t* __restrict__ col = members + t.mbase + lane;
   KT km = KT::mx();
   uint32_t mraw = 0, nlow = 0;
+  // the first four low members, in row order (hold members precede pivot
+  // members, so m is final when the first pivot member is compared)
+  KT l0 = KT::mx(), l1 = KT::mx(), l2 = KT::mx(), l3 = KT::mx();
+  uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0;
   for (uint32_t x0 = 0; x0 < smax; x0 += U) {
     uint32_t raw[U];
     KT key[U];
@@ -208,75 +213,39 @@ __device__ __forceinline__ void tile_lane(const Tile& t, const uint32_t* __restr
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) {
       const uint32_t x = x0 + u;
-      const bool hold = x < h, piv = x >= h && x < s;
+      const bool hold = x < h;
       const bool better = hold && key[u].lt(km);
       km = better ? key[u] : km;
       mraw = better ? raw[u] : mraw;
-      nlow += (piv && key[u].lt(km)) ? 1u : 0u;
-    }
-  }
-  if (nlow) {
-    if (nlow <= 4) {
-      KT l0 = KT::mx(), l1 = KT::mx(), l2 = KT::mx(), l3 = KT::mx();
-      uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0, c = 0;
-      for (uint32_t x0 = 0; x0 < smax; x0 += U) {
-        uint32_t raw[U];
-        KT key[U];
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u) raw[u] = col[(size_t)min(x0 + u, smax - 1) * 64];
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u) key[u] = member_key_nb<KT>(src, hkey, raw[u]);
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u) {
-          const uint32_t x = x0 + u;
-          if (x >= h && x < s && key[u].lt(km)) {
-            if (c == 0) { l0 = key[u]; r0 = raw[u]; }
-            else if (c == 1) { l1 = key[u]; r1 = raw[u]; }
-            else if (c == 2) { l2 = key[u]; r2 = raw[u]; }
-            else { l3 = key[u]; r3 = raw[u]; }
-            ++c;
-          }
-        }
-      }
-      // rank of each low member among the low members (unused slots hold the maximum key)
-      const uint32_t b0 = (l1.lt(l0) ? 1u : 0u) + (l2.lt(l0) ? 1u : 0u) + (l3.lt(l0) ? 1u : 0u);
-      const uint32_t b1 = (l0.lt(l1) ? 1u : 0u) + (l2.lt(l1) ? 1u : 0u) + (l3.lt(l1) ? 1u : 0u);
-      const uint32_t b2 = (l0.lt(l2) ? 1u : 0u) + (l1.lt(l2) ? 1u : 0u) + (l3.lt(l2) ? 1u : 0u);
-      const uint32_t b3 = (l0.lt(l3) ? 1u : 0u) + (l1.lt(l3) ? 1u : 0u) + (l2.lt(l3) ? 1u : 0u);
-      if (j >= 1) {
-        const uint64_t* row = binom + (j - 1);
-        sink.add(r0, row[(size_t)(p - 1 - b0) * k1]);
-        if (nlow > 1) sink.add(r1, row[(size_t)(p - 1 - b1) * k1]);
-        if (nlow > 2) sink.add(r2, row[(size_t)(p - 1 - b2) * k1]);
-        if (nlow > 3) sink.add(r3, row[(size_t)(p - 1 - b3) * k1]);
+      if (!hold && x < s && key[u].lt(km)) {
+        if (nlow == 0) { l0 = key[u]; r0 = raw[u]; }
+        else if (nlow == 1) { l1 = key[u]; r1 = raw[u]; }
+        else if (nlow == 2) { l2 = key[u]; r2 = raw[u]; }
+        else if (nlow == 3) { l3 = key[u]; r3 = raw[u]; }
+        ++nlow;
       }
     }
   }
-  // Leaves with more than four low members: the whole wavefront takes them one
-  // at a time, one member per lane (lane tiles hold at most 64 members).
-  uint64_t heavy = __ballot(nlow > 4);
-  while (heavy) {
-    const int L = __ffsll((unsigned long long)heavy) - 1;
-    heavy &= heavy - 1;
-    const uint32_t hL = (uint32_t)__builtin_amdgcn_readlane((int)h, L);
-    const uint32_t sL = (uint32_t)__builtin_amdgcn_readlane((int)s, L);
-    const uint32_t pL = sL - hL, jL = k - hL;
-    const KT kmL = km.rl(L);
-    const bool va = lane < sL;
-    const uint32_t ra = va ? members[t.mbase + (size_t)lane * 64 + (uint32_t)L] : 0u;
-    const KT ka = va ? member_key<KT>(src, hkey, ra) : KT::mx();
-    const bool low = va && lane >= hL && ka.lt(kmL);
-    uint64_t bm = __ballot(low);
-    uint32_t below = 0;
-    while (bm) {
-      const int tl = __ffsll((unsigned long long)bm) - 1;
-      bm &= bm - 1;
-      below += (low && ka.rl(tl).lt(ka)) ? 1u : 0u;
-    }
-    if (low && jL >= 1) {
-      const uint64_t c = binom[(size_t)(pL - 1 - below) * k1 + (jL - 1)];
-      if (c) sink.add(ra, c);
-    }
+  if (nlow && nlow <= 4 && j >= 1) {
+    // rank of each low member among the low members (unused slots hold the maximum key)
+    const uint32_t b0 = (l1.lt(l0) ? 1u : 0u) + (l2.lt(l0) ? 1u : 0u) + (l3.lt(l0) ? 1u : 0u);
+    const uint32_t b1 = (l0.lt(l1) ? 1u : 0u) + (l2.lt(l1) ? 1u : 0u) + (l3.lt(l1) ? 1u : 0u);
+    const uint32_t b2 = (l0.lt(l2) ? 1u : 0u) + (l1.lt(l2) ? 1u : 0u) + (l3.lt(l2) ? 1u : 0u);
+    const uint32_t b3 = (l0.lt(l3) ? 1u : 0u) + (l1.lt(l3) ? 1u : 0u) + (l2.lt(l3) ? 1u : 0u);
+    const uint64_t* row = binom + (j - 1);
+    sink.add(r0, row[(size_t)(p - 1 - b0) * k1]);
+    if (nlow > 1) sink.add(r1, row[(size_t)(p - 1 - b1) * k1]);
+    if (nlow > 2) sink.add(r2, row[(size_t)(p - 1 - b2) * k1]);
+    if (nlow > 3) sink.add(r3, row[(size_t)(p - 1 - b3) * k1]);
+  }
+  // Leaves with more than four low members go to the heavy-leaf queue; the
+  // heavy kernel spreads them over the whole grid.
+  const uint64_t heavy = __ballot(nlow > 4);
+  if (heavy) {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(qcount, (uint32_t)__popcll(heavy));
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+    if (nlow > 4) queue[base + (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull))] = (tile_idx << 6) | lane;
   }
   const uint64_t cm = h ? binom[(size_t)(p - nlow) * k1 + j] : 0ull;
   combine_add(sink, cm ? mraw : 0xFFFFFFFFu, cm);
@@ -344,7 +313,8 @@ __global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict
                                                           const uint64_t* __restrict__ binom, uint32_t nbinom,
                                                           uint32_t k, KeySrc src, uint64_t* __restrict__ out,
                                                           const uint32_t* __restrict__ hot, uint32_t nhot,
-                                                          uint64_t* __restrict__ scratch) {
+                                                          uint64_t* __restrict__ scratch, uint32_t* __restrict__ queue,
+                                                          uint32_t* __restrict__ qcount) {
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kBinomLds];
@@ -363,11 +333,90 @@ __global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict
   for (uint32_t tile = blockIdx.x * 4u + w; tile < ntiles; tile += stride) {
     const Tile t = tiles[tile];
     if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k, src, hkey, sink);
-    else tile_lane<KT>(t, members, hdr, bt, k, src, hkey, sink);
+    else tile_lane<KT>(t, tile, members, hdr, bt, k, src, hkey, sink, queue, qcount);
   }
   sink.flush();
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) scratch[(size_t)blockIdx.x * nhot + i] = hcnt[i];
+}
+
+// Heavy leaves (more than four pivot members below the hold minimum), queued
+// by the leaf-credit kernel as (tile << 6 | lane): one leaf per wavefront, one
+// member per lane, four leaves per batch so their loads overlap.  The hold
+// minimum m is recomputed; the rank of a low member among the low members is
+// counted with wavefront ballots.  Hot-node credit totals go to scratch rows
+// row0 + blockIdx.x.
+template <class KT>
+__global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ tiles, const uint32_t* __restrict__ members,
+                                                    const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ binom,
+                                                    uint32_t nbinom, uint32_t k, KeySrc src, uint64_t* __restrict__ out,
+                                                    const uint32_t* __restrict__ hot, uint32_t nhot,
+                                                    uint64_t* __restrict__ scratch, uint32_t row0,
+                                                    const uint32_t* __restrict__ queue,
+                                                    const uint32_t* __restrict__ qcount) {
+  __shared__ KT hkey[kHotMax];
+  __shared__ unsigned long long hcnt[kHotMax];
+  __shared__ uint64_t sbinom[kBinomLds];
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
+    hkey[i] = KT::load(src, hot[i]);
+    hcnt[i] = 0;
+  }
+  const bool lds_binom = nbinom <= kBinomLds;
+  if (lds_binom)
+    for (uint32_t i = threadIdx.x; i < nbinom; i += blockDim.x) sbinom[i] = binom[i];
+  __syncthreads();
+  const uint64_t* bt = lds_binom ? sbinom : binom;
+  Sink sink{hcnt, out, 0u, 0ull};
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t total = *qcount;
+  const uint32_t k1 = k + 1;
+  constexpr uint32_t B = 4;
+  const uint32_t nw = gridDim.x * 4u;
+  for (uint32_t e0 = (blockIdx.x * 4u + w) * B; e0 < total; e0 += nw * B) {
+    uint32_t hq[B], sq[B], ra[B];
+    KT ka[B];
+#pragma unroll
+    for (uint32_t q = 0; q < B; ++q) {
+      const uint32_t e = min(e0 + q, total - 1);
+      const uint32_t ent = queue[e];
+      const Tile t = tiles[ent >> 6];
+      const uint32_t L = ent & 63u;
+      const uint32_t hd = hdr[t.lbase + L];
+      hq[q] = hd & 31u;
+      sq[q] = hq[q] + (hd >> 5);
+      ra[q] = lane < sq[q] ? members[t.mbase + (size_t)lane * 64 + L] : 0u;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < B; ++q) ka[q] = lane < sq[q] ? member_key_nb<KT>(src, hkey, ra[q]) : KT::mx();
+#pragma unroll
+    for (uint32_t q = 0; q < B; ++q) {
+      if (e0 + q >= total) break;
+      const uint32_t h = hq[q], s = sq[q], p = s - h, j = k - h;
+      KT kh = lane < h ? ka[q] : KT::mx();
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        const KT o = kh.sx(d);
+        if (o.lt(kh)) kh = o;
+      }
+      const bool low = lane < s && lane >= h && ka[q].lt(kh);
+      uint64_t bm = __ballot(low);
+      uint32_t below = 0;
+      while (bm) {
+        const int tl = __ffsll((unsigned long long)bm) - 1;
+        bm &= bm - 1;
+        below += (low && ka[q].rl(tl).lt(ka[q])) ? 1u : 0u;
+      }
+      if (low && j >= 1) {
+        const uint64_t c = bt[(size_t)(p - 1 - below) * k1 + (j - 1)];
+        if (c) sink.add(ra[q], c);
+      }
+    }
+  }
+  sink.flush();
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x)
+    scratch[(size_t)(row0 + blockIdx.x) * nhot + i] = hcnt[i];
 }
 
 // Hot-node totals: out[hot[i]] += sum over workgroups b of scratch[b][i].  A
@@ -377,8 +426,9 @@ constexpr uint32_t kHotRowsPerBlock = 64;
 
 __global__ __launch_bounds__(256) void hot_reduce_kernel(const uint64_t* __restrict__ scratch, uint32_t blocks,
                                                          const uint32_t* __restrict__ hot, uint32_t nhot,
-                                                         uint64_t* __restrict__ out) {
+                                                         uint64_t* __restrict__ out, uint32_t* __restrict__ qcount) {
   __shared__ uint64_t part[4][64];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *qcount = 0;   // heavy queue emptied
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
   const uint32_t i = blockIdx.x * 64u + lane;
   const uint32_t b0 = blockIdx.y * kHotRowsPerBlock;
@@ -858,9 +908,14 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   const uint32_t* hot = ws.at<uint32_t>(P->off_hot);
   const uint32_t nhot = (uint32_t)P->hot.size();
   uint64_t* scratch = ws.at<uint64_t>(P->off_scratch);
-#define KDSS_LEAF(KT) \
-  leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, (uint32_t)P->binom.size(), \
-                                                 P->k, src, out, hot, nhot, scratch)
+  uint32_t* queue = ws.at<uint32_t>(P->off_queue);
+  uint32_t* qcount = ws.at<uint32_t>(P->off_qcount);
+  const uint32_t nbinom = (uint32_t)P->binom.size();
+#define KDSS_LEAF(KT)                                                                                       \
+  leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k, src, out, \
+                                                 hot, nhot, scratch, queue, qcount);                         \
+  heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(tiles, members, hdr, binom, nbinom, P->k, src, out, hot,  \
+                                                    nhot, scratch, blocks, queue, qcount)
   switch (mode) {
     case 0: KDSS_LEAF(KPacked); break;
     case 1: KDSS_LEAF(KFull); break;
@@ -869,11 +924,11 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   }
 #undef KDSS_LEAF
   HIP_TRY(hipGetLastError(), "leaf credit launch");
-  if (nhot) {
-    const dim3 grid((nhot + 63) / 64, (blocks + kHotRowsPerBlock - 1) / kHotRowsPerBlock);
-    hot_reduce_kernel<<<grid, 256, 0, st>>>(scratch, blocks, hot, nhot, out);
-    HIP_TRY(hipGetLastError(), "hot reduce launch");
-  }
+  // hot-node totals over all leaf and heavy workgroups; also empties the queue
+  const uint32_t rows = blocks + P->heavy_blocks;
+  const dim3 grid(nhot ? (nhot + 63) / 64 : 1, nhot ? (rows + kHotRowsPerBlock - 1) / kHotRowsPerBlock : 1);
+  hot_reduce_kernel<<<grid, 256, 0, st>>>(scratch, rows, hot, nhot, out, qcount);
+  HIP_TRY(hipGetLastError(), "hot reduce launch");
   return KDSS_OK;
 }
 
@@ -1057,6 +1112,8 @@ int kdss_plan_upload(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream) {
   if (!P->hot.empty())
     HIP_TRY(hipMemcpyAsync(ws.at<uint32_t>(P->off_hot), P->hot.data(), P->hot.size() * 4, hipMemcpyHostToDevice, st),
             "upload hot nodes");
+  // the heavy-leaf queue starts empty; every leaf pass leaves it empty again
+  HIP_TRY(hipMemsetAsync(ws.at<uint32_t>(P->off_qcount), 0, 64, st), "queue reset");
   HIP_TRY(hipStreamSynchronize(st), "upload synchronize");
   P->uploaded_ws = d_ws;
   return KDSS_OK;
