@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "leaf_credit_cfg2_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "leaf_credit_chung-lu-1m_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2403_05775_amd", "csrc", "kernels.hip")
 
 WORKLOADS = {
@@ -75,6 +75,75 @@ def cpu_baseline(g, w, L, sample_T):
                 seconds=secs, listing_seconds=res["enum_seconds"])
 
 
+def counters_mode(w):
+    """A short run for rocprofv3 counter passes: 20 iterations of the workload,
+    then a plain 1 GiB device copy (three times) that calibrates the counters."""
+    import torch
+    from paper_2403_05775_amd import kdss
+    g = make_graph(w)
+    tree = kdss.Tree(g, w["k"])
+    plan = kdss.Plan(tree, w["T"])
+    ws = plan.alloc_workspace("cuda:0")
+    plan.upload(ws)
+    r = plan.alloc_loads("cuda:0")
+    order = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    plan.run(ws, 20, r, order)
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_run": "done", "workload": w}))
+
+
+def _db_rows(db):
+    import sqlite3
+    c = sqlite3.connect(db)
+    cols = [r[1] for r in c.execute("pragma table_info(counters_collection)")]
+    ki, ci, vi, di = (cols.index(x) for x in ("kernel_name", "counter_name", "value", "dispatch_id"))
+    per = {}
+    for row in c.execute("select * from counters_collection"):
+        key = (row[ki], row[di])
+        per[key] = per.get(key, 0.0) + row[vi]
+    return per
+
+
+def summarize_counters(workload, fetch_db, write_db, command):
+    """Per-launch HBM bytes of the leaf-credit kernel from FETCH_SIZE / WRITE_SIZE
+    runs, each divided by the factor the same counter shows for a 1 GiB copy."""
+    out = {"workload": workload, "kernel_sha256_16": kernel_hash(), "command": command}
+    for name, db in (("fetch", fetch_db), ("write", write_db)):
+        per = _db_rows(db)
+        leaf = [v for (k, d), v in per.items() if "leaf_credit_kernel" in k and "KPacked" in k]
+        other = [v for (k, d), v in per.items() if "anonymous namespace" not in k]
+        copy = max(other) if other else None
+        leaf_kib = sum(leaf) / len(leaf)
+        factor = copy * 1024.0 / COPY_BYTES if copy else None
+        out[name] = {"leaf_kib_per_dispatch": leaf_kib, "dispatches": len(leaf), "copy_kib": copy,
+                     "copy_bytes": COPY_BYTES, "factor": factor,
+                     "bytes_per_launch": leaf_kib * 1024.0 / factor if factor else None}
+    out["hbm_bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    return out
+
+
+def summarize_trace(db, command):
+    """Kernel-trace statistics (rocprofv3 --kernel-trace --stats) as markdown."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    lines = ["# Kernel trace: " + command, "", "Durations from the dispatch records (end - start).", "",
+             "| kernel | calls | total us | average us | min us | max us |", "|---|---|---|---|---|---|"]
+    rows = c.execute("select name, count(*), sum(end - start), avg(end - start), min(end - start), "
+                     "max(end - start) from kernels group by name order by sum(end - start) desc limit 25")
+    for name, calls, tot, avg, mn, mx in rows:
+        short = name.replace("(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| {short} | {calls} | {tot / 1e3:.1f} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | {mx / 1e3:.2f} |")
+    return "\n".join(lines) + "\n"
+
+
+COPY_BYTES = 1 << 30
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,7 +153,28 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=20)
     ap.add_argument("--graph", action="store_true", help="replay iterations as hipGraphs")
+    ap.add_argument("--mode", default="bench", choices=["bench", "counters"],
+                    help="counters: short run for rocprofv3 --pmc passes (with a copy calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
+    ap.add_argument("--summarize-trace", metavar="DB")
+    ap.add_argument("--command", default="", help="command line recorded in a summary")
+    ap.add_argument("--out", default="")
     args = ap.parse_args()
+    if args.summarize_counters:
+        res = summarize_counters(args.workload, *args.summarize_counters, args.command)
+        with open(args.out or COUNTERS, "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res))
+        return
+    if args.summarize_trace:
+        md = summarize_trace(args.summarize_trace, args.command)
+        if args.out:
+            open(args.out, "w").write(md)
+        print(md)
+        return
+    if args.mode == "counters":
+        counters_mode(WORKLOADS[args.workload])
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -133,8 +223,12 @@ def main():
     for i in range(max(1, args.steps)):
         tplan.run(ws2, T, r2, order)
     tm = tplan.timing()
-    leaf_us = 1000.0 * tm.leaf_ms / max(1, tm.leaf_launches)
+    nl = max(1, tm.leaf_launches)
+    leaf_us = 1000.0 * tm.leaf_ms / nl
+    heavy_us = 1000.0 * tm.heavy_ms / nl
+    reduce_us = 1000.0 * tm.reduce_ms / nl
     apply_us = 1000.0 * tm.apply_ms / max(1, tm.apply_launches)
+    pass_us = leaf_us + heavy_us + reduce_us
     del ws2
     # algorithmic bytes of one leaf-credit launch: the leaf stream (4 B per member,
     # 4 B per leaf header) and one 8-byte key per node
@@ -165,10 +259,13 @@ def main():
         "sct_build_s": ts.build_seconds,
         "result": {"size": res.size, "dens_num": res.dens_num.value, "ub_num": res.ub_num.value,
                    "density": res.density, "upper_bound": res.upper_bound},
-        "kernel_us": {"leaf_credit": leaf_us, "apply": apply_us},
+        "kernel_us": {"leaf_credit": leaf_us, "heavy_leaf": heavy_us, "hot_reduce": reduce_us, "apply": apply_us},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "leaf_credit_kernel<KPacked>", "bytes_per_launch": leaf_bytes},
+        "credit_pass": {"kernels": "leaf_credit + heavy_leaf + hot_reduce", "us": pass_us,
+                        "achieved": leaf_bytes / (pass_us * 1e-6) / 1e9,
+                        "frac": leaf_bytes / (pass_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

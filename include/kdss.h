@@ -88,10 +88,12 @@ typedef struct {
 } kdss_opts;
 
 typedef struct {              /* accumulated by kdss_run when time_kernels = 1  */
-    uint64_t leaf_launches;   /* Frank-Wolfe leaf-credit launches timed         */
-    double leaf_ms;           /* their summed durations (hipEvent elapsed time) */
+    uint64_t leaf_launches;   /* Frank-Wolfe credit passes timed                */
+    double leaf_ms;           /* leaf-credit kernel, summed (hipEvent time)     */
+    double heavy_ms;          /* heavy-leaf kernel that follows it              */
+    double reduce_ms;         /* hot-node reduction that completes the pass     */
     uint64_t apply_launches;
-    double apply_ms;
+    double apply_ms;          /* load update r += credits                       */
 } kdss_timing;
 
 typedef struct {

@@ -269,7 +269,6 @@ int kdss_plan_create(const kdss_sct* s, uint32_t T_max, uint64_t r0_max, const k
     P->off_tiles = take(P->tiles.size() * sizeof(Tile));
     P->off_binom = take(P->binom.size() * 8);
     P->off_delta = take(n * 8);
-    P->off_key = take(P->key_mode == 0 ? n * 8 : 8);
     P->off_cnt = take(n * 8);
     P->off_kw[0][0] = take(n * 8);
     P->off_kw[1][0] = take(n * 8);

@@ -85,7 +85,7 @@ constexpr uint32_t kHotMax = 512;
 constexpr uint32_t kHotMinOccurrences = 32;
 constexpr uint32_t kHotFlag = 0x80000000u;
 constexpr uint32_t kLeafBlocksMax = 1024;        // persistent leaf-credit grid
-constexpr uint32_t kHeavyBlocks = 512;           // grid of the heavy-leaf kernel
+constexpr uint32_t kHeavyBlocks = 1024;          // grid of the heavy-leaf kernel
 
 // Device-side result of an extraction.
 struct DevResult {
@@ -121,7 +121,7 @@ struct kdss_plan {
   uint64_t class_tiles[kdss::kNumClasses] = {}, class_leaves[kdss::kNumClasses] = {},
            class_members[kdss::kNumClasses] = {};
   // workspace layout (byte offsets)
-  size_t off_members = 0, off_hdr = 0, off_tiles = 0, off_binom = 0, off_delta = 0, off_key = 0,
+  size_t off_members = 0, off_hdr = 0, off_tiles = 0, off_binom = 0, off_delta = 0,
          off_cnt = 0, off_kw[2][2] = {}, off_perm[2] = {}, off_keyp = 0, off_hist = 0, off_bsum = 0,
          off_bbest = 0, off_red = 0, off_dres = 0, ws_bytes = 0;
   uint32_t sort_blocks = 0, scan_blocks = 0, red_blocks = 0;

@@ -38,20 +38,20 @@ __device__ __forceinline__ uint32_t readlane32(uint32_t v, int lane) {
 // ----------------------------------------------------------------------------
 // Keys.  A leaf orders its members by (load, node id); the minimum of a clique
 // is the member with the smallest key.  Four encodings:
-//   KPacked: load << id_bits | id in one u64 (precomputed per iteration);
+//   KPacked: load << id_bits | id in one u64 (built from the gathered load);
 //   KFull:   (u64 load, id);  KWide: (u128 load, id);
 //   KRank:   a unique u32 (the extraction's n - 1 - position).
 // ----------------------------------------------------------------------------
 struct KeySrc {
-  const uint64_t* key;    // packed keys
   const uint64_t* r;      // loads (u64, or u128 as lo/hi pairs)
   const uint32_t* rank;   // extraction keys
+  uint32_t id_bits;       // packed keys: load << id_bits | id
 };
 
 struct KPacked {
   uint64_t v;
   __device__ static KPacked mx() { return {~0ull}; }
-  __device__ static KPacked load(const KeySrc& s, uint32_t u) { return {s.key[u]}; }
+  __device__ static KPacked load(const KeySrc& s, uint32_t u) { return {(s.r[u] << s.id_bits) | u}; }
   __device__ bool lt(const KPacked& o) const { return v < o.v; }
   __device__ bool eq(const KPacked& o) const { return v == o.v; }
   __device__ KPacked sx(int m) const { return {shfl_xor64(v, m)}; }
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ til
 // Hot-node totals: out[hot[i]] += sum over workgroups b of scratch[b][i].  A
 // block sums 64 hot nodes over a band of kHotRowsPerBlock rows (4 waves, each
 // a quarter of the band) and adds its partial sums with one atomic per node.
-constexpr uint32_t kHotRowsPerBlock = 64;
+constexpr uint32_t kHotRowsPerBlock = 16;
 
 __global__ __launch_bounds__(256) void hot_reduce_kernel(const uint64_t* __restrict__ scratch, uint32_t blocks,
                                                          const uint32_t* __restrict__ hot, uint32_t nhot,
@@ -467,8 +467,7 @@ __global__ void reset_result_kernel(DevResult* d) {
 }
 
 __global__ __launch_bounds__(256) void init_loads_kernel(const uint64_t* __restrict__ r0, uint64_t* __restrict__ r,
-                                                         uint64_t* __restrict__ delta, uint64_t* __restrict__ key,
-                                                         uint32_t n, uint32_t id_bits, int packed, int wide,
+                                                         uint64_t* __restrict__ delta, uint32_t n, int wide,
                                                          DevResult* dres) {
   uint64_t mx = 0;
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
@@ -481,7 +480,6 @@ __global__ __launch_bounds__(256) void init_loads_kernel(const uint64_t* __restr
       r[u] = x;
     }
     delta[u] = 0;
-    if (packed) key[u] = (x << id_bits) | u;
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
@@ -492,13 +490,10 @@ __global__ __launch_bounds__(256) void init_loads_kernel(const uint64_t* __restr
 }
 
 __global__ __launch_bounds__(256) void apply64_kernel(uint64_t* __restrict__ r, uint64_t* __restrict__ delta,
-                                                      uint64_t* __restrict__ key, uint32_t n, uint32_t id_bits,
-                                                      int packed) {
+                                                      uint32_t n) {
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
-    const uint64_t x = r[u] + delta[u];
-    r[u] = x;
+    r[u] += delta[u];
     delta[u] = 0;
-    if (packed) key[u] = (x << id_bits) | u;
   }
 }
 
@@ -896,8 +891,10 @@ struct WsView {
 };
 
 // mode: 0 packed FW keys, 1 full u64 loads, 2 full u128 loads, 3 extraction ranks
+// ev (nullable): four events recorded before the leaf kernel, after it, after
+// the heavy-leaf kernel and after the hot-node reduction.
 int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& src, uint64_t* out,
-                hipStream_t st) {
+                hipStream_t st, hipEvent_t* ev = nullptr) {
   const uint32_t ntiles = (uint32_t)P->tiles.size();
   if (ntiles == 0) return KDSS_OK;
   const uint32_t blocks = P->leaf_blocks;
@@ -911,10 +908,12 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   uint32_t* queue = ws.at<uint32_t>(P->off_queue);
   uint32_t* qcount = ws.at<uint32_t>(P->off_qcount);
   const uint32_t nbinom = (uint32_t)P->binom.size();
-#define KDSS_LEAF(KT)                                                                                       \
-  leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k, src, out, \
-                                                 hot, nhot, scratch, queue, qcount);                         \
-  heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(tiles, members, hdr, binom, nbinom, P->k, src, out, hot,  \
+  if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
+#define KDSS_LEAF(KT)                                                                                           \
+  leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k, src, out,     \
+                                                 hot, nhot, scratch, queue, qcount);                             \
+  if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event record");                                                    \
+  heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(tiles, members, hdr, binom, nbinom, P->k, src, out, hot,      \
                                                     nhot, scratch, blocks, queue, qcount)
   switch (mode) {
     case 0: KDSS_LEAF(KPacked); break;
@@ -927,16 +926,19 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   // hot-node totals over all leaf and heavy workgroups; also empties the queue
   const uint32_t rows = blocks + P->heavy_blocks;
   const dim3 grid(nhot ? (nhot + 63) / 64 : 1, nhot ? (rows + kHotRowsPerBlock - 1) / kHotRowsPerBlock : 1);
+  if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event record");
   hot_reduce_kernel<<<grid, 256, 0, st>>>(scratch, rows, hot, nhot, out, qcount);
   HIP_TRY(hipGetLastError(), "hot reduce launch");
+  if (ev) HIP_TRY(hipEventRecord(ev[3], st), "event record");
   return KDSS_OK;
 }
 
 int fw_mode(const kdss_plan* P) { return P->width == 128 ? 2 : (P->key_mode == 0 ? 0 : 1); }
 
 KeySrc fw_src(const kdss_plan* P, const WsView& ws, const void* d_r) {
+  (void)ws;
   KeySrc s{};
-  s.key = ws.at<uint64_t>(P->off_key);
+  s.id_bits = P->id_bits;
   s.r = static_cast<const uint64_t*>(d_r);
   s.rank = nullptr;
   return s;
@@ -950,8 +952,7 @@ int launch_iteration(const kdss_plan* P, const WsView& ws, void* d_r, hipStream_
   if (P->width == 128) {
     apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
   } else {
-    apply64_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, ws.at<uint64_t>(P->off_key),
-                                                    P->n, P->id_bits, P->key_mode == 0 ? 1 : 0);
+    apply64_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
   }
   HIP_TRY(hipGetLastError(), "apply launch");
   return KDSS_OK;
@@ -1130,13 +1131,12 @@ int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64
   DevResult* dres = ws.at<DevResult>(P->off_dres);
   reset_result_kernel<<<1, 64, 0, st>>>(dres);
   init_loads_kernel<<<grid_for(P->n), 256, 0, st>>>(d_r0, static_cast<uint64_t*>(d_r), ws.at<uint64_t>(P->off_delta),
-                                                    ws.at<uint64_t>(P->off_key), P->n, P->id_bits,
-                                                    P->key_mode == 0 ? 1 : 0, P->width == 128 ? 1 : 0, dres);
+                                                    P->n, P->width == 128 ? 1 : 0, dres);
   HIP_TRY(hipGetLastError(), "init launch");
   const uint32_t every = P->opts.extract_every;
   const bool timed = P->opts.time_kernels != 0;
   if (timed) {
-    while (P->events.size() < 3ull * T) {
+    while (P->events.size() < 5ull * T) {
       hipEvent_t e;
       HIP_TRY(hipEventCreate(&e), "event create");
       P->events.push_back(e);
@@ -1145,21 +1145,17 @@ int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64
   uint32_t rows = 0;
   for (uint32_t t = 1; t <= T; ++t) {
     if (timed) {
-      hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data()) + 3ull * (t - 1);
+      hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data()) + 5ull * (t - 1);
       uint64_t* delta = ws.at<uint64_t>(P->off_delta);
-      HIP_TRY(hipEventRecord(ev[0], st), "event record");
-      rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st);
+      rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev);
       if (rc) return rc;
-      HIP_TRY(hipEventRecord(ev[1], st), "event record");
       if (P->width == 128) {
         apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
       } else {
-        apply64_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta,
-                                                        ws.at<uint64_t>(P->off_key), P->n, P->id_bits,
-                                                        P->key_mode == 0 ? 1 : 0);
+        apply64_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
       }
       HIP_TRY(hipGetLastError(), "apply launch");
-      HIP_TRY(hipEventRecord(ev[2], st), "event record");
+      HIP_TRY(hipEventRecord(ev[4], st), "event record");
     } else if (P->opts.use_graph) {
       rc = ensure_graph(P, ws, d_r);
       if (rc) return rc;
@@ -1191,14 +1187,18 @@ int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64
   rc = read_result(P, ws, st, &h);
   if (rc) return rc;
   if (h.r0max > P->r0_max) return fail(KDSS_EOVERFLOW, "a start load exceeds the plan's r0_max");
-  if (timed) {
+  if (timed && !P->tiles.empty()) {
     hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data());
     for (uint32_t t = 0; t < T; ++t) {
-      float a = 0.f, b = 0.f;
-      HIP_TRY(hipEventElapsedTime(&a, ev[3 * t], ev[3 * t + 1]), "event elapsed");
-      HIP_TRY(hipEventElapsedTime(&b, ev[3 * t + 1], ev[3 * t + 2]), "event elapsed");
+      float a = 0.f, b = 0.f, c = 0.f, d = 0.f;
+      HIP_TRY(hipEventElapsedTime(&a, ev[5 * t], ev[5 * t + 1]), "event elapsed");
+      HIP_TRY(hipEventElapsedTime(&b, ev[5 * t + 1], ev[5 * t + 2]), "event elapsed");
+      HIP_TRY(hipEventElapsedTime(&c, ev[5 * t + 2], ev[5 * t + 3]), "event elapsed");
+      HIP_TRY(hipEventElapsedTime(&d, ev[5 * t + 3], ev[5 * t + 4]), "event elapsed");
       P->timing.leaf_ms += a;
-      P->timing.apply_ms += b;
+      P->timing.heavy_ms += b;
+      P->timing.reduce_ms += c;
+      P->timing.apply_ms += d;
     }
     P->timing.leaf_launches += T;
     P->timing.apply_launches += T;
