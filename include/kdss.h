@@ -203,6 +203,55 @@ int kdss_extract(kdss_plan *p, void *d_ws, size_t ws_bytes, const void *d_r,
                  const uint64_t *d_r0, uint32_t T, uint32_t *d_order, kdss_result *h_res,
                  void *stream);
 
+/* ---- launch tuning (the benchmark spec's autotuned tile schedules) ----
+ * The leaf-credit and heavy-leaf kernels run persistent grids; their sizes
+ * decide how tiles and queued heavy leaves are spread over the 256 CUs. */
+
+typedef struct {
+    uint32_t tried;               /* configurations timed                      */
+    uint32_t best_leaf_blocks, best_heavy_blocks;
+    double best_ms;               /* per iteration, best configuration         */
+    uint32_t leaf_blocks[16], heavy_blocks[16];
+    double ms[16];                /* per iteration, each configuration         */
+} kdss_tune_result;
+
+/* Sets the grid sizes (1..1024 workgroups each) used by later runs. */
+int kdss_plan_set_launch(kdss_plan *p, uint32_t leaf_blocks, uint32_t heavy_blocks);
+
+/* Times `iters` iterations after `warm` untimed ones (from zero loads) for each
+ * candidate pair of grid sizes on the plan's own data, keeps the fastest and
+ * reports all (out, host).  d_r (device, the plan's load width) is scratch.
+ * warm + iters must not exceed T_max.  Synchronises the stream. */
+int kdss_plan_autotune(kdss_plan *p, void *d_ws, size_t ws_bytes, uint64_t *d_r, uint32_t warm, uint32_t iters,
+                       kdss_tune_result *out, void *stream);
+
+/* ---- batches: many problems (graph, k) in one launch per iteration ----
+ * (the benchmark spec's batching addition; each problem is exactly the problem of
+ * kdss_run, and its result equals a solo run bit for bit) */
+
+/* Lays out `count` trees (each with its own graph and k) as one plan: problem q
+ * owns the node ids node_off[q] .. node_off[q+1]-1 of one concatenated id
+ * space (kdss_batch_offsets), every iteration is one persistent launch over all
+ * leaves, and leaves carry their own k.  The trees are read during the call
+ * only.  r0_max bounds every start load.  Errors as kdss_plan_create;
+ * KDSS_EUNSUPPORTED for more than 2^31 nodes in total. */
+int kdss_batch_create(const kdss_sct *const *trees, uint32_t count, uint32_t T_max, uint64_t r0_max,
+                      const kdss_opts *opts, kdss_plan **out);
+
+/* node_off[count + 1] (host): first node id of every problem, then the total. */
+int kdss_batch_offsets(const kdss_plan *p, uint64_t *node_off, uint32_t count);
+
+/* Runs T iterations for every problem of a batch plan, then every problem's
+ * extraction.  d_r0 (device u64[total], nullable), d_r (device u64[total]) and
+ * d_order (device u32[total]) use the concatenated id space; problem q's order
+ * occupies d_order[node_off[q] .. node_off[q+1]) and holds its local ids, its
+ * node set being the first h_res[q].size of them.  h_res (host) receives one
+ * result per problem.  Batches use 64-bit loads (KDSS_EUNSUPPORTED otherwise,
+ * or when log2(count) + log2(largest bound) exceeds 64 bits).  Other errors as
+ * kdss_run. */
+int kdss_batch_run(kdss_plan *p, void *d_ws, size_t ws_bytes, uint32_t T, const uint64_t *d_r0, uint64_t *d_r,
+                   uint32_t *d_order, kdss_result *h_res, uint32_t count, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

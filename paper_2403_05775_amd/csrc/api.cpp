@@ -125,99 +125,181 @@ int kdss_sct_core_numbers(const kdss_sct* s, uint32_t* core, uint32_t n) {
 
 void kdss_sct_free(kdss_sct* s) { delete s; }
 
-int kdss_plan_create(const kdss_sct* s, uint32_t T_max, uint64_t r0_max, const kdss_opts* opts,
-                     kdss_plan** out) {
-  if (!s || !out) return fail(KDSS_EINVAL, "null argument");
-  *out = nullptr;
+}  // extern "C"
+
+namespace kdss {
+
+// Byte offsets of every device buffer inside the caller's workspace.
+static void layout_workspace(kdss_plan* P) {
+  const size_t n = P->n;
+  const size_t nprob = P->node_off.size() - 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  P->sort_blocks = (uint32_t)((n + kSortTile - 1) / kSortTile);
+  P->scan_blocks = (uint32_t)((n + kScanTile - 1) / kScanTile);
+  P->red_blocks = (uint32_t)((n + kRedTile - 1) / kRedTile);
+  P->off_members = take(P->members.size() * 4);
+  P->off_hdr = take(P->hdr.size() * 4);
+  P->off_tiles = take(P->tiles.size() * sizeof(Tile));
+  P->off_binom = take(P->binom.size() * 8);
+  P->off_delta = take(n * 8);
+  P->off_cnt = take(n * 8);
+  P->off_kw[0][0] = take(n * 8);
+  P->off_kw[1][0] = take(n * 8);
+  P->off_kw[0][1] = take(P->width == 128 ? n * 8 : 8);
+  P->off_kw[1][1] = take(P->width == 128 ? n * 8 : 8);
+  P->off_perm[0] = take(n * 4);
+  P->off_perm[1] = take(n * 4);
+  P->off_keyp = take(n * 4);
+  P->off_hist = take((size_t)256 * P->sort_blocks * 4);
+  P->off_dbase = take(256 * 4);
+  P->off_bsum = take((size_t)P->scan_blocks * 8);
+  P->off_bbest = take((size_t)P->scan_blocks * 16);
+  P->off_red = take((size_t)P->red_blocks * 16);   // a (lo, hi) pair per block
+  P->off_dres = take(sizeof(DevResult));
+  P->leaf_blocks = (uint32_t)std::min<uint64_t>(kLeafBlocksMax, std::max<uint64_t>(1, (P->tiles.size() + 3) / 4));
+  P->heavy_blocks = kHeavyBlocks;
+  P->off_hot = take(P->hot.size() * 4);
+  // scratch rows for the largest grids the launch tuner may pick
+  P->off_scratch = take((size_t)(kLeafBlocksMax + kHeavyBlocks) * P->hot.size() * 8);
+  P->lane_leaves = 0;
+  for (const Tile& tl : P->tiles)
+    if ((tl.info & 7u) == kTileLane) P->lane_leaves += (tl.info >> 3) & 0x1FFFu;
+  P->off_queue = take(P->lane_leaves * 4);
+  P->off_qcount = take(64);
+  // batch extraction: prefix sums, per-problem results and node offsets
+  P->off_prefix = take(n * 8);
+  P->off_pres = take(nprob * sizeof(DevResult));
+  P->off_nodeoff = take((nprob + 1) * 8);
+  P->ws_bytes = o;
+}
+
+// Lays out one or more trees (a batch) for the GPU.  Problem q's nodes get the
+// ids node_off[q] .. node_off[q + 1] - 1 of one concatenated id space; leaves
+// never span problems, and each leaf header carries its own j = k - h.
+static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint64_t r0_max,
+                      const kdss_opts* opts, kdss_plan** out) {
   if (T_max == 0) return fail(KDSS_EINVAL, "T_max must be at least 1");
-  const Sct& t = s->s;
-  if (t.n == 0) return fail(KDSS_EINVAL, "graph has no nodes");
-  if ((t.c_k >> 64) != 0) return fail(KDSS_EOVERFLOW, "k-clique count does not fit 64 bits");
-  if (t.s_max > kMaxBigLeaf) return fail(KDSS_EUNSUPPORTED, "a leaf has more than 4096 members");
-  if (t.n > kHotFlag) return fail(KDSS_EUNSUPPORTED, "more than 2^31 nodes");
+  uint64_t n_total = 0;
+  uint32_t kmax = 0, s_max = 0;
+  u128 bound_max = 0, ck_total = 0;
+  for (const Sct* t : trees) {
+    if (t->n == 0) return fail(KDSS_EINVAL, "graph has no nodes");
+    if ((t->c_k >> 64) != 0) return fail(KDSS_EOVERFLOW, "k-clique count does not fit 64 bits");
+    if (t->s_max > kMaxBigLeaf) return fail(KDSS_EUNSUPPORTED, "a leaf has more than 4096 members");
+    n_total += t->n;
+    kmax = std::max(kmax, t->k);
+    s_max = std::max(s_max, t->s_max);
+    ck_total += t->c_k;
+    // every load of problem q stays <= r0_max + T_max * c_k(q)
+    bound_max = std::max(bound_max, (u128)r0_max + (u128)T_max * t->c_k);
+  }
+  if (n_total > kHotFlag) return fail(KDSS_EUNSUPPORTED, "more than 2^31 nodes");
   kdss_plan* P = new (std::nothrow) kdss_plan();
   if (!P) return fail(KDSS_ENOMEM, "cannot allocate the plan");
   try {
-    P->n = t.n;
-    P->k = t.k;
+    P->n = (uint32_t)n_total;
+    P->k = trees.size() == 1 ? trees[0]->k : kmax;
+    P->k1 = kmax + 1;
     P->T_max = T_max;
     P->r0_max = r0_max;
-    P->c_k = t.c_k;
-    P->s_max = t.s_max;
+    P->c_k = trees.size() == 1 ? trees[0]->c_k : ck_total;
+    P->s_max = s_max;
     if (opts) P->opts = *opts;
-    P->id_bits = std::max<uint32_t>(1, bit_length(t.n - 1));
-    // every load stays <= r0_max + T_max * c_k
-    const u128 bound = (u128)r0_max + (u128)T_max * t.c_k;
-    const bool fits64 = (bound >> 64) == 0;
-    if (P->opts.width == 64 && !fits64) {
-      delete P;
-      return fail(KDSS_EOVERFLOW, "loads may exceed 2^64 - 1 but width 64 was forced");
+    P->id_bits = std::max<uint32_t>(1, bit_length(n_total - 1));
+    P->node_off.assign(1, 0);
+    for (const Sct* t : trees) {
+      P->node_off.push_back(P->node_off.back() + t->n);
+      P->prob_k.push_back(t->k);
+      P->prob_ck.push_back(t->c_k);
     }
+    const bool fits64 = (bound_max >> 64) == 0;
     if (P->opts.width != 0 && P->opts.width != 64 && P->opts.width != 128) {
       delete P;
       return fail(KDSS_EINVAL, "width must be 0, 64 or 128");
     }
+    if (P->opts.width == 64 && !fits64) {
+      delete P;
+      return fail(KDSS_EOVERFLOW, "loads may exceed 2^64 - 1 but width 64 was forced");
+    }
     P->width = (P->opts.width == 128 || !fits64) ? 128 : 64;
     // packed keys r << id_bits | id need every load below 2^(64 - id_bits) - 1
     const u128 packed_limit = ((u128)1 << (64 - P->id_bits)) - 1;
-    P->key_mode = (P->width == 64 && bound < packed_limit) ? 0 : 1;
+    P->key_mode = (P->width == 64 && bound_max < packed_limit) ? 0 : 1;
+    P->bound_max = bound_max;
 
-    // ---- hot nodes: those occurring in the most leaves (ids must leave the flag bit free) ----
-    const uint64_t L = t.leaves();
-    std::vector<uint32_t> hot_index;
+    // ---- hot nodes: those occurring in the most leaves ----
+    std::vector<uint32_t> hot_index(n_total, ~0u);
     {
-      std::vector<uint64_t> occ(t.n, 0);
-      for (uint32_t u : t.members) occ[u]++;
+      std::vector<uint64_t> occ(n_total, 0);
+      for (size_t q = 0; q < trees.size(); ++q)
+        for (uint32_t u : trees[q]->members) occ[P->node_off[q] + u]++;
       std::vector<uint32_t> cand;
-      for (uint32_t u = 0; u < t.n; ++u)
-        if (occ[u] >= kHotMinOccurrences) cand.push_back(u);
+      for (uint64_t u = 0; u < n_total; ++u)
+        if (occ[u] >= kHotMinOccurrences) cand.push_back((uint32_t)u);
       std::sort(cand.begin(), cand.end(), [&](uint32_t a, uint32_t b) {
         return occ[a] != occ[b] ? occ[a] > occ[b] : a < b;
       });
       if (cand.size() > kHotMax) cand.resize(kHotMax);
       P->hot = cand;
-      hot_index.assign(t.n, ~0u);
       for (uint32_t i = 0; i < P->hot.size(); ++i) hot_index[P->hot[i]] = i;
     }
-    auto encode = [&](uint32_t u) -> uint32_t {
-      return (!hot_index.empty() && hot_index[u] != ~0u) ? (kHotFlag | hot_index[u]) : u;
-    };
-    auto append_leaf = [&](uint64_t id) {
-      const uint64_t b = t.off[id], e = b + t.h[id] + t.p[id];
-      for (uint64_t x = b; x < e; ++x) P->members.push_back(encode(t.members[x]));
+    auto encode = [&](uint64_t u) -> uint32_t {
+      return hot_index[u] != ~0u ? (kHotFlag | hot_index[u]) : (uint32_t)u;
     };
 
     // ---- tiles: big leaves first (longest work first), then lane tiles from
-    // the largest group to the smallest ----
-    std::vector<uint64_t> big;
-    std::vector<std::vector<uint64_t>> groups(kNumLaneGroups);
-    for (uint64_t i = 0; i < L; ++i) {
-      const uint32_t s = t.h[i] + t.p[i];
-      const int b = size_bucket(s);
-      P->class_leaves[b]++;
-      P->class_members[b] += s;
-      if (s > 64) big.push_back(i);
-      else groups[lane_group(s)].push_back(i);
+    // the largest group to the smallest; a tile holds leaves of one problem ----
+    struct LeafRef { uint32_t q; uint64_t id; };
+    std::vector<LeafRef> big;
+    std::vector<std::vector<LeafRef>> groups(kNumLaneGroups);
+    uint64_t L = 0, M = 0;
+    for (uint32_t q = 0; q < trees.size(); ++q) {
+      const Sct& t = *trees[q];
+      L += t.leaves();
+      M += t.members.size();
+      for (uint64_t i = 0; i < t.leaves(); ++i) {
+        const uint32_t s = t.h[i] + t.p[i];
+        const int b = size_bucket(s);
+        P->class_leaves[b]++;
+        P->class_members[b] += s;
+        if (s > 64) big.push_back({q, i});
+        else groups[lane_group(s)].push_back({q, i});
+      }
     }
-    P->members.reserve(t.members.size() + t.members.size() / 8);
+    P->members.reserve(M + M / 8);
     P->hdr.reserve(L);
-    for (uint64_t id : big) {
+    auto header = [&](const LeafRef& r) {
+      const Sct& t = *trees[r.q];
+      return pack_leaf(t.h[r.id], t.k - t.h[r.id], t.p[r.id]);
+    };
+    for (const LeafRef& r : big) {
+      const Sct& t = *trees[r.q];
       Tile tl;
       tl.mbase = P->members.size();
       tl.lbase = (uint32_t)P->hdr.size();
-      const uint32_t h = t.h[id], p = t.p[id];
       tl.info = pack_tile_info(kTileBig, 1, 0);
-      P->hdr.push_back(pack_leaf(h, p));
-      append_leaf(id);
+      P->hdr.push_back(header(r));
+      for (uint64_t x = t.off[r.id]; x < t.off[r.id + 1]; ++x)
+        P->members.push_back(encode(P->node_off[r.q] + t.members[x]));
       P->tiles.push_back(tl);
       P->class_tiles[kBigClass]++;
     }
     for (int gi = kNumLaneGroups - 1; gi >= 0; --gi) {
-      const auto& ids = groups[gi];
-      for (uint64_t i0 = 0; i0 < ids.size(); i0 += 64) {
-        const uint32_t nl = (uint32_t)std::min<uint64_t>(64, ids.size() - i0);
-        uint32_t smax = 0;
-        for (uint32_t r = 0; r < nl; ++r) smax = std::max<uint32_t>(smax, t.h[ids[i0 + r]] + t.p[ids[i0 + r]]);
+      const auto& refs = groups[gi];
+      uint64_t i0 = 0;
+      while (i0 < refs.size()) {
+        // up to 64 leaves of the same problem
+        uint32_t nl = 0, smax = 0;
+        while (nl < 64 && i0 + nl < refs.size() && refs[i0 + nl].q == refs[i0].q) {
+          const Sct& t = *trees[refs[i0 + nl].q];
+          smax = std::max<uint32_t>(smax, t.h[refs[i0 + nl].id] + t.p[refs[i0 + nl].id]);
+          ++nl;
+        }
         Tile tl;
         tl.mbase = P->members.size();
         tl.lbase = (uint32_t)P->hdr.size();
@@ -226,13 +308,16 @@ int kdss_plan_create(const kdss_sct* s, uint32_t T_max, uint64_t r0_max, const k
         P->members.resize(P->members.size() + (size_t)64 * smax, 0u);
         uint32_t* col = P->members.data() + tl.mbase;
         for (uint32_t r = 0; r < nl; ++r) {
-          const uint64_t id = ids[i0 + r];
-          const uint32_t h = t.h[id], p = t.p[id];
-          P->hdr.push_back(pack_leaf(h, p));
-          for (uint32_t x = 0; x < h + p; ++x) col[(size_t)64 * x + r] = encode(t.members[t.off[id] + x]);
+          const LeafRef& ref = refs[i0 + r];
+          const Sct& t = *trees[ref.q];
+          P->hdr.push_back(header(ref));
+          const uint32_t s = t.h[ref.id] + t.p[ref.id];
+          for (uint32_t x = 0; x < s; ++x)
+            col[(size_t)64 * x + r] = encode(P->node_off[ref.q] + t.members[t.off[ref.id] + x]);
         }
         P->tiles.push_back(tl);
         P->class_tiles[size_bucket(smax)]++;
+        i0 += nl;
       }
     }
     if (P->tiles.size() >= (1ull << 26)) {
@@ -243,61 +328,51 @@ int kdss_plan_create(const kdss_sct* s, uint32_t T_max, uint64_t r0_max, const k
       delete P;
       return fail(KDSS_ERANGE, "more than 2^32 - 1 leaves");
     }
-    // binomial table C(a, b), a <= s_max, b <= k (saturated entries are never used
-    // because every used entry is at most C(p, k - h) <= c_k < 2^64)
-    const uint32_t rows = t.s_max + 1, cols = t.k + 1;
+    // binomial table C(a, b), a <= s_max, b <= kmax (saturated entries are never
+    // used: every used entry is at most C(p, k - h) <= c_k < 2^64)
+    const uint32_t rows = s_max + 1, cols = P->k1;
     P->binom.resize((size_t)rows * cols);
     for (uint32_t a = 0; a < rows; ++a)
       for (uint32_t b = 0; b < cols; ++b) {
         u128 v = binom128(a, b);
         P->binom[(size_t)a * cols + b] = (v >> 64) ? ~0ull : (uint64_t)v;
       }
-
-    // ---- workspace layout ----
-    const size_t n = t.n;
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-      size_t at = o;
-      o = align256(o + std::max<size_t>(bytes, 1));
-      return at;
-    };
-    P->sort_blocks = (uint32_t)((n + kSortTile - 1) / kSortTile);
-    P->scan_blocks = (uint32_t)((n + kScanTile - 1) / kScanTile);
-    P->red_blocks = (uint32_t)((n + kRedTile - 1) / kRedTile);
-    P->off_members = take(P->members.size() * 4);
-    P->off_hdr = take(P->hdr.size() * 4);
-    P->off_tiles = take(P->tiles.size() * sizeof(Tile));
-    P->off_binom = take(P->binom.size() * 8);
-    P->off_delta = take(n * 8);
-    P->off_cnt = take(n * 8);
-    P->off_kw[0][0] = take(n * 8);
-    P->off_kw[1][0] = take(n * 8);
-    P->off_kw[0][1] = take(P->width == 128 ? n * 8 : 8);
-    P->off_kw[1][1] = take(P->width == 128 ? n * 8 : 8);
-    P->off_perm[0] = take(n * 4);
-    P->off_perm[1] = take(n * 4);
-    P->off_keyp = take(n * 4);
-    P->off_hist = take((size_t)256 * P->sort_blocks * 4);
-    P->off_dbase = take(256 * 4);
-    P->off_bsum = take((size_t)P->scan_blocks * 8);
-    P->off_bbest = take((size_t)P->scan_blocks * 16);
-    P->off_red = take((size_t)P->red_blocks * 16);   // a (lo, hi) pair per block
-    P->off_dres = take(sizeof(DevResult));
-    P->leaf_blocks = (uint32_t)std::min<uint64_t>(kLeafBlocksMax, std::max<uint64_t>(1, (P->tiles.size() + 3) / 4));
-    P->off_hot = take(P->hot.size() * 4);
-    P->heavy_blocks = kHeavyBlocks;
-    P->off_scratch = take((size_t)(P->leaf_blocks + P->heavy_blocks) * P->hot.size() * 8);
-    P->lane_leaves = 0;
-    for (const Tile& tl : P->tiles)
-      if ((tl.info & 7u) == kTileLane) P->lane_leaves += (tl.info >> 3) & 0x1FFFu;
-    P->off_queue = take(P->lane_leaves * 4);
-    P->off_qcount = take(64);
-    P->ws_bytes = o;
+    layout_workspace(P);
   } catch (const std::bad_alloc&) {
     delete P;
     return fail(KDSS_ENOMEM, "host memory exhausted while planning");
   }
   *out = P;
+  return KDSS_OK;
+}
+
+}  // namespace kdss
+
+extern "C" {
+
+int kdss_plan_create(const kdss_sct* s, uint32_t T_max, uint64_t r0_max, const kdss_opts* opts,
+                     kdss_plan** out) {
+  if (!s || !out) return fail(KDSS_EINVAL, "null argument");
+  *out = nullptr;
+  return build_plan({&s->s}, T_max, r0_max, opts, out);
+}
+
+int kdss_batch_create(const kdss_sct* const* trees, uint32_t count, uint32_t T_max, uint64_t r0_max,
+                      const kdss_opts* opts, kdss_plan** out) {
+  if (!trees || !out || count == 0) return fail(KDSS_EINVAL, "null argument or empty batch");
+  *out = nullptr;
+  std::vector<const Sct*> v;
+  for (uint32_t i = 0; i < count; ++i) {
+    if (!trees[i]) return fail(KDSS_EINVAL, "null tree in batch");
+    v.push_back(&trees[i]->s);
+  }
+  return build_plan(v, T_max, r0_max, opts, out);
+}
+
+int kdss_batch_offsets(const kdss_plan* P, uint64_t* node_off, uint32_t count) {
+  if (!P || !node_off) return fail(KDSS_EINVAL, "null argument");
+  if (count + 1 != P->node_off.size()) return fail(KDSS_ERANGE, "count does not match the plan");
+  std::memcpy(node_off, P->node_off.data(), sizeof(uint64_t) * (count + 1));
   return KDSS_OK;
 }
 

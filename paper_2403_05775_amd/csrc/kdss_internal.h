@@ -98,8 +98,8 @@ struct DevResult {
 };
 static_assert(sizeof(DevResult) == 64, "device result is 64 bytes");
 
-// Leaf header: h (5 bits), p (27 bits).
-inline uint32_t pack_leaf(uint32_t h, uint32_t p) { return h | (p << 5); }
+// Leaf header: h (5 bits), j = k - h (5 bits), p (22 bits).
+inline uint32_t pack_leaf(uint32_t h, uint32_t j, uint32_t p) { return h | (j << 5) | (p << 10); }
 inline uint32_t pack_tile_info(uint32_t kind, uint32_t leaves, uint32_t smax) {
   return kind | (leaves << 3) | (smax << 16);
 }
@@ -129,6 +129,12 @@ struct kdss_plan {
   std::vector<uint32_t> hot;           // original ids of the hot nodes
   size_t off_hot = 0, off_scratch = 0, off_dbase = 0, off_queue = 0, off_qcount = 0;
   uint32_t heavy_blocks = 0;           // grid of the heavy-leaf kernel
+  uint32_t k1 = 0;                     // binomial table row length (largest k + 1)
+  kdss::u128 bound_max = 0;            // largest r0_max + T_max * c_k over the problems
+  std::vector<uint64_t> node_off;      // problem q owns ids node_off[q] .. node_off[q+1]-1
+  std::vector<uint32_t> prob_k;
+  std::vector<kdss::u128> prob_ck;
+  size_t off_prefix = 0, off_pres = 0, off_nodeoff = 0;
   uint64_t lane_leaves = 0;            // leaves in lane tiles (queue capacity)
   // state of the device side
   void* uploaded_ws = nullptr;

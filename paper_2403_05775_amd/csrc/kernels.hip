@@ -144,7 +144,9 @@ __device__ __forceinline__ KT member_key_nb(const KeySrc& src, const KT* hkey, u
 // Leaf credit (paper: Algorithm 1's per-clique minimum-load step, batched per
 // SCT leaf with the counts of Lemma 5).
 //
-// A leaf (H, P) with h = |H|, p = |P|, j = k - h holds the k-cliques H + C',
+// A leaf (H, P) with h = |H|, p = |P|, j = k - h holds the k-cliques H + C'
+// (the header carries h, j and p, so leaves of problems with different k can
+// share a launch; k1 is the row length of the binomial table),
 // C' a j-subset of P.  Let m be the hold member with the smallest key.  The
 // minimum of H + C' is m unless C' holds a pivot member below m; then it is
 // the smallest such member u of C'.  With a(x) = the number of pivot members
@@ -186,16 +188,14 @@ __device__ __forceinline__ void combine_add(Sink& sink, uint32_t key, uint64_t v
 // while many loads tie, e.g. from all-zero start loads) are ranked by a rescan.
 template <class KT>
 __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, const uint32_t* __restrict__ members,
-                                          const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k,
+                                          const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k1,
                                           const KeySrc& src, const KT* hkey, Sink& sink, uint32_t* __restrict__ queue,
                                           uint32_t* __restrict__ qcount) {
   constexpr uint32_t U = 8;   // rows loaded per batch
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nl = (t.info >> 3) & 0x1FFFu, smax = t.info >> 16;
-  const uint32_t k1 = k + 1;
   const uint32_t hd = lane < nl ? hdr[t.lbase + lane] : 0u;   // a missing leaf reads as empty
-  const uint32_t h = hd & 31u, p = hd >> 5, s = h + p;
-  const uint32_t j = k - h;
+  const uint32_t h = hd & 31u, j = (hd >> 5) & 31u, p = hd >> 10, s = h + p;
   const uint32_t* __restrict__ col = members + t.mbase + lane;
   KT km = KT::mx();
   uint32_t mraw = 0, nlow = 0;
@@ -255,11 +255,10 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
 template <class KT>
 __device__ __forceinline__ void tile_big(const Tile& t, const uint32_t* __restrict__ members,
                                          const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ binom,
-                                         uint32_t k, const KeySrc& src, const KT* hkey, Sink& sink) {
+                                         uint32_t k1, const KeySrc& src, const KT* hkey, Sink& sink) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t hd = hdr[t.lbase];
-  const uint32_t h = hd & 31u, p = hd >> 5, s = h + p;
-  const uint32_t j = k - h, k1 = k + 1;
+  const uint32_t h = hd & 31u, j = (hd >> 5) & 31u, p = hd >> 10, s = h + p;
   const uint32_t* __restrict__ mem = members + t.mbase;
   // the hold members all sit in the first chunk (h <= 31)
   const uint32_t r0 = lane < s ? mem[lane] : 0u;
@@ -311,7 +310,7 @@ __global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict
                                                           const uint32_t* __restrict__ members,
                                                           const uint32_t* __restrict__ hdr,
                                                           const uint64_t* __restrict__ binom, uint32_t nbinom,
-                                                          uint32_t k, KeySrc src, uint64_t* __restrict__ out,
+                                                          uint32_t k1, KeySrc src, uint64_t* __restrict__ out,
                                                           const uint32_t* __restrict__ hot, uint32_t nhot,
                                                           uint64_t* __restrict__ scratch, uint32_t* __restrict__ queue,
                                                           uint32_t* __restrict__ qcount) {
@@ -332,8 +331,8 @@ __global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict
   const uint32_t stride = gridDim.x * 4u;
   for (uint32_t tile = blockIdx.x * 4u + w; tile < ntiles; tile += stride) {
     const Tile t = tiles[tile];
-    if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k, src, hkey, sink);
-    else tile_lane<KT>(t, tile, members, hdr, bt, k, src, hkey, sink, queue, qcount);
+    if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k1, src, hkey, sink);
+    else tile_lane<KT>(t, tile, members, hdr, bt, k1, src, hkey, sink, queue, qcount);
   }
   sink.flush();
   __syncthreads();
@@ -349,7 +348,7 @@ __global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict
 template <class KT>
 __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ tiles, const uint32_t* __restrict__ members,
                                                     const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ binom,
-                                                    uint32_t nbinom, uint32_t k, KeySrc src, uint64_t* __restrict__ out,
+                                                    uint32_t nbinom, uint32_t k1, KeySrc src, uint64_t* __restrict__ out,
                                                     const uint32_t* __restrict__ hot, uint32_t nhot,
                                                     uint64_t* __restrict__ scratch, uint32_t row0,
                                                     const uint32_t* __restrict__ queue,
@@ -370,11 +369,10 @@ __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ til
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t total = *qcount;
-  const uint32_t k1 = k + 1;
   constexpr uint32_t B = 4;
   const uint32_t nw = gridDim.x * 4u;
   for (uint32_t e0 = (blockIdx.x * 4u + w) * B; e0 < total; e0 += nw * B) {
-    uint32_t hq[B], sq[B], ra[B];
+    uint32_t hq[B], sq[B], jq[B], ra[B];
     KT ka[B];
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
@@ -384,7 +382,8 @@ __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ til
       const uint32_t L = ent & 63u;
       const uint32_t hd = hdr[t.lbase + L];
       hq[q] = hd & 31u;
-      sq[q] = hq[q] + (hd >> 5);
+      jq[q] = (hd >> 5) & 31u;
+      sq[q] = hq[q] + (hd >> 10);
       ra[q] = lane < sq[q] ? members[t.mbase + (size_t)lane * 64 + L] : 0u;
     }
 #pragma unroll
@@ -392,7 +391,7 @@ __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ til
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
       if (e0 + q >= total) break;
-      const uint32_t h = hq[q], s = sq[q], p = s - h, j = k - h;
+      const uint32_t h = hq[q], s = sq[q], p = s - h, j = jq[q];
       KT kh = lane < h ? ka[q] : KT::mx();
 #pragma unroll
       for (int d = 32; d >= 1; d >>= 1) {
@@ -859,6 +858,109 @@ __global__ __launch_bounds__(256) void copy_u32_kernel(const uint32_t* __restric
 }
 
 // ----------------------------------------------------------------------------
+// Batch extraction: problem q owns node ids [off[q], off[q+1]); after the sort
+// it also owns order positions [off[q], off[q+1]).
+// ----------------------------------------------------------------------------
+
+// Sort keys q << rbits | (B - r(u)): problems stay contiguous, and inside a
+// problem the order is r non-increasing with ties in ascending id.
+__global__ __launch_bounds__(256) void batch_sort_init_kernel(const uint64_t* __restrict__ r,
+                                                              const uint64_t* __restrict__ off, uint32_t rbits,
+                                                              uint64_t bound, uint64_t* __restrict__ kw,
+                                                              uint32_t* __restrict__ perm) {
+  const uint32_t q = blockIdx.x;
+  const uint64_t b = off[q], e = off[q + 1];
+  const uint64_t hi = (uint64_t)q << rbits;
+  for (uint64_t u = b + threadIdx.x; u < e; u += blockDim.x) {
+    kw[u] = hi | (bound - r[u]);
+    perm[u] = (uint32_t)u;
+  }
+}
+
+// Inclusive prefix sums P[i] = sum of cnt[order[0 .. i]] (block sums already scanned).
+__global__ __launch_bounds__(kScanThreads) void scan_prefix_kernel(const uint64_t* __restrict__ cnt,
+                                                                   const uint32_t* __restrict__ perm, uint32_t n,
+                                                                   const uint64_t* __restrict__ bsum,
+                                                                   uint64_t* __restrict__ prefix) {
+  __shared__ uint64_t wsum[kScanThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t first = blockIdx.x * kScanTile + tid * kScanItems;
+  uint64_t v[kScanItems];
+  uint64_t tsum = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kScanItems; ++j) {
+    const uint32_t i = first + j;
+    v[j] = i < n ? cnt[perm[i]] : 0ull;
+    tsum += v[j];
+  }
+  uint64_t inc = tsum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t o = shfl64(inc, (int)lane - d < 0 ? (int)lane : (int)lane - d);
+    if ((int)lane - d >= 0) inc += o;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint64_t K = bsum[blockIdx.x];
+  for (uint32_t x = 0; x < w; ++x) K += wsum[x];
+  K += inc - tsum;
+#pragma unroll
+  for (uint32_t j = 0; j < kScanItems; ++j) {
+    const uint32_t i = first + j;
+    K += v[j];
+    if (i < n) prefix[i] = K;
+  }
+}
+
+// One workgroup per problem: exact best prefix (largest i on ties), the upper
+// bound max (r - r0) over the problem's nodes, and the order in local ids.
+__global__ __launch_bounds__(256) void segment_best_kernel(const uint64_t* __restrict__ prefix,
+                                                           const uint64_t* __restrict__ off,
+                                                           const uint64_t* __restrict__ r,
+                                                           const uint64_t* __restrict__ r0,
+                                                           const uint32_t* __restrict__ perm,
+                                                           uint32_t* __restrict__ order, DevResult* __restrict__ pres) {
+  __shared__ uint64_t bk[4], ub[4];
+  __shared__ uint32_t bi[4];
+  const uint32_t q = blockIdx.x;
+  const uint64_t b = off[q], e = off[q + 1];
+  const uint64_t base = b ? prefix[b - 1] : 0ull;
+  uint64_t bestK = 0, mx = 0;
+  uint32_t besti = 0;
+  for (uint64_t pos = b + threadIdx.x; pos < e; pos += blockDim.x) {
+    const uint64_t K = prefix[pos] - base;
+    const uint32_t i = (uint32_t)(pos - b + 1);
+    if (better(K, i, bestK, besti)) { bestK = K; besti = i; }
+    order[pos] = perm[pos] - (uint32_t)b;
+    const uint64_t x = r[pos] - (r0 ? r0[pos] : 0ull);   // node ids of q are the same range
+    mx = x > mx ? x : mx;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t ok = shfl_xor64(bestK, d);
+    const uint32_t oi = shfl_xor32(besti, d);
+    if (better(ok, oi, bestK, besti)) { bestK = ok; besti = oi; }
+    const uint64_t om = shfl_xor64(mx, d);
+    mx = om > mx ? om : mx;
+  }
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0) { bk[w] = bestK; bi[w] = besti; ub[w] = mx; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t x = 1; x < blockDim.x / 64; ++x) {
+      if (better(bk[x], bi[x], bestK, besti)) { bestK = bk[x]; besti = bi[x]; }
+      mx = ub[x] > mx ? ub[x] : mx;
+    }
+    DevResult d{};
+    d.dens_num = bestK;
+    d.size = besti;
+    d.ub_lo = mx;
+    d.ub_hi = 0;
+    pres[q] = d;
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Host-side launch helpers.
 // ----------------------------------------------------------------------------
 int hip_fail(hipError_t e, const char* what) {
@@ -910,10 +1012,10 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   const uint32_t nbinom = (uint32_t)P->binom.size();
   if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
 #define KDSS_LEAF(KT)                                                                                           \
-  leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k, src, out,     \
+  leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src, out,    \
                                                  hot, nhot, scratch, queue, qcount);                             \
   if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event record");                                                    \
-  heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(tiles, members, hdr, binom, nbinom, P->k, src, out, hot,      \
+  heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(tiles, members, hdr, binom, nbinom, P->k1, src, out, hot,     \
                                                     nhot, scratch, blocks, queue, qcount)
   switch (mode) {
     case 0: KDSS_LEAF(KPacked); break;
@@ -958,6 +1060,33 @@ int launch_iteration(const kdss_plan* P, const WsView& ws, void* d_r, hipStream_
   return KDSS_OK;
 }
 
+// Stable LSD radix sort of kw[0] (and kw[0][1] for 128-bit keys) with the
+// permutation perm[0] over the low nbits bits; *cur receives the buffer index
+// that holds the result.
+int launch_radix(const kdss_plan* P, const WsView& ws, uint32_t nbits, int wide, hipStream_t st, int* cur_out) {
+  const uint32_t n = P->n;
+  uint64_t* kw[2][2] = {{ws.at<uint64_t>(P->off_kw[0][0]), ws.at<uint64_t>(P->off_kw[0][1])},
+                        {ws.at<uint64_t>(P->off_kw[1][0]), ws.at<uint64_t>(P->off_kw[1][1])}};
+  uint32_t* perm[2] = {ws.at<uint32_t>(P->off_perm[0]), ws.at<uint32_t>(P->off_perm[1])};
+  uint32_t* hist = ws.at<uint32_t>(P->off_hist);
+  uint32_t* dbase = ws.at<uint32_t>(P->off_dbase);
+  int cur = 0;
+  for (uint32_t sh = 0; sh < nbits; sh += 8) {
+    const int use_hi = sh >= 64 ? 1 : 0;
+    const uint64_t* src = use_hi ? kw[cur][1] : kw[cur][0];
+    radix_hist_kernel<<<P->sort_blocks, kSortThreads, 0, st>>>(src, n, sh & 63u, hist, P->sort_blocks);
+    radix_rowscan_kernel<<<256, 256, 0, st>>>(hist, P->sort_blocks, dbase);
+    radix_digitscan_kernel<<<1, 256, 0, st>>>(dbase);
+    radix_scatter_kernel<<<P->sort_blocks, kSortThreads, 0, st>>>(kw[cur][0], kw[cur][1], perm[cur], kw[cur ^ 1][0],
+                                                                  kw[cur ^ 1][1], perm[cur ^ 1], n, sh & 63u, use_hi,
+                                                                  wide, hist, P->sort_blocks, dbase);
+    HIP_TRY(hipGetLastError(), "radix pass launch");
+    cur ^= 1;
+  }
+  *cur_out = cur;
+  return KDSS_OK;
+}
+
 // Extraction at loads d_r; every load is <= bound.  The order lands in d_order
 // and the best prefix and upper bound in the device result.
 int launch_extract(const kdss_plan* P, const WsView& ws, const void* d_r, const uint64_t* d_r0, u128 bound,
@@ -972,28 +1101,15 @@ int launch_extract(const kdss_plan* P, const WsView& ws, const void* d_r, const 
   max_final_kernel<<<1, 256, 0, st>>>(red, P->red_blocks, &dres->ub_lo, &dres->ub_hi);
   HIP_TRY(hipGetLastError(), "upper bound launch");
   // order: sort B - r ascending, stable over ascending ids
-  int cur = 0;
   uint64_t* kw[2][2] = {{ws.at<uint64_t>(P->off_kw[0][0]), ws.at<uint64_t>(P->off_kw[0][1])},
                         {ws.at<uint64_t>(P->off_kw[1][0]), ws.at<uint64_t>(P->off_kw[1][1])}};
   uint32_t* perm[2] = {ws.at<uint32_t>(P->off_perm[0]), ws.at<uint32_t>(P->off_perm[1])};
-  uint32_t* hist = ws.at<uint32_t>(P->off_hist);
-  uint32_t* dbase = ws.at<uint32_t>(P->off_dbase);
   sort_init_kernel<<<grid_for(n), 256, 0, st>>>(r, n, wide, (uint64_t)bound, (uint64_t)(bound >> 64), kw[0][0],
                                                 kw[0][1], perm[0]);
   HIP_TRY(hipGetLastError(), "sort init launch");
-  const uint32_t nbits = bit_length128(bound);
-  for (uint32_t sh = 0; sh < nbits; sh += 8) {
-    const int use_hi = sh >= 64 ? 1 : 0;
-    const uint64_t* src = use_hi ? kw[cur][1] : kw[cur][0];
-    radix_hist_kernel<<<P->sort_blocks, kSortThreads, 0, st>>>(src, n, sh & 63u, hist, P->sort_blocks);
-    radix_rowscan_kernel<<<256, 256, 0, st>>>(hist, P->sort_blocks, dbase);
-    radix_digitscan_kernel<<<1, 256, 0, st>>>(dbase);
-    radix_scatter_kernel<<<P->sort_blocks, kSortThreads, 0, st>>>(kw[cur][0], kw[cur][1], perm[cur], kw[cur ^ 1][0],
-                                                                  kw[cur ^ 1][1], perm[cur ^ 1], n, sh & 63u, use_hi,
-                                                                  wide, hist, P->sort_blocks, dbase);
-    HIP_TRY(hipGetLastError(), "radix pass launch");
-    cur ^= 1;
-  }
+  int cur = 0;
+  int rc0 = launch_radix(P, ws, bit_length128(bound), wide, st, &cur);
+  if (rc0) return rc0;
   // prefix clique counts via the leaf pass on position keys
   uint32_t* rank = ws.at<uint32_t>(P->off_keyp);
   uint64_t* cnt = ws.at<uint64_t>(P->off_cnt);
@@ -1082,6 +1198,68 @@ int ensure_graph(kdss_plan* P, const WsView& ws, void* d_r) {
   return KDSS_OK;
 }
 
+// Start loads, zero credits and a cleared device result.
+int start_run(kdss_plan* P, const WsView& ws, const uint64_t* d_r0, void* d_r, uint32_t T, hipStream_t st) {
+  DevResult* dres = ws.at<DevResult>(P->off_dres);
+  reset_result_kernel<<<1, 64, 0, st>>>(dres);
+  init_loads_kernel<<<grid_for(P->n), 256, 0, st>>>(d_r0, static_cast<uint64_t*>(d_r), ws.at<uint64_t>(P->off_delta),
+                                                    P->n, P->width == 128 ? 1 : 0, dres);
+  HIP_TRY(hipGetLastError(), "init launch");
+  if (P->opts.time_kernels) {
+    while (P->events.size() < 5ull * T) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e), "event create");
+      P->events.push_back(e);
+    }
+  }
+  return KDSS_OK;
+}
+
+// Iteration t (1-based): timed launches, a graph replay, or plain launches.
+int iterate(kdss_plan* P, const WsView& ws, void* d_r, uint32_t t, hipStream_t st) {
+  if (P->opts.time_kernels) {
+    hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data()) + 5ull * (t - 1);
+    uint64_t* delta = ws.at<uint64_t>(P->off_delta);
+    int rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev);
+    if (rc) return rc;
+    if (P->width == 128) {
+      apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
+    } else {
+      apply64_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
+    }
+    HIP_TRY(hipGetLastError(), "apply launch");
+    HIP_TRY(hipEventRecord(ev[4], st), "event record");
+    return KDSS_OK;
+  }
+  if (P->opts.use_graph) {
+    int rc = ensure_graph(P, ws, d_r);
+    if (rc) return rc;
+    HIP_TRY(hipGraphLaunch(static_cast<hipGraphExec_t>(P->graph_exec), st), "graph launch");
+    return KDSS_OK;
+  }
+  return launch_iteration(P, ws, d_r, st);
+}
+
+// After the stream is synchronised: add the timed kernel durations of T iterations.
+int collect_timing(kdss_plan* P, uint32_t T) {
+  if (!P->opts.time_kernels || P->tiles.empty()) return KDSS_OK;
+  hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data());
+  for (uint32_t t = 0; t < T; ++t) {
+    float a = 0.f, b = 0.f, c = 0.f, d = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, ev[5 * t], ev[5 * t + 1]), "event elapsed");
+    HIP_TRY(hipEventElapsedTime(&b, ev[5 * t + 1], ev[5 * t + 2]), "event elapsed");
+    HIP_TRY(hipEventElapsedTime(&c, ev[5 * t + 2], ev[5 * t + 3]), "event elapsed");
+    HIP_TRY(hipEventElapsedTime(&d, ev[5 * t + 3], ev[5 * t + 4]), "event elapsed");
+    P->timing.leaf_ms += a;
+    P->timing.heavy_ms += b;
+    P->timing.reduce_ms += c;
+    P->timing.apply_ms += d;
+  }
+  P->timing.leaf_launches += T;
+  P->timing.apply_launches += T;
+  return KDSS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1113,6 +1291,8 @@ int kdss_plan_upload(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream) {
   if (!P->hot.empty())
     HIP_TRY(hipMemcpyAsync(ws.at<uint32_t>(P->off_hot), P->hot.data(), P->hot.size() * 4, hipMemcpyHostToDevice, st),
             "upload hot nodes");
+  HIP_TRY(hipMemcpyAsync(ws.at<uint64_t>(P->off_nodeoff), P->node_off.data(), P->node_off.size() * 8,
+                         hipMemcpyHostToDevice, st), "upload node offsets");
   // the heavy-leaf queue starts empty; every leaf pass leaves it empty again
   HIP_TRY(hipMemsetAsync(ws.at<uint32_t>(P->off_qcount), 0, 64, st), "queue reset");
   HIP_TRY(hipStreamSynchronize(st), "upload synchronize");
@@ -1128,42 +1308,13 @@ int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   WsView ws{static_cast<char*>(d_ws)};
-  DevResult* dres = ws.at<DevResult>(P->off_dres);
-  reset_result_kernel<<<1, 64, 0, st>>>(dres);
-  init_loads_kernel<<<grid_for(P->n), 256, 0, st>>>(d_r0, static_cast<uint64_t*>(d_r), ws.at<uint64_t>(P->off_delta),
-                                                    P->n, P->width == 128 ? 1 : 0, dres);
-  HIP_TRY(hipGetLastError(), "init launch");
+  rc = start_run(P, ws, d_r0, d_r, T, st);
+  if (rc) return rc;
   const uint32_t every = P->opts.extract_every;
-  const bool timed = P->opts.time_kernels != 0;
-  if (timed) {
-    while (P->events.size() < 5ull * T) {
-      hipEvent_t e;
-      HIP_TRY(hipEventCreate(&e), "event create");
-      P->events.push_back(e);
-    }
-  }
   uint32_t rows = 0;
   for (uint32_t t = 1; t <= T; ++t) {
-    if (timed) {
-      hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data()) + 5ull * (t - 1);
-      uint64_t* delta = ws.at<uint64_t>(P->off_delta);
-      rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev);
-      if (rc) return rc;
-      if (P->width == 128) {
-        apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
-      } else {
-        apply64_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
-      }
-      HIP_TRY(hipGetLastError(), "apply launch");
-      HIP_TRY(hipEventRecord(ev[4], st), "event record");
-    } else if (P->opts.use_graph) {
-      rc = ensure_graph(P, ws, d_r);
-      if (rc) return rc;
-      HIP_TRY(hipGraphLaunch(static_cast<hipGraphExec_t>(P->graph_exec), st), "graph launch");
-    } else {
-      rc = launch_iteration(P, ws, d_r, st);
-      if (rc) return rc;
-    }
+    rc = iterate(P, ws, d_r, t, st);
+    if (rc) return rc;
     if (every && t % every == 0 && t < T && h_trace && rows < trace_cap) {
       const u128 bound = (u128)P->r0_max + (u128)t * P->c_k;
       rc = launch_extract(P, ws, d_r, d_r0, bound, d_order, st);
@@ -1187,22 +1338,8 @@ int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64
   rc = read_result(P, ws, st, &h);
   if (rc) return rc;
   if (h.r0max > P->r0_max) return fail(KDSS_EOVERFLOW, "a start load exceeds the plan's r0_max");
-  if (timed && !P->tiles.empty()) {
-    hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data());
-    for (uint32_t t = 0; t < T; ++t) {
-      float a = 0.f, b = 0.f, c = 0.f, d = 0.f;
-      HIP_TRY(hipEventElapsedTime(&a, ev[5 * t], ev[5 * t + 1]), "event elapsed");
-      HIP_TRY(hipEventElapsedTime(&b, ev[5 * t + 1], ev[5 * t + 2]), "event elapsed");
-      HIP_TRY(hipEventElapsedTime(&c, ev[5 * t + 2], ev[5 * t + 3]), "event elapsed");
-      HIP_TRY(hipEventElapsedTime(&d, ev[5 * t + 3], ev[5 * t + 4]), "event elapsed");
-      P->timing.leaf_ms += a;
-      P->timing.heavy_ms += b;
-      P->timing.reduce_ms += c;
-      P->timing.apply_ms += d;
-    }
-    P->timing.leaf_launches += T;
-    P->timing.apply_launches += T;
-  }
+  rc = collect_timing(P, T);
+  if (rc) return rc;
   fill_result(P, h, T, h_res);
   if (every && h_trace && rows < trace_cap) {
     kdss_trace_row& row = h_trace[rows++];
@@ -1211,6 +1348,146 @@ int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64
     row.dens_num = h_res->dens_num;
     row.ub_num = h_res->ub_num;
   }
+  return KDSS_OK;
+}
+
+int kdss_batch_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64_t* d_r0, uint64_t* d_r,
+                   uint32_t* d_order, kdss_result* h_res, uint32_t count, void* stream) {
+  if (!P || !d_r || !d_order || !h_res) return fail(KDSS_EINVAL, "null argument");
+  const uint32_t nprob = (uint32_t)(P->node_off.size() - 1);
+  if (count != nprob) return fail(KDSS_ERANGE, "count does not match the plan's problems");
+  if (T == 0 || T > P->T_max) return fail(KDSS_EINVAL, "T must be in 1..T_max");
+  if (P->width != 64) return fail(KDSS_EUNSUPPORTED, "batches need 64-bit loads");
+  int rc = check_ws(P, d_ws, ws_bytes);
+  if (rc) return rc;
+  // sort keys q << rbits | (B - r): B bounds every load of every problem
+  u128 bound = 0;
+  for (u128 ck : P->prob_ck) bound = std::max(bound, (u128)P->r0_max + (u128)T * ck);
+  const uint32_t rbits = bit_length128(bound);
+  const uint32_t qbits = bit_length128(nprob - 1);
+  if (rbits + qbits > 64) return fail(KDSS_EUNSUPPORTED, "batch sort key exceeds 64 bits");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WsView ws{static_cast<char*>(d_ws)};
+  rc = start_run(P, ws, d_r0, d_r, T, st);
+  if (rc) return rc;
+  for (uint32_t t = 1; t <= T; ++t) {
+    rc = iterate(P, ws, d_r, t, st);
+    if (rc) return rc;
+  }
+  // segmented extraction
+  const uint32_t n = P->n;
+  const uint64_t* off = ws.at<uint64_t>(P->off_nodeoff);
+  uint64_t* kw0 = ws.at<uint64_t>(P->off_kw[0][0]);
+  uint32_t* perm0 = ws.at<uint32_t>(P->off_perm[0]);
+  batch_sort_init_kernel<<<nprob, 256, 0, st>>>(d_r, off, rbits, (uint64_t)bound, kw0, perm0);
+  HIP_TRY(hipGetLastError(), "batch sort init launch");
+  int cur = 0;
+  rc = launch_radix(P, ws, rbits + qbits, 0, st, &cur);
+  if (rc) return rc;
+  const uint32_t* perm = ws.at<uint32_t>(P->off_perm[cur]);
+  uint32_t* rank = ws.at<uint32_t>(P->off_keyp);
+  uint64_t* cnt = ws.at<uint64_t>(P->off_cnt);
+  rank_keys_kernel<<<grid_for(n), 256, 0, st>>>(perm, n, rank, cnt);
+  HIP_TRY(hipGetLastError(), "rank keys launch");
+  KeySrc ks{};
+  ks.rank = rank;
+  rc = launch_leaf(P, ws, 3, ks, cnt, st);
+  if (rc) return rc;
+  uint64_t* bsum = ws.at<uint64_t>(P->off_bsum);
+  uint64_t* prefix = ws.at<uint64_t>(P->off_prefix);
+  DevResult* pres = ws.at<DevResult>(P->off_pres);
+  scan_blocksum_kernel<<<P->scan_blocks, kScanThreads, 0, st>>>(cnt, perm, n, bsum);
+  scan_exclusive_single_kernel<uint64_t><<<1, 1024, 0, st>>>(bsum, P->scan_blocks);
+  scan_prefix_kernel<<<P->scan_blocks, kScanThreads, 0, st>>>(cnt, perm, n, bsum, prefix);
+  segment_best_kernel<<<nprob, 256, 0, st>>>(prefix, off, d_r, d_r0, perm, d_order, pres);
+  HIP_TRY(hipGetLastError(), "segment launch");
+  std::vector<DevResult> h(nprob);
+  DevResult hd;
+  HIP_TRY(hipMemcpyAsync(h.data(), pres, sizeof(DevResult) * nprob, hipMemcpyDeviceToHost, st), "result copy");
+  HIP_TRY(hipMemcpyAsync(&hd, ws.at<DevResult>(P->off_dres), sizeof(DevResult), hipMemcpyDeviceToHost, st),
+          "result copy");
+  HIP_TRY(hipStreamSynchronize(st), "stream synchronize");
+  if (hd.r0max > P->r0_max) return fail(KDSS_EOVERFLOW, "a start load exceeds the plan's r0_max");
+  rc = collect_timing(P, T);
+  if (rc) return rc;
+  for (uint32_t q = 0; q < nprob; ++q) {
+    kdss_result& o = h_res[q];
+    std::memset(&o, 0, sizeof(o));
+    o.T = T;
+    o.n = (uint32_t)(P->node_off[q + 1] - P->node_off[q]);
+    o.size = h[q].size;
+    o.width = 64;
+    o.dens_num.lo = h[q].dens_num;
+    o.ub_num.lo = h[q].ub_lo;
+    o.c_k.lo = (uint64_t)P->prob_ck[q];
+    o.density = o.size ? (double)h[q].dens_num / (double)o.size : 0.0;
+    o.upper_bound = (double)h[q].ub_lo / (double)T;
+  }
+  return KDSS_OK;
+}
+
+int kdss_plan_set_launch(kdss_plan* P, uint32_t leaf_blocks, uint32_t heavy_blocks) {
+  if (!P) return fail(KDSS_EINVAL, "null argument");
+  if (leaf_blocks == 0 || leaf_blocks > kLeafBlocksMax || heavy_blocks == 0 || heavy_blocks > kHeavyBlocks)
+    return fail(KDSS_ERANGE, "grid sizes must be in 1..1024");
+  if (P->leaf_blocks != leaf_blocks || P->heavy_blocks != heavy_blocks) drop_graph(P);
+  P->leaf_blocks = leaf_blocks;
+  P->heavy_blocks = heavy_blocks;
+  return KDSS_OK;
+}
+
+int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r, uint32_t warm, uint32_t iters,
+                       kdss_tune_result* out, void* stream) {
+  if (!P || !d_r || !out) return fail(KDSS_EINVAL, "null argument");
+  if (iters == 0 || warm + iters > P->T_max) return fail(KDSS_EINVAL, "warm + iters must be in 1..T_max");
+  int rc = check_ws(P, d_ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WsView ws{static_cast<char*>(d_ws)};
+  const kdss_opts saved = P->opts;
+  P->opts.time_kernels = 0;
+  P->opts.use_graph = 0;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "event create");
+  HIP_TRY(hipEventCreate(&e1), "event create");
+  const uint32_t leaf_c[] = {256, 512, 768, 1024};
+  const uint32_t heavy_c[] = {256, 512, 1024};
+  std::memset(out, 0, sizeof(*out));
+  out->best_ms = 1e30;
+  for (uint32_t lb : leaf_c) {
+    for (uint32_t hb : heavy_c) {
+      P->leaf_blocks = lb;
+      P->heavy_blocks = hb;
+      rc = start_run(P, ws, nullptr, d_r, warm + iters, st);
+      for (uint32_t t = 1; !rc && t <= warm; ++t) rc = iterate(P, ws, d_r, t, st);
+      if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = fail(KDSS_EHIP, "event record");
+      for (uint32_t t = warm + 1; !rc && t <= warm + iters; ++t) rc = iterate(P, ws, d_r, t, st);
+      if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = fail(KDSS_EHIP, "event record");
+      float ms = 0.f;
+      if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(KDSS_EHIP, "event timing");
+      if (rc) break;
+      const uint32_t idx = out->tried++;
+      if (idx < 16) {
+        out->leaf_blocks[idx] = lb;
+        out->heavy_blocks[idx] = hb;
+        out->ms[idx] = ms / iters;
+      }
+      if (ms / iters < out->best_ms) {
+        out->best_ms = ms / iters;
+        out->best_leaf_blocks = lb;
+        out->best_heavy_blocks = hb;
+      }
+    }
+    if (rc) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  P->opts = saved;
+  if (rc) return rc;
+  P->leaf_blocks = out->best_leaf_blocks;
+  P->heavy_blocks = out->best_heavy_blocks;
+  drop_graph(P);
   return KDSS_OK;
 }
 

@@ -54,6 +54,12 @@ class Timing(C.Structure):
                 ("reduce_ms", C.c_double), ("apply_launches", C.c_uint64), ("apply_ms", C.c_double)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("tried", C.c_uint32), ("best_leaf_blocks", C.c_uint32), ("best_heavy_blocks", C.c_uint32),
+                ("best_ms", C.c_double), ("leaf_blocks", C.c_uint32 * 16), ("heavy_blocks", C.c_uint32 * 16),
+                ("ms", C.c_double * 16)]
+
+
 class PlanStats(C.Structure):
     _fields_ = [("workspace_bytes", C.c_uint64), ("stream_bytes", C.c_uint64), ("width", C.c_int),
                 ("key_mode", C.c_int), ("id_bits", C.c_uint32), ("T_max", C.c_uint32),
@@ -74,6 +80,7 @@ EXPORTS = [
     "kdss_status_string", "kdss_last_error", "kdss_csr_validate", "kdss_sct_build", "kdss_sct_info",
     "kdss_sct_export", "kdss_sct_core_numbers", "kdss_sct_free", "kdss_plan_create", "kdss_plan_info",
     "kdss_plan_free", "kdss_plan_upload", "kdss_run", "kdss_leaf_credit", "kdss_extract", "kdss_plan_timing",
+    "kdss_batch_create", "kdss_batch_offsets", "kdss_batch_run", "kdss_plan_set_launch", "kdss_plan_autotune",
 ]
 
 _lib = None
@@ -107,6 +114,12 @@ def lib():
     L.kdss_run.argtypes = [vp, vp, C.c_size_t, C.c_uint32, vp, vp, vp, C.POINTER(TraceRow), C.c_uint32,
                            C.POINTER(Result), vp]
     L.kdss_leaf_credit.argtypes = [vp, vp, C.c_size_t, vp, vp, vp]
+    L.kdss_batch_create.argtypes = [C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_uint64, C.POINTER(Opts),
+                                    C.POINTER(vp)]
+    L.kdss_batch_offsets.argtypes = [vp, p64, C.c_uint32]
+    L.kdss_batch_run.argtypes = [vp, vp, C.c_size_t, C.c_uint32, vp, vp, vp, C.POINTER(Result), C.c_uint32, vp]
+    L.kdss_plan_set_launch.argtypes = [vp, C.c_uint32, C.c_uint32]
+    L.kdss_plan_autotune.argtypes = [vp, vp, C.c_size_t, vp, C.c_uint32, C.c_uint32, C.POINTER(TuneResult), vp]
     L.kdss_extract.argtypes = [vp, vp, C.c_size_t, vp, vp, C.c_uint32, vp, C.POINTER(Result), vp]
     _lib = L
     return L
@@ -207,6 +220,16 @@ class Plan:
         _check(lib().kdss_plan_info(self._h, C.byref(s)), "kdss_plan_info")
         return s
 
+    def set_launch(self, leaf_blocks: int, heavy_blocks: int):
+        _check(lib().kdss_plan_set_launch(self._h, leaf_blocks, heavy_blocks), "kdss_plan_set_launch")
+
+    def autotune(self, ws, r, warm: int = 3, iters: int = 3, stream=None) -> TuneResult:
+        """Time candidate grid sizes on this plan's data and keep the fastest."""
+        out = TuneResult()
+        _check(lib().kdss_plan_autotune(self._h, _ptr(ws), ws.numel(), _ptr(r), warm, iters, C.byref(out),
+                                        _stream(stream)), "kdss_plan_autotune")
+        return out
+
     def timing(self, reset: bool = False) -> Timing:
         t = Timing()
         _check(lib().kdss_plan_timing(self._h, C.byref(t), 1 if reset else 0), "kdss_plan_timing")
@@ -256,6 +279,36 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Batch(Plan):
+    """Many (graph, k) problems laid out as one plan: one launch per iteration
+    covers every problem; each problem's result equals its solo run."""
+
+    def __init__(self, trees, T_max: int, r0_max: int = 0, use_graph: bool = False, time_kernels: bool = False):
+        o = Opts(0, 1 if use_graph else 0, 0, 1 if time_kernels else 0)
+        arr = (C.c_void_p * len(trees))(*[t._h for t in trees])
+        h = C.c_void_p()
+        _check(lib().kdss_batch_create(arr, len(trees), T_max, r0_max, C.byref(o), C.byref(h)), "kdss_batch_create")
+        self._h = h
+        self.count = len(trees)
+        self.T_max = T_max
+        self.extract_every = 0
+        off = np.zeros(self.count + 1, dtype=np.uint64)
+        _check(lib().kdss_batch_offsets(h, off.ctypes.data_as(C.POINTER(C.c_uint64)), self.count),
+               "kdss_batch_offsets")
+        self.node_off = off
+        self.n = int(off[-1])
+        self.k = None
+        st = self.stats()
+        self.width = st.width
+        self.workspace_bytes = st.workspace_bytes
+
+    def run(self, ws, T: int, r, order, r0=None, stream=None):
+        res = (Result * self.count)()
+        _check(lib().kdss_batch_run(self._h, _ptr(ws), ws.numel(), T, _ptr(r0), _ptr(r), _ptr(order), res,
+                                    self.count, _stream(stream)), "kdss_batch_run")
+        return list(res)
 
 
 def loads_to_numpy(r_tensor, n: int, width: int):

@@ -186,3 +186,18 @@ def test_run_rejects_bad_arguments_before_device_work():
     assert L.kdss_run(p._h, C.c_void_p(256), 16, 3, None, C.c_void_p(8), C.c_void_p(8), None, 0,
                       C.byref(res), None) == kdss.EWORKSPACE
     assert b"workspace" in L.kdss_last_error()
+
+
+def test_batch_plan_layout():
+    probs = [(synth.chung_lu(300 + 50 * i, 2000 + 300 * i, 2.3, seed=i), 3 + i % 4) for i in range(5)]
+    trees = [kdss.Tree(g, k) for g, k in probs]
+    b = kdss.Batch(trees, 30)
+    assert b.count == 5
+    assert b.node_off.tolist() == list(np.cumsum([0] + [g.n for g, _ in probs]))
+    st = b.stats()
+    assert sum(st.leaves) == sum(t.stats().leaves for t in trees)
+    assert sum(st.members) == sum(t.stats().members for t in trees)
+    with pytest.raises(kdss.KdssError) as e:
+        b.set_launch(0, 10)
+    assert e.value.status == kdss.ERANGE
+    b.set_launch(512, 256)
