@@ -32,7 +32,77 @@ WORKLOADS = {
     "chung-lu-1m": dict(kind="chung_lu", n=1_000_000, m=10_000_000, beta=2.5, seed=0, planted=40,
                         planted_p=0.9, k=5, T=200),
     "er-200": dict(kind="er", n=200, p=0.08, seed=0, planted=12, k=3, T=64),
+    # 512 Chung-Lu graphs (n in [1k, 50k], average degree 8-40, exponent 2.2-2.8,
+    # seeds 1000 + g), each at k = 3, 4, 6, 8: 2048 problems in one plan
+    "batch-512": dict(kind="batch", graphs=512, ks=(3, 4, 6, 8), T=64),
 }
+
+
+def _batch_graph(i):
+    from paper_2403_05775_amd import synth
+    return synth.batch_member(i)
+
+
+def batch_bench(w, args):
+    """The batch workload: all problems in one plan, autotuned grids, iterations
+    replayed as hipGraphs; a step runs T iterations and every extraction."""
+    import concurrent.futures as cf
+    import numpy as np
+    import torch
+    from paper_2403_05775_amd import kdss
+    t0 = time.time()
+    count = args.batch_graphs or w["graphs"]
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        graphs = list(ex.map(_batch_graph, range(count), chunksize=4))
+    log(f"{count} graphs generated ({time.time() - t0:.1f} s), total n={sum(g.n for g in graphs)}")
+    t1 = time.time()
+    jobs = [(g, k) for g in graphs for k in w["ks"]]
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        trees = list(ex.map(lambda gk: kdss.Tree(gk[0], gk[1], threads=1), jobs))
+    build_s = time.time() - t1
+    L = sum(t.stats().leaves for t in trees)
+    M = sum(t.stats().members for t in trees)
+    log(f"{len(trees)} trees built in {build_s:.1f} s: leaves={L} members={M}")
+    T = w["T"]
+    t2 = time.time()
+    b = kdss.Batch(trees, T, use_graph=True)
+    plan_s = time.time() - t2
+    n_total = b.n
+    for t in trees:
+        t.close()
+    dev = torch.device("cuda:0")
+    ws = b.alloc_workspace(dev)
+    b.upload(ws)
+    r = torch.empty(n_total, dtype=torch.int64, device=dev)
+    order = torch.empty(n_total, dtype=torch.int32, device=dev)
+    tune = b.autotune(ws, r, warm=3, iters=3)
+    log(f"plan {plan_s:.1f} s, workspace {b.workspace_bytes / 1e9:.1f} GB, key mode {b.stats().key_mode}; "
+        f"autotune: leaf {tune.best_leaf_blocks} heavy {tune.best_heavy_blocks} ({tune.best_ms:.3f} ms/iter)")
+    for i in range(args.warmup):
+        b.run(ws, T, r, order)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for i in range(args.steps):
+        res = b.run(ws, T, r, order)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - ts) / args.steps
+    st = b.stats()
+    step_bytes = T * (4 * M + 4 * L + 8 * n_total + 16 * n_total) + 4 * M + 4 * L
+    out = {
+        "metric": "SCT-leaf updates/s", "value": L * T / (ms / 1000.0), "unit": "leaf-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"batch of {count} Chung-Lu graphs x k in {list(w['ks'])}, T={T}",
+                   "problems": len(jobs), "n_total": n_total, "leaves": L, "members": M,
+                   "key_mode": st.key_mode, "parallelism": "single GPU, one launch per iteration, hipGraph"},
+        "hbm_gbps_algorithmic": step_bytes / (ms / 1000.0) / 1e9,
+        "host_build_s": build_s, "plan_s": plan_s,
+        "autotune": {"leaf_blocks": tune.best_leaf_blocks, "heavy_blocks": tune.best_heavy_blocks,
+                     "ms_per_iter": tune.best_ms,
+                     "tried": [[tune.leaf_blocks[i], tune.heavy_blocks[i], tune.ms[i]] for i in range(tune.tried)]},
+        "densest_sizes_first8": [x.size for x in res[:8]],
+    }
+    print(json.dumps(out))
 
 
 def log(msg):
@@ -159,6 +229,7 @@ def main():
     ap.add_argument("--summarize-trace", metavar="DB")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
     ap.add_argument("--out", default="")
+    ap.add_argument("--batch-graphs", type=int, default=0, help="graphs in the batch workload (default 512)")
     args = ap.parse_args()
     if args.summarize_counters:
         res = summarize_counters(args.workload, *args.summarize_counters, args.command)
@@ -174,6 +245,12 @@ def main():
         return
     if args.mode == "counters":
         counters_mode(WORKLOADS[args.workload])
+        return
+    if WORKLOADS[args.workload]["kind"] == "batch":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+            sys.exit(2)
+        batch_bench(WORKLOADS[args.workload], args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))

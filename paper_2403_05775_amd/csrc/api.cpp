@@ -164,6 +164,7 @@ static void layout_workspace(kdss_plan* P) {
   P->leaf_blocks = (uint32_t)std::min<uint64_t>(kLeafBlocksMax, std::max<uint64_t>(1, (P->tiles.size() + 3) / 4));
   P->heavy_blocks = kHeavyBlocks;
   P->off_hot = take(P->hot.size() * 4);
+  P->off_hot_base = take(P->hot.size() * 4);
   // scratch rows for the largest grids the launch tuner may pick
   P->off_scratch = take((size_t)(kLeafBlocksMax + kHeavyBlocks) * P->hot.size() * 8);
   P->lane_leaves = 0;
@@ -210,7 +211,10 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
     P->c_k = trees.size() == 1 ? trees[0]->c_k : ck_total;
     P->s_max = s_max;
     if (opts) P->opts = *opts;
-    P->id_bits = std::max<uint32_t>(1, bit_length(n_total - 1));
+    // packed keys hold problem-local ids: ties are only ever compared inside one leaf
+    uint64_t n_max = 1;
+    for (const Sct* t : trees) n_max = std::max<uint64_t>(n_max, t->n);
+    P->id_bits = std::max<uint32_t>(1, bit_length(n_max - 1));
     P->node_off.assign(1, 0);
     for (const Sct* t : trees) {
       P->node_off.push_back(P->node_off.back() + t->n);
@@ -246,7 +250,12 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
       });
       if (cand.size() > kHotMax) cand.resize(kHotMax);
       P->hot = cand;
-      for (uint32_t i = 0; i < P->hot.size(); ++i) hot_index[P->hot[i]] = i;
+      for (uint32_t i = 0; i < P->hot.size(); ++i) {
+        hot_index[P->hot[i]] = i;
+        const uint64_t q = std::upper_bound(P->node_off.begin(), P->node_off.end(), (uint64_t)P->hot[i]) -
+                           P->node_off.begin() - 1;
+        P->hot_base.push_back((uint32_t)P->node_off[q]);
+      }
     }
     auto encode = [&](uint64_t u) -> uint32_t {
       return hot_index[u] != ~0u ? (kHotFlag | hot_index[u]) : (uint32_t)u;
@@ -279,10 +288,11 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
     };
     for (const LeafRef& r : big) {
       const Sct& t = *trees[r.q];
-      Tile tl;
+      Tile tl{};
       tl.mbase = P->members.size();
       tl.lbase = (uint32_t)P->hdr.size();
       tl.info = pack_tile_info(kTileBig, 1, 0);
+      tl.nbase = (uint32_t)P->node_off[r.q];
       P->hdr.push_back(header(r));
       for (uint64_t x = t.off[r.id]; x < t.off[r.id + 1]; ++x)
         P->members.push_back(encode(P->node_off[r.q] + t.members[x]));
@@ -300,10 +310,11 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
           smax = std::max<uint32_t>(smax, t.h[refs[i0 + nl].id] + t.p[refs[i0 + nl].id]);
           ++nl;
         }
-        Tile tl;
+        Tile tl{};
         tl.mbase = P->members.size();
         tl.lbase = (uint32_t)P->hdr.size();
         tl.info = pack_tile_info(kTileLane, nl, smax);
+        tl.nbase = (uint32_t)P->node_off[refs[i0].q];
         // column-major: member x of leaf r at mbase + 64 x + r; padding reads node 0
         P->members.resize(P->members.size() + (size_t)64 * smax, 0u);
         uint32_t* col = P->members.data() + tl.mbase;

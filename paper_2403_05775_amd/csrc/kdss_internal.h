@@ -70,8 +70,10 @@ struct Tile {
   uint32_t lbase;    // first leaf (index into the header array)
   uint32_t info;     // kind (3 bits: kTileLane / kTileBig) | leaf count (13 bits) << 3
                      // | largest leaf (16 bits) << 16
+  uint32_t nbase;    // first node id of the tile's problem (packed keys use local ids)
+  uint32_t pad[3];
 };
-static_assert(sizeof(Tile) == 16, "tile descriptor is 16 bytes");
+static_assert(sizeof(Tile) == 32, "tile descriptor is 32 bytes");
 
 // Launch geometry shared by the planner (workspace sizes) and the kernels.
 constexpr uint32_t kSortThreads = 256, kSortItems = 8, kSortTile = kSortThreads * kSortItems;
@@ -127,7 +129,8 @@ struct kdss_plan {
   uint32_t sort_blocks = 0, scan_blocks = 0, red_blocks = 0;
   uint32_t leaf_blocks = 0;            // persistent grid of the leaf-credit kernel
   std::vector<uint32_t> hot;           // original ids of the hot nodes
-  size_t off_hot = 0, off_scratch = 0, off_dbase = 0, off_queue = 0, off_qcount = 0;
+  std::vector<uint32_t> hot_base;      // first node id of each hot node's problem
+  size_t off_hot = 0, off_hot_base = 0, off_scratch = 0, off_dbase = 0, off_queue = 0, off_qcount = 0;
   uint32_t heavy_blocks = 0;           // grid of the heavy-leaf kernel
   uint32_t k1 = 0;                     // binomial table row length (largest k + 1)
   kdss::u128 bound_max = 0;            // largest r0_max + T_max * c_k over the problems

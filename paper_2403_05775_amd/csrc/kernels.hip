@@ -38,20 +38,22 @@ __device__ __forceinline__ uint32_t readlane32(uint32_t v, int lane) {
 // ----------------------------------------------------------------------------
 // Keys.  A leaf orders its members by (load, node id); the minimum of a clique
 // is the member with the smallest key.  Four encodings:
-//   KPacked: load << id_bits | id in one u64 (built from the gathered load);
+//   KPacked: load << id_bits | local id in one u64 (built from the gathered
+//            load; local id = id - first id of the node's problem);
 //   KFull:   (u64 load, id);  KWide: (u128 load, id);
 //   KRank:   a unique u32 (the extraction's n - 1 - position).
 // ----------------------------------------------------------------------------
 struct KeySrc {
   const uint64_t* r;      // loads (u64, or u128 as lo/hi pairs)
   const uint32_t* rank;   // extraction keys
-  uint32_t id_bits;       // packed keys: load << id_bits | id
+  uint32_t id_bits;       // packed keys: load << id_bits | (id - base)
+  uint32_t base;          // first node id of the problem being processed
 };
 
 struct KPacked {
   uint64_t v;
   __device__ static KPacked mx() { return {~0ull}; }
-  __device__ static KPacked load(const KeySrc& s, uint32_t u) { return {(s.r[u] << s.id_bits) | u}; }
+  __device__ static KPacked load(const KeySrc& s, uint32_t u) { return {(s.r[u] << s.id_bits) | (u - s.base)}; }
   __device__ bool lt(const KPacked& o) const { return v < o.v; }
   __device__ bool eq(const KPacked& o) const { return v == o.v; }
   __device__ KPacked sx(int m) const { return {shfl_xor64(v, m)}; }
@@ -311,14 +313,17 @@ __global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict
                                                           const uint32_t* __restrict__ hdr,
                                                           const uint64_t* __restrict__ binom, uint32_t nbinom,
                                                           uint32_t k1, KeySrc src, uint64_t* __restrict__ out,
-                                                          const uint32_t* __restrict__ hot, uint32_t nhot,
+                                                          const uint32_t* __restrict__ hot,
+                                                          const uint32_t* __restrict__ hot_base, uint32_t nhot,
                                                           uint64_t* __restrict__ scratch, uint32_t* __restrict__ queue,
                                                           uint32_t* __restrict__ qcount) {
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kBinomLds];
   for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
-    hkey[i] = KT::load(src, hot[i]);
+    KeySrc hs = src;
+    hs.base = hot_base[i];
+    hkey[i] = KT::load(hs, hot[i]);
     hcnt[i] = 0;
   }
   const bool lds_binom = nbinom <= kBinomLds;
@@ -331,8 +336,10 @@ __global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict
   const uint32_t stride = gridDim.x * 4u;
   for (uint32_t tile = blockIdx.x * 4u + w; tile < ntiles; tile += stride) {
     const Tile t = tiles[tile];
-    if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k1, src, hkey, sink);
-    else tile_lane<KT>(t, tile, members, hdr, bt, k1, src, hkey, sink, queue, qcount);
+    KeySrc ts = src;
+    ts.base = t.nbase;
+    if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k1, ts, hkey, sink);
+    else tile_lane<KT>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount);
   }
   sink.flush();
   __syncthreads();
@@ -349,7 +356,8 @@ template <class KT>
 __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ tiles, const uint32_t* __restrict__ members,
                                                     const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ binom,
                                                     uint32_t nbinom, uint32_t k1, KeySrc src, uint64_t* __restrict__ out,
-                                                    const uint32_t* __restrict__ hot, uint32_t nhot,
+                                                    const uint32_t* __restrict__ hot,
+                                                    const uint32_t* __restrict__ hot_base, uint32_t nhot,
                                                     uint64_t* __restrict__ scratch, uint32_t row0,
                                                     const uint32_t* __restrict__ queue,
                                                     const uint32_t* __restrict__ qcount) {
@@ -357,7 +365,9 @@ __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ til
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kBinomLds];
   for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
-    hkey[i] = KT::load(src, hot[i]);
+    KeySrc hs = src;
+    hs.base = hot_base[i];
+    hkey[i] = KT::load(hs, hot[i]);
     hcnt[i] = 0;
   }
   const bool lds_binom = nbinom <= kBinomLds;
@@ -372,7 +382,7 @@ __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ til
   constexpr uint32_t B = 4;
   const uint32_t nw = gridDim.x * 4u;
   for (uint32_t e0 = (blockIdx.x * 4u + w) * B; e0 < total; e0 += nw * B) {
-    uint32_t hq[B], sq[B], jq[B], ra[B];
+    uint32_t hq[B], sq[B], jq[B], ra[B], nb[B];
     KT ka[B];
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
@@ -380,6 +390,7 @@ __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ til
       const uint32_t ent = queue[e];
       const Tile t = tiles[ent >> 6];
       const uint32_t L = ent & 63u;
+      nb[q] = t.nbase;
       const uint32_t hd = hdr[t.lbase + L];
       hq[q] = hd & 31u;
       jq[q] = (hd >> 5) & 31u;
@@ -387,7 +398,11 @@ __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ til
       ra[q] = lane < sq[q] ? members[t.mbase + (size_t)lane * 64 + L] : 0u;
     }
 #pragma unroll
-    for (uint32_t q = 0; q < B; ++q) ka[q] = lane < sq[q] ? member_key_nb<KT>(src, hkey, ra[q]) : KT::mx();
+    for (uint32_t q = 0; q < B; ++q) {
+      KeySrc ts = src;
+      ts.base = nb[q];
+      ka[q] = lane < sq[q] ? member_key_nb<KT>(ts, hkey, ra[q]) : KT::mx();
+    }
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
       if (e0 + q >= total) break;
@@ -1005,6 +1020,7 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   const uint32_t* hdr = ws.at<uint32_t>(P->off_hdr);
   const uint64_t* binom = ws.at<uint64_t>(P->off_binom);
   const uint32_t* hot = ws.at<uint32_t>(P->off_hot);
+  const uint32_t* hot_base = ws.at<uint32_t>(P->off_hot_base);
   const uint32_t nhot = (uint32_t)P->hot.size();
   uint64_t* scratch = ws.at<uint64_t>(P->off_scratch);
   uint32_t* queue = ws.at<uint32_t>(P->off_queue);
@@ -1013,10 +1029,10 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
 #define KDSS_LEAF(KT)                                                                                           \
   leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src, out,    \
-                                                 hot, nhot, scratch, queue, qcount);                             \
+                                                 hot, hot_base, nhot, scratch, queue, qcount);                   \
   if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event record");                                                    \
   heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(tiles, members, hdr, binom, nbinom, P->k1, src, out, hot,     \
-                                                    nhot, scratch, blocks, queue, qcount)
+                                                    hot_base, nhot, scratch, blocks, queue, qcount)
   switch (mode) {
     case 0: KDSS_LEAF(KPacked); break;
     case 1: KDSS_LEAF(KFull); break;
@@ -1288,9 +1304,12 @@ int kdss_plan_upload(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream) {
                            hipMemcpyHostToDevice, st), "upload tiles");
   HIP_TRY(hipMemcpyAsync(ws.at<uint64_t>(P->off_binom), P->binom.data(), P->binom.size() * 8, hipMemcpyHostToDevice,
                          st), "upload binomials");
-  if (!P->hot.empty())
+  if (!P->hot.empty()) {
     HIP_TRY(hipMemcpyAsync(ws.at<uint32_t>(P->off_hot), P->hot.data(), P->hot.size() * 4, hipMemcpyHostToDevice, st),
             "upload hot nodes");
+    HIP_TRY(hipMemcpyAsync(ws.at<uint32_t>(P->off_hot_base), P->hot_base.data(), P->hot_base.size() * 4,
+                           hipMemcpyHostToDevice, st), "upload hot node bases");
+  }
   HIP_TRY(hipMemcpyAsync(ws.at<uint64_t>(P->off_nodeoff), P->node_off.data(), P->node_off.size() * 8,
                          hipMemcpyHostToDevice, st), "upload node offsets");
   // the heavy-leaf queue starts empty; every leaf pass leaves it empty again
