@@ -1,0 +1,94 @@
+/*
+ * kdss warm-start model -- a small message-passing network on gfx950.
+ *
+ * The loads r of Frank-Wolfe start from integers r0 (the paper's Algorithm 2
+ * leaves "initialize r(u)" open); this model predicts y(u) ~ log1p(r*(u) / T),
+ * the per-iteration load a long cold run reaches, from three node features
+ * (degree, core number, triangle count), and r0 = round(t0 * expm1(y)).
+ * Frank-Wolfe then runs unchanged (kdss_run with d_r0), so the results stay
+ * exact; only the number of iterations to a good density changes.
+ *
+ * Model: x0 = features (n x 32 BF16, columns 3..31 zero);
+ *   h1 = ReLU([x0 | mean_N(x0)] W1 + b1)      (K = 64)
+ *   h2 = ReLU([h1 | mean_N(h1)] W2 + b2)      (K = 128)
+ *   h3 = ReLU([h2 | mean_N(h2)] W3 + b3)      (K = 128)
+ *   y  = h3 w + b                             (FP32)
+ * Every product runs on the matrix cores with BF16 operands and FP32
+ * accumulation (v_mfma_f32_32x32x8_bf16); FP32 -> BF16 rounds to nearest even.
+ *
+ * Conventions as in kdss.h: device pointers are caller-owned, work is
+ * enqueued on `stream` (a hipStream_t), status codes are kdss.h's.  Row-major
+ * BF16 buffers are uint16_t; leading dimensions count elements and must be
+ * multiples of 4; buffers must be 8-byte aligned.
+ */
+#ifndef KDSS_GNN_H
+#define KDSS_GNN_H
+
+#include "kdss.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Device workspace (bytes) that kdss_gnn_features needs for graph g. */
+int kdss_gnn_features_workspace(const kdss_csr *g, size_t *bytes);
+
+/* x0 (device, n x 32 BF16) = [log1p(degree), log1p(core number),
+ * log1p(triangles through the node), 0, ...].  Core numbers come from the tree's
+ * degeneracy order; triangles are counted on the GPU over the DAG that orients
+ * every edge along that order.  g (host) must be the tree's graph; d_row_ptr is
+ * its row_ptr on the device.  Synchronises the stream. */
+int kdss_gnn_features(const kdss_sct *s, const kdss_csr *g, const uint64_t *d_row_ptr, uint16_t *d_x0,
+                      void *d_ws, size_t ws_bytes, void *stream);
+
+/* out[u] = mean over neighbours v of h[v] (F = 32 or 64 columns; 0 for isolated nodes). */
+int kdss_gnn_aggregate(uint32_t n, const uint64_t *d_row_ptr, const uint32_t *d_col, const uint16_t *d_h,
+                       uint32_t F, uint16_t *d_out, void *stream);
+
+/* Transpose of the mean: out[v] = dself[v] + sum over u in N(v) of dagg[u] / deg(u)
+ * (dagg and dself have leading dimension ld; out is dense n x F). */
+int kdss_gnn_aggregate_backward(uint32_t n, const uint64_t *d_row_ptr, const uint32_t *d_col,
+                                const uint16_t *d_dagg, const uint16_t *d_dself, uint32_t F, uint32_t ld,
+                                uint16_t *d_out, void *stream);
+
+/* Y[M x 64] (leading dim ldy) = act([A1 | A2] Bt^T + bias): A1 has K1 columns,
+ * A2 K2 (multiples of 8, K1 + K2 <= 128), Bt is 64 x (K1 + K2) BF16, bias
+ * (nullable) 64 FP32, act = ReLU when relu != 0. */
+int kdss_gnn_linear(uint32_t M, const uint16_t *d_a1, uint32_t K1, uint32_t lda1, const uint16_t *d_a2,
+                    uint32_t K2, uint32_t lda2, const uint16_t *d_bt, const float *d_bias, int relu,
+                    uint16_t *d_y, uint32_t ldy, void *stream);
+
+/* dW[(K1 + K2) x 64] += [A1 | A2]^T dY and db[64] += column sums of dY (FP32,
+ * accumulated; db nullable); K1 + K2 = 64 or 128; dY is M x 64 BF16. */
+int kdss_gnn_linear_wgrad(uint32_t M, const uint16_t *d_a1, uint32_t K1, uint32_t lda1, const uint16_t *d_a2,
+                          uint32_t K2, uint32_t lda2, const uint16_t *d_dy, float *d_dw, float *d_db,
+                          void *stream);
+
+/* dY[i] = 0 where Y[i] <= 0 (ReLU backward on BF16 buffers of `count` elements). */
+int kdss_gnn_relu_backward(uint64_t count, const uint16_t *d_y, uint16_t *d_dy, void *stream);
+
+/* pred[u] = sum_c h[u][c] w[c] + w[64]  (h: n x 64 BF16, w: 65 FP32). */
+int kdss_gnn_head(uint32_t n, const uint16_t *d_h, const float *d_w, float *d_pred, void *stream);
+
+/* Mean squared error against target: *loss += mean (pred - target)^2; with
+ * d = 2 (pred - target) / n: dh = d w (BF16), dw[c] += sum d h[.][c], dw[64] += sum d. */
+int kdss_gnn_head_backward(uint32_t n, const uint16_t *d_h, const float *d_w, const float *d_pred,
+                           const float *d_target, uint16_t *d_dh, float *d_dw, float *d_loss, void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on `count` FP32 parameters. */
+int kdss_gnn_adam(uint32_t count, float *d_p, const float *d_g, float *d_m, float *d_v, float lr, float b1,
+                  float b2, float eps, uint32_t step, void *stream);
+
+/* BF16 copies of a K x 64 FP32 weight: W (K x 64, nullable) and Wt (64 x K, nullable). */
+int kdss_gnn_pack_weights(uint32_t K, const float *d_w32, uint16_t *d_w, uint16_t *d_wt, void *stream);
+
+/* r0[u] = round(t0 * expm1(pred[u])) clamped to [0, cap]; *d_rmax = max(*d_rmax, max r0)
+ * (clear *d_rmax first). */
+int kdss_gnn_warm_start(uint32_t n, const float *d_pred, double t0, uint64_t cap, uint64_t *d_r0,
+                        uint64_t *d_rmax, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDSS_GNN_H */

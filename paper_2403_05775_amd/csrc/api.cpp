@@ -6,10 +6,6 @@
 
 #include "kdss_internal.h"
 
-struct kdss_sct {
-  kdss::Sct s;
-};
-
 namespace kdss {
 
 thread_local std::string g_last_error;

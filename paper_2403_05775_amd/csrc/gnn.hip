@@ -1,0 +1,521 @@
+// Warm-start model for the Frank-Wolfe loads: a small message-passing network
+// whose kernels run on gfx950 with BF16 operands and FP32 accumulation on the
+// matrix cores (v_mfma_f32_32x32x8_bf16).  The model only chooses the integer
+// start loads r0; the method's arithmetic is unchanged (a warm start is just
+// Algorithm 2's "initialize r(u)").
+//
+// Layout conventions: activations are row-major BF16 (n rows); weights of a
+// layer with K inputs are kept as W[K][64] (gradient layout) and Wt[64][K]
+// (forward layout).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/kdss_gnn.h"
+#include "kdss_internal.h"
+
+using namespace kdss;
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// IEEE binary32 -> bfloat16, round to nearest, ties to even; NaN stays a quiet NaN.
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x0040u);
+  const uint32_t rounding = 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)((u + rounding) >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+int hip_fail(hipError_t e, const char* what) { return fail(KDSS_EHIP, std::string(what) + ": " + hipGetErrorString(e)); }
+#define HIP_TRY(call, what)                            \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, what);   \
+  } while (0)
+
+uint32_t blocks_for(size_t n, uint32_t per, uint32_t cap = 65535) {
+  size_t b = (n + per - 1) / per;
+  return (uint32_t)std::max<size_t>(1, std::min<size_t>(b, cap));
+}
+
+// ---------------------------------------------------------------------------
+// Features
+// ---------------------------------------------------------------------------
+
+// Triangles through every node on the DAG that orients each edge from the
+// earlier to the later node of the degeneracy order (out-degree <= degeneracy):
+// a wavefront per node u; for every out-neighbour v of u and every
+// out-neighbour w of v, w in N+(u) closes the triangle {u, v, w}, found once.
+__global__ __launch_bounds__(256) void triangle_kernel(uint32_t n, const uint64_t* __restrict__ orp,
+                                                       const uint32_t* __restrict__ ocol,
+                                                       uint32_t* __restrict__ tri) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const uint32_t nw = gridDim.x * 4u;
+  for (uint32_t u = wave; u < n; u += nw) {
+    const uint64_t ub = orp[u], ue = orp[u + 1];
+    if (ue - ub < 2) continue;
+    for (uint64_t a = ub; a < ue; ++a) {
+      const uint32_t v = ocol[a];
+      const uint64_t vb = orp[v], ve = orp[v + 1];
+      for (uint64_t x = vb + lane; x < ve; x += 64) {
+        const uint32_t w = ocol[x];
+        // binary search w in N+(u) (sorted ascending)
+        uint64_t lo = ub, hi = ue;
+        while (lo < hi) {
+          const uint64_t mid = (lo + hi) >> 1;
+          if (ocol[mid] < w) lo = mid + 1; else hi = mid;
+        }
+        if (lo < ue && ocol[lo] == w) {
+          atomicAdd(tri + u, 1u);
+          atomicAdd(tri + v, 1u);
+          atomicAdd(tri + w, 1u);
+        }
+      }
+    }
+  }
+}
+
+// x0[u] = [log1p(degree), log1p(core), log1p(triangles), 0, ..., 0] (32 columns, BF16)
+__global__ __launch_bounds__(256) void features_kernel(uint32_t n, const uint64_t* __restrict__ row_ptr,
+                                                       const uint32_t* __restrict__ core,
+                                                       const uint32_t* __restrict__ tri, uint16_t* __restrict__ x0) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)n * 32u;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t u = i >> 5;
+    const uint32_t c = (uint32_t)(i & 31u);
+    float v = 0.f;
+    if (c == 0) v = log1pf((float)(row_ptr[u + 1] - row_ptr[u]));
+    else if (c == 1) v = log1pf((float)core[u]);
+    else if (c == 2) v = log1pf((float)tri[u]);
+    x0[i] = f2bf(v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mean aggregation over neighbours and its transpose
+// ---------------------------------------------------------------------------
+
+// out[u][f] = mean over v in N(u) of h[v][f]; F = 32 or 64; one wavefront per
+// node (F = 32: two nodes per wavefront), FP32 accumulation.
+__global__ __launch_bounds__(256) void aggregate_kernel(uint32_t n, const uint64_t* __restrict__ row_ptr,
+                                                        const uint32_t* __restrict__ col,
+                                                        const uint16_t* __restrict__ h, uint32_t F,
+                                                        uint16_t* __restrict__ out) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t per = 64u / F;                  // nodes per wavefront
+  const uint32_t sub = lane / F, f = lane % F;
+  const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const uint32_t nw = gridDim.x * 4u;
+  for (uint32_t u0 = wave * per; u0 < n; u0 += nw * per) {
+    const uint32_t u = u0 + sub;
+    if (u >= n) continue;
+    const uint64_t b = row_ptr[u], e = row_ptr[u + 1];
+    float s = 0.f;
+    for (uint64_t x = b; x < e; ++x) s += bf2f(h[(size_t)col[x] * F + f]);
+    out[(size_t)u * F + f] = f2bf(e > b ? s / (float)(e - b) : 0.f);
+  }
+}
+
+// out[v][f] = dself[v][f] + sum over u in N(v) of dagg[u][f] / deg(u)
+// (the transpose of the mean aggregation; the graph is symmetric).
+__global__ __launch_bounds__(256) void aggregate_backward_kernel(uint32_t n, const uint64_t* __restrict__ row_ptr,
+                                                                 const uint32_t* __restrict__ col,
+                                                                 const uint16_t* __restrict__ dagg,
+                                                                 const uint16_t* __restrict__ dself, uint32_t F,
+                                                                 uint32_t ld_self, uint16_t* __restrict__ out) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t per = 64u / F;
+  const uint32_t sub = lane / F, f = lane % F;
+  const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const uint32_t nw = gridDim.x * 4u;
+  for (uint32_t v0 = wave * per; v0 < n; v0 += nw * per) {
+    const uint32_t v = v0 + sub;
+    if (v >= n) continue;
+    float s = bf2f(dself[(size_t)v * ld_self + f]);
+    for (uint64_t x = row_ptr[v]; x < row_ptr[v + 1]; ++x) {
+      const uint32_t u = col[x];
+      const float du = (float)(row_ptr[u + 1] - row_ptr[u]);
+      s += bf2f(dagg[(size_t)u * ld_self + f]) / du;
+    }
+    out[(size_t)v * F + f] = f2bf(s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense layers on the matrix cores
+// ---------------------------------------------------------------------------
+
+// Y[row][c] = act(sum_k X[row][k] * Bt[c][k] + bias[c]), c < 64, where
+// X = [A1 (K1 columns, leading dim lda1) | A2 (K2 columns, lda2)], K = K1 + K2
+// <= 128, K1 and K2 multiples of 8.  A workgroup computes 128 rows; wavefront
+// w computes rows 32 w .. 32 w + 31 as two 32x32 tiles, 8 k per instruction.
+// Lane l holds A[l % 32][k0 + 4 (l / 32) .. + 3] and Bt[j0 + l % 32][k0 + 4 (l / 32) .. + 3];
+// accumulator v of lane l is row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
+__global__ __launch_bounds__(256) void gemm_bt_kernel(uint32_t M, const uint16_t* __restrict__ A1, uint32_t K1,
+                                                      uint32_t lda1, const uint16_t* __restrict__ A2, uint32_t K2,
+                                                      uint32_t lda2, const uint16_t* __restrict__ Bt,
+                                                      const float* __restrict__ bias, int relu,
+                                                      uint16_t* __restrict__ Y, uint32_t ldy) {
+  __shared__ __align__(16) uint16_t sB[64 * 128];
+  const uint32_t K = K1 + K2;
+  for (uint32_t i = threadIdx.x; i < 64u * K; i += blockDim.x) sB[i] = Bt[i];
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t li = lane & 31u, kq = (lane >> 5) * 4u;
+  const uint32_t row = blockIdx.x * 128u + w * 32u + li;
+  const bool rv = row < M;
+  f32x16 acc0 = {}, acc1 = {};
+  for (uint32_t k0 = 0; k0 < K; k0 += 8) {
+    bf16x4 a = {0, 0, 0, 0};
+    if (rv) {
+      const uint16_t* src = k0 < K1 ? A1 + (size_t)row * lda1 + k0 + kq : A2 + (size_t)row * lda2 + (k0 - K1) + kq;
+      a = *reinterpret_cast<const bf16x4*>(src);
+    }
+    const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(&sB[li * K + k0 + kq]);
+    const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(&sB[(32u + li) * K + k0 + kq]);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b1, acc1, 0, 0, 0);
+  }
+  const uint32_t rbase = blockIdx.x * 128u + w * 32u;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const uint32_t r = rbase + 8u * (v / 4) + (lane >> 5) * 4u + (v % 4);
+    if (r >= M) continue;
+    float y0 = acc0[v] + (bias ? bias[li] : 0.f);
+    float y1 = acc1[v] + (bias ? bias[32u + li] : 0.f);
+    if (relu) {
+      y0 = fmaxf(y0, 0.f);
+      y1 = fmaxf(y1, 0.f);
+    }
+    Y[(size_t)r * ldy + li] = f2bf(y0);
+    Y[(size_t)r * ldy + 32u + li] = f2bf(y1);
+  }
+}
+
+// dW[k][c] += sum_rows X[row][k] * dY[row][c];  db[c] += sum_rows dY[row][c].
+// Each workgroup takes a band of rows in chunks of 32 staged in LDS; the four
+// wavefronts own the K/32 x 2 output tiles; reduction over rows, 8 per MFMA:
+// A[i][r] = X[r][i0 + i], B[r][j] = dY[r][j0 + j].
+__global__ __launch_bounds__(256) void gemm_wgrad_kernel(uint32_t M, const uint16_t* __restrict__ A1, uint32_t K1,
+                                                         uint32_t lda1, const uint16_t* __restrict__ A2, uint32_t K2,
+                                                         uint32_t lda2, const uint16_t* __restrict__ dY,
+                                                         float* __restrict__ dW, float* __restrict__ db) {
+  __shared__ __align__(16) uint16_t sX[32 * 128];
+  __shared__ __align__(16) uint16_t sD[32 * 64];
+  const uint32_t K = K1 + K2;
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t li = lane & 31u, rq = (lane >> 5) * 4u;
+  const uint32_t ntile = (K / 32u) * 2u;   // 4 (K = 64) or 8 (K = 128)
+  f32x16 acc[2] = {{}, {}};
+  float bsum = 0.f;
+  const uint32_t band = (M + gridDim.x - 1) / gridDim.x;
+  const uint32_t r_begin = blockIdx.x * band, r_end = min(M, r_begin + band);
+  for (uint32_t r0 = r_begin; r0 < r_end; r0 += 32) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < 32u * K; i += blockDim.x) {
+      const uint32_t r = r0 + i / K, k = i % K;
+      uint16_t x = 0;
+      if (r < r_end) x = k < K1 ? A1[(size_t)r * lda1 + k] : A2[(size_t)r * lda2 + (k - K1)];
+      sX[i] = x;
+    }
+    for (uint32_t i = threadIdx.x; i < 32u * 64u; i += blockDim.x) {
+      const uint32_t r = r0 + i / 64u;
+      sD[i] = r < r_end ? dY[(size_t)r * 64u + (i % 64u)] : (uint16_t)0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64)
+      for (uint32_t r = 0; r < 32; ++r) bsum += bf2f(sD[r * 64u + threadIdx.x]);
+#pragma unroll
+    for (uint32_t t = 0; t < 2; ++t) {
+      const uint32_t tile = w * 2u + t;
+      if (tile >= ntile) continue;
+      const uint32_t i0 = (tile >> 1) * 32u, j0 = (tile & 1u) * 32u;
+      for (uint32_t kk = 0; kk < 32; kk += 8) {
+        bf16x4 a, b;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+          a[q] = (short)sX[(kk + rq + q) * K + i0 + li];
+          b[q] = (short)sD[(kk + rq + q) * 64u + j0 + li];
+        }
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (uint32_t t = 0; t < 2; ++t) {
+    const uint32_t tile = w * 2u + t;
+    if (tile >= ntile) continue;
+    const uint32_t i0 = (tile >> 1) * 32u, j0 = (tile & 1u) * 32u;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const uint32_t i = i0 + 8u * (v / 4) + rq + (v % 4);
+      atomicAdd(dW + (size_t)i * 64u + j0 + li, acc[t][v]);
+    }
+  }
+  if (db && threadIdx.x < 64) atomicAdd(db + threadIdx.x, bsum);
+}
+
+// dY *= (Y > 0)
+__global__ __launch_bounds__(256) void relu_backward_kernel(size_t count, const uint16_t* __restrict__ y,
+                                                            uint16_t* __restrict__ dy) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    if (!(bf2f(y[i]) > 0.f)) dy[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Head, loss, optimiser, warm start
+// ---------------------------------------------------------------------------
+
+// pred[u] = sum_c h[u][c] w[c] + b
+__global__ __launch_bounds__(256) void head_kernel(uint32_t n, const uint16_t* __restrict__ h,
+                                                   const float* __restrict__ w, const float* __restrict__ b,
+                                                   float* __restrict__ pred) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    float s = b[0];
+    for (uint32_t c = 0; c < 64; ++c) s += bf2f(h[(size_t)u * 64u + c]) * w[c];
+    pred[u] = s;
+  }
+}
+
+// MSE over n nodes: loss += sum (pred - y)^2 / n; dh = dpred * w (BF16);
+// dw[c] += sum dpred h[u][c]; dw[64] += sum dpred (the bias), dpred = 2 (pred - y) / n.
+__global__ __launch_bounds__(256) void head_backward_kernel(uint32_t n, const uint16_t* __restrict__ h,
+                                                            const float* __restrict__ w,
+                                                            const float* __restrict__ pred,
+                                                            const float* __restrict__ target,
+                                                            uint16_t* __restrict__ dh, float* __restrict__ dw,
+                                                            float* __restrict__ loss) {
+  __shared__ float sw[65 * 4];
+  float gw[65];
+  for (int c = 0; c < 65; ++c) gw[c] = 0.f;
+  float l = 0.f;
+  const float inv_n = 1.f / (float)n;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const float e = pred[u] - target[u];
+    l += e * e * inv_n;
+    const float d = 2.f * e * inv_n;
+    for (uint32_t c = 0; c < 64; ++c) {
+      gw[c] += d * bf2f(h[(size_t)u * 64u + c]);
+      dh[(size_t)u * 64u + c] = f2bf(d * w[c]);
+    }
+    gw[64] += d;
+  }
+  // reduce over the wavefront, then over the four wavefronts
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  for (int c = 0; c < 66; ++c) {
+    float x = c < 65 ? gw[c] : l;
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+    if (lane == 0) {
+      if (c < 65) sw[c * 4 + wv] = x;
+      else l = x;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 65) atomicAdd(dw + threadIdx.x, sw[threadIdx.x * 4] + sw[threadIdx.x * 4 + 1] +
+                                                         sw[threadIdx.x * 4 + 2] + sw[threadIdx.x * 4 + 3]);
+  if (lane == 0) atomicAdd(loss, l);
+}
+
+// Adam on FP32 master parameters (bias-corrected moments).
+__global__ __launch_bounds__(256) void adam_kernel(uint32_t count, float* __restrict__ p, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                                                   float b2, float eps, float c1, float c2) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// BF16 copies of a K x 64 FP32 weight: W[k][c] and its transpose Wt[c][k].
+__global__ __launch_bounds__(256) void pack_weights_kernel(uint32_t K, const float* __restrict__ w32,
+                                                           uint16_t* __restrict__ w, uint16_t* __restrict__ wt) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < K * 64u; i += gridDim.x * blockDim.x) {
+    const uint32_t k = i / 64u, c = i % 64u;
+    const uint16_t b = f2bf(w32[i]);
+    if (w) w[i] = b;
+    if (wt) wt[(size_t)c * K + k] = b;
+  }
+}
+
+// r0[u] = round(t0 * expm1(pred[u])) clamped to [0, cap]; max into *rmax.
+__global__ __launch_bounds__(256) void warm_start_kernel(uint32_t n, const float* __restrict__ pred, double t0,
+                                                         uint64_t cap, uint64_t* __restrict__ r0,
+                                                         unsigned long long* __restrict__ rmax) {
+  unsigned long long mx = 0;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    double x = t0 * expm1((double)pred[u]);
+    if (!(x > 0.0)) x = 0.0;
+    uint64_t r = x >= (double)cap ? cap : (uint64_t)llrint(x);
+    r0[u] = r;
+    mx = r > mx ? r : mx;
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    const unsigned long long o = __shfl_xor(mx, d);
+    mx = o > mx ? o : mx;
+  }
+  if ((threadIdx.x & 63u) == 0 && mx) atomicMax(rmax, mx);
+}
+
+}  // namespace
+
+extern "C" {
+
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+int kdss_gnn_features_workspace(const kdss_csr* g, size_t* bytes) {
+  if (!g || !bytes) return fail(KDSS_EINVAL, "null argument");
+  const size_t n = g->n;
+  *bytes = al256((n + 1) * 8) + al256(std::max<size_t>(1, g->nnz / 2) * 4) + 2 * al256(n * 4);
+  return KDSS_OK;
+}
+
+int kdss_gnn_features(const kdss_sct* s, const kdss_csr* g, const uint64_t* d_row_ptr, uint16_t* d_x0,
+                      void* d_ws, size_t ws_bytes, void* stream) {
+  if (!s || !g || !g->row_ptr || !d_row_ptr || !d_x0 || !d_ws) return fail(KDSS_EINVAL, "null argument");
+  if (g->n != s->s.n) return fail(KDSS_ERANGE, "graph does not match the tree");
+  const uint32_t n = g->n;
+  const Degeneracy& dg = s->s.deg;
+  // host: the DAG from earlier to later node in the degeneracy order, rows sorted by id
+  std::vector<uint64_t> orp(n + 1, 0);
+  for (uint32_t v = 0; v < n; ++v)
+    for (uint64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e)
+      if (dg.rank[g->col[e]] > dg.rank[v]) orp[v + 1]++;
+  for (uint32_t v = 0; v < n; ++v) orp[v + 1] += orp[v];
+  std::vector<uint32_t> ocol(std::max<uint64_t>(1, orp[n]));
+  {
+    std::vector<uint64_t> fp(orp.begin(), orp.end() - 1);
+    for (uint32_t v = 0; v < n; ++v)
+      for (uint64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e)
+        if (dg.rank[g->col[e]] > dg.rank[v]) ocol[fp[v]++] = g->col[e];   // ascending ids kept
+  }
+  auto al = [](size_t x) { return al256(x); };
+  size_t need = 0;
+  kdss_gnn_features_workspace(g, &need);
+  if (ws_bytes < need || ocol.size() > std::max<size_t>(1, g->nnz / 2))
+    return fail(KDSS_EWORKSPACE, "features workspace too small");
+  char* p = static_cast<char*>(d_ws);
+  uint64_t* d_orp = reinterpret_cast<uint64_t*>(p);
+  uint32_t* d_ocol = reinterpret_cast<uint32_t*>(p + al((n + 1) * 8));
+  uint32_t* d_core = reinterpret_cast<uint32_t*>(p + al((n + 1) * 8) + al(ocol.size() * 4));
+  uint32_t* d_tri = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_core) + al((size_t)n * 4));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(d_orp, orp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st), "upload dag");
+  HIP_TRY(hipMemcpyAsync(d_ocol, ocol.data(), ocol.size() * 4, hipMemcpyHostToDevice, st), "upload dag");
+  HIP_TRY(hipMemcpyAsync(d_core, dg.core.data(), (size_t)n * 4, hipMemcpyHostToDevice, st), "upload cores");
+  HIP_TRY(hipMemsetAsync(d_tri, 0, (size_t)n * 4, st), "clear triangles");
+  triangle_kernel<<<blocks_for(n, 4, 16384), 256, 0, st>>>(n, d_orp, d_ocol, d_tri);
+  features_kernel<<<blocks_for((size_t)n * 32, 256, 16384), 256, 0, st>>>(n, d_row_ptr, d_core, d_tri, d_x0);
+  HIP_TRY(hipGetLastError(), "features launch");
+  HIP_TRY(hipStreamSynchronize(st), "features synchronize");   // host DAG buffers go out of scope
+  return KDSS_OK;
+}
+
+int kdss_gnn_aggregate(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint16_t* d_h,
+                       uint32_t F, uint16_t* d_out, void* stream) {
+  if (!d_row_ptr || (!d_col && n) || !d_h || !d_out) return fail(KDSS_EINVAL, "null argument");
+  if (F != 32 && F != 64) return fail(KDSS_EINVAL, "F must be 32 or 64");
+  aggregate_kernel<<<blocks_for(n, 4 * (64 / F), 16384), 256, 0, static_cast<hipStream_t>(stream)>>>(
+      n, d_row_ptr, d_col, d_h, F, d_out);
+  HIP_TRY(hipGetLastError(), "aggregate launch");
+  return KDSS_OK;
+}
+
+int kdss_gnn_aggregate_backward(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint16_t* d_dagg,
+                                const uint16_t* d_dself, uint32_t F, uint32_t ld, uint16_t* d_out, void* stream) {
+  if (!d_row_ptr || (!d_col && n) || !d_dagg || !d_dself || !d_out) return fail(KDSS_EINVAL, "null argument");
+  if ((F != 32 && F != 64) || ld < F) return fail(KDSS_EINVAL, "F must be 32 or 64 and ld >= F");
+  aggregate_backward_kernel<<<blocks_for(n, 4 * (64 / F), 16384), 256, 0, static_cast<hipStream_t>(stream)>>>(
+      n, d_row_ptr, d_col, d_dagg, d_dself, F, ld, d_out);
+  HIP_TRY(hipGetLastError(), "aggregate backward launch");
+  return KDSS_OK;
+}
+
+int kdss_gnn_linear(uint32_t M, const uint16_t* d_a1, uint32_t K1, uint32_t lda1, const uint16_t* d_a2, uint32_t K2,
+                    uint32_t lda2, const uint16_t* d_bt, const float* d_bias, int relu, uint16_t* d_y, uint32_t ldy,
+                    void* stream) {
+  if (!d_a1 || !d_bt || !d_y || (K2 && !d_a2)) return fail(KDSS_EINVAL, "null argument");
+  if (K1 % 8 || K2 % 8 || K1 + K2 == 0 || K1 + K2 > 128 || lda1 < K1 || (K2 && lda2 < K2) || ldy < 64 ||
+      lda1 % 4 || lda2 % 4)
+    return fail(KDSS_EINVAL, "K1, K2 multiples of 8 with K1 + K2 <= 128; leading dims >= widths, multiples of 4");
+  gemm_bt_kernel<<<blocks_for(M, 128, 1u << 30), 256, 0, static_cast<hipStream_t>(stream)>>>(
+      M, d_a1, K1, lda1, d_a2, K2, lda2, d_bt, d_bias, relu, d_y, ldy);
+  HIP_TRY(hipGetLastError(), "linear launch");
+  return KDSS_OK;
+}
+
+int kdss_gnn_linear_wgrad(uint32_t M, const uint16_t* d_a1, uint32_t K1, uint32_t lda1, const uint16_t* d_a2,
+                          uint32_t K2, uint32_t lda2, const uint16_t* d_dy, float* d_dw, float* d_db, void* stream) {
+  if (!d_a1 || !d_dy || !d_dw || (K2 && !d_a2)) return fail(KDSS_EINVAL, "null argument");
+  const uint32_t K = K1 + K2;
+  if ((K != 64 && K != 128) || K1 % 8 || K2 % 8) return fail(KDSS_EINVAL, "K1 + K2 must be 64 or 128");
+  gemm_wgrad_kernel<<<blocks_for(M, 2048, 256), 256, 0, static_cast<hipStream_t>(stream)>>>(
+      M, d_a1, K1, lda1, d_a2, K2, lda2, d_dy, d_dw, d_db);
+  HIP_TRY(hipGetLastError(), "weight gradient launch");
+  return KDSS_OK;
+}
+
+int kdss_gnn_relu_backward(uint64_t count, const uint16_t* d_y, uint16_t* d_dy, void* stream) {
+  if (!d_y || !d_dy) return fail(KDSS_EINVAL, "null argument");
+  relu_backward_kernel<<<blocks_for(count, 256, 16384), 256, 0, static_cast<hipStream_t>(stream)>>>(count, d_y, d_dy);
+  HIP_TRY(hipGetLastError(), "relu backward launch");
+  return KDSS_OK;
+}
+
+int kdss_gnn_head(uint32_t n, const uint16_t* d_h, const float* d_w, float* d_pred, void* stream) {
+  if (!d_h || !d_w || !d_pred) return fail(KDSS_EINVAL, "null argument");
+  head_kernel<<<blocks_for(n, 256, 16384), 256, 0, static_cast<hipStream_t>(stream)>>>(n, d_h, d_w, d_w + 64, d_pred);
+  HIP_TRY(hipGetLastError(), "head launch");
+  return KDSS_OK;
+}
+
+int kdss_gnn_head_backward(uint32_t n, const uint16_t* d_h, const float* d_w, const float* d_pred,
+                           const float* d_target, uint16_t* d_dh, float* d_dw, float* d_loss, void* stream) {
+  if (!d_h || !d_w || !d_pred || !d_target || !d_dh || !d_dw || !d_loss || n == 0)
+    return fail(KDSS_EINVAL, "null argument or n == 0");
+  head_backward_kernel<<<blocks_for(n, 256, 2048), 256, 0, static_cast<hipStream_t>(stream)>>>(
+      n, d_h, d_w, d_pred, d_target, d_dh, d_dw, d_loss);
+  HIP_TRY(hipGetLastError(), "head backward launch");
+  return KDSS_OK;
+}
+
+int kdss_gnn_adam(uint32_t count, float* d_p, const float* d_g, float* d_m, float* d_v, float lr, float b1, float b2,
+                  float eps, uint32_t step, void* stream) {
+  if (!d_p || !d_g || !d_m || !d_v || step == 0) return fail(KDSS_EINVAL, "null argument or step == 0");
+  const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+  adam_kernel<<<blocks_for(count, 256, 4096), 256, 0, static_cast<hipStream_t>(stream)>>>(count, d_p, d_g, d_m, d_v, lr,
+                                                                                          b1, b2, eps, c1, c2);
+  HIP_TRY(hipGetLastError(), "adam launch");
+  return KDSS_OK;
+}
+
+int kdss_gnn_pack_weights(uint32_t K, const float* d_w32, uint16_t* d_w, uint16_t* d_wt, void* stream) {
+  if (!d_w32 || (!d_w && !d_wt)) return fail(KDSS_EINVAL, "null argument");
+  pack_weights_kernel<<<blocks_for((size_t)K * 64, 256, 4096), 256, 0, static_cast<hipStream_t>(stream)>>>(
+      K, d_w32, d_w, d_wt);
+  HIP_TRY(hipGetLastError(), "pack weights launch");
+  return KDSS_OK;
+}
+
+int kdss_gnn_warm_start(uint32_t n, const float* d_pred, double t0, uint64_t cap, uint64_t* d_r0, uint64_t* d_rmax,
+                        void* stream) {
+  if (!d_pred || !d_r0 || !d_rmax) return fail(KDSS_EINVAL, "null argument");
+  if (!(t0 >= 0.0)) return fail(KDSS_EINVAL, "t0 must be non-negative");
+  warm_start_kernel<<<blocks_for(n, 256, 4096), 256, 0, static_cast<hipStream_t>(stream)>>>(
+      n, d_pred, t0, cap, d_r0, reinterpret_cast<unsigned long long*>(d_rmax));
+  HIP_TRY(hipGetLastError(), "warm start launch");
+  return KDSS_OK;
+}
+
+}  // extern "C"

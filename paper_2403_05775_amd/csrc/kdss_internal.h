@@ -108,6 +108,11 @@ inline uint32_t pack_tile_info(uint32_t kind, uint32_t leaves, uint32_t smax) {
 
 }  // namespace kdss
 
+// The host clique tree behind the opaque kdss_sct handle.
+struct kdss_sct {
+  kdss::Sct s;
+};
+
 // The device plan of one clique tree (opaque to callers as kdss_plan).
 struct kdss_plan {
   uint32_t n = 0, k = 0, T_max = 0, id_bits = 0, s_max = 0;

@@ -1,0 +1,279 @@
+"""Warm start for Frank-Wolfe from a small message-passing network.
+
+Orchestration only: every feature, layer, gradient and optimiser step runs in
+the HIP kernels of libkdss.so (``include/kdss_gnn.h``); torch holds the device
+buffers.  The model predicts y(u) ~ log1p(r*(u) / T) -- the per-iteration load
+of node u after a long cold run -- and the warm start is
+r0 = round(t0 * expm1(y)), fed to ``kdss_run`` unchanged, so the method's
+arithmetic (and exactness) is untouched.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import time
+
+import numpy as np
+
+from . import kdss, synth
+
+HIDDEN = 64
+F0 = 32          # feature columns (3 used, padded for the matrix cores)
+LAYERS = [(F0, F0), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN)]   # (self columns, neighbour columns)
+WEIGHTS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gnn_weights.npz")
+
+_bound = False
+
+
+def _lib():
+    global _bound
+    L = kdss.lib()
+    if not _bound:
+        vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
+        L.kdss_gnn_features_workspace.argtypes = [C.POINTER(kdss.Csr), C.POINTER(C.c_size_t)]
+        L.kdss_gnn_features.argtypes = [vp, C.POINTER(kdss.Csr), vp, vp, vp, C.c_size_t, vp]
+        L.kdss_gnn_aggregate.argtypes = [u32, vp, vp, vp, u32, vp, vp]
+        L.kdss_gnn_aggregate_backward.argtypes = [u32, vp, vp, vp, vp, u32, u32, vp, vp]
+        L.kdss_gnn_linear.argtypes = [u32, vp, u32, u32, vp, u32, u32, vp, vp, C.c_int, vp, u32, vp]
+        L.kdss_gnn_linear_wgrad.argtypes = [u32, vp, u32, u32, vp, u32, u32, vp, vp, vp, vp]
+        L.kdss_gnn_relu_backward.argtypes = [u64, vp, vp, vp]
+        L.kdss_gnn_head.argtypes = [u32, vp, vp, vp, vp]
+        L.kdss_gnn_head_backward.argtypes = [u32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.kdss_gnn_adam.argtypes = [u32, vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, u32, vp]
+        L.kdss_gnn_pack_weights.argtypes = [u32, vp, vp, vp, vp]
+        L.kdss_gnn_warm_start.argtypes = [u32, vp, C.c_double, u64, vp, vp, vp]
+        _bound = True
+    return L
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def _s():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ck(status, where):
+    kdss._check(status, where)
+
+
+class DeviceGraph:
+    """A graph's CSR on the device, its features and (optionally) labels."""
+
+    def __init__(self, graph, tree=None, device="cuda"):
+        import torch
+        self.n = graph.n
+        self.row_ptr = torch.from_numpy(graph.row_ptr.astype(np.int64)).to(device)
+        col = graph.col if graph.col.size else np.zeros(1, np.uint32)
+        self.col = torch.from_numpy(col.view(np.int32)).to(device)
+        own = tree is None
+        tree = tree or kdss.Tree(graph, 3)
+        self.x0 = features(graph, tree, self.row_ptr)
+        if own:
+            tree.close()
+        self.target = None
+
+
+def features(graph, tree, d_row_ptr):
+    """x0 (n x 32 BF16 as int16) = log1p of degree, core number, triangle count."""
+    import torch
+    c, keep = kdss._csr(graph)
+    nbytes = C.c_size_t(0)
+    _ck(_lib().kdss_gnn_features_workspace(C.byref(c), C.byref(nbytes)), "kdss_gnn_features_workspace")
+    ws = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=d_row_ptr.device)
+    x0 = torch.empty((graph.n, F0), dtype=torch.int16, device=d_row_ptr.device)
+    _ck(_lib().kdss_gnn_features(tree._h, C.byref(c), _p(d_row_ptr), _p(x0), _p(ws), ws.numel(), _s()),
+        "kdss_gnn_features")
+    return x0
+
+
+def bf16_to_float(t):
+    """BF16 bits held in an int16 tensor -> float32 tensor (exact)."""
+    import torch
+    return (t.to(torch.int32) << 16).view(torch.float32)
+
+
+def float_to_bf16_rne(x):
+    """float32 -> BF16 bits with round to nearest even (torch reference of the kernels' rounding)."""
+    import torch
+    u = x.contiguous().view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (r & 0xFFFF).to(torch.int32).to(torch.int16)
+
+
+class Model:
+    """Parameters (FP32 masters + BF16 copies), Adam state, and the kernels' forward/backward."""
+
+    def __init__(self, device="cuda", seed=0):
+        import torch
+        self.device = device
+        rs = synth.Stream(seed, 77)
+        self.params = []
+        for (ks, kn) in LAYERS:
+            K = ks + kn
+            scale = math.sqrt(6.0 / (K + HIDDEN))
+            w = ((rs.uniform(K * HIDDEN) * 2 - 1) * scale).astype(np.float32).reshape(K, HIDDEN)
+            self.params.append(torch.from_numpy(w).to(device))
+            self.params.append(torch.zeros(HIDDEN, dtype=torch.float32, device=device))
+        head = ((rs.uniform(HIDDEN + 1) * 2 - 1) * math.sqrt(6.0 / (HIDDEN + 1))).astype(np.float32)
+        head[HIDDEN] = 0.0
+        self.params.append(torch.from_numpy(head).to(device))
+        self.grads = [torch.zeros_like(p) for p in self.params]
+        self.m = [torch.zeros_like(p) for p in self.params]
+        self.v = [torch.zeros_like(p) for p in self.params]
+        self.w16 = [torch.empty(p.shape, dtype=torch.int16, device=device) for p in self.params[0:6:2]]
+        self.wt16 = [torch.empty((HIDDEN, p.shape[0]), dtype=torch.int16, device=device) for p in self.params[0:6:2]]
+        self.step_count = 0
+        self.pack()
+
+    def pack(self):
+        for i, w in enumerate(self.params[0:6:2]):
+            _ck(_lib().kdss_gnn_pack_weights(w.shape[0], _p(w), _p(self.w16[i]), _p(self.wt16[i]), _s()),
+                "kdss_gnn_pack_weights")
+
+    def state(self):
+        return {f"p{i}": p.cpu().numpy() for i, p in enumerate(self.params)}
+
+    def load(self, state):
+        import torch
+        for i, p in enumerate(self.params):
+            p.copy_(torch.from_numpy(np.asarray(state[f"p{i}"], dtype=np.float32)))
+        self.pack()
+
+    def forward(self, dg):
+        """Returns (pred FP32 [n], activations for backward)."""
+        import torch
+        L = _lib()
+        n = dg.n
+        acts = []
+        h, F = dg.x0, F0
+        for li in range(3):
+            agg = torch.empty((n, F), dtype=torch.int16, device=self.device)
+            _ck(L.kdss_gnn_aggregate(n, _p(dg.row_ptr), _p(dg.col), _p(h), F, _p(agg), _s()), "aggregate")
+            y = torch.empty((n, HIDDEN), dtype=torch.int16, device=self.device)
+            _ck(L.kdss_gnn_linear(n, _p(h), F, F, _p(agg), F, F, _p(self.wt16[li]), _p(self.params[2 * li + 1]), 1,
+                                  _p(y), HIDDEN, _s()), "linear")
+            acts.append((h, agg, F, y))
+            h, F = y, HIDDEN
+        pred = torch.empty(n, dtype=torch.float32, device=self.device)
+        _ck(L.kdss_gnn_head(n, _p(h), _p(self.params[6]), _p(pred), _s()), "head")
+        return pred, acts
+
+    def backward(self, dg, pred, acts, target):
+        """Accumulates gradients into self.grads; returns the loss tensor (FP32 [1])."""
+        import torch
+        L = _lib()
+        n = dg.n
+        loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        h3 = acts[-1][3]
+        dy = torch.empty((n, HIDDEN), dtype=torch.int16, device=self.device)
+        _ck(L.kdss_gnn_head_backward(n, _p(h3), _p(self.params[6]), _p(pred), _p(target), _p(dy),
+                                     _p(self.grads[6]), _p(loss), _s()), "head backward")
+        for li in (2, 1, 0):
+            h, agg, F, y = acts[li]
+            _ck(L.kdss_gnn_relu_backward(n * HIDDEN, _p(y), _p(dy), _s()), "relu backward")
+            _ck(L.kdss_gnn_linear_wgrad(n, _p(h), F, F, _p(agg), F, F, _p(dy), _p(self.grads[2 * li]),
+                                        _p(self.grads[2 * li + 1]), _s()), "weight gradient")
+            if li == 0:
+                break
+            # dX = dY W^T: 64 self columns then 64 neighbour columns (ld 128)
+            dx = torch.empty((n, 2 * F), dtype=torch.int16, device=self.device)
+            w16 = self.w16[li]
+            _ck(L.kdss_gnn_linear(n, _p(dy), HIDDEN, HIDDEN, None, 0, 0, _p(w16[0:F]), None, 0, _p(dx), 2 * F,
+                                  _s()), "data gradient")
+            _ck(L.kdss_gnn_linear(n, _p(dy), HIDDEN, HIDDEN, None, 0, 0, _p(w16[F:2 * F]), None, 0,
+                                  _p(dx[:, F:]), 2 * F, _s()), "data gradient")
+            dh = torch.empty((n, F), dtype=torch.int16, device=self.device)
+            _ck(L.kdss_gnn_aggregate_backward(n, _p(dg.row_ptr), _p(dg.col), _p(dx[:, F:]), _p(dx), F, 2 * F,
+                                              _p(dh), _s()), "aggregate backward")
+            dy = dh
+        return loss
+
+    def zero_grad(self):
+        for g in self.grads:
+            g.zero_()
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step_count += 1
+        L = _lib()
+        for p, g, m, v in zip(self.params, self.grads, self.m, self.v):
+            _ck(L.kdss_gnn_adam(p.numel(), _p(p), _p(g), _p(m), _p(v), lr, b1, b2, eps, self.step_count, _s()),
+                "adam")
+        self.pack()
+
+    def warm_start(self, dg, t0, cap=1 << 62):
+        """r0 (device uint64 as int64) and its maximum, from a forward pass."""
+        import torch
+        pred, _ = self.forward(dg)
+        r0 = torch.empty(dg.n, dtype=torch.int64, device=self.device)
+        rmax = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _ck(_lib().kdss_gnn_warm_start(dg.n, _p(pred), float(t0), cap, _p(r0), _p(rmax), _s()), "warm start")
+        return r0, int(rmax.item())
+
+
+def label(graph, tree, T, device="cuda"):
+    """Cold-run label y = log1p(r_T / T) (FP32) for a graph's tree."""
+    import torch
+    plan = kdss.Plan(tree, T)
+    ws = plan.alloc_workspace(device)
+    plan.upload(ws)
+    r = plan.alloc_loads(device)
+    order = torch.empty(max(graph.n, 1), dtype=torch.int32, device=device)
+    plan.run(ws, T, r, order)
+    def unsigned(w):
+        w = w.to(torch.float64)
+        return torch.where(w < 0, w + 2.0 ** 64, w)
+    if plan.width == 64:
+        rr = unsigned(r[:graph.n])
+    else:   # (lo, hi) word pairs
+        rr = unsigned(r[0:2 * graph.n:2]) + unsigned(r[1:2 * graph.n:2]) * 2.0 ** 64
+    plan.close()
+    return torch.log1p(rr / T).to(torch.float32)
+
+
+def training_set(count, k=6, T=200, base_seed=10000, n_lo=10_000, n_hi=200_000, workers=16, device="cuda",
+                 log=print):
+    """Chung-Lu graphs (n in [n_lo, n_hi], degree 8-40, exponent 2.2-2.8), each with
+    its features and its cold-run label at (k, T)."""
+    import concurrent.futures as cf
+    t0 = time.time()
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        graphs = list(ex.map(_member, [(i, base_seed, n_lo, n_hi) for i in range(count)], chunksize=2))
+    log(f"{count} training graphs generated in {time.time() - t0:.1f} s")
+    out = []
+    t1 = time.time()
+    for g in graphs:
+        tree = kdss.Tree(g, k)
+        dg = DeviceGraph(g, tree, device)
+        dg.target = label(g, tree, T, device)
+        tree.close()
+        out.append(dg)
+    log(f"features and labels in {time.time() - t1:.1f} s")
+    return out
+
+
+def _member(args):
+    i, base, lo, hi = args
+    return synth.batch_member(i, base_seed=base, n_lo=lo, n_hi=hi)
+
+
+def train(model, data, epochs=3, lr=1e-3, seed=0, log=print):
+    import torch
+    rs = synth.Stream(seed, 78)
+    hist = []
+    for ep in range(epochs):
+        order = rs.shuffle_order(len(data))
+        tot = 0.0
+        for i in order:
+            dg = data[int(i)]
+            model.zero_grad()
+            pred, acts = model.forward(dg)
+            loss = model.backward(dg, pred, acts, dg.target)
+            model.adam(lr)
+            tot += float(loss.item())
+        hist.append(tot / len(data))
+        log(f"epoch {ep + 1}: mean loss {hist[-1]:.4f}")
+    return hist

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "kdss.h")).read()
+    text = "".join(open(os.path.join(ROOT, "include", h)).read() for h in ("kdss.h", "kdss_gnn.h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(kdss_[a-z0-9_]+)\s*\(", text)))
 
@@ -32,6 +32,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(kdss.EXPORTS) | (set(names) - set(kdss.EXPORTS))
     for name in kdss.EXPORTS:
         assert name in names
+    assert sum(1 for x in names if x.startswith("kdss_gnn_")) >= 12
 
 
 def test_status_strings():
