@@ -19,7 +19,7 @@
  * Conventions as in kdss.h: device pointers are caller-owned, work is
  * enqueued on `stream` (a hipStream_t), status codes are kdss.h's.  Row-major
  * BF16 buffers are uint16_t; leading dimensions count elements and must be
- * multiples of 4; buffers must be 8-byte aligned.
+ * multiples of 4 (even for the aggregation); buffers must be 8-byte aligned.
  */
 #ifndef KDSS_GNN_H
 #define KDSS_GNN_H
@@ -30,16 +30,20 @@
 extern "C" {
 #endif
 
-/* Device workspace (bytes) that kdss_gnn_features needs for graph g. */
-int kdss_gnn_features_workspace(const kdss_csr *g, size_t *bytes);
+/* Device workspace (bytes) that kdss_gnn_features needs for a graph of n nodes
+ * and nnz directed edges (row_ptr[n]). */
+int kdss_gnn_features_workspace(uint32_t n, uint64_t nnz, size_t *bytes);
 
 /* x0 (device, n x 32 BF16) = [log1p(degree), log1p(core number),
- * log1p(triangles through the node), 0, ...].  Core numbers come from the tree's
- * degeneracy order; triangles are counted on the GPU over the DAG that orients
- * every edge along that order.  g (host) must be the tree's graph; d_row_ptr is
- * its row_ptr on the device.  Synchronises the stream. */
-int kdss_gnn_features(const kdss_sct *s, const kdss_csr *g, const uint64_t *d_row_ptr, uint16_t *d_x0,
-                      void *d_ws, size_t ws_bytes, void *stream);
+ * log1p(triangles through the node), 0, ...] for the tree's graph, n = the
+ * tree's node count.  d_row_ptr (u64[n + 1]) and d_col (u32[nnz]) are that
+ * graph's CSR on the device; edges past nnz and ids >= n are ignored.  Core
+ * numbers and the degeneracy order come from the tree's host build and are
+ * copied up; on the device the edges are oriented along that order (a DAG
+ * with out-degree <= degeneracy), the DAG's row offsets are scanned, and the
+ * triangles are counted by intersecting out-neighbour lists.  Enqueued only. */
+int kdss_gnn_features(const kdss_sct *s, const uint64_t *d_row_ptr, const uint32_t *d_col, uint64_t nnz,
+                      uint16_t *d_x0, void *d_ws, size_t ws_bytes, void *stream);
 
 /* out[u] = mean over neighbours v of h[v] (F = 32 or 64 columns; 0 for isolated nodes). */
 int kdss_gnn_aggregate(uint32_t n, const uint64_t *d_row_ptr, const uint32_t *d_col, const uint16_t *d_h,

@@ -49,10 +49,134 @@ uint32_t blocks_for(size_t n, uint32_t per, uint32_t cap = 65535) {
 // Features
 // ---------------------------------------------------------------------------
 
-// Triangles through every node on the DAG that orients each edge from the
-// earlier to the later node of the degeneracy order (out-degree <= degeneracy):
-// a wavefront per node u; for every out-neighbour v of u and every
-// out-neighbour w of v, w in N+(u) closes the triangle {u, v, w}, found once.
+// The DAG that orients each edge from the earlier to the later node of the
+// degeneracy order (out-degree <= degeneracy) is built on the device in three
+// steps: out-degree per node, a scan into row offsets, and a fill that keeps
+// each row's ascending id order.  One wavefront per node in the first and the
+// last step.
+__global__ __launch_bounds__(256) void orient_count_kernel(uint32_t n, uint64_t nnz,
+                                                           const uint64_t* __restrict__ row_ptr,
+                                                           const uint32_t* __restrict__ col,
+                                                           const uint32_t* __restrict__ rank,
+                                                           uint64_t* __restrict__ out_deg) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const uint32_t nw = gridDim.x * 4u;
+  for (uint32_t u = wave; u < n; u += nw) {
+    const uint32_t ru = rank[u];
+    uint32_t c = 0;
+    const uint64_t e_end = min(row_ptr[u + 1], nnz);
+    for (uint64_t e = row_ptr[u] + lane; e < e_end; e += 64) {
+      const uint32_t v = col[e];
+      c += (v < n && rank[v] > ru) ? 1u : 0u;
+    }
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
+    if (lane == 0) out_deg[u] = c;
+  }
+}
+
+constexpr uint32_t kScanItems = 8, kScanChunk = 256 * kScanItems;
+
+// Inclusive scan of a[0..count) in chunks of 2048 (one workgroup each); the
+// chunk totals go to part[].
+__global__ __launch_bounds__(256) void scan_chunks_kernel(uint64_t* __restrict__ a, uint32_t count,
+                                                          uint64_t* __restrict__ part) {
+  __shared__ uint64_t wsum[4];
+  const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanItems;
+  uint64_t v[kScanItems];
+  uint64_t run = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < count ? a[base + i] : 0;
+    run += v[i];
+    v[i] = run;
+  }
+  // exclusive prefix of the thread totals across the workgroup
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  uint64_t x = run;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint64_t off = x - run;
+  for (uint32_t j = 0; j < w; ++j) off += wsum[j];
+#pragma unroll
+  for (uint32_t i = 0; i < kScanItems; ++i)
+    if (base + i < count) a[base + i] = v[i] + off;
+  if (threadIdx.x == 255) part[blockIdx.x] = off + run;
+}
+
+// Exclusive scan of the chunk totals (one workgroup, any count), then the
+// offsets are added to every chunk.
+__global__ __launch_bounds__(256) void scan_parts_kernel(uint64_t* __restrict__ part, uint32_t count) {
+  __shared__ uint64_t wsum[4];
+  __shared__ uint64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  for (uint32_t b = 0; b < count; b += 256) {
+    const uint32_t i = b + threadIdx.x;
+    const uint64_t own = i < count ? part[i] : 0;
+    uint64_t x = own;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t y = __shfl_up(x, d);
+      if (lane >= (uint32_t)d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint64_t off = carry + x - own;
+    for (uint32_t j = 0; j < w; ++j) off += wsum[j];
+    const uint64_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    if (i < count) part[i] = off;
+    if (threadIdx.x == 0) carry += total;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void scan_add_kernel(uint64_t* __restrict__ a, uint32_t count,
+                                                       const uint64_t* __restrict__ part) {
+  const uint32_t i = blockIdx.x * kScanChunk + threadIdx.x;
+  const uint64_t off = part[blockIdx.x];
+#pragma unroll
+  for (uint32_t j = 0; j < kScanItems; ++j)
+    if (i + j * 256u < count) a[i + j * 256u] += off;
+}
+
+__global__ __launch_bounds__(256) void orient_fill_kernel(uint32_t n, uint64_t nnz,
+                                                          const uint64_t* __restrict__ row_ptr,
+                                                          const uint32_t* __restrict__ col,
+                                                          const uint32_t* __restrict__ rank,
+                                                          const uint64_t* __restrict__ orp,
+                                                          uint32_t* __restrict__ ocol) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const uint32_t nw = gridDim.x * 4u;
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (uint32_t u = wave; u < n; u += nw) {
+    const uint32_t ru = rank[u];
+    uint64_t pos = orp[u];
+    const uint64_t e_end = min(row_ptr[u + 1], nnz);
+    for (uint64_t e0 = row_ptr[u]; e0 < e_end; e0 += 64) {
+      const uint64_t e = e0 + lane;
+      uint32_t v = 0;
+      bool keep = false;
+      if (e < e_end) {
+        v = col[e];
+        keep = v < n && rank[v] > ru;
+      }
+      const uint64_t m = __ballot(keep);
+      if (keep) ocol[pos + (uint64_t)__popcll(m & below)] = v;
+      pos += (uint64_t)__popcll(m);
+    }
+  }
+}
+
+// Triangles through every node on that DAG: a wavefront per node u; for every
+// out-neighbour v of u and every out-neighbour w of v, w in N+(u) closes the
+// triangle {u, v, w}, found once.
 __global__ __launch_bounds__(256) void triangle_kernel(uint32_t n, const uint64_t* __restrict__ orp,
                                                        const uint32_t* __restrict__ ocol,
                                                        uint32_t* __restrict__ tri) {
@@ -103,49 +227,86 @@ __global__ __launch_bounds__(256) void features_kernel(uint32_t n, const uint64_
 // Mean aggregation over neighbours and its transpose
 // ---------------------------------------------------------------------------
 
-// out[u][f] = mean over v in N(u) of h[v][f]; F = 32 or 64; one wavefront per
-// node (F = 32: two nodes per wavefront), FP32 accumulation.
+// One wavefront per node.  A row of F BF16 values is read as F / 2 words by a
+// group of F / 2 lanes; the G = 128 / F groups of a wavefront take every G-th
+// neighbour, four loads in flight per lane, and are summed across groups at
+// the end.  Neighbour ids (and, for the transpose, 1 / deg) are loaded 64 at a
+// time, one per lane, and broadcast with shuffles.
+template <uint32_t F, bool kTranspose>
+__device__ __forceinline__ void aggregate_row(uint32_t u, uint32_t lane, const uint64_t* __restrict__ row_ptr,
+                                              const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
+                                              uint32_t ld_words, float& s0, float& s1) {
+  constexpr uint32_t LPR = F / 2, G = 64 / LPR;
+  const uint32_t g = lane / LPR, q = lane % LPR;
+  const uint64_t b = row_ptr[u], e = row_ptr[u + 1];
+  for (uint64_t c0 = b; c0 < e; c0 += 64) {
+    const uint32_t cnt = (uint32_t)min<uint64_t>(64, e - c0);
+    uint32_t my = 0;
+    float myw = 1.f;
+    if (lane < cnt) {
+      my = col[c0 + lane];
+      if (kTranspose) myw = 1.f / (float)(row_ptr[my + 1] - row_ptr[my]);
+    }
+    for (uint32_t j0 = 0; j0 < cnt; j0 += 4 * G) {
+      uint32_t w[4];
+      float sc[4];
+#pragma unroll
+      for (uint32_t t = 0; t < 4; ++t) {
+        const uint32_t j = j0 + t * G + g;
+        const uint32_t v = __shfl(my, (int)(j & 63u));
+        sc[t] = kTranspose ? __shfl(myw, (int)(j & 63u)) : 1.f;
+        w[t] = j < cnt ? src[(size_t)v * ld_words + q] : 0u;
+      }
+#pragma unroll
+      for (uint32_t t = 0; t < 4; ++t) {
+        s0 += bf2f((uint16_t)(w[t] & 0xFFFFu)) * sc[t];
+        s1 += bf2f((uint16_t)(w[t] >> 16)) * sc[t];
+      }
+    }
+  }
+  for (uint32_t d = LPR; d < 64; d <<= 1) {
+    s0 += __shfl_xor(s0, (int)d);
+    s1 += __shfl_xor(s1, (int)d);
+  }
+}
+
+template <uint32_t F>
 __global__ __launch_bounds__(256) void aggregate_kernel(uint32_t n, const uint64_t* __restrict__ row_ptr,
                                                         const uint32_t* __restrict__ col,
-                                                        const uint16_t* __restrict__ h, uint32_t F,
-                                                        uint16_t* __restrict__ out) {
+                                                        const uint32_t* __restrict__ h, uint32_t* __restrict__ out) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t per = 64u / F;                  // nodes per wavefront
-  const uint32_t sub = lane / F, f = lane % F;
   const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
   const uint32_t nw = gridDim.x * 4u;
-  for (uint32_t u0 = wave * per; u0 < n; u0 += nw * per) {
-    const uint32_t u = u0 + sub;
-    if (u >= n) continue;
-    const uint64_t b = row_ptr[u], e = row_ptr[u + 1];
-    float s = 0.f;
-    for (uint64_t x = b; x < e; ++x) s += bf2f(h[(size_t)col[x] * F + f]);
-    out[(size_t)u * F + f] = f2bf(e > b ? s / (float)(e - b) : 0.f);
+  for (uint32_t u = wave; u < n; u += nw) {
+    float s0 = 0.f, s1 = 0.f;
+    aggregate_row<F, false>(u, lane, row_ptr, col, h, F / 2, s0, s1);
+    const uint64_t deg = row_ptr[u + 1] - row_ptr[u];
+    const float inv = deg ? 1.f / (float)deg : 0.f;
+    if (lane < F / 2)
+      out[(size_t)u * (F / 2) + lane] = (uint32_t)f2bf(s0 * inv) | ((uint32_t)f2bf(s1 * inv) << 16);
   }
 }
 
 // out[v][f] = dself[v][f] + sum over u in N(v) of dagg[u][f] / deg(u)
 // (the transpose of the mean aggregation; the graph is symmetric).
+template <uint32_t F>
 __global__ __launch_bounds__(256) void aggregate_backward_kernel(uint32_t n, const uint64_t* __restrict__ row_ptr,
                                                                  const uint32_t* __restrict__ col,
-                                                                 const uint16_t* __restrict__ dagg,
-                                                                 const uint16_t* __restrict__ dself, uint32_t F,
-                                                                 uint32_t ld_self, uint16_t* __restrict__ out) {
+                                                                 const uint32_t* __restrict__ dagg,
+                                                                 const uint32_t* __restrict__ dself,
+                                                                 uint32_t ld_words, uint32_t* __restrict__ out) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t per = 64u / F;
-  const uint32_t sub = lane / F, f = lane % F;
   const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
   const uint32_t nw = gridDim.x * 4u;
-  for (uint32_t v0 = wave * per; v0 < n; v0 += nw * per) {
-    const uint32_t v = v0 + sub;
-    if (v >= n) continue;
-    float s = bf2f(dself[(size_t)v * ld_self + f]);
-    for (uint64_t x = row_ptr[v]; x < row_ptr[v + 1]; ++x) {
-      const uint32_t u = col[x];
-      const float du = (float)(row_ptr[u + 1] - row_ptr[u]);
-      s += bf2f(dagg[(size_t)u * ld_self + f]) / du;
+  for (uint32_t v = wave; v < n; v += nw) {
+    float s0 = 0.f, s1 = 0.f;
+    aggregate_row<F, true>(v, lane, row_ptr, col, dagg, ld_words, s0, s1);
+    if (lane < F / 2) {
+      const uint32_t d = dself[(size_t)v * ld_words + lane];
+      s0 += bf2f((uint16_t)(d & 0xFFFFu));
+      s1 += bf2f((uint16_t)(d >> 16));
+      out[(size_t)v * (F / 2) + lane] = (uint32_t)f2bf(s0) | ((uint32_t)f2bf(s1) << 16);
     }
-    out[(size_t)v * F + f] = f2bf(s);
   }
 }
 
@@ -374,51 +535,46 @@ extern "C" {
 
 static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
-int kdss_gnn_features_workspace(const kdss_csr* g, size_t* bytes) {
-  if (!g || !bytes) return fail(KDSS_EINVAL, "null argument");
-  const size_t n = g->n;
-  *bytes = al256((n + 1) * 8) + al256(std::max<size_t>(1, g->nnz / 2) * 4) + 2 * al256(n * 4);
+int kdss_gnn_features_workspace(uint32_t n, uint64_t nnz, size_t* bytes) {
+  if (!bytes) return fail(KDSS_EINVAL, "null argument");
+  const size_t parts = ((size_t)n + kScanChunk - 1) / kScanChunk;
+  *bytes = 3 * al256((size_t)n * 4) + al256(((size_t)n + 1) * 8) + al256(std::max<size_t>(1, parts) * 8) +
+           al256(std::max<uint64_t>(1, nnz) * 4);
   return KDSS_OK;
 }
 
-int kdss_gnn_features(const kdss_sct* s, const kdss_csr* g, const uint64_t* d_row_ptr, uint16_t* d_x0,
-                      void* d_ws, size_t ws_bytes, void* stream) {
-  if (!s || !g || !g->row_ptr || !d_row_ptr || !d_x0 || !d_ws) return fail(KDSS_EINVAL, "null argument");
-  if (g->n != s->s.n) return fail(KDSS_ERANGE, "graph does not match the tree");
-  const uint32_t n = g->n;
-  const Degeneracy& dg = s->s.deg;
-  // host: the DAG from earlier to later node in the degeneracy order, rows sorted by id
-  std::vector<uint64_t> orp(n + 1, 0);
-  for (uint32_t v = 0; v < n; ++v)
-    for (uint64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e)
-      if (dg.rank[g->col[e]] > dg.rank[v]) orp[v + 1]++;
-  for (uint32_t v = 0; v < n; ++v) orp[v + 1] += orp[v];
-  std::vector<uint32_t> ocol(std::max<uint64_t>(1, orp[n]));
-  {
-    std::vector<uint64_t> fp(orp.begin(), orp.end() - 1);
-    for (uint32_t v = 0; v < n; ++v)
-      for (uint64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e)
-        if (dg.rank[g->col[e]] > dg.rank[v]) ocol[fp[v]++] = g->col[e];   // ascending ids kept
-  }
-  auto al = [](size_t x) { return al256(x); };
+int kdss_gnn_features(const kdss_sct* s, const uint64_t* d_row_ptr, const uint32_t* d_col, uint64_t nnz,
+                      uint16_t* d_x0, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!s || !d_row_ptr || !d_x0 || !d_ws || (nnz && !d_col)) return fail(KDSS_EINVAL, "null argument");
+  const uint32_t n = s->s.n;
   size_t need = 0;
-  kdss_gnn_features_workspace(g, &need);
-  if (ws_bytes < need || ocol.size() > std::max<size_t>(1, g->nnz / 2))
-    return fail(KDSS_EWORKSPACE, "features workspace too small");
+  kdss_gnn_features_workspace(n, nnz, &need);
+  if (ws_bytes < need) return fail(KDSS_EWORKSPACE, "features workspace too small");
+  if (n == 0) return KDSS_OK;
+  const Degeneracy& dg = s->s.deg;
+  const uint32_t parts = (uint32_t)(((size_t)n + kScanChunk - 1) / kScanChunk);
   char* p = static_cast<char*>(d_ws);
-  uint64_t* d_orp = reinterpret_cast<uint64_t*>(p);
-  uint32_t* d_ocol = reinterpret_cast<uint32_t*>(p + al((n + 1) * 8));
-  uint32_t* d_core = reinterpret_cast<uint32_t*>(p + al((n + 1) * 8) + al(ocol.size() * 4));
-  uint32_t* d_tri = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_core) + al((size_t)n * 4));
+  uint32_t* d_rank = reinterpret_cast<uint32_t*>(p);
+  uint32_t* d_core = reinterpret_cast<uint32_t*>(p + al256((size_t)n * 4));
+  uint32_t* d_tri = reinterpret_cast<uint32_t*>(p + 2 * al256((size_t)n * 4));
+  uint64_t* d_orp = reinterpret_cast<uint64_t*>(p + 3 * al256((size_t)n * 4));
+  uint64_t* d_part = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(d_orp) + al256(((size_t)n + 1) * 8));
+  uint32_t* d_ocol = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d_part) + al256((size_t)parts * 8));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIP_TRY(hipMemcpyAsync(d_orp, orp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st), "upload dag");
-  HIP_TRY(hipMemcpyAsync(d_ocol, ocol.data(), ocol.size() * 4, hipMemcpyHostToDevice, st), "upload dag");
+  // the tree's host arrays outlive the copies
+  HIP_TRY(hipMemcpyAsync(d_rank, dg.rank.data(), (size_t)n * 4, hipMemcpyHostToDevice, st), "upload order");
   HIP_TRY(hipMemcpyAsync(d_core, dg.core.data(), (size_t)n * 4, hipMemcpyHostToDevice, st), "upload cores");
   HIP_TRY(hipMemsetAsync(d_tri, 0, (size_t)n * 4, st), "clear triangles");
-  triangle_kernel<<<blocks_for(n, 4, 16384), 256, 0, st>>>(n, d_orp, d_ocol, d_tri);
+  HIP_TRY(hipMemsetAsync(d_orp, 0, 8, st), "clear offsets");
+  const uint32_t wave_grid = blocks_for(n, 4, 16384);
+  orient_count_kernel<<<wave_grid, 256, 0, st>>>(n, nnz, d_row_ptr, d_col, d_rank, d_orp + 1);
+  scan_chunks_kernel<<<parts, 256, 0, st>>>(d_orp + 1, n, d_part);
+  scan_parts_kernel<<<1, 256, 0, st>>>(d_part, parts);
+  scan_add_kernel<<<parts, 256, 0, st>>>(d_orp + 1, n, d_part);
+  orient_fill_kernel<<<wave_grid, 256, 0, st>>>(n, nnz, d_row_ptr, d_col, d_rank, d_orp, d_ocol);
+  triangle_kernel<<<wave_grid, 256, 0, st>>>(n, d_orp, d_ocol, d_tri);
   features_kernel<<<blocks_for((size_t)n * 32, 256, 16384), 256, 0, st>>>(n, d_row_ptr, d_core, d_tri, d_x0);
   HIP_TRY(hipGetLastError(), "features launch");
-  HIP_TRY(hipStreamSynchronize(st), "features synchronize");   // host DAG buffers go out of scope
   return KDSS_OK;
 }
 
@@ -426,8 +582,12 @@ int kdss_gnn_aggregate(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_
                        uint32_t F, uint16_t* d_out, void* stream) {
   if (!d_row_ptr || (!d_col && n) || !d_h || !d_out) return fail(KDSS_EINVAL, "null argument");
   if (F != 32 && F != 64) return fail(KDSS_EINVAL, "F must be 32 or 64");
-  aggregate_kernel<<<blocks_for(n, 4 * (64 / F), 16384), 256, 0, static_cast<hipStream_t>(stream)>>>(
-      n, d_row_ptr, d_col, d_h, F, d_out);
+  if (n == 0) return KDSS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t* h = reinterpret_cast<const uint32_t*>(d_h);
+  uint32_t* out = reinterpret_cast<uint32_t*>(d_out);
+  if (F == 32) aggregate_kernel<32><<<blocks_for(n, 4, 16384), 256, 0, st>>>(n, d_row_ptr, d_col, h, out);
+  else aggregate_kernel<64><<<blocks_for(n, 4, 16384), 256, 0, st>>>(n, d_row_ptr, d_col, h, out);
   HIP_TRY(hipGetLastError(), "aggregate launch");
   return KDSS_OK;
 }
@@ -435,9 +595,16 @@ int kdss_gnn_aggregate(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_
 int kdss_gnn_aggregate_backward(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint16_t* d_dagg,
                                 const uint16_t* d_dself, uint32_t F, uint32_t ld, uint16_t* d_out, void* stream) {
   if (!d_row_ptr || (!d_col && n) || !d_dagg || !d_dself || !d_out) return fail(KDSS_EINVAL, "null argument");
-  if ((F != 32 && F != 64) || ld < F) return fail(KDSS_EINVAL, "F must be 32 or 64 and ld >= F");
-  aggregate_backward_kernel<<<blocks_for(n, 4 * (64 / F), 16384), 256, 0, static_cast<hipStream_t>(stream)>>>(
-      n, d_row_ptr, d_col, d_dagg, d_dself, F, ld, d_out);
+  if ((F != 32 && F != 64) || ld < F || ld % 2) return fail(KDSS_EINVAL, "F must be 32 or 64; ld >= F and even");
+  if (n == 0) return KDSS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t* da = reinterpret_cast<const uint32_t*>(d_dagg);
+  const uint32_t* ds = reinterpret_cast<const uint32_t*>(d_dself);
+  uint32_t* out = reinterpret_cast<uint32_t*>(d_out);
+  if (F == 32)
+    aggregate_backward_kernel<32><<<blocks_for(n, 4, 16384), 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out);
+  else
+    aggregate_backward_kernel<64><<<blocks_for(n, 4, 16384), 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out);
   HIP_TRY(hipGetLastError(), "aggregate backward launch");
   return KDSS_OK;
 }

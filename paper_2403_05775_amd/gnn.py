@@ -31,8 +31,8 @@ def _lib():
     L = kdss.lib()
     if not _bound:
         vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
-        L.kdss_gnn_features_workspace.argtypes = [C.POINTER(kdss.Csr), C.POINTER(C.c_size_t)]
-        L.kdss_gnn_features.argtypes = [vp, C.POINTER(kdss.Csr), vp, vp, vp, C.c_size_t, vp]
+        L.kdss_gnn_features_workspace.argtypes = [u32, u64, C.POINTER(C.c_size_t)]
+        L.kdss_gnn_features.argtypes = [vp, vp, vp, u64, vp, vp, C.c_size_t, vp]
         L.kdss_gnn_aggregate.argtypes = [u32, vp, vp, vp, u32, vp, vp]
         L.kdss_gnn_aggregate_backward.argtypes = [u32, vp, vp, vp, vp, u32, u32, vp, vp]
         L.kdss_gnn_linear.argtypes = [u32, vp, u32, u32, vp, u32, u32, vp, vp, C.c_int, vp, u32, vp]
@@ -71,23 +71,23 @@ class DeviceGraph:
         self.col = torch.from_numpy(col.view(np.int32)).to(device)
         own = tree is None
         tree = tree or kdss.Tree(graph, 3)
-        self.x0 = features(graph, tree, self.row_ptr)
+        self.nnz = int(graph.row_ptr[graph.n])
+        self.x0 = features(tree, self.row_ptr, self.col, self.nnz)
         if own:
             tree.close()
         self.target = None
 
 
-def features(graph, tree, d_row_ptr):
+def features(tree, d_row_ptr, d_col, nnz):
     """x0 (n x 32 BF16 as int16) = log1p of degree, core number, triangle count."""
     import torch
-    c, keep = kdss._csr(graph)
     nbytes = C.c_size_t(0)
-    _ck(_lib().kdss_gnn_features_workspace(C.byref(c), C.byref(nbytes)), "kdss_gnn_features_workspace")
+    _ck(_lib().kdss_gnn_features_workspace(tree.n, nnz, C.byref(nbytes)), "kdss_gnn_features_workspace")
     ws = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=d_row_ptr.device)
-    x0 = torch.empty((graph.n, F0), dtype=torch.int16, device=d_row_ptr.device)
-    _ck(_lib().kdss_gnn_features(tree._h, C.byref(c), _p(d_row_ptr), _p(x0), _p(ws), ws.numel(), _s()),
+    x0 = torch.empty((max(tree.n, 1), F0), dtype=torch.int16, device=d_row_ptr.device)
+    _ck(_lib().kdss_gnn_features(tree._h, _p(d_row_ptr), _p(d_col), nnz, _p(x0), _p(ws), ws.numel(), _s()),
         "kdss_gnn_features")
-    return x0
+    return x0[: tree.n]
 
 
 def bf16_to_float(t):

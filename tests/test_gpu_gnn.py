@@ -125,12 +125,16 @@ def test_aggregate_and_transpose(G):
         assert np.all(np.abs(gotb - refb) <= 2 ** -8 * np.abs(refb) + 1e-4)
 
 
-def test_features_triangles(G, oracle_mod):
-    """Column 2 is log1p of the triangles through each node (triangles listed by the oracle)."""
+@pytest.mark.parametrize("size", ["small", "many-chunks"])
+def test_features_triangles(G, oracle_mod, size):
+    """Column 2 is log1p of the triangles through each node (triangles listed by the
+    oracle).  The larger graph has more than 256 scan chunks of 2048 offsets and
+    rows longer than one wavefront."""
     from paper_2403_05775_amd import kdss
-    g = small_graph()
+    g = small_graph() if size == "small" else synth.chung_lu(600_000, 1_500_000, 2.5, seed=22)
     tree = kdss.Tree(g, 3)
-    x0 = G.features(g, tree, torch.from_numpy(g.row_ptr.astype(np.int64)).cuda())
+    x0 = G.features(tree, torch.from_numpy(g.row_ptr.astype(np.int64)).cuda(),
+                    torch.from_numpy(g.col.view(np.int32)).cuda(), int(g.row_ptr[-1]))
     torch.cuda.synchronize()
     tri = np.zeros(g.n, dtype=np.int64)
     for c in oracle_mod.list_cliques(g.n, g.row_ptr, g.col, 3):
