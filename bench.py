@@ -35,6 +35,11 @@ WORKLOADS = {
     # 512 Chung-Lu graphs (n in [1k, 50k], average degree 8-40, exponent 2.2-2.8,
     # seeds 1000 + g), each at k = 3, 4, 6, 8: 2048 problems in one plan
     "batch-512": dict(kind="batch", graphs=512, ks=(3, 4, 6, 8), T=64),
+    # warm start vs cold start on an unseen Chung-Lu graph, n = 2M, m = 40M,
+    # exponent 2.5, seed 90000; k = 6; the reference density is the best over a
+    # 4T cold run with an extraction after every iteration
+    "gnn-warm-2m": dict(kind="gnn", n=2_000_000, m=40_000_000, beta=2.5, seed=90000, k=6, T=200, t0=50,
+                        gap=0.01),
 }
 
 
@@ -101,6 +106,173 @@ def batch_bench(w, args):
                      "ms_per_iter": tune.best_ms,
                      "tried": [[tune.leaf_blocks[i], tune.heavy_blocks[i], tune.ms[i]] for i in range(tune.tried)]},
         "densest_sizes_first8": [x.size for x in res[:8]],
+    }
+    print(json.dumps(out))
+
+
+def _within(K, i, K_ref, i_ref, gap):
+    """K / i >= (1 - gap) K_ref / i_ref, exactly (gap given in hundredths)."""
+    h = round(gap * 100)
+    return 100 * K * i_ref >= (100 - h) * K_ref * i
+
+
+def gnn_bench(w, args):
+    """Time to a 1% density gap from the model's warm start vs from zero loads.
+
+    Untimed: the graph, its tree, a 4T cold reference run (extraction after
+    every iteration) that fixes rho_ref and the cold iteration count t_c, and a
+    warm trace that fixes t_w (t_w = 0 when the start loads alone are within the
+    gap).  Timed, each on inputs resident in HBM: cold = t_c iterations plus the
+    extraction; warm = features + model + r0 + t_w iterations plus the
+    extraction.  The tree build is excluded from both."""
+    import numpy as np
+    import torch
+    from paper_2403_05775_amd import gnn, kdss, synth
+    k, T, t0, gap = w["k"], w["T"], w["t0"], w["gap"]
+    t_start = time.time()
+    g = synth.chung_lu(w["n"], w["m"], w["beta"], seed=w["seed"])
+    log(f"graph {g.name}: n={g.n} m={g.m} ({time.time() - t_start:.1f} s)")
+    tree = kdss.Tree(g, k)
+    ts = tree.stats()
+    log(f"tree k={k}: leaves={ts.leaves} members={ts.members} c_k={ts.c_k.value} build={ts.build_seconds:.1f} s")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rp = torch.from_numpy(g.row_ptr.astype(np.int64)).to(dev)
+    col = torch.from_numpy(g.col.view(np.int32)).to(dev)
+    nnz = int(g.row_ptr[-1])
+    n = g.n
+    model = gnn.Model(device=dev)
+    trained = os.path.exists(gnn.WEIGHTS_FILE) and not args.gnn_untrained
+    meta = {}
+    if trained:
+        with np.load(gnn.WEIGHTS_FILE) as z:
+            model.load(z)
+            meta = {x: z[x].item() for x in z.files if x.startswith("meta_")}
+    log(f"model: {'trained ' + str(meta) if trained else 'untrained (random init)'}")
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def free(plan):
+        plan.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+    # reference: 4T cold iterations, extraction after each
+    Tref = 4 * T
+    pref = kdss.Plan(tree, Tref, extract_every=1)
+    ws = pref.alloc_workspace(dev)
+    pref.upload(ws)
+    r = pref.alloc_loads(dev)
+    _, trace = pref.run(ws, Tref, r, order, trace_cap=Tref + 1)
+    best = trace[0]
+    for row in trace:
+        if row["dens_num"] * best["size"] > best["dens_num"] * row["size"]:
+            best = row
+    K_ref, i_ref = best["dens_num"], best["size"]
+    t_cold = next(row["t"] for row in trace if _within(row["dens_num"], row["size"], K_ref, i_ref, gap))
+    r_ref = kdss.loads_to_numpy(r, n, pref.width)
+    r_ref = np.asarray(r_ref, dtype=np.float64)
+    ideal = np.rint(t0 * r_ref / Tref).astype(np.uint64)
+    log(f"cold reference: rho_ref={K_ref}/{i_ref}={K_ref / max(i_ref, 1):.2f} (best at t={best['t']}), "
+        f"t_cold={t_cold}")
+    del ws, r
+    free(pref)
+
+    # warm traces: the model's start and the start taken from the reference loads
+    dg = gnn.DeviceGraph.resident(n, rp, col, nnz)
+    dg.x0 = gnn.features(tree, rp, col, nnz)
+    r0, rmax = model.warm_start(dg, t0)
+    r0_ideal = torch.from_numpy(ideal.view(np.int64)).to(dev)
+    pw = kdss.Plan(tree, Tref, r0_max=max(rmax, int(ideal.max())), extract_every=1)
+    assert pw.width == 64
+    ws = pw.alloc_workspace(dev)
+    pw.upload(ws)
+    r = pw.alloc_loads(dev)
+
+    def first_within(start):
+        res0 = pw.extract(ws, start, order, 1, r0=start)
+        curve = [(0, res0.dens_num.value, res0.size)]
+        if _within(res0.dens_num.value, res0.size, K_ref, i_ref, gap):
+            return 0, curve
+        _, tr = pw.run(ws, Tref, r, order, r0=start, trace_cap=Tref + 1)
+        curve += [(row["t"], row["dens_num"], row["size"]) for row in tr]
+        for t, K, i in curve:
+            if _within(K, i, K_ref, i_ref, gap):
+                return t, curve
+        return None, curve
+
+    t_warm, curve_w = first_within(r0)
+    t_ideal, _ = first_within(r0_ideal)
+    log(f"warm: t_warm={t_warm} (start density {curve_w[0][1]}/{curve_w[0][2]}), "
+        f"reference-loads start: t={t_ideal}")
+    del ws, r, r0_ideal
+    free(pw)
+
+    # timed runs (no per-iteration extraction)
+    t_run = max(1, t_cold, t_warm or 1)
+    pt = kdss.Plan(tree, t_run, r0_max=rmax)
+    ws = pt.alloc_workspace(dev)
+    pt.upload(ws)
+    r = pt.alloc_loads(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    parts = {"features": 0.0, "model": 0.0, "frank_wolfe_and_extraction": 0.0}
+
+    def cold_once():
+        res, _ = pt.run(ws, t_cold, r, order)
+        return res
+
+    def warm_once(split=False):
+        ev[0].record()
+        dg.x0 = gnn.features(tree, rp, col, nnz)
+        ev[1].record()
+        r0w, _ = model.warm_start(dg, t0, sync=False)
+        ev[2].record()
+        if t_warm == 0:
+            res = pt.extract(ws, r0w, order, 1, r0=r0w)
+        else:
+            res, _ = pt.run(ws, t_warm, r, order, r0=r0w)
+        ev[3].record()
+        if split:
+            torch.cuda.synchronize()
+            parts["features"] += ev[0].elapsed_time(ev[1])
+            parts["model"] += ev[1].elapsed_time(ev[2])
+            parts["frank_wolfe_and_extraction"] += ev[2].elapsed_time(ev[3])
+        return res
+
+    def timed(fn, **kw):
+        for _ in range(args.warmup):
+            fn(**kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            res = fn(**kw)
+        torch.cuda.synchronize()
+        return 1000.0 * (time.perf_counter() - t1) / args.steps, res
+
+    cold_ms, res_c = timed(cold_once)
+    warm_ms = None
+    res_w = None
+    if t_warm is not None:
+        warm_ms, res_w = timed(warm_once)
+        for _ in range(max(1, args.steps)):
+            warm_once(split=True)
+        for key in parts:
+            parts[key] /= max(1, args.steps)
+    log(f"cold {cold_ms:.2f} ms ({t_cold} iterations), warm {warm_ms} ms ({t_warm} iterations)")
+    out = {
+        "metric": "time to 1% density gap, GNN-warm vs cold PSCTL",
+        "value": warm_ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": warm_ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64 loads; bf16 model with fp32 accumulation", "data": "synthetic",
+        "config": {"workload": f"gnn-warm-2m: {g.name}, k={k}, gap {gap:.0%}", "n": n, "m": g.m, "k": k,
+                   "leaves": ts.leaves, "members": ts.members, "c_k": ts.c_k.value, "t0": t0,
+                   "reference_iterations": Tref, "parallelism": "single GPU"},
+        "cold_ms": cold_ms, "speedup": (cold_ms / warm_ms) if warm_ms else None,
+        "t_cold": t_cold, "t_warm": t_warm, "t_start_from_reference_loads": t_ideal,
+        "rho_ref": [K_ref, i_ref], "rho_cold": [res_c.dens_num.value, res_c.size],
+        "rho_warm": [res_w.dens_num.value, res_w.size] if res_w is not None else None,
+        "warm_breakdown_ms": parts if warm_ms else None,
+        "model": {"trained": trained, **meta},
+        "sct_build_s": ts.build_seconds,
     }
     print(json.dumps(out))
 
@@ -230,6 +402,7 @@ def main():
     ap.add_argument("--command", default="", help="command line recorded in a summary")
     ap.add_argument("--out", default="")
     ap.add_argument("--batch-graphs", type=int, default=0, help="graphs in the batch workload (default 512)")
+    ap.add_argument("--gnn-untrained", action="store_true", help="warm start from a randomly initialised model")
     args = ap.parse_args()
     if args.summarize_counters:
         res = summarize_counters(args.workload, *args.summarize_counters, args.command)
@@ -246,11 +419,14 @@ def main():
     if args.mode == "counters":
         counters_mode(WORKLOADS[args.workload])
         return
-    if WORKLOADS[args.workload]["kind"] == "batch":
+    if WORKLOADS[args.workload]["kind"] in ("batch", "gnn"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
             sys.exit(2)
-        batch_bench(WORKLOADS[args.workload], args)
+        if WORKLOADS[args.workload]["kind"] == "batch":
+            batch_bench(WORKLOADS[args.workload], args)
+        else:
+            gnn_bench(WORKLOADS[args.workload], args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))

@@ -8,8 +8,8 @@
  * Frank-Wolfe then runs unchanged (kdss_run with d_r0), so the results stay
  * exact; only the number of iterations to a good density changes.
  *
- * Model: x0 = features (n x 32 BF16, columns 3..31 zero);
- *   h1 = ReLU([x0 | mean_N(x0)] W1 + b1)      (K = 64)
+ * Model: x0 = features (n x 8 BF16, columns 3..7 zero);
+ *   h1 = ReLU([x0 | mean_N(x0)] W1 + b1)      (K = 16)
  *   h2 = ReLU([h1 | mean_N(h1)] W2 + b2)      (K = 128)
  *   h3 = ReLU([h2 | mean_N(h2)] W3 + b3)      (K = 128)
  *   y  = h3 w + b                             (FP32)
@@ -34,7 +34,7 @@ extern "C" {
  * and nnz directed edges (row_ptr[n]). */
 int kdss_gnn_features_workspace(uint32_t n, uint64_t nnz, size_t *bytes);
 
-/* x0 (device, n x 32 BF16) = [log1p(degree), log1p(core number),
+/* x0 (device, n x 8 BF16) = [log1p(degree), log1p(core number),
  * log1p(triangles through the node), 0, ...] for the tree's graph, n = the
  * tree's node count.  d_row_ptr (u64[n + 1]) and d_col (u32[nnz]) are that
  * graph's CSR on the device; edges past nnz and ids >= n are ignored.  Core
@@ -45,7 +45,7 @@ int kdss_gnn_features_workspace(uint32_t n, uint64_t nnz, size_t *bytes);
 int kdss_gnn_features(const kdss_sct *s, const uint64_t *d_row_ptr, const uint32_t *d_col, uint64_t nnz,
                       uint16_t *d_x0, void *d_ws, size_t ws_bytes, void *stream);
 
-/* out[u] = mean over neighbours v of h[v] (F = 32 or 64 columns; 0 for isolated nodes). */
+/* out[u] = mean over neighbours v of h[v] (F = 8, 16, 32 or 64 columns; 0 for isolated nodes). */
 int kdss_gnn_aggregate(uint32_t n, const uint64_t *d_row_ptr, const uint32_t *d_col, const uint16_t *d_h,
                        uint32_t F, uint16_t *d_out, void *stream);
 
@@ -63,7 +63,8 @@ int kdss_gnn_linear(uint32_t M, const uint16_t *d_a1, uint32_t K1, uint32_t lda1
                     uint16_t *d_y, uint32_t ldy, void *stream);
 
 /* dW[(K1 + K2) x 64] += [A1 | A2]^T dY and db[64] += column sums of dY (FP32,
- * accumulated; db nullable); K1 + K2 = 64 or 128; dY is M x 64 BF16. */
+ * accumulated; db nullable); K1, K2 multiples of 8 with K1 + K2 a multiple of 16
+ * and at most 128; dY is M x 64 BF16. */
 int kdss_gnn_linear_wgrad(uint32_t M, const uint16_t *d_a1, uint32_t K1, uint32_t lda1, const uint16_t *d_a2,
                           uint32_t K2, uint32_t lda2, const uint16_t *d_dy, float *d_dw, float *d_db,
                           void *stream);

@@ -1,8 +1,11 @@
 // Host side of the C-ABI: status strings, clique-tree handles and the planner
 // that lays a tree out for the GPU.
 #include <algorithm>
+#include <array>
+#include <cstdlib>
 #include <cstring>
 #include <new>
+#include <thread>
 
 #include "kdss_internal.h"
 
@@ -13,6 +16,32 @@ thread_local std::string g_last_error;
 int fail(int status, const std::string& msg) {
   g_last_error = msg;
   return status;
+}
+
+unsigned host_threads() {
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v > 0) return (unsigned)std::min<long>(v, 256);
+  }
+  return std::max(1u, std::min(256u, std::thread::hardware_concurrency()));
+}
+
+void parallel_ranges(uint64_t count, uint64_t min_per_thread,
+                     const std::function<void(unsigned, uint64_t, uint64_t)>& f) {
+  const unsigned nt = (unsigned)std::max<uint64_t>(
+      1, std::min<uint64_t>(host_threads(), count / std::max<uint64_t>(1, min_per_thread)));
+  if (nt == 1) {
+    f(0, 0, count);
+    return;
+  }
+  const uint64_t chunk = (count + nt - 1) / nt;
+  std::vector<std::thread> pool;
+  for (unsigned t = 0; t < nt; ++t)
+    pool.emplace_back([&f, t, chunk, count]() {
+      const uint64_t b = std::min<uint64_t>(count, (uint64_t)t * chunk), e = std::min<uint64_t>(count, b + chunk);
+      f(t, b, e);
+    });
+  for (auto& th : pool) th.join();
 }
 
 namespace {
@@ -232,12 +261,21 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
     P->key_mode = (P->width == 64 && bound_max < packed_limit) ? 0 : 1;
     P->bound_max = bound_max;
 
-    // ---- hot nodes: those occurring in the most leaves ----
+    // ---- hot nodes: those occurring in the most leaves (per-thread counts) ----
     std::vector<uint32_t> hot_index(n_total, ~0u);
     {
       std::vector<uint64_t> occ(n_total, 0);
-      for (size_t q = 0; q < trees.size(); ++q)
-        for (uint32_t u : trees[q]->members) occ[P->node_off[q] + u]++;
+      for (size_t q = 0; q < trees.size(); ++q) {
+        const std::vector<uint32_t>& mem = trees[q]->members;
+        const uint32_t tn = trees[q]->n;
+        const unsigned nt = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(host_threads(), mem.size() >> 20));
+        std::vector<std::vector<uint32_t>> local(nt, std::vector<uint32_t>(tn, 0));
+        parallel_ranges(mem.size(), (mem.size() + nt - 1) / nt, [&](unsigned t, uint64_t b, uint64_t e) {
+          for (uint64_t x = b; x < e; ++x) local[t][mem[x]]++;
+        });
+        for (const auto& lc : local)
+          for (uint32_t u = 0; u < lc.size(); ++u) occ[P->node_off[q] + u] += lc[u];
+      }
       std::vector<uint32_t> cand;
       for (uint64_t u = 0; u < n_total; ++u)
         if (occ[u] >= kHotMinOccurrences) cand.push_back((uint32_t)u);
@@ -258,42 +296,88 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
     };
 
     // ---- tiles: big leaves first (longest work first), then lane tiles from
-    // the largest group to the smallest; a tile holds leaves of one problem ----
-    struct LeafRef { uint32_t q; uint64_t id; };
-    std::vector<LeafRef> big;
-    std::vector<std::vector<LeafRef>> groups(kNumLaneGroups);
+    // the largest group to the smallest; a tile holds leaves of one problem.
+    // Within a group, leaves keep the tree's (depth-first) order. ----
+    // a leaf reference packs (problem << 40 | leaf index)
+    auto ref_q = [](uint64_t r) { return (uint32_t)(r >> 40); };
+    auto ref_id = [](uint64_t r) { return r & ((1ull << 40) - 1); };
+    constexpr int kGroups = kNumLaneGroups + 1;   // the last one holds big leaves
+    std::vector<std::vector<uint64_t, NoInitAlloc<uint64_t>>> groups(kGroups);
     uint64_t L = 0, M = 0;
     for (uint32_t q = 0; q < trees.size(); ++q) {
       const Sct& t = *trees[q];
+      if (t.leaves() >= (1ull << 40)) {
+        delete P;
+        return fail(KDSS_ERANGE, "more than 2^40 leaves in one tree");
+      }
       L += t.leaves();
       M += t.members.size();
-      for (uint64_t i = 0; i < t.leaves(); ++i) {
+      // count per thread range, then scatter in order
+      const unsigned nt = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(host_threads(), t.leaves() >> 18));
+      const uint64_t chunk = (t.leaves() + nt - 1) / nt;
+      std::vector<std::array<uint64_t, kGroups>> cnt(nt);
+      std::vector<std::array<uint64_t, kNumClasses>> cl(nt), cm(nt);
+      auto group_of = [&](uint64_t i) {
         const uint32_t s = t.h[i] + t.p[i];
-        const int b = size_bucket(s);
-        P->class_leaves[b]++;
-        P->class_members[b] += s;
-        if (s > 64) big.push_back({q, i});
-        else groups[lane_group(s)].push_back({q, i});
+        return s > 64 ? kNumLaneGroups : lane_group(s);
+      };
+      parallel_ranges(t.leaves(), chunk, [&](unsigned th, uint64_t b, uint64_t e) {
+        for (uint64_t i = b; i < e; ++i) {
+          const uint32_t s = t.h[i] + t.p[i];
+          cnt[th][group_of(i)]++;
+          cl[th][size_bucket(s)]++;
+          cm[th][size_bucket(s)] += s;
+        }
+      });
+      std::vector<std::array<uint64_t, kGroups>> pos(nt);
+      for (int gi = 0; gi < kGroups; ++gi) {
+        uint64_t at = groups[gi].size();
+        for (unsigned th = 0; th < nt; ++th) {
+          pos[th][gi] = at;
+          at += cnt[th][gi];
+        }
+        groups[gi].resize(at);
       }
+      for (unsigned th = 0; th < nt; ++th)
+        for (int c = 0; c < kNumClasses; ++c) {
+          P->class_leaves[c] += cl[th][c];
+          P->class_members[c] += cm[th][c];
+        }
+      parallel_ranges(t.leaves(), chunk, [&](unsigned th, uint64_t b, uint64_t e) {
+        auto at = pos[th];
+        for (uint64_t i = b; i < e; ++i) {
+          const int gi = group_of(i);
+          groups[gi][at[gi]++] = ((uint64_t)q << 40) | i;
+        }
+      });
     }
-    P->members.reserve(M + M / 8);
-    P->hdr.reserve(L);
-    auto header = [&](const LeafRef& r) {
-      const Sct& t = *trees[r.q];
-      return pack_leaf(t.h[r.id], t.k - t.h[r.id], t.p[r.id]);
+    auto leaf_size = [&](uint64_t r) {
+      const Sct& t = *trees[ref_q(r)];
+      return (uint32_t)(t.h[ref_id(r)] + t.p[ref_id(r)]);
     };
-    for (const LeafRef& r : big) {
-      const Sct& t = *trees[r.q];
-      Tile tl{};
-      tl.mbase = P->members.size();
-      tl.lbase = (uint32_t)P->hdr.size();
-      tl.info = pack_tile_info(kTileBig, 1, 0);
-      tl.nbase = (uint32_t)P->node_off[r.q];
-      P->hdr.push_back(header(r));
-      for (uint64_t x = t.off[r.id]; x < t.off[r.id + 1]; ++x)
-        P->members.push_back(encode(P->node_off[r.q] + t.members[x]));
-      P->tiles.push_back(tl);
-      P->class_tiles[kBigClass]++;
+    auto header = [&](uint64_t r) {
+      const Sct& t = *trees[ref_q(r)];
+      return pack_leaf(t.h[ref_id(r)], t.k - t.h[ref_id(r)], t.p[ref_id(r)]);
+    };
+    // tile shapes (sequential, cheap), then the member fill (parallel over tiles)
+    struct TileJob { int gi; uint64_t i0; };
+    std::vector<TileJob> jobs;
+    uint64_t mtotal = 0;
+    P->hdr.reserve(L);
+    {
+      const auto& refs = groups[kNumLaneGroups];
+      for (uint64_t i = 0; i < refs.size(); ++i) {
+        Tile tl{};
+        tl.mbase = mtotal;
+        tl.lbase = (uint32_t)P->hdr.size();
+        tl.info = pack_tile_info(kTileBig, 1, 0);
+        tl.nbase = (uint32_t)P->node_off[ref_q(refs[i])];
+        P->hdr.push_back(header(refs[i]));
+        mtotal += leaf_size(refs[i]);
+        jobs.push_back({kNumLaneGroups, i});
+        P->tiles.push_back(tl);
+        P->class_tiles[kBigClass]++;
+      }
     }
     for (int gi = kNumLaneGroups - 1; gi >= 0; --gi) {
       const auto& refs = groups[gi];
@@ -301,32 +385,56 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
       while (i0 < refs.size()) {
         // up to 64 leaves of the same problem
         uint32_t nl = 0, smax = 0;
-        while (nl < 64 && i0 + nl < refs.size() && refs[i0 + nl].q == refs[i0].q) {
-          const Sct& t = *trees[refs[i0 + nl].q];
-          smax = std::max<uint32_t>(smax, t.h[refs[i0 + nl].id] + t.p[refs[i0 + nl].id]);
+        while (nl < 64 && i0 + nl < refs.size() && ref_q(refs[i0 + nl]) == ref_q(refs[i0])) {
+          smax = std::max<uint32_t>(smax, leaf_size(refs[i0 + nl]));
+          P->hdr.push_back(header(refs[i0 + nl]));
           ++nl;
         }
         Tile tl{};
-        tl.mbase = P->members.size();
-        tl.lbase = (uint32_t)P->hdr.size();
+        tl.mbase = mtotal;
+        tl.lbase = (uint32_t)(P->hdr.size() - nl);
         tl.info = pack_tile_info(kTileLane, nl, smax);
-        tl.nbase = (uint32_t)P->node_off[refs[i0].q];
-        // column-major: member x of leaf r at mbase + 64 x + r; padding reads node 0
-        P->members.resize(P->members.size() + (size_t)64 * smax, 0u);
-        uint32_t* col = P->members.data() + tl.mbase;
-        for (uint32_t r = 0; r < nl; ++r) {
-          const LeafRef& ref = refs[i0 + r];
-          const Sct& t = *trees[ref.q];
-          P->hdr.push_back(header(ref));
-          const uint32_t s = t.h[ref.id] + t.p[ref.id];
-          for (uint32_t x = 0; x < s; ++x)
-            col[(size_t)64 * x + r] = encode(P->node_off[ref.q] + t.members[t.off[ref.id] + x]);
-        }
+        tl.nbase = (uint32_t)P->node_off[ref_q(refs[i0])];
+        mtotal += (uint64_t)64 * smax;
+        jobs.push_back({gi, i0});
         P->tiles.push_back(tl);
         P->class_tiles[size_bucket(smax)]++;
         i0 += nl;
       }
     }
+    // every word of the stream is written below, padding included (node 0)
+    P->members.resize(mtotal);
+    parallel_ranges(jobs.size(), 256, [&](unsigned, uint64_t b, uint64_t e) {
+      for (uint64_t j = b; j < e; ++j) {
+        const Tile& tl = P->tiles[j];
+        uint32_t* dst = P->members.data() + tl.mbase;
+        const auto& refs = groups[jobs[j].gi];
+        if ((tl.info & 7u) == kTileBig) {
+          const uint64_t r = refs[jobs[j].i0];
+          const Sct& t = *trees[ref_q(r)];
+          const uint64_t nb = P->node_off[ref_q(r)];
+          for (uint64_t x = t.off[ref_id(r)]; x < t.off[ref_id(r) + 1]; ++x) *dst++ = encode(nb + t.members[x]);
+          continue;
+        }
+        // column-major: member x of leaf r at mbase + 64 x + r
+        const uint32_t nl = (tl.info >> 3) & 0x1FFFu, smax = tl.info >> 16;
+        uint64_t moff[64];
+        uint32_t msz[64];
+        const Sct& t = *trees[ref_q(refs[jobs[j].i0])];
+        const uint64_t nb = P->node_off[ref_q(refs[jobs[j].i0])];
+        for (uint32_t r = 0; r < 64; ++r) {
+          msz[r] = 0;
+          if (r < nl) {
+            const uint64_t id = ref_id(refs[jobs[j].i0 + r]);
+            moff[r] = t.off[id];
+            msz[r] = t.h[id] + t.p[id];
+          }
+        }
+        for (uint32_t x = 0; x < smax; ++x)
+          for (uint32_t r = 0; r < 64; ++r)
+            dst[(size_t)64 * x + r] = x < msz[r] ? encode(nb + t.members[moff[r] + x]) : 0u;
+      }
+    });
     if (P->tiles.size() >= (1ull << 26)) {
       delete P;
       return fail(KDSS_ERANGE, "more than 2^26 tiles");

@@ -40,6 +40,8 @@ int hip_fail(hipError_t e, const char* what) { return fail(KDSS_EHIP, std::strin
     if (e_ != hipSuccess) return hip_fail(e_, what);   \
   } while (0)
 
+constexpr uint32_t kFeatureCols = 8;
+
 uint32_t blocks_for(size_t n, uint32_t per, uint32_t cap = 65535) {
   size_t b = (n + per - 1) / per;
   return (uint32_t)std::max<size_t>(1, std::min<size_t>(b, cap));
@@ -176,45 +178,112 @@ __global__ __launch_bounds__(256) void orient_fill_kernel(uint32_t n, uint64_t n
 
 // Triangles through every node on that DAG: a wavefront per node u; for every
 // out-neighbour v of u and every out-neighbour w of v, w in N+(u) closes the
-// triangle {u, v, w}, found once.
+// triangle {u, v, w}, found once.  N+(u) goes into an open-addressing hash set
+// in the wavefront's LDS slice (at most half full), so a membership test is
+// one or two LDS reads; rows too long for the slice are binary-searched in
+// global memory.  Four v are walked at a time, one 16-lane group each.
+constexpr uint32_t kTriSlots = 2048;          // hash slots per wavefront
+constexpr uint32_t kTriMaxStaged = kTriSlots / 2;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kGroupLanes = 16;
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t tri_hash(uint32_t x, uint32_t bits) { return (x * 0x9E3779B1u) >> (32u - bits); }
+
 __global__ __launch_bounds__(256) void triangle_kernel(uint32_t n, const uint64_t* __restrict__ orp,
                                                        const uint32_t* __restrict__ ocol,
                                                        uint32_t* __restrict__ tri) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
+  __shared__ uint32_t sH[4][kTriSlots];
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t g = lane / kGroupLanes, q = lane % kGroupLanes;
+  const uint32_t wave = blockIdx.x * 4u + wv;
   const uint32_t nw = gridDim.x * 4u;
+  uint32_t* table = sH[wv];
   for (uint32_t u = wave; u < n; u += nw) {
     const uint64_t ub = orp[u], ue = orp[u + 1];
-    if (ue - ub < 2) continue;
-    for (uint64_t a = ub; a < ue; ++a) {
-      const uint32_t v = ocol[a];
-      const uint64_t vb = orp[v], ve = orp[v + 1];
-      for (uint64_t x = vb + lane; x < ve; x += 64) {
-        const uint32_t w = ocol[x];
-        // binary search w in N+(u) (sorted ascending)
-        uint64_t lo = ub, hi = ue;
-        while (lo < hi) {
-          const uint64_t mid = (lo + hi) >> 1;
-          if (ocol[mid] < w) lo = mid + 1; else hi = mid;
+    const uint32_t d = (uint32_t)(ue - ub);
+    if (d < 2) continue;
+    const uint32_t* nu = ocol + ub;
+    const bool staged = d <= kTriMaxStaged;
+    uint32_t bits = 7;                         // table of 2^bits >= 2 d slots
+    while ((1u << bits) < 2u * d && bits < 11) ++bits;
+    const uint32_t mask = (1u << bits) - 1u;
+    if (staged) {
+      wave_lds_sync();   // earlier reads of the slice are done
+      for (uint32_t i = lane; i <= mask; i += 64) table[i] = kEmpty;
+      wave_lds_sync();
+      for (uint32_t i = lane; i < d; i += 64) {
+        const uint32_t key = nu[i];
+        uint32_t h = tri_hash(key, bits);
+        while (atomicCAS(&table[h], kEmpty, key) != kEmpty) h = (h + 1u) & mask;
+      }
+      wave_lds_sync();
+    }
+    uint32_t found_u = 0;
+    for (uint32_t a0 = 0; a0 < d; a0 += 64) {
+      // 64 out-neighbours v at a time, their row bounds loaded in parallel
+      const uint32_t cnt = min(64u, d - a0);
+      uint32_t my_v = 0;
+      uint64_t my_b = 0, my_e = 0;
+      if (lane < cnt) {
+        my_v = nu[a0 + lane];
+        my_b = orp[my_v];
+        my_e = orp[my_v + 1];
+      }
+      for (uint32_t j0 = 0; j0 < cnt; j0 += 4) {
+        const uint32_t j = j0 + g;
+        const uint32_t v = __shfl(my_v, (int)(j & 63u));
+        const uint64_t vb = __shfl(my_b, (int)(j & 63u)), ve = __shfl(my_e, (int)(j & 63u));
+        uint32_t found = 0;
+        if (j < cnt) {
+          for (uint64_t x = vb + q; x < ve; x += kGroupLanes) {
+            const uint32_t w = ocol[x];
+            bool hit = false;
+            if (staged) {
+              uint32_t h = tri_hash(w, bits);
+              for (;;) {
+                const uint32_t y = table[h];
+                if (y == w) { hit = true; break; }
+                if (y == kEmpty) break;
+                h = (h + 1u) & mask;
+              }
+            } else {
+              uint32_t lo = 0, hi = d;
+              while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (nu[mid] < w) lo = mid + 1; else hi = mid;
+              }
+              hit = lo < d && nu[lo] == w;
+            }
+            if (hit) {
+              ++found;
+              atomicAdd(tri + w, 1u);
+            }
+          }
         }
-        if (lo < ue && ocol[lo] == w) {
-          atomicAdd(tri + u, 1u);
-          atomicAdd(tri + v, 1u);
-          atomicAdd(tri + w, 1u);
-        }
+        for (uint32_t s2 = kGroupLanes / 2; s2 >= 1; s2 >>= 1) found += __shfl_xor(found, (int)s2);
+        if (j < cnt && q == 0 && found) atomicAdd(tri + v, found);
+        found_u += q == 0 ? found : 0u;
       }
     }
+    for (int s2 = 32; s2 >= 1; s2 >>= 1) found_u += __shfl_xor(found_u, s2);
+    if (lane == 0 && found_u) atomicAdd(tri + u, found_u);
   }
 }
 
-// x0[u] = [log1p(degree), log1p(core), log1p(triangles), 0, ..., 0] (32 columns, BF16)
+// x0[u] = [log1p(degree), log1p(core), log1p(triangles), 0, 0, 0, 0, 0] (8 columns, BF16)
 __global__ __launch_bounds__(256) void features_kernel(uint32_t n, const uint64_t* __restrict__ row_ptr,
                                                        const uint32_t* __restrict__ core,
                                                        const uint32_t* __restrict__ tri, uint16_t* __restrict__ x0) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)n * 32u;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)n * kFeatureCols;
        i += (size_t)gridDim.x * blockDim.x) {
-    const size_t u = i >> 5;
-    const uint32_t c = (uint32_t)(i & 31u);
+    const size_t u = i / kFeatureCols;
+    const uint32_t c = (uint32_t)(i % kFeatureCols);
     float v = 0.f;
     if (c == 0) v = log1pf((float)(row_ptr[u + 1] - row_ptr[u]));
     else if (c == 1) v = log1pf((float)core[u]);
@@ -229,7 +298,7 @@ __global__ __launch_bounds__(256) void features_kernel(uint32_t n, const uint64_
 
 // One wavefront per node.  A row of F BF16 values is read as F / 2 words by a
 // group of F / 2 lanes; the G = 128 / F groups of a wavefront take every G-th
-// neighbour, four loads in flight per lane, and are summed across groups at
+// neighbour, up to eight loads in flight per lane, and are summed across groups at
 // the end.  Neighbour ids (and, for the transpose, 1 / deg) are loaded 64 at a
 // time, one per lane, and broadcast with shuffles.
 template <uint32_t F, bool kTranspose>
@@ -237,6 +306,7 @@ __device__ __forceinline__ void aggregate_row(uint32_t u, uint32_t lane, const u
                                               const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
                                               uint32_t ld_words, float& s0, float& s1) {
   constexpr uint32_t LPR = F / 2, G = 64 / LPR;
+  constexpr uint32_t U = G >= 8 ? 64 / G : 8;   // loads in flight per lane
   const uint32_t g = lane / LPR, q = lane % LPR;
   const uint64_t b = row_ptr[u], e = row_ptr[u + 1];
   for (uint64_t c0 = b; c0 < e; c0 += 64) {
@@ -247,18 +317,18 @@ __device__ __forceinline__ void aggregate_row(uint32_t u, uint32_t lane, const u
       my = col[c0 + lane];
       if (kTranspose) myw = 1.f / (float)(row_ptr[my + 1] - row_ptr[my]);
     }
-    for (uint32_t j0 = 0; j0 < cnt; j0 += 4 * G) {
-      uint32_t w[4];
-      float sc[4];
+    for (uint32_t j0 = 0; j0 < cnt; j0 += U * G) {
+      uint32_t w[U];
+      float sc[U];
 #pragma unroll
-      for (uint32_t t = 0; t < 4; ++t) {
+      for (uint32_t t = 0; t < U; ++t) {
         const uint32_t j = j0 + t * G + g;
         const uint32_t v = __shfl(my, (int)(j & 63u));
         sc[t] = kTranspose ? __shfl(myw, (int)(j & 63u)) : 1.f;
         w[t] = j < cnt ? src[(size_t)v * ld_words + q] : 0u;
       }
 #pragma unroll
-      for (uint32_t t = 0; t < 4; ++t) {
+      for (uint32_t t = 0; t < U; ++t) {
         s0 += bf2f((uint16_t)(w[t] & 0xFFFFu)) * sc[t];
         s1 += bf2f((uint16_t)(w[t] >> 16)) * sc[t];
       }
@@ -374,7 +444,7 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(uint32_t M, const uint1
   const uint32_t K = K1 + K2;
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
   const uint32_t li = lane & 31u, rq = (lane >> 5) * 4u;
-  const uint32_t ntile = (K / 32u) * 2u;   // 4 (K = 64) or 8 (K = 128)
+  const uint32_t ntile = ((K + 31u) / 32u) * 2u;   // 32-row tiles, the last one zero-padded
   f32x16 acc[2] = {{}, {}};
   float bsum = 0.f;
   const uint32_t band = (M + gridDim.x - 1) / gridDim.x;
@@ -403,7 +473,7 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(uint32_t M, const uint1
         bf16x4 a, b;
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q) {
-          a[q] = (short)sX[(kk + rq + q) * K + i0 + li];
+          a[q] = i0 + li < K ? (short)sX[(kk + rq + q) * K + i0 + li] : (short)0;
           b[q] = (short)sD[(kk + rq + q) * 64u + j0 + li];
         }
         acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[t], 0, 0, 0);
@@ -418,7 +488,7 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(uint32_t M, const uint1
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const uint32_t i = i0 + 8u * (v / 4) + rq + (v % 4);
-      atomicAdd(dW + (size_t)i * 64u + j0 + li, acc[t][v]);
+      if (i < K) atomicAdd(dW + (size_t)i * 64u + j0 + li, acc[t][v]);
     }
   }
   if (db && threadIdx.x < 64) atomicAdd(db + threadIdx.x, bsum);
@@ -573,7 +643,7 @@ int kdss_gnn_features(const kdss_sct* s, const uint64_t* d_row_ptr, const uint32
   scan_add_kernel<<<parts, 256, 0, st>>>(d_orp + 1, n, d_part);
   orient_fill_kernel<<<wave_grid, 256, 0, st>>>(n, nnz, d_row_ptr, d_col, d_rank, d_orp, d_ocol);
   triangle_kernel<<<wave_grid, 256, 0, st>>>(n, d_orp, d_ocol, d_tri);
-  features_kernel<<<blocks_for((size_t)n * 32, 256, 16384), 256, 0, st>>>(n, d_row_ptr, d_core, d_tri, d_x0);
+  features_kernel<<<blocks_for((size_t)n * kFeatureCols, 256, 16384), 256, 0, st>>>(n, d_row_ptr, d_core, d_tri, d_x0);
   HIP_TRY(hipGetLastError(), "features launch");
   return KDSS_OK;
 }
@@ -581,13 +651,18 @@ int kdss_gnn_features(const kdss_sct* s, const uint64_t* d_row_ptr, const uint32
 int kdss_gnn_aggregate(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint16_t* d_h,
                        uint32_t F, uint16_t* d_out, void* stream) {
   if (!d_row_ptr || (!d_col && n) || !d_h || !d_out) return fail(KDSS_EINVAL, "null argument");
-  if (F != 32 && F != 64) return fail(KDSS_EINVAL, "F must be 32 or 64");
+  if (F != 8 && F != 16 && F != 32 && F != 64) return fail(KDSS_EINVAL, "F must be 8, 16, 32 or 64");
   if (n == 0) return KDSS_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const uint32_t* h = reinterpret_cast<const uint32_t*>(d_h);
   uint32_t* out = reinterpret_cast<uint32_t*>(d_out);
-  if (F == 32) aggregate_kernel<32><<<blocks_for(n, 4, 16384), 256, 0, st>>>(n, d_row_ptr, d_col, h, out);
-  else aggregate_kernel<64><<<blocks_for(n, 4, 16384), 256, 0, st>>>(n, d_row_ptr, d_col, h, out);
+  const uint32_t grid = blocks_for(n, 4, 16384);
+  switch (F) {
+    case 8: aggregate_kernel<8><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, h, out); break;
+    case 16: aggregate_kernel<16><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, h, out); break;
+    case 32: aggregate_kernel<32><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, h, out); break;
+    default: aggregate_kernel<64><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, h, out); break;
+  }
   HIP_TRY(hipGetLastError(), "aggregate launch");
   return KDSS_OK;
 }
@@ -595,16 +670,20 @@ int kdss_gnn_aggregate(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_
 int kdss_gnn_aggregate_backward(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint16_t* d_dagg,
                                 const uint16_t* d_dself, uint32_t F, uint32_t ld, uint16_t* d_out, void* stream) {
   if (!d_row_ptr || (!d_col && n) || !d_dagg || !d_dself || !d_out) return fail(KDSS_EINVAL, "null argument");
-  if ((F != 32 && F != 64) || ld < F || ld % 2) return fail(KDSS_EINVAL, "F must be 32 or 64; ld >= F and even");
+  if ((F != 8 && F != 16 && F != 32 && F != 64) || ld < F || ld % 2)
+    return fail(KDSS_EINVAL, "F must be 8, 16, 32 or 64; ld >= F and even");
   if (n == 0) return KDSS_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const uint32_t* da = reinterpret_cast<const uint32_t*>(d_dagg);
   const uint32_t* ds = reinterpret_cast<const uint32_t*>(d_dself);
   uint32_t* out = reinterpret_cast<uint32_t*>(d_out);
-  if (F == 32)
-    aggregate_backward_kernel<32><<<blocks_for(n, 4, 16384), 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out);
-  else
-    aggregate_backward_kernel<64><<<blocks_for(n, 4, 16384), 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out);
+  const uint32_t grid = blocks_for(n, 4, 16384);
+  switch (F) {
+    case 8: aggregate_backward_kernel<8><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out); break;
+    case 16: aggregate_backward_kernel<16><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out); break;
+    case 32: aggregate_backward_kernel<32><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out); break;
+    default: aggregate_backward_kernel<64><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out); break;
+  }
   HIP_TRY(hipGetLastError(), "aggregate backward launch");
   return KDSS_OK;
 }
@@ -626,7 +705,8 @@ int kdss_gnn_linear_wgrad(uint32_t M, const uint16_t* d_a1, uint32_t K1, uint32_
                           uint32_t K2, uint32_t lda2, const uint16_t* d_dy, float* d_dw, float* d_db, void* stream) {
   if (!d_a1 || !d_dy || !d_dw || (K2 && !d_a2)) return fail(KDSS_EINVAL, "null argument");
   const uint32_t K = K1 + K2;
-  if ((K != 64 && K != 128) || K1 % 8 || K2 % 8) return fail(KDSS_EINVAL, "K1 + K2 must be 64 or 128");
+  if (K == 0 || K > 128 || K % 16 || K1 % 8 || K2 % 8 || lda1 < K1 || (K2 && lda2 < K2))
+    return fail(KDSS_EINVAL, "K1, K2 multiples of 8 with K1 + K2 a multiple of 16, at most 128");
   gemm_wgrad_kernel<<<blocks_for(M, 2048, 256), 256, 0, static_cast<hipStream_t>(stream)>>>(
       M, d_a1, K1, lda1, d_a2, K2, lda2, d_dy, d_dw, d_db);
   HIP_TRY(hipGetLastError(), "weight gradient launch");

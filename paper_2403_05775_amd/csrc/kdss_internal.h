@@ -2,6 +2,9 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
+#include <memory>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -13,6 +16,30 @@ using u128 = unsigned __int128;
 
 // Records a detail message for kdss_last_error() and returns status.
 int fail(int status, const std::string& msg);
+
+// An allocator whose value-less construct() leaves trivial types uninitialised,
+// so that large buffers filled in parallel are not zeroed first on one thread.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind { using other = NoInitAlloc<U>; };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) {}
+  template <class U>
+  void construct(U* p) noexcept { ::new ((void*)p) U; }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) { ::new ((void*)p) U(std::forward<A>(a)...); }
+};
+
+// Host worker threads: OMP_NUM_THREADS when set, else the hardware's count (<= 256).
+unsigned host_threads();
+
+// f(thread, begin, end) over contiguous ranges of [0, count) on up to
+// host_threads() threads, each range at least min_per_thread long; the same
+// arguments always give the same ranges.
+void parallel_ranges(uint64_t count, uint64_t min_per_thread,
+                     const std::function<void(unsigned, uint64_t, uint64_t)>& f);
 
 // ---- graph checks and degeneracy order (host) ----
 int validate_csr(const kdss_csr* g);
@@ -121,7 +148,7 @@ struct kdss_plan {
   uint64_t r0_max = 0;
   kdss::u128 c_k = 0;
   kdss_opts opts{};
-  std::vector<uint32_t> members;      // class-major, tile order
+  std::vector<uint32_t, kdss::NoInitAlloc<uint32_t>> members;   // class-major, tile order
   std::vector<uint32_t> hdr;          // one per leaf
   std::vector<kdss::Tile> tiles;
   std::vector<uint64_t> binom;        // C(a, b), a <= s_max, b <= k, row length k + 1

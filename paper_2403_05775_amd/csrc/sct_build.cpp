@@ -309,7 +309,7 @@ int build_sct(const kdss_csr* g, uint32_t k, uint32_t threads, Sct* out) {
   for (uint32_t a = 0; a <= dmax + 1; ++a)
     for (uint32_t b = 0; b <= k; ++b) binom[(size_t)a * (k + 1) + b] = binom128(a, b);
 
-  unsigned nt = threads ? threads : std::max(1u, std::thread::hardware_concurrency());
+  unsigned nt = threads ? threads : host_threads();
   nt = std::min<unsigned>(nt, 256);
   // roots in degeneracy order, in chunks; each chunk's leaves are kept apart and
   // concatenated in chunk order so the output does not depend on scheduling

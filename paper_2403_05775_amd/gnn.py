@@ -19,7 +19,7 @@ import numpy as np
 from . import kdss, synth
 
 HIDDEN = 64
-F0 = 32          # feature columns (3 used, padded for the matrix cores)
+F0 = 8           # feature columns (3 used, padded to one 8-wide matrix-core step)
 LAYERS = [(F0, F0), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN)]   # (self columns, neighbour columns)
 WEIGHTS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gnn_weights.npz")
 
@@ -77,9 +77,18 @@ class DeviceGraph:
             tree.close()
         self.target = None
 
+    @classmethod
+    def resident(cls, n, row_ptr, col, nnz):
+        """A graph whose CSR is already on the device; x0 is left for the caller."""
+        self = cls.__new__(cls)
+        self.n, self.row_ptr, self.col, self.nnz = n, row_ptr, col, nnz
+        self.x0 = None
+        self.target = None
+        return self
+
 
 def features(tree, d_row_ptr, d_col, nnz):
-    """x0 (n x 32 BF16 as int16) = log1p of degree, core number, triangle count."""
+    """x0 (n x 8 BF16 as int16) = log1p of degree, core number, triangle count, then zeros."""
     import torch
     nbytes = C.c_size_t(0)
     _ck(_lib().kdss_gnn_features_workspace(tree.n, nnz, C.byref(nbytes)), "kdss_gnn_features_workspace")
@@ -204,14 +213,15 @@ class Model:
                 "adam")
         self.pack()
 
-    def warm_start(self, dg, t0, cap=1 << 62):
-        """r0 (device uint64 as int64) and its maximum, from a forward pass."""
+    def warm_start(self, dg, t0, cap=1 << 62, sync=True):
+        """r0 (device uint64 as int64) and its maximum (an int when sync, else the
+        device scalar), from a forward pass."""
         import torch
         pred, _ = self.forward(dg)
         r0 = torch.empty(dg.n, dtype=torch.int64, device=self.device)
         rmax = torch.zeros(1, dtype=torch.int64, device=self.device)
         _ck(_lib().kdss_gnn_warm_start(dg.n, _p(pred), float(t0), cap, _p(r0), _p(rmax), _s()), "warm start")
-        return r0, int(rmax.item())
+        return r0, (int(rmax.item()) if sync else rmax)
 
 
 def label(graph, tree, T, device="cuda"):
@@ -234,25 +244,40 @@ def label(graph, tree, T, device="cuda"):
     return torch.log1p(rr / T).to(torch.float32)
 
 
-def training_set(count, k=6, T=200, base_seed=10000, n_lo=10_000, n_hi=200_000, workers=16, device="cuda",
-                 log=print):
-    """Chung-Lu graphs (n in [n_lo, n_hi], degree 8-40, exponent 2.2-2.8), each with
-    its features and its cold-run label at (k, T)."""
+def generate(count, base_seed=10000, n_lo=10_000, n_hi=200_000, workers=6, first=0, log=print):
+    """Chung-Lu graphs first .. first + count - 1 of the seeded family (n in
+    [n_lo, n_hi], average degree 8-40, exponent 2.2-2.8), made on worker threads
+    (the process that drives the GPU is never forked)."""
     import concurrent.futures as cf
     t0 = time.time()
-    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-        graphs = list(ex.map(_member, [(i, base_seed, n_lo, n_hi) for i in range(count)], chunksize=2))
-    log(f"{count} training graphs generated in {time.time() - t0:.1f} s")
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        graphs = list(ex.map(_member, [(i, base_seed, n_lo, n_hi) for i in range(first, first + count)]))
+    log(f"{count} graphs generated in {time.time() - t0:.0f} s")
+    return graphs
+
+
+def prepare(graphs, k=6, T=200, device="cuda", log=print):
+    """Features and cold-run labels at (k, T) on the device; the host graphs are
+    released as they are consumed."""
     out = []
     t1 = time.time()
-    for g in graphs:
+    for i in range(len(graphs)):
+        g = graphs[i]
+        graphs[i] = None
         tree = kdss.Tree(g, k)
         dg = DeviceGraph(g, tree, device)
         dg.target = label(g, tree, T, device)
         tree.close()
         out.append(dg)
-    log(f"features and labels in {time.time() - t1:.1f} s")
+        if len(out) % 25 == 0 or len(out) == len(graphs):
+            log(f"{len(out)}/{len(graphs)} graphs labelled ({time.time() - t1:.0f} s)")
     return out
+
+
+def training_set(count, k=6, T=200, base_seed=10000, n_lo=10_000, n_hi=200_000, workers=6, device="cuda",
+                 first=0, log=print):
+    """generate() then prepare()."""
+    return prepare(generate(count, base_seed, n_lo, n_hi, workers, first, log), k, T, device, log)
 
 
 def _member(args):
@@ -260,8 +285,20 @@ def _member(args):
     return synth.batch_member(i, base_seed=base, n_lo=lo, n_hi=hi)
 
 
-def train(model, data, epochs=3, lr=1e-3, seed=0, log=print):
-    import torch
+def evaluate(model, data):
+    """Mean loss over graphs (the gradients it accumulates are discarded)."""
+    tot = 0.0
+    for dg in data:
+        model.zero_grad()
+        pred, acts = model.forward(dg)
+        tot += float(model.backward(dg, pred, acts, dg.target).item())
+    model.zero_grad()
+    return tot / max(1, len(data))
+
+
+def train(model, data, epochs=3, lr=1e-3, seed=0, val=None, log=print):
+    """One Adam step per graph (MSE over its nodes), graphs in a seeded shuffled
+    order each epoch.  Returns the mean training loss of each epoch."""
     rs = synth.Stream(seed, 78)
     hist = []
     for ep in range(epochs):
@@ -275,5 +312,46 @@ def train(model, data, epochs=3, lr=1e-3, seed=0, log=print):
             model.adam(lr)
             tot += float(loss.item())
         hist.append(tot / len(data))
-        log(f"epoch {ep + 1}: mean loss {hist[-1]:.4f}")
+        msg = f"epoch {ep + 1}: mean loss {hist[-1]:.4f}"
+        if val:
+            msg += f", held-out {evaluate(model, val):.4f}"
+        log(msg)
     return hist
+
+
+def main(argv=None):
+    """Trains the model on the seeded Chung-Lu family and saves its FP32
+    parameters (with the training settings as meta_* entries)."""
+    import argparse
+    ap = argparse.ArgumentParser(prog="python -m paper_2403_05775_amd.gnn", description=main.__doc__)
+    ap.add_argument("--graphs", type=int, default=2000, help="training graphs (seeds 10000 + i)")
+    ap.add_argument("--held-out", type=int, default=8, help="validation graphs (seeds 20000 + i)")
+    ap.add_argument("--k", type=int, default=6)
+    ap.add_argument("--T", type=int, default=200, help="cold iterations behind each label")
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--workers", type=int, default=6, help="graph generator processes")
+    ap.add_argument("--out", default=WEIGHTS_FILE)
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    t0 = time.time()
+    g_val = generate(args.held_out, base_seed=20000, workers=args.workers, log=log)
+    g_train = generate(args.graphs, workers=args.workers, log=log)
+    val = prepare(g_val, k=args.k, T=args.T, log=log)
+    data = prepare(g_train, k=args.k, T=args.T, log=log)
+    log(f"data ready in {time.time() - t0:.0f} s")
+    model = Model(seed=0)
+    hist = train(model, data, epochs=args.epochs, lr=args.lr, val=val, log=log)
+    state = model.state()
+    state.update(meta_graphs=np.int64(args.graphs), meta_k=np.int64(args.k), meta_T=np.int64(args.T),
+                 meta_epochs=np.int64(args.epochs), meta_train_loss=np.float64(hist[-1]),
+                 meta_held_out_loss=np.float64(evaluate(model, val)))
+    np.savez(args.out, **state)
+    log(f"saved {args.out} ({time.time() - t0:.0f} s)")
+
+
+if __name__ == "__main__":
+    main()

@@ -93,6 +93,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    # torch supplies the device memory and streams; its HIP runtime must be the
+    # one libkdss binds to, so it is loaded first (a second runtime loaded
+    # beside it finds no device)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, p64, p32 = C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)
     L.kdss_status_string.restype = C.c_char_p

@@ -51,7 +51,8 @@ def test_bf16_rounding_ties_to_even(G):
     assert got[1] == 0x3F80 and got[2] == 0x3F82   # 1 + 2^-8 ties down to even, 1 + 3 * 2^-8 up
 
 
-@pytest.mark.parametrize("M,K1,K2,relu", [(1000, 32, 32, 1), (777, 64, 64, 1), (4096, 64, 0, 0), (33, 64, 64, 0)])
+@pytest.mark.parametrize("M,K1,K2,relu", [(1000, 32, 32, 1), (777, 64, 64, 1), (4096, 64, 0, 0), (33, 64, 64, 0),
+                                          (2049, 8, 8, 1)])
 def test_linear_matches_fp32(G, M, K1, K2, relu):
     a1 = rand_bf16(G, (M, K1), 1)
     a2 = rand_bf16(G, (M, max(K2, 8)), 2)[:, :K2].contiguous() if K2 else None
@@ -70,7 +71,7 @@ def test_linear_matches_fp32(G, M, K1, K2, relu):
     assert torch.all((got - ref).abs() <= 2 ** -8 * ref.abs() + 1e-5), (got - ref).abs().max()
 
 
-@pytest.mark.parametrize("M,K1,K2", [(5000, 32, 32), (3333, 64, 64)])
+@pytest.mark.parametrize("M,K1,K2", [(5000, 32, 32), (3333, 64, 64), (4001, 8, 8)])
 def test_weight_gradient(G, M, K1, K2):
     a1 = rand_bf16(G, (M, K1), 4)
     a2 = rand_bf16(G, (M, K2), 5)
@@ -97,7 +98,7 @@ def test_aggregate_and_transpose(G):
     dg_col = torch.from_numpy(g.col.view(np.int32)).cuda()
     n = g.n
     deg = np.diff(g.row_ptr.astype(np.int64))
-    for F in (32, 64):
+    for F in (8, 16, 32, 64):
         h = rand_bf16(G, (n, F), 7)
         out = torch.empty((n, F), dtype=torch.int16, device="cuda")
         G._ck(G._lib().kdss_gnn_aggregate(n, G._p(dg_rp), G._p(dg_col), G._p(h), F, G._p(out), G._s()), "agg")
