@@ -480,6 +480,7 @@ def main():
     leaf_us = 1000.0 * tm.leaf_ms / nl
     heavy_us = 1000.0 * tm.heavy_ms / nl
     reduce_us = 1000.0 * tm.reduce_ms / nl
+    heavy_per_iter = tm.heavy_leaves / nl
     apply_us = 1000.0 * tm.apply_ms / max(1, tm.apply_launches)
     pass_us = leaf_us + heavy_us + reduce_us
     del ws2
@@ -513,6 +514,7 @@ def main():
         "result": {"size": res.size, "dens_num": res.dens_num.value, "ub_num": res.ub_num.value,
                    "density": res.density, "upper_bound": res.upper_bound},
         "kernel_us": {"leaf_credit": leaf_us, "heavy_leaf": heavy_us, "hot_reduce": reduce_us, "apply": apply_us},
+        "heavy_leaves_per_iteration": heavy_per_iter,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "leaf_credit_kernel<KPacked>", "bytes_per_launch": leaf_bytes},

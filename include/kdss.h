@@ -94,6 +94,7 @@ typedef struct {              /* accumulated by kdss_run when time_kernels = 1  
     double reduce_ms;         /* hot-node reduction that completes the pass     */
     uint64_t apply_launches;
     double apply_ms;          /* load update r += credits                       */
+    uint64_t heavy_leaves;    /* leaves queued for the heavy-leaf kernel, summed */
 } kdss_timing;
 
 typedef struct {
@@ -203,7 +204,7 @@ int kdss_extract(kdss_plan *p, void *d_ws, size_t ws_bytes, const void *d_r,
                  const uint64_t *d_r0, uint32_t T, uint32_t *d_order, kdss_result *h_res,
                  void *stream);
 
-/* ---- launch tuning (the benchmark spec's autotuned tile schedules) ----
+/* ---- launch tuning (autotuned tile schedules) ----
  * The leaf-credit and heavy-leaf kernels run persistent grids; their sizes
  * decide how tiles and queued heavy leaves are spread over the 256 CUs. */
 
@@ -215,7 +216,7 @@ typedef struct {
     double ms[16];                /* per iteration, each configuration         */
 } kdss_tune_result;
 
-/* Sets the grid sizes (1..1024 workgroups each) used by later runs. */
+/* Sets the grid sizes (leaf-credit 1..2048, heavy-leaf 1..1024 workgroups) used by later runs. */
 int kdss_plan_set_launch(kdss_plan *p, uint32_t leaf_blocks, uint32_t heavy_blocks);
 
 /* Times `iters` iterations after `warm` untimed ones (from zero loads) for each
@@ -226,7 +227,7 @@ int kdss_plan_autotune(kdss_plan *p, void *d_ws, size_t ws_bytes, uint64_t *d_r,
                        kdss_tune_result *out, void *stream);
 
 /* ---- batches: many problems (graph, k) in one launch per iteration ----
- * (the benchmark spec's batching addition; each problem is exactly the problem of
+ * (each problem is exactly the problem of
  * kdss_run, and its result equals a solo run bit for bit) */
 
 /* Lays out `count` trees (each with its own graph and k) as one plan: problem q

@@ -186,17 +186,18 @@ static void layout_workspace(kdss_plan* P) {
   P->off_bbest = take((size_t)P->scan_blocks * 16);
   P->off_red = take((size_t)P->red_blocks * 16);   // a (lo, hi) pair per block
   P->off_dres = take(sizeof(DevResult));
-  P->leaf_blocks = (uint32_t)std::min<uint64_t>(kLeafBlocksMax, std::max<uint64_t>(1, (P->tiles.size() + 3) / 4));
+  P->leaf_blocks = (uint32_t)std::min<uint64_t>(kLeafBlocksDefault, std::max<uint64_t>(1, (P->tiles.size() + 3) / 4));
   P->heavy_blocks = kHeavyBlocks;
   P->off_hot = take(P->hot.size() * 4);
   P->off_hot_base = take(P->hot.size() * 4);
-  // scratch rows for the largest grids the launch tuner may pick
-  P->off_scratch = take((size_t)(kLeafBlocksMax + kHeavyBlocks) * P->hot.size() * 8);
+  // hot-node credit slot rows (kept zero between passes)
+  P->off_scratch = take((size_t)kHotSlots * P->hot.size() * 8);
   P->lane_leaves = 0;
   for (const Tile& tl : P->tiles)
     if ((tl.info & 7u) == kTileLane) P->lane_leaves += (tl.info >> 3) & 0x1FFFu;
   P->off_queue = take(P->lane_leaves * 4);
   P->off_qcount = take(64);
+  P->off_qlog = take((size_t)P->T_max * 4);
   // batch extraction: prefix sums, per-problem results and node offsets
   P->off_prefix = take(n * 8);
   P->off_pres = take(nprob * sizeof(DevResult));
@@ -373,7 +374,8 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
         tl.info = pack_tile_info(kTileBig, 1, 0);
         tl.nbase = (uint32_t)P->node_off[ref_q(refs[i])];
         P->hdr.push_back(header(refs[i]));
-        mtotal += leaf_size(refs[i]);
+        // whole 16-byte groups, so every lane tile starts 16-byte aligned
+        mtotal += (leaf_size(refs[i]) + kRowGroup - 1) / kRowGroup * kRowGroup;
         jobs.push_back({kNumLaneGroups, i});
         P->tiles.push_back(tl);
         P->class_tiles[kBigClass]++;
@@ -395,7 +397,7 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
         tl.lbase = (uint32_t)(P->hdr.size() - nl);
         tl.info = pack_tile_info(kTileLane, nl, smax);
         tl.nbase = (uint32_t)P->node_off[ref_q(refs[i0])];
-        mtotal += (uint64_t)64 * smax;
+        mtotal += (uint64_t)64 * ((smax + kRowGroup - 1) / kRowGroup * kRowGroup);
         jobs.push_back({gi, i0});
         P->tiles.push_back(tl);
         P->class_tiles[size_bucket(smax)]++;
@@ -414,10 +416,13 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
           const Sct& t = *trees[ref_q(r)];
           const uint64_t nb = P->node_off[ref_q(r)];
           for (uint64_t x = t.off[ref_id(r)]; x < t.off[ref_id(r) + 1]; ++x) *dst++ = encode(nb + t.members[x]);
+          const uint32_t sz = leaf_size(r);
+          for (uint32_t x = sz; x % kRowGroup; ++x) *dst++ = 0u;
           continue;
         }
-        // column-major: member x of leaf r at mbase + 64 x + r
+        // groups of four rows: member x of leaf r at mbase + 256 (x / 4) + 4 r + x % 4
         const uint32_t nl = (tl.info >> 3) & 0x1FFFu, smax = tl.info >> 16;
+        const uint32_t rows = (smax + kRowGroup - 1) / kRowGroup * kRowGroup;
         uint64_t moff[64];
         uint32_t msz[64];
         const Sct& t = *trees[ref_q(refs[jobs[j].i0])];
@@ -430,9 +435,9 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
             msz[r] = t.h[id] + t.p[id];
           }
         }
-        for (uint32_t x = 0; x < smax; ++x)
+        for (uint32_t x = 0; x < rows; ++x)
           for (uint32_t r = 0; r < 64; ++r)
-            dst[(size_t)64 * x + r] = x < msz[r] ? encode(nb + t.members[moff[r] + x]) : 0u;
+            dst[lane_tile_offset(x, r)] = x < msz[r] ? encode(nb + t.members[moff[r] + x]) : 0u;
       }
     });
     if (P->tiles.size() >= (1ull << 26)) {

@@ -132,13 +132,14 @@ __device__ __forceinline__ KT member_key(const KeySrc& src, const KT* hkey, uint
   return (raw & kHotFlag) ? hkey[raw & ~kHotFlag] : KT::load(src, raw);
 }
 
-// Branch-free form for batched loads: both the LDS slot and the global key are
-// read (the hot index is also a valid node id, and the LDS index is masked into
-// the table), then one is selected, so a batch of these issues back to back.
+// Form for batched loads: the LDS slot is always read (its index masked into
+// the table) and the global key only for a valid, non-hot member, so a batch
+// of these issues back to back under per-lane masks.
 template <class KT>
-__device__ __forceinline__ KT member_key_nb(const KeySrc& src, const KT* hkey, uint32_t raw) {
+__device__ __forceinline__ KT member_key_nb(const KeySrc& src, const KT* hkey, uint32_t raw, bool valid = true) {
   const KT a = hkey[raw & (kHotMax - 1)];
-  const KT b = KT::load(src, raw & ~kHotFlag);
+  KT b = KT::mx();
+  if (valid && !(raw & kHotFlag)) b = KT::load(src, raw);
   return (raw & kHotFlag) ? a : b;
 }
 
@@ -182,23 +183,59 @@ __device__ __forceinline__ void combine_add(Sink& sink, uint32_t key, uint64_t v
   if (run_end && v) sink.add(key, v);
 }
 
-// Lane tile: one leaf per lane; member x of the lane's leaf is the row-x word
-// of the column-major tile, so every load below is one contiguous 256-byte row.
+constexpr uint32_t kLaneBatch = 4;   // rows per lane-tile batch (one 16-byte load)
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wavefront's heavy-leaf queue entries, staged in its LDS slice and copied
+// to the global queue with one counter atomic per flush (at the end of the
+// wavefront's tiles, or when the slice is full) instead of one per tile.
+constexpr uint32_t kQueueBuf = 256;
+
+struct WaveQueue {
+  uint32_t* buf;   // the wavefront's kQueueBuf LDS words
+  uint32_t n;      // entries staged (wave-uniform)
+  __device__ __forceinline__ void flush(uint32_t* __restrict__ queue, uint32_t* __restrict__ qcount) {
+    if (n == 0) return;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(qcount, n);
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+    wave_lds_sync();
+    for (uint32_t i = lane; i < n; i += 64) queue[base + i] = buf[i];
+    wave_lds_sync();   // the slice is reused only after every lane has read it
+    n = 0;
+  }
+};
+
+// Device twin of the planner's lane_tile_offset (member x of lane i's leaf).
+__device__ __forceinline__ uint64_t lane_tile_word(uint32_t x, uint32_t i) {
+  return (uint64_t)64 * kRowGroup * (x / kRowGroup) + (uint64_t)kRowGroup * i + x % kRowGroup;
+}
+
+// Lane tile: one leaf per lane; the lane's members x .. x + 3 are one 16-byte
+// word of the tile (groups of four rows), so every batch below is one or two
+// contiguous kilobyte loads per wavefront.
 // A single pass over the rows finds the hold minimum m (hold members come first
 // in every leaf) and counts the pivot members below m.  Lanes that have such
-// "low" members rank them: up to four are kept in registers, more (frequent only
-// while many loads tie, e.g. from all-zero start loads) are ranked by a rescan.
+// "low" members rank them: up to four are kept in registers; leaves with more
+// go to the heavy-leaf queue.  Keys are gathered only for members inside the
+// lane's leaf that are not hot (hot keys come from LDS).
 template <class KT>
 __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, const uint32_t* __restrict__ members,
                                           const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k1,
                                           const KeySrc& src, const KT* hkey, Sink& sink, uint32_t* __restrict__ queue,
-                                          uint32_t* __restrict__ qcount) {
-  constexpr uint32_t U = 8;   // rows loaded per batch
+                                          uint32_t* __restrict__ qcount, WaveQueue& hq) {
+  constexpr uint32_t U = kLaneBatch;   // rows per batch, a multiple of four
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nl = (t.info >> 3) & 0x1FFFu, smax = t.info >> 16;
   const uint32_t hd = lane < nl ? hdr[t.lbase + lane] : 0u;   // a missing leaf reads as empty
   const uint32_t h = hd & 31u, j = (hd >> 5) & 31u, p = hd >> 10, s = h + p;
-  const uint32_t* __restrict__ col = members + t.mbase + lane;
+  const uint32_t* __restrict__ grp = members + t.mbase + kRowGroup * lane;
   KT km = KT::mx();
   uint32_t mraw = 0, nlow = 0;
   // the first four low members, in row order (hold members precede pivot
@@ -209,9 +246,17 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
     uint32_t raw[U];
     KT key[U];
 #pragma unroll
-    for (uint32_t u = 0; u < U; ++u) raw[u] = col[(size_t)min(x0 + u, smax - 1) * 64];
+    for (uint32_t g = 0; g < U / kRowGroup; ++g) {
+      uint4 w4 = {0u, 0u, 0u, 0u};
+      if (g == 0 || x0 + g * kRowGroup < smax)   // groups past the tile's rows are absent
+        w4 = *reinterpret_cast<const uint4*>(grp + (size_t)64 * (x0 + g * kRowGroup));
+      raw[g * 4 + 0] = w4.x;
+      raw[g * 4 + 1] = w4.y;
+      raw[g * 4 + 2] = w4.z;
+      raw[g * 4 + 3] = w4.w;
+    }
 #pragma unroll
-    for (uint32_t u = 0; u < U; ++u) key[u] = member_key_nb<KT>(src, hkey, raw[u]);
+    for (uint32_t u = 0; u < U; ++u) key[u] = member_key_nb<KT>(src, hkey, raw[u], x0 + u < s);
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) {
       const uint32_t x = x0 + u;
@@ -240,14 +285,14 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
     if (nlow > 2) sink.add(r2, row[(size_t)(p - 1 - b2) * k1]);
     if (nlow > 3) sink.add(r3, row[(size_t)(p - 1 - b3) * k1]);
   }
-  // Leaves with more than four low members go to the heavy-leaf queue; the
-  // heavy kernel spreads them over the whole grid.
+  // Leaves with more than four low members go to the heavy-leaf queue (through
+  // the wavefront's LDS buffer); the heavy kernel spreads them over the grid.
   const uint64_t heavy = __ballot(nlow > 4);
   if (heavy) {
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(qcount, (uint32_t)__popcll(heavy));
-    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-    if (nlow > 4) queue[base + (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull))] = (tile_idx << 6) | lane;
+    const uint32_t cnt = (uint32_t)__popcll(heavy);
+    if (hq.n + cnt > kQueueBuf) hq.flush(queue, qcount);
+    if (nlow > 4) hq.buf[hq.n + (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull))] = (tile_idx << 6) | lane;
+    hq.n += cnt;
   }
   const uint64_t cm = h ? binom[(size_t)(p - nlow) * k1 + j] : 0ull;
   combine_add(sink, cm ? mraw : 0xFFFFFFFFu, cm);
@@ -306,9 +351,12 @@ __device__ __forceinline__ void tile_big(const Tile& t, const uint32_t* __restri
 }
 
 // Persistent grid: wave w of the grid takes tiles w, w + 4 * gridDim.x, ...
-// Each workgroup writes its hot-node credit totals to scratch[blockIdx.x][*].
+// Each workgroup adds its nonzero hot-node credit totals into one of
+// kHotSlots scratch rows (row blockIdx.x % kHotSlots).
+// At least seven wavefronts per SIMD (<= 64 VGPRs): the pass is latency-bound,
+// and occupancy hides more of it than wider row batches do.
 template <class KT>
-__global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict__ tiles, uint32_t ntiles,
+__global__ __launch_bounds__(256, 7) void leaf_credit_kernel(const Tile* __restrict__ tiles, uint32_t ntiles,
                                                           const uint32_t* __restrict__ members,
                                                           const uint32_t* __restrict__ hdr,
                                                           const uint64_t* __restrict__ binom, uint32_t nbinom,
@@ -320,6 +368,7 @@ __global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kBinomLds];
+  __shared__ uint32_t qslice[4][kQueueBuf];
   for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
     KeySrc hs = src;
     hs.base = hot_base[i];
@@ -333,54 +382,45 @@ __global__ __launch_bounds__(256) void leaf_credit_kernel(const Tile* __restrict
   const uint64_t* bt = lds_binom ? sbinom : binom;
   Sink sink{hcnt, out, 0u, 0ull};
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  WaveQueue hq{qslice[w], 0u};
   const uint32_t stride = gridDim.x * 4u;
   for (uint32_t tile = blockIdx.x * 4u + w; tile < ntiles; tile += stride) {
     const Tile t = tiles[tile];
     KeySrc ts = src;
     ts.base = t.nbase;
     if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k1, ts, hkey, sink);
-    else tile_lane<KT>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount);
+    else tile_lane<KT>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq);
   }
   sink.flush();
+  hq.flush(queue, qcount);
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) scratch[(size_t)blockIdx.x * nhot + i] = hcnt[i];
+  // hot-node totals into slot row blockIdx % kHotSlots (nonzero ones only)
+  uint64_t* row = scratch + (size_t)(blockIdx.x % kHotSlots) * nhot;
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x)
+    if (hcnt[i]) atomicAdd(reinterpret_cast<unsigned long long*>(row + i), hcnt[i]);
 }
 
 // Heavy leaves (more than four pivot members below the hold minimum), queued
 // by the leaf-credit kernel as (tile << 6 | lane): one leaf per wavefront, one
 // member per lane, four leaves per batch so their loads overlap.  The hold
 // minimum m is recomputed; the rank of a low member among the low members is
-// counted with wavefront ballots.  Hot-node credit totals go to scratch rows
-// row0 + blockIdx.x.
+// counted with wavefront ballots.  No workgroup state: hot members' keys are
+// read through the hot table, and their credits go to the slot rows
+// (row blockIdx.x % kHotSlots) that the hot reduction adds up.
 template <class KT>
 __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ tiles, const uint32_t* __restrict__ members,
                                                     const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ binom,
-                                                    uint32_t nbinom, uint32_t k1, KeySrc src, uint64_t* __restrict__ out,
-                                                    const uint32_t* __restrict__ hot,
-                                                    const uint32_t* __restrict__ hot_base, uint32_t nhot,
-                                                    uint64_t* __restrict__ scratch, uint32_t row0,
+                                                    uint32_t k1, KeySrc src, uint64_t* __restrict__ out,
+                                                    const uint32_t* __restrict__ hot, uint32_t nhot,
+                                                    uint64_t* __restrict__ scratch,
                                                     const uint32_t* __restrict__ queue,
                                                     const uint32_t* __restrict__ qcount) {
-  __shared__ KT hkey[kHotMax];
-  __shared__ unsigned long long hcnt[kHotMax];
-  __shared__ uint64_t sbinom[kBinomLds];
-  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
-    KeySrc hs = src;
-    hs.base = hot_base[i];
-    hkey[i] = KT::load(hs, hot[i]);
-    hcnt[i] = 0;
-  }
-  const bool lds_binom = nbinom <= kBinomLds;
-  if (lds_binom)
-    for (uint32_t i = threadIdx.x; i < nbinom; i += blockDim.x) sbinom[i] = binom[i];
-  __syncthreads();
-  const uint64_t* bt = lds_binom ? sbinom : binom;
-  Sink sink{hcnt, out, 0u, 0ull};
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t total = *qcount;
   constexpr uint32_t B = 4;
   const uint32_t nw = gridDim.x * 4u;
+  uint64_t* row = scratch + (size_t)(blockIdx.x % kHotSlots) * nhot;
   for (uint32_t e0 = (blockIdx.x * 4u + w) * B; e0 < total; e0 += nw * B) {
     uint32_t hq[B], sq[B], jq[B], ra[B], nb[B];
     KT ka[B];
@@ -395,13 +435,14 @@ __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ til
       hq[q] = hd & 31u;
       jq[q] = (hd >> 5) & 31u;
       sq[q] = hq[q] + (hd >> 10);
-      ra[q] = lane < sq[q] ? members[t.mbase + (size_t)lane * 64 + L] : 0u;
+      ra[q] = lane < sq[q] ? members[t.mbase + lane_tile_word(lane, L)] : 0u;
     }
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
       KeySrc ts = src;
       ts.base = nb[q];
-      ka[q] = lane < sq[q] ? member_key_nb<KT>(ts, hkey, ra[q]) : KT::mx();
+      const uint32_t node = (ra[q] & kHotFlag) ? hot[ra[q] & (kHotMax - 1)] : ra[q];
+      ka[q] = lane < sq[q] ? KT::load(ts, node) : KT::mx();
     }
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
@@ -422,27 +463,32 @@ __global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ til
         below += (low && ka[q].rl(tl).lt(ka[q])) ? 1u : 0u;
       }
       if (low && j >= 1) {
-        const uint64_t c = bt[(size_t)(p - 1 - below) * k1 + (j - 1)];
-        if (c) sink.add(ra[q], c);
+        const uint64_t c = binom[(size_t)(p - 1 - below) * k1 + (j - 1)];
+        if (c) {
+          uint64_t* dst = (ra[q] & kHotFlag) ? row + (ra[q] & (kHotMax - 1)) : out + ra[q];
+          atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)c);
+        }
       }
     }
   }
-  sink.flush();
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x)
-    scratch[(size_t)(row0 + blockIdx.x) * nhot + i] = hcnt[i];
 }
 
-// Hot-node totals: out[hot[i]] += sum over workgroups b of scratch[b][i].  A
-// block sums 64 hot nodes over a band of kHotRowsPerBlock rows (4 waves, each
-// a quarter of the band) and adds its partial sums with one atomic per node.
-constexpr uint32_t kHotRowsPerBlock = 16;
+// Hot-node totals: out[hot[i]] += sum over the slot rows b of scratch[b][i],
+// and every slot entry is cleared for the next pass (each is read exactly
+// once).  A block sums 64 hot nodes over a band of kHotRowsPerBlock rows (4
+// waves, each a quarter of the band) and adds its partial sums with one atomic
+// per node.
+constexpr uint32_t kHotRowsPerBlock = 32;
 
-__global__ __launch_bounds__(256) void hot_reduce_kernel(const uint64_t* __restrict__ scratch, uint32_t blocks,
+__global__ __launch_bounds__(256) void hot_reduce_kernel(uint64_t* __restrict__ scratch, uint32_t blocks,
                                                          const uint32_t* __restrict__ hot, uint32_t nhot,
-                                                         uint64_t* __restrict__ out, uint32_t* __restrict__ qcount) {
+                                                         uint64_t* __restrict__ out, uint32_t* __restrict__ qcount,
+                                                         uint32_t* __restrict__ qlog) {
   __shared__ uint64_t part[4][64];
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *qcount = 0;   // heavy queue emptied
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (qlog) *qlog = *qcount;   // timed runs keep the queue size
+    *qcount = 0;                 // heavy queue emptied
+  }
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
   const uint32_t i = blockIdx.x * 64u + lane;
   const uint32_t b0 = blockIdx.y * kHotRowsPerBlock;
@@ -450,7 +496,10 @@ __global__ __launch_bounds__(256) void hot_reduce_kernel(const uint64_t* __restr
   uint64_t s = 0;
   if (i < nhot) {
 #pragma unroll 4
-    for (uint32_t b = b0 + w; b < b1; b += 4) s += scratch[(size_t)b * nhot + i];
+    for (uint32_t b = b0 + w; b < b1; b += 4) {
+      s += scratch[(size_t)b * nhot + i];
+      scratch[(size_t)b * nhot + i] = 0;
+    }
   }
   part[w][lane] = s;
   __syncthreads();
@@ -508,6 +557,79 @@ __global__ __launch_bounds__(256) void apply64_kernel(uint64_t* __restrict__ r, 
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
     r[u] += delta[u];
     delta[u] = 0;
+  }
+}
+
+// The load update fused with the hot-node reduction (64-bit loads): the first
+// ceil(nhot / 4) workgroups give each hot node i a wavefront that sums and
+// clears its kHotSlots slot entries and adds the total to r[hot[i]] with one
+// atomic; the other workgroups apply the credits pairwise, writing only the
+// entries whose credit is nonzero (hot nodes never have one: their credits
+// live in the slot rows), so the two parts never touch the same word.  Also
+// empties the heavy-leaf queue, keeping its size in *qlog for timed runs.
+__global__ __launch_bounds__(256) void apply64_hot_kernel(uint64_t* __restrict__ r, uint64_t* __restrict__ delta,
+                                                          uint32_t n, uint64_t* __restrict__ scratch,
+                                                          const uint32_t* __restrict__ hot, uint32_t nhot,
+                                                          uint32_t hot_blocks, uint32_t* __restrict__ qcount,
+                                                          uint32_t* __restrict__ qlog) {
+  const uint32_t lane = threadIdx.x & 63u;
+  if (blockIdx.x < hot_blocks) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (qlog) *qlog = *qcount;
+      *qcount = 0;
+    }
+    const uint32_t i = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (i >= nhot) return;
+    uint64_t t = 0;
+    for (uint32_t b = lane; b < kHotSlots; b += 64) {
+      t += scratch[(size_t)b * nhot + i];
+      scratch[(size_t)b * nhot + i] = 0;
+    }
+    for (int d = 32; d >= 1; d >>= 1) t += shfl_xor64(t, d);
+    if (lane == 0 && t) atomicAdd(reinterpret_cast<unsigned long long*>(r + hot[i]), (unsigned long long)t);
+    return;
+  }
+  const uint32_t pairs = n / 2;
+  const ulonglong2* d2 = reinterpret_cast<const ulonglong2*>(delta);
+  const uint32_t nb = gridDim.x - hot_blocks, b = blockIdx.x - hot_blocks;
+  for (uint32_t k = b * blockDim.x + threadIdx.x; k < pairs; k += nb * blockDim.x) {
+    const ulonglong2 d = d2[k];
+    if (d.x) {
+      r[2 * k] += d.x;
+      delta[2 * k] = 0;
+    }
+    if (d.y) {
+      r[2 * k + 1] += d.y;
+      delta[2 * k + 1] = 0;
+    }
+  }
+  if ((n & 1u) && b == 0 && threadIdx.x == 0 && delta[n - 1]) {
+    r[n - 1] += delta[n - 1];
+    delta[n - 1] = 0;
+  }
+}
+
+// The same on 16-byte pairs (r and delta 16-byte aligned): the credits are
+// read for every pair, the loads are read and written, and the credits
+// cleared, only where a credit arrived.
+__global__ __launch_bounds__(256) void apply64_pairs_kernel(uint64_t* __restrict__ r, uint64_t* __restrict__ delta,
+                                                            uint32_t n) {
+  const uint32_t pairs = n / 2;
+  ulonglong2* r2 = reinterpret_cast<ulonglong2*>(r);
+  ulonglong2* d2 = reinterpret_cast<ulonglong2*>(delta);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < pairs; i += gridDim.x * blockDim.x) {
+    const ulonglong2 d = d2[i];
+    if (d.x | d.y) {
+      ulonglong2 v = r2[i];
+      v.x += d.x;
+      v.y += d.y;
+      r2[i] = v;
+      d2[i] = make_ulonglong2(0ull, 0ull);
+    }
+  }
+  if ((n & 1u) && blockIdx.x == 0 && threadIdx.x == 0) {
+    r[n - 1] += delta[n - 1];
+    delta[n - 1] = 0;
   }
 }
 
@@ -995,6 +1117,14 @@ uint32_t grid_for(size_t n, uint32_t threads = 256, uint32_t cap = 16384) {
   return (uint32_t)b;
 }
 
+// r_t = r_{t-1} + delta: the pair kernel when the caller's loads are 16-byte aligned.
+void launch_apply64(uint64_t* r, uint64_t* delta, uint32_t n, hipStream_t st) {
+  if ((reinterpret_cast<uintptr_t>(r) & 15u) == 0)
+    apply64_pairs_kernel<<<grid_for(n / 2 + 1), 256, 0, st>>>(r, delta, n);
+  else
+    apply64_kernel<<<grid_for(n), 256, 0, st>>>(r, delta, n);
+}
+
 uint32_t bit_length128(u128 x) {
   uint32_t b = 0;
   while (x) { ++b; x >>= 1; }
@@ -1011,7 +1141,7 @@ struct WsView {
 // ev (nullable): four events recorded before the leaf kernel, after it, after
 // the heavy-leaf kernel and after the hot-node reduction.
 int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& src, uint64_t* out,
-                hipStream_t st, hipEvent_t* ev = nullptr) {
+                hipStream_t st, hipEvent_t* ev = nullptr, uint32_t* qlog = nullptr, bool reduce_hot = true) {
   const uint32_t ntiles = (uint32_t)P->tiles.size();
   if (ntiles == 0) return KDSS_OK;
   const uint32_t blocks = P->leaf_blocks;
@@ -1031,8 +1161,8 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src, out,    \
                                                  hot, hot_base, nhot, scratch, queue, qcount);                   \
   if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event record");                                                    \
-  heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(tiles, members, hdr, binom, nbinom, P->k1, src, out, hot,     \
-                                                    hot_base, nhot, scratch, blocks, queue, qcount)
+  heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(tiles, members, hdr, binom, P->k1, src, out, hot, nhot,     \
+                                                    scratch, queue, qcount)
   switch (mode) {
     case 0: KDSS_LEAF(KPacked); break;
     case 1: KDSS_LEAF(KFull); break;
@@ -1041,12 +1171,14 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   }
 #undef KDSS_LEAF
   HIP_TRY(hipGetLastError(), "leaf credit launch");
-  // hot-node totals over all leaf and heavy workgroups; also empties the queue
-  const uint32_t rows = blocks + P->heavy_blocks;
+  // hot-node totals over the slot rows (cleared again); also empties the queue
+  const uint32_t rows = kHotSlots;
   const dim3 grid(nhot ? (nhot + 63) / 64 : 1, nhot ? (rows + kHotRowsPerBlock - 1) / kHotRowsPerBlock : 1);
   if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event record");
-  hot_reduce_kernel<<<grid, 256, 0, st>>>(scratch, rows, hot, nhot, out, qcount);
-  HIP_TRY(hipGetLastError(), "hot reduce launch");
+  if (reduce_hot) {
+    hot_reduce_kernel<<<grid, 256, 0, st>>>(scratch, rows, hot, nhot, out, qcount, qlog);
+    HIP_TRY(hipGetLastError(), "hot reduce launch");
+  }
   if (ev) HIP_TRY(hipEventRecord(ev[3], st), "event record");
   return KDSS_OK;
 }
@@ -1062,18 +1194,33 @@ KeySrc fw_src(const kdss_plan* P, const WsView& ws, const void* d_r) {
   return s;
 }
 
-// One Frank-Wolfe iteration: credits at r_{t-1} into delta, then r_t = r_{t-1} + delta.
-int launch_iteration(const kdss_plan* P, const WsView& ws, void* d_r, hipStream_t st) {
+// One Frank-Wolfe iteration: credits at r_{t-1} into delta (hot nodes' into the
+// slot rows), then r_t = r_{t-1} + delta.  With 64-bit loads the hot-node
+// reduction is part of the update kernel.
+int launch_fw_step(const kdss_plan* P, const WsView& ws, void* d_r, hipStream_t st, hipEvent_t* ev,
+                   uint32_t* qlog) {
   uint64_t* delta = ws.at<uint64_t>(P->off_delta);
-  int rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st);
+  const bool fused = P->width == 64 && !P->tiles.empty();
+  int rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev, qlog, !fused);
   if (rc) return rc;
   if (P->width == 128) {
     apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
+  } else if (fused) {
+    const uint32_t nhot = (uint32_t)P->hot.size();
+    const uint32_t hot_blocks = std::max(1u, (nhot + 3) / 4);   // block 0 also empties the queue
+    apply64_hot_kernel<<<hot_blocks + grid_for(P->n / 2 + 1), 256, 0, st>>>(
+        static_cast<uint64_t*>(d_r), delta, P->n, ws.at<uint64_t>(P->off_scratch), ws.at<uint32_t>(P->off_hot), nhot,
+        hot_blocks, ws.at<uint32_t>(P->off_qcount), qlog);
   } else {
-    apply64_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
+    launch_apply64(static_cast<uint64_t*>(d_r), delta, P->n, st);
   }
   HIP_TRY(hipGetLastError(), "apply launch");
+  if (ev) HIP_TRY(hipEventRecord(ev[4], st), "event record");
   return KDSS_OK;
+}
+
+int launch_iteration(const kdss_plan* P, const WsView& ws, void* d_r, hipStream_t st) {
+  return launch_fw_step(P, ws, d_r, st, nullptr, nullptr);
 }
 
 // Stable LSD radix sort of kw[0] (and kw[0][1] for 128-bit keys) with the
@@ -1214,10 +1361,18 @@ int ensure_graph(kdss_plan* P, const WsView& ws, void* d_r) {
   return KDSS_OK;
 }
 
+// The hot-node slot rows are zero between passes; entry points clear them
+// again (with a kernel, not a memset) in case an earlier pass was cut short.
+void clear_hot_rows(const kdss_plan* P, const WsView& ws, hipStream_t st) {
+  const size_t count = (size_t)kHotSlots * P->hot.size();
+  if (count) fill_u64_kernel<<<grid_for(count), 256, 0, st>>>(ws.at<uint64_t>(P->off_scratch), 0ull, count);
+}
+
 // Start loads, zero credits and a cleared device result.
 int start_run(kdss_plan* P, const WsView& ws, const uint64_t* d_r0, void* d_r, uint32_t T, hipStream_t st) {
   DevResult* dres = ws.at<DevResult>(P->off_dres);
   reset_result_kernel<<<1, 64, 0, st>>>(dres);
+  clear_hot_rows(P, ws, st);
   init_loads_kernel<<<grid_for(P->n), 256, 0, st>>>(d_r0, static_cast<uint64_t*>(d_r), ws.at<uint64_t>(P->off_delta),
                                                     P->n, P->width == 128 ? 1 : 0, dres);
   HIP_TRY(hipGetLastError(), "init launch");
@@ -1235,17 +1390,7 @@ int start_run(kdss_plan* P, const WsView& ws, const uint64_t* d_r0, void* d_r, u
 int iterate(kdss_plan* P, const WsView& ws, void* d_r, uint32_t t, hipStream_t st) {
   if (P->opts.time_kernels) {
     hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data()) + 5ull * (t - 1);
-    uint64_t* delta = ws.at<uint64_t>(P->off_delta);
-    int rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev);
-    if (rc) return rc;
-    if (P->width == 128) {
-      apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
-    } else {
-      apply64_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
-    }
-    HIP_TRY(hipGetLastError(), "apply launch");
-    HIP_TRY(hipEventRecord(ev[4], st), "event record");
-    return KDSS_OK;
+    return launch_fw_step(P, ws, d_r, st, ev, ws.at<uint32_t>(P->off_qlog) + (t - 1));
   }
   if (P->opts.use_graph) {
     int rc = ensure_graph(P, ws, d_r);
@@ -1257,8 +1402,11 @@ int iterate(kdss_plan* P, const WsView& ws, void* d_r, uint32_t t, hipStream_t s
 }
 
 // After the stream is synchronised: add the timed kernel durations of T iterations.
-int collect_timing(kdss_plan* P, uint32_t T) {
+int collect_timing(kdss_plan* P, const WsView& ws, uint32_t T) {
   if (!P->opts.time_kernels || P->tiles.empty()) return KDSS_OK;
+  std::vector<uint32_t> q(T);
+  HIP_TRY(hipMemcpy(q.data(), ws.at<uint32_t>(P->off_qlog), (size_t)T * 4, hipMemcpyDeviceToHost), "queue log");
+  for (uint32_t v : q) P->timing.heavy_leaves += v;
   hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data());
   for (uint32_t t = 0; t < T; ++t) {
     float a = 0.f, b = 0.f, c = 0.f, d = 0.f;
@@ -1312,8 +1460,12 @@ int kdss_plan_upload(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream) {
   }
   HIP_TRY(hipMemcpyAsync(ws.at<uint64_t>(P->off_nodeoff), P->node_off.data(), P->node_off.size() * 8,
                          hipMemcpyHostToDevice, st), "upload node offsets");
-  // the heavy-leaf queue starts empty; every leaf pass leaves it empty again
+  // the heavy-leaf queue and the hot-node slot rows start empty; every leaf
+  // pass leaves them empty again
   HIP_TRY(hipMemsetAsync(ws.at<uint32_t>(P->off_qcount), 0, 64, st), "queue reset");
+  if (!P->hot.empty())
+    HIP_TRY(hipMemsetAsync(ws.at<uint64_t>(P->off_scratch), 0, (size_t)kHotSlots * P->hot.size() * 8, st),
+            "hot rows reset");
   HIP_TRY(hipStreamSynchronize(st), "upload synchronize");
   P->uploaded_ws = d_ws;
   return KDSS_OK;
@@ -1357,7 +1509,7 @@ int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64
   rc = read_result(P, ws, st, &h);
   if (rc) return rc;
   if (h.r0max > P->r0_max) return fail(KDSS_EOVERFLOW, "a start load exceeds the plan's r0_max");
-  rc = collect_timing(P, T);
+  rc = collect_timing(P, ws, T);
   if (rc) return rc;
   fill_result(P, h, T, h_res);
   if (every && h_trace && rows < trace_cap) {
@@ -1427,7 +1579,7 @@ int kdss_batch_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const 
           "result copy");
   HIP_TRY(hipStreamSynchronize(st), "stream synchronize");
   if (hd.r0max > P->r0_max) return fail(KDSS_EOVERFLOW, "a start load exceeds the plan's r0_max");
-  rc = collect_timing(P, T);
+  rc = collect_timing(P, ws, T);
   if (rc) return rc;
   for (uint32_t q = 0; q < nprob; ++q) {
     kdss_result& o = h_res[q];
@@ -1469,8 +1621,8 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "event create");
   HIP_TRY(hipEventCreate(&e1), "event create");
-  const uint32_t leaf_c[] = {256, 512, 768, 1024};
-  const uint32_t heavy_c[] = {256, 512, 1024};
+  const uint32_t leaf_c[] = {512, 1024, 1536, 2048};
+  const uint32_t heavy_c[] = {128, 256, 512, 1024};
   std::memset(out, 0, sizeof(*out));
   out->best_ms = 1e30;
   for (uint32_t lb : leaf_c) {
@@ -1524,6 +1676,7 @@ int kdss_leaf_credit(kdss_plan* P, void* d_ws, size_t ws_bytes, const void* d_r,
   hipStream_t st = static_cast<hipStream_t>(stream);
   WsView ws{static_cast<char*>(d_ws)};
   fill_u64_kernel<<<grid_for(P->n), 256, 0, st>>>(d_out, 0ull, P->n);
+  clear_hot_rows(P, ws, st);
   int mode = P->width == 128 ? 2 : 1;   // loads given directly: full keys
   KeySrc s{};
   s.r = static_cast<const uint64_t*>(d_r);
@@ -1543,6 +1696,7 @@ int kdss_extract(kdss_plan* P, void* d_ws, size_t ws_bytes, const void* d_r, con
   WsView ws{static_cast<char*>(d_ws)};
   DevResult* dres = ws.at<DevResult>(P->off_dres);
   reset_result_kernel<<<1, 64, 0, st>>>(dres);
+  clear_hot_rows(P, ws, st);
   // the sort needs a bound on the loads: their maximum
   uint64_t* red = ws.at<uint64_t>(P->off_red);
   max_partial_kernel<<<P->red_blocks, 256, 0, st>>>(static_cast<const uint64_t*>(d_r), nullptr, P->n,

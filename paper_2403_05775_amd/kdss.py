@@ -51,7 +51,8 @@ class Opts(C.Structure):
 
 class Timing(C.Structure):
     _fields_ = [("leaf_launches", C.c_uint64), ("leaf_ms", C.c_double), ("heavy_ms", C.c_double),
-                ("reduce_ms", C.c_double), ("apply_launches", C.c_uint64), ("apply_ms", C.c_double)]
+                ("reduce_ms", C.c_double), ("apply_launches", C.c_uint64), ("apply_ms", C.c_double),
+                ("heavy_leaves", C.c_uint64)]
 
 
 class TuneResult(C.Structure):
