@@ -195,7 +195,8 @@ static void layout_workspace(kdss_plan* P) {
   P->lane_leaves = 0;
   for (const Tile& tl : P->tiles)
     if ((tl.info & 7u) == kTileLane) P->lane_leaves += (tl.info >> 3) & 0x1FFFu;
-  P->off_queue = take(P->lane_leaves * 4);
+  P->off_queue = take(P->lane_leaves * 16);   // 16-byte heavy-leaf entries
+  P->off_hotkey = take((size_t)kHotMax * 32);  // hot-node keys of the current pass
   P->off_qcount = take(64);
   P->off_qlog = take((size_t)P->T_max * 4);
   // batch extraction: prefix sums, per-problem results and node offsets

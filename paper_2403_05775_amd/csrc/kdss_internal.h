@@ -173,7 +173,8 @@ struct kdss_plan {
   std::vector<uint32_t> hot;           // original ids of the hot nodes
   std::vector<uint32_t> hot_base;      // first node id of each hot node's problem
   size_t off_hot = 0, off_hot_base = 0, off_scratch = 0, off_dbase = 0, off_queue = 0, off_qcount = 0;
-  size_t off_qlog = 0;                 // heavy-queue sizes of timed iterations (u32[T_max])
+  size_t off_qlog = 0;
+  size_t off_hotkey = 0;               // hot-node keys published by the leaf pass for the heavy pass                 // heavy-queue sizes of timed iterations (u32[T_max])
   uint32_t heavy_blocks = 0;           // grid of the heavy-leaf kernel
   uint32_t k1 = 0;                     // binomial table row length (largest k + 1)
   kdss::u128 bound_max = 0;            // largest r0_max + T_max * c_k over the problems

@@ -37,7 +37,9 @@ __device__ __forceinline__ uint32_t readlane32(uint32_t v, int lane) {
 
 // ----------------------------------------------------------------------------
 // Keys.  A leaf orders its members by (load, node id); the minimum of a clique
-// is the member with the smallest key.  Four encodings:
+// is the member with the smallest key.  Every selection between keys goes
+// through pick() field by field, so multi-word keys stay in registers.  Four
+// encodings:
 //   KPacked: load << id_bits | local id in one u64 (built from the gathered
 //            load; local id = id - first id of the node's problem);
 //   KFull:   (u64 load, id);  KWide: (u128 load, id);
@@ -59,6 +61,7 @@ struct KPacked {
   __device__ KPacked sx(int m) const { return {shfl_xor64(v, m)}; }
   __device__ KPacked sl(int l) const { return {shfl64(v, l)}; }
   __device__ KPacked rl(int l) const { return {readlane64(v, l)}; }
+  __device__ static KPacked pick(bool c, const KPacked& a, const KPacked& b) { return {c ? a.v : b.v}; }
 };
 
 struct KFull {
@@ -71,6 +74,7 @@ struct KFull {
   __device__ KFull sx(int m) const { return {shfl_xor64(r, m), shfl_xor32(id, m)}; }
   __device__ KFull sl(int l) const { return {shfl64(r, l), shfl32(id, l)}; }
   __device__ KFull rl(int l) const { return {readlane64(r, l), readlane32(id, l)}; }
+  __device__ static KFull pick(bool c, const KFull& a, const KFull& b) { return {c ? a.r : b.r, c ? a.id : b.id}; }
 };
 
 struct KWide {
@@ -85,6 +89,9 @@ struct KWide {
   __device__ KWide sx(int m) const { return {shfl_xor64(hi, m), shfl_xor64(lo, m), shfl_xor32(id, m)}; }
   __device__ KWide sl(int l) const { return {shfl64(hi, l), shfl64(lo, l), shfl32(id, l)}; }
   __device__ KWide rl(int l) const { return {readlane64(hi, l), readlane64(lo, l), readlane32(id, l)}; }
+  __device__ static KWide pick(bool c, const KWide& a, const KWide& b) {
+    return {c ? a.hi : b.hi, c ? a.lo : b.lo, c ? a.id : b.id};
+  }
 };
 
 struct KRank {
@@ -96,6 +103,7 @@ struct KRank {
   __device__ KRank sx(int m) const { return {shfl_xor32(v, m)}; }
   __device__ KRank sl(int l) const { return {shfl32(v, l)}; }
   __device__ KRank rl(int l) const { return {readlane32(v, l)}; }
+  __device__ static KRank pick(bool c, const KRank& a, const KRank& b) { return {c ? a.v : b.v}; }
 };
 
 // Where a lane's credits go.  Hot nodes (member id kHotFlag | index) add into
@@ -140,7 +148,7 @@ __device__ __forceinline__ KT member_key_nb(const KeySrc& src, const KT* hkey, u
   const KT a = hkey[raw & (kHotMax - 1)];
   KT b = KT::mx();
   if (valid && !(raw & kHotFlag)) b = KT::load(src, raw);
-  return (raw & kHotFlag) ? a : b;
+  return KT::pick((raw & kHotFlag) != 0, a, b);
 }
 
 // ----------------------------------------------------------------------------
@@ -193,13 +201,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // A wavefront's heavy-leaf queue entries, staged in its LDS slice and copied
 // to the global queue with one counter atomic per flush (at the end of the
-// wavefront's tiles, or when the slice is full) instead of one per tile.
-constexpr uint32_t kQueueBuf = 256;
+// wavefront's tiles, or when the slice is full) instead of one per tile.  An
+// entry carries what the heavy pass needs without looking the tile up again:
+// the word of the leaf's first member group (tile member base + 4 lane), the
+// leaf's header word and the first node id of its problem.
+constexpr uint32_t kQueueBuf = 128;
 
 struct WaveQueue {
-  uint32_t* buf;   // the wavefront's kQueueBuf LDS words
+  uint4* buf;      // the wavefront's kQueueBuf LDS entries
   uint32_t n;      // entries staged (wave-uniform)
-  __device__ __forceinline__ void flush(uint32_t* __restrict__ queue, uint32_t* __restrict__ qcount) {
+  __device__ __forceinline__ void flush(uint4* __restrict__ queue, uint32_t* __restrict__ qcount) {
     if (n == 0) return;
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t base = 0;
@@ -212,23 +223,10 @@ struct WaveQueue {
   }
 };
 
-// Device twin of the planner's lane_tile_offset (member x of lane i's leaf).
-__device__ __forceinline__ uint64_t lane_tile_word(uint32_t x, uint32_t i) {
-  return (uint64_t)64 * kRowGroup * (x / kRowGroup) + (uint64_t)kRowGroup * i + x % kRowGroup;
-}
-
-// Lane tile: one leaf per lane; the lane's members x .. x + 3 are one 16-byte
-// word of the tile (groups of four rows), so every batch below is one or two
-// contiguous kilobyte loads per wavefront.
-// A single pass over the rows finds the hold minimum m (hold members come first
-// in every leaf) and counts the pivot members below m.  Lanes that have such
-// "low" members rank them: up to four are kept in registers; leaves with more
-// go to the heavy-leaf queue.  Keys are gathered only for members inside the
-// lane's leaf that are not hot (hot keys come from LDS).
 template <class KT>
 __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, const uint32_t* __restrict__ members,
                                           const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k1,
-                                          const KeySrc& src, const KT* hkey, Sink& sink, uint32_t* __restrict__ queue,
+                                          const KeySrc& src, const KT* hkey, Sink& sink, uint4* __restrict__ queue,
                                           uint32_t* __restrict__ qcount, WaveQueue& hq) {
   constexpr uint32_t U = kLaneBatch;   // rows per batch, a multiple of four
   const uint32_t lane = threadIdx.x & 63u;
@@ -262,15 +260,19 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
       const uint32_t x = x0 + u;
       const bool hold = x < h;
       const bool better = hold && key[u].lt(km);
-      km = better ? key[u] : km;
+      km = KT::pick(better, key[u], km);
       mraw = better ? raw[u] : mraw;
-      if (!hold && x < s && key[u].lt(km)) {
-        if (nlow == 0) { l0 = key[u]; r0 = raw[u]; }
-        else if (nlow == 1) { l1 = key[u]; r1 = raw[u]; }
-        else if (nlow == 2) { l2 = key[u]; r2 = raw[u]; }
-        else if (nlow == 3) { l3 = key[u]; r3 = raw[u]; }
-        ++nlow;
-      }
+      // straight-line slot update (no indexed array of keys)
+      const bool take = !hold && x < s && key[u].lt(km);
+      l0 = KT::pick(take && nlow == 0, key[u], l0);
+      l1 = KT::pick(take && nlow == 1, key[u], l1);
+      l2 = KT::pick(take && nlow == 2, key[u], l2);
+      l3 = KT::pick(take && nlow == 3, key[u], l3);
+      r0 = (take && nlow == 0) ? raw[u] : r0;
+      r1 = (take && nlow == 1) ? raw[u] : r1;
+      r2 = (take && nlow == 2) ? raw[u] : r2;
+      r3 = (take && nlow == 3) ? raw[u] : r3;
+      nlow += take ? 1u : 0u;
     }
   }
   if (nlow && nlow <= 4 && j >= 1) {
@@ -291,7 +293,11 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
   if (heavy) {
     const uint32_t cnt = (uint32_t)__popcll(heavy);
     if (hq.n + cnt > kQueueBuf) hq.flush(queue, qcount);
-    if (nlow > 4) hq.buf[hq.n + (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull))] = (tile_idx << 6) | lane;
+    if (nlow > 4) {
+      const uint64_t mw = t.mbase + kRowGroup * lane;
+      hq.buf[hq.n + (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull))] =
+          make_uint4((uint32_t)mw, (uint32_t)(mw >> 32), hd, t.nbase);
+    }
     hq.n += cnt;
   }
   const uint64_t cm = h ? binom[(size_t)(p - nlow) * k1 + j] : 0ull;
@@ -363,17 +369,18 @@ __global__ __launch_bounds__(256, 7) void leaf_credit_kernel(const Tile* __restr
                                                           uint32_t k1, KeySrc src, uint64_t* __restrict__ out,
                                                           const uint32_t* __restrict__ hot,
                                                           const uint32_t* __restrict__ hot_base, uint32_t nhot,
-                                                          uint64_t* __restrict__ scratch, uint32_t* __restrict__ queue,
-                                                          uint32_t* __restrict__ qcount) {
+                                                          uint64_t* __restrict__ scratch, uint4* __restrict__ queue,
+                                                          uint32_t* __restrict__ qcount, KT* __restrict__ hotkey) {
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kBinomLds];
-  __shared__ uint32_t qslice[4][kQueueBuf];
+  __shared__ uint4 qslice[4][kQueueBuf];
   for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
     KeySrc hs = src;
     hs.base = hot_base[i];
     hkey[i] = KT::load(hs, hot[i]);
     hcnt[i] = 0;
+    if (blockIdx.x == 0) hotkey[i] = hkey[i];   // for the heavy pass
   }
   const bool lds_binom = nbinom <= kBinomLds;
   if (lds_binom)
@@ -401,48 +408,51 @@ __global__ __launch_bounds__(256, 7) void leaf_credit_kernel(const Tile* __restr
 }
 
 // Heavy leaves (more than four pivot members below the hold minimum), queued
-// by the leaf-credit kernel as (tile << 6 | lane): one leaf per wavefront, one
+// by the leaf-credit kernel as 16-byte entries: one leaf per wavefront, one
 // member per lane, four leaves per batch so their loads overlap.  The hold
 // minimum m is recomputed; the rank of a low member among the low members is
-// counted with wavefront ballots.  No workgroup state: hot members' keys are
-// read through the hot table, and their credits go to the slot rows
-// (row blockIdx.x % kHotSlots) that the hot reduction adds up.
+// counted with wavefront ballots.  No workgroup state: hot members' keys come
+// from the table the leaf pass published, and their credits go to the slot
+// rows (row blockIdx.x % kHotSlots) that the hot reduction adds up.
 template <class KT>
-__global__ __launch_bounds__(256) void heavy_kernel(const Tile* __restrict__ tiles, const uint32_t* __restrict__ members,
-                                                    const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ binom,
-                                                    uint32_t k1, KeySrc src, uint64_t* __restrict__ out,
-                                                    const uint32_t* __restrict__ hot, uint32_t nhot,
-                                                    uint64_t* __restrict__ scratch,
-                                                    const uint32_t* __restrict__ queue,
-                                                    const uint32_t* __restrict__ qcount) {
+__global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__ members,
+                                                    const uint64_t* __restrict__ binom, uint32_t k1, KeySrc src,
+                                                    uint64_t* __restrict__ out, uint32_t nhot,
+                                                    uint64_t* __restrict__ scratch, const uint4* __restrict__ queue,
+                                                    const uint32_t* __restrict__ qcount,
+                                                    const KT* __restrict__ hotkey) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t total = *qcount;
   constexpr uint32_t B = 4;
   const uint32_t nw = gridDim.x * 4u;
   uint64_t* row = scratch + (size_t)(blockIdx.x % kHotSlots) * nhot;
+  // member x of the queued leaf: its group word + 256 (x / 4) + x % 4
+  const uint64_t xoff = (uint64_t)64 * kRowGroup * (lane / kRowGroup) + lane % kRowGroup;
   for (uint32_t e0 = (blockIdx.x * 4u + w) * B; e0 < total; e0 += nw * B) {
     uint32_t hq[B], sq[B], jq[B], ra[B], nb[B];
     KT ka[B];
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
-      const uint32_t e = min(e0 + q, total - 1);
-      const uint32_t ent = queue[e];
-      const Tile t = tiles[ent >> 6];
-      const uint32_t L = ent & 63u;
-      nb[q] = t.nbase;
-      const uint32_t hd = hdr[t.lbase + L];
+      const uint4 ent = queue[min(e0 + q, total - 1)];
+      const uint64_t mw = ((uint64_t)ent.y << 32) | ent.x;
+      const uint32_t hd = ent.z;
+      nb[q] = ent.w;
       hq[q] = hd & 31u;
       jq[q] = (hd >> 5) & 31u;
       sq[q] = hq[q] + (hd >> 10);
-      ra[q] = lane < sq[q] ? members[t.mbase + lane_tile_word(lane, L)] : 0u;
+      ra[q] = lane < sq[q] ? members[mw + xoff] : 0u;
     }
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
       KeySrc ts = src;
       ts.base = nb[q];
-      const uint32_t node = (ra[q] & kHotFlag) ? hot[ra[q] & (kHotMax - 1)] : ra[q];
-      ka[q] = lane < sq[q] ? KT::load(ts, node) : KT::mx();
+      KT k = KT::mx();
+      if (lane < sq[q]) {
+        if (ra[q] & kHotFlag) k = hotkey[ra[q] & (kHotMax - 1)];
+        else k = KT::load(ts, ra[q]);
+      }
+      ka[q] = k;
     }
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
@@ -1153,16 +1163,17 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   const uint32_t* hot_base = ws.at<uint32_t>(P->off_hot_base);
   const uint32_t nhot = (uint32_t)P->hot.size();
   uint64_t* scratch = ws.at<uint64_t>(P->off_scratch);
-  uint32_t* queue = ws.at<uint32_t>(P->off_queue);
+  uint4* queue = ws.at<uint4>(P->off_queue);
   uint32_t* qcount = ws.at<uint32_t>(P->off_qcount);
   const uint32_t nbinom = (uint32_t)P->binom.size();
   if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
 #define KDSS_LEAF(KT)                                                                                           \
   leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src, out,    \
-                                                 hot, hot_base, nhot, scratch, queue, qcount);                   \
+                                                 hot, hot_base, nhot, scratch, queue, qcount,                    \
+                                                 ws.at<KT>(P->off_hotkey));                                      \
   if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event record");                                                    \
-  heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(tiles, members, hdr, binom, P->k1, src, out, hot, nhot,     \
-                                                    scratch, queue, qcount)
+  heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(members, binom, P->k1, src, out, nhot, scratch, queue,      \
+                                                    qcount, ws.at<KT>(P->off_hotkey))
   switch (mode) {
     case 0: KDSS_LEAF(KPacked); break;
     case 1: KDSS_LEAF(KFull); break;
