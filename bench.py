@@ -35,6 +35,10 @@ WORKLOADS = {
     # 512 Chung-Lu graphs (n in [1k, 50k], average degree 8-40, exponent 2.2-2.8,
     # seeds 1000 + g), each at k = 3, 4, 6, 8: 2048 problems in one plan
     "batch-512": dict(kind="batch", graphs=512, ks=(3, 4, 6, 8), T=64),
+    # R-MAT (a, b, c) = (0.57, 0.19, 0.19), edge factor 8, seed 0, k = 6, T = 100,
+    # at scale 16: the scale-27 graph's clique tree is far beyond host memory
+    # (members grow about 28x per two scales); the oracle samples 1 iteration
+    "rmat-16": dict(kind="rmat", scale=16, edge_factor=8, seed=0, k=6, T=100, cpu_iters=1),
     # warm start vs cold start on an unseen Chung-Lu graph, n = 2M, m = 40M,
     # exponent 2.5, seed 90000; k = 6; the reference density is the best over a
     # 4T cold run with an extraction after every iteration
@@ -286,6 +290,8 @@ def make_graph(w):
     if w["kind"] == "chung_lu":
         return synth.chung_lu(w["n"], w["m"], w["beta"], seed=w["seed"], planted=w["planted"],
                               planted_p=w["planted_p"])
+    if w["kind"] == "rmat":
+        return synth.rmat(w["scale"], w["edge_factor"], seed=w["seed"])
     return synth.erdos_renyi(w["n"], w["p"], seed=w["seed"], planted_clique=w["planted"])
 
 
@@ -525,7 +531,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(g, w, ts.leaves, args.cpu_sample_iters)
+        out["cpu_baseline"] = cpu_baseline(g, w, ts.leaves, w.get("cpu_iters", args.cpu_sample_iters))
     print(json.dumps(out))
 
 

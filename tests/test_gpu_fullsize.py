@@ -1,0 +1,151 @@
+"""Parity at the benchmarked sizes, in the launch configurations bench.py times.
+
+* Chung-Lu n = 1,000,000, m = 10,000,000, k = 5, T = 200: the oracle runs the
+  whole problem (its clique listing fits in memory), so loads, order, density
+  and upper bound are compared bit for bit.
+* The 2048-problem batch (512 Chung-Lu graphs x k in {3, 4, 6, 8}, T = 64, one
+  plan, autotuned grids, hipGraph iterations): eight sampled problems, each
+  solved by the oracle on its own.
+* The warm-start evaluation graph (n = 2,000,000, m = 40,000,000, k = 6) and
+  R-MAT scale 16 (k = 6): too many cliques for the oracle, so properties that
+  hold at any size are checked: Lemma 6 (the loads grow by exactly T c_k),
+  the order is the sort of the loads (descending, ties by ascending id), and
+  density <= upper bound.  R-MAT scale 12 is compared with the oracle bit for
+  bit at both load widths.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2403_05775_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_05775_amd import kdss
+    kdss.lib()
+    return kdss
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def loads(x):
+    return [int(v) for v in (x if isinstance(x, list) else x.tolist())]
+
+
+def assert_properties(g, sol, T, r0=None):
+    """Lemma 6, order = sort of the loads, density <= upper bound (64-bit loads)."""
+    assert not isinstance(sol.r, list)
+    r = sol.r.astype(np.uint64)
+    base = np.zeros(g.n, dtype=np.uint64) if r0 is None else np.asarray(r0, dtype=np.uint64)
+    assert np.all(r >= base)
+    grow = r - base
+    assert int(grow.astype(object).sum()) == T * sol.c_k          # Lemma 6
+    order = sol.order.astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(g.n))
+    ro = r[order]
+    assert np.all(ro[:-1] >= ro[1:])                               # loads non-increasing
+    tie = ro[:-1] == ro[1:]
+    assert np.all(order[:-1][tie] < order[1:][tie])                # ties by ascending id
+    assert sol.ub_num == int(grow.max())
+    assert sol.dens_num * T <= sol.ub_num * max(sol.size, 1)        # density <= upper bound
+
+
+def test_chung_lu_1m_bit_exact(K, oracle_mod):
+    say("chung-lu 1M k=5 T=200: generating")
+    g = synth.chung_lu(1_000_000, 10_000_000, 2.5, seed=0, planted=40, planted_p=0.9)
+    say("chung-lu 1M k=5 T=200: GPU")
+    sol = K.solve(g, 5, 200)
+    say("chung-lu 1M k=5 T=200: oracle")
+    ref = oracle_mod.solve(g.n, g.row_ptr, g.col, 5, 200)
+    assert loads(sol.r) == loads(ref["r"])
+    assert np.array_equal(sol.order, ref["order"])
+    assert (sol.size, sol.dens_num, sol.ub_num, sol.c_k) == (ref["size"], ref["dens_num"], ref["ub_num"],
+                                                            ref["c_k"])
+
+
+def test_batch_512_sampled(K, oracle_mod):
+    from paper_2403_05775_amd import gnn
+    say("batch 512 x 4: generating")
+    graphs = gnn.generate(512, base_seed=1000, n_lo=1000, n_hi=50000, workers=16, log=lambda *_: None)
+    jobs = [(g, k) for g in graphs for k in (3, 4, 6, 8)]
+    trees = [K.Tree(g, k) for g, k in jobs]
+    T = 64
+    say("batch 512 x 4: plan and run")
+    b = K.Batch(trees, T, use_graph=True)
+    ws = b.alloc_workspace()
+    b.upload(ws)
+    r = torch.empty(b.n, dtype=torch.int64, device="cuda")
+    order = torch.empty(b.n, dtype=torch.int32, device="cuda")
+    b.autotune(ws, r, warm=2, iters=2)
+    res = b.run(ws, T, r, order)
+    torch.cuda.synchronize()
+    rr = r.cpu().numpy().view(np.uint64)
+    oo = order.cpu().numpy().view(np.uint32)
+    off = b.node_off.astype(np.int64)
+    # eight problems the oracle finishes in seconds: for each k, the smallest
+    # and the largest clique count up to 2e7
+    ck = np.array([t.stats().c_k.value for t in trees], dtype=np.float64)
+    picks = []
+    for k in (3, 4, 6, 8):
+        idx = [q for q, (_, kk) in enumerate(jobs) if kk == k and 0 < ck[q] <= 2e7]
+        idx.sort(key=lambda q: ck[q])
+        picks += [idx[0], idx[-1]]
+    for q in picks:
+        g, k = jobs[q]
+        say(f"batch problem {q} (n={g.n}, k={k}, c_k={int(ck[q])}): oracle")
+        ref = oracle_mod.solve(g.n, g.row_ptr, g.col, k, T)
+        assert rr[off[q]:off[q + 1]].tolist() == loads(ref["r"]), q
+        assert np.array_equal(oo[off[q]:off[q + 1]], ref["order"]), q
+        assert (res[q].size, res[q].dens_num.value, res[q].ub_num.value) == (ref["size"], ref["dens_num"],
+                                                                              ref["ub_num"]), q
+    for t in trees:
+        t.close()
+
+
+def test_warm_start_graph_properties(K):
+    from paper_2403_05775_amd import gnn
+    say("chung-lu 2M m=40M k=6: generating")
+    g = synth.chung_lu(2_000_000, 40_000_000, 2.5, seed=90000)
+    tree = K.Tree(g, 6)
+    dev = torch.device("cuda:0")
+    dg = gnn.DeviceGraph(g, tree, dev)
+    model = gnn.Model(device=dev)
+    import os
+    if os.path.exists(gnn.WEIGHTS_FILE):
+        with np.load(gnn.WEIGHTS_FILE) as z:
+            model.load(z)
+    r0, rmax = model.warm_start(dg, 50)
+    r0h = r0.cpu().numpy().view(np.uint64)
+    assert rmax == int(r0h.max())
+    tree.close()
+    for T, start in ((3, None), (3, r0h)):
+        say(f"chung-lu 2M k=6 T={T} {'warm' if start is not None else 'cold'}: GPU")
+        sol = K.solve(g, 6, T, r0=start)
+        assert_properties(g, sol, T, start)
+
+
+@pytest.mark.parametrize("width", [0, 128])
+def test_rmat_12_bit_exact(K, oracle_mod, width):
+    g = synth.rmat(12, 8, seed=0)
+    say(f"rmat 12 k=6 T=100 width={width}")
+    sol = K.solve(g, 6, 100, width=width)
+    ref = oracle_mod.solve(g.n, g.row_ptr, g.col, 6, 100)
+    assert loads(sol.r) == loads(ref["r"])
+    assert np.array_equal(sol.order, ref["order"])
+    assert (sol.size, sol.dens_num, sol.ub_num) == (ref["size"], ref["dens_num"], ref["ub_num"])
+
+
+def test_rmat_16_properties(K):
+    g = synth.rmat(16, 8, seed=0)
+    say("rmat 16 k=6 T=100")
+    sol = K.solve(g, 6, 100)
+    assert_properties(g, sol, 100)
