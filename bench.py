@@ -86,7 +86,8 @@ def batch_bench(w, args):
     order = torch.empty(n_total, dtype=torch.int32, device=dev)
     tune = b.autotune(ws, r, warm=3, iters=3)
     log(f"plan {plan_s:.1f} s, workspace {b.workspace_bytes / 1e9:.1f} GB, key mode {b.stats().key_mode}; "
-        f"autotune: leaf {tune.best_leaf_blocks} heavy {tune.best_heavy_blocks} ({tune.best_ms:.3f} ms/iter)")
+        f"autotune: leaf {tune.best_leaf_blocks} heavy {tune.best_heavy_blocks} gather {tune.best_gather} "
+        f"({tune.best_ms:.3f} ms/iter; masked {tune.gather_ms[0]:.3f}, full {tune.gather_ms[1]:.3f})")
     for i in range(args.warmup):
         b.run(ws, T, r, order)
     torch.cuda.synchronize()
@@ -107,8 +108,11 @@ def batch_bench(w, args):
         "hbm_gbps_algorithmic": step_bytes / (ms / 1000.0) / 1e9,
         "host_build_s": build_s, "plan_s": plan_s,
         "autotune": {"leaf_blocks": tune.best_leaf_blocks, "heavy_blocks": tune.best_heavy_blocks,
-                     "ms_per_iter": tune.best_ms,
-                     "tried": [[tune.leaf_blocks[i], tune.heavy_blocks[i], tune.ms[i]] for i in range(tune.tried)]},
+                     "ms_per_iter": tune.best_ms, "gather": tune.best_gather,
+                     "gather_ms": {"masked": tune.gather_ms[0], "full": tune.gather_ms[1]},
+                     "hot_share": st.hot_share,
+                     "tried": [[tune.leaf_blocks[i], tune.heavy_blocks[i], tune.ms[i]]
+                               for i in range(min(tune.tried, 32))]},
         "densest_sizes_first8": [x.size for x in res[:8]],
     }
     print(json.dumps(out))
@@ -323,8 +327,21 @@ def cpu_baseline(g, w, L, sample_T):
                 seconds=secs, listing_seconds=res["enum_seconds"])
 
 
-def counters_mode(w):
-    """A short run for rocprofv3 counter passes: 20 iterations of the workload,
+def tune_plan(plan, ws, r, T, args):
+    """Grid sizes and gather mode timed on the plan's own data (outside any
+    timed region), as the default workload runs them."""
+    if args.no_autotune or T < 8:
+        return None
+    tune = plan.autotune(ws, r, warm=3, iters=5)
+    log(f"autotune: leaf {tune.best_leaf_blocks} heavy {tune.best_heavy_blocks} gather {tune.best_gather} "
+        f"({tune.best_ms * 1000:.2f} us/iter; masked {tune.gather_ms[0] * 1000:.2f}, "
+        f"full {tune.gather_ms[1] * 1000:.2f})")
+    return tune
+
+
+def counters_mode(w, args):
+    """A short run for rocprofv3 counter passes: the tuning of the bench run,
+    then 20 iterations of the workload (the last 20 leaf-credit dispatches),
     then a plain 1 GiB device copy (three times) that calibrates the counters."""
     import torch
     from paper_2403_05775_amd import kdss
@@ -335,6 +352,7 @@ def counters_mode(w):
     plan.upload(ws)
     r = plan.alloc_loads("cuda:0")
     order = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    tune_plan(plan, ws, r, w["T"], args)
     plan.run(ws, 20, r, order)
     a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
     b = torch.empty_like(a)
@@ -363,7 +381,9 @@ def summarize_counters(workload, fetch_db, write_db, command):
     out = {"workload": workload, "kernel_sha256_16": kernel_hash(), "command": command}
     for name, db in (("fetch", fetch_db), ("write", write_db)):
         per = _db_rows(db)
-        leaf = [v for (k, d), v in per.items() if "leaf_credit_kernel" in k and "KPacked" in k]
+        # the last 20 dispatches: the run after the tuning launches
+        leaf = [v for (k, d), v in sorted(per.items(), key=lambda kv: kv[0][1])
+                if "leaf_credit_kernel" in k and "KPacked" in k][-20:]
         other = [v for (k, d), v in per.items() if "anonymous namespace" not in k]
         copy = max(other) if other else None
         leaf_kib = sum(leaf) / len(leaf)
@@ -379,13 +399,18 @@ def summarize_trace(db, command):
     """Kernel-trace statistics (rocprofv3 --kernel-trace --stats) as markdown."""
     import sqlite3
     c = sqlite3.connect(db)
-    lines = ["# Kernel trace: " + command, "", "Durations from the dispatch records (end - start).", "",
-             "| kernel | calls | total us | average us | min us | max us |", "|---|---|---|---|---|---|"]
-    rows = c.execute("select name, count(*), sum(end - start), avg(end - start), min(end - start), "
-                     "max(end - start) from kernels group by name order by sum(end - start) desc limit 25")
-    for name, calls, tot, avg, mn, mx in rows:
+    lines = ["# Kernel trace: " + command, "",
+             "Durations from the dispatch records (end - start), per kernel and grid size "
+             "(the tuning launches run the other grid sizes).", "",
+             "| kernel | workgroups | calls | total us | average us | min us | max us |",
+             "|---|---|---|---|---|---|---|"]
+    rows = c.execute("select name, grid_x / max(workgroup_x, 1), count(*), sum(end - start), avg(end - start), "
+                     "min(end - start), max(end - start) from kernels group by name, grid_x "
+                     "order by sum(end - start) desc limit 30")
+    for name, wg, calls, tot, avg, mn, mx in rows:
         short = name.replace("(anonymous namespace)::", "").split("(")[0]
-        lines.append(f"| {short} | {calls} | {tot / 1e3:.1f} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | {mx / 1e3:.2f} |")
+        lines.append(f"| {short} | {wg} | {calls} | {tot / 1e3:.1f} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | "
+                     f"{mx / 1e3:.2f} |")
     return "\n".join(lines) + "\n"
 
 
@@ -401,6 +426,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=20)
     ap.add_argument("--graph", action="store_true", help="replay iterations as hipGraphs")
+    ap.add_argument("--no-autotune", action="store_true", help="default grid sizes and gather mode")
     ap.add_argument("--mode", default="bench", choices=["bench", "counters"],
                     help="counters: short run for rocprofv3 --pmc passes (with a copy calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
@@ -423,7 +449,7 @@ def main():
         print(md)
         return
     if args.mode == "counters":
-        counters_mode(WORKLOADS[args.workload])
+        counters_mode(WORKLOADS[args.workload], args)
         return
     if WORKLOADS[args.workload]["kind"] in ("batch", "gnn"):
         if args.gpus != 1:
@@ -452,8 +478,6 @@ def main():
         f"c_k={ts.c_k.value} build={ts.build_seconds:.2f} s")
     T = w["T"]
     plan = kdss.Plan(tree, T, use_graph=args.graph)
-    tplan = kdss.Plan(tree, T, time_kernels=True)
-    ps = plan.stats()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
@@ -461,6 +485,12 @@ def main():
     plan.upload(ws)
     r = plan.alloc_loads(dev)
     order = torch.empty(g.n, dtype=torch.int32, device=dev)
+    tune = tune_plan(plan, ws, r, T, args)
+    ps = plan.stats()
+    # the same launch configuration with hipEvents around every launch
+    tplan = kdss.Plan(tree, T, time_kernels=True, gather=ps.gather)
+    if tune is not None:
+        tplan.set_launch(tune.best_leaf_blocks, tune.best_heavy_blocks)
 
     for i in range(args.warmup):
         res, _ = plan.run(ws, T, r, order)
@@ -514,13 +544,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {g.name}, k={w['k']}, T={T}", "n": g.n, "m": g.m,
                    "k": w["k"], "T": T, "leaves": ts.leaves, "members": ts.members, "c_k": ts.c_k.value,
-                   "parallelism": "single GPU", "hip_graph": bool(args.graph)},
+                   "parallelism": "single GPU", "hip_graph": bool(args.graph),
+                   "gather": "masked" if ps.gather == 1 else "full", "hot_share": round(ps.hot_share, 4)},
         "hbm_gbps_algorithmic": step_bytes / (ms_per_step / 1000.0) / 1e9,
         "sct_build_s": ts.build_seconds,
         "result": {"size": res.size, "dens_num": res.dens_num.value, "ub_num": res.ub_num.value,
                    "density": res.density, "upper_bound": res.upper_bound},
         "kernel_us": {"leaf_credit": leaf_us, "heavy_leaf": heavy_us, "hot_reduce": reduce_us, "apply": apply_us},
         "heavy_leaves_per_iteration": heavy_per_iter,
+        "launch": ({"leaf_blocks": tune.best_leaf_blocks, "heavy_blocks": tune.best_heavy_blocks,
+                    "gather": tune.best_gather, "us_per_iter": tune.best_ms * 1000,
+                    "gather_us": {"masked": tune.gather_ms[0] * 1000, "full": tune.gather_ms[1] * 1000}}
+                   if tune is not None else "defaults"),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "leaf_credit_kernel<KPacked>", "bytes_per_launch": leaf_bytes},

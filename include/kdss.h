@@ -85,6 +85,14 @@ typedef struct {
     int time_kernels;         /* 1: bracket every leaf-credit and load-update
                                  launch of kdss_run with hipEvents (plain
                                  launches, no graph); see kdss_plan_timing    */
+    int gather;               /* key gathers of the leaf-credit pass:
+                                 0: choose (masked when hot nodes hold at least
+                                    half of the member occurrences; autotune
+                                    may switch);
+                                 1: masked: only members inside the lane's leaf
+                                    that are not hot are gathered;
+                                 2: full: every row's key is gathered (no
+                                    branch, more loads in flight)              */
 } kdss_opts;
 
 typedef struct {              /* accumulated by kdss_run when time_kernels = 1  */
@@ -108,6 +116,9 @@ typedef struct {
     uint64_t tiles[5];        /* per size class: s <= 8, 16, 32, 64, > 64       */
     uint64_t leaves[5];
     uint64_t members[5];
+    int gather;               /* gather mode of later runs: 1 masked, 2 full   */
+    uint32_t hot_nodes;       /* nodes whose keys and credits live in LDS       */
+    double hot_share;         /* their share of all member occurrences          */
 } kdss_plan_stats;
 
 typedef struct {
@@ -212,8 +223,11 @@ typedef struct {
     uint32_t tried;               /* configurations timed                      */
     uint32_t best_leaf_blocks, best_heavy_blocks;
     double best_ms;               /* per iteration, best configuration         */
-    uint32_t leaf_blocks[16], heavy_blocks[16];
-    double ms[16];                /* per iteration, each configuration         */
+    uint32_t leaf_blocks[32], heavy_blocks[32];
+    double ms[32];                /* per iteration, each grid-size pair        */
+    int best_gather;              /* gather mode kept (1 masked, 2 full)       */
+    double gather_ms[2];          /* per iteration at the best grid sizes with
+                                     masked / full gathers (0: not timed)      */
 } kdss_tune_result;
 
 /* Sets the grid sizes (leaf-credit 1..2048, heavy-leaf 1..1024 workgroups) used by later runs. */
@@ -221,7 +235,8 @@ int kdss_plan_set_launch(kdss_plan *p, uint32_t leaf_blocks, uint32_t heavy_bloc
 
 /* Times `iters` iterations after `warm` untimed ones (from zero loads) for each
  * candidate pair of grid sizes on the plan's own data, keeps the fastest and
- * reports all (out, host).  d_r (device, the plan's load width) is scratch.
+ * reports all (out, host).  When the plan's options left the gather mode to the
+ * library, the other mode is then timed at the best sizes and kept if faster.  d_r (device, the plan's load width) is scratch.
  * warm + iters must not exceed T_max.  Synchronises the stream. */
 int kdss_plan_autotune(kdss_plan *p, void *d_ws, size_t ws_bytes, uint64_t *d_r, uint32_t warm, uint32_t iters,
                        kdss_tune_result *out, void *stream);

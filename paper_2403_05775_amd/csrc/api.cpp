@@ -190,13 +190,14 @@ static void layout_workspace(kdss_plan* P) {
   P->heavy_blocks = kHeavyBlocks;
   P->off_hot = take(P->hot.size() * 4);
   P->off_hot_base = take(P->hot.size() * 4);
-  // hot-node credit slot rows (kept zero between passes)
+  // hot-node credit slots, hot-node-major (kept zero between passes)
   P->off_scratch = take((size_t)kHotSlots * P->hot.size() * 8);
   P->lane_leaves = 0;
   for (const Tile& tl : P->tiles)
     if ((tl.info & 7u) == kTileLane) P->lane_leaves += (tl.info >> 3) & 0x1FFFu;
   P->off_queue = take(P->lane_leaves * 16);   // 16-byte heavy-leaf entries
-  P->off_hotkey = take((size_t)kHotMax * 32);  // hot-node keys of the current pass
+  P->off_hotkey = take((size_t)kHotMax * 32);     // hot-node keys of the current pass
+  P->off_hotkey_fw = take((size_t)kHotMax * 32);  // hot-node keys at the current loads (64-bit runs)
   P->off_qcount = take(64);
   P->off_qlog = take((size_t)P->T_max * 4);
   // batch extraction: prefix sums, per-problem results and node offsets
@@ -253,6 +254,10 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
       delete P;
       return fail(KDSS_EINVAL, "width must be 0, 64 or 128");
     }
+    if (P->opts.gather < 0 || P->opts.gather > 2) {
+      delete P;
+      return fail(KDSS_EINVAL, "gather must be 0, 1 or 2");
+    }
     if (P->opts.width == 64 && !fits64) {
       delete P;
       return fail(KDSS_EOVERFLOW, "loads may exceed 2^64 - 1 but width 64 was forced");
@@ -286,6 +291,11 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
       });
       if (cand.size() > kHotMax) cand.resize(kHotMax);
       P->hot = cand;
+      uint64_t occ_all = 0, occ_hot = 0;
+      for (uint64_t u = 0; u < n_total; ++u) occ_all += occ[u];
+      for (uint32_t u : cand) occ_hot += occ[u];
+      P->hot_share = occ_all ? (double)occ_hot / (double)occ_all : 0.0;
+      P->gather = P->opts.gather != 0 ? P->opts.gather : (P->hot_share >= kMaskedGatherShare ? 1 : 2);
       for (uint32_t i = 0; i < P->hot.size(); ++i) {
         hot_index[P->hot[i]] = i;
         const uint64_t q = std::upper_bound(P->node_off.begin(), P->node_off.end(), (uint64_t)P->hot[i]) -
@@ -375,8 +385,7 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
         tl.info = pack_tile_info(kTileBig, 1, 0);
         tl.nbase = (uint32_t)P->node_off[ref_q(refs[i])];
         P->hdr.push_back(header(refs[i]));
-        // whole 16-byte groups, so every lane tile starts 16-byte aligned
-        mtotal += (leaf_size(refs[i]) + kRowGroup - 1) / kRowGroup * kRowGroup;
+        mtotal += leaf_size(refs[i]);
         jobs.push_back({kNumLaneGroups, i});
         P->tiles.push_back(tl);
         P->class_tiles[kBigClass]++;
@@ -398,7 +407,7 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
         tl.lbase = (uint32_t)(P->hdr.size() - nl);
         tl.info = pack_tile_info(kTileLane, nl, smax);
         tl.nbase = (uint32_t)P->node_off[ref_q(refs[i0])];
-        mtotal += (uint64_t)64 * ((smax + kRowGroup - 1) / kRowGroup * kRowGroup);
+        mtotal += (uint64_t)64 * smax;
         jobs.push_back({gi, i0});
         P->tiles.push_back(tl);
         P->class_tiles[size_bucket(smax)]++;
@@ -417,13 +426,11 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
           const Sct& t = *trees[ref_q(r)];
           const uint64_t nb = P->node_off[ref_q(r)];
           for (uint64_t x = t.off[ref_id(r)]; x < t.off[ref_id(r) + 1]; ++x) *dst++ = encode(nb + t.members[x]);
-          const uint32_t sz = leaf_size(r);
-          for (uint32_t x = sz; x % kRowGroup; ++x) *dst++ = 0u;
           continue;
         }
-        // groups of four rows: member x of leaf r at mbase + 256 (x / 4) + 4 r + x % 4
+        // column-major: member x of leaf r at mbase + 64 x + r
         const uint32_t nl = (tl.info >> 3) & 0x1FFFu, smax = tl.info >> 16;
-        const uint32_t rows = (smax + kRowGroup - 1) / kRowGroup * kRowGroup;
+        const uint32_t rows = smax;
         uint64_t moff[64];
         uint32_t msz[64];
         const Sct& t = *trees[ref_q(refs[jobs[j].i0])];
@@ -506,6 +513,9 @@ int kdss_plan_info(const kdss_plan* P, kdss_plan_stats* out) {
   out->key_mode = P->key_mode;
   out->id_bits = P->id_bits;
   out->T_max = P->T_max;
+  out->gather = P->gather;
+  out->hot_nodes = (uint32_t)P->hot.size();
+  out->hot_share = P->hot_share;
   for (int c = 0; c < kNumClasses; ++c) {
     out->tiles[c] = P->class_tiles[c];
     out->leaves[c] = P->class_leaves[c];

@@ -77,10 +77,8 @@ u128 binom128(uint64_t a, uint64_t b);
 // ---- device layout ----
 // Leaves with at most 64 members are processed one leaf per lane: a "lane
 // tile" is one round of up to 64 leaves of similar size, whose members are
-// stored in groups of four rows: member x of the tile's leaf i at
-// mbase + 256 (x / 4) + 4 i + x % 4 (rows padded to a multiple of four, short
-// leaves padded), so each lane reads four of its members with one 16-byte load
-// and a wavefront's load is one contiguous kilobyte.
+// stored column-major (member x of the tile's leaf i at mbase + 64 x + i, short
+// leaves padded), so every member load of a wavefront is one contiguous row.
 // Leaves are grouped by size (kLaneBounds) and keep the tree's depth-first
 // order inside a group, so neighbouring lanes usually share the leaf's root.
 // Larger leaves ("big") are processed one per wavefront, members contiguous.
@@ -90,12 +88,9 @@ constexpr int kBigClass = 4;
 constexpr uint32_t kTileLane = 0, kTileBig = 4;
 constexpr uint32_t kMaxBigLeaf = 4096;     // largest leaf the planner accepts
 constexpr uint32_t kMaxK = 31;
-constexpr uint32_t kRowGroup = 4;          // rows interleaved per lane in lane tiles
 
 // Word offset of member x of leaf i (lane i) inside a lane tile.
-inline uint64_t lane_tile_offset(uint32_t x, uint32_t i) {
-  return (uint64_t)64 * kRowGroup * (x / kRowGroup) + (uint64_t)kRowGroup * i + x % kRowGroup;
-}
+inline uint64_t lane_tile_offset(uint32_t x, uint32_t i) { return (uint64_t)64 * x + i; }
 constexpr uint32_t kLaneBounds[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64};
 constexpr int kNumLaneGroups = sizeof(kLaneBounds) / sizeof(kLaneBounds[0]);
 
@@ -117,14 +112,17 @@ constexpr uint32_t kRedThreads = 256, kRedTile = 4096;
 constexpr uint32_t kBinomLds = 512;              // binomial tables up to this size live in LDS
 // Hot nodes: the nodes that occur in the most leaves.  Their member ids carry
 // kHotFlag | index into the hot table; every workgroup keeps their keys and
-// credits in LDS and writes its credit totals to a scratch row at its end.
+// credits in LDS and adds its nonzero credit totals, at its end, into one of
+// kHotSlots slot entries per hot node (hot-node-major: slot b of hot node i is
+// word i * kHotSlots + b, so one node's slots are read as one contiguous run).
 constexpr uint32_t kHotMax = 512;
 constexpr uint32_t kHotMinOccurrences = 32;
 constexpr uint32_t kHotFlag = 0x80000000u;
 constexpr uint32_t kLeafBlocksMax = 2048;        // persistent leaf-credit grid, largest
 constexpr uint32_t kLeafBlocksDefault = 1792;    // seven workgroups per CU
 constexpr uint32_t kHeavyBlocks = 1024;          // grid of the heavy-leaf kernel
-constexpr uint32_t kHotSlots = 256;              // hot-node credit rows shared by workgroups
+constexpr uint32_t kHotSlots = 256;              // credit slots per hot node, shared by workgroups
+constexpr double kMaskedGatherShare = 0.5;       // hot share from which masked gathers are the default
 
 // Device-side result of an extraction.
 struct DevResult {
@@ -155,6 +153,8 @@ struct kdss_plan {
   uint32_t n = 0, k = 0, T_max = 0, id_bits = 0, s_max = 0;
   int width = 64;          // load width
   int key_mode = 0;        // 0 packed, 1 full
+  int gather = 1;          // leaf-pass key gathers: 1 masked, 2 full
+  double hot_share = 0.0;  // hot nodes' share of all member occurrences
   uint64_t r0_max = 0;
   kdss::u128 c_k = 0;
   kdss_opts opts{};
@@ -174,7 +174,8 @@ struct kdss_plan {
   std::vector<uint32_t> hot_base;      // first node id of each hot node's problem
   size_t off_hot = 0, off_hot_base = 0, off_scratch = 0, off_dbase = 0, off_queue = 0, off_qcount = 0;
   size_t off_qlog = 0;
-  size_t off_hotkey = 0;               // hot-node keys published by the leaf pass for the heavy pass                 // heavy-queue sizes of timed iterations (u32[T_max])
+  size_t off_hotkey = 0;               // hot-node keys published by a leaf pass for its heavy pass
+  size_t off_hotkey_fw = 0;            // hot-node keys at the current loads, kept by the load update
   uint32_t heavy_blocks = 0;           // grid of the heavy-leaf kernel
   uint32_t k1 = 0;                     // binomial table row length (largest k + 1)
   kdss::u128 bound_max = 0;            // largest r0_max + T_max * c_k over the problems

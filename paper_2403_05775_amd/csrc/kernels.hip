@@ -141,13 +141,23 @@ __device__ __forceinline__ KT member_key(const KeySrc& src, const KT* hkey, uint
 }
 
 // Form for batched loads: the LDS slot is always read (its index masked into
-// the table) and the global key only for a valid, non-hot member, so a batch
-// of these issues back to back under per-lane masks.
-template <class KT>
-__device__ __forceinline__ KT member_key_nb(const KeySrc& src, const KT* hkey, uint32_t raw, bool valid = true) {
+// the table), then one of the two keys is selected.
+// * Masked: the global key is gathered only for a valid, non-hot member.  The
+//   gathers run under per-lane masks, and the compiler waits for each before the
+//   next, but no load is spent on hot members (the right choice when hot nodes
+//   hold most member occurrences).
+// * Full: every row's key is gathered, a hot member's from its hot index read
+//   as a node id (below the hot count, which never exceeds n; padding is node
+//   0), so a batch issues all its gathers back to back with no branch.
+template <class KT, bool kMasked>
+__device__ __forceinline__ KT member_key_nb(const KeySrc& src, const KT* hkey, uint32_t raw, bool valid) {
   const KT a = hkey[raw & (kHotMax - 1)];
   KT b = KT::mx();
-  if (valid && !(raw & kHotFlag)) b = KT::load(src, raw);
+  if constexpr (kMasked) {
+    if (valid && !(raw & kHotFlag)) b = KT::load(src, raw);
+  } else {
+    b = KT::load(src, raw & ~kHotFlag);
+  }
   return KT::pick((raw & kHotFlag) != 0, a, b);
 }
 
@@ -191,7 +201,7 @@ __device__ __forceinline__ void combine_add(Sink& sink, uint32_t key, uint64_t v
   if (run_end && v) sink.add(key, v);
 }
 
-constexpr uint32_t kLaneBatch = 4;   // rows per lane-tile batch (one 16-byte load)
+constexpr uint32_t kLaneBatch = 4;   // rows per lane-tile batch
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -203,8 +213,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // to the global queue with one counter atomic per flush (at the end of the
 // wavefront's tiles, or when the slice is full) instead of one per tile.  An
 // entry carries what the heavy pass needs without looking the tile up again:
-// the word of the leaf's first member group (tile member base + 4 lane), the
-// leaf's header word and the first node id of its problem.
+// the word of the leaf's first member (tile member base + lane), the leaf's
+// header word and the first node id of its problem.
 constexpr uint32_t kQueueBuf = 128;
 
 struct WaveQueue {
@@ -223,17 +233,24 @@ struct WaveQueue {
   }
 };
 
-template <class KT>
+// Lane tile: one leaf per lane; member x of the lane's leaf is the row-x word
+// of the column-major tile, so every row load below is one contiguous 256-byte
+// row.  A single pass over the rows finds the hold minimum m (hold members come
+// first in every leaf) and counts the pivot members below m.  Lanes that have
+// such "low" members rank them: up to four are kept in registers; leaves with
+// more go to the heavy-leaf queue.  Keys are gathered only for members inside
+// the lane's leaf that are not hot (hot keys come from LDS).
+template <class KT, bool kMasked>
 __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, const uint32_t* __restrict__ members,
                                           const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k1,
                                           const KeySrc& src, const KT* hkey, Sink& sink, uint4* __restrict__ queue,
                                           uint32_t* __restrict__ qcount, WaveQueue& hq) {
-  constexpr uint32_t U = kLaneBatch;   // rows per batch, a multiple of four
+  constexpr uint32_t U = kLaneBatch;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nl = (t.info >> 3) & 0x1FFFu, smax = t.info >> 16;
   const uint32_t hd = lane < nl ? hdr[t.lbase + lane] : 0u;   // a missing leaf reads as empty
   const uint32_t h = hd & 31u, j = (hd >> 5) & 31u, p = hd >> 10, s = h + p;
-  const uint32_t* __restrict__ grp = members + t.mbase + kRowGroup * lane;
+  const uint32_t* __restrict__ col = members + t.mbase + lane;
   KT km = KT::mx();
   uint32_t mraw = 0, nlow = 0;
   // the first four low members, in row order (hold members precede pivot
@@ -244,17 +261,9 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
     uint32_t raw[U];
     KT key[U];
 #pragma unroll
-    for (uint32_t g = 0; g < U / kRowGroup; ++g) {
-      uint4 w4 = {0u, 0u, 0u, 0u};
-      if (g == 0 || x0 + g * kRowGroup < smax)   // groups past the tile's rows are absent
-        w4 = *reinterpret_cast<const uint4*>(grp + (size_t)64 * (x0 + g * kRowGroup));
-      raw[g * 4 + 0] = w4.x;
-      raw[g * 4 + 1] = w4.y;
-      raw[g * 4 + 2] = w4.z;
-      raw[g * 4 + 3] = w4.w;
-    }
+    for (uint32_t u = 0; u < U; ++u) raw[u] = col[(size_t)min(x0 + u, smax - 1) * 64];   // rows past the tile repeat its last
 #pragma unroll
-    for (uint32_t u = 0; u < U; ++u) key[u] = member_key_nb<KT>(src, hkey, raw[u], x0 + u < s);
+    for (uint32_t u = 0; u < U; ++u) key[u] = member_key_nb<KT, kMasked>(src, hkey, raw[u], x0 + u < s);
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) {
       const uint32_t x = x0 + u;
@@ -294,7 +303,7 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
     const uint32_t cnt = (uint32_t)__popcll(heavy);
     if (hq.n + cnt > kQueueBuf) hq.flush(queue, qcount);
     if (nlow > 4) {
-      const uint64_t mw = t.mbase + kRowGroup * lane;
+      const uint64_t mw = t.mbase + lane;
       hq.buf[hq.n + (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull))] =
           make_uint4((uint32_t)mw, (uint32_t)(mw >> 32), hd, t.nbase);
     }
@@ -361,7 +370,7 @@ __device__ __forceinline__ void tile_big(const Tile& t, const uint32_t* __restri
 // kHotSlots scratch rows (row blockIdx.x % kHotSlots).
 // At least seven wavefronts per SIMD (<= 64 VGPRs): the pass is latency-bound,
 // and occupancy hides more of it than wider row batches do.
-template <class KT>
+template <class KT, bool kMasked>
 __global__ __launch_bounds__(256, 7) void leaf_credit_kernel(const Tile* __restrict__ tiles, uint32_t ntiles,
                                                           const uint32_t* __restrict__ members,
                                                           const uint32_t* __restrict__ hdr,
@@ -370,17 +379,30 @@ __global__ __launch_bounds__(256, 7) void leaf_credit_kernel(const Tile* __restr
                                                           const uint32_t* __restrict__ hot,
                                                           const uint32_t* __restrict__ hot_base, uint32_t nhot,
                                                           uint64_t* __restrict__ scratch, uint4* __restrict__ queue,
-                                                          uint32_t* __restrict__ qcount, KT* __restrict__ hotkey) {
+                                                          uint32_t* __restrict__ qcount, KT* __restrict__ hotkey,
+                                                          bool hot_published) {
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kBinomLds];
   __shared__ uint4 qslice[4][kQueueBuf];
-  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
-    KeySrc hs = src;
-    hs.base = hot_base[i];
-    hkey[i] = KT::load(hs, hot[i]);
-    hcnt[i] = 0;
-    if (blockIdx.x == 0) hotkey[i] = hkey[i];   // for the heavy pass
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t stride = gridDim.x * 4u;
+  uint32_t tile = blockIdx.x * 4u + w;
+  Tile t = tile < ntiles ? tiles[tile] : Tile{};   // in flight during the LDS set-up
+  if (hot_published) {
+    // the hot keys at these loads were written by the previous load update
+    for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
+      hkey[i] = hotkey[i];
+      hcnt[i] = 0;
+    }
+  } else {
+    for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
+      KeySrc hs = src;
+      hs.base = hot_base[i];
+      hkey[i] = KT::load(hs, hot[i]);
+      hcnt[i] = 0;
+      if (blockIdx.x == 0) hotkey[i] = hkey[i];   // for the heavy pass
+    }
   }
   const bool lds_binom = nbinom <= kBinomLds;
   if (lds_binom)
@@ -388,50 +410,52 @@ __global__ __launch_bounds__(256, 7) void leaf_credit_kernel(const Tile* __restr
   __syncthreads();
   const uint64_t* bt = lds_binom ? sbinom : binom;
   Sink sink{hcnt, out, 0u, 0ull};
-  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   WaveQueue hq{qslice[w], 0u};
-  const uint32_t stride = gridDim.x * 4u;
-  for (uint32_t tile = blockIdx.x * 4u + w; tile < ntiles; tile += stride) {
-    const Tile t = tiles[tile];
+  for (; tile < ntiles; tile += stride) {
+    if (tile >= blockIdx.x * 4u + w + stride) t = tiles[tile];   // the first one is loaded
     KeySrc ts = src;
     ts.base = t.nbase;
     if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k1, ts, hkey, sink);
-    else tile_lane<KT>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq);
+    else tile_lane<KT, kMasked>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq);
   }
   sink.flush();
   hq.flush(queue, qcount);
   __syncthreads();
-  // hot-node totals into slot row blockIdx % kHotSlots (nonzero ones only)
-  uint64_t* row = scratch + (size_t)(blockIdx.x % kHotSlots) * nhot;
+  // hot-node totals into slot blockIdx % kHotSlots of each node (nonzero ones only)
+  const uint32_t slot = blockIdx.x % kHotSlots;
   for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x)
-    if (hcnt[i]) atomicAdd(reinterpret_cast<unsigned long long*>(row + i), hcnt[i]);
+    if (hcnt[i]) atomicAdd(reinterpret_cast<unsigned long long*>(scratch + (size_t)i * kHotSlots + slot), hcnt[i]);
 }
 
 // Heavy leaves (more than four pivot members below the hold minimum), queued
 // by the leaf-credit kernel as 16-byte entries: one leaf per wavefront, one
 // member per lane, four leaves per batch so their loads overlap.  The hold
 // minimum m is recomputed; the rank of a low member among the low members is
-// counted with wavefront ballots.  No workgroup state: hot members' keys come
-// from the table the leaf pass published, and their credits go to the slot
-// rows (row blockIdx.x % kHotSlots) that the hot reduction adds up.
+// counted with wavefront ballots.  Hot members' keys come from the table the
+// leaf pass published; their credits add up in LDS and reach the nodes' slot
+// entries (slot blockIdx.x % kHotSlots) once per workgroup.  Workgroups past the queue
+// return at once.
 template <class KT>
 __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__ members,
                                                     const uint64_t* __restrict__ binom, uint32_t k1, KeySrc src,
                                                     uint64_t* __restrict__ out, uint32_t nhot,
                                                     uint64_t* __restrict__ scratch, const uint4* __restrict__ queue,
                                                     const uint32_t* __restrict__ qcount,
-                                                    const KT* __restrict__ hotkey) {
+                                                    const KT* __restrict__ hotkey, uint32_t nbinom) {
+  __shared__ KT hkey[kHotMax];
+  __shared__ unsigned long long hcnt[kHotMax];
+  __shared__ uint64_t sbinom[kBinomLds];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t total = *qcount;
   constexpr uint32_t B = 4;
   const uint32_t nw = gridDim.x * 4u;
-  uint64_t* row = scratch + (size_t)(blockIdx.x % kHotSlots) * nhot;
-  // member x of the queued leaf: its group word + 256 (x / 4) + x % 4
-  const uint64_t xoff = (uint64_t)64 * kRowGroup * (lane / kRowGroup) + lane % kRowGroup;
-  for (uint32_t e0 = (blockIdx.x * 4u + w) * B; e0 < total; e0 += nw * B) {
-    uint32_t hq[B], sq[B], jq[B], ra[B], nb[B];
-    KT ka[B];
+  if ((blockIdx.x * 4u) * B >= total) return;   // no entries for this workgroup (uniform)
+  // member x of the queued leaf: its first word + 64 x
+  const uint64_t xoff = (uint64_t)64 * lane;
+  uint32_t hq[B], sq[B], jq[B], ra[B], nb[B];
+  // headers and member ids of the batch of entries e0 .. e0 + B - 1
+  auto fetch = [&](uint32_t e0) {
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
       const uint4 ent = queue[min(e0 + q, total - 1)];
@@ -443,13 +467,29 @@ __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__
       sq[q] = hq[q] + (hd >> 10);
       ra[q] = lane < sq[q] ? members[mw + xoff] : 0u;
     }
+  };
+  const uint32_t first = (blockIdx.x * 4u + w) * B;
+  if (first < total) fetch(first);   // in flight during the LDS set-up
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
+    hkey[i] = hotkey[i];
+    hcnt[i] = 0;
+  }
+  const bool lds_binom = nbinom <= kBinomLds;
+  if (lds_binom)
+    for (uint32_t i = threadIdx.x; i < nbinom; i += blockDim.x) sbinom[i] = binom[i];
+  __syncthreads();
+  const uint64_t* bt = lds_binom ? sbinom : binom;
+  Sink sink{hcnt, out, 0u, 0ull};
+  for (uint32_t e0 = first; e0 < total; e0 += nw * B) {
+    if (e0 != first) fetch(e0);
+    KT ka[B];
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
       KeySrc ts = src;
       ts.base = nb[q];
       KT k = KT::mx();
       if (lane < sq[q]) {
-        if (ra[q] & kHotFlag) k = hotkey[ra[q] & (kHotMax - 1)];
+        if (ra[q] & kHotFlag) k = hkey[ra[q] & (kHotMax - 1)];
         else k = KT::load(ts, ra[q]);
       }
       ka[q] = k;
@@ -473,50 +513,41 @@ __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__
         below += (low && ka[q].rl(tl).lt(ka[q])) ? 1u : 0u;
       }
       if (low && j >= 1) {
-        const uint64_t c = binom[(size_t)(p - 1 - below) * k1 + (j - 1)];
-        if (c) {
-          uint64_t* dst = (ra[q] & kHotFlag) ? row + (ra[q] & (kHotMax - 1)) : out + ra[q];
-          atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)c);
-        }
+        const uint64_t c = bt[(size_t)(p - 1 - below) * k1 + (j - 1)];
+        if (c) sink.add(ra[q], c);
       }
     }
   }
+  sink.flush();
+  __syncthreads();
+  const uint32_t slot = blockIdx.x % kHotSlots;
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x)
+    if (hcnt[i]) atomicAdd(reinterpret_cast<unsigned long long*>(scratch + (size_t)i * kHotSlots + slot), hcnt[i]);
 }
 
-// Hot-node totals: out[hot[i]] += sum over the slot rows b of scratch[b][i],
-// and every slot entry is cleared for the next pass (each is read exactly
-// once).  A block sums 64 hot nodes over a band of kHotRowsPerBlock rows (4
-// waves, each a quarter of the band) and adds its partial sums with one atomic
-// per node.
-constexpr uint32_t kHotRowsPerBlock = 32;
-
-__global__ __launch_bounds__(256) void hot_reduce_kernel(uint64_t* __restrict__ scratch, uint32_t blocks,
+// Hot-node totals: out[hot[i]] += the sum of hot node i's kHotSlots slot
+// entries (contiguous: slot b of node i is scratch[i * kHotSlots + b]), and the
+// entries are cleared for the next pass (each is read exactly once).  One
+// wavefront per hot node; block 0 also empties the heavy-leaf queue.
+__global__ __launch_bounds__(256) void hot_reduce_kernel(uint64_t* __restrict__ scratch,
                                                          const uint32_t* __restrict__ hot, uint32_t nhot,
                                                          uint64_t* __restrict__ out, uint32_t* __restrict__ qcount,
                                                          uint32_t* __restrict__ qlog) {
-  __shared__ uint64_t part[4][64];
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (qlog) *qlog = *qcount;   // timed runs keep the queue size
     *qcount = 0;                 // heavy queue emptied
   }
-  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  const uint32_t i = blockIdx.x * 64u + lane;
-  const uint32_t b0 = blockIdx.y * kHotRowsPerBlock;
-  const uint32_t b1 = min(blocks, b0 + kHotRowsPerBlock);
-  uint64_t s = 0;
-  if (i < nhot) {
-#pragma unroll 4
-    for (uint32_t b = b0 + w; b < b1; b += 4) {
-      s += scratch[(size_t)b * nhot + i];
-      scratch[(size_t)b * nhot + i] = 0;
-    }
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t i = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (i >= nhot) return;
+  uint64_t* e = scratch + (size_t)i * kHotSlots;
+  uint64_t t = 0;
+  for (uint32_t b = lane; b < kHotSlots; b += 64) {
+    t += e[b];
+    e[b] = 0;
   }
-  part[w][lane] = s;
-  __syncthreads();
-  if (w == 0 && i < nhot) {
-    const uint64_t t = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
-    if (t) atomicAdd(reinterpret_cast<unsigned long long*>(out + hot[i]), (unsigned long long)t);
-  }
+  for (int d = 32; d >= 1; d >>= 1) t += shfl_xor64(t, d);
+  if (lane == 0 && t) atomicAdd(reinterpret_cast<unsigned long long*>(out + hot[i]), (unsigned long long)t);
 }
 
 // ----------------------------------------------------------------------------
@@ -570,18 +601,42 @@ __global__ __launch_bounds__(256) void apply64_kernel(uint64_t* __restrict__ r, 
   }
 }
 
+// Key of hot node i (node u of the problem starting at base) at load v into
+// the table the next leaf pass reads: packed (key_mode 0) or (load, id).
+__device__ __forceinline__ void publish_hot_key(uint64_t* __restrict__ table, uint32_t i, uint64_t v, uint32_t u,
+                                                uint32_t base, int key_mode, uint32_t id_bits) {
+  if (key_mode == 0) {
+    table[i] = (v << id_bits) | (u - base);
+  } else {
+    KFull* t = reinterpret_cast<KFull*>(table);
+    t[i] = KFull{v, u};
+  }
+}
+
+// The hot-node key table at the start loads of a run (64-bit loads).
+__global__ __launch_bounds__(256) void hot_keys_kernel(const uint64_t* __restrict__ r, const uint32_t* __restrict__ hot,
+                                                       const uint32_t* __restrict__ hot_base, uint32_t nhot,
+                                                       int key_mode, uint32_t id_bits, uint64_t* __restrict__ table) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nhot) publish_hot_key(table, i, r[hot[i]], hot[i], hot_base[i], key_mode, id_bits);
+}
+
 // The load update fused with the hot-node reduction (64-bit loads): the first
 // ceil(nhot / 4) workgroups give each hot node i a wavefront that sums and
-// clears its kHotSlots slot entries and adds the total to r[hot[i]] with one
-// atomic; the other workgroups apply the credits pairwise, writing only the
-// entries whose credit is nonzero (hot nodes never have one: their credits
-// live in the slot rows), so the two parts never touch the same word.  Also
-// empties the heavy-leaf queue, keeping its size in *qlog for timed runs.
+// clears its kHotSlots slot entries, adds the total to r[hot[i]] and writes
+// the node's new key into the hot-key table of the next leaf pass; the other
+// workgroups apply the credits pairwise, writing only the entries whose credit
+// is nonzero.  Hot nodes never have one (their credits live in slot entries),
+// so the two parts never touch the same word and r[hot[i]] is written by its
+// wavefront alone.  Also empties the heavy-leaf queue, keeping its size in
+// *qlog for timed runs.
 __global__ __launch_bounds__(256) void apply64_hot_kernel(uint64_t* __restrict__ r, uint64_t* __restrict__ delta,
                                                           uint32_t n, uint64_t* __restrict__ scratch,
-                                                          const uint32_t* __restrict__ hot, uint32_t nhot,
+                                                          const uint32_t* __restrict__ hot,
+                                                          const uint32_t* __restrict__ hot_base, uint32_t nhot,
                                                           uint32_t hot_blocks, uint32_t* __restrict__ qcount,
-                                                          uint32_t* __restrict__ qlog) {
+                                                          uint32_t* __restrict__ qlog, int key_mode, uint32_t id_bits,
+                                                          uint64_t* __restrict__ hot_table) {
   const uint32_t lane = threadIdx.x & 63u;
   if (blockIdx.x < hot_blocks) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -590,13 +645,19 @@ __global__ __launch_bounds__(256) void apply64_hot_kernel(uint64_t* __restrict__
     }
     const uint32_t i = blockIdx.x * 4u + (threadIdx.x >> 6);
     if (i >= nhot) return;
+    uint64_t* e = scratch + (size_t)i * kHotSlots;
     uint64_t t = 0;
     for (uint32_t b = lane; b < kHotSlots; b += 64) {
-      t += scratch[(size_t)b * nhot + i];
-      scratch[(size_t)b * nhot + i] = 0;
+      t += e[b];
+      e[b] = 0;
     }
     for (int d = 32; d >= 1; d >>= 1) t += shfl_xor64(t, d);
-    if (lane == 0 && t) atomicAdd(reinterpret_cast<unsigned long long*>(r + hot[i]), (unsigned long long)t);
+    if (lane == 0) {
+      const uint32_t u = hot[i];
+      const uint64_t v = r[u] + t;
+      if (t) r[u] = v;
+      publish_hot_key(hot_table, i, v, u, hot_base[i], key_mode, id_bits);
+    }
     return;
   }
   const uint32_t pairs = n / 2;
@@ -1150,8 +1211,11 @@ struct WsView {
 // mode: 0 packed FW keys, 1 full u64 loads, 2 full u128 loads, 3 extraction ranks
 // ev (nullable): four events recorded before the leaf kernel, after it, after
 // the heavy-leaf kernel and after the hot-node reduction.
+// hot_published: the hot keys at these loads are in the load update's table
+// (64-bit Frank-Wolfe passes); otherwise every workgroup computes them.
 int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& src, uint64_t* out,
-                hipStream_t st, hipEvent_t* ev = nullptr, uint32_t* qlog = nullptr, bool reduce_hot = true) {
+                hipStream_t st, hipEvent_t* ev = nullptr, uint32_t* qlog = nullptr, bool reduce_hot = true,
+                bool hot_published = false) {
   const uint32_t ntiles = (uint32_t)P->tiles.size();
   if (ntiles == 0) return KDSS_OK;
   const uint32_t blocks = P->leaf_blocks;
@@ -1166,14 +1230,20 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   uint4* queue = ws.at<uint4>(P->off_queue);
   uint32_t* qcount = ws.at<uint32_t>(P->off_qcount);
   const uint32_t nbinom = (uint32_t)P->binom.size();
+  const size_t table_off = hot_published ? P->off_hotkey_fw : P->off_hotkey;
   if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
 #define KDSS_LEAF(KT)                                                                                           \
-  leaf_credit_kernel<KT><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src, out,    \
-                                                 hot, hot_base, nhot, scratch, queue, qcount,                    \
-                                                 ws.at<KT>(P->off_hotkey));                                      \
+  if (P->gather == 2)                                                                                            \
+    leaf_credit_kernel<KT, false><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src, \
+                                                          out, hot, hot_base, nhot, scratch, queue, qcount,      \
+                                                          ws.at<KT>(table_off), hot_published);                  \
+  else                                                                                                           \
+    leaf_credit_kernel<KT, true><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src,  \
+                                                         out, hot, hot_base, nhot, scratch, queue, qcount,       \
+                                                         ws.at<KT>(table_off), hot_published);                   \
   if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event record");                                                    \
   heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(members, binom, P->k1, src, out, nhot, scratch, queue,      \
-                                                    qcount, ws.at<KT>(P->off_hotkey))
+                                                    qcount, ws.at<KT>(table_off), nbinom)
   switch (mode) {
     case 0: KDSS_LEAF(KPacked); break;
     case 1: KDSS_LEAF(KFull); break;
@@ -1182,12 +1252,11 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   }
 #undef KDSS_LEAF
   HIP_TRY(hipGetLastError(), "leaf credit launch");
-  // hot-node totals over the slot rows (cleared again); also empties the queue
-  const uint32_t rows = kHotSlots;
-  const dim3 grid(nhot ? (nhot + 63) / 64 : 1, nhot ? (rows + kHotRowsPerBlock - 1) / kHotRowsPerBlock : 1);
+  // hot-node totals over the slot entries (cleared again); also empties the queue
+  const uint32_t grid = std::max(1u, (nhot + 3) / 4);   // a wavefront per hot node; block 0 empties the queue
   if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event record");
   if (reduce_hot) {
-    hot_reduce_kernel<<<grid, 256, 0, st>>>(scratch, rows, hot, nhot, out, qcount, qlog);
+    hot_reduce_kernel<<<grid, 256, 0, st>>>(scratch, hot, nhot, out, qcount, qlog);
     HIP_TRY(hipGetLastError(), "hot reduce launch");
   }
   if (ev) HIP_TRY(hipEventRecord(ev[3], st), "event record");
@@ -1206,13 +1275,13 @@ KeySrc fw_src(const kdss_plan* P, const WsView& ws, const void* d_r) {
 }
 
 // One Frank-Wolfe iteration: credits at r_{t-1} into delta (hot nodes' into the
-// slot rows), then r_t = r_{t-1} + delta.  With 64-bit loads the hot-node
+// slot entries), then r_t = r_{t-1} + delta.  With 64-bit loads the hot-node
 // reduction is part of the update kernel.
 int launch_fw_step(const kdss_plan* P, const WsView& ws, void* d_r, hipStream_t st, hipEvent_t* ev,
                    uint32_t* qlog) {
   uint64_t* delta = ws.at<uint64_t>(P->off_delta);
   const bool fused = P->width == 64 && !P->tiles.empty();
-  int rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev, qlog, !fused);
+  int rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev, qlog, !fused, fused);
   if (rc) return rc;
   if (P->width == 128) {
     apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
@@ -1220,8 +1289,9 @@ int launch_fw_step(const kdss_plan* P, const WsView& ws, void* d_r, hipStream_t 
     const uint32_t nhot = (uint32_t)P->hot.size();
     const uint32_t hot_blocks = std::max(1u, (nhot + 3) / 4);   // block 0 also empties the queue
     apply64_hot_kernel<<<hot_blocks + grid_for(P->n / 2 + 1), 256, 0, st>>>(
-        static_cast<uint64_t*>(d_r), delta, P->n, ws.at<uint64_t>(P->off_scratch), ws.at<uint32_t>(P->off_hot), nhot,
-        hot_blocks, ws.at<uint32_t>(P->off_qcount), qlog);
+        static_cast<uint64_t*>(d_r), delta, P->n, ws.at<uint64_t>(P->off_scratch), ws.at<uint32_t>(P->off_hot),
+        ws.at<uint32_t>(P->off_hot_base), nhot, hot_blocks, ws.at<uint32_t>(P->off_qcount), qlog, P->key_mode,
+        P->id_bits, ws.at<uint64_t>(P->off_hotkey_fw));
   } else {
     launch_apply64(static_cast<uint64_t*>(d_r), delta, P->n, st);
   }
@@ -1372,7 +1442,7 @@ int ensure_graph(kdss_plan* P, const WsView& ws, void* d_r) {
   return KDSS_OK;
 }
 
-// The hot-node slot rows are zero between passes; entry points clear them
+// The hot-node slot entries are zero between passes; entry points clear them
 // again (with a kernel, not a memset) in case an earlier pass was cut short.
 void clear_hot_rows(const kdss_plan* P, const WsView& ws, hipStream_t st) {
   const size_t count = (size_t)kHotSlots * P->hot.size();
@@ -1387,6 +1457,13 @@ int start_run(kdss_plan* P, const WsView& ws, const uint64_t* d_r0, void* d_r, u
   init_loads_kernel<<<grid_for(P->n), 256, 0, st>>>(d_r0, static_cast<uint64_t*>(d_r), ws.at<uint64_t>(P->off_delta),
                                                     P->n, P->width == 128 ? 1 : 0, dres);
   HIP_TRY(hipGetLastError(), "init launch");
+  const uint32_t nhot = (uint32_t)P->hot.size();
+  if (P->width == 64 && !P->tiles.empty() && nhot) {   // the iterations' leaf passes read the hot keys from a table
+    hot_keys_kernel<<<(nhot + 255) / 256, 256, 0, st>>>(static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot),
+                                                         ws.at<uint32_t>(P->off_hot_base), nhot, P->key_mode,
+                                                         P->id_bits, ws.at<uint64_t>(P->off_hotkey_fw));
+    HIP_TRY(hipGetLastError(), "hot keys launch");
+  }
   if (P->opts.time_kernels) {
     while (P->events.size() < 5ull * T) {
       hipEvent_t e;
@@ -1471,7 +1548,7 @@ int kdss_plan_upload(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream) {
   }
   HIP_TRY(hipMemcpyAsync(ws.at<uint64_t>(P->off_nodeoff), P->node_off.data(), P->node_off.size() * 8,
                          hipMemcpyHostToDevice, st), "upload node offsets");
-  // the heavy-leaf queue and the hot-node slot rows start empty; every leaf
+  // the heavy-leaf queue and the hot-node slot entries start empty; every leaf
   // pass leaves them empty again
   HIP_TRY(hipMemsetAsync(ws.at<uint32_t>(P->off_qcount), 0, 64, st), "queue reset");
   if (!P->hot.empty())
@@ -1632,36 +1709,64 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "event create");
   HIP_TRY(hipEventCreate(&e1), "event create");
-  const uint32_t leaf_c[] = {512, 1024, 1536, 2048};
+  const uint32_t leaf_c[] = {512, 1024, 1536, 1792, 2048};
   const uint32_t heavy_c[] = {128, 256, 512, 1024};
   std::memset(out, 0, sizeof(*out));
   out->best_ms = 1e30;
+  // per-iteration time of the plan's current launch configuration
+  auto time_config = [&](float* ms_per_iter) -> int {
+    int r = start_run(P, ws, nullptr, d_r, warm + iters, st);
+    for (uint32_t t = 1; !r && t <= warm; ++t) r = iterate(P, ws, d_r, t, st);
+    if (!r && hipEventRecord(e0, st) != hipSuccess) r = fail(KDSS_EHIP, "event record");
+    for (uint32_t t = warm + 1; !r && t <= warm + iters; ++t) r = iterate(P, ws, d_r, t, st);
+    if (!r && hipEventRecord(e1, st) != hipSuccess) r = fail(KDSS_EHIP, "event record");
+    float ms = 0.f;
+    if (!r && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      r = fail(KDSS_EHIP, "event timing");
+    *ms_per_iter = ms / iters;
+    return r;
+  };
   for (uint32_t lb : leaf_c) {
     for (uint32_t hb : heavy_c) {
       P->leaf_blocks = lb;
       P->heavy_blocks = hb;
-      rc = start_run(P, ws, nullptr, d_r, warm + iters, st);
-      for (uint32_t t = 1; !rc && t <= warm; ++t) rc = iterate(P, ws, d_r, t, st);
-      if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = fail(KDSS_EHIP, "event record");
-      for (uint32_t t = warm + 1; !rc && t <= warm + iters; ++t) rc = iterate(P, ws, d_r, t, st);
-      if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = fail(KDSS_EHIP, "event record");
       float ms = 0.f;
-      if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-        rc = fail(KDSS_EHIP, "event timing");
+      rc = time_config(&ms);
       if (rc) break;
       const uint32_t idx = out->tried++;
-      if (idx < 16) {
+      if (idx < 32) {
         out->leaf_blocks[idx] = lb;
         out->heavy_blocks[idx] = hb;
-        out->ms[idx] = ms / iters;
+        out->ms[idx] = ms;
       }
-      if (ms / iters < out->best_ms) {
-        out->best_ms = ms / iters;
+      if (ms < out->best_ms) {
+        out->best_ms = ms;
         out->best_leaf_blocks = lb;
         out->best_heavy_blocks = hb;
       }
     }
     if (rc) break;
+  }
+  out->best_gather = P->gather;
+  if (!rc) {
+    out->gather_ms[P->gather - 1] = out->best_ms;
+    if (saved.gather == 0) {   // the mode was left to the library: try the other one at the best sizes
+      const int current = P->gather;
+      P->leaf_blocks = out->best_leaf_blocks;
+      P->heavy_blocks = out->best_heavy_blocks;
+      P->gather = 3 - current;
+      float ms = 0.f;
+      rc = time_config(&ms);
+      if (!rc) {
+        ++out->tried;
+        out->gather_ms[P->gather - 1] = ms;
+        if (ms < out->best_ms) {
+          out->best_ms = ms;
+          out->best_gather = P->gather;
+        }
+      }
+      P->gather = out->best_gather;
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

@@ -172,6 +172,29 @@ def test_plan_layout_and_errors():
     assert kdss.Plan(t, 10, r0_max=2**60).stats().key_mode == 1
 
 
+def test_gather_mode_option():
+    g = synth.chung_lu(3000, 30000, 2.2, seed=6, planted=30)
+    t = kdss.Tree(g, 4)
+    s = kdss.Plan(t, 10).stats()
+    assert 0 < s.hot_nodes <= 512 and 0.0 < s.hot_share <= 1.0
+    # left to the library: masked gathers once hot nodes hold half the occurrences
+    assert s.gather == (1 if s.hot_share >= 0.5 else 2)
+    assert kdss.Plan(t, 10, gather=1).stats().gather == 1
+    assert kdss.Plan(t, 10, gather=2).stats().gather == 2
+    for bad in (-1, 3):
+        with pytest.raises(kdss.KdssError) as e:
+            kdss.Plan(t, 10, gather=bad)
+        assert e.value.status == kdss.EINVAL
+    # hot nodes: the (at most 512) nodes with the most member occurrences, at
+    # least 32 each; the share is their part of all occurrences
+    _, _, mem = t.export()
+    occ = np.bincount(mem, minlength=g.n)
+    cand = np.flatnonzero(occ >= 32)
+    cand = cand[np.lexsort((cand, -occ[cand]))][:512]
+    assert s.hot_nodes == cand.size
+    assert abs(s.hot_share - occ[cand].sum() / occ.sum()) < 1e-12
+
+
 def test_run_rejects_bad_arguments_before_device_work():
     g = synth.complete_graph(8)
     t = kdss.Tree(g, 3)

@@ -33,10 +33,12 @@ def _problems(count, seed0):
     return probs
 
 
-def run_batch(K, probs, T, r0s=None, use_graph=False, tune=False):
+def run_batch(K, probs, T, r0s=None, use_graph=False, tune=False, gather=0):
     trees = [K.Tree(g, k) for g, k in probs]
     r0_max = 0 if r0s is None else int(max(int(np.max(x)) if x.size else 0 for x in r0s))
-    b = K.Batch(trees, T, r0_max=r0_max, use_graph=use_graph)
+    b = K.Batch(trees, T, r0_max=r0_max, use_graph=use_graph, gather=gather)
+    if gather:
+        assert b.stats().gather == gather
     ws = b.alloc_workspace()
     b.upload(ws)
     r = torch.empty(b.n, dtype=torch.int64, device="cuda")
@@ -66,10 +68,11 @@ def same(a, ref):
                                                                    ref["c_k"])
 
 
-def test_batch_matches_oracle(K, oracle_mod):
+@pytest.mark.parametrize("gather", [1, 2])
+def test_batch_matches_oracle(K, oracle_mod, gather):
     probs = _problems(18, 300)
-    print("batch of 18 problems, T=15", flush=True)
-    out = run_batch(K, probs, 15)
+    print(f"batch of 18 problems, T=15, gather mode {gather}", flush=True)
+    out = run_batch(K, probs, 15, gather=gather)
     for (g, k), got in zip(probs, out):
         same(got, oracle_mod.solve(g.n, g.row_ptr, g.col, k, 15))
 

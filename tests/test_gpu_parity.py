@@ -129,6 +129,24 @@ def test_full_keys_and_wide_loads(K, oracle_mod):
     assert_same(sol, ref(oracle_mod, g, 3, 5), 5)
 
 
+@pytest.mark.parametrize("gather", [1, 2])
+def test_gather_modes(K, oracle_mod, gather):
+    """Both key-gather modes of the leaf pass (masked: non-hot members inside
+    the leaf only; full: every row), with packed keys, (load, id) keys and
+    128-bit loads, from cold and tied start loads."""
+    g = synth.chung_lu(4000, 30000, 2.2, seed=21, planted=28)
+    rs = synth.Stream(21, 72)
+    ties = (rs.u64(g.n) % np.uint64(3)).astype(np.uint64)
+    high = np.uint64(2**62) + (rs.u64(g.n) % np.uint64(3)).astype(np.uint64)
+    for k, T, r0, width, key_mode in ((4, 25, None, 0, 0), (5, 9, ties, 0, 0), (4, 7, high, 0, 1),
+                                      (3, 5, None, 128, 1)):
+        print(f"gather {gather} k={k} T={T} width={width}", flush=True)
+        sol = K.solve(g, k, T, r0=r0, width=width, gather=gather)
+        assert sol.plan_stats.gather == gather and sol.plan_stats.key_mode == key_mode
+        assert sol.plan_stats.hot_nodes > 0
+        assert_same(sol, ref(oracle_mod, g, k, T, r0=r0), T, f"gather={gather} k={k}")
+
+
 def test_leaf_credit_with_forced_ties(K, oracle_mod):
     """One credit pass at arbitrary loads with many equal values (ties by id)."""
     from paper_2403_05775_amd import kdss
