@@ -518,7 +518,7 @@ def main():
     reduce_us = 1000.0 * tm.reduce_ms / nl
     heavy_per_iter = tm.heavy_leaves / nl
     apply_us = 1000.0 * tm.apply_ms / max(1, tm.apply_launches)
-    pass_us = leaf_us + heavy_us + reduce_us
+    pass_us = leaf_us + heavy_us + (reduce_us if ps.width == 128 else 0.0)
     del ws2
     # algorithmic bytes of one leaf-credit launch: the leaf stream (4 B per member,
     # 4 B per leaf header) and one 8-byte key per node
@@ -550,7 +550,9 @@ def main():
         "sct_build_s": ts.build_seconds,
         "result": {"size": res.size, "dens_num": res.dens_num.value, "ub_num": res.ub_num.value,
                    "density": res.density, "upper_bound": res.upper_bound},
-        "kernel_us": {"leaf_credit": leaf_us, "heavy_leaf": heavy_us, "hot_reduce": reduce_us, "apply": apply_us},
+        # with 64-bit loads the hot-node reduction is part of the load update
+        "kernel_us": {"leaf_credit": leaf_us, "heavy_leaf": heavy_us,
+                      "hot_reduce": reduce_us if ps.width == 128 else None, "apply": apply_us},
         "heavy_leaves_per_iteration": heavy_per_iter,
         "launch": ({"leaf_blocks": tune.best_leaf_blocks, "heavy_blocks": tune.best_heavy_blocks,
                     "gather": tune.best_gather, "us_per_iter": tune.best_ms * 1000,
@@ -559,7 +561,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "leaf_credit_kernel<KPacked>", "bytes_per_launch": leaf_bytes},
-        "credit_pass": {"kernels": "leaf_credit + heavy_leaf + hot_reduce", "us": pass_us,
+        "credit_pass": {"kernels": "leaf_credit + heavy_leaf" + (" + hot_reduce" if ps.width == 128 else ""),
+                        "us": pass_us,
                         "achieved": leaf_bytes / (pass_us * 1e-6) / 1e9,
                         "frac": leaf_bytes / (pass_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
         "cpu_baseline": None,
