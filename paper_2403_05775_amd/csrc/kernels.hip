@@ -442,13 +442,14 @@ __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__
                                                     uint64_t* __restrict__ scratch, const uint4* __restrict__ queue,
                                                     const uint32_t* __restrict__ qcount,
                                                     const KT* __restrict__ hotkey, uint32_t nbinom) {
+  constexpr uint32_t B = 4;
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kBinomLds];
+  __shared__ KT lowk[4][B][64];   // per wavefront and queued leaf: its low members' keys, compacted
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t total = *qcount;
-  constexpr uint32_t B = 4;
   const uint32_t nw = gridDim.x * 4u;
   if ((blockIdx.x * 4u) * B >= total) return;   // no entries for this workgroup (uniform)
   // member x of the queued leaf: its first word + 64 x
@@ -482,41 +483,60 @@ __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__
   Sink sink{hcnt, out, 0u, 0ull};
   for (uint32_t e0 = first; e0 < total; e0 += nw * B) {
     if (e0 != first) fetch(e0);
+    // every lane gathers (a hot member's hot index and a missing member's 0
+    // are node ids too), so the four gathers are in flight together; the LDS
+    // key, or the maximum past the leaf, is selected afterwards
     KT ka[B];
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
       KeySrc ts = src;
       ts.base = nb[q];
-      KT k = KT::mx();
-      if (lane < sq[q]) {
-        if (ra[q] & kHotFlag) k = hkey[ra[q] & (kHotMax - 1)];
-        else k = KT::load(ts, ra[q]);
-      }
-      ka[q] = k;
+      ka[q] = KT::load(ts, ra[q] & ~kHotFlag);
     }
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
-      if (e0 + q >= total) break;
-      const uint32_t h = hq[q], s = sq[q], p = s - h, j = jq[q];
-      KT kh = lane < h ? ka[q] : KT::mx();
+      ka[q] = KT::pick((ra[q] & kHotFlag) != 0, hkey[ra[q] & (kHotMax - 1)], ka[q]);
+      ka[q] = KT::pick(lane < sq[q], ka[q], KT::mx());
+    }
+    // the hold minimum m of each leaf: the hold members are its first h <= 31
+    // members, so lanes 0..31 hold them all; the B reductions are interleaved
+    KT kh[B];
 #pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) {
-        const KT o = kh.sx(d);
-        if (o.lt(kh)) kh = o;
+    for (uint32_t q = 0; q < B; ++q) kh[q] = KT::pick(lane < hq[q], ka[q], KT::mx());
+#pragma unroll
+    for (int d = 16; d >= 1; d >>= 1) {
+#pragma unroll
+      for (uint32_t q = 0; q < B; ++q) {
+        const KT o = kh[q].sx(d);
+        kh[q] = KT::pick(o.lt(kh[q]), o, kh[q]);
       }
-      const bool low = lane < s && lane >= h && ka[q].lt(kh);
-      uint64_t bm = __ballot(low);
+    }
+    // the low members (pivot members below m) are compacted into LDS, and each
+    // counts the smaller ones with broadcast reads
+    bool low[B];
+    uint32_t nlow[B];
+#pragma unroll
+    for (uint32_t q = 0; q < B; ++q) {
+      const KT m = kh[q].rl(0);
+      low[q] = lane < sq[q] && lane >= hq[q] && ka[q].lt(m);
+      const uint64_t bm = __ballot(low[q]);
+      nlow[q] = (uint32_t)__popcll(bm);
+      if (low[q]) lowk[w][q][__popcll(bm & ((1ull << lane) - 1ull))] = ka[q];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (uint32_t q = 0; q < B; ++q) {
+      if (e0 + q >= total) break;
       uint32_t below = 0;
-      while (bm) {
-        const int tl = __ffsll((unsigned long long)bm) - 1;
-        bm &= bm - 1;
-        below += (low && ka[q].rl(tl).lt(ka[q])) ? 1u : 0u;
-      }
-      if (low && j >= 1) {
+#pragma unroll 4
+      for (uint32_t i = 0; i < nlow[q]; ++i) below += lowk[w][q][i].lt(ka[q]) ? 1u : 0u;
+      const uint32_t p = sq[q] - hq[q], j = jq[q];
+      if (low[q] && j >= 1) {
         const uint64_t c = bt[(size_t)(p - 1 - below) * k1 + (j - 1)];
         if (c) sink.add(ra[q], c);
       }
     }
+    wave_lds_sync();   // the slices are rewritten by the next batch
   }
   sink.flush();
   __syncthreads();
