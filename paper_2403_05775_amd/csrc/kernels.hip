@@ -177,26 +177,53 @@ __device__ __forceinline__ KT member_key_nb(const KeySrc& src, const KT* hkey, u
 // members below u), and a(m) = p - (number of low members).
 // ----------------------------------------------------------------------------
 
+// Data-parallel-primitive lane moves (DPP controls of the CDNA ISA).  Lanes
+// whose source is outside the row (or outside the wavefront) read 0; rows
+// left out by the row mask keep 0.
+constexpr int kDppRowShr = 0x110;     // + n: lane l reads lane l - n of its row of 16
+constexpr int kDppWaveShl1 = 0x130;   // lane l reads lane l + 1
+constexpr int kDppWaveShr1 = 0x138;   // lane l reads lane l - 1
+constexpr int kDppRowBcast15 = 0x142; // rows 1 and 3 (row mask 0xA) read lane 15 of the row before
+constexpr int kDppRowBcast31 = 0x143; // rows 2 and 3 (row mask 0xC) read lane 31
+
+template <int kCtrl, int kRowMask = 0xF>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xF, true);
+}
+
+// One step of a segmented inclusive scan: (vu, fu) is the partial sum and
+// head flag of the lane the step reads (0, 0 where there is none).
+template <int kCtrl, int kRowMask = 0xF>
+__device__ __forceinline__ void seg_scan_step(uint64_t& v, uint32_t& f) {
+  const uint32_t lo = dpp32<kCtrl, kRowMask>((uint32_t)v);
+  const uint32_t hi = dpp32<kCtrl, kRowMask>((uint32_t)(v >> 32));
+  const uint32_t fu = dpp32<kCtrl, kRowMask>(f);
+  if (!f) {
+    v += ((uint64_t)hi << 32) | lo;
+    f |= fu;
+  }
+}
+
 // Adds (key, val) of every lane to the sink after combining runs of adjacent
 // lanes with the same key (a segmented inclusive scan over the wavefront): only
 // the last lane of a run adds the run's total.  Lanes with val == 0 add nothing.
+// The scan runs within rows of 16 lanes (shifts by 1, 2, 4, 8), then carries
+// each row's open segment into the rows after it (the last lane of row 0 into
+// rows 1 and 3, then the last lane of row 1 into rows 2 and 3), all as DPP
+// lane moves.  Every lane of the wavefront must be active.
 __device__ __forceinline__ void combine_add(Sink& sink, uint32_t key, uint64_t val) {
-  const int lane = (int)(threadIdx.x & 63u);
-  const uint32_t kp = shfl32(key, lane > 0 ? lane - 1 : 0);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t kp = dpp32<kDppWaveShr1>(key);
   const uint32_t head = (lane == 0 || kp != key) ? 1u : 0u;
   uint32_t f = head;
   uint64_t v = val;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int src = lane >= d ? lane - d : lane;
-    const uint64_t vu = shfl64(v, src);
-    const uint32_t fu = shfl32(f, src);
-    if (lane >= d && !f) {
-      v += vu;
-      f |= fu;
-    }
-  }
-  const uint32_t next_head = shfl32(head, lane < 63 ? lane + 1 : 63);
+  seg_scan_step<kDppRowShr + 1>(v, f);
+  seg_scan_step<kDppRowShr + 2>(v, f);
+  seg_scan_step<kDppRowShr + 4>(v, f);
+  seg_scan_step<kDppRowShr + 8>(v, f);
+  seg_scan_step<kDppRowBcast15, 0xA>(v, f);
+  seg_scan_step<kDppRowBcast31, 0xC>(v, f);
+  const uint32_t next_head = dpp32<kDppWaveShl1>(head);
   const bool run_end = lane == 63 || next_head;
   if (run_end && v) sink.add(key, v);
 }
@@ -419,8 +446,22 @@ __global__ __launch_bounds__(256, 7) void leaf_credit_kernel(const Tile* __restr
     else tile_lane<KT, kMasked>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq);
   }
   sink.flush();
-  hq.flush(queue, qcount);
+  // the heavy entries the four wavefronts still stage: one counter atomic for
+  // the workgroup (thousands of wavefronts contending for one counter cost
+  // more than the barrier)
+  __shared__ uint32_t qn[4], qbase;
+  if ((threadIdx.x & 63u) == 0) qn[w] = hq.n;
   __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t staged = qn[0] + qn[1] + qn[2] + qn[3];
+    qbase = staged ? atomicAdd(qcount, staged) : 0u;
+  }
+  __syncthreads();
+  {
+    uint32_t at = qbase;
+    for (uint32_t x = 0; x < w; ++x) at += qn[x];
+    for (uint32_t i = threadIdx.x & 63u; i < hq.n; i += 64) queue[at + i] = hq.buf[i];
+  }
   // hot-node totals into slot blockIdx % kHotSlots of each node (nonzero ones only)
   const uint32_t slot = blockIdx.x % kHotSlots;
   for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x)
