@@ -284,13 +284,24 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
   // members, so m is final when the first pivot member is compared)
   KT l0 = KT::mx(), l1 = KT::mx(), l2 = KT::mx(), l3 = KT::mx();
   uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+  // rows past the tile repeat its last; each batch's rows are requested
+  // during the batch before, right after that batch's key gathers, so waiting
+  // for those keys leaves the rows in flight
+  uint32_t nxt[U];
+#pragma unroll
+  for (uint32_t u = 0; u < U; ++u) nxt[u] = col[(size_t)min(u, smax - 1) * 64];
   for (uint32_t x0 = 0; x0 < smax; x0 += U) {
     uint32_t raw[U];
     KT key[U];
 #pragma unroll
-    for (uint32_t u = 0; u < U; ++u) raw[u] = col[(size_t)min(x0 + u, smax - 1) * 64];   // rows past the tile repeat its last
+    for (uint32_t u = 0; u < U; ++u) raw[u] = nxt[u];
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) key[u] = member_key_nb<KT, kMasked>(src, hkey, raw[u], x0 + u < s);
+    __builtin_amdgcn_sched_barrier(0);
+    if (x0 + U < smax) {
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) nxt[u] = col[(size_t)min(x0 + U + u, smax - 1) * 64];
+    }
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) {
       const uint32_t x = x0 + u;
