@@ -32,6 +32,11 @@ WORKLOADS = {
     "chung-lu-1m": dict(kind="chung_lu", n=1_000_000, m=10_000_000, beta=2.5, seed=0, planted=40,
                         planted_p=0.9, k=5, T=200),
     "er-200": dict(kind="er", n=200, p=0.08, seed=0, planted=12, k=3, T=64),
+    # the paper's own update rule (PBUpdate, synchronous over the tree's pairs)
+    # on the default workload's graph; the oracle's synchronous pass samples 5
+    # iterations
+    "pbupdate-1m": dict(kind="chung_lu", n=1_000_000, m=10_000_000, beta=2.5, seed=0, planted=40,
+                        planted_p=0.9, k=5, T=200, update=1, cpu_iters=5),
     # 512 Chung-Lu graphs (n in [1k, 50k], average degree 8-40, exponent 2.2-2.8,
     # seeds 1000 + g), each at k = 3, 4, 6, 8: 2048 problems in one plan
     "batch-512": dict(kind="batch", graphs=512, ks=(3, 4, 6, 8), T=64),
@@ -314,6 +319,19 @@ def counter_traffic(workload, launch_bytes):
     return c.get("hbm_bytes_per_launch")
 
 
+def cpu_baseline_pb(g, w, tree, L, sample_T):
+    """The CPU oracle's synchronous PBUpdate over the same pairs (the tree's
+    leaves, exported), sample_T iterations."""
+    from oracle import oracle as O
+    O.build()
+    h, p, mem = tree.export()
+    res = O.pb_run(g.n, h, p, mem, w["k"], sample_T, True)
+    secs = res["seconds"]
+    return dict(value=L * sample_T / secs, unit="leaf-updates/s", cores=1, kind="oracle",
+                sample=f"same graph, k and pairs, {sample_T} synchronous PBUpdate iterations ({secs:.2f} s), "
+                       f"one thread", seconds=secs)
+
+
 def cpu_baseline(g, w, L, sample_T):
     """The CPU oracle (clique listing + synchronous Frank-Wolfe) on the same graph,
     sample_T iterations; listing excluded like the tree build on the GPU side."""
@@ -477,7 +495,8 @@ def main():
     log(f"tree k={w['k']}: leaves={ts.leaves} members={ts.members} s_max={ts.s_max} "
         f"c_k={ts.c_k.value} build={ts.build_seconds:.2f} s")
     T = w["T"]
-    plan = kdss.Plan(tree, T, use_graph=args.graph)
+    update = w.get("update", 0)
+    plan = kdss.Plan(tree, T, use_graph=args.graph, update=update)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
@@ -488,7 +507,7 @@ def main():
     tune = tune_plan(plan, ws, r, T, args)
     ps = plan.stats()
     # the same launch configuration with hipEvents around every launch
-    tplan = kdss.Plan(tree, T, time_kernels=True, gather=ps.gather)
+    tplan = kdss.Plan(tree, T, time_kernels=True, gather=ps.gather, update=update)
     if tune is not None:
         tplan.set_launch(tune.best_leaf_blocks, tune.best_heavy_blocks)
 
@@ -545,7 +564,8 @@ def main():
         "config": {"workload": f"{args.workload}: {g.name}, k={w['k']}, T={T}", "n": g.n, "m": g.m,
                    "k": w["k"], "T": T, "leaves": ts.leaves, "members": ts.members, "c_k": ts.c_k.value,
                    "parallelism": "single GPU", "hip_graph": bool(args.graph),
-                   "gather": "masked" if ps.gather == 1 else "full", "hot_share": round(ps.hot_share, 4)},
+                   "gather": "masked" if ps.gather == 1 else "full", "hot_share": round(ps.hot_share, 4),
+                   "update": "PBUpdate (synchronous)" if update else "Frank-Wolfe"},
         "hbm_gbps_algorithmic": step_bytes / (ms_per_step / 1000.0) / 1e9,
         "sct_build_s": ts.build_seconds,
         "result": {"size": res.size, "dens_num": res.dens_num.value, "ub_num": res.ub_num.value,
@@ -560,7 +580,8 @@ def main():
                    if tune is not None else "defaults"),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "leaf_credit_kernel<KPacked>", "bytes_per_launch": leaf_bytes},
+                     "kernel": "pb_kernel" if update else "leaf_credit_kernel<KPacked>",
+                     "bytes_per_launch": leaf_bytes},
         "credit_pass": {"kernels": "leaf_credit + heavy_leaf" + (" + hot_reduce" if ps.width == 128 else ""),
                         "us": pass_us,
                         "achieved": leaf_bytes / (pass_us * 1e-6) / 1e9,
@@ -569,7 +590,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(g, w, ts.leaves, w.get("cpu_iters", args.cpu_sample_iters))
+        if update:
+            out["cpu_baseline"] = cpu_baseline_pb(g, w, tree, ts.leaves, w.get("cpu_iters", args.cpu_sample_iters))
+        else:
+            out["cpu_baseline"] = cpu_baseline(g, w, ts.leaves, w.get("cpu_iters", args.cpu_sample_iters))
     print(json.dumps(out))
 
 

@@ -93,6 +93,20 @@ typedef struct {
                                     that are not hot are gathered;
                                  2: full: every row's key is gathered (no
                                     branch, more loads in flight)              */
+    int update;               /* the per-iteration update:
+                                 0: Frank-Wolfe (Algorithm 1): every k-clique
+                                    credits its minimum-load member;
+                                 1: PBUpdate (Algorithm 3), synchronous: every
+                                    pair of the tree water-fills its C(p, k - h)
+                                    cliques onto its lowest-load members, up to
+                                    each member's clique count in the pair, all
+                                    pairs reading r_{t-1}; a remainder smaller
+                                    than the lowest plateau goes to its lowest
+                                    ids.  The paper applies the pairs one after
+                                    another; this variant sums them, so it does
+                                    not depend on the pair order.  64-bit loads
+                                    only.  The result's upper bound is certified
+                                    only for update 0.                         */
 } kdss_opts;
 
 typedef struct {              /* accumulated by kdss_run when time_kernels = 1  */
@@ -117,6 +131,7 @@ typedef struct {
     uint64_t leaves[5];
     uint64_t members[5];
     int gather;               /* gather mode of later runs: 1 masked, 2 full   */
+    int update;               /* 0 Frank-Wolfe, 1 PBUpdate (synchronous)       */
     uint32_t hot_nodes;       /* nodes whose keys and credits live in LDS       */
     double hot_share;         /* their share of all member occurrences          */
 } kdss_plan_stats;

@@ -538,3 +538,197 @@ int kor_credits(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k,
 }
 
 int kor_threads(int threads) { return set_threads(threads); }
+
+/* Extraction alone on given loads r (u64): the order pi, i* and K_{i*}. */
+int kor_extract(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k, const uint64_t *r,
+                int threads, uint32_t *order_out, uint32_t *size_out, uint64_t *dens_out) {
+    if (k < 2 || !row_ptr || !r || !order_out || !size_out || !dens_out) return KOR_EINVAL;
+    graph_t g = {n, row_ptr, col};
+    run_t R = {&g, k, 0, NULL, 0, max_degree(&g), set_threads(threads)};
+    if (R.nthreads > 1024) R.nthreads = 1024;
+    u128 *rr = (u128 *)malloc(sizeof(u128) * (size_t)(n ? n : 1));
+    uint32_t *pos = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    uint64_t *hist_t[1024];
+    int err = (rr && pos) ? KOR_OK : KOR_ENOMEM;
+    int made = 0;
+    for (; !err && made < R.nthreads; ++made) {
+        hist_t[made] = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+        if (!hist_t[made]) err = KOR_ENOMEM;
+    }
+    if (!err) {
+        for (uint32_t u = 0; u < n; ++u) rr[u] = r[u];
+        err = extract(&R, rr, order_out, size_out, dens_out, hist_t, pos);
+    }
+    for (int t = 0; t < made; ++t) free(hist_t[t]);
+    free(rr);
+    free(pos);
+    return err;
+}
+
+/*
+ * ---- PBUpdate: the paper's per-pair update (Algorithm 3) ----
+ *
+ * Input is a set of pairs (V_h, V_p) of a succinct clique tree (Sec. 3.1):
+ * the k-cliques of a pair are V_h plus any (k - h)-subset of V_p.  This oracle
+ * does not build the tree; it takes the pairs as given (the test suite checks
+ * separately that the pairs it uses partition C_k(V)).
+ *
+ * One pair, following the algorithm's steps and notation:
+ *   n_C = C(p, k - h) cliques to allocate; caps up(u) = C(p, k - h) for
+ *   u in V_h and C(p - 1, k - h - 1) for u in V_p (the number of the pair's
+ *   cliques that contain u);
+ *   V_1 .. V_s = the nodes of the pair grouped by equal load, loads
+ *   r_1 < .. < r_s;
+ *   for i = 1, 2, ..: gap = r_{i+1} - r_i (infinite for the last plateau);
+ *     while cliques remain, gap > 0 and V_i is not empty:
+ *       w = min(min over V_i of up(u), gap, floor(n_C / |V_i|));
+ *       w > 0: every u in V_i gains w (up(u) -= w), n_C -= w |V_i|, gap -= w;
+ *       w = 0: n_C < |V_i|: n_C nodes of V_i gain 1 each, n_C = 0;
+ *       nodes with up(u) = 0 leave V_i;
+ *     what is left of V_i joins V_{i+1}.
+ * The paper picks the nodes of the last step uniformly at random; here they
+ * are the n_C nodes of V_i with the lowest ids (a deterministic reading).
+ *
+ * Two ways to apply it over the pairs of one iteration:
+ *   sequential (the paper's Algorithm 2 loop): pairs in the given order, each
+ *     reading the loads the pairs before it left;
+ *   synchronous: every pair reads r_{t-1}; the increments of all pairs are
+ *     summed and added at the end of the iteration (order independent).
+ * Loads are u128 inside; the u64 outputs report overflow as an error.
+ */
+static u128 binom_u128(uint64_t a, uint64_t b) {
+    if (b > a) return 0;
+    if (b > a - b) b = a - b;
+    u128 c = 1;
+    for (uint64_t i = 1; i <= b; ++i) c = c * (a - b + i) / i;   /* exact at every step */
+    return c;
+}
+
+typedef struct { uint32_t u; u128 cur, up; int alive; } pb_node;
+
+static int cmp_pb_load_id(const void *a, const void *b) {
+    const pb_node *x = (const pb_node *)a, *y = (const pb_node *)b;
+    if (x->cur != y->cur) return x->cur < y->cur ? -1 : 1;
+    return x->u < y->u ? -1 : (x->u > y->u ? 1 : 0);
+}
+
+static int cmp_u32(const void *a, const void *b) {
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* One pair: reads loads r, adds the pair's allocation into add (may equal r). */
+static int pb_pair(const uint32_t *mem, uint32_t h, uint32_t p, int k, const u128 *r, u128 *add) {
+    if ((int)h > k || (uint32_t)(k - (int)h) > p) return KOR_OK;   /* the pair holds no k-clique */
+    uint32_t j = (uint32_t)k - h, sz = h + p;
+    if (j == 0 && p > 0) return KOR_EINVAL;   /* k-pruned trees emit (H, {}) once |H| = k */
+    u128 nC = binom_u128(p, j);
+    pb_node *V = (pb_node *)malloc(sizeof(pb_node) * (size_t)sz);
+    uint32_t *plat = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(sz + 1));
+    uint32_t *pick = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)sz);
+    if (!V || !plat || !pick) { free(V); free(plat); free(pick); return KOR_ENOMEM; }
+    for (uint32_t x = 0; x < sz; ++x) {
+        V[x].u = mem[x];
+        V[x].cur = r[mem[x]];
+        V[x].up = x < h ? binom_u128(p, j) : binom_u128(p - 1, j - 1);
+        V[x].alive = 1;
+    }
+    /* plateaus: V sorted by (load, id); plateau q covers V[plat[q] .. plat[q + 1]) */
+    qsort(V, sz, sizeof(pb_node), cmp_pb_load_id);
+    uint32_t s = 0;
+    for (uint32_t x = 0; x < sz; ++x)
+        if (x == 0 || V[x].cur != V[x - 1].cur) plat[s++] = x;
+    plat[s] = sz;
+    /* the current set V_i is every alive node with index below plat[i + 1]
+       that has not been removed: earlier plateaus merge into later ones */
+    for (uint32_t i = 0; nC > 0 && i < s; ++i) {
+        const uint32_t end = plat[i + 1];
+        int inf_gap = (i + 1 >= s);
+        u128 gap = inf_gap ? 0 : V[plat[i + 1]].cur - V[plat[i]].cur;
+        for (;;) {
+            uint64_t cnt = 0;
+            u128 minup = 0;
+            for (uint32_t x = 0; x < end; ++x)
+                if (V[x].alive) {
+                    if (cnt == 0 || V[x].up < minup) minup = V[x].up;
+                    ++cnt;
+                }
+            if (nC == 0 || (!inf_gap && gap == 0) || cnt == 0) break;
+            u128 w = minup;
+            if (!inf_gap && gap < w) w = gap;
+            if (nC / cnt < w) w = nC / cnt;
+            if (w > 0) {
+                for (uint32_t x = 0; x < end; ++x)
+                    if (V[x].alive) { V[x].cur += w; V[x].up -= w; }
+                nC -= w * cnt;
+                if (!inf_gap) gap -= w;
+            } else {
+                /* fewer cliques left than nodes in V_i: the lowest ids gain 1 */
+                uint32_t m = 0;
+                for (uint32_t x = 0; x < end; ++x)
+                    if (V[x].alive) pick[m++] = V[x].u;
+                qsort(pick, m, sizeof(uint32_t), cmp_u32);
+                for (uint32_t x = 0; x < end; ++x)
+                    if (V[x].alive) {
+                        for (uint64_t q = 0; q < (uint64_t)nC; ++q)
+                            if (pick[q] == V[x].u) { V[x].cur += 1; V[x].up -= 1; break; }
+                    }
+                nC = 0;
+            }
+            for (uint32_t x = 0; x < end; ++x)
+                if (V[x].alive && V[x].up == 0) V[x].alive = 0;
+        }
+        /* the rest of V_i has reached r_{i+1} and joins V_{i+1} (end grows with i) */
+    }
+    for (uint32_t x = 0; x < sz; ++x) add[V[x].u] += V[x].cur - r[V[x].u];
+    free(V); free(plat); free(pick);
+    return nC == 0 ? KOR_OK : KOR_EINVAL;
+}
+
+/* One pair at loads r (u64): the pair's allocation added into d (u64). */
+int kor_pb_pair(uint32_t n, const uint32_t *mem, uint32_t h, uint32_t p, int k, const uint64_t *r, uint64_t *d) {
+    if (k < 2 || !mem || !r || !d) return KOR_EINVAL;
+    u128 *rr = (u128 *)calloc((size_t)(n ? n : 1), sizeof(u128));
+    u128 *dd = (u128 *)calloc((size_t)(n ? n : 1), sizeof(u128));
+    if (!rr || !dd) { free(rr); free(dd); return KOR_ENOMEM; }
+    for (uint32_t u = 0; u < n; ++u) rr[u] = r[u];
+    int err = pb_pair(mem, h, p, k, rr, dd);
+    for (uint32_t u = 0; !err && u < n; ++u) {
+        if (dd[u] + d[u] > (u128)UINT64_MAX) err = KOR_EINVAL;
+        d[u] += (uint64_t)dd[u];
+    }
+    free(rr); free(dd);
+    return err;
+}
+
+/*
+ * T iterations of PBUpdate over the pairs (members of pair q at
+ * mem[off[q] .. off[q] + h[q] + p[q]), hold nodes first); r holds r_0 on entry
+ * and r_T on return.  synchronous = 0: the paper's sequential pass.
+ */
+int kor_pb_run(uint32_t n, uint64_t npairs, const uint32_t *h, const uint32_t *p, const uint64_t *off,
+               const uint32_t *mem, int k, uint32_t T, int synchronous, uint64_t *r, double *seconds) {
+    if (k < 2 || !r || (npairs && (!h || !p || !off || !mem))) return KOR_EINVAL;
+    u128 *cur = (u128 *)malloc(sizeof(u128) * (size_t)(n ? n : 1));
+    u128 *nxt = (u128 *)malloc(sizeof(u128) * (size_t)(n ? n : 1));
+    if (!cur || !nxt) { free(cur); free(nxt); return KOR_ENOMEM; }
+    for (uint32_t u = 0; u < n; ++u) cur[u] = r[u];
+    double t0 = now_s();
+    int err = KOR_OK;
+    for (uint32_t t = 1; !err && t <= T; ++t) {
+        if (synchronous) {
+            for (uint32_t u = 0; u < n; ++u) nxt[u] = cur[u];
+            for (uint64_t q = 0; !err && q < npairs; ++q) err = pb_pair(mem + off[q], h[q], p[q], k, cur, nxt);
+            u128 *sw = cur; cur = nxt; nxt = sw;
+        } else {
+            for (uint64_t q = 0; !err && q < npairs; ++q) err = pb_pair(mem + off[q], h[q], p[q], k, cur, cur);
+        }
+    }
+    if (seconds) *seconds = now_s() - t0;
+    for (uint32_t u = 0; !err && u < n; ++u) {
+        if (cur[u] > (u128)UINT64_MAX) err = KOR_EINVAL;
+        r[u] = (uint64_t)cur[u];
+    }
+    free(cur); free(nxt);
+    return err;
+}

@@ -62,6 +62,10 @@ def lib(path: str | None = None):
                                 C.POINTER(TraceRow)]
         L.kor_credits.argtypes = [C.c_uint32, p64, p32, C.c_int, p64, p64]
         L.kor_threads.argtypes = [C.c_int]
+        L.kor_extract.argtypes = [C.c_uint32, p64, p32, C.c_int, p64, C.c_int, p32, p32, p64]
+        L.kor_pb_pair.argtypes = [C.c_uint32, p32, C.c_uint32, C.c_uint32, C.c_int, p64, p64]
+        L.kor_pb_run.argtypes = [C.c_uint32, C.c_uint64, p32, p32, p64, p32, C.c_int, C.c_uint32, C.c_int,
+                                 p64, C.POINTER(C.c_double)]
         _libs[path] = L
     return _libs[path]
 
@@ -151,3 +155,47 @@ def solve(n, row_ptr, col, k, T, r0=None, trace=False, threads=0,
         out["trace"] = [dict(t=rw.t, size=rw.size, dens_num=rw.dens_num,
                              ub_num=(rw.ub_num_hi << 64) | rw.ub_num_lo) for rw in rows]
     return out
+
+
+def extract(n, row_ptr, col, k, r, threads=0, libpath=None) -> dict:
+    """The extraction alone at loads r (uint64): order, size i* and K_{i*}."""
+    rp, cl = _csr(row_ptr, col)
+    rr = np.ascontiguousarray(r, dtype=np.uint64)
+    order = np.zeros(max(n, 1), dtype=np.uint32)
+    size = C.c_uint32(0)
+    dens = np.zeros(1, dtype=np.uint64)
+    err = lib(libpath).kor_extract(n, _p64(rp), _p32(cl), k, _p64(rr), threads, _p32(order), C.byref(size),
+                                   _p64(dens))
+    if err:
+        raise RuntimeError(f"kor_extract failed: {err}")
+    return dict(order=order[:n], size=size.value, dens_num=int(dens[0]))
+
+
+def pb_pair(n, members, h, p, k, r, libpath=None) -> np.ndarray:
+    """PBUpdate (Algorithm 3) of one pair at loads r: the increments of its nodes."""
+    mem = np.ascontiguousarray(members, dtype=np.uint32)
+    rr = np.ascontiguousarray(r, dtype=np.uint64)
+    d = np.zeros(max(n, 1), dtype=np.uint64)
+    err = lib(libpath).kor_pb_pair(n, _p32(mem), h, p, k, _p64(rr), _p64(d))
+    if err:
+        raise RuntimeError(f"kor_pb_pair failed: {err}")
+    return d[:n]
+
+
+def pb_run(n, h, p, members, k, T, synchronous, r0=None, libpath=None) -> dict:
+    """T iterations of PBUpdate over the pairs (h[q], p[q], members flattened,
+    hold nodes first), sequential (the paper's loop) or synchronous."""
+    hh = np.ascontiguousarray(h, dtype=np.uint32)
+    pp = np.ascontiguousarray(p, dtype=np.uint32)
+    mem = np.ascontiguousarray(members, dtype=np.uint32)
+    off = np.zeros(len(hh) + 1, dtype=np.uint64)
+    np.cumsum(hh.astype(np.uint64) + pp.astype(np.uint64), out=off[1:])
+    r = np.zeros(max(n, 1), dtype=np.uint64)
+    if r0 is not None:
+        r[:n] = np.asarray(r0, dtype=np.uint64)
+    secs = C.c_double(0.0)
+    err = lib(libpath).kor_pb_run(n, len(hh), _p32(hh), _p32(pp), _p64(off), _p32(mem), k, T,
+                                  1 if synchronous else 0, _p64(r), C.byref(secs))
+    if err:
+        raise RuntimeError(f"kor_pb_run failed: {err}")
+    return dict(r=r[:n], seconds=secs.value)

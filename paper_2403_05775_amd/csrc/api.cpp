@@ -193,8 +193,16 @@ static void layout_workspace(kdss_plan* P) {
   // hot-node credit slots, hot-node-major (kept zero between passes)
   P->off_scratch = take((size_t)kHotSlots * P->hot.size() * 8);
   P->lane_leaves = 0;
-  for (const Tile& tl : P->tiles)
-    if ((tl.info & 7u) == kTileLane) P->lane_leaves += (tl.info >> 3) & 0x1FFFu;
+  P->pb_rows = 1;
+  for (const Tile& tl : P->tiles) {
+    const uint32_t smax = tl.info >> 16;
+    if ((tl.info & 7u) == kTileLane) {
+      P->lane_leaves += (tl.info >> 3) & 0x1FFFu;
+      P->pb_rows = std::max(P->pb_rows, smax);             // one row of 64 per member position
+    } else {
+      P->pb_rows = std::max(P->pb_rows, (smax + 63) / 64);  // a big leaf, 64 members per row
+    }
+  }
   P->off_queue = take(P->lane_leaves * 16);   // 16-byte heavy-leaf entries
   P->off_hotkey = take((size_t)kHotMax * 32);     // hot-node keys of the current pass
   P->off_hotkey_fw = take((size_t)kHotMax * 32);  // hot-node keys at the current loads (64-bit runs)
@@ -257,6 +265,14 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
     if (P->opts.gather < 0 || P->opts.gather > 2) {
       delete P;
       return fail(KDSS_EINVAL, "gather must be 0, 1 or 2");
+    }
+    if (P->opts.update < 0 || P->opts.update > 1) {
+      delete P;
+      return fail(KDSS_EINVAL, "update must be 0 (Frank-Wolfe) or 1 (PBUpdate)");
+    }
+    if (P->opts.update == 1 && (P->opts.width == 128 || !fits64)) {
+      delete P;
+      return fail(KDSS_EINVAL, "PBUpdate runs with 64-bit loads only");
     }
     if (P->opts.width == 64 && !fits64) {
       delete P;
@@ -514,6 +530,7 @@ int kdss_plan_info(const kdss_plan* P, kdss_plan_stats* out) {
   out->id_bits = P->id_bits;
   out->T_max = P->T_max;
   out->gather = P->gather;
+  out->update = P->opts.update;
   out->hot_nodes = (uint32_t)P->hot.size();
   out->hot_share = P->hot_share;
   for (int c = 0; c < kNumClasses; ++c) {

@@ -154,6 +154,7 @@ struct kdss_plan {
   int width = 64;          // load width
   int key_mode = 0;        // 0 packed, 1 full
   int gather = 1;          // leaf-pass key gathers: 1 masked, 2 full
+  uint32_t pb_rows = 0;    // PBUpdate: staged rows of 64 members (largest lane tile or big leaf)
   double hot_share = 0.0;  // hot nodes' share of all member occurrences
   uint64_t r0_max = 0;
   kdss::u128 c_k = 0;

@@ -597,6 +597,224 @@ __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__
     if (hcnt[i]) atomicAdd(reinterpret_cast<unsigned long long*>(scratch + (size_t)i * kHotSlots + slot), hcnt[i]);
 }
 
+// ----------------------------------------------------------------------------
+// PBUpdate (paper: Algorithm 3), synchronous over the pairs (leaves) of the
+// tree: every leaf reads r_{t-1} and its allocation goes into out.
+//
+// A leaf with h hold and p pivot members holds n_C = C(p, j) k-cliques,
+// j = k - h; member x may receive at most cap(x) = n_C (hold) or C(p - 1, j - 1)
+// (pivot), the number of the leaf's cliques that contain it.  The algorithm's
+// plateau steps raise the lowest loads first, equally, within the caps; they end
+// at a level L: every member gets min(cap, max(0, L - r)), and the n_C - S(L)
+// cliques left over (fewer than the members still below both L + 1 and their
+// caps) go one each to the lowest ids among those.  Here L is found in closed
+// form: S(L) = sum over members of min(cap, max(0, L - r)) is piecewise linear
+// with breakpoints r(x) and r(x) + cap(x); b0 = the largest breakpoint with
+// S(b0) <= n_C; sigma = the members growing just above b0; then
+// L = b0 + floor((n_C - S(b0)) / sigma) and the remainder is
+// (n_C - S(b0)) mod sigma.
+// ----------------------------------------------------------------------------
+
+// S(L) saturated at n_C + 1 (only S <= n_C matters), over members
+// x = x0, x0 + dx, .. < s whose loads are lr[x * stride].
+__device__ __forceinline__ uint64_t pb_level_sum(const uint64_t* lr, uint32_t stride, uint32_t x0, uint32_t dx,
+                                                 uint32_t s, uint32_t h, uint64_t nC, uint64_t cp, uint64_t L) {
+  const uint64_t sat = nC + 1;   // n_C < 2^64 - 1: the plan keeps r_0 + T c_k below 2^64
+  uint64_t S = 0;
+#pragma unroll 4
+  for (uint32_t x = x0; x < s; x += dx) {
+    const uint64_t rx = lr[(size_t)x * stride];
+    const uint64_t cap = x < h ? nC : cp;
+    const uint64_t term = L > rx ? min(cap, L - rx) : 0ull;
+    S = term > sat - S ? sat : S + term;   // saturating, never wraps (S <= sat)
+  }
+  return S;
+}
+
+__device__ __forceinline__ uint32_t pb_node_id(uint32_t raw, const uint32_t* hid) {
+  return (raw & kHotFlag) ? hid[raw & (kHotMax - 1)] : raw;
+}
+
+// One leaf per lane: lr / lm hold the lane's column (member x at x * 64).
+__device__ __forceinline__ void pb_leaf_lane(const uint64_t* lr, const uint32_t* lm, uint32_t h, uint32_t p,
+                                             uint64_t nC, uint64_t cp, const uint32_t* hid, Sink& sink) {
+  const uint32_t s = h + p;
+  if (s == 0 || nC == 0) return;
+  uint64_t b0 = ~0ull, top = 0;
+  for (uint32_t x = 0; x < s; ++x) {
+    b0 = min(b0, lr[(size_t)x * 64]);   // S(min r) = 0
+    top = max(top, lr[(size_t)x * 64]);
+  }
+  if (s <= 16) {
+    // small leaves: every breakpoint r(x), r(x) + cap(x) in turn
+    for (uint32_t y = 0; y < s; ++y) {
+      const uint64_t ry = lr[(size_t)y * 64];
+      if (ry > b0 && pb_level_sum(lr, 64, 0, 1, s, h, nC, cp, ry) <= nC) b0 = ry;
+      if (y >= h) {
+        const uint64_t c = ry + cp;
+        if (c > b0 && pb_level_sum(lr, 64, 0, 1, s, h, nC, cp, c) <= nC) b0 = c;
+      }
+    }
+  } else {
+    // larger leaves: bisection on the level itself, S(lo) <= n_C < S(hi)
+    // (at max r + n_C + 1 every member is at its cap, and the caps sum to
+    // k n_C > n_C); the level found is the largest with S <= n_C, so the
+    // closing steps below give the same allocation
+    uint64_t lo = b0, hi = top + nC + 1;
+    while (hi - lo > 1) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      if (pb_level_sum(lr, 64, 0, 1, s, h, nC, cp, mid) <= nC) lo = mid;
+      else hi = mid;
+    }
+    b0 = lo;
+  }
+  uint64_t S0 = 0;
+  uint32_t sigma = 0;
+  for (uint32_t x = 0; x < s; ++x) {
+    const uint64_t rx = lr[(size_t)x * 64], cap = x < h ? nC : cp;
+    if (b0 > rx) S0 += min(cap, b0 - rx);
+    sigma += (rx <= b0 && b0 - rx < cap) ? 1u : 0u;
+  }
+  sigma = max(sigma, 1u);   // at least one member grows above b0 whenever n_C > 0
+  const uint64_t L = b0 + (nC - S0) / sigma, R = (nC - S0) % sigma;
+  for (uint32_t x = 0; x < s; ++x) {
+    const uint64_t rx = lr[(size_t)x * 64], cap = x < h ? nC : cp;
+    uint64_t inc = L > rx ? min(cap, L - rx) : 0ull;
+    if (R && rx <= L && L - rx < cap) {
+      // rank of this member's id among the members still growing at L
+      const uint32_t id = pb_node_id(lm[(size_t)x * 64], hid);
+      uint32_t below = 0;
+      for (uint32_t y = 0; y < s; ++y) {
+        const uint64_t ry = lr[(size_t)y * 64], cy = y < h ? nC : cp;
+        below += (ry <= L && L - ry < cy && pb_node_id(lm[(size_t)y * 64], hid) < id) ? 1u : 0u;
+      }
+      inc += below < R ? 1u : 0u;
+    }
+    if (inc) sink.add(lm[(size_t)x * 64], inc);
+  }
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v = max(v, shfl_xor64(v, d));
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v = min(v, shfl_xor64(v, d));
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v += shfl_xor64(v, d);
+  return v;
+}
+
+// One leaf of more than 64 members per wavefront: lr / lm hold its members
+// contiguously (member x at x); lane l owns members l, l + 64, ..
+__device__ __forceinline__ void pb_leaf_wave(const uint64_t* lr, const uint32_t* lm, uint32_t h, uint32_t p,
+                                             uint64_t nC, uint64_t cp, const uint32_t* hid, Sink& sink) {
+  const uint32_t lane = threadIdx.x & 63u, s = h + p;
+  if (s == 0 || nC == 0) return;
+  uint64_t m = ~0ull;
+  for (uint32_t x = lane; x < s; x += 64) m = min(m, lr[x]);
+  uint64_t b0 = wave_min_u64(m);
+  uint64_t best = b0;
+  for (uint32_t y = lane; y < s; y += 64) {
+    const uint64_t ry = lr[y];
+    if (ry > best && pb_level_sum(lr, 1, 0, 1, s, h, nC, cp, ry) <= nC) best = ry;
+    if (y >= h) {
+      const uint64_t c = ry + cp;
+      if (c > best && pb_level_sum(lr, 1, 0, 1, s, h, nC, cp, c) <= nC) best = c;
+    }
+  }
+  b0 = wave_max_u64(best);
+  uint64_t S0 = 0, sg = 0;
+  for (uint32_t x = lane; x < s; x += 64) {
+    const uint64_t rx = lr[x], cap = x < h ? nC : cp;
+    if (b0 > rx) S0 += min(cap, b0 - rx);
+    sg += (rx <= b0 && b0 - rx < cap) ? 1u : 0u;
+  }
+  S0 = wave_sum_u64(S0);
+  const uint64_t sigma = max(wave_sum_u64(sg), (uint64_t)1);
+  const uint64_t L = b0 + (nC - S0) / sigma, R = (nC - S0) % sigma;
+  for (uint32_t x = lane; x < s; x += 64) {
+    const uint64_t rx = lr[x], cap = x < h ? nC : cp;
+    uint64_t inc = L > rx ? min(cap, L - rx) : 0ull;
+    if (R && rx <= L && L - rx < cap) {
+      const uint32_t id = pb_node_id(lm[x], hid);
+      uint64_t below = 0;
+      for (uint32_t y = 0; y < s; ++y) {
+        const uint64_t ry = lr[y], cy = y < h ? nC : cp;
+        below += (ry <= L && L - ry < cy && pb_node_id(lm[y], hid) < id) ? 1u : 0u;
+      }
+      inc += below < R ? 1u : 0u;
+    }
+    if (inc) sink.add(lm[x], inc);
+  }
+}
+
+// One wavefront per workgroup, tiles w, w + gridDim.x, ..  Dynamic LDS: rows
+// of 64 loads (u64) and then rows of 64 member words; a lane tile stages its
+// rows there (each lane then reads only its own column), a big leaf its
+// members.  Hot loads, ids and credit totals live in static LDS; the totals
+// reach the hot nodes' slot entries at the end, as in the leaf-credit pass.
+__global__ __launch_bounds__(64) void pb_kernel(const Tile* __restrict__ tiles, uint32_t ntiles,
+                                                const uint32_t* __restrict__ members,
+                                                const uint32_t* __restrict__ hdr,
+                                                const uint64_t* __restrict__ binom, uint32_t k1,
+                                                const uint64_t* __restrict__ r, const uint32_t* __restrict__ hot,
+                                                uint32_t nhot, uint64_t* __restrict__ out,
+                                                uint64_t* __restrict__ scratch, uint32_t rows) {
+  extern __shared__ uint64_t pb_lds[];
+  __shared__ uint64_t hr[kHotMax];
+  __shared__ uint32_t hid[kHotMax];
+  __shared__ unsigned long long hcnt[kHotMax];
+  uint64_t* lr = pb_lds;
+  uint32_t* lm = reinterpret_cast<uint32_t*>(pb_lds + (size_t)rows * 64);
+  const uint32_t lane = threadIdx.x & 63u;
+  for (uint32_t i = lane; i < nhot; i += 64) {
+    hid[i] = hot[i];
+    hr[i] = r[hot[i]];
+    hcnt[i] = 0;
+  }
+  __syncthreads();
+  Sink sink{hcnt, out, 0u, 0ull};
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const Tile t = tiles[tile];
+    const uint32_t smax = t.info >> 16;
+    if ((t.info & 7u) == kTileBig) {
+      const uint32_t hd = hdr[t.lbase];
+      const uint32_t h = hd & 31u, j = (hd >> 5) & 31u, p = hd >> 10, sz = h + p;
+      wave_lds_sync();   // the previous tile's reads are done
+      for (uint32_t x = lane; x < sz; x += 64) {
+        const uint32_t raw = members[t.mbase + x];
+        lm[x] = raw;
+        lr[x] = (raw & kHotFlag) ? hr[raw & (kHotMax - 1)] : r[raw];
+      }
+      wave_lds_sync();
+      const uint64_t nC = binom[(size_t)p * k1 + j], cp = j ? binom[(size_t)(p - 1) * k1 + (j - 1)] : 0ull;
+      pb_leaf_wave(lr, lm, h, p, nC, cp, hid, sink);
+    } else {
+      const uint32_t nl = (t.info >> 3) & 0x1FFFu;
+      const uint32_t hd = lane < nl ? hdr[t.lbase + lane] : 0u;   // a missing leaf reads as empty
+      const uint32_t h = hd & 31u, j = (hd >> 5) & 31u, p = hd >> 10;
+      const uint32_t* col = members + t.mbase + lane;
+      wave_lds_sync();
+      for (uint32_t x = 0; x < smax; ++x) {
+        const uint32_t raw = col[(size_t)x * 64];
+        lm[(size_t)x * 64 + lane] = raw;
+        lr[(size_t)x * 64 + lane] = (raw & kHotFlag) ? hr[raw & (kHotMax - 1)] : r[raw];
+      }
+      const uint64_t nC = hd ? binom[(size_t)p * k1 + j] : 0ull;
+      const uint64_t cp = (hd && j) ? binom[(size_t)(p - 1) * k1 + (j - 1)] : 0ull;
+      pb_leaf_lane(lr + lane, lm + lane, h, p, nC, cp, hid, sink);
+    }
+  }
+  sink.flush();
+  __syncthreads();
+  const uint32_t slot = blockIdx.x % kHotSlots;
+  for (uint32_t i = lane; i < nhot; i += 64)
+    if (hcnt[i]) atomicAdd(reinterpret_cast<unsigned long long*>(scratch + (size_t)i * kHotSlots + slot), hcnt[i]);
+}
+
 // Hot-node totals: out[hot[i]] += the sum of hot node i's kHotSlots slot
 // entries (contiguous: slot b of node i is scratch[i * kHotSlots + b]), and the
 // entries are cleared for the next pass (each is read exactly once).  One
@@ -1337,6 +1555,27 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
 
 int fw_mode(const kdss_plan* P) { return P->width == 128 ? 2 : (P->key_mode == 0 ? 0 : 1); }
 
+// One synchronous PBUpdate pass at loads d_r (64-bit) into out; hot-node
+// totals go to the slot entries that the load update sums.  Events as for the
+// leaf-credit pass (the last three mark its end).
+int launch_pb(const kdss_plan* P, const WsView& ws, const void* d_r, uint64_t* out, hipStream_t st,
+              hipEvent_t* ev) {
+  const uint32_t ntiles = (uint32_t)P->tiles.size();
+  if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
+  if (ntiles) {
+    const uint32_t blocks = std::min<uint32_t>(ntiles, 4u * P->leaf_blocks);
+    const size_t lds = (size_t)P->pb_rows * 64 * 12;
+    pb_kernel<<<blocks, 64, lds, st>>>(ws.at<Tile>(P->off_tiles), ntiles, ws.at<uint32_t>(P->off_members),
+                                       ws.at<uint32_t>(P->off_hdr), ws.at<uint64_t>(P->off_binom), P->k1,
+                                       static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot),
+                                       (uint32_t)P->hot.size(), out, ws.at<uint64_t>(P->off_scratch), P->pb_rows);
+    HIP_TRY(hipGetLastError(), "PBUpdate launch");
+  }
+  if (ev)
+    for (int i = 1; i < 4; ++i) HIP_TRY(hipEventRecord(ev[i], st), "event record");
+  return KDSS_OK;
+}
+
 KeySrc fw_src(const kdss_plan* P, const WsView& ws, const void* d_r) {
   (void)ws;
   KeySrc s{};
@@ -1346,14 +1585,16 @@ KeySrc fw_src(const kdss_plan* P, const WsView& ws, const void* d_r) {
   return s;
 }
 
-// One Frank-Wolfe iteration: credits at r_{t-1} into delta (hot nodes' into the
-// slot entries), then r_t = r_{t-1} + delta.  With 64-bit loads the hot-node
+// One iteration: credits at r_{t-1} into delta (hot nodes' into the slot
+// entries) -- Frank-Wolfe's per-clique minimum, or PBUpdate's per-pair water
+// fill -- then r_t = r_{t-1} + delta.  With 64-bit loads the hot-node
 // reduction is part of the update kernel.
 int launch_fw_step(const kdss_plan* P, const WsView& ws, void* d_r, hipStream_t st, hipEvent_t* ev,
                    uint32_t* qlog) {
   uint64_t* delta = ws.at<uint64_t>(P->off_delta);
   const bool fused = P->width == 64 && !P->tiles.empty();
-  int rc = launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev, qlog, !fused, fused);
+  int rc = P->opts.update == 1 ? launch_pb(P, ws, d_r, delta, st, ev)
+                               : launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev, qlog, !fused, fused);
   if (rc) return rc;
   if (P->width == 128) {
     apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);

@@ -195,6 +195,17 @@ def test_gather_mode_option():
     assert abs(s.hot_share - occ[cand].sum() / occ.sum()) < 1e-12
 
 
+def test_update_option():
+    g = synth.chung_lu(2000, 20000, 2.3, seed=5, planted=30)
+    t = kdss.Tree(g, 4)
+    assert kdss.Plan(t, 10).stats().update == 0
+    assert kdss.Plan(t, 10, update=1).stats().update == 1
+    for kw in (dict(update=2), dict(update=-1), dict(update=1, width=128), dict(update=1, r0_max=2**64 - 2)):
+        with pytest.raises(kdss.KdssError) as e:
+            kdss.Plan(t, 10, **kw)
+        assert e.value.status == kdss.EINVAL, kw
+
+
 def test_run_rejects_bad_arguments_before_device_work():
     g = synth.complete_graph(8)
     t = kdss.Tree(g, 3)
