@@ -193,15 +193,21 @@ static void layout_workspace(kdss_plan* P) {
   // hot-node credit slots, hot-node-major (kept zero between passes)
   P->off_scratch = take((size_t)kHotSlots * P->hot.size() * 8);
   P->lane_leaves = 0;
+  for (const Tile& tl : P->tiles)
+    if ((tl.info & 7u) == kTileLane) P->lane_leaves += (tl.info >> 3) & 0x1FFFu;
+  // PBUpdate: the lane tiles of at most kPbRegRows rows form a suffix (groups
+  // run from the largest to the smallest); the tiles before it are staged in LDS
+  P->pb_split = (uint32_t)P->tiles.size();
+  while (P->pb_split > 0) {
+    const Tile& tl = P->tiles[P->pb_split - 1];
+    if ((tl.info & 7u) != kTileLane || (tl.info >> 16) > kPbRegRows) break;
+    --P->pb_split;
+  }
   P->pb_rows = 1;
-  for (const Tile& tl : P->tiles) {
+  for (uint32_t i = 0; i < P->pb_split; ++i) {
+    const Tile& tl = P->tiles[i];
     const uint32_t smax = tl.info >> 16;
-    if ((tl.info & 7u) == kTileLane) {
-      P->lane_leaves += (tl.info >> 3) & 0x1FFFu;
-      P->pb_rows = std::max(P->pb_rows, smax);             // one row of 64 per member position
-    } else {
-      P->pb_rows = std::max(P->pb_rows, (smax + 63) / 64);  // a big leaf, 64 members per row
-    }
+    P->pb_rows = std::max(P->pb_rows, (tl.info & 7u) == kTileLane ? smax : (smax + 63) / 64);
   }
   P->off_queue = take(P->lane_leaves * 16);   // 16-byte heavy-leaf entries
   P->off_hotkey = take((size_t)kHotMax * 32);     // hot-node keys of the current pass

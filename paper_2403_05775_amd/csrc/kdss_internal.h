@@ -123,6 +123,7 @@ constexpr uint32_t kLeafBlocksDefault = 1792;    // seven workgroups per CU
 constexpr uint32_t kHeavyBlocks = 1024;          // grid of the heavy-leaf kernel
 constexpr uint32_t kHotSlots = 256;              // credit slots per hot node, shared by workgroups
 constexpr double kMaskedGatherShare = 0.5;       // hot share from which masked gathers are the default
+constexpr uint32_t kPbRegRows = 16;              // PBUpdate: lane tiles up to this many rows run from registers
 
 // Device-side result of an extraction.
 struct DevResult {
@@ -154,7 +155,9 @@ struct kdss_plan {
   int width = 64;          // load width
   int key_mode = 0;        // 0 packed, 1 full
   int gather = 1;          // leaf-pass key gathers: 1 masked, 2 full
-  uint32_t pb_rows = 0;    // PBUpdate: staged rows of 64 members (largest lane tile or big leaf)
+  uint32_t pb_split = 0;   // PBUpdate: tiles [0, pb_split) are staged in LDS, the rest (lane tiles of
+                           // at most kPbRegRows rows) kept in registers
+  uint32_t pb_rows = 0;    // PBUpdate: staged rows of 64 members (largest such tile or big leaf)
   double hot_share = 0.0;  // hot nodes' share of all member occurrences
   uint64_t r0_max = 0;
   kdss::u128 c_k = 0;

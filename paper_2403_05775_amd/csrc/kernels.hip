@@ -815,6 +815,138 @@ __global__ __launch_bounds__(64) void pb_kernel(const Tile* __restrict__ tiles, 
     if (hcnt[i]) atomicAdd(reinterpret_cast<unsigned long long*>(scratch + (size_t)i * kHotSlots + slot), hcnt[i]);
 }
 
+// The same for lane tiles of at most SM rows, the members' loads and words in
+// registers (loops unrolled over SM, masked to the leaf's s members).
+template <int SM>
+__device__ __forceinline__ uint64_t pb_level_sum_reg(const uint64_t (&rv)[SM], uint32_t s, uint32_t h, uint64_t nC,
+                                                     uint64_t cp, uint64_t L) {
+  const uint64_t sat = nC + 1;
+  uint64_t S = 0;
+#pragma unroll
+  for (int x = 0; x < SM; ++x) {
+    const uint64_t cap = (uint32_t)x < h ? nC : cp;
+    const uint64_t term = ((uint32_t)x < s && L > rv[x]) ? min(cap, L - rv[x]) : 0ull;
+    S = term > sat - S ? sat : S + term;
+  }
+  return S;
+}
+
+template <int SM>
+__device__ __forceinline__ void pb_tile_reg(const Tile& t, const uint32_t* __restrict__ members,
+                                            const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ binom,
+                                            uint32_t k1, const uint64_t* __restrict__ r, const uint64_t* hr,
+                                            const uint32_t* hid, Sink& sink) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t nl = (t.info >> 3) & 0x1FFFu, smax = t.info >> 16;
+  const uint32_t hd = lane < nl ? hdr[t.lbase + lane] : 0u;
+  const uint32_t h = hd & 31u, j = (hd >> 5) & 31u, p = hd >> 10, s = h + p;
+  const uint32_t* col = members + t.mbase + lane;
+  uint32_t raw[SM];
+  uint64_t rv[SM];
+#pragma unroll
+  for (int x = 0; x < SM; ++x) raw[x] = (uint32_t)x < smax ? col[(size_t)x * 64] : 0u;
+#pragma unroll
+  for (int x = 0; x < SM; ++x) rv[x] = (raw[x] & kHotFlag) ? hr[raw[x] & (kHotMax - 1)] : r[raw[x]];
+  const uint64_t nC = hd ? binom[(size_t)p * k1 + j] : 0ull;
+  const uint64_t cp = (hd && j) ? binom[(size_t)(p - 1) * k1 + (j - 1)] : 0ull;
+  if (s == 0 || nC == 0) return;
+  uint64_t b0 = ~0ull, top = 0;
+#pragma unroll
+  for (int x = 0; x < SM; ++x)
+    if ((uint32_t)x < s) {
+      b0 = min(b0, rv[x]);
+      top = max(top, rv[x]);
+    }
+  if (SM <= 16) {
+    // breakpoints r(y), r(y) + cap(y) in turn; the candidate is selected out of
+    // the register array (a runtime index would put the array in scratch)
+#pragma unroll 1
+    for (uint32_t y = 0; y < s; ++y) {
+      uint64_t ry = 0;
+#pragma unroll
+      for (int x = 0; x < SM; ++x) ry = (uint32_t)x == y ? rv[x] : ry;
+      if (ry > b0 && pb_level_sum_reg<SM>(rv, s, h, nC, cp, ry) <= nC) b0 = ry;
+      const uint64_t c = ry + cp;
+      if (y >= h && c > b0 && pb_level_sum_reg<SM>(rv, s, h, nC, cp, c) <= nC) b0 = c;
+    }
+  } else {
+    uint64_t lo = b0, hi = top + nC + 1;
+    while (hi - lo > 1) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      if (pb_level_sum_reg<SM>(rv, s, h, nC, cp, mid) <= nC) lo = mid;
+      else hi = mid;
+    }
+    b0 = lo;
+  }
+  uint64_t S0 = 0;
+  uint32_t sigma = 0;
+#pragma unroll
+  for (int x = 0; x < SM; ++x) {
+    const uint64_t cap = (uint32_t)x < h ? nC : cp;
+    if ((uint32_t)x < s) {
+      if (b0 > rv[x]) S0 += min(cap, b0 - rv[x]);
+      sigma += (rv[x] <= b0 && b0 - rv[x] < cap) ? 1u : 0u;
+    }
+  }
+  sigma = max(sigma, 1u);
+  const uint64_t L = b0 + (nC - S0) / sigma, R = (nC - S0) % sigma;
+  // members still growing at L, with their node ids (the remainder goes to the lowest)
+  uint32_t gid[SM];
+#pragma unroll
+  for (int x = 0; x < SM; ++x) {
+    const uint64_t cap = (uint32_t)x < h ? nC : cp;
+    const bool grow = (uint32_t)x < s && rv[x] <= L && L - rv[x] < cap;
+    gid[x] = grow ? pb_node_id(raw[x], hid) : ~0u;   // ~0u: not growing (ids stay below it)
+  }
+#pragma unroll
+  for (int x = 0; x < SM; ++x) {
+    if ((uint32_t)x >= s) continue;
+    const uint64_t cap = (uint32_t)x < h ? nC : cp;
+    uint64_t inc = L > rv[x] ? min(cap, L - rv[x]) : 0ull;
+    if (R && gid[x] != ~0u) {
+      uint32_t below = 0;
+#pragma unroll
+      for (int y = 0; y < SM; ++y) below += gid[y] < gid[x] ? 1u : 0u;
+      inc += below < R ? 1u : 0u;
+    }
+    if (inc) sink.add(raw[x], inc);
+  }
+}
+
+// Lane tiles of at most kPbRegRows rows (a suffix of the tile list, which runs from the
+// largest size group to the smallest): four wavefronts per workgroup, wavefront
+// w takes tiles first + w, first + w + 4 gridDim.x, ..; no staging in LDS.
+__global__ __launch_bounds__(256) void pb_reg_kernel(const Tile* __restrict__ tiles, uint32_t first, uint32_t ntiles,
+                                                     const uint32_t* __restrict__ members,
+                                                     const uint32_t* __restrict__ hdr,
+                                                     const uint64_t* __restrict__ binom, uint32_t k1,
+                                                     const uint64_t* __restrict__ r, const uint32_t* __restrict__ hot,
+                                                     uint32_t nhot, uint64_t* __restrict__ out,
+                                                     uint64_t* __restrict__ scratch) {
+  __shared__ uint64_t hr[kHotMax];
+  __shared__ uint32_t hid[kHotMax];
+  __shared__ unsigned long long hcnt[kHotMax];
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
+    hid[i] = hot[i];
+    hr[i] = r[hot[i]];
+    hcnt[i] = 0;
+  }
+  __syncthreads();
+  Sink sink{hcnt, out, 0u, 0ull};
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (uint32_t tile = first + blockIdx.x * 4u + w; tile < ntiles; tile += gridDim.x * 4u) {
+    const Tile t = tiles[tile];
+    const uint32_t smax = t.info >> 16;
+    if (smax <= 8) pb_tile_reg<8>(t, members, hdr, binom, k1, r, hr, hid, sink);
+    else pb_tile_reg<16>(t, members, hdr, binom, k1, r, hr, hid, sink);
+  }
+  sink.flush();
+  __syncthreads();
+  const uint32_t slot = blockIdx.x % kHotSlots;
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x)
+    if (hcnt[i]) atomicAdd(reinterpret_cast<unsigned long long*>(scratch + (size_t)i * kHotSlots + slot), hcnt[i]);
+}
+
 // Hot-node totals: out[hot[i]] += the sum of hot node i's kHotSlots slot
 // entries (contiguous: slot b of node i is scratch[i * kHotSlots + b]), and the
 // entries are cleared for the next pass (each is read exactly once).  One
@@ -1562,13 +1694,22 @@ int launch_pb(const kdss_plan* P, const WsView& ws, const void* d_r, uint64_t* o
               hipEvent_t* ev) {
   const uint32_t ntiles = (uint32_t)P->tiles.size();
   if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
-  if (ntiles) {
-    const uint32_t blocks = std::min<uint32_t>(ntiles, 4u * P->leaf_blocks);
+  const uint32_t split = P->pb_split, nhot = (uint32_t)P->hot.size();
+  if (split) {   // big leaves and lane tiles of more than kPbRegRows rows, staged in LDS
+    const uint32_t blocks = std::min<uint32_t>(split, 4u * P->leaf_blocks);
     const size_t lds = (size_t)P->pb_rows * 64 * 12;
-    pb_kernel<<<blocks, 64, lds, st>>>(ws.at<Tile>(P->off_tiles), ntiles, ws.at<uint32_t>(P->off_members),
+    pb_kernel<<<blocks, 64, lds, st>>>(ws.at<Tile>(P->off_tiles), split, ws.at<uint32_t>(P->off_members),
                                        ws.at<uint32_t>(P->off_hdr), ws.at<uint64_t>(P->off_binom), P->k1,
-                                       static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot),
-                                       (uint32_t)P->hot.size(), out, ws.at<uint64_t>(P->off_scratch), P->pb_rows);
+                                       static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot), nhot, out,
+                                       ws.at<uint64_t>(P->off_scratch), P->pb_rows);
+    HIP_TRY(hipGetLastError(), "PBUpdate launch");
+  }
+  if (split < ntiles) {   // the other lane tiles, from registers
+    const uint32_t blocks = std::min<uint32_t>((ntiles - split + 3) / 4, P->leaf_blocks);
+    pb_reg_kernel<<<blocks, 256, 0, st>>>(ws.at<Tile>(P->off_tiles), split, ntiles, ws.at<uint32_t>(P->off_members),
+                                          ws.at<uint32_t>(P->off_hdr), ws.at<uint64_t>(P->off_binom), P->k1,
+                                          static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot), nhot, out,
+                                          ws.at<uint64_t>(P->off_scratch));
     HIP_TRY(hipGetLastError(), "PBUpdate launch");
   }
   if (ev)
