@@ -569,7 +569,11 @@ def main():
         "hbm_gbps_algorithmic": step_bytes / (ms_per_step / 1000.0) / 1e9,
         "sct_build_s": ts.build_seconds,
         "result": {"size": res.size, "dens_num": res.dens_num.value, "ub_num": res.ub_num.value,
-                   "density": res.density, "upper_bound": res.upper_bound},
+                   "density": res.density, "upper_bound": res.upper_bound,
+                   "bound": {"num": res.bound_num.value, "den": res.bound_den, "value": res.bound,
+                             "kind": "top-s" if res.bound_kind == 1 else "max load",
+                             "certified_optimal": bool(res.certified),
+                             "gap": (res.bound - res.density) / res.bound if res.bound else 0.0}},
         # with 64-bit loads the hot-node reduction is part of the load update
         "kernel_us": {"leaf_credit": leaf_us, "heavy_leaf": heavy_us,
                       "hot_reduce": reduce_us if ps.width == 128 else None, "apply": apply_us},

@@ -146,6 +146,21 @@ typedef struct {
     kdss_u128 c_k;
     double density;           /* dens_num / size (0 when size == 0)             */
     double upper_bound;       /* ub_num / T                                     */
+    /* A certified bound on rho* = max_S |C_k(S)| / |S| and an optimality check
+     * (Frank-Wolfe runs).  Any node set S of s nodes has |C_k(S)| <=
+     * (sum of its (r - r0)) / T, since the cliques inside S put their weight
+     * inside S, and |C_k(S)| <= C(s, k); so rho* <= max_s min(A_s, T C(s, k))
+     * / (T s), A_s = the s largest (r - r0).  bound_kind 1: this top-s bound
+     * (single problems with 64-bit loads and no start loads); 0: the plain
+     * bound ub_num / T.  Two densities with denominators <= n differ by at
+     * least 1 / (n (n - 1)), so certified = 1 when bound - density is below
+     * that: the density is then rho*.  PBUpdate runs report bound_kind 0 and
+     * certified 0 (their loads need not bound rho*).                         */
+    kdss_u128 bound_num;      /* the bound is bound_num / bound_den             */
+    uint64_t bound_den;
+    int bound_kind;
+    int certified;
+    double bound;
 } kdss_result;
 
 typedef struct {              /* one extraction during a run                    */

@@ -199,3 +199,29 @@ def pb_run(n, h, p, members, k, T, synchronous, r0=None, libpath=None) -> dict:
     if err:
         raise RuntimeError(f"kor_pb_run failed: {err}")
     return dict(r=r[:n], seconds=secs.value)
+
+
+def top_bound(r, r0, T, k):
+    """A certified bound on rho* = max_S |C_k(S)| / |S| from Frank-Wolfe loads:
+    every S of s nodes has |C_k(S)| <= (sum over S of (r - r0)) / T (the
+    cliques inside S put their weight inside S) and |C_k(S)| <= C(s, k), so
+    rho* <= max_s min(A_s, T C(s, k)) / (T s), A_s = the s largest (r - r0)."""
+    from fractions import Fraction
+    import math
+    base = [0] * len(r) if r0 is None else [int(x) for x in r0]
+    vals = sorted((int(a) - b for a, b in zip(r, base)), reverse=True)
+    best, A = Fraction(0), 0
+    for s, x in enumerate(vals, 1):
+        A += x
+        best = max(best, Fraction(min(A, T * math.comb(s, k)), T * s))
+    return best
+
+
+def certified(dens_num, size, bound, n):
+    """Distinct densities with denominators <= n differ by at least
+    1 / (n (n - 1)): a density within that of a bound on rho* is rho*."""
+    from fractions import Fraction
+    rho = Fraction(dens_num, size) if size else Fraction(0)
+    if bound < rho:
+        return False
+    return n < 2 or bound - rho < Fraction(1, n * (n - 1))

@@ -186,6 +186,8 @@ static void layout_workspace(kdss_plan* P) {
   P->off_bbest = take((size_t)P->scan_blocks * 16);
   P->off_red = take((size_t)P->red_blocks * 16);   // a (lo, hi) pair per block
   P->off_dres = take(sizeof(DevResult));
+  P->off_tb_sum = take((size_t)P->scan_blocks * 16);    // u128 per block
+  P->off_tb_best = take((size_t)P->scan_blocks * 32);   // (numerator u128, s) per block
   P->leaf_blocks = (uint32_t)std::min<uint64_t>(kLeafBlocksDefault, std::max<uint64_t>(1, (P->tiles.size() + 3) / 4));
   P->heavy_blocks = kHeavyBlocks;
   P->off_hot = take(P->hot.size() * 4);

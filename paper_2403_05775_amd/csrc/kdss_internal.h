@@ -133,8 +133,12 @@ struct DevResult {
   uint64_t ub_lo, ub_hi;  // max (r - r0)
   uint64_t r0max;         // largest start load seen
   uint64_t pad1[3];
+  uint64_t tb_lo, tb_hi;  // top-s bound numerator min(A_s, T C(s, k)) at the best s
+  uint32_t tb_size;       // that s (0: not computed)
+  uint32_t pad2;
+  uint64_t pad3[5];
 };
-static_assert(sizeof(DevResult) == 64, "device result is 64 bytes");
+static_assert(sizeof(DevResult) == 128, "device result is 128 bytes");
 
 // Leaf header: h (5 bits), j = k - h (5 bits), p (22 bits).
 inline uint32_t pack_leaf(uint32_t h, uint32_t j, uint32_t p) { return h | (j << 5) | (p << 10); }
@@ -187,6 +191,7 @@ struct kdss_plan {
   std::vector<uint32_t> prob_k;
   std::vector<kdss::u128> prob_ck;
   size_t off_prefix = 0, off_pres = 0, off_nodeoff = 0;
+  size_t off_tb_sum = 0, off_tb_best = 0;   // top-s bound: per-block load sums and best candidates
   uint64_t lane_leaves = 0;            // leaves in lane tiles (queue capacity)
   // state of the device side
   void* uploaded_ws = nullptr;

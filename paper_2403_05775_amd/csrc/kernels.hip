@@ -989,6 +989,8 @@ __global__ void reset_result_kernel(DevResult* d) {
     d->ub_lo = d->ub_hi = 0;
     d->r0max = 0;
     d->pad1[0] = d->pad1[1] = d->pad1[2] = 0;
+    d->tb_lo = d->tb_hi = 0;
+    d->tb_size = 0;
   }
 }
 
@@ -1785,6 +1787,154 @@ int launch_radix(const kdss_plan* P, const WsView& ws, uint32_t nbits, int wide,
   return KDSS_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Top-s bound on rho* (single problem, 64-bit loads, zero start loads): with
+// A_s = the sum of the s largest loads (the extraction order's first s),
+// rho* <= max_s min(A_s, T C(s, k)) / (T s).  Sums are u128; candidates are
+// compared exactly (u128 x u32 products, 160 bits).
+// ----------------------------------------------------------------------------
+struct U160 {
+  u128 lo;
+  uint32_t hi;
+};
+
+__host__ __device__ inline U160 mul_u128_u32(u128 a, uint32_t b) {
+  const u128 p0 = (u128)(uint64_t)a * b, p1 = (u128)(uint64_t)(a >> 64) * b;
+  const u128 lo = p0 + (p1 << 64);
+  return U160{lo, (uint32_t)(p1 >> 64) + (lo < p0 ? 1u : 0u)};
+}
+
+// x / s > y / t
+__host__ __device__ inline bool ratio_greater(u128 x, uint32_t s, u128 y, uint32_t t) {
+  const U160 a = mul_u128_u32(x, t), b = mul_u128_u32(y, s);
+  return a.hi != b.hi ? a.hi > b.hi : a.lo > b.lo;
+}
+
+// min(A, T C(s, k)), C saturating at 2^128 - 1
+__device__ inline u128 top_candidate(u128 A, uint32_t s, uint32_t k, uint32_t T) {
+  if (s < k) return 0;
+  const u128 mx = ~(u128)0;
+  u128 c = 1;
+  for (uint32_t t = 1; t <= k; ++t) {
+    const uint64_t f = (uint64_t)s - k + t;   // c = C(s - k + t, t) after this step
+    if (c > mx / f) return A;                 // C(s, k) >= 2^128 / s > A / T
+    c = c * f / t;
+  }
+  if (c > mx / T) return A;
+  const u128 tc = c * T;
+  return tc < A ? tc : A;
+}
+
+__global__ __launch_bounds__(kScanThreads) void tb_blocksum_kernel(const uint64_t* __restrict__ r,
+                                                                   const uint32_t* __restrict__ order, uint32_t n,
+                                                                   uint64_t* __restrict__ bsum) {
+  __shared__ uint64_t slo[kScanThreads], shi[kScanThreads];
+  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  u128 acc = 0;
+  for (uint32_t q = 0; q < kScanItems; ++q)
+    if (base + q < n) acc += r[order[base + q]];
+  slo[threadIdx.x] = (uint64_t)acc;
+  shi[threadIdx.x] = (uint64_t)(acc >> 64);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u128 t = 0;
+    for (uint32_t i = 0; i < kScanThreads; ++i) t += ((u128)shi[i] << 64) | slo[i];
+    bsum[2ull * blockIdx.x] = (uint64_t)t;
+    bsum[2ull * blockIdx.x + 1] = (uint64_t)(t >> 64);
+  }
+}
+
+// exclusive scan of the nb block sums, in place (one thread: nb <= n / 1024)
+__global__ void tb_scan_kernel(uint64_t* __restrict__ bsum, uint32_t nb) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  u128 run = 0;
+  for (uint32_t b = 0; b < nb; ++b) {
+    const u128 v = ((u128)bsum[2ull * b + 1] << 64) | bsum[2ull * b];
+    bsum[2ull * b] = (uint64_t)run;
+    bsum[2ull * b + 1] = (uint64_t)(run >> 64);
+    run += v;
+  }
+}
+
+// the best candidate of each block: (numerator lo, hi, s)
+__global__ __launch_bounds__(kScanThreads) void tb_best_kernel(const uint64_t* __restrict__ r,
+                                                               const uint32_t* __restrict__ order, uint32_t n,
+                                                               const uint64_t* __restrict__ bsum, uint32_t T,
+                                                               uint32_t k, uint64_t* __restrict__ bbest) {
+  __shared__ uint64_t slo[kScanThreads], shi[kScanThreads];
+  __shared__ uint64_t blo[kScanThreads], bhi[kScanThreads];
+  __shared__ uint32_t bs[kScanThreads];
+  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  uint64_t v[kScanItems];
+  u128 acc = 0;
+  for (uint32_t q = 0; q < kScanItems; ++q) {
+    v[q] = base + q < n ? r[order[base + q]] : 0ull;
+    acc += v[q];
+  }
+  slo[threadIdx.x] = (uint64_t)acc;
+  shi[threadIdx.x] = (uint64_t)(acc >> 64);
+  __syncthreads();
+  // prefix of the loads before this thread's items (block offset + earlier threads)
+  u128 run = ((u128)bsum[2ull * blockIdx.x + 1] << 64) | bsum[2ull * blockIdx.x];
+  for (uint32_t i = 0; i < threadIdx.x; ++i) run += ((u128)shi[i] << 64) | slo[i];
+  u128 best = 0;
+  uint32_t bsz = 0;
+  for (uint32_t q = 0; q < kScanItems; ++q) {
+    if (base + q >= n) break;
+    run += v[q];
+    const uint32_t sz = base + q + 1;
+    const u128 c = top_candidate(run, sz, k, T);
+    if (bsz == 0 || ratio_greater(c, sz, best, bsz)) { best = c; bsz = sz; }
+  }
+  blo[threadIdx.x] = (uint64_t)best;
+  bhi[threadIdx.x] = (uint64_t)(best >> 64);
+  bs[threadIdx.x] = bsz;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u128 b = 0;
+    uint32_t z = 0;
+    for (uint32_t i = 0; i < kScanThreads; ++i) {
+      if (bs[i] == 0) continue;
+      const u128 c = ((u128)bhi[i] << 64) | blo[i];
+      if (z == 0 || ratio_greater(c, bs[i], b, z)) { b = c; z = bs[i]; }
+    }
+    bbest[4ull * blockIdx.x] = (uint64_t)b;
+    bbest[4ull * blockIdx.x + 1] = (uint64_t)(b >> 64);
+    bbest[4ull * blockIdx.x + 2] = z;
+  }
+}
+
+__global__ void tb_final_kernel(const uint64_t* __restrict__ bbest, uint32_t nb, DevResult* d) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  u128 b = 0;
+  uint32_t z = 0;
+  for (uint32_t i = 0; i < nb; ++i) {
+    const uint32_t s = (uint32_t)bbest[4ull * i + 2];
+    if (s == 0) continue;
+    const u128 c = ((u128)bbest[4ull * i + 1] << 64) | bbest[4ull * i];
+    if (z == 0 || ratio_greater(c, s, b, z)) { b = c; z = s; }
+  }
+  d->tb_lo = (uint64_t)b;
+  d->tb_hi = (uint64_t)(b >> 64);
+  d->tb_size = z;
+}
+
+// After an extraction at loads d_r: the top-s bound into the device result,
+// when it applies (one problem, Frank-Wolfe, 64-bit loads, no start loads).
+int launch_top_bound(const kdss_plan* P, const WsView& ws, const void* d_r, const uint64_t* d_r0, uint32_t T,
+                     const uint32_t* d_order, hipStream_t st) {
+  if (P->width != 64 || d_r0 || P->opts.update != 0 || P->node_off.size() != 2 || P->n == 0) return KDSS_OK;
+  const uint64_t* r = static_cast<const uint64_t*>(d_r);
+  uint64_t* bsum = ws.at<uint64_t>(P->off_tb_sum);
+  uint64_t* bbest = ws.at<uint64_t>(P->off_tb_best);
+  tb_blocksum_kernel<<<P->scan_blocks, kScanThreads, 0, st>>>(r, d_order, P->n, bsum);
+  tb_scan_kernel<<<1, 64, 0, st>>>(bsum, P->scan_blocks);
+  tb_best_kernel<<<P->scan_blocks, kScanThreads, 0, st>>>(r, d_order, P->n, bsum, T, P->k, bbest);
+  tb_final_kernel<<<1, 64, 0, st>>>(bbest, P->scan_blocks, ws.at<DevResult>(P->off_dres));
+  HIP_TRY(hipGetLastError(), "top-s bound launch");
+  return KDSS_OK;
+}
+
 // Extraction at loads d_r; every load is <= bound.  The order lands in d_order
 // and the best prefix and upper bound in the device result.
 int launch_extract(const kdss_plan* P, const WsView& ws, const void* d_r, const uint64_t* d_r0, u128 bound,
@@ -1828,6 +1978,76 @@ int launch_extract(const kdss_plan* P, const WsView& ws, const void* d_r, const 
   return KDSS_OK;
 }
 
+// Exact 256-bit unsigned helpers for the optimality check (four 64-bit limbs,
+// least significant first).
+struct U256 {
+  uint64_t w[4];
+};
+U256 u256_mul(u128 a, u128 b) {   // a * b
+  const uint64_t x[2] = {(uint64_t)a, (uint64_t)(a >> 64)}, y[2] = {(uint64_t)b, (uint64_t)(b >> 64)};
+  U256 r{{0, 0, 0, 0}};
+  for (int i = 0; i < 2; ++i) {
+    u128 carry = 0;
+    for (int j = 0; j < 2; ++j) {
+      const u128 t = (u128)x[i] * y[j] + r.w[i + j] + carry;
+      r.w[i + j] = (uint64_t)t;
+      carry = t >> 64;
+    }
+    r.w[i + 2] = (uint64_t)carry;
+  }
+  return r;
+}
+U256 u256_mul64(const U256& a, uint64_t b) {   // a * b, a < 2^192 here
+  U256 r{{0, 0, 0, 0}};
+  u128 carry = 0;
+  for (int i = 0; i < 4; ++i) {
+    const u128 t = (u128)a.w[i] * b + carry;
+    r.w[i] = (uint64_t)t;
+    carry = t >> 64;
+  }
+  return r;
+}
+int u256_cmp(const U256& a, const U256& b) {
+  for (int i = 3; i >= 0; --i)
+    if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
+  return 0;
+}
+U256 u256_sub(const U256& a, const U256& b) {   // a - b, a >= b
+  U256 r{{0, 0, 0, 0}};
+  uint64_t borrow = 0;
+  for (int i = 0; i < 4; ++i) {
+    const u128 t = (u128)a.w[i] - b.w[i] - borrow;
+    r.w[i] = (uint64_t)t;
+    borrow = (uint64_t)(t >> 64) ? 1u : 0u;
+  }
+  return r;
+}
+
+// The bound num / den on rho* and the optimality check: certified when
+// bound - K / i < 1 / (n (n - 1)), i.e. (num i - K den) n (n - 1) < den i.
+void set_bound(kdss_result* o, u128 num, uint64_t den, int kind, bool may_certify) {
+  o->bound_num.lo = (uint64_t)num;
+  o->bound_num.hi = (uint64_t)(num >> 64);
+  o->bound_den = den;
+  o->bound_kind = kind;
+  o->bound = den ? ((double)(uint64_t)(num >> 64) * 18446744073709551616.0 + (double)(uint64_t)num) / (double)den
+                 : 0.0;
+  o->certified = 0;
+  if (!may_certify || den == 0) return;
+  const u128 K = ((u128)o->dens_num.hi << 64) | o->dens_num.lo;
+  const uint64_t i = o->size;
+  if (i == 0) {   // no k-clique at all: density 0 and rho* = 0
+    o->certified = (num == 0) ? 1 : 0;
+    return;
+  }
+  const U256 a = u256_mul(num, i), b = u256_mul(K, den);
+  if (u256_cmp(a, b) < 0) return;   // the bound is below the density: no claim
+  const U256 diff = u256_sub(a, b);
+  const uint64_t n = o->n;
+  const U256 lhs = n >= 2 ? u256_mul64(u256_mul64(diff, n), n - 1) : U256{{0, 0, 0, 0}};
+  o->certified = u256_cmp(lhs, u256_mul((u128)den, i)) < 0 ? 1 : 0;
+}
+
 void fill_result(const kdss_plan* P, const DevResult& d, uint32_t T, kdss_result* out) {
   std::memset(out, 0, sizeof(*out));
   out->T = T;
@@ -1843,6 +2063,11 @@ void fill_result(const kdss_plan* P, const DevResult& d, uint32_t T, kdss_result
   out->density = d.size ? (double)d.dens_num / (double)d.size : 0.0;
   const double ub = (double)d.ub_hi * 18446744073709551616.0 + (double)d.ub_lo;
   out->upper_bound = T ? ub / (double)T : 0.0;
+  const bool fw = P->opts.update == 0;
+  if (d.tb_size)
+    set_bound(out, ((u128)d.tb_hi << 64) | d.tb_lo, (uint64_t)T * d.tb_size, 1, fw);
+  else
+    set_bound(out, ((u128)d.ub_hi << 64) | d.ub_lo, T, 0, fw);
 }
 
 int check_ws(const kdss_plan* P, void* d_ws, size_t ws_bytes) {
@@ -2047,6 +2272,8 @@ int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64
   const u128 bound = (u128)P->r0_max + (u128)T * P->c_k;
   rc = launch_extract(P, ws, d_r, d_r0, bound, d_order, st);
   if (rc) return rc;
+  rc = launch_top_bound(P, ws, d_r, d_r0, T, d_order, st);
+  if (rc) return rc;
   DevResult h;
   rc = read_result(P, ws, st, &h);
   if (rc) return rc;
@@ -2135,6 +2362,7 @@ int kdss_batch_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const 
     o.c_k.lo = (uint64_t)P->prob_ck[q];
     o.density = o.size ? (double)h[q].dens_num / (double)o.size : 0.0;
     o.upper_bound = (double)h[q].ub_lo / (double)T;
+    set_bound(&o, h[q].ub_lo, T, 0, P->opts.update == 0);
   }
   return KDSS_OK;
 }
@@ -2278,6 +2506,8 @@ int kdss_extract(kdss_plan* P, void* d_ws, size_t ws_bytes, const void* d_r, con
   if (rc) return rc;
   const u128 bound = ((u128)h.pad1[1] << 64) | h.pad1[0];
   rc = launch_extract(P, ws, d_r, d_r0, bound, d_order, st);
+  if (rc) return rc;
+  rc = launch_top_bound(P, ws, d_r, d_r0, T, d_order, st);
   if (rc) return rc;
   rc = read_result(P, ws, st, &h);
   if (rc) return rc;

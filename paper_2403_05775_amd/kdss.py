@@ -71,7 +71,8 @@ class PlanStats(C.Structure):
 class Result(C.Structure):
     _fields_ = [("T", C.c_uint32), ("size", C.c_uint32), ("n", C.c_uint32), ("width", C.c_int),
                 ("dens_num", U128), ("ub_num", U128), ("c_k", U128), ("density", C.c_double),
-                ("upper_bound", C.c_double)]
+                ("upper_bound", C.c_double), ("bound_num", U128), ("bound_den", C.c_uint64),
+                ("bound_kind", C.c_int), ("certified", C.c_int), ("bound", C.c_double)]
 
 
 class TraceRow(C.Structure):
@@ -342,6 +343,10 @@ class Solution:
     trace: list | None
     tree_stats: TreeStats
     plan_stats: PlanStats
+    bound_num: int = 0        # certified bound on rho*: bound_num / bound_den
+    bound_den: int = 1
+    bound_kind: int = 0       # 1: top-s bound, 0: max (r - r0) / T
+    certified: bool = False   # the density is rho*
 
     @property
     def nodes(self) -> np.ndarray:
@@ -369,7 +374,9 @@ def solve(graph, k: int, T: int, r0=None, width: int = 0, use_graph: bool = Fals
     out = Solution(r=loads_to_numpy(r, graph.n, plan.width),
                    order=order.cpu().numpy().view(np.uint32)[: graph.n].copy(), size=res.size,
                    dens_num=res.dens_num.value, ub_num=res.ub_num.value, T=res.T, c_k=res.c_k.value,
-                   width=res.width, trace=trace, tree_stats=tree.stats(), plan_stats=plan.stats())
+                   width=res.width, trace=trace, tree_stats=tree.stats(), plan_stats=plan.stats(),
+                   bound_num=res.bound_num.value, bound_den=res.bound_den, bound_kind=res.bound_kind,
+                   certified=bool(res.certified))
     plan.close()
     tree.close()
     return out

@@ -70,6 +70,11 @@ def test_chung_lu_1m_bit_exact(K, oracle_mod):
     assert np.array_equal(sol.order, ref["order"])
     assert (sol.size, sol.dens_num, sol.ub_num, sol.c_k) == (ref["size"], ref["dens_num"], ref["ub_num"],
                                                             ref["c_k"])
+    say("chung-lu 1M: certified bound")
+    want = oracle_mod.top_bound(ref["r"], None, 200, 5)
+    from fractions import Fraction
+    assert sol.bound_kind == 1 and Fraction(sol.bound_num, sol.bound_den) == want
+    assert sol.certified == oracle_mod.certified(ref["dens_num"], ref["size"], want, g.n)
 
 
 def test_batch_512_sampled(K, oracle_mod):
