@@ -37,6 +37,12 @@ WORKLOADS = {
     # iterations
     "pbupdate-1m": dict(kind="chung_lu", n=1_000_000, m=10_000_000, beta=2.5, seed=0, planted=40,
                         planted_p=0.9, k=5, T=200, update=1, cpu_iters=5),
+    # CPSample (Algorithm 4): 2,000,000 k-color path samples (draw seed 1) on
+    # R-MAT scale 16 at k = 4, then Frank-Wolfe over the distinct sampled
+    # cliques; on the Chung-Lu default graph only about 3e-5 of the paths are
+    # cliques at k = 5, too few to use
+    "cpsample-rmat16": dict(kind="sample", graph=dict(kind="rmat", scale=16, edge_factor=8, seed=0), k=4,
+                            t=2_000_000, draw_seed=1, T=64),
     # 512 Chung-Lu graphs (n in [1k, 50k], average degree 8-40, exponent 2.2-2.8,
     # seeds 1000 + g), each at k = 3, 4, 6, 8: 2048 problems in one plan
     "batch-512": dict(kind="batch", graphs=512, ks=(3, 4, 6, 8), T=64),
@@ -308,6 +314,65 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
+def sample_bench(w, args):
+    """CPSample: the sample tree is built once (sampler timed on its own, like
+    the tree build); a step runs T Frank-Wolfe iterations over the distinct
+    sampled cliques and the rho'_k extraction."""
+    import numpy as np
+    import torch
+    from paper_2403_05775_amd import kdss, synth
+    g = make_graph(w["graph"])
+    k, t, T = w["k"], w["t"], w["T"]
+    draws = synth.sample_draws(w["draw_seed"], t, k)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    tree = kdss.SampleTree(g, k, draws)
+    tree.close()
+    tree = kdss.SampleTree(g, k, draws)   # the second build is the timed one (the first loads the kernels)
+    info = tree.info
+    L = tree.stats().leaves
+    log(f"{t} samples: {info.cliques} cliques, {info.distinct} distinct, {info.paths.value} colour-increasing "
+        f"paths, {info.colors} colours; device {info.device_seconds:.3f} s, host {info.host_seconds:.3f} s")
+    plan = kdss.Plan(tree, T, use_graph=True)
+    ws = plan.alloc_workspace(dev)
+    plan.upload(ws)
+    r = plan.alloc_loads(dev)
+    order = torch.empty(g.n, dtype=torch.int32, device=dev)
+    for _ in range(args.warmup):
+        res, _ = plan.run(ws, T, r, order)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res, _ = plan.run(ws, T, r, order)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+    out = {
+        "metric": "SCT-leaf updates/s", "value": L * T / (ms / 1000.0), "unit": "leaf-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"cpsample-rmat16: {g.name}, k={k}, {t} samples, T={T}", "n": g.n, "m": g.m, "k": k,
+                   "samples": t, "T": T, "leaves": L, "parallelism": "single GPU, hipGraph iterations"},
+        "sampler": {"cliques": info.cliques, "distinct": info.distinct, "paths": info.paths.value,
+                    "colors": info.colors, "device_s": info.device_seconds, "host_s": info.host_seconds,
+                    "samples_per_s_device": t / info.device_seconds if info.device_seconds else None,
+                    "clique_fraction": info.cliques / t if t else 0.0},
+        "result": {"size": res.size, "dens_num": res.dens_num.value, "density_sampled": res.density},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        O.build()
+        h, p, mem = tree.export()
+        cl = mem.reshape(-1, k)
+        s0 = time.perf_counter()
+        O.solve_list(g.n, cl, k, T)
+        secs = time.perf_counter() - s0
+        out["cpu_baseline"] = dict(value=L * T / secs, unit="leaf-updates/s", cores=1, kind="oracle",
+                                   sample=f"the same distinct sample set, {T} synchronous Frank-Wolfe iterations "
+                                          f"and the extraction ({secs:.2f} s), one thread", seconds=secs)
+    tree.close()
+    print(json.dumps(out))
+
+
 def counter_traffic(workload, launch_bytes):
     """HBM bytes per leaf-credit launch from committed rocprofv3 counter runs,
     only while they describe the current kernel source."""
@@ -469,12 +534,15 @@ def main():
     if args.mode == "counters":
         counters_mode(WORKLOADS[args.workload], args)
         return
-    if WORKLOADS[args.workload]["kind"] in ("batch", "gnn"):
+    if WORKLOADS[args.workload]["kind"] in ("batch", "gnn", "sample"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
             sys.exit(2)
-        if WORKLOADS[args.workload]["kind"] == "batch":
+        kind = WORKLOADS[args.workload]["kind"]
+        if kind == "batch":
             batch_bench(WORKLOADS[args.workload], args)
+        elif kind == "sample":
+            sample_bench(WORKLOADS[args.workload], args)
         else:
             gnn_bench(WORKLOADS[args.workload], args)
         return

@@ -193,10 +193,45 @@ int kdss_sct_info(const kdss_sct *s, kdss_tree_stats *out);
 int kdss_sct_export(const kdss_sct *s, uint32_t *h, uint32_t *p, uint32_t *members,
                     uint64_t leaf_cap, uint64_t member_cap);
 
-/* Core number of every node (a by-product of the degeneracy order); core[n]. */
+/* Core number of every node (a by-product of the degeneracy order); core[n].
+ * KDSS_EUNSUPPORTED for a tree of sampled cliques (kdss_sample_build). */
 int kdss_sct_core_numbers(const kdss_sct *s, uint32_t *core, uint32_t n);
 
 void kdss_sct_free(kdss_sct *s);
+
+/* ---- CPSample (Algorithm 4): a tree of uniformly sampled k-cliques ----
+ * Samples t colour-increasing k-node paths uniformly (the CCPATH sampler the
+ * algorithm cites): nodes are coloured greedily in order of degree
+ * (descending, ties by ascending id), each taking the smallest colour no
+ * coloured neighbour has; P_j(v), the number of colour-increasing paths of j
+ * nodes from v, is counted for j = 1..k; a sample picks its start with weight
+ * P_k(v) and each next node among the higher-coloured neighbours with weight
+ * P_{j-1}(u), using the caller's random draws: h_draws (host) holds t * k
+ * pairs of u64 (high word, then low word), pair s of sample i being step s's
+ * 128-bit draw, reduced mod the step's total.  A k-clique sorted by colour is
+ * exactly one such path, so the samples that are cliques are uniform
+ * k-cliques.  The distinct sampled cliques C become the leaves (C, {}) of the
+ * returned tree: a plan and kdss_run on it run Algorithm 4's loop (here
+ * synchronous) over the sample set and its extraction by
+ * rho'_k(V_i) = |C_k(V_i) with sampled C| / i.  The path counts and walks run
+ * on the current device on `stream` (device memory is allocated and freed
+ * inside the call, which synchronises the stream); colouring and the
+ * de-duplication run on the host.
+ * Errors: KDSS_EINVAL (k < 2, null draws with t > 0), KDSS_EGRAPH,
+ * KDSS_ERANGE (k > 31), KDSS_EOVERFLOW (2^128 or more paths), KDSS_ENOMEM,
+ * KDSS_EHIP. */
+typedef struct {
+    uint64_t samples;         /* t                                             */
+    uint64_t cliques;         /* samples that are k-cliques                    */
+    uint64_t distinct;        /* distinct sampled cliques (the tree's leaves)  */
+    kdss_u128 paths;          /* colour-increasing k-node paths in g           */
+    uint32_t colors;          /* colours used                                  */
+    double device_seconds;    /* path counts and walks (synchronised)          */
+    double host_seconds;      /* colouring, uploads, de-duplication, the tree  */
+} kdss_sample_info;
+
+int kdss_sample_build(const kdss_csr *g, uint32_t k, uint64_t t, const uint64_t *h_draws, void *stream,
+                      kdss_sample_info *info, kdss_sct **out);
 
 /* Lays out s for the GPU, for runs of at most T_max iterations whose start
  * loads r0 are all <= r0_max.  Chooses the load width (u64 when

@@ -732,3 +732,152 @@ int kor_pb_run(uint32_t n, uint64_t npairs, const uint32_t *h, const uint32_t *p
     free(cur); free(nxt);
     return err;
 }
+
+/*
+ * ---- CPSample (Algorithm 4): uniform k-clique samples from k-color paths ----
+ *
+ * Colouring: nodes in order of degree (descending, ties by ascending id), each
+ * taking the smallest colour no already coloured neighbour has; adjacent nodes
+ * differ.  A k-color path is a path v_1 .. v_k whose colours increase; a
+ * k-clique sorted by colour is exactly one such path, so a uniform k-color path
+ * that happens to be a clique is a uniform k-clique (the paper's CCPATH
+ * sampler, read as colour-increasing paths).
+ *   P_j(v) = number of colour-increasing paths of j nodes starting at v:
+ *   P_1(v) = 1, P_j(v) = sum over neighbours u with c(u) > c(v) of P_{j-1}(u).
+ * Sample i uses the given random draws R(i, s) (two u64 each, high word first):
+ *   v_1 = the node (ascending ids) whose share of [0, sum_v P_k(v)) holds
+ *         R(i, 0) mod sum_v P_k(v);
+ *   v_{s+1}: x = R(i, s) mod P_{k-s+1}(v_s); the neighbours u of v_s with
+ *         c(u) > c(v_s), in adjacency order, take shares P_{k-s}(u); v_{s+1}
+ *         is the one whose share holds x.
+ * The path is a sample; it is kept (valid) when every pair of its nodes is
+ * adjacent.  Its ids are returned sorted.
+ */
+static uint32_t *g_deg_order_deg;
+static int cmp_deg_desc(const void *a, const void *b) {
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    if (g_deg_order_deg[x] != g_deg_order_deg[y]) return g_deg_order_deg[x] > g_deg_order_deg[y] ? -1 : 1;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+int kor_color(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, uint32_t *color) {
+    if (!row_ptr || !color) return KOR_EINVAL;
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    uint32_t *deg = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    uint32_t *seen = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n + 2));
+    if (!order || !deg || !seen) { free(order); free(deg); free(seen); return KOR_ENOMEM; }
+    for (uint32_t v = 0; v < n; ++v) {
+        order[v] = v;
+        deg[v] = (uint32_t)(row_ptr[v + 1] - row_ptr[v]);
+        color[v] = UINT32_MAX;
+    }
+    g_deg_order_deg = deg;
+    qsort(order, n, sizeof(uint32_t), cmp_deg_desc);
+    for (uint32_t c = 0; c < n + 2; ++c) seen[c] = UINT32_MAX;
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t v = order[i];
+        for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+            if (color[col[e]] != UINT32_MAX) seen[color[col[e]]] = v;   /* colours taken around v */
+        uint32_t c = 0;
+        while (seen[c] == v) ++c;
+        color[v] = c;
+    }
+    free(order); free(deg); free(seen);
+    return KOR_OK;
+}
+
+int kor_sample(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k, uint64_t t,
+               const uint64_t *draws, uint32_t *cliques, uint8_t *valid, uint64_t *paths_lo, uint64_t *paths_hi) {
+    if (k < 2 || !row_ptr || (t && (!draws || !cliques || !valid))) return KOR_EINVAL;
+    uint32_t *color = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    u128 *P = (u128 *)calloc((size_t)(n ? n : 1) * (size_t)(k + 1), sizeof(u128));   /* P[j * n + v] */
+    if (!color || !P) { free(color); free(P); return KOR_ENOMEM; }
+    int err = kor_color(n, row_ptr, col, color);
+    for (uint32_t v = 0; !err && v < n; ++v) P[1 * (size_t)n + v] = 1;
+    for (int j = 2; !err && j <= k; ++j)
+        for (uint32_t v = 0; v < n; ++v) {
+            u128 s = 0;
+            for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+                if (color[col[e]] > color[v]) s += P[(size_t)(j - 1) * n + col[e]];
+            P[(size_t)j * n + v] = s;
+        }
+    u128 total = 0;
+    for (uint32_t v = 0; !err && v < n; ++v) total += P[(size_t)k * n + v];
+    if (paths_lo) *paths_lo = (uint64_t)total;
+    if (paths_hi) *paths_hi = (uint64_t)(total >> 64);
+    graph_t g = {n, row_ptr, col};
+    uint32_t path[64];
+    for (uint64_t i = 0; !err && i < t; ++i) {
+        valid[i] = 0;
+        for (int s = 0; s < k; ++s) cliques[i * (uint64_t)k + s] = 0;
+        if (total == 0) continue;
+        const uint64_t *d = draws + 2 * i * (uint64_t)k;
+        u128 x = ((((u128)d[0]) << 64) | d[1]) % total;
+        uint32_t v = 0;
+        for (; v < n; ++v) {                       /* the start node's share */
+            u128 w = P[(size_t)k * n + v];
+            if (x < w) break;
+            x -= w;
+        }
+        path[0] = v;
+        for (int s = 1; s < k; ++s) {
+            const int j = k - s + 1;                /* nodes left on the path, v included */
+            u128 y = ((((u128)d[2 * s]) << 64) | d[2 * s + 1]) % P[(size_t)j * n + v];
+            uint32_t next = UINT32_MAX;
+            for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                uint32_t u = col[e];
+                if (color[u] <= color[v]) continue;
+                u128 w = P[(size_t)(j - 1) * n + u];
+                if (y < w) { next = u; break; }
+                y -= w;
+            }
+            v = next;
+            path[s] = v;
+        }
+        int clique = 1;
+        for (int a = 0; clique && a < k; ++a)
+            for (int b = a + 1; clique && b < k; ++b)
+                if (!has_edge(&g, path[a], path[b])) clique = 0;
+        qsort(path, (size_t)k, sizeof(uint32_t), cmp_u32);
+        for (int s = 0; s < k; ++s) cliques[i * (uint64_t)k + s] = path[s];
+        valid[i] = (uint8_t)clique;
+    }
+    free(color); free(P);
+    return err;
+}
+
+/* Synchronous Frank-Wolfe (every listed clique credits its minimum-load node)
+ * and the extraction, over a given list of k-cliques (ids ascending within a
+ * clique): Algorithm 4's loop and its rho'_k extraction over the sample set. */
+int kor_solve_list(uint32_t n, const uint32_t *cliques, uint64_t nclq, int k, uint32_t T, uint64_t *r_out,
+                   uint32_t *order_out, uint32_t *size_out, uint64_t *dens_out) {
+    if (k < 2 || T == 0 || !r_out || !order_out || !size_out || !dens_out || (nclq && !cliques)) return KOR_EINVAL;
+    graph_t g = {n, NULL, NULL};
+    run_t R;
+    memset(&R, 0, sizeof(R));
+    R.g = &g;
+    R.k = k;
+    R.stored = 1;
+    R.nclq = nclq;
+    R.cliques = (uint32_t *)cliques;
+    R.nthreads = 1;
+    set_threads(1);
+    u128 *r = (u128 *)calloc((size_t)(n ? n : 1), sizeof(u128));
+    uint64_t *delta = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+    uint32_t *pos = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    int err = (r && delta && pos) ? KOR_OK : KOR_ENOMEM;
+    for (uint32_t it = 1; !err && it <= T; ++it) {
+        memset(delta, 0, sizeof(uint64_t) * (size_t)n);
+        fw_ctx fc = {r, delta};
+        void *ctxs[1] = {&fc};
+        err = for_each_clique(&R, fw_fn, ctxs);
+        for (uint32_t u = 0; !err && u < n; ++u) r[u] += delta[u];
+    }
+    if (!err) {
+        uint64_t *hist[1] = {delta};
+        err = extract(&R, r, order_out, size_out, dens_out, hist, pos);
+    }
+    for (uint32_t u = 0; !err && u < n; ++u) r_out[u] = (uint64_t)r[u];
+    free(r); free(delta); free(pos);
+    return err;
+}

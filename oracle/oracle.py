@@ -66,6 +66,10 @@ def lib(path: str | None = None):
         L.kor_pb_pair.argtypes = [C.c_uint32, p32, C.c_uint32, C.c_uint32, C.c_int, p64, p64]
         L.kor_pb_run.argtypes = [C.c_uint32, C.c_uint64, p32, p32, p64, p32, C.c_int, C.c_uint32, C.c_int,
                                  p64, C.POINTER(C.c_double)]
+        L.kor_color.argtypes = [C.c_uint32, p64, p32, p32]
+        L.kor_sample.argtypes = [C.c_uint32, p64, p32, C.c_int, C.c_uint64, p64, p32, C.POINTER(C.c_uint8),
+                                 p64, p64]
+        L.kor_solve_list.argtypes = [C.c_uint32, p32, C.c_uint64, C.c_int, C.c_uint32, p64, p32, p32, p64]
         _libs[path] = L
     return _libs[path]
 
@@ -225,3 +229,47 @@ def certified(dens_num, size, bound, n):
     if bound < rho:
         return False
     return n < 2 or bound - rho < Fraction(1, n * (n - 1))
+
+
+def color(n, row_ptr, col, libpath=None) -> np.ndarray:
+    """Greedy colouring, nodes by degree (descending, ties by id)."""
+    rp, cl = _csr(row_ptr, col)
+    c = np.zeros(max(n, 1), dtype=np.uint32)
+    err = lib(libpath).kor_color(n, _p64(rp), _p32(cl), _p32(c))
+    if err:
+        raise RuntimeError(f"kor_color failed: {err}")
+    return c[:n]
+
+
+def sample(n, row_ptr, col, k, draws, libpath=None) -> dict:
+    """k-color path samples (Algorithm 4's first step) from given draws
+    (uint64[t, k, 2]): per sample its sorted ids and whether it is a k-clique,
+    plus the number of colour-increasing k-node paths."""
+    rp, cl = _csr(row_ptr, col)
+    d = np.ascontiguousarray(draws, dtype=np.uint64)
+    t = d.shape[0] if d.size else 0
+    out = np.zeros(max(t * k, 1), dtype=np.uint32)
+    valid = np.zeros(max(t, 1), dtype=np.uint8)
+    lo = C.c_uint64(0)
+    hi = C.c_uint64(0)
+    err = lib(libpath).kor_sample(n, _p64(rp), _p32(cl), k, t, _p64(d.reshape(-1)) if t else None, _p32(out),
+                                  valid.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(lo), C.byref(hi))
+    if err:
+        raise RuntimeError(f"kor_sample failed: {err}")
+    return dict(cliques=out[: t * k].reshape(t, k), valid=valid[:t].astype(bool),
+                paths=(hi.value << 64) | lo.value)
+
+
+def solve_list(n, cliques, k, T, libpath=None) -> dict:
+    """Synchronous Frank-Wolfe and the extraction over a given clique list."""
+    cl = np.ascontiguousarray(cliques, dtype=np.uint32).reshape(-1)
+    ncl = cl.size // k
+    r = np.zeros(max(n, 1), dtype=np.uint64)
+    order = np.zeros(max(n, 1), dtype=np.uint32)
+    size = C.c_uint32(0)
+    dens = np.zeros(1, dtype=np.uint64)
+    err = lib(libpath).kor_solve_list(n, _p32(cl) if ncl else None, ncl, k, T, _p64(r), _p32(order),
+                                      C.byref(size), _p64(dens))
+    if err:
+        raise RuntimeError(f"kor_solve_list failed: {err}")
+    return dict(r=r[:n], order=order[:n], size=size.value, dens_num=int(dens[0]))

@@ -68,6 +68,11 @@ class PlanStats(C.Structure):
                 ("gather", C.c_int), ("update", C.c_int), ("hot_nodes", C.c_uint32), ("hot_share", C.c_double)]
 
 
+class SampleInfo(C.Structure):
+    _fields_ = [("samples", C.c_uint64), ("cliques", C.c_uint64), ("distinct", C.c_uint64), ("paths", U128),
+                ("colors", C.c_uint32), ("device_seconds", C.c_double), ("host_seconds", C.c_double)]
+
+
 class Result(C.Structure):
     _fields_ = [("T", C.c_uint32), ("size", C.c_uint32), ("n", C.c_uint32), ("width", C.c_int),
                 ("dens_num", U128), ("ub_num", U128), ("c_k", U128), ("density", C.c_double),
@@ -84,6 +89,7 @@ EXPORTS = [
     "kdss_sct_export", "kdss_sct_core_numbers", "kdss_sct_free", "kdss_plan_create", "kdss_plan_info",
     "kdss_plan_free", "kdss_plan_upload", "kdss_run", "kdss_leaf_credit", "kdss_extract", "kdss_plan_timing",
     "kdss_batch_create", "kdss_batch_offsets", "kdss_batch_run", "kdss_plan_set_launch", "kdss_plan_autotune",
+    "kdss_sample_build",
 ]
 
 _lib = None
@@ -111,6 +117,8 @@ def lib():
     L.kdss_sct_export.argtypes = [vp, p32, p32, p32, C.c_uint64, C.c_uint64]
     L.kdss_sct_core_numbers.argtypes = [vp, p32, C.c_uint32]
     L.kdss_sct_free.argtypes = [vp]
+    L.kdss_sample_build.argtypes = [C.POINTER(Csr), C.c_uint32, C.c_uint64, p64, vp, C.POINTER(SampleInfo),
+                                    C.POINTER(vp)]
     L.kdss_sct_free.restype = None
     L.kdss_plan_create.argtypes = [vp, C.c_uint32, C.c_uint64, C.POINTER(Opts), C.POINTER(vp)]
     L.kdss_plan_info.argtypes = [vp, C.POINTER(PlanStats)]
@@ -195,6 +203,25 @@ class Tree:
             self.close()
         except Exception:
             pass
+
+
+class SampleTree(Tree):
+    """Algorithm 4's sample set as a clique tree: t colour-increasing k-node
+    paths sampled on the GPU with the given draws (uint64[t, k, 2]); the
+    distinct ones that are k-cliques become leaves (C, {})."""
+
+    def __init__(self, graph, k: int, draws, stream=None):
+        c, keep = _csr(graph)
+        d = np.ascontiguousarray(draws, dtype=np.uint64)
+        t = d.shape[0] if d.size else 0
+        h = C.c_void_p()
+        info = SampleInfo()
+        _check(lib().kdss_sample_build(C.byref(c), k, t, d.ctypes.data_as(C.POINTER(C.c_uint64)) if t else None,
+                                       _stream(stream) if t else None, C.byref(info), C.byref(h)),
+               "kdss_sample_build")
+        self._h = h
+        self.n, self.k = graph.n, k
+        self.info = info
 
 
 def _ptr(t) -> int | None:

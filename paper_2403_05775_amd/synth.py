@@ -66,6 +66,13 @@ class Stream:
         return lo + np.minimum((self.uniform(count) * width).astype(np.int64), width - 1)
 
 
+def sample_draws(seed: int, t: int, k: int) -> np.ndarray:
+    """The random draws of t k-color path samples: uint64[t, k, 2], two words
+    (high, low) per step; stream 97 of the seed.  Both the GPU sampler and
+    the CPU reference take them as input."""
+    return Stream(seed, 97).u64(2 * k * t).reshape(t, k, 2)
+
+
 @dataclass
 class Graph:
     n: int

@@ -206,6 +206,23 @@ def test_update_option():
         assert e.value.status == kdss.EINVAL, kw
 
 
+def test_sample_build_arguments_and_empty_sample():
+    g = synth.chung_lu(300, 2000, 2.3, seed=4, planted=10)
+    c, keep = kdss._csr(g)
+    L = kdss.lib()
+    h = C.c_void_p()
+    assert L.kdss_sample_build(C.byref(c), 4, 5, None, None, None, C.byref(h)) == kdss.EINVAL   # no draws
+    assert L.kdss_sample_build(C.byref(c), 1, 0, None, None, None, C.byref(h)) == kdss.EINVAL   # k < 2
+    assert L.kdss_sample_build(C.byref(c), 32, 0, None, None, None, C.byref(h)) == kdss.ERANGE  # k > 31
+    # no samples: no device work, an empty tree with no core numbers
+    t = kdss.SampleTree(g, 4, np.zeros((0, 4, 2), dtype=np.uint64))
+    st = t.stats()
+    assert (st.leaves, st.members, st.c_k.value, t.info.samples, t.info.colors > 0) == (0, 0, 0, 0, True)
+    with pytest.raises(kdss.KdssError) as e:
+        t.core_numbers()
+    assert e.value.status == kdss.EUNSUPPORTED
+
+
 def test_run_rejects_bad_arguments_before_device_work():
     g = synth.complete_graph(8)
     t = kdss.Tree(g, 3)

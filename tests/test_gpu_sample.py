@@ -1,0 +1,82 @@
+"""CPSample (Algorithm 4) through the C-ABI against the CPU oracle, bit for bit:
+the GPU sampler's distinct sampled cliques equal the oracle sampler's on the
+same draws; Frank-Wolfe and the rho'_k extraction over that sample set equal
+the oracle's over its own set."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2403_05775_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_05775_amd import kdss
+    kdss.lib()
+    return kdss
+
+
+def oracle_set(O, g, k, draws):
+    s = O.sample(g.n, g.row_ptr, g.col, k, draws)
+    distinct = sorted({tuple(int(x) for x in row) for row, v in zip(s["cliques"], s["valid"]) if v})
+    return s, distinct
+
+
+def gpu_set(tree, k):
+    h, p, m = tree.export()
+    assert np.all(h == k) and np.all(p == 0)
+    return [tuple(int(x) for x in m[i * k:(i + 1) * k]) for i in range(len(h))]
+
+
+def run(K, tree, T):
+    plan = K.Plan(tree, T)
+    ws = plan.alloc_workspace()
+    plan.upload(ws)
+    r = plan.alloc_loads()
+    order = torch.empty(max(tree.n, 1), dtype=torch.int32, device="cuda")
+    res, _ = plan.run(ws, T, r, order)
+    torch.cuda.synchronize()
+    return (r.cpu().numpy().view(np.uint64)[: tree.n], order.cpu().numpy().view(np.uint32)[: tree.n], res)
+
+
+def check(K, O, g, k, t, T, seed, label):
+    print(f"CPSample {label} n={g.n} k={k} t={t} T={T}", flush=True)
+    draws = synth.sample_draws(seed, t, k)
+    tree = K.SampleTree(g, k, draws)
+    s, want = oracle_set(O, g, k, draws)
+    assert tree.info.paths.value == s["paths"] and tree.info.cliques == int(s["valid"].sum())
+    assert gpu_set(tree, k) == want
+    assert tree.stats().c_k.value == len(want)
+    r, order, res = run(K, tree, T)
+    ref = O.solve_list(g.n, np.array(want, dtype=np.uint32).reshape(-1, k), k, T)
+    assert np.array_equal(r, ref["r"]) and np.array_equal(order, ref["order"])
+    assert (res.size, res.dens_num.value) == (ref["size"], ref["dens_num"])
+    tree.close()
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_sample_random_graphs(K, oracle_mod, seed):
+    rs = synth.Stream(seed, 85)
+    n = int(rs.integers(50, 800)[0])
+    g = synth.chung_lu(n, int(rs.integers(3 * n, 10 * n)[0]), 2.2, seed=seed, planted=int(rs.integers(8, 30)[0]))
+    k = int(rs.integers(3, 7)[0])
+    check(K, oracle_mod, g, k, int(rs.integers(100, 20000)[0]), int(rs.integers(1, 40)[0]), seed, f"seed={seed}")
+
+
+def test_sample_planted_clique_found(K, oracle_mod):
+    """A sparse graph with a planted 25-clique, 50,000 samples (most of them
+    from the planted clique)."""
+    g = synth.erdos_renyi(400, 0.02, seed=3, planted_clique=25)
+    check(K, oracle_mod, g, 4, 50000, 32, 3, "planted")
+
+
+def test_sample_chung_lu_1m(K, oracle_mod):
+    """The benchmarked graph (n = 1,000,000, m = 10,000,000, k = 5), 200,000 samples."""
+    g = synth.chung_lu(1_000_000, 10_000_000, 2.5, seed=0, planted=40, planted_p=0.9)
+    check(K, oracle_mod, g, 5, 200_000, 16, 1, "chung-lu 1M")
