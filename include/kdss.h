@@ -185,6 +185,17 @@ int kdss_csr_validate(const kdss_csr *g);
  * KDSS_EOVERFLOW (|C_k| >= 2^128), KDSS_ENOMEM. */
 int kdss_sct_build(const kdss_csr *g, uint32_t k, uint32_t threads, kdss_sct **out);
 
+/* The same tree built on the current device on `stream`: the degeneracy order
+ * on the host, then one thread per start node runs the pivoting recursion over
+ * its later neighbours (local adjacency bitsets, explicit stack); a counting
+ * pass and a writing pass over chunks of start nodes.  The leaves may differ
+ * from kdss_sct_build's (another valid tree: every k-clique in exactly one
+ * kept leaf), so every result computed on it is the same.  Device memory is
+ * allocated and freed inside the call, which synchronises the stream.
+ * Errors: as kdss_sct_build, plus KDSS_EUNSUPPORTED (degeneracy above 256) and
+ * KDSS_EHIP. */
+int kdss_sct_build_gpu(const kdss_csr *g, uint32_t k, void *stream, kdss_sct **out);
+
 int kdss_sct_info(const kdss_sct *s, kdss_tree_stats *out);
 
 /* Copies the kept leaves to host arrays: h[i], p[i] per leaf and the members

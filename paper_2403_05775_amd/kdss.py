@@ -89,7 +89,7 @@ EXPORTS = [
     "kdss_sct_export", "kdss_sct_core_numbers", "kdss_sct_free", "kdss_plan_create", "kdss_plan_info",
     "kdss_plan_free", "kdss_plan_upload", "kdss_run", "kdss_leaf_credit", "kdss_extract", "kdss_plan_timing",
     "kdss_batch_create", "kdss_batch_offsets", "kdss_batch_run", "kdss_plan_set_launch", "kdss_plan_autotune",
-    "kdss_sample_build",
+    "kdss_sample_build", "kdss_sct_build_gpu",
 ]
 
 _lib = None
@@ -117,6 +117,7 @@ def lib():
     L.kdss_sct_export.argtypes = [vp, p32, p32, p32, C.c_uint64, C.c_uint64]
     L.kdss_sct_core_numbers.argtypes = [vp, p32, C.c_uint32]
     L.kdss_sct_free.argtypes = [vp]
+    L.kdss_sct_build_gpu.argtypes = [C.POINTER(Csr), C.c_uint32, vp, C.POINTER(vp)]
     L.kdss_sample_build.argtypes = [C.POINTER(Csr), C.c_uint32, C.c_uint64, p64, vp, C.POINTER(SampleInfo),
                                     C.POINTER(vp)]
     L.kdss_sct_free.restype = None
@@ -203,6 +204,19 @@ class Tree:
             self.close()
         except Exception:
             pass
+
+
+class GpuTree(Tree):
+    """The k-pruned succinct clique tree built on the GPU (kdss_sct_build_gpu)."""
+
+    def __init__(self, graph, k: int, stream=None):
+        c, keep = _csr(graph)
+        h = C.c_void_p()
+        _check(lib().kdss_sct_build_gpu(C.byref(c), k, _stream(stream) if stream is not None else None,
+                                        C.byref(h)),
+               "kdss_sct_build_gpu")
+        self._h = h
+        self.n, self.k = graph.n, k
 
 
 class SampleTree(Tree):

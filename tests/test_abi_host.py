@@ -223,6 +223,12 @@ def test_sample_build_arguments_and_empty_sample():
     assert e.value.status == kdss.EUNSUPPORTED
 
 
+def test_gpu_tree_build_rejects_large_degeneracy_before_device_work():
+    with pytest.raises(kdss.KdssError) as e:
+        kdss.GpuTree(synth.complete_graph(300), 3)   # degeneracy 299 > 256
+    assert e.value.status == kdss.EUNSUPPORTED
+
+
 def test_run_rejects_bad_arguments_before_device_work():
     g = synth.complete_graph(8)
     t = kdss.Tree(g, 3)
