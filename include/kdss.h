@@ -186,12 +186,14 @@ int kdss_csr_validate(const kdss_csr *g);
 int kdss_sct_build(const kdss_csr *g, uint32_t k, uint32_t threads, kdss_sct **out);
 
 /* The same tree built on the current device on `stream`: the degeneracy order
- * on the host, then one thread per start node runs the pivoting recursion over
- * its later neighbours (local adjacency bitsets, explicit stack); a counting
- * pass and a writing pass over chunks of start nodes.  The leaves may differ
- * from kdss_sct_build's (another valid tree: every k-clique in exactly one
- * kept leaf), so every result computed on it is the same.  Device memory is
- * allocated and freed inside the call, which synchronises the stream.
+ * on the host; on the device the graph oriented along it (each node keeps its
+ * later neighbours), then one thread per start node runs the pivoting
+ * recursion over its later neighbours (local adjacency bitsets, explicit
+ * stack), heaviest start nodes first; a counting pass and a writing pass over
+ * chunks of start nodes (scratch up to 8 GiB per chunk).  The leaves may
+ * differ from kdss_sct_build's (another valid tree: every k-clique in exactly
+ * one kept leaf), so every result computed on it is the same.  Device memory
+ * is allocated and freed inside the call, which synchronises the stream.
  * Errors: as kdss_sct_build, plus KDSS_EUNSUPPORTED (degeneracy above 256) and
  * KDSS_EHIP. */
 int kdss_sct_build_gpu(const kdss_csr *g, uint32_t k, void *stream, kdss_sct **out);

@@ -1,9 +1,12 @@
 // The k-pruned succinct clique tree (paper: Sec. 2, Lemmas 3-5) built on the
-// GPU: one thread per start node v.  v's later neighbours in the degeneracy
-// order (at most the degeneracy, here at most kSctMaxLocal) get local indices
-// and adjacency bitsets; the pivoting recursion then runs with an explicit
-// stack, both in a per-thread slice of global scratch (word i of thread t at
-// i * threads + t, so a wavefront's equal-index accesses coalesce):
+// GPU.  The graph is first oriented along the degeneracy order: out(v) holds
+// v's later neighbours, ascending by id, at most D (the degeneracy) of them.
+// One thread per start node v then gives out(v) local indices, builds their
+// adjacency bitsets (out(x) of each member x merged with out(v): every edge
+// inside out(v) is found once, from its earlier end) and runs the pivoting
+// recursion with an explicit stack, both in a per-thread slice of global
+// scratch sized by D (word i of thread t at i * threads + t, so a wavefront's
+// equal-index accesses coalesce):
 //   node (H, P, S): h = |H| = k: the leaf (H, {}); h + p + |S| < k: nothing;
 //   S empty: the leaf (H, P) when p >= k - h; otherwise a pivot q of S with
 //   the most neighbours in S: (H, P + q, S and N(q)), then for each w of S
@@ -12,8 +15,10 @@
 // Every k-clique of the graph lies in exactly one leaf (the tree of a node
 // covers the cliques whose earliest node it is); the leaves may differ from
 // the host build's, and any such tree gives the same results.
-// Two passes over chunks of start nodes: counts, then the leaves written at
-// the prefix-sum offsets.
+// Start nodes run in decreasing |out(v)| (the heaviest recursions first, and
+// wavefronts of similar work); nodes with |out(v)| + 1 < k hold no k-clique
+// and are skipped.  Two passes over chunks of start nodes: counts, then the
+// leaves written at the prefix-sum offsets.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,13 +32,15 @@ using kdss::u128;
 
 namespace {
 
-constexpr uint32_t kSctMaxLocal = 256;                 // largest later-neighbour set handled
-constexpr uint32_t kSctWords = kSctMaxLocal / 64;      // bitset words
-constexpr uint32_t kSctFrames = kSctMaxLocal + 2;      // recursion depth <= |S| + 1
-constexpr uint32_t kFrameWords = 2 * kSctWords + 1;    // S, NN, (q | h << 16 | p << 32 | stage << 48)
-constexpr uint32_t kWords64 = kSctMaxLocal * kSctWords + kSctFrames * kFrameWords;
-constexpr uint32_t kWords32 = kSctMaxLocal + 32 + kSctMaxLocal;   // local ids, hold list, pivot list
-constexpr uint32_t kChunk = 32768;                     // start nodes per launch
+constexpr uint32_t kSctMaxLocal = 256;                 // largest degeneracy handled
+constexpr uint32_t kSctMaxHold = 32;                   // hold list entries (k <= 31)
+constexpr size_t kSctScratchBudget = size_t(8) << 30;  // per-chunk scratch bytes
+
+// Scratch words of one thread for degeneracy D with W bitset words:
+// adjacency D * W, frames (D + 2) * (2 W + 1) in 64-bit words; hold and pivot
+// lists kSctMaxHold + D in 32-bit words.
+inline size_t sct_words64(uint32_t D, uint32_t W) { return (size_t)D * W + (size_t)(D + 2) * (2 * W + 1); }
+inline size_t sct_words32(uint32_t D) { return kSctMaxHold + (size_t)D; }
 
 int sct_hip_fail(hipError_t e, const char* what) {
   return kdss::fail(KDSS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -45,23 +52,43 @@ int sct_hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return sct_hip_fail(e_, what); \
   } while (0)
 
-__device__ inline bool has_edge_dev(const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col, uint32_t a,
-                                    uint32_t b) {
-  uint64_t lo = rp[a], hi = rp[a + 1];
-  while (lo < hi) {
-    const uint64_t mid = lo + (hi - lo) / 2;
-    if (col[mid] < b) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo < rp[a + 1] && col[lo] == b;
+// out-degree of every node along the order (rank): ocnt[v] = |out(v)|.
+__global__ __launch_bounds__(256) void orient_count_kernel(const uint64_t* __restrict__ rp,
+                                                           const uint32_t* __restrict__ col,
+                                                           const uint32_t* __restrict__ rank, uint32_t n,
+                                                           uint32_t* __restrict__ ocnt) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t rv = rank[v];
+  uint32_t c = 0;
+  for (uint64_t e = rp[v]; e < rp[v + 1]; ++e) c += rank[col[e]] > rv;
+  ocnt[v] = c;
 }
 
-// One thread per start node v0 + tid.  write = 0: counts[2 t] = leaves,
-// counts[2 t + 1] = members.  write = 1: leaves from leaf_off[t], members from
-// member_off[t]; hp[leaf] = h | p << 8.  *err: 1 = a later-neighbour set above
-// kSctMaxLocal, 2 = the stack would overflow (neither writes out of bounds).
-__global__ __launch_bounds__(64) void sct_kernel(const uint64_t* __restrict__ rp, const uint32_t* __restrict__ col,
-                                                 const uint32_t* __restrict__ rank, uint32_t n, uint32_t k,
+// out(v) at orp[v], ascending by id (the row's order).
+__global__ __launch_bounds__(256) void orient_fill_kernel(const uint64_t* __restrict__ rp,
+                                                          const uint32_t* __restrict__ col,
+                                                          const uint32_t* __restrict__ rank, uint32_t n,
+                                                          const uint64_t* __restrict__ orp,
+                                                          uint32_t* __restrict__ ocol) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t rv = rank[v];
+  uint64_t at = orp[v];
+  for (uint64_t e = rp[v]; e < rp[v + 1]; ++e) {
+    const uint32_t u = col[e];
+    if (rank[u] > rv) ocol[at++] = u;
+  }
+}
+
+// One thread per start node perm[v0 + t].  D: the degeneracy (every |out(v)|
+// is at most D, W * 64 >= D).  write = 0: counts[2 t] = leaves, counts[2 t + 1]
+// = members.  write = 1: leaves from leaf_off[t], members from member_off[t];
+// hp[leaf] = h | p << 8.  *err: 1 = an out-list above D, 2 = the stack would
+// overflow (neither writes out of bounds).
+template <uint32_t W>
+__global__ __launch_bounds__(64) void sct_kernel(const uint64_t* __restrict__ orp, const uint32_t* __restrict__ ocol,
+                                                 const uint32_t* __restrict__ perm, uint32_t k, uint32_t D,
                                                  uint32_t v0, uint32_t count, uint64_t* __restrict__ s64,
                                                  uint32_t* __restrict__ s32, int write,
                                                  uint64_t* __restrict__ counts, const uint64_t* __restrict__ leaf_off,
@@ -69,38 +96,48 @@ __global__ __launch_bounds__(64) void sct_kernel(const uint64_t* __restrict__ rp
                                                  uint32_t* __restrict__ members, int* __restrict__ err) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
-  const uint32_t v = v0 + t;
+  const uint32_t v = perm[v0 + t];
   const size_t stride = count;
-  auto A = [&](uint32_t i, uint32_t w) -> uint64_t& { return s64[((size_t)i * kSctWords + w) * stride + t]; };
+  const size_t fbase = (size_t)D * W;
+  const uint32_t nframes = D + 2;
+  auto A = [&](uint32_t i, uint32_t w) -> uint64_t& { return s64[((size_t)i * W + w) * stride + t]; };
   auto F = [&](uint32_t f, uint32_t w) -> uint64_t& {
-    return s64[((size_t)kSctMaxLocal * kSctWords + (size_t)f * kFrameWords + w) * stride + t];
+    return s64[(fbase + (size_t)f * (2 * W + 1) + w) * stride + t];
   };
-  auto L = [&](uint32_t i) -> uint32_t& { return s32[(size_t)i * stride + t]; };
-  auto Hl = [&](uint32_t i) -> uint32_t& { return s32[((size_t)kSctMaxLocal + i) * stride + t]; };
-  auto Pl = [&](uint32_t i) -> uint32_t& { return s32[((size_t)kSctMaxLocal + 32 + i) * stride + t]; };
+  auto Hl = [&](uint32_t i) -> uint32_t& { return s32[(size_t)i * stride + t]; };
+  auto Pl = [&](uint32_t i) -> uint32_t& { return s32[((size_t)kSctMaxHold + i) * stride + t]; };
   uint64_t nleaves = 0, nmembers = 0;
-  uint64_t lo_leaf = write ? leaf_off[t] : 0, lo_mem = write ? member_off[t] : 0;
-  // later neighbours of v (ascending ids, as in its row)
-  uint32_t d = 0;
-  const uint32_t rv = rank[v];
-  for (uint64_t e = rp[v]; e < rp[v + 1]; ++e) {
-    const uint32_t u = col[e];
-    if (rank[u] <= rv) continue;
-    if (d == kSctMaxLocal) {
-      atomicOr(err, 1);
-      return;
-    }
-    L(d++) = u;
+  const uint64_t lo_leaf = write ? leaf_off[t] : 0, lo_mem = write ? member_off[t] : 0;
+  const uint64_t ob = orp[v];
+  const uint32_t d = (uint32_t)(orp[v + 1] - ob);
+  const uint32_t* __restrict__ L = ocol + ob;
+  if (d > D || d > W * 64) {
+    atomicOr(err, 1);
+    return;
   }
-  if (d + 1 >= k || (k == 2 && d >= 1)) {
+  if (d + 1 >= k) {
     for (uint32_t i = 0; i < d; ++i)
-      for (uint32_t w = 0; w < kSctWords; ++w) A(i, w) = 0;
-    for (uint32_t i = 0; i < d; ++i)
-      for (uint32_t j = i + 1; j < d; ++j)
-        if (has_edge_dev(rp, col, L(i), L(j))) {
+      for (uint32_t w = 0; w < W; ++w) A(i, w) = 0;
+    // edges inside out(v): merge out(x) with out(v), both ascending by id
+    for (uint32_t i = 0; i < d; ++i) {
+      const uint32_t x = L[i];
+      uint64_t a = orp[x];
+      const uint64_t ae = orp[x + 1];
+      uint32_t j = 0;
+      while (a < ae && j < d) {
+        const uint32_t ya = ocol[a], yb = L[j];
+        if (ya < yb) {
+          ++a;
+        } else if (ya > yb) {
+          ++j;
+        } else {
           A(i, j >> 6) |= 1ull << (j & 63);
           A(j, i >> 6) |= 1ull << (i & 63);
+          ++a;
+          ++j;
         }
+      }
+    }
     auto emit = [&](uint32_t h, uint32_t p) {
       if (write) {
         hp[lo_leaf + nleaves] = h | (p << 8);
@@ -111,22 +148,24 @@ __global__ __launch_bounds__(64) void sct_kernel(const uint64_t* __restrict__ rp
       ++nleaves;
       nmembers += h + p;
     };
-    // root frame: H = {v}, P = {}, S = all later neighbours
+    // root frame: H = {v}, P = {}, S = all of out(v)
     Hl(0) = v;
-    for (uint32_t w = 0; w < kSctWords; ++w) {
+    for (uint32_t w = 0; w < W; ++w) {
       const uint32_t lo = w * 64;
       F(0, w) = d >= lo + 64 ? ~0ull : (d > lo ? (1ull << (d - lo)) - 1 : 0ull);
     }
-    F(0, 2 * kSctWords) = (uint64_t)1 << 16;   // q 0, h 1, p 0, stage 0
+    F(0, 2 * W) = (uint64_t)1 << 16;   // q 0, h 1, p 0, stage 0
     uint32_t depth = 1;
     while (depth > 0) {
       const uint32_t f = depth - 1;
-      const uint64_t meta = F(f, 2 * kSctWords);
+      const uint64_t meta = F(f, 2 * W);
       const uint32_t h = (uint32_t)(meta >> 16) & 0xFFFFu, p = (uint32_t)(meta >> 32) & 0xFFFFu;
       const uint32_t stage = (uint32_t)(meta >> 48);
+      uint64_t S[W];
+      for (uint32_t w = 0; w < W; ++w) S[w] = F(f, w);
       if (stage == 0) {
         uint32_t cs = 0;
-        for (uint32_t w = 0; w < kSctWords; ++w) cs += __popcll(F(f, w));
+        for (uint32_t w = 0; w < W; ++w) cs += __popcll(S[w]);
         if (h == k) { emit(h, 0); --depth; continue; }
         if (h + p + cs < k) { --depth; continue; }
         if (cs == 0) {
@@ -137,38 +176,46 @@ __global__ __launch_bounds__(64) void sct_kernel(const uint64_t* __restrict__ rp
         // pivot: the member of S with the most neighbours in S (lowest index on ties)
         uint32_t q = 0, best = 0;
         bool first = true;
-        for (uint32_t w = 0; w < kSctWords; ++w) {
-          uint64_t bits = F(f, w);
+        for (uint32_t w = 0; w < W; ++w) {
+          uint64_t bits = S[w];
           while (bits) {
             const uint32_t i = w * 64 + (uint32_t)__ffsll((unsigned long long)bits) - 1;
             bits &= bits - 1;
             uint32_t c = 0;
-            for (uint32_t x = 0; x < kSctWords; ++x) c += __popcll(A(i, x) & F(f, x));
+            for (uint32_t x = 0; x < W; ++x) c += __popcll(A(i, x) & S[x]);
             if (first || c > best) { q = i; best = c; first = false; }
           }
         }
-        for (uint32_t w = 0; w < kSctWords; ++w) F(f, kSctWords + w) = F(f, w) & ~A(q, w);
-        F(f, kSctWords + (q >> 6)) &= ~(1ull << (q & 63));
-        F(f, 2 * kSctWords) = (uint64_t)q | ((uint64_t)h << 16) | ((uint64_t)p << 32) | (1ull << 48);
-        if (depth == kSctFrames || p >= kSctMaxLocal) { atomicOr(err, 2); return; }
-        Pl(p) = L(q);
-        for (uint32_t w = 0; w < kSctWords; ++w) F(depth, w) = F(f, w) & A(q, w);
-        F(depth, 2 * kSctWords) = ((uint64_t)h << 16) | ((uint64_t)(p + 1) << 32);
+        if (depth == nframes || p >= D) { atomicOr(err, 2); return; }
+        uint64_t Aq[W];
+        for (uint32_t w = 0; w < W; ++w) Aq[w] = A(q, w);
+        for (uint32_t w = 0; w < W; ++w) {
+          uint64_t nn = S[w] & ~Aq[w];
+          if (w == (q >> 6)) nn &= ~(1ull << (q & 63));
+          F(f, W + w) = nn;
+        }
+        F(f, 2 * W) = (uint64_t)q | ((uint64_t)h << 16) | ((uint64_t)p << 32) | (1ull << 48);
+        Pl(p) = L[q];
+        for (uint32_t w = 0; w < W; ++w) F(depth, w) = S[w] & Aq[w];
+        F(depth, 2 * W) = ((uint64_t)h << 16) | ((uint64_t)(p + 1) << 32);
         ++depth;
         continue;
       }
       // stage 1: the next non-neighbour of the pivot, as a hold node
-      uint32_t w0 = kSctWords;
-      for (uint32_t w = 0; w < kSctWords; ++w)
-        if (F(f, kSctWords + w)) { w0 = w; break; }
-      if (w0 == kSctWords) { --depth; continue; }
-      const uint32_t wi = w0 * 64 + (uint32_t)__ffsll((unsigned long long)F(f, kSctWords + w0)) - 1;
-      F(f, kSctWords + w0) &= ~(1ull << (wi & 63));
-      if (depth == kSctFrames || h >= 32) { atomicOr(err, 2); return; }
-      Hl(h) = L(wi);
-      for (uint32_t w = 0; w < kSctWords; ++w) F(depth, w) = F(f, w) & A(wi, w);
-      F(f, wi >> 6) &= ~(1ull << (wi & 63));   // later branches exclude w
-      F(depth, 2 * kSctWords) = ((uint64_t)(h + 1) << 16) | ((uint64_t)p << 32);
+      uint32_t w0 = W;
+      uint64_t nw = 0;
+      for (uint32_t w = 0; w < W; ++w) {
+        nw = F(f, W + w);
+        if (nw) { w0 = w; break; }
+      }
+      if (w0 == W) { --depth; continue; }
+      const uint32_t wi = w0 * 64 + (uint32_t)__ffsll((unsigned long long)nw) - 1;
+      F(f, W + w0) = nw & (nw - 1);
+      if (depth == nframes || h >= kSctMaxHold) { atomicOr(err, 2); return; }
+      Hl(h) = L[wi];
+      for (uint32_t w = 0; w < W; ++w) F(depth, w) = S[w] & A(wi, w);
+      F(f, wi >> 6) = S[wi >> 6] & ~(1ull << (wi & 63));   // later branches exclude w
+      F(depth, 2 * W) = ((uint64_t)(h + 1) << 16) | ((uint64_t)p << 32);
       ++depth;
     }
   }
@@ -176,6 +223,18 @@ __global__ __launch_bounds__(64) void sct_kernel(const uint64_t* __restrict__ rp
     counts[2 * (size_t)t] = nleaves;
     counts[2 * (size_t)t + 1] = nmembers;
   }
+}
+
+}  // namespace
+
+namespace {
+
+template <uint32_t W>
+void launch_sct(uint32_t blocks, hipStream_t st, const uint64_t* orp, const uint32_t* ocol, const uint32_t* perm,
+                uint32_t k, uint32_t D, uint32_t v0, uint32_t c, uint64_t* s64, uint32_t* s32, int write,
+                uint64_t* counts, const uint64_t* loff, const uint64_t* moff, uint32_t* hp, uint32_t* mem, int* err) {
+  sct_kernel<W><<<blocks, 64, 0, st>>>(orp, ocol, perm, k, D, v0, c, s64, s32, write, counts, loff, moff, hp, mem,
+                                       err);
 }
 
 }  // namespace
@@ -196,11 +255,12 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
   T.n = n;
   T.k = k;
   kdss::degeneracy_order(g, &T.deg);
-  if (T.deg.degeneracy > kSctMaxLocal) {
+  const uint32_t D = T.deg.degeneracy;
+  if (D > kSctMaxLocal) {
     delete s;
     return kdss::fail(KDSS_EUNSUPPORTED, "the GPU tree build handles degeneracy up to 256");
   }
-  std::vector<uint64_t> counts(2 * (size_t)n);
+  const uint32_t W = std::max<uint32_t>(1, (D + 63) / 64);
   std::vector<void*> bufs;
   auto cleanup = [&]() {
     for (void* p : bufs) (void)hipFree(p);
@@ -210,63 +270,99 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
     bufs.push_back(*p);
     return KDSS_OK;
   };
-  uint64_t *rp = nullptr, *s64 = nullptr, *dcounts = nullptr, *loff = nullptr, *moff = nullptr;
-  uint32_t *col = nullptr, *rank = nullptr, *s32 = nullptr, *dhp = nullptr, *dmem = nullptr;
-  int* derr = nullptr;
-  const uint32_t chunk = std::min<uint32_t>(std::max<uint32_t>(n, 1), kChunk);
-  int rcx = KDSS_OK;
-  if ((rcx = alloc((void**)&rp, ((size_t)n + 1) * 8)) || (rcx = alloc((void**)&col, g->nnz * 4)) ||
-      (rcx = alloc((void**)&rank, (size_t)n * 4)) || (rcx = alloc((void**)&s64, (size_t)chunk * kWords64 * 8)) ||
-      (rcx = alloc((void**)&s32, (size_t)chunk * kWords32 * 4)) ||
-      (rcx = alloc((void**)&dcounts, (size_t)chunk * 16)) || (rcx = alloc((void**)&loff, (size_t)chunk * 8)) ||
-      (rcx = alloc((void**)&moff, (size_t)chunk * 8)) || (rcx = alloc((void**)&derr, sizeof(int)))) {
-    cleanup();
-    delete s;
-    return rcx;
-  }
   auto run = [&]() -> int {
+    uint64_t *rp = nullptr, *orp = nullptr;
+    uint32_t *col = nullptr, *rank = nullptr, *ocnt = nullptr, *ocol = nullptr, *perm = nullptr;
+    int* derr = nullptr;
+    int r = KDSS_OK;
+    if ((r = alloc((void**)&rp, ((size_t)n + 1) * 8)) || (r = alloc((void**)&col, g->nnz * 4)) ||
+        (r = alloc((void**)&rank, (size_t)n * 4)) || (r = alloc((void**)&ocnt, (size_t)n * 4)) ||
+        (r = alloc((void**)&orp, ((size_t)n + 1) * 8)) || (r = alloc((void**)&ocol, g->nnz / 2 * 4)) ||
+        (r = alloc((void**)&perm, (size_t)n * 4)) || (r = alloc((void**)&derr, sizeof(int))))
+      return r;
     SCT_TRY(hipMemcpyAsync(rp, g->row_ptr, ((size_t)n + 1) * 8, hipMemcpyHostToDevice, st), "upload graph");
     if (g->nnz) SCT_TRY(hipMemcpyAsync(col, g->col, g->nnz * 4, hipMemcpyHostToDevice, st), "upload graph");
     SCT_TRY(hipMemcpyAsync(rank, T.deg.rank.data(), (size_t)n * 4, hipMemcpyHostToDevice, st), "upload order");
     SCT_TRY(hipMemsetAsync(derr, 0, sizeof(int), st), "clear flag");
+    // orientation along the order: out-degrees, offsets on the host, lists
+    std::vector<uint32_t> oc(n);
+    if (n) {
+      orient_count_kernel<<<(n + 255) / 256, 256, 0, st>>>(rp, col, rank, n, ocnt);
+      SCT_TRY(hipGetLastError(), "orientation count launch");
+      SCT_TRY(hipMemcpyAsync(oc.data(), ocnt, (size_t)n * 4, hipMemcpyDeviceToHost, st), "read out-degrees");
+      SCT_TRY(hipStreamSynchronize(st), "stream synchronize");
+    }
+    std::vector<uint64_t> ob(n + 1, 0);
+    for (uint32_t v = 0; v < n; ++v) {
+      if (oc[v] > D) return kdss::fail(KDSS_EUNSUPPORTED, "internal: an out-degree above the degeneracy");
+      ob[v + 1] = ob[v] + oc[v];
+    }
+    if (ob[n] != g->nnz / 2) return kdss::fail(KDSS_EUNSUPPORTED, "internal: the orientation lost edges");
+    // start nodes that can hold a k-clique, by decreasing out-degree (ties by id)
+    std::vector<uint64_t> bucket(D + 2, 0);
+    for (uint32_t v = 0; v < n; ++v)
+      if (oc[v] + 1 >= k) ++bucket[D - oc[v] + 1];
+    for (uint32_t b = 1; b <= D + 1; ++b) bucket[b] += bucket[b - 1];
+    const uint32_t active = (uint32_t)bucket[D + 1];
+    std::vector<uint32_t> order(std::max<uint32_t>(active, 1));
+    for (uint32_t v = 0; v < n; ++v)
+      if (oc[v] + 1 >= k) order[bucket[D - oc[v]]++] = v;
+    SCT_TRY(hipMemcpyAsync(orp, ob.data(), ((size_t)n + 1) * 8, hipMemcpyHostToDevice, st), "upload offsets");
+    if (active) SCT_TRY(hipMemcpyAsync(perm, order.data(), (size_t)active * 4, hipMemcpyHostToDevice, st),
+                        "upload start order");
+    if (n) {
+      orient_fill_kernel<<<(n + 255) / 256, 256, 0, st>>>(rp, col, rank, n, orp, ocol);
+      SCT_TRY(hipGetLastError(), "orientation fill launch");
+    }
+    // scratch for one chunk of start nodes
+    const size_t per_thread = sct_words64(D, W) * 8 + sct_words32(D) * 4;
+    const uint32_t chunk = (uint32_t)std::max<size_t>(
+        64, std::min<size_t>(std::max<uint32_t>(active, 1), kSctScratchBudget / per_thread));
+    uint64_t *s64 = nullptr, *dcounts = nullptr, *loff = nullptr, *moff = nullptr;
+    uint32_t *s32 = nullptr, *dhp = nullptr, *dmem = nullptr;
+    if ((r = alloc((void**)&s64, (size_t)chunk * sct_words64(D, W) * 8)) ||
+        (r = alloc((void**)&s32, (size_t)chunk * sct_words32(D) * 4)) ||
+        (r = alloc((void**)&dcounts, (size_t)chunk * 16)) || (r = alloc((void**)&loff, (size_t)chunk * 8)) ||
+        (r = alloc((void**)&moff, (size_t)chunk * 8)))
+      return r;
+    auto launch = [&](uint32_t v0, uint32_t c, int write, uint32_t* hp, uint32_t* mem) {
+      const uint32_t blocks = (c + 63) / 64;
+      switch (W) {
+        case 1: launch_sct<1>(blocks, st, orp, ocol, perm, k, D, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
+        case 2: launch_sct<2>(blocks, st, orp, ocol, perm, k, D, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
+        case 3: launch_sct<3>(blocks, st, orp, ocol, perm, k, D, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
+        default: launch_sct<4>(blocks, st, orp, ocol, perm, k, D, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
+      }
+      return hipGetLastError();
+    };
     // pass 1: leaves and members per start node
-    for (uint32_t v0 = 0; v0 < n; v0 += chunk) {
-      const uint32_t c = std::min(chunk, n - v0);
-      sct_kernel<<<(c + 63) / 64, 64, 0, st>>>(rp, col, rank, n, k, v0, c, s64, s32, 0, dcounts, nullptr, nullptr,
-                                               nullptr, nullptr, derr);
-      SCT_TRY(hipGetLastError(), "tree count launch");
+    std::vector<uint64_t> counts(2 * (size_t)active);
+    for (uint32_t v0 = 0; v0 < active; v0 += chunk) {
+      const uint32_t c = std::min(chunk, active - v0);
+      SCT_TRY(launch(v0, c, 0, nullptr, nullptr), "tree count launch");
       SCT_TRY(hipMemcpyAsync(counts.data() + 2 * (size_t)v0, dcounts, (size_t)c * 16, hipMemcpyDeviceToHost, st),
               "read counts");
     }
     int herr = 0;
     SCT_TRY(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, st), "read flag");
     SCT_TRY(hipStreamSynchronize(st), "stream synchronize");
-    if (herr & 1) return kdss::fail(KDSS_EUNSUPPORTED, "a later-neighbour set above 256 nodes");
-    if (herr & 2) return kdss::fail(KDSS_EUNSUPPORTED, "the tree recursion went deeper than its stack");
-    std::vector<uint64_t> lo(n + 1, 0), mo(n + 1, 0);
-    for (uint32_t v = 0; v < n; ++v) {
+    if (herr & 1) return kdss::fail(KDSS_EUNSUPPORTED, "internal: an out-list above the degeneracy");
+    if (herr & 2) return kdss::fail(KDSS_EUNSUPPORTED, "internal: the tree recursion went deeper than its stack");
+    std::vector<uint64_t> lo((size_t)active + 1, 0), mo((size_t)active + 1, 0);
+    for (uint32_t v = 0; v < active; ++v) {
       lo[v + 1] = lo[v] + counts[2 * (size_t)v];
       mo[v + 1] = mo[v] + counts[2 * (size_t)v + 1];
     }
-    const uint64_t L = lo[n], M = mo[n];
+    const uint64_t L = lo[active], M = mo[active];
     if (L >= (1ull << 40)) return kdss::fail(KDSS_ERANGE, "more than 2^40 leaves");
-    int r2 = alloc((void**)&dhp, L * 4);
-    if (!r2) r2 = alloc((void**)&dmem, M * 4);
-    if (r2) return r2;
-    // pass 2: the leaves at their offsets (offsets relative to the chunk's first node)
-    std::vector<uint64_t> cl(chunk), cm(chunk);
-    for (uint32_t v0 = 0; v0 < n; v0 += chunk) {
-      const uint32_t c = std::min(chunk, n - v0);
-      for (uint32_t i = 0; i < c; ++i) {
-        cl[i] = lo[v0 + i];
-        cm[i] = mo[v0 + i];
-      }
-      SCT_TRY(hipMemcpyAsync(loff, cl.data(), (size_t)c * 8, hipMemcpyHostToDevice, st), "upload offsets");
-      SCT_TRY(hipMemcpyAsync(moff, cm.data(), (size_t)c * 8, hipMemcpyHostToDevice, st), "upload offsets");
-      sct_kernel<<<(c + 63) / 64, 64, 0, st>>>(rp, col, rank, n, k, v0, c, s64, s32, 1, nullptr, loff, moff, dhp,
-                                               dmem, derr);
-      SCT_TRY(hipGetLastError(), "tree write launch");
-      SCT_TRY(hipStreamSynchronize(st), "stream synchronize");   // the host offset buffers are reused
+    if ((r = alloc((void**)&dhp, L * 4)) || (r = alloc((void**)&dmem, M * 4))) return r;
+    // pass 2: the leaves at their offsets (offsets of the chunk's start nodes)
+    for (uint32_t v0 = 0; v0 < active; v0 += chunk) {
+      const uint32_t c = std::min(chunk, active - v0);
+      SCT_TRY(hipMemcpyAsync(loff, lo.data() + v0, (size_t)c * 8, hipMemcpyHostToDevice, st), "upload offsets");
+      SCT_TRY(hipMemcpyAsync(moff, mo.data() + v0, (size_t)c * 8, hipMemcpyHostToDevice, st), "upload offsets");
+      SCT_TRY(launch(v0, c, 1, dhp, dmem), "tree write launch");
+      SCT_TRY(hipStreamSynchronize(st), "stream synchronize");   // the device offset buffers are reused
     }
     std::vector<uint32_t> hpv(L);
     T.members.resize(M);
