@@ -187,8 +187,7 @@ static void layout_workspace(kdss_plan* P) {
   P->off_bbest = take((size_t)P->scan_blocks * 16);
   P->off_red = take((size_t)P->red_blocks * 16);   // a (lo, hi) pair per block
   P->off_dres = take(sizeof(DevResult));
-  P->off_tb_sum = take((size_t)P->scan_blocks * 16);    // u128 per block
-  P->off_tb_best = take((size_t)P->scan_blocks * 32);   // (numerator u128, s) per block
+  P->off_tb_binom = take(P->tb_binom.size() * 8);
   P->leaf_blocks = (uint32_t)std::min<uint64_t>(kLeafBlocksDefault, std::max<uint64_t>(1, (P->tiles.size() + 3) / 4));
   P->heavy_blocks = kHeavyBlocks;
   P->off_hot = take(P->hot.size() * 4);
@@ -490,6 +489,19 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
         u128 v = binom128(a, b);
         P->binom[(size_t)a * cols + b] = (v >> 64) ? ~0ull : (uint64_t)v;
       }
+    // the top-s bound looks at s <= s0 only, s0 the first s with C(s, k) >= c_k:
+    // beyond it every candidate is A_s, and A_s / s does not grow
+    if (trees.size() == 1 && n_total > 0 && (P->c_k >> 64) == 0) {
+      const uint32_t k = P->k;
+      u128 c = 0;   // C(s, k)
+      P->tb_binom.push_back(0);
+      for (uint64_t s = 1; s <= n_total; ++s) {
+        if (s == k) c = 1;
+        else if (s > k) c = c * s / (s - k);   // c < c_k < 2^64 here, so no overflow
+        P->tb_binom.push_back((c >> 64) ? ~0ull : (uint64_t)c);
+        if (c >= P->c_k) break;
+      }
+    }
     layout_workspace(P);
   } catch (const std::bad_alloc&) {
     delete P;

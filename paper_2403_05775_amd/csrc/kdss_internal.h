@@ -191,7 +191,10 @@ struct kdss_plan {
   std::vector<uint32_t> prob_k;
   std::vector<kdss::u128> prob_ck;
   size_t off_prefix = 0, off_pres = 0, off_nodeoff = 0;
-  size_t off_tb_sum = 0, off_tb_best = 0;   // top-s bound: per-block load sums and best candidates
+  // top-s bound: C(s, k) for s = 0 .. its last entry, the first s with C(s, k) >= c_k
+  // (saturated at 2^64 - 1; single problems with c_k < 2^64 only)
+  std::vector<uint64_t> tb_binom;
+  size_t off_tb_binom = 0;
   uint64_t lane_leaves = 0;            // leaves in lane tiles (queue capacity)
   // state of the device side
   void* uploaded_ws = nullptr;

@@ -1790,147 +1790,92 @@ int launch_radix(const kdss_plan* P, const WsView& ws, uint32_t nbits, int wide,
 // ----------------------------------------------------------------------------
 // Top-s bound on rho* (single problem, 64-bit loads, zero start loads): with
 // A_s = the sum of the s largest loads (the extraction order's first s),
-// rho* <= max_s min(A_s, T C(s, k)) / (T s).  Sums are u128; candidates are
-// compared exactly (u128 x u32 products, 160 bits).
+// rho* <= max_s min(A_s, T C(s, k)) / (T s).  From s0, the first s with
+// C(s, k) >= c_k, on every candidate is A_s (A_s <= T c_k) and A_s / s does
+// not grow, so the maximum and its smallest s lie in s <= s0.  Every A_s is at
+// most T c_k < 2^64; candidates are compared exactly (64 x 32-bit products).
 // ----------------------------------------------------------------------------
-struct U160 {
-  u128 lo;
-  uint32_t hi;
-};
+constexpr uint32_t kTbThreads = 256;
+constexpr uint32_t kTbItems = 4;
 
-__host__ __device__ inline U160 mul_u128_u32(u128 a, uint32_t b) {
-  const u128 p0 = (u128)(uint64_t)a * b, p1 = (u128)(uint64_t)(a >> 64) * b;
-  const u128 lo = p0 + (p1 << 64);
-  return U160{lo, (uint32_t)(p1 >> 64) + (lo < p0 ? 1u : 0u)};
+// (c1 / s1) beats (c2 / s2): a larger ratio, or an equal one at a smaller s;
+// s = 0 marks "none yet"
+__device__ inline bool tb_better(uint64_t c1, uint32_t s1, uint64_t c2, uint32_t s2) {
+  if (s1 == 0) return false;
+  if (s2 == 0) return true;
+  const u128 a = (u128)c1 * s2, b = (u128)c2 * s1;
+  return a != b ? a > b : s1 < s2;
 }
 
-// x / s > y / t
-__host__ __device__ inline bool ratio_greater(u128 x, uint32_t s, u128 y, uint32_t t) {
-  const U160 a = mul_u128_u32(x, t), b = mul_u128_u32(y, s);
-  return a.hi != b.hi ? a.hi > b.hi : a.lo > b.lo;
-}
-
-// min(A, T C(s, k)), C saturating at 2^128 - 1
-__device__ inline u128 top_candidate(u128 A, uint32_t s, uint32_t k, uint32_t T) {
-  if (s < k) return 0;
-  const u128 mx = ~(u128)0;
-  u128 c = 1;
-  for (uint32_t t = 1; t <= k; ++t) {
-    const uint64_t f = (uint64_t)s - k + t;   // c = C(s - k + t, t) after this step
-    if (c > mx / f) return A;                 // C(s, k) >= 2^128 / s > A / T
-    c = c * f / t;
-  }
-  if (c > mx / T) return A;
-  const u128 tc = c * T;
-  return tc < A ? tc : A;
-}
-
-__global__ __launch_bounds__(kScanThreads) void tb_blocksum_kernel(const uint64_t* __restrict__ r,
-                                                                   const uint32_t* __restrict__ order, uint32_t n,
-                                                                   uint64_t* __restrict__ bsum) {
-  __shared__ uint64_t slo[kScanThreads], shi[kScanThreads];
-  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  u128 acc = 0;
-  for (uint32_t q = 0; q < kScanItems; ++q)
-    if (base + q < n) acc += r[order[base + q]];
-  slo[threadIdx.x] = (uint64_t)acc;
-  shi[threadIdx.x] = (uint64_t)(acc >> 64);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    u128 t = 0;
-    for (uint32_t i = 0; i < kScanThreads; ++i) t += ((u128)shi[i] << 64) | slo[i];
-    bsum[2ull * blockIdx.x] = (uint64_t)t;
-    bsum[2ull * blockIdx.x + 1] = (uint64_t)(t >> 64);
-  }
-}
-
-// exclusive scan of the nb block sums, in place (one thread: nb <= n / 1024)
-__global__ void tb_scan_kernel(uint64_t* __restrict__ bsum, uint32_t nb) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  u128 run = 0;
-  for (uint32_t b = 0; b < nb; ++b) {
-    const u128 v = ((u128)bsum[2ull * b + 1] << 64) | bsum[2ull * b];
-    bsum[2ull * b] = (uint64_t)run;
-    bsum[2ull * b + 1] = (uint64_t)(run >> 64);
-    run += v;
-  }
-}
-
-// the best candidate of each block: (numerator lo, hi, s)
-__global__ __launch_bounds__(kScanThreads) void tb_best_kernel(const uint64_t* __restrict__ r,
-                                                               const uint32_t* __restrict__ order, uint32_t n,
-                                                               const uint64_t* __restrict__ bsum, uint32_t T,
-                                                               uint32_t k, uint64_t* __restrict__ bbest) {
-  __shared__ uint64_t slo[kScanThreads], shi[kScanThreads];
-  __shared__ uint64_t blo[kScanThreads], bhi[kScanThreads];
-  __shared__ uint32_t bs[kScanThreads];
-  const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  uint64_t v[kScanItems];
-  u128 acc = 0;
-  for (uint32_t q = 0; q < kScanItems; ++q) {
-    v[q] = base + q < n ? r[order[base + q]] : 0ull;
-    acc += v[q];
-  }
-  slo[threadIdx.x] = (uint64_t)acc;
-  shi[threadIdx.x] = (uint64_t)(acc >> 64);
-  __syncthreads();
-  // prefix of the loads before this thread's items (block offset + earlier threads)
-  u128 run = ((u128)bsum[2ull * blockIdx.x + 1] << 64) | bsum[2ull * blockIdx.x];
-  for (uint32_t i = 0; i < threadIdx.x; ++i) run += ((u128)shi[i] << 64) | slo[i];
-  u128 best = 0;
+// One workgroup: s = 1 .. slim in chunks of kTbThreads * kTbItems; per chunk
+// a workgroup scan of the per-thread sums, then each thread's best candidate;
+// the best over the workgroup goes to the device result.
+__global__ __launch_bounds__(kTbThreads) void tb_prefix_kernel(const uint64_t* __restrict__ r,
+                                                               const uint32_t* __restrict__ order, uint32_t slim,
+                                                               const uint64_t* __restrict__ cbin, uint32_t T,
+                                                               DevResult* d) {
+  __shared__ uint64_t sc[2][kTbThreads];
+  __shared__ uint64_t bc[kTbThreads];
+  __shared__ uint32_t bz[kTbThreads];
+  const uint32_t tid = threadIdx.x;
+  uint64_t carry = 0, best = 0;
   uint32_t bsz = 0;
-  for (uint32_t q = 0; q < kScanItems; ++q) {
-    if (base + q >= n) break;
-    run += v[q];
-    const uint32_t sz = base + q + 1;
-    const u128 c = top_candidate(run, sz, k, T);
-    if (bsz == 0 || ratio_greater(c, sz, best, bsz)) { best = c; bsz = sz; }
-  }
-  blo[threadIdx.x] = (uint64_t)best;
-  bhi[threadIdx.x] = (uint64_t)(best >> 64);
-  bs[threadIdx.x] = bsz;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    u128 b = 0;
-    uint32_t z = 0;
-    for (uint32_t i = 0; i < kScanThreads; ++i) {
-      if (bs[i] == 0) continue;
-      const u128 c = ((u128)bhi[i] << 64) | blo[i];
-      if (z == 0 || ratio_greater(c, bs[i], b, z)) { b = c; z = bs[i]; }
+  for (uint32_t base = 0; base < slim; base += kTbThreads * kTbItems) {
+    const uint32_t i0 = base + tid * kTbItems;
+    uint64_t v[kTbItems], sum = 0;
+    for (uint32_t q = 0; q < kTbItems; ++q) {
+      v[q] = i0 + q < slim ? r[order[i0 + q]] : 0ull;
+      sum += v[q];
     }
-    bbest[4ull * blockIdx.x] = (uint64_t)b;
-    bbest[4ull * blockIdx.x + 1] = (uint64_t)(b >> 64);
-    bbest[4ull * blockIdx.x + 2] = z;
+    // inclusive scan of the thread sums (Hillis-Steele, double-buffered)
+    uint32_t cur = 0;
+    sc[0][tid] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < kTbThreads; off <<= 1) {
+      const uint64_t x = sc[cur][tid] + (tid >= off ? sc[cur][tid - off] : 0ull);
+      sc[cur ^ 1][tid] = x;
+      cur ^= 1;
+      __syncthreads();
+    }
+    uint64_t run = carry + sc[cur][tid] - sum;
+    for (uint32_t q = 0; q < kTbItems; ++q) {
+      const uint32_t s = i0 + q + 1;
+      if (s > slim) break;
+      run += v[q];
+      const u128 tc = (u128)T * cbin[s];
+      const uint64_t c = tc < run ? (uint64_t)tc : run;
+      if (tb_better(c, s, best, bsz)) { best = c; bsz = s; }
+    }
+    carry += sc[cur][kTbThreads - 1];
+    __syncthreads();   // sc is rewritten by the next chunk
   }
-}
-
-__global__ void tb_final_kernel(const uint64_t* __restrict__ bbest, uint32_t nb, DevResult* d) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  u128 b = 0;
-  uint32_t z = 0;
-  for (uint32_t i = 0; i < nb; ++i) {
-    const uint32_t s = (uint32_t)bbest[4ull * i + 2];
-    if (s == 0) continue;
-    const u128 c = ((u128)bbest[4ull * i + 1] << 64) | bbest[4ull * i];
-    if (z == 0 || ratio_greater(c, s, b, z)) { b = c; z = s; }
+  bc[tid] = best;
+  bz[tid] = bsz;
+  __syncthreads();
+  for (uint32_t half = kTbThreads / 2; half > 0; half >>= 1) {
+    if (tid < half && tb_better(bc[tid + half], bz[tid + half], bc[tid], bz[tid])) {
+      bc[tid] = bc[tid + half];
+      bz[tid] = bz[tid + half];
+    }
+    __syncthreads();
   }
-  d->tb_lo = (uint64_t)b;
-  d->tb_hi = (uint64_t)(b >> 64);
-  d->tb_size = z;
+  if (tid == 0) {
+    d->tb_lo = bc[0];
+    d->tb_hi = 0;
+    d->tb_size = bz[0];
+  }
 }
 
 // After an extraction at loads d_r: the top-s bound into the device result,
 // when it applies (one problem, Frank-Wolfe, 64-bit loads, no start loads).
 int launch_top_bound(const kdss_plan* P, const WsView& ws, const void* d_r, const uint64_t* d_r0, uint32_t T,
                      const uint32_t* d_order, hipStream_t st) {
-  if (P->width != 64 || d_r0 || P->opts.update != 0 || P->node_off.size() != 2 || P->n == 0) return KDSS_OK;
-  const uint64_t* r = static_cast<const uint64_t*>(d_r);
-  uint64_t* bsum = ws.at<uint64_t>(P->off_tb_sum);
-  uint64_t* bbest = ws.at<uint64_t>(P->off_tb_best);
-  tb_blocksum_kernel<<<P->scan_blocks, kScanThreads, 0, st>>>(r, d_order, P->n, bsum);
-  tb_scan_kernel<<<1, 64, 0, st>>>(bsum, P->scan_blocks);
-  tb_best_kernel<<<P->scan_blocks, kScanThreads, 0, st>>>(r, d_order, P->n, bsum, T, P->k, bbest);
-  tb_final_kernel<<<1, 64, 0, st>>>(bbest, P->scan_blocks, ws.at<DevResult>(P->off_dres));
+  if (P->width != 64 || d_r0 || P->opts.update != 0 || P->node_off.size() != 2 || P->n == 0 ||
+      P->tb_binom.size() < 2)
+    return KDSS_OK;
+  const uint32_t slim = (uint32_t)(P->tb_binom.size() - 1);
+  tb_prefix_kernel<<<1, kTbThreads, 0, st>>>(static_cast<const uint64_t*>(d_r), d_order, slim,
+                                             ws.at<uint64_t>(P->off_tb_binom), T, ws.at<DevResult>(P->off_dres));
   HIP_TRY(hipGetLastError(), "top-s bound launch");
   return KDSS_OK;
 }
@@ -2219,6 +2164,9 @@ int kdss_plan_upload(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream) {
                            hipMemcpyHostToDevice, st), "upload tiles");
   HIP_TRY(hipMemcpyAsync(ws.at<uint64_t>(P->off_binom), P->binom.data(), P->binom.size() * 8, hipMemcpyHostToDevice,
                          st), "upload binomials");
+  if (!P->tb_binom.empty())
+    HIP_TRY(hipMemcpyAsync(ws.at<uint64_t>(P->off_tb_binom), P->tb_binom.data(), P->tb_binom.size() * 8,
+                           hipMemcpyHostToDevice, st), "upload bound binomials");
   if (!P->hot.empty()) {
     HIP_TRY(hipMemcpyAsync(ws.at<uint32_t>(P->off_hot), P->hot.data(), P->hot.size() * 4, hipMemcpyHostToDevice, st),
             "upload hot nodes");

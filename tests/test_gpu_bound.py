@@ -39,6 +39,26 @@ def test_top_bound_matches_oracle(K, oracle_mod, seed):
     assert sol.certified == oracle_mod.certified(ref["dens_num"], ref["size"], want, g.n)
 
 
+@pytest.mark.parametrize("k,T", [(2, 5), (3, 2)])
+def test_top_bound_long_prefix(K, oracle_mod, k, T):
+    """A dense graph: the bound's prefix (up to the first s with C(s, k) >= c_k,
+    about 2,100 nodes at k = 2) spans several chunks of the bound kernel."""
+    g = synth.erdos_renyi(3000, 0.5 if k == 2 else 0.1, seed=31)
+    print(f"long prefix k={k} T={T} m={g.m}", flush=True)
+    sol = K.solve(g, k, T)
+    ref = oracle_mod.solve(g.n, g.row_ptr, g.col, k, T)
+    want = oracle_mod.top_bound(ref["r"], None, T, k)
+    s0 = next(s for s in range(g.n + 1) if math.comb(s, k) >= ref["c_k"])
+    assert k > 2 or s0 > 2048
+    assert Fraction(sol.bound_num, sol.bound_den) == want
+
+
+def test_top_bound_without_cliques(K, oracle_mod):
+    g = synth.erdos_renyi(200, 0.02, seed=3)
+    sol = K.solve(g, 7, 4)
+    assert sol.c_k == 0 and sol.bound_kind == 1 and sol.bound_num == 0
+
+
 def test_complete_graph_is_certified(K, oracle_mod):
     g = synth.complete_graph(40)
     sol = K.solve(g, 4, 3)
