@@ -205,11 +205,20 @@ static void layout_workspace(kdss_plan* P) {
     if ((tl.info & 7u) != kTileLane || (tl.info >> 16) > kPbRegRows) break;
     --P->pb_split;
   }
+  // ... and before it, a run of lane tiles of at most kPbMidRows rows
+  P->pb_mid = P->pb_split;
+  while (P->pb_mid > 0) {
+    const Tile& tl = P->tiles[P->pb_mid - 1];
+    if ((tl.info & 7u) != kTileLane || (tl.info >> 16) > kPbMidRows) break;
+    --P->pb_mid;
+  }
   P->pb_rows = 1;
+  P->pb_rows_lo = 1;
   for (uint32_t i = 0; i < P->pb_split; ++i) {
     const Tile& tl = P->tiles[i];
     const uint32_t smax = tl.info >> 16;
-    P->pb_rows = std::max(P->pb_rows, (tl.info & 7u) == kTileLane ? smax : (smax + 63) / 64);
+    uint32_t& rows = i < P->pb_mid ? P->pb_rows : P->pb_rows_lo;
+    rows = std::max(rows, (tl.info & 7u) == kTileLane ? smax : (smax + 63) / 64);
   }
   P->off_queue = take(P->lane_leaves * 16);   // 16-byte heavy-leaf entries
   P->off_hotkey = take((size_t)kHotMax * 32);     // hot-node keys of the current pass

@@ -124,6 +124,7 @@ constexpr uint32_t kHeavyBlocks = 1024;          // grid of the heavy-leaf kerne
 constexpr uint32_t kHotSlots = 256;              // credit slots per hot node, shared by workgroups
 constexpr double kMaskedGatherShare = 0.5;       // hot share from which masked gathers are the default
 constexpr uint32_t kPbRegRows = 16;              // PBUpdate: lane tiles up to this many rows run from registers
+constexpr uint32_t kPbMidRows = 32;              // PBUpdate: lane tiles up to this many rows share 4-wave workgroups
 
 // Device-side result of an extraction.
 struct DevResult {
@@ -161,7 +162,9 @@ struct kdss_plan {
   int gather = 1;          // leaf-pass key gathers: 1 masked, 2 full
   uint32_t pb_split = 0;   // PBUpdate: tiles [0, pb_split) are staged in LDS, the rest (lane tiles of
                            // at most kPbRegRows rows) kept in registers
-  uint32_t pb_rows = 0;    // PBUpdate: staged rows of 64 members (largest such tile or big leaf)
+  uint32_t pb_rows = 0;    // PBUpdate: staged rows of 64 members (largest tile or big leaf before pb_mid)
+  uint32_t pb_mid = 0;     // PBUpdate: tiles [pb_mid, pb_split) are lane tiles of at most kPbMidRows rows
+  uint32_t pb_rows_lo = 0; // PBUpdate: largest of those
   double hot_share = 0.0;  // hot nodes' share of all member occurrences
   uint64_t r0_max = 0;
   kdss::u128 c_k = 0;

@@ -635,7 +635,8 @@ __device__ __forceinline__ uint32_t pb_node_id(uint32_t raw, const uint32_t* hid
   return (raw & kHotFlag) ? hid[raw & (kHotMax - 1)] : raw;
 }
 
-// One leaf per lane: lr / lm hold the lane's column (member x at x * 64).
+// One leaf per lane: lr (LDS) and lm (the tile's member words in memory) hold
+// the lane's column (member x at x * 64).
 __device__ __forceinline__ void pb_leaf_lane(const uint64_t* lr, const uint32_t* lm, uint32_t h, uint32_t p,
                                              uint64_t nC, uint64_t cp, const uint32_t* hid, Sink& sink) {
   const uint32_t s = h + p;
@@ -707,8 +708,8 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
-// One leaf of more than 64 members per wavefront: lr / lm hold its members
-// contiguously (member x at x); lane l owns members l, l + 64, ..
+// One leaf of more than 64 members per wavefront: lr (LDS) and lm (memory)
+// hold its members contiguously (member x at x); lane l owns members l, l + 64, ..
 __device__ __forceinline__ void pb_leaf_wave(const uint64_t* lr, const uint32_t* lm, uint32_t h, uint32_t p,
                                              uint64_t nC, uint64_t cp, const uint32_t* hid, Sink& sink) {
   const uint32_t lane = threadIdx.x & 63u, s = h + p;
@@ -751,42 +752,46 @@ __device__ __forceinline__ void pb_leaf_wave(const uint64_t* lr, const uint32_t*
   }
 }
 
-// One wavefront per workgroup, tiles w, w + gridDim.x, ..  Dynamic LDS: rows
-// of 64 loads (u64) and then rows of 64 member words; a lane tile stages its
-// rows there (each lane then reads only its own column), a big leaf its
-// members.  Hot loads, ids and credit totals live in static LDS; the totals
-// reach the hot nodes' slot entries at the end, as in the leaf-credit pass.
-__global__ __launch_bounds__(64) void pb_kernel(const Tile* __restrict__ tiles, uint32_t ntiles,
-                                                const uint32_t* __restrict__ members,
-                                                const uint32_t* __restrict__ hdr,
-                                                const uint64_t* __restrict__ binom, uint32_t k1,
-                                                const uint64_t* __restrict__ r, const uint32_t* __restrict__ hot,
-                                                uint32_t nhot, uint64_t* __restrict__ out,
-                                                uint64_t* __restrict__ scratch, uint32_t rows) {
+// Tiles first .. ntiles - 1, blockDim.x / 64 wavefronts per workgroup, wavefront
+// w of workgroup b taking tiles first + b * W + w, + gridDim.x * W, ..  Dynamic
+// LDS: one region of `rows` rows of 64 loads (u64) per wavefront; a lane tile
+// stages its members' loads there (each lane then reads only its own column), a
+// big leaf its members' loads contiguously.  Member words are read from memory
+// (a lane tile's rows are contiguous).  Hot loads, ids and credit totals live in
+// static LDS, shared by the workgroup; the totals reach the hot nodes' slot
+// entries at the end, as in the leaf-credit pass.
+__global__ __launch_bounds__(256) void pb_kernel(const Tile* __restrict__ tiles, uint32_t first, uint32_t ntiles,
+                                                 const uint32_t* __restrict__ members,
+                                                 const uint32_t* __restrict__ hdr,
+                                                 const uint64_t* __restrict__ binom, uint32_t k1,
+                                                 const uint64_t* __restrict__ r, const uint32_t* __restrict__ hot,
+                                                 uint32_t nhot, uint64_t* __restrict__ out,
+                                                 uint64_t* __restrict__ scratch, uint32_t rows) {
   extern __shared__ uint64_t pb_lds[];
   __shared__ uint64_t hr[kHotMax];
   __shared__ uint32_t hid[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
-  uint64_t* lr = pb_lds;
-  uint32_t* lm = reinterpret_cast<uint32_t*>(pb_lds + (size_t)rows * 64);
   const uint32_t lane = threadIdx.x & 63u;
-  for (uint32_t i = lane; i < nhot; i += 64) {
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  uint64_t* lr = pb_lds + (size_t)w * rows * 64;
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
     hid[i] = hot[i];
     hr[i] = r[hot[i]];
     hcnt[i] = 0;
   }
   __syncthreads();
   Sink sink{hcnt, out, 0u, 0ull};
-  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (uint32_t tile = first + blockIdx.x * nw + w; tile < ntiles; tile += gridDim.x * nw) {
     const Tile t = tiles[tile];
     const uint32_t smax = t.info >> 16;
     if ((t.info & 7u) == kTileBig) {
       const uint32_t hd = hdr[t.lbase];
       const uint32_t h = hd & 31u, j = (hd >> 5) & 31u, p = hd >> 10, sz = h + p;
+      const uint32_t* lm = members + t.mbase;
       wave_lds_sync();   // the previous tile's reads are done
       for (uint32_t x = lane; x < sz; x += 64) {
-        const uint32_t raw = members[t.mbase + x];
-        lm[x] = raw;
+        const uint32_t raw = lm[x];
         lr[x] = (raw & kHotFlag) ? hr[raw & (kHotMax - 1)] : r[raw];
       }
       wave_lds_sync();
@@ -800,18 +805,17 @@ __global__ __launch_bounds__(64) void pb_kernel(const Tile* __restrict__ tiles, 
       wave_lds_sync();
       for (uint32_t x = 0; x < smax; ++x) {
         const uint32_t raw = col[(size_t)x * 64];
-        lm[(size_t)x * 64 + lane] = raw;
         lr[(size_t)x * 64 + lane] = (raw & kHotFlag) ? hr[raw & (kHotMax - 1)] : r[raw];
       }
       const uint64_t nC = hd ? binom[(size_t)p * k1 + j] : 0ull;
       const uint64_t cp = (hd && j) ? binom[(size_t)(p - 1) * k1 + (j - 1)] : 0ull;
-      pb_leaf_lane(lr + lane, lm + lane, h, p, nC, cp, hid, sink);
+      pb_leaf_lane(lr + lane, col, h, p, nC, cp, hid, sink);
     }
   }
   sink.flush();
   __syncthreads();
   const uint32_t slot = blockIdx.x % kHotSlots;
-  for (uint32_t i = lane; i < nhot; i += 64)
+  for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x)
     if (hcnt[i]) atomicAdd(reinterpret_cast<unsigned long long*>(scratch + (size_t)i * kHotSlots + slot), hcnt[i]);
 }
 
@@ -1697,13 +1701,19 @@ int launch_pb(const kdss_plan* P, const WsView& ws, const void* d_r, uint64_t* o
   const uint32_t ntiles = (uint32_t)P->tiles.size();
   if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
   const uint32_t split = P->pb_split, nhot = (uint32_t)P->hot.size();
-  if (split) {   // big leaves and lane tiles of more than kPbRegRows rows, staged in LDS
-    const uint32_t blocks = std::min<uint32_t>(split, 4u * P->leaf_blocks);
-    const size_t lds = (size_t)P->pb_rows * 64 * 12;
-    pb_kernel<<<blocks, 64, lds, st>>>(ws.at<Tile>(P->off_tiles), split, ws.at<uint32_t>(P->off_members),
-                                       ws.at<uint32_t>(P->off_hdr), ws.at<uint64_t>(P->off_binom), P->k1,
-                                       static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot), nhot, out,
-                                       ws.at<uint64_t>(P->off_scratch), P->pb_rows);
+  // big leaves and lane tiles of more than kPbRegRows rows, staged in LDS: those
+  // of more than kPbMidRows rows (one wavefront per workgroup), then the rest
+  // (four per workgroup, sharing the hot-node tables)
+  const uint32_t mid = P->pb_mid;
+  for (int part = 0; part < 2; ++part) {
+    const uint32_t lo = part ? mid : 0u, hi = part ? split : mid, rows = part ? P->pb_rows_lo : P->pb_rows;
+    if (lo >= hi) continue;
+    const uint32_t nw = part ? 4u : 1u;
+    const uint32_t blocks = std::min<uint32_t>((hi - lo + nw - 1) / nw, 4u * P->leaf_blocks / nw);
+    pb_kernel<<<blocks, 64 * nw, (size_t)rows * 64 * 8 * nw, st>>>(
+        ws.at<Tile>(P->off_tiles), lo, hi, ws.at<uint32_t>(P->off_members), ws.at<uint32_t>(P->off_hdr),
+        ws.at<uint64_t>(P->off_binom), P->k1, static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot), nhot,
+        out, ws.at<uint64_t>(P->off_scratch), rows);
     HIP_TRY(hipGetLastError(), "PBUpdate launch");
   }
   if (split < ntiles) {   // the other lane tiles, from registers
