@@ -43,6 +43,10 @@ WORKLOADS = {
     # cliques at k = 5, too few to use
     "cpsample-rmat16": dict(kind="sample", graph=dict(kind="rmat", scale=16, edge_factor=8, seed=0), k=4,
                             t=2_000_000, draw_seed=1, T=64),
+    # the clique tree of the default workload's graph built on the GPU (one
+    # thread per start node); a step is one whole build, host order included
+    "sctbuild-1m": dict(kind="sctbuild", graph=dict(kind="chung_lu", n=1_000_000, m=10_000_000, beta=2.5, seed=0,
+                                                    planted=40, planted_p=0.9), k=5),
     # 512 Chung-Lu graphs (n in [1k, 50k], average degree 8-40, exponent 2.2-2.8,
     # seeds 1000 + g), each at k = 3, 4, 6, 8: 2048 problems in one plan
     "batch-512": dict(kind="batch", graphs=512, ks=(3, 4, 6, 8), T=64),
@@ -373,6 +377,57 @@ def sample_bench(w, args):
     print(json.dumps(out))
 
 
+def sctbuild_bench(w, args):
+    """The GPU clique-tree build: a step is one kdss_sct_build_gpu call (host
+    degeneracy order, device orientation and recursion, leaves back to the
+    host); the figure is k-cliques covered per second.  The host build of the
+    same tree is timed beside it, and the CPU baseline is the oracle counting
+    the same k-cliques."""
+    import torch
+    from paper_2403_05775_amd import kdss
+    g = make_graph(w["graph"])
+    k = w["k"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    for _ in range(max(1, args.warmup)):
+        kdss.GpuTree(g, k).close()
+    secs = []
+    for _ in range(args.steps):
+        t = kdss.GpuTree(g, k)
+        st = t.stats()
+        secs.append(st.build_seconds)
+        t.close()
+    ms = 1000.0 * sum(secs) / len(secs)
+    host = kdss.Tree(g, k)
+    hs = host.stats()
+    host.close()
+    ck = st.c_k.value
+    log(f"GPU tree build: {ms:.1f} ms ({st.leaves} leaves, {st.members} members, degeneracy {st.degeneracy}); "
+        f"host build {1000 * hs.build_seconds:.1f} ms")
+    out = {
+        "metric": "k-cliques covered by the built tree per second", "value": ck / (ms / 1000.0),
+        "unit": "k-cliques/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"sctbuild-1m: {g.name}, k={k}", "n": g.n, "m": g.m, "k": k, "c_k": ck,
+                   "leaves": st.leaves, "members": st.members, "degeneracy": st.degeneracy,
+                   "parallelism": "single GPU"},
+        "host_build_ms": 1000.0 * hs.build_seconds,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        O.build()
+        cores = min(16, os.cpu_count() or 1)
+        s0 = time.perf_counter()
+        n_or = O.count(g.n, g.row_ptr, g.col, k, threads=cores)
+        secs_or = time.perf_counter() - s0
+        if n_or != ck:
+            raise SystemExit(f"the oracle counts {n_or} k-cliques, the GPU tree covers {ck}")
+        out["cpu_baseline"] = dict(value=ck / secs_or, unit="k-cliques/s", cores=cores, kind="oracle",
+                                   sample=f"the same graph and k: the oracle's k-clique count ({secs_or:.2f} s)",
+                                   seconds=secs_or)
+    print(json.dumps(out))
+
+
 def counter_traffic(workload, launch_bytes):
     """HBM bytes per leaf-credit launch from committed rocprofv3 counter runs,
     only while they describe the current kernel source."""
@@ -534,7 +589,7 @@ def main():
     if args.mode == "counters":
         counters_mode(WORKLOADS[args.workload], args)
         return
-    if WORKLOADS[args.workload]["kind"] in ("batch", "gnn", "sample"):
+    if WORKLOADS[args.workload]["kind"] in ("batch", "gnn", "sample", "sctbuild"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
             sys.exit(2)
@@ -543,6 +598,8 @@ def main():
             batch_bench(WORKLOADS[args.workload], args)
         elif kind == "sample":
             sample_bench(WORKLOADS[args.workload], args)
+        elif kind == "sctbuild":
+            sctbuild_bench(WORKLOADS[args.workload], args)
         else:
             gnn_bench(WORKLOADS[args.workload], args)
         return
@@ -646,6 +703,9 @@ def main():
         "kernel_us": {"leaf_credit": leaf_us, "heavy_leaf": heavy_us,
                       "hot_reduce": reduce_us if ps.width == 128 else None, "apply": apply_us},
         "heavy_leaves_per_iteration": heavy_per_iter,
+        # leaves, members and lane tiles per size class s = h + p
+        "size_classes": {name: {"leaves": int(ps.leaves[c]), "members": int(ps.members[c]), "tiles": int(ps.tiles[c])}
+                         for c, name in enumerate(("s<=8", "s<=16", "s<=32", "s<=64", "s>64"))},
         "launch": ({"leaf_blocks": tune.best_leaf_blocks, "heavy_blocks": tune.best_heavy_blocks,
                     "gather": tune.best_gather, "us_per_iter": tune.best_ms * 1000,
                     "gather_us": {"masked": tune.gather_ms[0] * 1000, "full": tune.gather_ms[1] * 1000}}

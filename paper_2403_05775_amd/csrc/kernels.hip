@@ -151,14 +151,16 @@ __device__ __forceinline__ KT member_key(const KeySrc& src, const KT* hkey, uint
 //   0), so a batch issues all its gathers back to back with no branch.
 template <class KT, bool kMasked>
 __device__ __forceinline__ KT member_key_nb(const KeySrc& src, const KT* hkey, uint32_t raw, bool valid) {
-  const KT a = hkey[raw & (kHotMax - 1)];
-  KT b = KT::mx();
+  KT a = hkey[raw & (kHotMax - 1)];
   if constexpr (kMasked) {
-    if (valid && !(raw & kHotFlag)) b = KT::load(src, raw);
+    // a member outside the leaf (invalid) keeps whatever key it read: rows
+    // past the leaf's size are never compared
+    if (valid && !(raw & kHotFlag)) a = KT::load(src, raw);
+    return a;
   } else {
-    b = KT::load(src, raw & ~kHotFlag);
+    const KT b = KT::load(src, raw & ~kHotFlag);
+    return KT::pick((raw & kHotFlag) != 0, a, b);
   }
-  return KT::pick((raw & kHotFlag) != 0, a, b);
 }
 
 // ----------------------------------------------------------------------------
@@ -242,7 +244,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // entry carries what the heavy pass needs without looking the tile up again:
 // the word of the leaf's first member (tile member base + lane), the leaf's
 // header word and the first node id of its problem.
-constexpr uint32_t kQueueBuf = 128;
+constexpr uint32_t kQueueBuf = 32;   // a tile with more heavy leaves writes them to the queue directly
 
 struct WaveQueue {
   uint4* buf;      // the wavefront's kQueueBuf LDS entries
@@ -263,15 +265,18 @@ struct WaveQueue {
 // Lane tile: one leaf per lane; member x of the lane's leaf is the row-x word
 // of the column-major tile, so every row load below is one contiguous 256-byte
 // row.  A single pass over the rows finds the hold minimum m (hold members come
-// first in every leaf) and counts the pivot members below m.  Lanes that have
-// such "low" members rank them: up to four are kept in registers; leaves with
-// more go to the heavy-leaf queue.  Keys are gathered only for members inside
-// the lane's leaf that are not hot (hot keys come from LDS).
+// first in every leaf) and counts the pivot members below m.  The member words
+// of the first low members go to the lane's four LDS slots (lcol[i * 256],
+// written only by lanes that find one, so a row costs no register selects);
+// lanes with at most four rank them from their keys, looked up again; leaves
+// with more go to the heavy-leaf queue.  Keys are gathered only for members
+// inside the lane's leaf that are not hot (hot keys come from LDS).
+constexpr uint32_t kLeafThreads = 256;   // leaf-credit workgroup size (LDS slot stride)
 template <class KT, bool kMasked>
 __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, const uint32_t* __restrict__ members,
                                           const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k1,
                                           const KeySrc& src, const KT* hkey, Sink& sink, uint4* __restrict__ queue,
-                                          uint32_t* __restrict__ qcount, WaveQueue& hq) {
+                                          uint32_t* __restrict__ qcount, WaveQueue& hq, uint32_t* lcol) {
   constexpr uint32_t U = kLaneBatch;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nl = (t.info >> 3) & 0x1FFFu, smax = t.info >> 16;
@@ -280,10 +285,6 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
   const uint32_t* __restrict__ col = members + t.mbase + lane;
   KT km = KT::mx();
   uint32_t mraw = 0, nlow = 0;
-  // the first four low members, in row order (hold members precede pivot
-  // members, so m is final when the first pivot member is compared)
-  KT l0 = KT::mx(), l1 = KT::mx(), l2 = KT::mx(), l3 = KT::mx();
-  uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0;
   // rows past the tile repeat its last; each batch's rows are requested
   // during the batch before, right after that batch's key gathers, so waiting
   // for those keys leaves the rows in flight
@@ -302,28 +303,38 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u) nxt[u] = col[(size_t)min(x0 + U + u, smax - 1) * 64];
     }
+    if (__ballot(x0 < h)) {
+      // some lane still has hold rows here (hold members precede pivot
+      // members, so m is final when a lane compares its first pivot member)
 #pragma unroll
-    for (uint32_t u = 0; u < U; ++u) {
-      const uint32_t x = x0 + u;
-      const bool hold = x < h;
-      const bool better = hold && key[u].lt(km);
-      km = KT::pick(better, key[u], km);
-      mraw = better ? raw[u] : mraw;
-      // straight-line slot update (no indexed array of keys)
-      const bool take = !hold && x < s && key[u].lt(km);
-      l0 = KT::pick(take && nlow == 0, key[u], l0);
-      l1 = KT::pick(take && nlow == 1, key[u], l1);
-      l2 = KT::pick(take && nlow == 2, key[u], l2);
-      l3 = KT::pick(take && nlow == 3, key[u], l3);
-      r0 = (take && nlow == 0) ? raw[u] : r0;
-      r1 = (take && nlow == 1) ? raw[u] : r1;
-      r2 = (take && nlow == 2) ? raw[u] : r2;
-      r3 = (take && nlow == 3) ? raw[u] : r3;
-      nlow += take ? 1u : 0u;
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t x = x0 + u;
+        const bool hold = x < h;
+        const bool better = hold && key[u].lt(km);
+        km = KT::pick(better, key[u], km);
+        mraw = better ? raw[u] : mraw;
+        const bool take = !hold && x < s && key[u].lt(km);
+        if (take) lcol[min(nlow, 3u) * kLeafThreads] = raw[u];
+        nlow += take ? 1u : 0u;
+      }
+    } else {
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const bool take = x0 + u < s && key[u].lt(km);
+        if (take) lcol[min(nlow, 3u) * kLeafThreads] = raw[u];
+        nlow += take ? 1u : 0u;
+      }
     }
   }
   if (nlow && nlow <= 4 && j >= 1) {
-    // rank of each low member among the low members (unused slots hold the maximum key)
+    // the low members' keys again (unused slots hold the maximum key), and
+    // the rank of each among the low members
+    const uint32_t r0 = lcol[0], r1 = lcol[kLeafThreads], r2 = lcol[2 * kLeafThreads], r3 = lcol[3 * kLeafThreads];
+    const KT l0 = member_key<KT>(src, hkey, r0);
+    KT l1 = KT::mx(), l2 = KT::mx(), l3 = KT::mx();
+    if (nlow > 1) l1 = member_key<KT>(src, hkey, r1);
+    if (nlow > 2) l2 = member_key<KT>(src, hkey, r2);
+    if (nlow > 3) l3 = member_key<KT>(src, hkey, r3);
     const uint32_t b0 = (l1.lt(l0) ? 1u : 0u) + (l2.lt(l0) ? 1u : 0u) + (l3.lt(l0) ? 1u : 0u);
     const uint32_t b1 = (l0.lt(l1) ? 1u : 0u) + (l2.lt(l1) ? 1u : 0u) + (l3.lt(l1) ? 1u : 0u);
     const uint32_t b2 = (l0.lt(l2) ? 1u : 0u) + (l1.lt(l2) ? 1u : 0u) + (l3.lt(l2) ? 1u : 0u);
@@ -339,13 +350,20 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
   const uint64_t heavy = __ballot(nlow > 4);
   if (heavy) {
     const uint32_t cnt = (uint32_t)__popcll(heavy);
+    const uint32_t below = (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull));
+    const uint64_t mw = t.mbase + lane;
+    const uint4 entry = make_uint4((uint32_t)mw, (uint32_t)(mw >> 32), hd, t.nbase);
     if (hq.n + cnt > kQueueBuf) hq.flush(queue, qcount);
-    if (nlow > 4) {
-      const uint64_t mw = t.mbase + lane;
-      hq.buf[hq.n + (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull))] =
-          make_uint4((uint32_t)mw, (uint32_t)(mw >> 32), hd, t.nbase);
+    if (cnt > kQueueBuf) {
+      // more than the slice holds: this tile's entries go to the queue at once
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(qcount, cnt);
+      base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+      if (nlow > 4) queue[base + below] = entry;
+    } else {
+      if (nlow > 4) hq.buf[hq.n + below] = entry;
+      hq.n += cnt;
     }
-    hq.n += cnt;
   }
   const uint64_t cm = h ? binom[(size_t)(p - nlow) * k1 + j] : 0ull;
   combine_add(sink, cm ? mraw : 0xFFFFFFFFu, cm);
@@ -406,10 +424,11 @@ __device__ __forceinline__ void tile_big(const Tile& t, const uint32_t* __restri
 // Persistent grid: wave w of the grid takes tiles w, w + 4 * gridDim.x, ...
 // Each workgroup adds its nonzero hot-node credit totals into one of
 // kHotSlots scratch rows (row blockIdx.x % kHotSlots).
-// At least seven wavefronts per SIMD (<= 64 VGPRs): the pass is latency-bound,
-// and occupancy hides more of it than wider row batches do.
+// Eight wavefronts per SIMD (<= 64 VGPRs, 18 KB of LDS per workgroup): the
+// pass is latency-bound, and occupancy hides more of it than wider row
+// batches do.
 template <class KT, bool kMasked>
-__global__ __launch_bounds__(256, 7) void leaf_credit_kernel(const Tile* __restrict__ tiles, uint32_t ntiles,
+__global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restrict__ tiles, uint32_t ntiles,
                                                           const uint32_t* __restrict__ members,
                                                           const uint32_t* __restrict__ hdr,
                                                           const uint64_t* __restrict__ binom, uint32_t nbinom,
@@ -423,6 +442,9 @@ __global__ __launch_bounds__(256, 7) void leaf_credit_kernel(const Tile* __restr
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kBinomLds];
   __shared__ uint4 qslice[4][kQueueBuf];
+  __shared__ uint32_t lowslot[4 * kLeafThreads];   // four low-member slots per lane
+  uint32_t* lcol = lowslot + threadIdx.x;
+  for (uint32_t i = 0; i < 4; ++i) lcol[i * kLeafThreads] = 0u;   // node 0 until a lane writes its own
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t stride = gridDim.x * 4u;
   uint32_t tile = blockIdx.x * 4u + w;
@@ -454,7 +476,7 @@ __global__ __launch_bounds__(256, 7) void leaf_credit_kernel(const Tile* __restr
     KeySrc ts = src;
     ts.base = t.nbase;
     if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k1, ts, hkey, sink);
-    else tile_lane<KT, kMasked>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq);
+    else tile_lane<KT, kMasked>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq, lcol);
   }
   sink.flush();
   // the heavy entries the four wavefronts still stage: one counter atomic for
@@ -1662,11 +1684,11 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
 #define KDSS_LEAF(KT)                                                                                           \
   if (P->gather == 2)                                                                                            \
-    leaf_credit_kernel<KT, false><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src, \
+    leaf_credit_kernel<KT, false><<<blocks, kLeafThreads, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src, \
                                                           out, hot, hot_base, nhot, scratch, queue, qcount,      \
                                                           ws.at<KT>(table_off), hot_published);                  \
   else                                                                                                           \
-    leaf_credit_kernel<KT, true><<<blocks, 256, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src,  \
+    leaf_credit_kernel<KT, true><<<blocks, kLeafThreads, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src,  \
                                                          out, hot, hot_base, nhot, scratch, queue, qcount,       \
                                                          ws.at<KT>(table_off), hot_published);                   \
   if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event record");                                                    \
@@ -2328,7 +2350,7 @@ int kdss_batch_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const 
 int kdss_plan_set_launch(kdss_plan* P, uint32_t leaf_blocks, uint32_t heavy_blocks) {
   if (!P) return fail(KDSS_EINVAL, "null argument");
   if (leaf_blocks == 0 || leaf_blocks > kLeafBlocksMax || heavy_blocks == 0 || heavy_blocks > kHeavyBlocks)
-    return fail(KDSS_ERANGE, "grid sizes must be in 1..1024");
+    return fail(KDSS_ERANGE, "grid sizes must be in 1..2048 (leaf) and 1..1024 (heavy)");
   if (P->leaf_blocks != leaf_blocks || P->heavy_blocks != heavy_blocks) drop_graph(P);
   P->leaf_blocks = leaf_blocks;
   P->heavy_blocks = heavy_blocks;

@@ -372,17 +372,22 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
     T.h.resize(L);
     T.p.resize(L);
     T.off.resize(L + 1);
+    // C(p, j) for p <= D, j <= k (every leaf has p <= D pivots)
+    std::vector<u128> cb((size_t)(D + 1) * (k + 1));
+    for (uint32_t pp = 0; pp <= D; ++pp)
+      for (uint32_t jj = 0; jj <= k; ++jj) cb[(size_t)pp * (k + 1) + jj] = kdss::binom128(pp, jj);
     uint64_t at = 0;
     u128 ck = 0;
     uint32_t smax = 0;
     for (uint64_t i = 0; i < L; ++i) {
       const uint32_t h = hpv[i] & 0xFFu, p = hpv[i] >> 8;
+      if (p > D || h > k) return kdss::fail(KDSS_EUNSUPPORTED, "internal: a leaf outside the tree's bounds");
       T.h[i] = (uint8_t)h;
       T.p[i] = p;
       T.off[i] = at;
       at += h + p;
       smax = std::max(smax, h + p);
-      const u128 c = kdss::binom128(p, k - h);
+      const u128 c = cb[(size_t)p * (k + 1) + (k - h)];
       if (ck + c < ck) return kdss::fail(KDSS_EOVERFLOW, "2^128 or more k-cliques");
       ck += c;
     }

@@ -195,3 +195,28 @@ def test_no_cliques(K, oracle_mod):
     assert sol.c_k == 0 and sol.size == 0 and sol.dens_num == 0 and sol.ub_num == 0
     assert np.all(sol.r == 0)
     assert_same(sol, ref(oracle_mod, g, 7, 3), 3)
+
+
+@pytest.mark.parametrize("leaf_blocks", [1, 3, 7, 9])
+def test_small_leaf_grids(K, oracle_mod, leaf_blocks):
+    """Grids far smaller than the tile count: the tiles past the first stride
+    come from the tile counters (fewer counters than eight when the grid is
+    smaller), and every tile is processed once."""
+    from paper_2403_05775_amd import kdss
+    g = synth.chung_lu(4000, 30000, 2.3, seed=23, planted=25)
+    T = 7
+    tree = kdss.Tree(g, 4)
+    plan = kdss.Plan(tree, T)
+    plan.set_launch(leaf_blocks, 3)
+    ws = plan.alloc_workspace()
+    plan.upload(ws)
+    r = plan.alloc_loads()
+    order = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    print(f"leaf grid {leaf_blocks}, {sum(plan.stats().tiles)} tiles", flush=True)
+    assert sum(plan.stats().tiles) > 4 * leaf_blocks
+    res, _ = plan.run(ws, T, r, order)
+    torch.cuda.synchronize()
+    want = ref(oracle_mod, g, 4, T)
+    assert np.array_equal(r.cpu().numpy().view(np.uint64)[: g.n], want["r"])
+    assert np.array_equal(order.cpu().numpy().view(np.uint32), want["order"])
+    assert (res.size, res.dens_num.value, res.ub_num.value) == (want["size"], want["dens_num"], want["ub_num"])
