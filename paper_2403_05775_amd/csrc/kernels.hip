@@ -56,6 +56,10 @@ struct KPacked {
   uint64_t v;
   __device__ static KPacked mx() { return {~0ull}; }
   __device__ static KPacked load(const KeySrc& s, uint32_t u) { return {(s.r[u] << s.id_bits) | (u - s.base)}; }
+  // the memory read of load alone, and the key made from it
+  using Raw = uint64_t;
+  __device__ static Raw fetch(const KeySrc& s, uint32_t u) { return s.r[u]; }
+  __device__ static KPacked finish(Raw x, const KeySrc& s, uint32_t u) { return {(x << s.id_bits) | (u - s.base)}; }
   __device__ bool lt(const KPacked& o) const { return v < o.v; }
   __device__ bool eq(const KPacked& o) const { return v == o.v; }
   __device__ KPacked sx(int m) const { return {shfl_xor64(v, m)}; }
@@ -69,6 +73,9 @@ struct KFull {
   uint32_t id;
   __device__ static KFull mx() { return {~0ull, ~0u}; }
   __device__ static KFull load(const KeySrc& s, uint32_t u) { return {s.r[u], u}; }
+  using Raw = uint64_t;
+  __device__ static Raw fetch(const KeySrc& s, uint32_t u) { return s.r[u]; }
+  __device__ static KFull finish(Raw x, const KeySrc&, uint32_t u) { return {x, u}; }
   __device__ bool lt(const KFull& o) const { return r < o.r || (r == o.r && id < o.id); }
   __device__ bool eq(const KFull& o) const { return r == o.r && id == o.id; }
   __device__ KFull sx(int m) const { return {shfl_xor64(r, m), shfl_xor32(id, m)}; }
@@ -82,6 +89,11 @@ struct KWide {
   uint32_t id;
   __device__ static KWide mx() { return {~0ull, ~0ull, ~0u}; }
   __device__ static KWide load(const KeySrc& s, uint32_t u) { return {s.r[2ull * u + 1], s.r[2ull * u], u}; }
+  struct Raw {
+    uint64_t hi, lo;
+  };
+  __device__ static Raw fetch(const KeySrc& s, uint32_t u) { return {s.r[2ull * u + 1], s.r[2ull * u]}; }
+  __device__ static KWide finish(Raw x, const KeySrc&, uint32_t u) { return {x.hi, x.lo, u}; }
   __device__ bool lt(const KWide& o) const {
     return hi < o.hi || (hi == o.hi && (lo < o.lo || (lo == o.lo && id < o.id)));
   }
@@ -98,6 +110,9 @@ struct KRank {
   uint32_t v;
   __device__ static KRank mx() { return {~0u}; }
   __device__ static KRank load(const KeySrc& s, uint32_t u) { return {s.rank[u]}; }
+  using Raw = uint32_t;
+  __device__ static Raw fetch(const KeySrc& s, uint32_t u) { return s.rank[u]; }
+  __device__ static KRank finish(Raw x, const KeySrc&, uint32_t) { return {x}; }
   __device__ bool lt(const KRank& o) const { return v < o.v; }
   __device__ bool eq(const KRank& o) const { return v == o.v; }
   __device__ KRank sx(int m) const { return {shfl_xor32(v, m)}; }
@@ -140,29 +155,13 @@ __device__ __forceinline__ KT member_key(const KeySrc& src, const KT* hkey, uint
   return (raw & kHotFlag) ? hkey[raw & ~kHotFlag] : KT::load(src, raw);
 }
 
-// Form for batched loads: the LDS slot is always read (its index masked into
-// the table), then one of the two keys is selected.
-// * Masked: the global key is gathered only for a valid, non-hot member.  The
-//   gathers run under per-lane masks, and the compiler waits for each before the
-//   next, but no load is spent on hot members (the right choice when hot nodes
-//   hold most member occurrences).
-// * Full: every row's key is gathered, a hot member's from its hot index read
-//   as a node id (below the hot count, which never exceeds n; padding is node
-//   0), so a batch issues all its gathers back to back with no branch.
-template <class KT, bool kMasked>
-__device__ __forceinline__ KT member_key_nb(const KeySrc& src, const KT* hkey, uint32_t raw, bool valid) {
-  KT a = hkey[raw & (kHotMax - 1)];
-  if constexpr (kMasked) {
-    // a member outside the leaf (invalid) keeps whatever key it read: rows
-    // past the leaf's size are never compared
-    if (valid && !(raw & kHotFlag)) a = KT::load(src, raw);
-    return a;
-  } else {
-    const KT b = KT::load(src, raw & ~kHotFlag);
-    return KT::pick((raw & kHotFlag) != 0, a, b);
-  }
-}
-
+// Gather modes of the lane-tile pass (every lane gathers a key for every row,
+// with no lane mask; only the address of a hot or padding member differs):
+// * Masked: it reads the problem's first node, one line shared by the
+//   wavefront, so the gather costs the cache almost nothing (the right choice
+//   when hot nodes hold most member occurrences).
+// * Full: it reads its hot index as a node id (below the hot count, which
+//   never exceeds n; padding is node 0).
 // ----------------------------------------------------------------------------
 // Leaf credit (paper: Algorithm 1's per-clique minimum-load step, batched per
 // SCT leaf with the counts of Lemma 5).
@@ -293,16 +292,33 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
   for (uint32_t u = 0; u < U; ++u) nxt[u] = col[(size_t)min(u, smax - 1) * 64];
   for (uint32_t x0 = 0; x0 < smax; x0 += U) {
     uint32_t raw[U];
-    KT key[U];
+    KT key[U], hk[U];
+    typename KT::Raw g[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) raw[u] = nxt[u];
+    // Hot keys first (so every row has arrived before the first gather and no
+    // gather waits behind a row), then every lane's gather with no lane mask
+    // (so the compiler counts the loads in flight exactly), then the next
+    // batch's rows; the keys are made only after that, so waiting for the
+    // gathers leaves the rows in flight.  A hot or padding member gathers a
+    // line shared by the wavefront (masked mode: the problem's first node) or
+    // its hot index read as a node id (full mode), and takes its hot key.
 #pragma unroll
-    for (uint32_t u = 0; u < U; ++u) key[u] = member_key_nb<KT, kMasked>(src, hkey, raw[u], x0 + u < s);
+    for (uint32_t u = 0; u < U; ++u) hk[u] = hkey[raw[u] & (kHotMax - 1)];
     __builtin_amdgcn_sched_barrier(0);
-    if (x0 + U < smax) {
 #pragma unroll
-      for (uint32_t u = 0; u < U; ++u) nxt[u] = col[(size_t)min(x0 + U + u, smax - 1) * 64];
+    for (uint32_t u = 0; u < U; ++u) {
+      uint32_t at = raw[u] & ~kHotFlag;
+      if constexpr (kMasked) at = (x0 + u < s && !(raw[u] & kHotFlag)) ? raw[u] : src.base;
+      g[u] = KT::fetch(src, at);
     }
+    __builtin_amdgcn_sched_barrier(0);
+    // unconditional (the last batch reads the tile's last row again)
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) nxt[u] = col[(size_t)min(x0 + U + u, smax - 1) * 64];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u)
+      key[u] = KT::pick((raw[u] & kHotFlag) != 0, hk[u], KT::finish(g[u], src, raw[u] & ~kHotFlag));
     if (__ballot(x0 < h)) {
       // some lane still has hold rows here (hold members precede pivot
       // members, so m is final when a lane compares its first pivot member)
