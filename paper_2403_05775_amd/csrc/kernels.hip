@@ -790,15 +790,19 @@ __device__ __forceinline__ void pb_leaf_wave(const uint64_t* lr, const uint32_t*
   }
 }
 
-// Tiles first .. ntiles - 1, blockDim.x / 64 wavefronts per workgroup, wavefront
-// w of workgroup b taking tiles first + b * W + w, + gridDim.x * W, ..  Dynamic
-// LDS: one region of `rows` rows of 64 loads (u64) per wavefront; a lane tile
-// stages its members' loads there (each lane then reads only its own column), a
-// big leaf its members' loads contiguously.  Member words are read from memory
-// (a lane tile's rows are contiguous).  Hot loads, ids and credit totals live in
-// static LDS, shared by the workgroup; the totals reach the hot nodes' slot
-// entries at the end, as in the leaf-credit pass.
-__global__ __launch_bounds__(256) void pb_kernel(const Tile* __restrict__ tiles, uint32_t first, uint32_t ntiles,
+// Four wavefronts per workgroup.  The first `nbig` workgroups take one tile
+// each of tiles 0 .. nbig - 1 (big leaves and lane tiles of more than
+// kPbMidRows rows) on their first wavefront, staged in the whole dynamic LDS;
+// the others take tiles nbig .. ntiles - 1, wavefront w of workgroup nbig + b
+// taking tiles nbig + 4 b + w, + 4 (gridDim.x - nbig), .., each staged in its
+// own region of `rows` rows (one launch, so the large tiles' long searches
+// overlap the rest).  A lane tile stages its members' loads (u64) in rows of
+// 64 (each lane then reads only its own column), a big leaf its members' loads
+// contiguously.  Member words are read from memory (a lane tile's rows are
+// contiguous).  Hot loads, ids and credit totals live in static LDS, shared by
+// the workgroup; the totals reach the hot nodes' slot entries at the end, as
+// in the leaf-credit pass.
+__global__ __launch_bounds__(256) void pb_kernel(const Tile* __restrict__ tiles, uint32_t nbig, uint32_t ntiles,
                                                  const uint32_t* __restrict__ members,
                                                  const uint32_t* __restrict__ hdr,
                                                  const uint64_t* __restrict__ binom, uint32_t k1,
@@ -810,9 +814,12 @@ __global__ __launch_bounds__(256) void pb_kernel(const Tile* __restrict__ tiles,
   __shared__ uint32_t hid[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t nw = blockDim.x >> 6;
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  uint64_t* lr = pb_lds + (size_t)w * rows * 64;
+  const bool big = blockIdx.x < nbig;
+  uint64_t* lr = big ? pb_lds : pb_lds + (size_t)w * rows * 64;
+  // this wavefront's tiles: one large tile, or every (4 (gridDim.x - nbig))-th from its start
+  uint32_t tile = big ? (w == 0 ? blockIdx.x : ntiles) : nbig + (blockIdx.x - nbig) * 4u + w;
+  const uint32_t step = big ? ntiles : (gridDim.x - nbig) * 4u;
   for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
     hid[i] = hot[i];
     hr[i] = r[hot[i]];
@@ -820,7 +827,7 @@ __global__ __launch_bounds__(256) void pb_kernel(const Tile* __restrict__ tiles,
   }
   __syncthreads();
   Sink sink{hcnt, out, 0u, 0ull};
-  for (uint32_t tile = first + blockIdx.x * nw + w; tile < ntiles; tile += gridDim.x * nw) {
+  for (; tile < ntiles; tile += step) {
     const Tile t = tiles[tile];
     const uint32_t smax = t.info >> 16;
     if ((t.info & 7u) == kTileBig) {
@@ -1739,19 +1746,17 @@ int launch_pb(const kdss_plan* P, const WsView& ws, const void* d_r, uint64_t* o
   const uint32_t ntiles = (uint32_t)P->tiles.size();
   if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
   const uint32_t split = P->pb_split, nhot = (uint32_t)P->hot.size();
-  // big leaves and lane tiles of more than kPbRegRows rows, staged in LDS: those
-  // of more than kPbMidRows rows (one wavefront per workgroup), then the rest
-  // (four per workgroup, sharing the hot-node tables)
-  const uint32_t mid = P->pb_mid;
-  for (int part = 0; part < 2; ++part) {
-    const uint32_t lo = part ? mid : 0u, hi = part ? split : mid, rows = part ? P->pb_rows_lo : P->pb_rows;
-    if (lo >= hi) continue;
-    const uint32_t nw = part ? 4u : 1u;
-    const uint32_t blocks = std::min<uint32_t>((hi - lo + nw - 1) / nw, 4u * P->leaf_blocks / nw);
-    pb_kernel<<<blocks, 64 * nw, (size_t)rows * 64 * 8 * nw, st>>>(
-        ws.at<Tile>(P->off_tiles), lo, hi, ws.at<uint32_t>(P->off_members), ws.at<uint32_t>(P->off_hdr),
+  // big leaves and lane tiles of more than kPbRegRows rows, staged in LDS, in
+  // one launch: one workgroup per tile of more than kPbMidRows rows, then
+  // four wavefronts per workgroup for the rest
+  if (split) {
+    const uint32_t nbig = P->pb_mid, nmid = split - nbig;
+    const uint32_t mid_blocks = nmid ? std::min<uint32_t>((nmid + 3) / 4, P->leaf_blocks) : 0u;
+    const size_t rows = std::max<size_t>((size_t)4 * P->pb_rows_lo, nbig ? P->pb_rows : 0);
+    pb_kernel<<<nbig + mid_blocks, 256, rows * 64 * 8, st>>>(
+        ws.at<Tile>(P->off_tiles), nbig, split, ws.at<uint32_t>(P->off_members), ws.at<uint32_t>(P->off_hdr),
         ws.at<uint64_t>(P->off_binom), P->k1, static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot), nhot,
-        out, ws.at<uint64_t>(P->off_scratch), rows);
+        out, ws.at<uint64_t>(P->off_scratch), P->pb_rows_lo);
     HIP_TRY(hipGetLastError(), "PBUpdate launch");
   }
   if (split < ntiles) {   // the other lane tiles, from registers
