@@ -91,3 +91,30 @@ def test_gpu_tree_chung_lu_1m(K):
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
     host.close()
     gpu.close()
+
+
+@pytest.mark.parametrize("n,p,k", [(300, 0.55, 3), (300, 0.55, 4), (420, 0.62, 3)])
+def test_gpu_tree_dense_graphs(K, oracle_mod, n, p, k):
+    """Dense graphs whose degeneracy needs three (146) and four (236) bitset
+    words per node: c_k equals the host tree's and the oracle's count, and a
+    run on the GPU-built tree equals the oracle bit for bit."""
+    g = synth.erdos_renyi(n, p, seed=5)
+    t = K.GpuTree(g, k)
+    st = t.stats()
+    print(f"dense n={n} p={p} k={k}: degeneracy {st.degeneracy}, {st.leaves} leaves", flush=True)
+    assert st.degeneracy > 128
+    host = K.Tree(g, k)
+    assert st.c_k.value == host.stats().c_k.value == oracle_mod.count(g.n, g.row_ptr, g.col, k)
+    host.close()
+    T = 3
+    plan = K.Plan(t, T)
+    ws = plan.alloc_workspace()
+    plan.upload(ws)
+    r = plan.alloc_loads()
+    order = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    res, _ = plan.run(ws, T, r, order)
+    torch.cuda.synchronize()
+    ref = oracle_mod.solve(g.n, g.row_ptr, g.col, k, T)
+    assert np.array_equal(r.cpu().numpy().view(np.uint64)[: g.n], ref["r"])
+    assert (res.size, res.dens_num.value, res.ub_num.value) == (ref["size"], ref["dens_num"], ref["ub_num"])
+    t.close()
