@@ -49,20 +49,37 @@ int validate_csr(const kdss_csr* g) {
   if (rp[0] != 0 || rp[n] != g->nnz) return fail(KDSS_EGRAPH, "row_ptr[0] != 0 or row_ptr[n] != nnz");
   for (uint32_t u = 0; u < n; ++u)
     if (rp[u + 1] < rp[u]) return fail(KDSS_EGRAPH, "row_ptr decreases at node " + std::to_string(u));
-  for (uint32_t u = 0; u < n; ++u) {
-    for (uint64_t e = rp[u]; e < rp[u + 1]; ++e) {
-      uint32_t v = g->col[e];
-      if (v >= n) return fail(KDSS_EGRAPH, "neighbour id out of range in row " + std::to_string(u));
-      if (v == u) return fail(KDSS_EGRAPH, "self-loop at node " + std::to_string(u));
-      if (e > rp[u] && g->col[e - 1] >= v)
-        return fail(KDSS_EGRAPH, "row " + std::to_string(u) + " not strictly ascending");
-      const uint32_t* b = g->col + rp[v];
-      const uint32_t* en = g->col + rp[v + 1];
-      const uint32_t* f = std::lower_bound(b, en, u);
-      if (f == en || *f != u)
-        return fail(KDSS_EGRAPH, "edge " + std::to_string(u) + "-" + std::to_string(v) + " is not symmetric");
+  // rows in contiguous ranges on host threads; each range keeps its first
+  // error, and the earliest range's is reported (the error a row-by-row pass
+  // meets first)
+  struct Err {
+    bool set = false;
+    std::string msg;
+  };
+  std::vector<Err> errs(host_threads());
+  parallel_ranges(n, 4096, [&](unsigned t, uint64_t b, uint64_t e) {
+    for (uint32_t u = (uint32_t)b; u < (uint32_t)e; ++u) {
+      for (uint64_t x = rp[u]; x < rp[u + 1]; ++x) {
+        const uint32_t v = g->col[x];
+        std::string m;
+        if (v >= n) m = "neighbour id out of range in row " + std::to_string(u);
+        else if (v == u) m = "self-loop at node " + std::to_string(u);
+        else if (x > rp[u] && g->col[x - 1] >= v) m = "row " + std::to_string(u) + " not strictly ascending";
+        else {
+          const uint32_t* bb = g->col + rp[v];
+          const uint32_t* en = g->col + rp[v + 1];
+          const uint32_t* f = std::lower_bound(bb, en, u);
+          if (f == en || *f != u) m = "edge " + std::to_string(u) + "-" + std::to_string(v) + " is not symmetric";
+        }
+        if (!m.empty()) {
+          errs[t] = Err{true, m};
+          return;
+        }
+      }
     }
-  }
+  });
+  for (const Err& e : errs)
+    if (e.set) return fail(KDSS_EGRAPH, e.msg);
   return KDSS_OK;
 }
 

@@ -1,12 +1,8 @@
 // The k-pruned succinct clique tree (paper: Sec. 2, Lemmas 3-5) built on the
 // GPU.  The graph is first oriented along the degeneracy order: out(v) holds
 // v's later neighbours, ascending by id, at most D (the degeneracy) of them.
-// One thread per start node v then gives out(v) local indices, builds their
-// adjacency bitsets (out(x) of each member x merged with out(v): every edge
-// inside out(v) is found once, from its earlier end) and runs the pivoting
-// recursion with an explicit stack, both in a per-thread slice of global
-// scratch sized by D (word i of thread t at i * threads + t, so a wavefront's
-// equal-index accesses coalesce):
+// The tree of a start node v is the pivoting recursion over out(v) (local
+// indices, adjacency bitsets):
 //   node (H, P, S): h = |H| = k: the leaf (H, {}); h + p + |S| < k: nothing;
 //   S empty: the leaf (H, P) when p >= k - h; otherwise a pivot q of S with
 //   the most neighbours in S: (H, P + q, S and N(q)), then for each w of S
@@ -15,10 +11,18 @@
 // Every k-clique of the graph lies in exactly one leaf (the tree of a node
 // covers the cliques whose earliest node it is); the leaves may differ from
 // the host build's, and any such tree gives the same results.
-// Start nodes run in decreasing |out(v)| (the heaviest recursions first, and
-// wavefronts of similar work); nodes with |out(v)| + 1 < k hold no k-clique
-// and are skipped.  Two passes over chunks of start nodes: counts, then the
-// leaves written at the prefix-sum offsets.
+// A hub's tree can hold millions of leaves, so the work is split at the root:
+// one thread per start node builds its bitsets once (out(x) of each member x
+// merged with out(v): every edge inside out(v) is found once, from its
+// earlier end) into a device store, picks the root pivot and lists the root's
+// children that can hold a k-clique; then one thread per child ("task") runs
+// the recursion below it with an explicit stack in a per-thread slice of
+// global scratch sized by D (word i of thread t at i * threads + t, so a
+// wavefront's equal-index accesses coalesce).  Start nodes run in decreasing
+// |out(v)| and a node's tasks in its tree's order, so the leaves come out in
+// the order a whole-tree recursion per node would give.  Nodes with
+// |out(v)| + 1 < k hold no k-clique and are skipped.  Two passes over chunks
+// of tasks: counts, then the leaves written at the prefix-sum offsets.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,11 +39,12 @@ namespace {
 constexpr uint32_t kSctMaxLocal = 256;                 // largest degeneracy handled
 constexpr uint32_t kSctMaxHold = 32;                   // hold list entries (k <= 31)
 constexpr size_t kSctScratchBudget = size_t(8) << 30;  // per-chunk scratch bytes
+constexpr uint32_t kPivotTask = 0x80000000u;           // task code: the root's pivot child
 
-// Scratch words of one thread for degeneracy D with W bitset words:
-// adjacency D * W, frames (D + 2) * (2 W + 1) in 64-bit words; hold and pivot
-// lists kSctMaxHold + D in 32-bit words.
-inline size_t sct_words64(uint32_t D, uint32_t W) { return (size_t)D * W + (size_t)(D + 2) * (2 * W + 1); }
+// Scratch words of one task thread for degeneracy D with W bitset words:
+// frames (D + 2) * (2 W + 1) in 64-bit words; hold and pivot lists
+// kSctMaxHold + D in 32-bit words.
+inline size_t sct_words64(uint32_t D, uint32_t W) { return (size_t)(D + 2) * (2 * W + 1); }
 inline size_t sct_words32(uint32_t D) { return kSctMaxHold + (size_t)D; }
 
 int sct_hip_fail(hipError_t e, const char* what) {
@@ -81,33 +86,46 @@ __global__ __launch_bounds__(256) void orient_fill_kernel(const uint64_t* __rest
   }
 }
 
-// One thread per start node perm[v0 + t].  D: the degeneracy (every |out(v)|
-// is at most D, W * 64 >= D).  write = 0: counts[2 t] = leaves, counts[2 t + 1]
-// = members.  write = 1: leaves from leaf_off[t], members from member_off[t];
-// hp[leaf] = h | p << 8.  *err: 1 = an out-list above D, 2 = the stack would
-// overflow (neither writes out of bounds).
+// The first d bits set (d <= 64 W).
 template <uint32_t W>
-__global__ __launch_bounds__(64) void sct_kernel(const uint64_t* __restrict__ orp, const uint32_t* __restrict__ ocol,
-                                                 const uint32_t* __restrict__ perm, uint32_t k, uint32_t D,
-                                                 uint32_t v0, uint32_t count, uint64_t* __restrict__ s64,
-                                                 uint32_t* __restrict__ s32, int write,
-                                                 uint64_t* __restrict__ counts, const uint64_t* __restrict__ leaf_off,
-                                                 const uint64_t* __restrict__ member_off, uint32_t* __restrict__ hp,
-                                                 uint32_t* __restrict__ members, int* __restrict__ err) {
+__device__ inline void all_bits(uint64_t (&S)[W], uint32_t d) {
+  for (uint32_t w = 0; w < W; ++w) {
+    const uint32_t lo = w * 64;
+    S[w] = d >= lo + 64 ? ~0ull : (d > lo ? (1ull << (d - lo)) - 1 : 0ull);
+  }
+}
+
+// The root's hold child for w (local index): S and N(w) minus the members of
+// NQ (S's non-neighbours of the pivot, handled in local order) before w.
+template <uint32_t W>
+__device__ inline void hold_child(const uint64_t (&S)[W], const uint64_t (&NQ)[W], const uint64_t* A, uint32_t wi,
+                                  uint64_t (&out)[W]) {
+  for (uint32_t x = 0; x < W; ++x) {
+    const uint64_t before = x < (wi >> 6) ? ~0ull : (x == (wi >> 6) ? (1ull << (wi & 63)) - 1 : 0ull);
+    out[x] = S[x] & A[(size_t)wi * W + x] & ~(NQ[x] & before);
+  }
+}
+
+// One thread per active start node perm[t] (t < nact).  D: the degeneracy
+// (every |out(v)| is at most D, W * 64 >= D).  The node's bitsets live at
+// abits + aoff[t], row i of W words at row i.  write = 0: builds the bitsets,
+// picks the root pivot (qv[t]) and counts the root's children that can hold
+// a k-clique (tcnt[t]): the pivot child (H = {v}, P = {q}) when
+// 2 + |S and N(q)| >= k, and each hold child (H = {v, w}, P = {}) when
+// 2 + |its S| >= k.  write = 1: their task records from toff[t], in the
+// tree's order: t << 32 | code, code = q | kPivotTask or w.  *err: 1 = an
+// out-list above D.
+template <uint32_t W>
+__global__ __launch_bounds__(64) void root_kernel(const uint64_t* __restrict__ orp, const uint32_t* __restrict__ ocol,
+                                                  const uint32_t* __restrict__ perm, uint32_t k, uint32_t D,
+                                                  uint32_t nact, uint64_t* __restrict__ abits,
+                                                  const uint64_t* __restrict__ aoff, uint32_t* __restrict__ qv,
+                                                  int write, uint32_t* __restrict__ tcnt,
+                                                  const uint64_t* __restrict__ toff, uint64_t* __restrict__ tasks,
+                                                  int* __restrict__ err) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  const uint32_t v = perm[v0 + t];
-  const size_t stride = count;
-  const size_t fbase = (size_t)D * W;
-  const uint32_t nframes = D + 2;
-  auto A = [&](uint32_t i, uint32_t w) -> uint64_t& { return s64[((size_t)i * W + w) * stride + t]; };
-  auto F = [&](uint32_t f, uint32_t w) -> uint64_t& {
-    return s64[(fbase + (size_t)f * (2 * W + 1) + w) * stride + t];
-  };
-  auto Hl = [&](uint32_t i) -> uint32_t& { return s32[(size_t)i * stride + t]; };
-  auto Pl = [&](uint32_t i) -> uint32_t& { return s32[((size_t)kSctMaxHold + i) * stride + t]; };
-  uint64_t nleaves = 0, nmembers = 0;
-  const uint64_t lo_leaf = write ? leaf_off[t] : 0, lo_mem = write ? member_off[t] : 0;
+  if (t >= nact) return;
+  const uint32_t v = perm[t];
   const uint64_t ob = orp[v];
   const uint32_t d = (uint32_t)(orp[v + 1] - ob);
   const uint32_t* __restrict__ L = ocol + ob;
@@ -115,9 +133,13 @@ __global__ __launch_bounds__(64) void sct_kernel(const uint64_t* __restrict__ or
     atomicOr(err, 1);
     return;
   }
-  if (d + 1 >= k) {
+  uint64_t* __restrict__ A = abits + aoff[t];
+  uint64_t S[W];
+  all_bits<W>(S, d);
+  uint32_t q = 0;
+  if (!write) {
     for (uint32_t i = 0; i < d; ++i)
-      for (uint32_t w = 0; w < W; ++w) A(i, w) = 0;
+      for (uint32_t w = 0; w < W; ++w) A[(size_t)i * W + w] = 0;
     // edges inside out(v): merge out(x) with out(v), both ascending by id
     for (uint32_t i = 0; i < d; ++i) {
       const uint32_t x = L[i];
@@ -131,97 +153,182 @@ __global__ __launch_bounds__(64) void sct_kernel(const uint64_t* __restrict__ or
         } else if (ya > yb) {
           ++j;
         } else {
-          A(i, j >> 6) |= 1ull << (j & 63);
-          A(j, i >> 6) |= 1ull << (i & 63);
+          A[(size_t)i * W + (j >> 6)] |= 1ull << (j & 63);
+          A[(size_t)j * W + (i >> 6)] |= 1ull << (i & 63);
           ++a;
           ++j;
         }
       }
     }
-    auto emit = [&](uint32_t h, uint32_t p) {
-      if (write) {
-        hp[lo_leaf + nleaves] = h | (p << 8);
-        uint64_t at = lo_mem + nmembers;
-        for (uint32_t i = 0; i < h; ++i) members[at++] = Hl(i);
-        for (uint32_t i = 0; i < p; ++i) members[at++] = Pl(i);
-      }
-      ++nleaves;
-      nmembers += h + p;
-    };
-    // root frame: H = {v}, P = {}, S = all of out(v)
-    Hl(0) = v;
-    for (uint32_t w = 0; w < W; ++w) {
-      const uint32_t lo = w * 64;
-      F(0, w) = d >= lo + 64 ? ~0ull : (d > lo ? (1ull << (d - lo)) - 1 : 0ull);
+    // root pivot: the member with the most neighbours in S (lowest index on ties)
+    uint32_t best = 0;
+    bool first = true;
+    for (uint32_t i = 0; i < d; ++i) {
+      uint32_t c = 0;
+      for (uint32_t x = 0; x < W; ++x) c += __popcll(A[(size_t)i * W + x] & S[x]);
+      if (first || c > best) { q = i; best = c; first = false; }
     }
-    F(0, 2 * W) = (uint64_t)1 << 16;   // q 0, h 1, p 0, stage 0
-    uint32_t depth = 1;
-    while (depth > 0) {
-      const uint32_t f = depth - 1;
-      const uint64_t meta = F(f, 2 * W);
-      const uint32_t h = (uint32_t)(meta >> 16) & 0xFFFFu, p = (uint32_t)(meta >> 32) & 0xFFFFu;
-      const uint32_t stage = (uint32_t)(meta >> 48);
-      uint64_t S[W];
-      for (uint32_t w = 0; w < W; ++w) S[w] = F(f, w);
-      if (stage == 0) {
-        uint32_t cs = 0;
-        for (uint32_t w = 0; w < W; ++w) cs += __popcll(S[w]);
-        if (h == k) { emit(h, 0); --depth; continue; }
-        if (h + p + cs < k) { --depth; continue; }
-        if (cs == 0) {
-          if (p >= k - h) emit(h, p);
-          --depth;
-          continue;
-        }
-        // pivot: the member of S with the most neighbours in S (lowest index on ties)
-        uint32_t q = 0, best = 0;
-        bool first = true;
-        for (uint32_t w = 0; w < W; ++w) {
-          uint64_t bits = S[w];
-          while (bits) {
-            const uint32_t i = w * 64 + (uint32_t)__ffsll((unsigned long long)bits) - 1;
-            bits &= bits - 1;
-            uint32_t c = 0;
-            for (uint32_t x = 0; x < W; ++x) c += __popcll(A(i, x) & S[x]);
-            if (first || c > best) { q = i; best = c; first = false; }
-          }
-        }
-        if (depth == nframes || p >= D) { atomicOr(err, 2); return; }
-        uint64_t Aq[W];
-        for (uint32_t w = 0; w < W; ++w) Aq[w] = A(q, w);
-        for (uint32_t w = 0; w < W; ++w) {
-          uint64_t nn = S[w] & ~Aq[w];
-          if (w == (q >> 6)) nn &= ~(1ull << (q & 63));
-          F(f, W + w) = nn;
-        }
-        F(f, 2 * W) = (uint64_t)q | ((uint64_t)h << 16) | ((uint64_t)p << 32) | (1ull << 48);
-        Pl(p) = L[q];
-        for (uint32_t w = 0; w < W; ++w) F(depth, w) = S[w] & Aq[w];
-        F(depth, 2 * W) = ((uint64_t)h << 16) | ((uint64_t)(p + 1) << 32);
-        ++depth;
-        continue;
+    qv[t] = q;
+  } else {
+    q = qv[t];
+  }
+  uint64_t NQ[W];
+  uint32_t cp = 0;
+  for (uint32_t w = 0; w < W; ++w) {
+    const uint64_t aq = A[(size_t)q * W + w];
+    cp += __popcll(S[w] & aq);
+    NQ[w] = S[w] & ~aq;
+  }
+  NQ[q >> 6] &= ~(1ull << (q & 63));
+  const uint64_t base = write ? toff[t] : 0;
+  uint32_t n = 0;
+  if (2 + cp >= k) {
+    if (write) tasks[base + n] = ((uint64_t)t << 32) | (q | kPivotTask);
+    ++n;
+  }
+  for (uint32_t w = 0; w < W; ++w) {
+    uint64_t bits = NQ[w];
+    while (bits) {
+      const uint32_t wi = w * 64 + (uint32_t)__ffsll((unsigned long long)bits) - 1;
+      bits &= bits - 1;
+      uint64_t C[W];
+      hold_child<W>(S, NQ, A, wi, C);
+      uint32_t c = 0;
+      for (uint32_t x = 0; x < W; ++x) c += __popcll(C[x]);
+      if (2 + c >= k) {
+        if (write) tasks[base + n] = ((uint64_t)t << 32) | wi;
+        ++n;
       }
-      // stage 1: the next non-neighbour of the pivot, as a hold node
-      uint32_t w0 = W;
-      uint64_t nw = 0;
-      for (uint32_t w = 0; w < W; ++w) {
-        nw = F(f, W + w);
-        if (nw) { w0 = w; break; }
-      }
-      if (w0 == W) { --depth; continue; }
-      const uint32_t wi = w0 * 64 + (uint32_t)__ffsll((unsigned long long)nw) - 1;
-      F(f, W + w0) = nw & (nw - 1);
-      if (depth == nframes || h >= kSctMaxHold) { atomicOr(err, 2); return; }
-      Hl(h) = L[wi];
-      for (uint32_t w = 0; w < W; ++w) F(depth, w) = S[w] & A(wi, w);
-      F(f, wi >> 6) = S[wi >> 6] & ~(1ull << (wi & 63));   // later branches exclude w
-      F(depth, 2 * W) = ((uint64_t)(h + 1) << 16) | ((uint64_t)p << 32);
-      ++depth;
     }
   }
+  if (!write) tcnt[t] = n;
+}
+
+// One thread per task tasks[v0 + i] (i < count): the recursion below one of
+// a root's children, from the start node's stored bitsets.  write = 0:
+// counts[2 i] = leaves, counts[2 i + 1] = members.  write = 1: leaves from
+// leaf_off[i], members from member_off[i]; hp[leaf] = h | p << 8.  *err:
+// 2 = the stack would overflow (nothing is written out of bounds).
+template <uint32_t W>
+__global__ __launch_bounds__(64) void task_kernel(const uint64_t* __restrict__ orp, const uint32_t* __restrict__ ocol,
+                                                  const uint32_t* __restrict__ perm, uint32_t k, uint32_t D,
+                                                  const uint64_t* __restrict__ abits,
+                                                  const uint64_t* __restrict__ aoff, const uint32_t* __restrict__ qv,
+                                                  const uint64_t* __restrict__ tasks, uint64_t v0, uint32_t count,
+                                                  uint64_t* __restrict__ s64, uint32_t* __restrict__ s32, int write,
+                                                  uint64_t* __restrict__ counts, const uint64_t* __restrict__ leaf_off,
+                                                  const uint64_t* __restrict__ member_off, uint32_t* __restrict__ hp,
+                                                  uint32_t* __restrict__ members, int* __restrict__ err) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t rec = tasks[v0 + i];
+  const uint32_t t = (uint32_t)(rec >> 32), code = (uint32_t)rec;
+  const uint32_t v = perm[t];
+  const uint64_t ob = orp[v];
+  const uint32_t d = (uint32_t)(orp[v + 1] - ob);
+  const uint32_t* __restrict__ L = ocol + ob;
+  const uint64_t* __restrict__ A = abits + aoff[t];
+  const size_t stride = count;
+  const uint32_t nframes = D + 2;
+  auto F = [&](uint32_t f, uint32_t w) -> uint64_t& { return s64[((size_t)f * (2 * W + 1) + w) * stride + i]; };
+  auto Hl = [&](uint32_t x) -> uint32_t& { return s32[(size_t)x * stride + i]; };
+  auto Pl = [&](uint32_t x) -> uint32_t& { return s32[((size_t)kSctMaxHold + x) * stride + i]; };
+  uint64_t nleaves = 0, nmembers = 0;
+  const uint64_t lo_leaf = write ? leaf_off[i] : 0, lo_mem = write ? member_off[i] : 0;
+  auto emit = [&](uint32_t h, uint32_t p) {
+    if (write) {
+      hp[lo_leaf + nleaves] = h | (p << 8);
+      uint64_t at = lo_mem + nmembers;
+      for (uint32_t x = 0; x < h; ++x) members[at++] = Hl(x);
+      for (uint32_t x = 0; x < p; ++x) members[at++] = Pl(x);
+    }
+    ++nleaves;
+    nmembers += h + p;
+  };
+  // the root's child: its frame at depth 0
+  uint64_t S[W];
+  all_bits<W>(S, d);
+  const uint32_t q = qv[t];
+  Hl(0) = v;
+  if (code & kPivotTask) {
+    Pl(0) = L[q];
+    for (uint32_t w = 0; w < W; ++w) F(0, w) = S[w] & A[(size_t)q * W + w];
+    F(0, 2 * W) = ((uint64_t)1 << 16) | ((uint64_t)1 << 32);   // h 1, p 1, stage 0
+  } else {
+    uint64_t NQ[W], C[W];
+    for (uint32_t w = 0; w < W; ++w) NQ[w] = S[w] & ~A[(size_t)q * W + w];
+    NQ[q >> 6] &= ~(1ull << (q & 63));
+    hold_child<W>(S, NQ, A, code, C);
+    Hl(1) = L[code];
+    for (uint32_t w = 0; w < W; ++w) F(0, w) = C[w];
+    F(0, 2 * W) = (uint64_t)2 << 16;   // h 2, p 0, stage 0
+  }
+  uint32_t depth = 1;
+  while (depth > 0) {
+    const uint32_t f = depth - 1;
+    const uint64_t meta = F(f, 2 * W);
+    const uint32_t h = (uint32_t)(meta >> 16) & 0xFFFFu, p = (uint32_t)(meta >> 32) & 0xFFFFu;
+    const uint32_t stage = (uint32_t)(meta >> 48);
+    uint64_t Sf[W];
+    for (uint32_t w = 0; w < W; ++w) Sf[w] = F(f, w);
+    if (stage == 0) {
+      uint32_t cs = 0;
+      for (uint32_t w = 0; w < W; ++w) cs += __popcll(Sf[w]);
+      if (h == k) { emit(h, 0); --depth; continue; }
+      if (h + p + cs < k) { --depth; continue; }
+      if (cs == 0) {
+        if (p >= k - h) emit(h, p);
+        --depth;
+        continue;
+      }
+      // pivot: the member of S with the most neighbours in S (lowest index on ties)
+      uint32_t qq = 0, best = 0;
+      bool first = true;
+      for (uint32_t w = 0; w < W; ++w) {
+        uint64_t bits = Sf[w];
+        while (bits) {
+          const uint32_t x = w * 64 + (uint32_t)__ffsll((unsigned long long)bits) - 1;
+          bits &= bits - 1;
+          uint32_t c = 0;
+          for (uint32_t y = 0; y < W; ++y) c += __popcll(A[(size_t)x * W + y] & Sf[y]);
+          if (first || c > best) { qq = x; best = c; first = false; }
+        }
+      }
+      if (depth == nframes || p >= D) { atomicOr(err, 2); return; }
+      uint64_t Aq[W];
+      for (uint32_t w = 0; w < W; ++w) Aq[w] = A[(size_t)qq * W + w];
+      for (uint32_t w = 0; w < W; ++w) {
+        uint64_t nn = Sf[w] & ~Aq[w];
+        if (w == (qq >> 6)) nn &= ~(1ull << (qq & 63));
+        F(f, W + w) = nn;
+      }
+      F(f, 2 * W) = (uint64_t)qq | ((uint64_t)h << 16) | ((uint64_t)p << 32) | (1ull << 48);
+      Pl(p) = L[qq];
+      for (uint32_t w = 0; w < W; ++w) F(depth, w) = Sf[w] & Aq[w];
+      F(depth, 2 * W) = ((uint64_t)h << 16) | ((uint64_t)(p + 1) << 32);
+      ++depth;
+      continue;
+    }
+    // stage 1: the next non-neighbour of the pivot, as a hold node
+    uint32_t w0 = W;
+    uint64_t nw = 0;
+    for (uint32_t w = 0; w < W; ++w) {
+      nw = F(f, W + w);
+      if (nw) { w0 = w; break; }
+    }
+    if (w0 == W) { --depth; continue; }
+    const uint32_t wi = w0 * 64 + (uint32_t)__ffsll((unsigned long long)nw) - 1;
+    F(f, W + w0) = nw & (nw - 1);
+    if (depth == nframes || h >= kSctMaxHold) { atomicOr(err, 2); return; }
+    Hl(h) = L[wi];
+    for (uint32_t w = 0; w < W; ++w) F(depth, w) = Sf[w] & A[(size_t)wi * W + w];
+    F(f, wi >> 6) = Sf[wi >> 6] & ~(1ull << (wi & 63));   // later branches exclude w
+    F(depth, 2 * W) = ((uint64_t)(h + 1) << 16) | ((uint64_t)p << 32);
+    ++depth;
+  }
   if (!write) {
-    counts[2 * (size_t)t] = nleaves;
-    counts[2 * (size_t)t + 1] = nmembers;
+    counts[2 * (size_t)i] = nleaves;
+    counts[2 * (size_t)i + 1] = nmembers;
   }
 }
 
@@ -230,11 +337,20 @@ __global__ __launch_bounds__(64) void sct_kernel(const uint64_t* __restrict__ or
 namespace {
 
 template <uint32_t W>
-void launch_sct(uint32_t blocks, hipStream_t st, const uint64_t* orp, const uint32_t* ocol, const uint32_t* perm,
-                uint32_t k, uint32_t D, uint32_t v0, uint32_t c, uint64_t* s64, uint32_t* s32, int write,
-                uint64_t* counts, const uint64_t* loff, const uint64_t* moff, uint32_t* hp, uint32_t* mem, int* err) {
-  sct_kernel<W><<<blocks, 64, 0, st>>>(orp, ocol, perm, k, D, v0, c, s64, s32, write, counts, loff, moff, hp, mem,
-                                       err);
+void launch_root(hipStream_t st, const uint64_t* orp, const uint32_t* ocol, const uint32_t* perm, uint32_t k,
+                 uint32_t D, uint32_t nact, uint64_t* abits, const uint64_t* aoff, uint32_t* qv, int write,
+                 uint32_t* tcnt, const uint64_t* toff, uint64_t* tasks, int* err) {
+  root_kernel<W><<<(nact + 63) / 64, 64, 0, st>>>(orp, ocol, perm, k, D, nact, abits, aoff, qv, write, tcnt, toff,
+                                                  tasks, err);
+}
+
+template <uint32_t W>
+void launch_task(hipStream_t st, const uint64_t* orp, const uint32_t* ocol, const uint32_t* perm, uint32_t k,
+                 uint32_t D, const uint64_t* abits, const uint64_t* aoff, const uint32_t* qv, const uint64_t* tasks,
+                 uint64_t v0, uint32_t c, uint64_t* s64, uint32_t* s32, int write, uint64_t* counts,
+                 const uint64_t* loff, const uint64_t* moff, uint32_t* hp, uint32_t* mem, int* err) {
+  task_kernel<W><<<(c + 63) / 64, 64, 0, st>>>(orp, ocol, perm, k, D, abits, aoff, qv, tasks, v0, c, s64, s32, write,
+                                               counts, loff, moff, hp, mem, err);
 }
 
 }  // namespace
@@ -244,9 +360,9 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
   if (!g || !out) return kdss::fail(KDSS_EINVAL, "null argument");
   if (k < 2) return kdss::fail(KDSS_EINVAL, "k must be at least 2");
   if (k > kdss::kMaxK) return kdss::fail(KDSS_ERANGE, "k must be at most 31");
+  const auto t0 = clock::now();   // the build time includes the graph check, as the host build's does
   int rc = kdss::validate_csr(g);
   if (rc) return rc;
-  const auto t0 = clock::now();
   hipStream_t st = static_cast<hipStream_t>(stream);
   kdss_sct* s = new (std::nothrow) kdss_sct();
   if (!s) return kdss::fail(KDSS_ENOMEM, "cannot allocate the tree handle");
@@ -314,10 +430,47 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
       orient_fill_kernel<<<(n + 255) / 256, 256, 0, st>>>(rp, col, rank, n, orp, ocol);
       SCT_TRY(hipGetLastError(), "orientation fill launch");
     }
-    // scratch for one chunk of start nodes
+    // the roots: bitsets into the store (row length W words, start node t at
+    // aoff[t]), pivots and the number of tasks of each start node
+    std::vector<uint64_t> ao((size_t)active + 1, 0);
+    for (uint32_t t = 0; t < active; ++t) ao[t + 1] = ao[t] + (uint64_t)oc[order[t]] * W;
+    uint64_t *abits = nullptr, *aoff = nullptr, *toff = nullptr, *tasks = nullptr;
+    uint32_t *qv = nullptr, *tcnt = nullptr;
+    if ((r = alloc((void**)&abits, ao[active] * 8)) || (r = alloc((void**)&aoff, ((size_t)active + 1) * 8)) ||
+        (r = alloc((void**)&qv, (size_t)active * 4)) || (r = alloc((void**)&tcnt, (size_t)active * 4)) ||
+        (r = alloc((void**)&toff, ((size_t)active + 1) * 8)))
+      return r;
+    SCT_TRY(hipMemcpyAsync(aoff, ao.data(), ((size_t)active + 1) * 8, hipMemcpyHostToDevice, st), "upload offsets");
+    auto roots = [&](int write) {
+      if (!active) return hipSuccess;
+      switch (W) {
+        case 1: launch_root<1>(st, orp, ocol, perm, k, D, active, abits, aoff, qv, write, tcnt, toff, tasks, derr); break;
+        case 2: launch_root<2>(st, orp, ocol, perm, k, D, active, abits, aoff, qv, write, tcnt, toff, tasks, derr); break;
+        case 3: launch_root<3>(st, orp, ocol, perm, k, D, active, abits, aoff, qv, write, tcnt, toff, tasks, derr); break;
+        default: launch_root<4>(st, orp, ocol, perm, k, D, active, abits, aoff, qv, write, tcnt, toff, tasks, derr); break;
+      }
+      return hipGetLastError();
+    };
+    SCT_TRY(roots(0), "tree root launch");
+    std::vector<uint32_t> tc(std::max<uint32_t>(active, 1));
+    if (active) SCT_TRY(hipMemcpyAsync(tc.data(), tcnt, (size_t)active * 4, hipMemcpyDeviceToHost, st), "read tasks");
+    int herr = 0;
+    SCT_TRY(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, st), "read flag");
+    SCT_TRY(hipStreamSynchronize(st), "stream synchronize");
+    if (herr & 1) return kdss::fail(KDSS_EUNSUPPORTED, "internal: an out-list above the degeneracy");
+    std::vector<uint64_t> to((size_t)active + 1, 0);
+    for (uint32_t t = 0; t < active; ++t) {
+      if (tc[t] > oc[order[t]] + 1) return kdss::fail(KDSS_EUNSUPPORTED, "internal: more root children than nodes");
+      to[t + 1] = to[t] + tc[t];
+    }
+    const uint64_t ntask = to[active];
+    if ((r = alloc((void**)&tasks, ntask * 8))) return r;
+    SCT_TRY(hipMemcpyAsync(toff, to.data(), ((size_t)active + 1) * 8, hipMemcpyHostToDevice, st), "upload offsets");
+    SCT_TRY(roots(1), "tree root launch");
+    // scratch for one chunk of tasks
     const size_t per_thread = sct_words64(D, W) * 8 + sct_words32(D) * 4;
-    const uint32_t chunk = (uint32_t)std::max<size_t>(
-        64, std::min<size_t>(std::max<uint32_t>(active, 1), kSctScratchBudget / per_thread));
+    const uint32_t chunk = (uint32_t)std::max<uint64_t>(
+        64, std::min<uint64_t>(std::max<uint64_t>(ntask, 1), kSctScratchBudget / per_thread));
     uint64_t *s64 = nullptr, *dcounts = nullptr, *loff = nullptr, *moff = nullptr;
     uint32_t *s32 = nullptr, *dhp = nullptr, *dmem = nullptr;
     if ((r = alloc((void**)&s64, (size_t)chunk * sct_words64(D, W) * 8)) ||
@@ -325,40 +478,37 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
         (r = alloc((void**)&dcounts, (size_t)chunk * 16)) || (r = alloc((void**)&loff, (size_t)chunk * 8)) ||
         (r = alloc((void**)&moff, (size_t)chunk * 8)))
       return r;
-    auto launch = [&](uint32_t v0, uint32_t c, int write, uint32_t* hp, uint32_t* mem) {
-      const uint32_t blocks = (c + 63) / 64;
+    auto launch = [&](uint64_t v0, uint32_t c, int write, uint32_t* hp, uint32_t* mem) {
       switch (W) {
-        case 1: launch_sct<1>(blocks, st, orp, ocol, perm, k, D, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
-        case 2: launch_sct<2>(blocks, st, orp, ocol, perm, k, D, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
-        case 3: launch_sct<3>(blocks, st, orp, ocol, perm, k, D, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
-        default: launch_sct<4>(blocks, st, orp, ocol, perm, k, D, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
+        case 1: launch_task<1>(st, orp, ocol, perm, k, D, abits, aoff, qv, tasks, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
+        case 2: launch_task<2>(st, orp, ocol, perm, k, D, abits, aoff, qv, tasks, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
+        case 3: launch_task<3>(st, orp, ocol, perm, k, D, abits, aoff, qv, tasks, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
+        default: launch_task<4>(st, orp, ocol, perm, k, D, abits, aoff, qv, tasks, v0, c, s64, s32, write, dcounts, loff, moff, hp, mem, derr); break;
       }
       return hipGetLastError();
     };
-    // pass 1: leaves and members per start node
-    std::vector<uint64_t> counts(2 * (size_t)active);
-    for (uint32_t v0 = 0; v0 < active; v0 += chunk) {
-      const uint32_t c = std::min(chunk, active - v0);
+    // pass 1: leaves and members per task
+    std::vector<uint64_t> counts(2 * (size_t)ntask);
+    for (uint64_t v0 = 0; v0 < ntask; v0 += chunk) {
+      const uint32_t c = (uint32_t)std::min<uint64_t>(chunk, ntask - v0);
       SCT_TRY(launch(v0, c, 0, nullptr, nullptr), "tree count launch");
       SCT_TRY(hipMemcpyAsync(counts.data() + 2 * (size_t)v0, dcounts, (size_t)c * 16, hipMemcpyDeviceToHost, st),
               "read counts");
     }
-    int herr = 0;
     SCT_TRY(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, st), "read flag");
     SCT_TRY(hipStreamSynchronize(st), "stream synchronize");
-    if (herr & 1) return kdss::fail(KDSS_EUNSUPPORTED, "internal: an out-list above the degeneracy");
     if (herr & 2) return kdss::fail(KDSS_EUNSUPPORTED, "internal: the tree recursion went deeper than its stack");
-    std::vector<uint64_t> lo((size_t)active + 1, 0), mo((size_t)active + 1, 0);
-    for (uint32_t v = 0; v < active; ++v) {
-      lo[v + 1] = lo[v] + counts[2 * (size_t)v];
-      mo[v + 1] = mo[v] + counts[2 * (size_t)v + 1];
+    std::vector<uint64_t> lo((size_t)ntask + 1, 0), mo((size_t)ntask + 1, 0);
+    for (uint64_t x = 0; x < ntask; ++x) {
+      lo[x + 1] = lo[x] + counts[2 * x];
+      mo[x + 1] = mo[x] + counts[2 * x + 1];
     }
-    const uint64_t L = lo[active], M = mo[active];
+    const uint64_t L = lo[ntask], M = mo[ntask];
     if (L >= (1ull << 40)) return kdss::fail(KDSS_ERANGE, "more than 2^40 leaves");
     if ((r = alloc((void**)&dhp, L * 4)) || (r = alloc((void**)&dmem, M * 4))) return r;
-    // pass 2: the leaves at their offsets (offsets of the chunk's start nodes)
-    for (uint32_t v0 = 0; v0 < active; v0 += chunk) {
-      const uint32_t c = std::min(chunk, active - v0);
+    // pass 2: the leaves at their offsets (offsets of the chunk's tasks)
+    for (uint64_t v0 = 0; v0 < ntask; v0 += chunk) {
+      const uint32_t c = (uint32_t)std::min<uint64_t>(chunk, ntask - v0);
       SCT_TRY(hipMemcpyAsync(loff, lo.data() + v0, (size_t)c * 8, hipMemcpyHostToDevice, st), "upload offsets");
       SCT_TRY(hipMemcpyAsync(moff, mo.data() + v0, (size_t)c * 8, hipMemcpyHostToDevice, st), "upload offsets");
       SCT_TRY(launch(v0, c, 1, dhp, dmem), "tree write launch");

@@ -54,6 +54,34 @@ def test_validate_codes():
     assert e.value.status == kdss.EGRAPH
 
 
+def test_validate_large_graph_reports_the_first_fault():
+    """Rows are checked on several host threads; the fault reported is the one
+    a row-by-row pass meets first."""
+    g = synth.chung_lu(50_000, 300_000, 2.4, seed=3)
+    assert kdss.validate(g) == kdss.OK
+    rp = g.row_ptr
+    # drop the symmetric copy of one edge late in the graph: row u keeps v,
+    # row v's entry for u becomes a duplicate of its neighbour (breaking order)
+    u = 45_000
+    while rp[u + 1] == rp[u]:
+        u += 1
+    v = int(g.col[rp[u]])
+    col = g.col.copy()
+    pos = int(rp[v]) + int(np.searchsorted(g.col[rp[v]:rp[v + 1]], u))
+    col[pos] = g.n - 1 if u != g.n - 1 else 0
+    bad = synth.Graph(n=g.n, row_ptr=rp, col=col)
+    assert kdss.validate(bad) == kdss.EGRAPH
+    # a self-loop in an early row as well: that one is reported
+    w = 10
+    while rp[w + 1] == rp[w]:
+        w += 1
+    col2 = col.copy()
+    col2[rp[w]] = w
+    with pytest.raises(kdss.KdssError) as e:
+        kdss.Tree(synth.Graph(n=g.n, row_ptr=rp, col=col2), 3)
+    assert e.value.status == kdss.EGRAPH and f"node {w}" in str(e.value)
+
+
 def test_tree_argument_errors():
     g = synth.complete_graph(6)
     for k, code in [(1, kdss.EINVAL), (0, kdss.EINVAL), (32, kdss.ERANGE)]:
