@@ -118,3 +118,28 @@ def test_gpu_tree_dense_graphs(K, oracle_mod, n, p, k):
     assert np.array_equal(r.cpu().numpy().view(np.uint64)[: g.n], ref["r"])
     assert (res.size, res.dens_num.value, res.ub_num.value) == (ref["size"], ref["dens_num"], ref["ub_num"])
     t.close()
+
+
+@pytest.mark.parametrize("case", ["empty", "no_edges", "star_k2", "k_above_clique_number", "triangle_k3"])
+def test_gpu_tree_edge_cases(K, oracle_mod, case):
+    """Degenerate inputs: no nodes, no edges, stars (k = 2: every edge is a
+    leaf), k above the clique number (no leaves), one triangle."""
+    if case == "empty":
+        g, k = synth.from_edge_list(0, []), 3
+    elif case == "no_edges":
+        g, k = synth.from_edge_list(50, []), 2
+    elif case == "star_k2":
+        g, k = synth.from_edge_list(40, [(0, i) for i in range(1, 40)]), 2
+    elif case == "k_above_clique_number":
+        g, k = synth.complete_graph(7), 8
+    else:
+        g, k = synth.from_edge_list(3, [(0, 1), (1, 2), (0, 2)]), 3
+    print(f"edge case {case}: n={g.n} k={k}", flush=True)
+    t = K.GpuTree(g, k)
+    st = t.stats()
+    want = oracle_mod.count(g.n, g.row_ptr, g.col, k) if g.n else 0
+    assert st.c_k.value == want
+    got = sorted(expand(t, k)) if st.leaves else []
+    want_list = sorted(tuple(c) for c in oracle_mod.list_cliques(g.n, g.row_ptr, g.col, k).tolist()) if want else []
+    assert got == want_list
+    t.close()
