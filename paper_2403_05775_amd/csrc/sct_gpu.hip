@@ -1,6 +1,10 @@
 // The k-pruned succinct clique tree (paper: Sec. 2, Lemmas 3-5) built on the
-// GPU.  The graph is first oriented along the degeneracy order: out(v) holds
-// v's later neighbours, ascending by id, at most D (the degeneracy) of them.
+// GPU.  The order comes from a level-synchronous peeling on the device: at
+// level L, every node left with at most L remaining neighbours leaves in the
+// same sub-round (ranks in id order within it, core number L), and L grows
+// when none is left; a node then has at most L <= D (the degeneracy) later
+// neighbours.  The graph is oriented along that order: out(v) holds v's later
+// neighbours, ascending by id.
 // The tree of a start node v is the pivoting recursion over out(v) (local
 // indices, adjacency bitsets):
 //   node (H, P, S): h = |H| = k: the leaf (H, {}); h + p + |S| < k: nothing;
@@ -56,6 +60,82 @@ int sct_hip_fail(hipError_t e, const char* what) {
     hipError_t e_ = (call);                              \
     if (e_ != hipSuccess) return sct_hip_fail(e_, what); \
   } while (0)
+
+constexpr uint32_t kPeelTile = 1024;   // nodes per peeling workgroup (256 threads x 4)
+
+__global__ __launch_bounds__(256) void peel_init_kernel(const uint64_t* __restrict__ rp, uint32_t n,
+                                                        uint32_t* __restrict__ deg, uint32_t* __restrict__ rank) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  deg[v] = (uint32_t)(rp[v + 1] - rp[v]);
+  rank[v] = ~0u;   // still in the graph
+}
+
+// The nodes of tile b (ids b * kPeelTile ..) still in the graph with at most L
+// remaining neighbours: tcnt[b] = how many.
+__global__ __launch_bounds__(256) void peel_count_kernel(const uint32_t* __restrict__ deg,
+                                                         const uint32_t* __restrict__ rank, uint32_t n, uint32_t L,
+                                                         uint32_t* __restrict__ tcnt) {
+  __shared__ uint32_t tot;
+  if (threadIdx.x == 0) tot = 0;
+  __syncthreads();
+  const uint32_t v0 = blockIdx.x * kPeelTile + threadIdx.x * 4;
+  uint32_t c = 0;
+  for (uint32_t i = 0; i < 4; ++i) {
+    const uint32_t v = v0 + i;
+    if (v < n && rank[v] == ~0u && deg[v] <= L) ++c;
+  }
+  if (c) atomicAdd(&tot, c);
+  __syncthreads();
+  if (threadIdx.x == 0) tcnt[blockIdx.x] = tot;
+}
+
+// The same nodes leave: rank = toff[b] + their position among the tile's, in
+// id order; core number L.
+__global__ __launch_bounds__(256) void peel_assign_kernel(const uint32_t* __restrict__ deg,
+                                                          uint32_t* __restrict__ rank, uint32_t* __restrict__ core,
+                                                          uint32_t n, uint32_t L, const uint32_t* __restrict__ toff) {
+  __shared__ uint32_t sc[256];
+  const uint32_t t = threadIdx.x;
+  const uint32_t v0 = blockIdx.x * kPeelTile + t * 4;
+  bool f[4];
+  uint32_t c = 0;
+  for (uint32_t i = 0; i < 4; ++i) {
+    const uint32_t v = v0 + i;
+    f[i] = v < n && rank[v] == ~0u && deg[v] <= L;
+    c += f[i] ? 1u : 0u;
+  }
+  sc[t] = c;
+  __syncthreads();
+  for (uint32_t off = 1; off < 256; off <<= 1) {   // inclusive scan of the counts
+    const uint32_t x = t >= off ? sc[t - off] : 0u;
+    __syncthreads();
+    sc[t] += x;
+    __syncthreads();
+  }
+  uint32_t pos = toff[blockIdx.x] + sc[t] - c;
+  for (uint32_t i = 0; i < 4; ++i)
+    if (f[i]) {
+      rank[v0 + i] = pos++;
+      core[v0 + i] = L;
+    }
+}
+
+// The sub-round's nodes (ranks lo .. hi - 1) are gone: each neighbour still in
+// the graph loses one remaining neighbour.
+__global__ __launch_bounds__(256) void peel_drop_kernel(const uint64_t* __restrict__ rp,
+                                                        const uint32_t* __restrict__ col,
+                                                        const uint32_t* __restrict__ rank, uint32_t n, uint32_t lo,
+                                                        uint32_t hi, uint32_t* __restrict__ deg) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t r = rank[v];
+  if (r < lo || r >= hi) return;
+  for (uint64_t e = rp[v]; e < rp[v + 1]; ++e) {
+    const uint32_t u = col[e];
+    if (rank[u] == ~0u) atomicSub(&deg[u], 1u);
+  }
+}
 
 // out-degree of every node along the order (rank): ocnt[v] = |out(v)|.
 __global__ __launch_bounds__(256) void orient_count_kernel(const uint64_t* __restrict__ rp,
@@ -370,13 +450,7 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
   const uint32_t n = g->n;
   T.n = n;
   T.k = k;
-  kdss::degeneracy_order(g, &T.deg);
-  const uint32_t D = T.deg.degeneracy;
-  if (D > kSctMaxLocal) {
-    delete s;
-    return kdss::fail(KDSS_EUNSUPPORTED, "the GPU tree build handles degeneracy up to 256");
-  }
-  const uint32_t W = std::max<uint32_t>(1, (D + 63) / 64);
+  uint32_t D = 0, W = 1;   // the degeneracy and the bitset words, known after the peeling
   std::vector<void*> bufs;
   auto cleanup = [&]() {
     for (void* p : bufs) (void)hipFree(p);
@@ -398,8 +472,59 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
       return r;
     SCT_TRY(hipMemcpyAsync(rp, g->row_ptr, ((size_t)n + 1) * 8, hipMemcpyHostToDevice, st), "upload graph");
     if (g->nnz) SCT_TRY(hipMemcpyAsync(col, g->col, g->nnz * 4, hipMemcpyHostToDevice, st), "upload graph");
-    SCT_TRY(hipMemcpyAsync(rank, T.deg.rank.data(), (size_t)n * 4, hipMemcpyHostToDevice, st), "upload order");
     SCT_TRY(hipMemsetAsync(derr, 0, sizeof(int), st), "clear flag");
+    // the order: level-synchronous peeling (one synchronisation per sub-round)
+    {
+      uint32_t *pdeg = nullptr, *pcore = nullptr, *ptc = nullptr, *pto = nullptr;
+      const uint32_t ntile = (n + kPeelTile - 1) / kPeelTile;
+      if ((r = alloc((void**)&pdeg, (size_t)n * 4)) || (r = alloc((void**)&pcore, (size_t)n * 4)) ||
+          (r = alloc((void**)&ptc, (size_t)ntile * 4)) || (r = alloc((void**)&pto, (size_t)ntile * 4)))
+        return r;
+      if (n) {
+        peel_init_kernel<<<(n + 255) / 256, 256, 0, st>>>(rp, n, pdeg, rank);
+        SCT_TRY(hipGetLastError(), "peeling launch");
+      }
+      std::vector<uint32_t> tc(ntile), to(ntile);
+      uint32_t L = 0, done = 0;
+      while (done < n) {
+        peel_count_kernel<<<ntile, 256, 0, st>>>(pdeg, rank, n, L, ptc);
+        SCT_TRY(hipGetLastError(), "peeling launch");
+        SCT_TRY(hipMemcpyAsync(tc.data(), ptc, (size_t)ntile * 4, hipMemcpyDeviceToHost, st), "read peeling counts");
+        SCT_TRY(hipStreamSynchronize(st), "stream synchronize");
+        uint64_t tot = 0;
+        for (uint32_t b = 0; b < ntile; ++b) {
+          to[b] = done + (uint32_t)tot;
+          tot += tc[b];
+        }
+        if (tot == 0) {   // nobody left with at most L remaining neighbours
+          ++L;
+          continue;
+        }
+        if (tot > n - done) return kdss::fail(KDSS_EUNSUPPORTED, "internal: the peeling removed a node twice");
+        SCT_TRY(hipMemcpyAsync(pto, to.data(), (size_t)ntile * 4, hipMemcpyHostToDevice, st), "upload ranks");
+        peel_assign_kernel<<<ntile, 256, 0, st>>>(pdeg, rank, pcore, n, L, pto);
+        SCT_TRY(hipGetLastError(), "peeling launch");
+        peel_drop_kernel<<<(n + 255) / 256, 256, 0, st>>>(rp, col, rank, n, done, done + (uint32_t)tot, pdeg);
+        SCT_TRY(hipGetLastError(), "peeling launch");
+        done += (uint32_t)tot;
+        D = std::max(D, L);
+      }
+      T.deg.rank.resize(n);
+      T.deg.core.resize(n);
+      T.deg.order.resize(n);
+      if (n) {
+        SCT_TRY(hipMemcpyAsync(T.deg.rank.data(), rank, (size_t)n * 4, hipMemcpyDeviceToHost, st), "read order");
+        SCT_TRY(hipMemcpyAsync(T.deg.core.data(), pcore, (size_t)n * 4, hipMemcpyDeviceToHost, st), "read cores");
+        SCT_TRY(hipStreamSynchronize(st), "stream synchronize");
+      }
+      for (uint32_t v = 0; v < n; ++v) {
+        if (T.deg.rank[v] >= n) return kdss::fail(KDSS_EUNSUPPORTED, "internal: a node left without a rank");
+        T.deg.order[T.deg.rank[v]] = v;
+      }
+      T.deg.degeneracy = D;
+    }
+    if (D > kSctMaxLocal) return kdss::fail(KDSS_EUNSUPPORTED, "the GPU tree build handles degeneracy up to 256");
+    W = std::max<uint32_t>(1, (D + 63) / 64);
     // orientation along the order: out-degrees, offsets on the host, lists
     std::vector<uint32_t> oc(n);
     if (n) {

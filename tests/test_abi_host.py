@@ -251,10 +251,16 @@ def test_sample_build_arguments_and_empty_sample():
     assert e.value.status == kdss.EUNSUPPORTED
 
 
-def test_gpu_tree_build_rejects_large_degeneracy_before_device_work():
+def test_gpu_tree_build_rejects_bad_arguments_before_device_work():
+    g = synth.complete_graph(6)
+    for k, code in [(1, kdss.EINVAL), (32, kdss.ERANGE)]:
+        with pytest.raises(kdss.KdssError) as e:
+            kdss.GpuTree(g, k)
+        assert e.value.status == code
+    bad = synth.Graph(n=4, row_ptr=np.array([0, 0, 2, 4, 5], np.uint64), col=np.array([0, 2, 1, 3, 2], np.uint32))
     with pytest.raises(kdss.KdssError) as e:
-        kdss.GpuTree(synth.complete_graph(300), 3)   # degeneracy 299 > 256
-    assert e.value.status == kdss.EUNSUPPORTED
+        kdss.GpuTree(bad, 3)
+    assert e.value.status == kdss.EGRAPH
 
 
 def test_run_rejects_bad_arguments_before_device_work():

@@ -143,3 +143,26 @@ def test_gpu_tree_edge_cases(K, oracle_mod, case):
     want_list = sorted(tuple(c) for c in oracle_mod.list_cliques(g.n, g.row_ptr, g.col, k).tolist()) if want else []
     assert got == want_list
     t.close()
+
+
+def test_gpu_tree_rejects_degeneracy_above_256(K):
+    with pytest.raises(K.KdssError) as e:
+        K.GpuTree(synth.complete_graph(300), 3)   # degeneracy 299
+    assert e.value.status == K.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gpu_tree_core_numbers(K, seed):
+    """The device peeling gives every node its core number (unique, so equal to
+    the host peeling's) and an order with at most the degeneracy later
+    neighbours per node."""
+    rs = synth.Stream(seed, 88)
+    n = int(rs.integers(500, 20000)[0])
+    g = synth.chung_lu(n, int(rs.integers(2 * n, 10 * n)[0]), 2.2 + 0.5 * float(rs.uniform(1)[0]), seed=seed,
+                       planted=int(rs.integers(0, 30)[0]))
+    host, gpu = K.Tree(g, 3), K.GpuTree(g, 3)
+    assert np.array_equal(gpu.core_numbers(), host.core_numbers())
+    assert gpu.stats().degeneracy == host.stats().degeneracy
+    assert gpu.stats().c_k.value == host.stats().c_k.value
+    host.close()
+    gpu.close()
