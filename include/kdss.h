@@ -185,20 +185,23 @@ int kdss_csr_validate(const kdss_csr *g);
  * KDSS_EOVERFLOW (|C_k| >= 2^128), KDSS_ENOMEM. */
 int kdss_sct_build(const kdss_csr *g, uint32_t k, uint32_t threads, kdss_sct **out);
 
-/* The same tree built on the current device on `stream`: the graph check and
- * the degeneracy order on the host; on the device the graph oriented along it
- * (each node keeps its later neighbours), then, per start node, the local
- * adjacency bitsets of its later neighbours (built once, kept in a device
- * store), the root pivot and the root's children; one thread per root child
- * runs the pivoting recursion below it with an explicit stack, heaviest start
- * nodes first; a counting pass and a writing pass over chunks of children
- * (scratch up to 8 GiB per chunk).  The leaves may differ from
- * kdss_sct_build's (another valid tree: every k-clique in exactly one kept
- * leaf), so every result computed on it is the same.  Device memory is
- * allocated and freed inside the call, which synchronises the stream;
- * build_seconds covers the whole call.
- * Errors: as kdss_sct_build, plus KDSS_EUNSUPPORTED (degeneracy above 256) and
- * KDSS_EHIP. */
+/* The same tree built on the current device on `stream`: the graph check on
+ * the host; on the device a degeneracy order by level-synchronous peeling
+ * (every node left with at most L remaining neighbours leaves in one
+ * sub-round, ranked by id within it, and L grows when none is left; the
+ * tree's core numbers are the levels), the graph oriented along it (each node
+ * keeps its later neighbours), then, per start node, the local adjacency
+ * bitsets of its later neighbours (built once, kept in a device store), the
+ * root pivot and the root's children; one thread per root child runs the
+ * pivoting recursion below it with an explicit stack, heaviest start nodes
+ * first; a counting pass and a writing pass over chunks of children (scratch
+ * up to 8 GiB per chunk).  The leaves may differ from kdss_sct_build's
+ * (another valid tree: every k-clique in exactly one kept leaf), so every
+ * result computed on it is the same.  Device memory is allocated and freed
+ * inside the call, which synchronises the stream (once per peeling sub-round
+ * too); build_seconds covers the whole call.
+ * Errors: as kdss_sct_build, plus KDSS_EUNSUPPORTED (degeneracy above 256,
+ * found by the peeling) and KDSS_EHIP. */
 int kdss_sct_build_gpu(const kdss_csr *g, uint32_t k, void *stream, kdss_sct **out);
 
 int kdss_sct_info(const kdss_sct *s, kdss_tree_stats *out);
