@@ -91,10 +91,11 @@ __global__ __launch_bounds__(256) void peel_count_kernel(const uint32_t* __restr
 }
 
 // The same nodes leave: rank = toff[b] + their position among the tile's, in
-// id order; core number L.
+// id order (order[rank] = the node); core number L.
 __global__ __launch_bounds__(256) void peel_assign_kernel(const uint32_t* __restrict__ deg,
                                                           uint32_t* __restrict__ rank, uint32_t* __restrict__ core,
-                                                          uint32_t n, uint32_t L, const uint32_t* __restrict__ toff) {
+                                                          uint32_t* __restrict__ order, uint32_t n, uint32_t L,
+                                                          const uint32_t* __restrict__ toff) {
   __shared__ uint32_t sc[256];
   const uint32_t t = threadIdx.x;
   const uint32_t v0 = blockIdx.x * kPeelTile + t * 4;
@@ -116,22 +117,24 @@ __global__ __launch_bounds__(256) void peel_assign_kernel(const uint32_t* __rest
   uint32_t pos = toff[blockIdx.x] + sc[t] - c;
   for (uint32_t i = 0; i < 4; ++i)
     if (f[i]) {
+      order[pos] = v0 + i;
       rank[v0 + i] = pos++;
       core[v0 + i] = L;
     }
 }
 
-// The sub-round's nodes (ranks lo .. hi - 1) are gone: each neighbour still in
-// the graph loses one remaining neighbour.
+// The sub-round's nodes (order[lo .. lo + cnt - 1]) are gone: each neighbour
+// still in the graph loses one remaining neighbour.  One wavefront per
+// removed node, its lanes over the node's row.
 __global__ __launch_bounds__(256) void peel_drop_kernel(const uint64_t* __restrict__ rp,
                                                         const uint32_t* __restrict__ col,
-                                                        const uint32_t* __restrict__ rank, uint32_t n, uint32_t lo,
-                                                        uint32_t hi, uint32_t* __restrict__ deg) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const uint32_t r = rank[v];
-  if (r < lo || r >= hi) return;
-  for (uint64_t e = rp[v]; e < rp[v + 1]; ++e) {
+                                                        const uint32_t* __restrict__ rank,
+                                                        const uint32_t* __restrict__ order, uint32_t lo, uint32_t cnt,
+                                                        uint32_t* __restrict__ deg) {
+  const uint32_t i = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (i >= cnt) return;
+  const uint32_t v = order[lo + i];
+  for (uint64_t e = rp[v] + (threadIdx.x & 63u); e < rp[v + 1]; e += 64) {
     const uint32_t u = col[e];
     if (rank[u] == ~0u) atomicSub(&deg[u], 1u);
   }
@@ -475,10 +478,11 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
     SCT_TRY(hipMemsetAsync(derr, 0, sizeof(int), st), "clear flag");
     // the order: level-synchronous peeling (one synchronisation per sub-round)
     {
-      uint32_t *pdeg = nullptr, *pcore = nullptr, *ptc = nullptr, *pto = nullptr;
+      uint32_t *pdeg = nullptr, *pcore = nullptr, *pord = nullptr, *ptc = nullptr, *pto = nullptr;
       const uint32_t ntile = (n + kPeelTile - 1) / kPeelTile;
       if ((r = alloc((void**)&pdeg, (size_t)n * 4)) || (r = alloc((void**)&pcore, (size_t)n * 4)) ||
-          (r = alloc((void**)&ptc, (size_t)ntile * 4)) || (r = alloc((void**)&pto, (size_t)ntile * 4)))
+          (r = alloc((void**)&pord, (size_t)n * 4)) || (r = alloc((void**)&ptc, (size_t)ntile * 4)) ||
+          (r = alloc((void**)&pto, (size_t)ntile * 4)))
         return r;
       if (n) {
         peel_init_kernel<<<(n + 255) / 256, 256, 0, st>>>(rp, n, pdeg, rank);
@@ -502,9 +506,9 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
         }
         if (tot > n - done) return kdss::fail(KDSS_EUNSUPPORTED, "internal: the peeling removed a node twice");
         SCT_TRY(hipMemcpyAsync(pto, to.data(), (size_t)ntile * 4, hipMemcpyHostToDevice, st), "upload ranks");
-        peel_assign_kernel<<<ntile, 256, 0, st>>>(pdeg, rank, pcore, n, L, pto);
+        peel_assign_kernel<<<ntile, 256, 0, st>>>(pdeg, rank, pcore, pord, n, L, pto);
         SCT_TRY(hipGetLastError(), "peeling launch");
-        peel_drop_kernel<<<(n + 255) / 256, 256, 0, st>>>(rp, col, rank, n, done, done + (uint32_t)tot, pdeg);
+        peel_drop_kernel<<<(uint32_t)((tot + 3) / 4), 256, 0, st>>>(rp, col, rank, pord, done, (uint32_t)tot, pdeg);
         SCT_TRY(hipGetLastError(), "peeling launch");
         done += (uint32_t)tot;
         D = std::max(D, L);
