@@ -80,3 +80,29 @@ def test_sample_chung_lu_1m(K, oracle_mod):
     """The benchmarked graph (n = 1,000,000, m = 10,000,000, k = 5), 200,000 samples."""
     g = synth.chung_lu(1_000_000, 10_000_000, 2.5, seed=0, planted=40, planted_p=0.9)
     check(K, oracle_mod, g, 5, 200_000, 16, 1, "chung-lu 1M")
+
+
+@pytest.mark.parametrize("case", ["k2_edges", "too_few_colours", "path_graph_k3", "k_above_clique_number"])
+def test_sample_edge_cases(K, oracle_mod, case):
+    """k = 2 (every sampled 2-path is an edge), no colour-increasing k-paths at
+    all (fewer colours than k: the sampler has nothing to draw from), and
+    paths that are never cliques."""
+    if case == "k2_edges":
+        g, k = synth.chung_lu(400, 2000, 2.3, seed=5), 2
+    elif case == "too_few_colours":
+        g, k = synth.complete_graph(3), 5
+    elif case == "path_graph_k3":
+        g, k = synth.from_edge_list(6, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5)]), 3
+    else:
+        g, k = synth.erdos_renyi(300, 0.02, seed=4), 6
+    check(K, oracle_mod, g, k, 3000, 9, 41, case)
+
+
+def test_sample_no_draws(K):
+    """t = 0: an empty sample set; the run over it finds nothing."""
+    g = synth.complete_graph(6)
+    tree = K.SampleTree(g, 3, synth.sample_draws(1, 0, 3))
+    assert tree.stats().leaves == 0 and tree.stats().c_k.value == 0 and tree.info.samples == 0
+    r, order, res = run(K, tree, 4)
+    assert res.size == 0 and res.dens_num.value == 0 and not np.any(r)
+    tree.close()
