@@ -119,3 +119,22 @@ def test_pb_chung_lu_1m_sampled(K, oracle_mod):
     assert np.array_equal(got, want)
     assert int(got.astype(object).sum()) == 8 * tree.stats().c_k.value
     tree.close()
+
+
+@pytest.mark.parametrize("case", ["no_cliques", "k2_one_iteration", "complete_k4_ties", "star_k2_r0"])
+def test_pb_edge_cases(K, oracle_mod, case):
+    """No k-cliques, k = 2 with a single iteration, a complete graph (every
+    load tied: the remainder rule decides), a star with start loads."""
+    r0 = None
+    if case == "no_cliques":
+        g, k, T = synth.erdos_renyi(200, 0.02, seed=4), 6, 5
+    elif case == "k2_one_iteration":
+        g, k, T = synth.chung_lu(500, 3000, 2.3, seed=6), 2, 1
+    elif case == "complete_k4_ties":
+        g, k, T = synth.complete_graph(12), 4, 7
+    else:
+        g, k, T = synth.from_edge_list(30, [(0, i) for i in range(1, 30)]), 2, 6
+        r0 = (synth.Stream(7, 89).u64(g.n) % np.uint64(5)).astype(np.uint64)
+    sol = check(K, oracle_mod, g, k, T, r0=r0, label=case)
+    if case == "no_cliques":
+        assert sol.c_k == 0 and sol.size == 0
