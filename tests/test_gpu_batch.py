@@ -94,3 +94,15 @@ def test_batch_equals_solo_after_autotune(K):
         sol = K.solve(g, k, 20)
         same(got, dict(r=sol.r, order=sol.order, size=sol.size, dens_num=sol.dens_num, ub_num=sol.ub_num,
                        c_k=sol.c_k))
+
+
+def test_batch_with_degenerate_members(K, oracle_mod):
+    """Members with no edges, a single node, k above the clique number and a
+    complete graph, between ordinary ones: each equals its own oracle run."""
+    probs = [(synth.from_edge_list(20, []), 3), (synth.chung_lu(300, 1500, 2.3, seed=71, planted=12), 4),
+             (synth.from_edge_list(1, []), 2), (synth.complete_graph(7), 8), (synth.complete_graph(15), 5),
+             (synth.chung_lu(500, 2500, 2.4, seed=72), 3)]
+    print("batch with degenerate members, T=6", flush=True)
+    out = run_batch(K, probs, 6)
+    for (g, k), got in zip(probs, out):
+        same(got, oracle_mod.solve(g.n, g.row_ptr, g.col, k, 6))
