@@ -364,9 +364,10 @@ static int for_each_clique(run_t *R, clique_fn fn, void **ctxs) {
     return err;
 }
 
-/* Extraction on loads r: writes order[n], returns (i*, K_{i*}). */
+/* Extraction on loads r: writes order[n], returns (i*, K_{i*}); K_out
+ * (nullable) receives every prefix count, K_out[i - 1] = K_i. */
 static int extract(run_t *R, const u128 *r, uint32_t *order, uint32_t *size, uint64_t *dens_num,
-                   uint64_t **hist_t, uint32_t *pos) {
+                   uint64_t **hist_t, uint32_t *pos, uint64_t *K_out) {
     uint32_t n = R->g->n;
     for (uint32_t i = 0; i < n; ++i) order[i] = i;
     g_sort_r = r;
@@ -389,6 +390,7 @@ static int extract(run_t *R, const u128 *r, uint32_t *order, uint32_t *size, uin
     uint32_t best_i = 0;
     for (uint32_t i = 1; i <= n; ++i) {
         for (int t = 0; t < R->nthreads; ++t) K += hist_t[t][i - 1];
+        if (K_out) K_out[i - 1] = K;
         if (K == 0) continue;
         if (best_i == 0 || (u128)K * best_i >= (u128)bestK * i) { bestK = K; best_i = i; }
     }
@@ -478,7 +480,7 @@ int kor_solve(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k, u
             double te = now_s();
             kor_trace_row *row = &trace[it - 1];
             row->t = it;
-            err = extract(&R, r, order_out, &row->size, &row->dens_num, delta_t, pos);
+            err = extract(&R, r, order_out, &row->size, &row->dens_num, delta_t, pos, NULL);
             if (err) goto done;
             u128 ub = upper_bound_num(r, r0, n);
             row->ub_num_lo = (uint64_t)ub;
@@ -497,7 +499,7 @@ int kor_solve(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k, u
         res->size = 0;
         res->dens_num = 0;
     } else {
-        err = extract(&R, r, order_out, &res->size, &res->dens_num, delta_t, pos);
+        err = extract(&R, r, order_out, &res->size, &res->dens_num, delta_t, pos, NULL);
         if (err) goto done;
     }
     u128 ub = upper_bound_num(r, r0, n);
@@ -539,9 +541,11 @@ int kor_credits(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k,
 
 int kor_threads(int threads) { return set_threads(threads); }
 
-/* Extraction alone on given loads r (u64): the order pi, i* and K_{i*}. */
-int kor_extract(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k, const uint64_t *r,
-                int threads, uint32_t *order_out, uint32_t *size_out, uint64_t *dens_out) {
+/* Extraction alone on given loads r (u64): the order pi, i* and K_{i*};
+ * K_out (nullable, n entries) receives K_i = |C_k(pi[0 .. i))| for i = 1..n. */
+int kor_prefix_counts(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k, const uint64_t *r,
+                      int threads, uint32_t *order_out, uint32_t *size_out, uint64_t *dens_out,
+                      uint64_t *K_out) {
     if (k < 2 || !row_ptr || !r || !order_out || !size_out || !dens_out) return KOR_EINVAL;
     graph_t g = {n, row_ptr, col};
     run_t R = {&g, k, 0, NULL, 0, max_degree(&g), set_threads(threads)};
@@ -557,12 +561,17 @@ int kor_extract(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k,
     }
     if (!err) {
         for (uint32_t u = 0; u < n; ++u) rr[u] = r[u];
-        err = extract(&R, rr, order_out, size_out, dens_out, hist_t, pos);
+        err = extract(&R, rr, order_out, size_out, dens_out, hist_t, pos, K_out);
     }
     for (int t = 0; t < made; ++t) free(hist_t[t]);
     free(rr);
     free(pos);
     return err;
+}
+
+int kor_extract(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int k, const uint64_t *r,
+                int threads, uint32_t *order_out, uint32_t *size_out, uint64_t *dens_out) {
+    return kor_prefix_counts(n, row_ptr, col, k, r, threads, order_out, size_out, dens_out, NULL);
 }
 
 /*
@@ -621,7 +630,6 @@ static int cmp_u32(const void *a, const void *b) {
 static int pb_pair(const uint32_t *mem, uint32_t h, uint32_t p, int k, const u128 *r, u128 *add) {
     if ((int)h > k || (uint32_t)(k - (int)h) > p) return KOR_OK;   /* the pair holds no k-clique */
     uint32_t j = (uint32_t)k - h, sz = h + p;
-    if (j == 0 && p > 0) return KOR_EINVAL;   /* k-pruned trees emit (H, {}) once |H| = k */
     u128 nC = binom_u128(p, j);
     pb_node *V = (pb_node *)malloc(sizeof(pb_node) * (size_t)sz);
     uint32_t *plat = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(sz + 1));
@@ -630,8 +638,10 @@ static int pb_pair(const uint32_t *mem, uint32_t h, uint32_t p, int k, const u12
     for (uint32_t x = 0; x < sz; ++x) {
         V[x].u = mem[x];
         V[x].cur = r[mem[x]];
-        V[x].up = x < h ? binom_u128(p, j) : binom_u128(p - 1, j - 1);
-        V[x].alive = 1;
+        /* a pivot node lies in C(p - 1, j - 1) of the pair's cliques: none when
+           j = 0 (h = k, Lemma 4's pair holding H alone), so it takes nothing */
+        V[x].up = x < h ? binom_u128(p, j) : (j ? binom_u128(p - 1, j - 1) : 0);
+        V[x].alive = V[x].up > 0;
     }
     /* plateaus: V sorted by (load, id); plateau q covers V[plat[q] .. plat[q + 1]) */
     qsort(V, sz, sizeof(pb_node), cmp_pb_load_id);
@@ -875,7 +885,7 @@ int kor_solve_list(uint32_t n, const uint32_t *cliques, uint64_t nclq, int k, ui
     }
     if (!err) {
         uint64_t *hist[1] = {delta};
-        err = extract(&R, r, order_out, size_out, dens_out, hist, pos);
+        err = extract(&R, r, order_out, size_out, dens_out, hist, pos, NULL);
     }
     for (uint32_t u = 0; !err && u < n; ++u) r_out[u] = (uint64_t)r[u];
     free(r); free(delta); free(pos);

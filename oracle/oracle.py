@@ -63,6 +63,7 @@ def lib(path: str | None = None):
         L.kor_credits.argtypes = [C.c_uint32, p64, p32, C.c_int, p64, p64]
         L.kor_threads.argtypes = [C.c_int]
         L.kor_extract.argtypes = [C.c_uint32, p64, p32, C.c_int, p64, C.c_int, p32, p32, p64]
+        L.kor_prefix_counts.argtypes = [C.c_uint32, p64, p32, C.c_int, p64, C.c_int, p32, p32, p64, p64]
         L.kor_pb_pair.argtypes = [C.c_uint32, p32, C.c_uint32, C.c_uint32, C.c_int, p64, p64]
         L.kor_pb_run.argtypes = [C.c_uint32, C.c_uint64, p32, p32, p64, p32, C.c_int, C.c_uint32, C.c_int,
                                  p64, C.POINTER(C.c_double)]
@@ -173,6 +174,22 @@ def extract(n, row_ptr, col, k, r, threads=0, libpath=None) -> dict:
     if err:
         raise RuntimeError(f"kor_extract failed: {err}")
     return dict(order=order[:n], size=size.value, dens_num=int(dens[0]))
+
+
+def prefix_counts(n, row_ptr, col, k, r, threads=0, libpath=None) -> dict:
+    """The extraction at loads r (uint64) with every prefix count:
+    K[i - 1] = |C_k(order[0 .. i))| for i = 1..n."""
+    rp, cl = _csr(row_ptr, col)
+    rr = np.ascontiguousarray(r, dtype=np.uint64)
+    order = np.zeros(max(n, 1), dtype=np.uint32)
+    K = np.zeros(max(n, 1), dtype=np.uint64)
+    size = C.c_uint32(0)
+    dens = np.zeros(1, dtype=np.uint64)
+    err = lib(libpath).kor_prefix_counts(n, _p64(rp), _p32(cl), k, _p64(rr), threads, _p32(order),
+                                         C.byref(size), _p64(dens), _p64(K))
+    if err:
+        raise RuntimeError(f"kor_prefix_counts failed: {err}")
+    return dict(order=order[:n], size=size.value, dens_num=int(dens[0]), K=K[:n])
 
 
 def pb_pair(n, members, h, p, k, r, libpath=None) -> np.ndarray:

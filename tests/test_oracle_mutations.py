@@ -2,7 +2,8 @@
 
 This is evidence that the pins in test_oracle_pins.py constrain the oracle: a
 mutated oracle (tie rule, sort direction, argmax tie rule, prefix index,
-per-thread reduction) must fail at least one of them.  Mutations are made on
+per-thread reduction, credits that ignore the loads, exclusive prefix counts)
+must fail at least one of them.  Mutations are made on
 the CPU, in a temporary copy of the source.
 """
 from __future__ import annotations
@@ -25,6 +26,12 @@ MUTATIONS = {
     "prefix by first node": ("if (p->pos[c[i]] > last) last = p->pos[c[i]];", "if (p->pos[c[i]] < last) last = p->pos[c[i]];"),
     "one thread's credits": ("for (int t = 0; t < R.nthreads; ++t) r[u] += delta_t[t][u];", "r[u] += delta_t[0][u];"),
     "credit the maximum": ("if (r[c[i]] < r[best]) best = c[i];", "if (r[c[i]] > r[best]) best = c[i];"),
+    "credits ignore the loads": ("for (uint32_t u = 0; u < n; ++u) { rr[u] = r[u]; d_out[u] = 0; }",
+                                 "for (uint32_t u = 0; u < n; ++u) { rr[u] = 0; d_out[u] = 0; }"),
+    "exclusive prefix counts": ("for (int t = 0; t < R->nthreads; ++t) K += hist_t[t][i - 1];\n"
+                                "        if (K_out) K_out[i - 1] = K;",
+                                "if (K_out) K_out[i - 1] = K;\n"
+                                "        for (int t = 0; t < R->nthreads; ++t) K += hist_t[t][i - 1];"),
 }
 
 
@@ -61,6 +68,14 @@ def _pins(O, path):
     assert res4["r"].tolist() == rb
     _, i_star, K = B.best_prefix(10, cl4, rb)
     assert (res4["size"], res4["dens_num"]) == (i_star, K)
+    # one credit pass at tied, non-zero loads
+    r5 = [5, 0, 3, 1, 2, 0, 4]
+    d5 = O.credits(g.n, g.row_ptr, g.col, 3, np.array(r5, dtype=np.uint64), libpath=path)
+    assert d5.tolist() == [a - b for a, b in zip(B.frank_wolfe(g.n, cl, 1, r5), r5)]
+    # every prefix count at those loads
+    order5 = sorted(range(g.n), key=lambda v: (-r5[v], v))
+    K5 = [sum(1 for c in cl if set(c) <= set(order5[:i])) for i in range(1, g.n + 1)]
+    assert O.prefix_counts(g.n, g.row_ptr, g.col, 3, np.array(r5, dtype=np.uint64), libpath=path)["K"].tolist() == K5
 
 
 def test_unmutated_oracle_passes(oracle_mod):

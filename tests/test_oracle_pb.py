@@ -39,7 +39,7 @@ def read_steps():
 
 def caps(h, p, k):
     j = k - len(h)
-    return {**{u: math.comb(len(p), j) for u in h}, **{u: math.comb(len(p) - 1, j - 1) for u in p}}
+    return {**{u: math.comb(len(p), j) for u in h}, **{u: math.comb(len(p) - 1, j - 1) if j else 0 for u in p}}
 
 
 def unit_fill(h, p, k, r):
@@ -61,7 +61,7 @@ def unit_fill(h, p, k, r):
 def random_pair(rs, n, kmax=6):
     k = int(rs.integers(2, kmax + 1))
     h = int(rs.integers(1, k + 1))
-    p = 0 if h == k else int(rs.integers(k - h, 9))
+    p = int(rs.integers(k - h, 9))   # h = k with p > 0: the pair holds H alone (Lemma 4)
     nodes = rs.permutation(n)[: h + p].tolist()
     return nodes[:h], nodes[h:], k
 
@@ -73,6 +73,10 @@ def _pb_pins(O, path):
         d = O.pb_pair(7, h + p, len(h), len(p), 3, r, libpath=path)
         assert sorted(np.flatnonzero(d).tolist()) == gain and set(d[gain].tolist()) == {1}
         r = r + d
+    # a pair with h = k and p > 0 holds the one clique H (Lemma 4): the pivot
+    # nodes are in none of its cliques, and H's least (load, id) node takes it
+    d = O.pb_pair(5, [0, 1, 2, 3, 4], 3, 2, 3, np.array([2, 1, 1, 0, 0], dtype=np.uint64), libpath=path)
+    assert d.tolist() == [0, 1, 0, 0, 0]
     # brute force on random tiny pairs, loads with many ties
     rs = np.random.default_rng(7)
     for _ in range(300):
@@ -86,7 +90,7 @@ def _pb_pins(O, path):
     # synchronous passes do not depend on the pair order; both add T * sum C(p, k - h)
     pairs = [random_pair(rs, 30, kmax=4) for _ in range(40)]
     for kk in (3, 4):
-        ps = [(h, p) for h, p, k in pairs if len(h) <= kk <= len(h) + len(p) and (len(h) < kk or not p)]
+        ps = [(h, p) for h, p, k in pairs if len(h) <= kk <= len(h) + len(p)]
         hs = np.array([len(h) for h, _ in ps])
         pp = np.array([len(p) for _, p in ps])
         mem = np.array([u for h, p in ps for u in h + p], dtype=np.uint32)

@@ -93,6 +93,83 @@ def test_example_first_iteration_ties(oracle_mod):
     assert np.array_equal(oracle_mod.credits(g.n, g.row_ptr, g.col, 3, np.zeros(g.n)), expect)
 
 
+def _brute_credits(n, cl, r):
+    """One synchronous Frank-Wolfe step at loads r, from the brute-force
+    iteration (each clique credits its minimum (load, id) member)."""
+    return [a - b for a, b in zip(B.frank_wolfe(n, cl, 1, r), r)]
+
+
+def test_credits_at_tied_nonzero_loads_example(oracle_mod):
+    """Algorithm 1's per-clique step at given loads: on the example graph with
+    loads (5, 0, 3, 1, 2, 0, 4) -- two ties at 0 -- every triangle credits its
+    member of least load, the lower id on a tie.  The loads decide the winner
+    (a credit rule that ignored them would give the first-iteration vector)."""
+    g, _, _ = example_graph()
+    cl = B.cliques(g, 3)
+    r = [5, 0, 3, 1, 2, 0, 4]
+    expect = _brute_credits(g.n, cl, r)
+    got = oracle_mod.credits(g.n, g.row_ptr, g.col, 3, np.array(r, dtype=np.uint64))
+    assert got.tolist() == expect
+    first = [sum(1 for c in cl if min(c) == u) for u in range(g.n)]
+    assert expect != first
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_credits_at_random_tied_loads(oracle_mod, seed):
+    """Random tiny graphs, k = 2..5, loads drawn from {0..3} (many ties) and
+    shifted by a large offset on some nodes: the oracle's one-pass credits equal
+    the brute-force per-clique minimum of (load, id), and they sum to |C_k|."""
+    rs = synth.Stream(seed, 23)
+    n = int(rs.integers(6, 13)[0])
+    g = _tiny_graph(500 + seed, n, 0.6)
+    k = int(rs.integers(2, 6)[0])
+    r = (rs.u64(n) % np.uint64(4)).astype(np.uint64)
+    if seed % 3 == 2:
+        r[::3] += np.uint64(1 << 40)
+    cl = B.cliques(g, k)
+    got = oracle_mod.credits(g.n, g.row_ptr, g.col, k, r)
+    assert got.tolist() == _brute_credits(n, cl, [int(x) for x in r])
+    assert int(got.sum()) == len(cl)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_prefix_counts_brute_force(oracle_mod, seed):
+    """K_i = |C_k(V_i)| for every prefix V_i of the load order (Algorithm 2's
+    prefix scoring; Sec. 2's k-clique density numerator), against counting the
+    cliques inside each prefix of the brute-force order one by one."""
+    rs = synth.Stream(seed, 27)
+    n = int(rs.integers(6, 13)[0])
+    g = _tiny_graph(700 + seed, n, 0.6)
+    k = int(rs.integers(2, 5)[0])
+    r = (rs.u64(n) % np.uint64(5)).astype(np.uint64)
+    cl = B.cliques(g, k)
+    order = sorted(range(n), key=lambda v: (-int(r[v]), v))
+    K = [sum(1 for c in cl if set(c) <= set(order[:i])) for i in range(1, n + 1)]
+    res = oracle_mod.prefix_counts(g.n, g.row_ptr, g.col, k, r)
+    assert res["order"].tolist() == order
+    assert res["K"].tolist() == K
+    _, i_star, K_star = B.best_prefix(n, cl, [int(x) for x in r])
+    assert (res["size"], res["dens_num"]) == (i_star, K_star)
+
+
+def test_prefix_counts_closed_forms(oracle_mod):
+    """On K_n every prefix of i nodes holds C(i, k) cliques, whatever the loads;
+    on the example graph after 64 iterations the first six nodes are {u1..u6}
+    with 8 triangles (density 4/3) and all seven hold the 9 triangles of
+    Example 1."""
+    rs = synth.Stream(3, 29)
+    for n, k in ((9, 3), (11, 4), (7, 2)):
+        g = synth.complete_graph(n)
+        r = (rs.u64(n) % np.uint64(6)).astype(np.uint64)
+        assert oracle_mod.prefix_counts(g.n, g.row_ptr, g.col, k, r)["K"].tolist() == \
+            [math.comb(i, k) for i in range(1, n + 1)]
+    g, _, vals = example_graph()
+    r = solve(oracle_mod, g, 3, 64)["r"]
+    res = oracle_mod.prefix_counts(g.n, g.row_ptr, g.col, 3, r)
+    assert sorted(res["order"][:6].tolist()) == vals["densest_set"]
+    assert res["K"][5] == 8 and res["K"][6] == vals["triangles"][0]
+
+
 # ---- closed forms -----------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,k", [(6, 2), (9, 3), (10, 4), (12, 5), (7, 7)])
