@@ -262,6 +262,12 @@ int kdss_plan_create(const kdss_sct *s, uint32_t T_max, uint64_t r0_max, const k
                      kdss_plan **out);
 int kdss_plan_info(const kdss_plan *p, kdss_plan_stats *out);
 
+/* Device workspace (bytes, into *bytes) that a plan of s with these arguments
+ * needs: kdss_plan_info().workspace_bytes of that plan, without keeping it.
+ * Errors as kdss_plan_create. */
+int kdss_workspace_size(const kdss_sct *s, uint32_t T_max, uint64_t r0_max, const kdss_opts *opts,
+                        size_t *bytes);
+
 /* Kernel durations gathered by kdss_run with opts.time_kernels = 1 since the
  * plan was created or the last reset (reset != 0 clears them after copying). */
 int kdss_plan_timing(kdss_plan *p, kdss_timing *out, int reset);
@@ -280,11 +286,40 @@ int kdss_plan_upload(kdss_plan *p, void *d_ws, size_t ws_bytes, void *stream);
  * whose first h_res->size entries are the node set.  h_trace (host, nullable)
  * receives one row per extraction when opts->extract_every > 0, at most
  * trace_cap rows.  h_res (host) is filled after the stream is synchronised.
- * Errors: KDSS_EINVAL, KDSS_EWORKSPACE, KDSS_EOVERFLOW (an r0 entry exceeded
- * r0_max: results are invalid), KDSS_EHIP. */
+ * Errors: KDSS_EINVAL, KDSS_EWORKSPACE, KDSS_EOVERFLOW (an r0 entry exceeds
+ * r0_max: found when the start loads are read, before the first iteration), KDSS_EHIP. */
 int kdss_run(kdss_plan *p, void *d_ws, size_t ws_bytes, uint32_t T, const uint64_t *d_r0,
              void *d_r, uint32_t *d_order, kdss_trace_row *h_trace, uint32_t trace_cap,
              kdss_result *h_res, void *stream);
+
+/* Continues a run from a checkpoint (Algorithm 2's loop is a map r_{t-1} ->
+ * r_t, so T more iterations from r_t equal iterations t + 1 .. t + T of one
+ * run).  d_start (device u64[n]) holds the checkpoint loads r_{t_offset} of a
+ * run that began at d_r0 (device u64[n], nullable = zero); every d_start entry
+ * must be <= the plan's r0_max (create the plan with r0_max >= the largest
+ * checkpoint load).  Runs T iterations from d_start, then the extraction; the
+ * upper bound and certificate use r - r0 over t_offset + T iterations, h_res->T
+ * and trace rows count from t_offset, so the result equals that of one
+ * kdss_run of t_offset + T iterations from d_r0, bit for bit.  Outputs and the
+ * other errors as kdss_run; KDSS_ERANGE when t_offset + T >= 2^32. */
+int kdss_run_resume(kdss_plan *p, void *d_ws, size_t ws_bytes, uint32_t T, uint32_t t_offset,
+                    const uint64_t *d_start, const uint64_t *d_r0, void *d_r, uint32_t *d_order,
+                    kdss_trace_row *h_trace, uint32_t trace_cap, kdss_result *h_res, void *stream);
+
+/* One-shot (Algorithm 2 end to end): builds g's k-pruned tree on host threads,
+ * lays it out for T iterations with start loads <= r0_max, and, when the
+ * caller's buffers are large enough, uploads it into d_ws, runs kdss_run (T
+ * iterations from d_r0, nullable) and the extraction, and frees the tree and
+ * plan.  *ws_needed (host) always receives the workspace the plan needs, and
+ * h_res->width / h_res->n the load width and node count; when d_ws is NULL, or
+ * ws_bytes < *ws_needed, or r_words (u64 words at d_r) < n (2n for 128-bit
+ * loads), nothing runs and KDSS_EWORKSPACE is returned, so a caller can size
+ * its buffers with a first call.  The library allocates no device memory.
+ * Synchronises the stream.  Other errors as kdss_sct_build, kdss_plan_create
+ * and kdss_run. */
+int kdss_solve(const kdss_csr *g, uint32_t k, uint32_t T, const kdss_opts *opts, const uint64_t *d_r0,
+               uint64_t r0_max, void *d_ws, size_t ws_bytes, size_t *ws_needed, void *d_r, size_t r_words,
+               uint32_t *d_order, kdss_result *h_res, void *stream);
 
 /* One leaf-credit pass (Algorithm 1's per-clique step, batched by Lemma 5) at loads
  * d_r (device, the plan's width): d_out[u] (device u64[n], overwritten) =
@@ -298,6 +333,14 @@ int kdss_leaf_credit(kdss_plan *p, void *d_ws, size_t ws_bytes, const void *d_r,
 int kdss_extract(kdss_plan *p, void *d_ws, size_t ws_bytes, const void *d_r,
                  const uint64_t *d_r0, uint32_t T, uint32_t *d_order, kdss_result *h_res,
                  void *stream);
+
+/* kdss_extract that also writes every prefix count of Algorithm 2's scoring:
+ * d_counts[i - 1] = K_i = |C_k(order[0 .. i))| for i = 1..n (device u64[n],
+ * caller-owned; each k-clique counted once, Lemma 4), so K_i / i is the
+ * k-clique density (Sec. 2) of every prefix.  d_counts may be NULL.
+ * KDSS_EUNSUPPORTED for batch plans with d_counts. */
+int kdss_extract_counts(kdss_plan *p, void *d_ws, size_t ws_bytes, const void *d_r, const uint64_t *d_r0,
+                        uint32_t T, uint32_t *d_order, uint64_t *d_counts, kdss_result *h_res, void *stream);
 
 /* ---- launch tuning (autotuned tile schedules) ----
  * The leaf-credit and heavy-leaf kernels run persistent grids; their sizes
@@ -351,6 +394,9 @@ int kdss_batch_offsets(const kdss_plan *p, uint64_t *node_off, uint32_t count);
  * kdss_run. */
 int kdss_batch_run(kdss_plan *p, void *d_ws, size_t ws_bytes, uint32_t T, const uint64_t *d_r0, uint64_t *d_r,
                    uint32_t *d_order, kdss_result *h_res, uint32_t count, void *stream);
+
+/* Releases a batch plan (the same as kdss_plan_free; NULL is accepted). */
+void kdss_batch_free(kdss_plan *p);
 
 #ifdef __cplusplus
 }

@@ -543,6 +543,46 @@ int kdss_batch_create(const kdss_sct* const* trees, uint32_t count, uint32_t T_m
   return build_plan(v, T_max, r0_max, opts, out);
 }
 
+int kdss_workspace_size(const kdss_sct* s, uint32_t T_max, uint64_t r0_max, const kdss_opts* opts,
+                        size_t* bytes) {
+  if (!s || !bytes) return fail(KDSS_EINVAL, "null argument");
+  kdss_plan* P = nullptr;
+  int rc = build_plan({&s->s}, T_max, r0_max, opts, &P);
+  if (rc) return rc;
+  *bytes = P->ws_bytes;
+  kdss_plan_free(P);
+  return KDSS_OK;
+}
+
+int kdss_solve(const kdss_csr* g, uint32_t k, uint32_t T, const kdss_opts* opts, const uint64_t* d_r0,
+               uint64_t r0_max, void* d_ws, size_t ws_bytes, size_t* ws_needed, void* d_r, size_t r_words,
+               uint32_t* d_order, kdss_result* h_res, void* stream) {
+  if (!g || !ws_needed || !h_res) return fail(KDSS_EINVAL, "null argument");
+  std::memset(h_res, 0, sizeof(*h_res));
+  kdss_sct* tree = nullptr;
+  int rc = kdss_sct_build(g, k, 0, &tree);
+  if (rc) return rc;
+  kdss_plan* P = nullptr;
+  rc = build_plan({&tree->s}, T, r0_max, opts, &P);
+  if (!rc) {
+    *ws_needed = P->ws_bytes;
+    h_res->width = P->width;
+    h_res->n = P->n;
+    const size_t words = (size_t)P->n * (P->width == 128 ? 2 : 1);
+    if (!d_ws || ws_bytes < P->ws_bytes)
+      rc = fail(KDSS_EWORKSPACE, "workspace smaller than the plan needs (see *ws_needed)");
+    else if (r_words < words)
+      rc = fail(KDSS_EWORKSPACE, "load buffer smaller than n words (2n for 128-bit loads)");
+    else if (!d_r || !d_order)
+      rc = fail(KDSS_EINVAL, "null output");
+    if (!rc) rc = kdss_plan_upload(P, d_ws, ws_bytes, stream);
+    if (!rc) rc = kdss_run(P, d_ws, ws_bytes, T, d_r0, d_r, d_order, nullptr, 0, h_res, stream);
+  }
+  kdss_plan_free(P);
+  kdss_sct_free(tree);
+  return rc;
+}
+
 int kdss_batch_offsets(const kdss_plan* P, uint64_t* node_off, uint32_t count) {
   if (!P || !node_off) return fail(KDSS_EINVAL, "null argument");
   if (count + 1 != P->node_off.size()) return fail(KDSS_ERANGE, "count does not match the plan");

@@ -1935,8 +1935,9 @@ int launch_top_bound(const kdss_plan* P, const WsView& ws, const void* d_r, cons
 
 // Extraction at loads d_r; every load is <= bound.  The order lands in d_order
 // and the best prefix and upper bound in the device result.
+// d_counts (nullable, u64[n]) receives every prefix count K_i at index i - 1.
 int launch_extract(const kdss_plan* P, const WsView& ws, const void* d_r, const uint64_t* d_r0, u128 bound,
-                   uint32_t* d_order, hipStream_t st) {
+                   uint32_t* d_order, hipStream_t st, uint64_t* d_counts = nullptr) {
   const uint32_t n = P->n;
   const int wide = P->width == 128 ? 1 : 0;
   const uint64_t* r = static_cast<const uint64_t*>(d_r);
@@ -1971,6 +1972,7 @@ int launch_extract(const kdss_plan* P, const WsView& ws, const void* d_r, const 
   scan_exclusive_single_kernel<uint64_t><<<1, 1024, 0, st>>>(bsum, P->scan_blocks);
   scan_argmax_kernel<<<P->scan_blocks, kScanThreads, 0, st>>>(cnt, perm[cur], n, bsum, bbest);
   argmax_final_kernel<<<1, 256, 0, st>>>(bbest, P->scan_blocks, dres);
+  if (d_counts) scan_prefix_kernel<<<P->scan_blocks, kScanThreads, 0, st>>>(cnt, perm[cur], n, bsum, d_counts);
   copy_u32_kernel<<<grid_for(n), 256, 0, st>>>(perm[cur], d_order, n);
   HIP_TRY(hipGetLastError(), "prefix count launch");
   return KDSS_OK;
@@ -2134,6 +2136,12 @@ int start_run(kdss_plan* P, const WsView& ws, const uint64_t* d_r0, void* d_r, u
   init_loads_kernel<<<grid_for(P->n), 256, 0, st>>>(d_r0, static_cast<uint64_t*>(d_r), ws.at<uint64_t>(P->off_delta),
                                                     P->n, P->width == 128 ? 1 : 0, dres);
   HIP_TRY(hipGetLastError(), "init launch");
+  if (d_r0) {   // a start load above r0_max would wrap the packed keys: refuse before the first iteration
+    DevResult h;
+    int rc = read_result(P, ws, st, &h);
+    if (rc) return rc;
+    if (h.r0max > P->r0_max) return fail(KDSS_EOVERFLOW, "a start load exceeds the plan's r0_max");
+  }
   const uint32_t nhot = (uint32_t)P->hot.size();
   if (P->width == 64 && !P->tiles.empty() && nhot) {   // the iterations' leaf passes read the hot keys from a table
     hot_keys_kernel<<<(nhot + 255) / 256, 256, 0, st>>>(static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot),
@@ -2239,22 +2247,33 @@ int kdss_plan_upload(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream) {
   return KDSS_OK;
 }
 
-int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64_t* d_r0, void* d_r,
-             uint32_t* d_order, kdss_trace_row* h_trace, uint32_t trace_cap, kdss_result* h_res, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// T iterations from the loads d_start (nullable: zero), then the extraction.
+// The run continues one that began at loads d_r0 (nullable: zero) t_offset
+// iterations earlier: the upper bound and the certificate use r - r0 over
+// t_offset + T iterations, and trace rows count from t_offset.
+int run_impl(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, uint32_t t_offset, const uint64_t* d_start,
+             const uint64_t* d_r0, void* d_r, uint32_t* d_order, kdss_trace_row* h_trace, uint32_t trace_cap,
+             kdss_result* h_res, void* stream) {
   if (!P || !d_r || !d_order || !h_res) return fail(KDSS_EINVAL, "null argument");
   if (T == 0 || T > P->T_max) return fail(KDSS_EINVAL, "T must be in 1..T_max");
+  if ((uint64_t)t_offset + T > 0xFFFFFFFFull) return fail(KDSS_ERANGE, "t_offset + T exceeds 2^32 - 1");
   int rc = check_ws(P, d_ws, ws_bytes);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   WsView ws{static_cast<char*>(d_ws)};
-  rc = start_run(P, ws, d_r0, d_r, T, st);
+  rc = start_run(P, ws, d_start, d_r, T, st);
   if (rc) return rc;
   const uint32_t every = P->opts.extract_every;
+  const uint32_t T_all = t_offset + T;
   uint32_t rows = 0;
   for (uint32_t t = 1; t <= T; ++t) {
     rc = iterate(P, ws, d_r, t, st);
     if (rc) return rc;
-    if (every && t % every == 0 && t < T && h_trace && rows < trace_cap) {
+    if (every && (t_offset + t) % every == 0 && t < T && h_trace && rows < trace_cap) {
       const u128 bound = (u128)P->r0_max + (u128)t * P->c_k;
       rc = launch_extract(P, ws, d_r, d_r0, bound, d_order, st);
       if (rc) return rc;
@@ -2262,7 +2281,7 @@ int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64
       rc = read_result(P, ws, st, &h);
       if (rc) return rc;
       kdss_trace_row& row = h_trace[rows++];
-      row.t = t;
+      row.t = t_offset + t;
       row.size = h.size;
       row.dens_num.lo = h.dens_num;
       row.dens_num.hi = 0;
@@ -2273,23 +2292,38 @@ int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64
   const u128 bound = (u128)P->r0_max + (u128)T * P->c_k;
   rc = launch_extract(P, ws, d_r, d_r0, bound, d_order, st);
   if (rc) return rc;
-  rc = launch_top_bound(P, ws, d_r, d_r0, T, d_order, st);
+  rc = launch_top_bound(P, ws, d_r, d_r0, T_all, d_order, st);
   if (rc) return rc;
   DevResult h;
   rc = read_result(P, ws, st, &h);
   if (rc) return rc;
-  if (h.r0max > P->r0_max) return fail(KDSS_EOVERFLOW, "a start load exceeds the plan's r0_max");
   rc = collect_timing(P, ws, T);
   if (rc) return rc;
-  fill_result(P, h, T, h_res);
+  fill_result(P, h, T_all, h_res);
   if (every && h_trace && rows < trace_cap) {
     kdss_trace_row& row = h_trace[rows++];
-    row.t = T;
+    row.t = T_all;
     row.size = h.size;
     row.dens_num = h_res->dens_num;
     row.ub_num = h_res->ub_num;
   }
   return KDSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kdss_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64_t* d_r0, void* d_r,
+             uint32_t* d_order, kdss_trace_row* h_trace, uint32_t trace_cap, kdss_result* h_res, void* stream) {
+  return run_impl(P, d_ws, ws_bytes, T, 0, d_r0, d_r0, d_r, d_order, h_trace, trace_cap, h_res, stream);
+}
+
+int kdss_run_resume(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, uint32_t t_offset,
+                    const uint64_t* d_start, const uint64_t* d_r0, void* d_r, uint32_t* d_order,
+                    kdss_trace_row* h_trace, uint32_t trace_cap, kdss_result* h_res, void* stream) {
+  if (!d_start) return fail(KDSS_EINVAL, "null checkpoint loads");
+  return run_impl(P, d_ws, ws_bytes, T, t_offset, d_start, d_r0, d_r, d_order, h_trace, trace_cap, h_res, stream);
 }
 
 int kdss_batch_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64_t* d_r0, uint64_t* d_r,
@@ -2487,8 +2521,16 @@ int kdss_leaf_credit(kdss_plan* P, void* d_ws, size_t ws_bytes, const void* d_r,
 
 int kdss_extract(kdss_plan* P, void* d_ws, size_t ws_bytes, const void* d_r, const uint64_t* d_r0, uint32_t T,
                  uint32_t* d_order, kdss_result* h_res, void* stream) {
+  return kdss_extract_counts(P, d_ws, ws_bytes, d_r, d_r0, T, d_order, nullptr, h_res, stream);
+}
+
+void kdss_batch_free(kdss_plan* P) { kdss_plan_free(P); }
+
+int kdss_extract_counts(kdss_plan* P, void* d_ws, size_t ws_bytes, const void* d_r, const uint64_t* d_r0,
+                        uint32_t T, uint32_t* d_order, uint64_t* d_counts, kdss_result* h_res, void* stream) {
   if (!P || !d_r || !d_order || !h_res) return fail(KDSS_EINVAL, "null argument");
   if (T == 0) return fail(KDSS_EINVAL, "T must be at least 1");
+  if (d_counts && P->node_off.size() != 2) return fail(KDSS_EUNSUPPORTED, "prefix counts of a batch plan");
   int rc = check_ws(P, d_ws, ws_bytes);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -2506,7 +2548,7 @@ int kdss_extract(kdss_plan* P, void* d_ws, size_t ws_bytes, const void* d_r, con
   rc = read_result(P, ws, st, &h);
   if (rc) return rc;
   const u128 bound = ((u128)h.pad1[1] << 64) | h.pad1[0];
-  rc = launch_extract(P, ws, d_r, d_r0, bound, d_order, st);
+  rc = launch_extract(P, ws, d_r, d_r0, bound, d_order, st, d_counts);
   if (rc) return rc;
   rc = launch_top_bound(P, ws, d_r, d_r0, T, d_order, st);
   if (rc) return rc;

@@ -89,7 +89,8 @@ EXPORTS = [
     "kdss_sct_export", "kdss_sct_core_numbers", "kdss_sct_free", "kdss_plan_create", "kdss_plan_info",
     "kdss_plan_free", "kdss_plan_upload", "kdss_run", "kdss_leaf_credit", "kdss_extract", "kdss_plan_timing",
     "kdss_batch_create", "kdss_batch_offsets", "kdss_batch_run", "kdss_plan_set_launch", "kdss_plan_autotune",
-    "kdss_sample_build", "kdss_sct_build_gpu",
+    "kdss_sample_build", "kdss_sct_build_gpu", "kdss_workspace_size", "kdss_solve", "kdss_run_resume",
+    "kdss_extract_counts", "kdss_batch_free",
 ]
 
 _lib = None
@@ -137,6 +138,14 @@ def lib():
     L.kdss_plan_set_launch.argtypes = [vp, C.c_uint32, C.c_uint32]
     L.kdss_plan_autotune.argtypes = [vp, vp, C.c_size_t, vp, C.c_uint32, C.c_uint32, C.POINTER(TuneResult), vp]
     L.kdss_extract.argtypes = [vp, vp, C.c_size_t, vp, vp, C.c_uint32, vp, C.POINTER(Result), vp]
+    L.kdss_extract_counts.argtypes = [vp, vp, C.c_size_t, vp, vp, C.c_uint32, vp, vp, C.POINTER(Result), vp]
+    L.kdss_workspace_size.argtypes = [vp, C.c_uint32, C.c_uint64, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+    L.kdss_solve.argtypes = [C.POINTER(Csr), C.c_uint32, C.c_uint32, C.POINTER(Opts), vp, C.c_uint64, vp,
+                             C.c_size_t, C.POINTER(C.c_size_t), vp, C.c_size_t, vp, C.POINTER(Result), vp]
+    L.kdss_run_resume.argtypes = [vp, vp, C.c_size_t, C.c_uint32, C.c_uint32, vp, vp, vp, vp, C.POINTER(TraceRow),
+                                  C.c_uint32, C.POINTER(Result), vp]
+    L.kdss_batch_free.argtypes = [vp]
+    L.kdss_batch_free.restype = None
     _lib = L
     return L
 
@@ -176,6 +185,13 @@ class Tree:
         s = TreeStats()
         _check(lib().kdss_sct_info(self._h, C.byref(s)), "kdss_sct_info")
         return s
+
+    def workspace_size(self, T_max: int, r0_max: int = 0, width: int = 0, update: int = 0) -> int:
+        """Device workspace a plan of this tree would need (kdss_workspace_size)."""
+        o = Opts(width, 0, 0, 0, 0, update)
+        b = C.c_size_t(0)
+        _check(lib().kdss_workspace_size(self._h, T_max, r0_max, C.byref(o), C.byref(b)), "kdss_workspace_size")
+        return b.value
 
     def export(self):
         """(h, p, members) of the kept leaves."""
@@ -307,6 +323,27 @@ class Plan:
                      for x in rows if x.t]
         return res, trace
 
+    def resume(self, ws, T: int, t_offset: int, start, r, order, r0=None, trace_cap: int = 0, stream=None):
+        """T more iterations from checkpoint loads `start` (u64[n]) of a run that
+        began at r0 (nullable) t_offset iterations earlier (kdss_run_resume)."""
+        res = Result()
+        rows = (TraceRow * trace_cap)() if trace_cap else None
+        _check(lib().kdss_run_resume(self._h, _ptr(ws), ws.numel(), T, t_offset, _ptr(start), _ptr(r0), _ptr(r),
+                                     _ptr(order), C.cast(rows, C.POINTER(TraceRow)) if rows is not None else None,
+                                     trace_cap, C.byref(res), _stream(stream)), "kdss_run_resume")
+        trace = None
+        if rows is not None:
+            trace = [dict(t=x.t, size=x.size, dens_num=x.dens_num.value, ub_num=x.ub_num.value)
+                     for x in rows if x.t]
+        return res, trace
+
+    def extract_counts(self, ws, r, order, counts, T: int, r0=None, stream=None) -> Result:
+        """The extraction with every prefix count K_i into counts (u64[n])."""
+        res = Result()
+        _check(lib().kdss_extract_counts(self._h, _ptr(ws), ws.numel(), _ptr(r), _ptr(r0), T, _ptr(order),
+                                         _ptr(counts), C.byref(res), _stream(stream)), "kdss_extract_counts")
+        return res
+
     def leaf_credit(self, ws, r, out, stream=None):
         _check(lib().kdss_leaf_credit(self._h, _ptr(ws), ws.numel(), _ptr(r), _ptr(out), _stream(stream)),
                "kdss_leaf_credit")
@@ -352,6 +389,11 @@ class Batch(Plan):
         st = self.stats()
         self.width = st.width
         self.workspace_bytes = st.workspace_bytes
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kdss_batch_free(self._h)
+            self._h = None
 
     def run(self, ws, T: int, r, order, r0=None, stream=None):
         res = (Result * self.count)()
@@ -421,3 +463,30 @@ def solve(graph, k: int, T: int, r0=None, width: int = 0, use_graph: bool = Fals
     plan.close()
     tree.close()
     return out
+
+
+def solve_one_shot(graph, k: int, T: int, r0=None, width: int = 0, device="cuda", stream=None):
+    """kdss_solve: a first call sizes the buffers (nothing runs), the second
+    builds, lays out, uploads and runs in one C call."""
+    import torch
+    c, keep = _csr(graph)
+    o = Opts(width, 0, 0, 0, 0, 0)
+    need = C.c_size_t(0)
+    res = Result()
+    r0_max = 0 if r0 is None or graph.n == 0 else int(np.max(np.asarray(r0, dtype=np.uint64)))
+    r0_t = None
+    if r0 is not None:
+        r0_t = torch.from_numpy(np.asarray(r0, dtype=np.uint64).view(np.int64).copy()).to(device)
+    st = _stream(stream)
+    rc = lib().kdss_solve(C.byref(c), k, T, C.byref(o), _ptr(r0_t), r0_max, None, 0, C.byref(need), None, 0, None,
+                          C.byref(res), st)
+    if rc != EWORKSPACE:
+        _check(rc, "kdss_solve (size query)")
+    words = max(graph.n * (2 if res.width == 128 else 1), 1)
+    ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=device)
+    r = torch.empty(words, dtype=torch.int64, device=device)
+    order = torch.empty(max(graph.n, 1), dtype=torch.int32, device=device)
+    _check(lib().kdss_solve(C.byref(c), k, T, C.byref(o), _ptr(r0_t), r0_max, _ptr(ws), ws.numel(), C.byref(need),
+                            _ptr(r), words, _ptr(order), C.byref(res), st), "kdss_solve")
+    torch.cuda.synchronize()
+    return res, loads_to_numpy(r, graph.n, res.width), order.cpu().numpy().view(np.uint32)[: graph.n].copy()

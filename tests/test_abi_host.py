@@ -293,3 +293,62 @@ def test_batch_plan_layout():
         b.set_launch(0, 10)
     assert e.value.status == kdss.ERANGE
     b.set_launch(512, 256)
+
+
+def test_workspace_size_matches_plan():
+    g = synth.chung_lu(2000, 20000, 2.3, seed=5, planted=30)
+    t = kdss.Tree(g, 4)
+    for T, r0_max, width in ((50, 0, 0), (10, 2**60, 0), (10, 0, 128), (7, 3, 64)):
+        assert t.workspace_size(T, r0_max, width) == kdss.Plan(t, T, r0_max, width=width).workspace_bytes
+    with pytest.raises(kdss.KdssError) as e:
+        t.workspace_size(0)
+    assert e.value.status == kdss.EINVAL
+
+
+def test_solve_sizes_buffers_before_device_work():
+    """kdss_solve with no workspace builds and lays out the tree, reports the
+    workspace and load width, and runs nothing (no device call)."""
+    g = synth.chung_lu(1500, 12000, 2.3, seed=2, planted=20)
+    L = kdss.lib()
+    c, keep = kdss._csr(g)
+    need = C.c_size_t(0)
+    res = kdss.Result()
+    o = kdss.Opts(0, 0, 0, 0, 0, 0)
+    rc = L.kdss_solve(C.byref(c), 4, 20, C.byref(o), None, 0, None, 0, C.byref(need), None, 0, None, C.byref(res),
+                      None)
+    assert rc == kdss.EWORKSPACE
+    assert need.value == kdss.Plan(kdss.Tree(g, 4), 20).workspace_bytes
+    assert (res.width, res.n) == (64, g.n)
+    o128 = kdss.Opts(128, 0, 0, 0, 0, 0)
+    rc = L.kdss_solve(C.byref(c), 4, 20, C.byref(o128), None, 0, None, 0, C.byref(need), None, 0, None,
+                      C.byref(res), None)
+    assert rc == kdss.EWORKSPACE and res.width == 128
+    # argument and graph errors come first
+    assert L.kdss_solve(None, 4, 20, None, None, 0, None, 0, C.byref(need), None, 0, None, C.byref(res),
+                        None) == kdss.EINVAL
+    assert L.kdss_solve(C.byref(c), 1, 20, None, None, 0, None, 0, C.byref(need), None, 0, None, C.byref(res),
+                        None) == kdss.EINVAL
+    assert L.kdss_solve(C.byref(c), 4, 0, None, None, 0, None, 0, C.byref(need), None, 0, None, C.byref(res),
+                        None) == kdss.EINVAL
+
+
+def test_resume_and_counts_reject_bad_arguments_before_device_work():
+    g = synth.complete_graph(8)
+    t = kdss.Tree(g, 3)
+    p = kdss.Plan(t, 5)
+    L = kdss.lib()
+    res = kdss.Result()
+    v = C.c_void_p(8)
+    assert L.kdss_run_resume(p._h, C.c_void_p(256), p.workspace_bytes, 3, 2, None, None, v, v, None, 0,
+                             C.byref(res), None) == kdss.EINVAL           # no checkpoint loads
+    assert L.kdss_run_resume(p._h, C.c_void_p(256), p.workspace_bytes, 3, 2**32 - 2, v, None, v, v, None, 0,
+                             C.byref(res), None) == kdss.ERANGE           # t_offset + T past 2^32 - 1
+    assert L.kdss_run_resume(p._h, C.c_void_p(256), p.workspace_bytes, 3, 2, v, None, v, v, None, 0,
+                             C.byref(res), None) == kdss.EWORKSPACE       # not uploaded
+    assert L.kdss_extract_counts(p._h, C.c_void_p(256), p.workspace_bytes, v, None, 0, v, v, C.byref(res),
+                                 None) == kdss.EINVAL                     # T = 0
+    b = kdss.Batch([t, kdss.Tree(g, 4)], 5)
+    assert L.kdss_extract_counts(b._h, C.c_void_p(256), b.workspace_bytes, v, None, 3, v, v, C.byref(res),
+                                 None) == kdss.EUNSUPPORTED               # batch plans: no prefix counts
+    b.close()
+    L.kdss_batch_free(None)

@@ -1,8 +1,8 @@
 """Parity at the benchmarked sizes, in the launch configurations bench.py times.
 
 * Chung-Lu n = 1,000,000, m = 10,000,000, k = 5, T = 200: the oracle runs the
-  whole problem (its clique listing fits in memory), so loads, order, density
-  and upper bound are compared bit for bit.
+  whole problem (its clique listing fits in memory), so loads, order, density,
+  upper bound and every prefix count K_i are compared bit for bit.
 * The 2048-problem batch (512 Chung-Lu graphs x k in {3, 4, 6, 8}, T = 64, one
   plan, autotuned grids, hipGraph iterations): eight sampled problems, each
   solved by the oracle on its own.
@@ -75,6 +75,22 @@ def test_chung_lu_1m_bit_exact(K, oracle_mod):
     from fractions import Fraction
     assert sol.bound_kind == 1 and Fraction(sol.bound_num, sol.bound_den) == want
     assert sol.certified == oracle_mod.certified(ref["dens_num"], ref["size"], want, g.n)
+    say("chung-lu 1M: every prefix count K_i at r_200")
+    tree = K.Tree(g, 5)
+    plan = K.Plan(tree, 200)
+    ws = plan.alloc_workspace()
+    plan.upload(ws)
+    rt = torch.from_numpy(np.asarray(ref["r"], dtype=np.uint64).view(np.int64).copy()).cuda()
+    order = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    cnt = torch.empty(g.n, dtype=torch.int64, device="cuda")
+    plan.extract_counts(ws, rt, order, cnt, 200)
+    torch.cuda.synchronize()
+    want_k = oracle_mod.prefix_counts(g.n, g.row_ptr, g.col, 5, ref["r"])
+    assert np.array_equal(order.cpu().numpy().view(np.uint32), want_k["order"])
+    assert np.array_equal(cnt.cpu().numpy().view(np.uint64), want_k["K"])
+    assert int(want_k["K"][-1]) == ref["c_k"]
+    plan.close()
+    tree.close()
 
 
 def test_batch_512_sampled(K, oracle_mod):
