@@ -342,6 +342,27 @@ int kdss_extract(kdss_plan *p, void *d_ws, size_t ws_bytes, const void *d_r,
 int kdss_extract_counts(kdss_plan *p, void *d_ws, size_t ws_bytes, const void *d_r, const uint64_t *d_r0,
                         uint32_t T, uint32_t *d_order, uint64_t *d_counts, kdss_result *h_res, void *stream);
 
+/* ---- runs without device allocation ----
+ * For callers that cannot allocate device memory (tight serving loops, code
+ * that must not call hipMalloc): kdss_run with the plan's workspace taken from
+ * a static device array of KDSS_STATIC_WORKSPACE_BYTES that the library holds
+ * on every GPU it runs on until the process ends.  Each call copies the plan's
+ * leaf stream and tables into the current device's array (kdss_plan_upload's
+ * work; the stream is synchronised), clears its queue and hot-node slots with
+ * kernels, then runs T iterations from d_r0 (device u64[n], nullable, entries
+ * <= r0_max) and the extraction with plain launches (the plan's use_graph,
+ * time_kernels and extract_every are ignored).  d_r, d_order and h_res as in
+ * kdss_run; the result equals kdss_run's bit for bit.  The call makes no
+ * device allocation.  All calls on one GPU share its array: calls that
+ * overlap on one GPU (from several threads or streams) race and are not
+ * allowed.  After the call the plan is uploaded to the array, not to any
+ * earlier workspace (kdss_plan_upload again before kdss_run there).
+ * Errors: KDSS_ERANGE when kdss_plan_info().workspace_bytes exceeds
+ * KDSS_STATIC_WORKSPACE_BYTES; others as kdss_run. */
+#define KDSS_STATIC_WORKSPACE_BYTES (64u << 20)
+int kdss_run_static(kdss_plan *p, uint32_t T, const uint64_t *d_r0, void *d_r, uint32_t *d_order,
+                    kdss_result *h_res, void *stream);
+
 /* ---- launch tuning (autotuned tile schedules) ----
  * The leaf-credit and heavy-leaf kernels run persistent grids; their sizes
  * decide how tiles and queued heavy leaves are spread over the 256 CUs. */

@@ -18,7 +18,7 @@ BUILD = os.path.join(PKG, "_build")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["api.cpp", "sct_build.cpp"]
-DEVICE_SOURCES = ["kernels.hip", "gnn.hip", "sample.hip", "sct_gpu.hip"]
+DEVICE_SOURCES = ["kernels.hip", "gnn.hip", "sample.hip", "sct_gpu.hip", "run_static.hip"]
 HEADERS = ["kdss_internal.h", os.path.join(ROOT, "include", "kdss.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -10,6 +10,8 @@
 
 #include "../../include/kdss.h"
 
+struct kdss_plan;
+
 namespace kdss {
 
 using u128 = unsigned __int128;
@@ -125,6 +127,14 @@ constexpr uint32_t kHotSlots = 256;              // credit slots per hot node, s
 constexpr double kMaskedGatherShare = 0.5;       // hot share from which masked gathers are the default
 constexpr uint32_t kPbRegRows = 16;              // PBUpdate: lane tiles up to this many rows run from registers
 constexpr uint32_t kPbMidRows = 32;              // PBUpdate: lane tiles up to this many rows share 4-wave workgroups
+
+// Copies a plan's leaf stream and tables into the device workspace d_ws and
+// empties its queue and hot-node slots (with kernels when fill_by_kernel, else
+// with memsets); synchronises the stream.
+int upload_plan(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream, bool fill_by_kernel);
+// kdss_run without a trace.
+int run_plan(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64_t* d_r0, void* d_r,
+             uint32_t* d_order, kdss_result* h_res, void* stream);
 
 // Device-side result of an extraction.
 struct DevResult {

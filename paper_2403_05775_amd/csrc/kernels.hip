@@ -2210,6 +2210,14 @@ void kdss_plan_free(kdss_plan* P) {
 }
 
 int kdss_plan_upload(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream) {
+  return kdss::upload_plan(P, d_ws, ws_bytes, stream, false);
+}
+
+}  // extern "C"
+
+namespace kdss {
+
+int upload_plan(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream, bool fill_by_kernel) {
   if (!P || !d_ws) return fail(KDSS_EINVAL, "null argument");
   if (ws_bytes < P->ws_bytes) return fail(KDSS_EWORKSPACE, "workspace smaller than kdss_plan_info().workspace_bytes");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -2238,14 +2246,24 @@ int kdss_plan_upload(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream) {
                          hipMemcpyHostToDevice, st), "upload node offsets");
   // the heavy-leaf queue and the hot-node slot entries start empty; every leaf
   // pass leaves them empty again
-  HIP_TRY(hipMemsetAsync(ws.at<uint32_t>(P->off_qcount), 0, 64, st), "queue reset");
-  if (!P->hot.empty())
-    HIP_TRY(hipMemsetAsync(ws.at<uint64_t>(P->off_scratch), 0, (size_t)kHotSlots * P->hot.size() * 8, st),
-            "hot rows reset");
+  if (fill_by_kernel) {
+    fill_u64_kernel<<<1, 64, 0, st>>>(ws.at<uint64_t>(P->off_qcount), 0ull, 8);
+    clear_hot_rows(P, ws, st);
+    HIP_TRY(hipGetLastError(), "queue and hot rows reset");
+  } else {
+    HIP_TRY(hipMemsetAsync(ws.at<uint32_t>(P->off_qcount), 0, 64, st), "queue reset");
+    if (!P->hot.empty())
+      HIP_TRY(hipMemsetAsync(ws.at<uint64_t>(P->off_scratch), 0, (size_t)kHotSlots * P->hot.size() * 8, st),
+              "hot rows reset");
+  }
   HIP_TRY(hipStreamSynchronize(st), "upload synchronize");
   P->uploaded_ws = d_ws;
   return KDSS_OK;
 }
+
+}  // namespace kdss
+
+extern "C" {
 
 }  // extern "C"
 
@@ -2325,6 +2343,15 @@ int kdss_run_resume(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, uint3
   if (!d_start) return fail(KDSS_EINVAL, "null checkpoint loads");
   return run_impl(P, d_ws, ws_bytes, T, t_offset, d_start, d_r0, d_r, d_order, h_trace, trace_cap, h_res, stream);
 }
+
+}  // extern "C"
+
+int kdss::run_plan(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64_t* d_r0, void* d_r,
+                   uint32_t* d_order, kdss_result* h_res, void* stream) {
+  return run_impl(P, d_ws, ws_bytes, T, 0, d_r0, d_r0, d_r, d_order, nullptr, 0, h_res, stream);
+}
+
+extern "C" {
 
 int kdss_batch_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const uint64_t* d_r0, uint64_t* d_r,
                    uint32_t* d_order, kdss_result* h_res, uint32_t count, void* stream) {

@@ -90,8 +90,10 @@ EXPORTS = [
     "kdss_plan_free", "kdss_plan_upload", "kdss_run", "kdss_leaf_credit", "kdss_extract", "kdss_plan_timing",
     "kdss_batch_create", "kdss_batch_offsets", "kdss_batch_run", "kdss_plan_set_launch", "kdss_plan_autotune",
     "kdss_sample_build", "kdss_sct_build_gpu", "kdss_workspace_size", "kdss_solve", "kdss_run_resume",
-    "kdss_extract_counts", "kdss_batch_free",
+    "kdss_extract_counts", "kdss_batch_free", "kdss_run_static",
 ]
+
+STATIC_WORKSPACE_BYTES = 64 << 20   # KDSS_STATIC_WORKSPACE_BYTES
 
 _lib = None
 
@@ -144,6 +146,7 @@ def lib():
                              C.c_size_t, C.POINTER(C.c_size_t), vp, C.c_size_t, vp, C.POINTER(Result), vp]
     L.kdss_run_resume.argtypes = [vp, vp, C.c_size_t, C.c_uint32, C.c_uint32, vp, vp, vp, vp, C.POINTER(TraceRow),
                                   C.c_uint32, C.POINTER(Result), vp]
+    L.kdss_run_static.argtypes = [vp, C.c_uint32, vp, vp, vp, C.POINTER(Result), vp]
     L.kdss_batch_free.argtypes = [vp]
     L.kdss_batch_free.restype = None
     _lib = L
@@ -342,6 +345,13 @@ class Plan:
         res = Result()
         _check(lib().kdss_extract_counts(self._h, _ptr(ws), ws.numel(), _ptr(r), _ptr(r0), T, _ptr(order),
                                          _ptr(counts), C.byref(res), _stream(stream)), "kdss_extract_counts")
+        return res
+
+    def run_static(self, T: int, r, order, r0=None, stream=None) -> Result:
+        """kdss_run on the library's static device workspace (no device allocation)."""
+        res = Result()
+        _check(lib().kdss_run_static(self._h, T, _ptr(r0), _ptr(r), _ptr(order), C.byref(res), _stream(stream)),
+               "kdss_run_static")
         return res
 
     def leaf_credit(self, ws, r, out, stream=None):
