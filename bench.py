@@ -1,8 +1,12 @@
 """Benchmark: synchronous Frank-Wolfe over the k-pruned SCT on one MI355X.
 
-Workload (default): Chung-Lu power-law graph, n = 1,000,000, m = 10,000,000
-distinct edges, degree exponent 2.5, planted 40-node near-clique (pair
-probability 0.9), seed 0; k = 5; T = 200 iterations; u32 ids, u64 loads.
+Workload (default, batch-512): 512 Chung-Lu power-law graphs (n uniform in
+[1000, 50000], average degree 8-40, exponent 2.2-2.8, seeds 1000 + g), each at
+k = 3, 4, 6 and 8: 2048 problems, 3.3e8 leaves and 5.0e9 members per iteration,
+in one plan with one launch per kernel per iteration; T = 64; u32 ids, u64
+loads.  The other configurations are named workloads (--workload): chung-lu-1m
+(n = 1,000,000, m = 10,000,000, exponent 2.5, planted 40-node near-clique,
+k = 5, T = 200), er-200, rmat-16, gnn-warm-2m, and the paper's other parts.
 
 A step is one whole pass of the hot path on inputs already resident in HBM:
 start loads, T leaf-credit + load-update iterations, and the extraction
@@ -10,7 +14,8 @@ start loads, T leaf-credit + load-update iterations, and the extraction
 on the host is reported separately (the paper also excludes it).
 
 Prints one JSON line: SCT-leaf updates/s (leaves * T per second of step time),
-the dominant kernel's roofline figures, and the CPU oracle on a bounded sample.
+the leaf-credit kernel's roofline figures from kernel-attached HIP events over
+the timed steps, and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -25,13 +30,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "leaf_credit_chung-lu-1m_counters.txt")
+VALU_PEAK_WAVE_INSTS = 256 * 2.4e9     # one wave64 VALU instruction per CU per cycle
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_2403_05775_amd", "csrc", "kernels.hip")
 
 WORKLOADS = {
     "chung-lu-1m": dict(kind="chung_lu", n=1_000_000, m=10_000_000, beta=2.5, seed=0, planted=40,
                         planted_p=0.9, k=5, T=200),
-    "er-200": dict(kind="er", n=200, p=0.08, seed=0, planted=12, k=3, T=64),
+    "er-200": dict(kind="er", n=200, p=0.08, seed=0, planted=12, k=3, T=64, cpu_full=True),
     # the paper's own update rule (PBUpdate, synchronous over the tree's pairs)
     # on the default workload's graph; the oracle's synchronous pass samples 5
     # iterations
@@ -67,70 +73,212 @@ def _batch_graph(i):
     return synth.batch_member(i)
 
 
+def cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores():
+    """Threads the oracle uses: the box's share (at most 16), or fewer cores."""
+    return min(16, os.cpu_count() or 1)
+
+
+def rooflines(tm, L, M, n, width=64):
+    """HBM roofline fractions from the kernel durations of the timed region
+    (kernel-attached HIP events; averages per launch), with the algorithmic
+    bytes of one iteration: the leaf stream (4 B per member, 4 B per leaf
+    header) and w B per node to read the loads, plus w B per node to write them
+    in the load update (w = 8 for 64-bit loads)."""
+    nl = max(1, tm.leaf_launches)
+    leaf_us = 1000.0 * tm.leaf_ms / nl
+    heavy_us = 1000.0 * tm.heavy_ms / nl
+    reduce_us = 1000.0 * tm.reduce_ms / nl
+    apply_us = 1000.0 * tm.apply_ms / max(1, tm.apply_launches)
+    w = width // 8
+    pass_bytes = 4 * M + 4 * L + w * n
+    iter_bytes = pass_bytes + w * n
+    pass_us = leaf_us + heavy_us + reduce_us
+    iter_us = pass_us + apply_us
+
+    def frac(b, us):
+        gbs = b / (us * 1e-6) / 1e9 if us > 0 else 0.0
+        return gbs, gbs / HBM_PEAK_GBS
+
+    a_leaf, f_leaf = frac(pass_bytes, leaf_us)
+    a_pass, f_pass = frac(pass_bytes, pass_us)
+    a_iter, f_iter = frac(iter_bytes, iter_us)
+    return dict(leaf_us=leaf_us, heavy_us=heavy_us, reduce_us=reduce_us, apply_us=apply_us, pass_bytes=pass_bytes,
+                iter_bytes=iter_bytes, leaf=(a_leaf, f_leaf), credit_pass=(a_pass, f_pass, pass_us),
+                iteration=(a_iter, f_iter, iter_us), heavy_per_iter=tm.heavy_leaves / nl)
+
+
+def roofline_fields(rf, kernel, workload, counters_key):
+    """The line's roofline object (the leaf-credit kernel) and the two wider scopes."""
+    traffic = counter_field(counters_key, "hbm_bytes_per_launch")
+    valu = counter_field(counters_key, "valu_insts_per_launch")
+    out = {"roofline": {"bound": "hbm", "achieved": rf["leaf"][0], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": rf["leaf"][1], "traffic": traffic, "kernel": kernel,
+                        "bytes_per_launch": rf["pass_bytes"], "us_per_launch": rf["leaf_us"],
+                        "timing": "kernel-attached HIP events (hipExtLaunchKernel) over the timed steps"},
+           "credit_pass": {"kernels": "leaf_credit + heavy_leaf" + (" + hot_reduce" if rf["reduce_us"] else ""),
+                           "us": rf["credit_pass"][2], "achieved": rf["credit_pass"][0], "frac": rf["credit_pass"][1]},
+           "iteration": {"kernels": "credit pass + load update", "us": rf["iteration"][2],
+                         "bytes": rf["iter_bytes"], "achieved": rf["iteration"][0], "frac": rf["iteration"][1]},
+           "kernel_us": {"leaf_credit": rf["leaf_us"], "heavy_leaf": rf["heavy_us"],
+                         "hot_reduce": rf["reduce_us"] or None, "apply": rf["apply_us"]},
+           "heavy_leaves_per_iteration": rf["heavy_per_iter"]}
+    if valu:
+        # one wave64 VALU instruction per CU per cycle: 256 CUs x 2.4 GHz
+        peak = VALU_PEAK_WAVE_INSTS
+        got = valu / (rf["leaf_us"] * 1e-6)
+        out["valu_issue"] = {"bound": "alu", "insts_per_launch": valu, "achieved": got, "peak": peak,
+                             "unit": "wave-instructions/s", "frac": got / peak,
+                             "formula": "SQ_INSTS_VALU per launch / leaf-credit duration; peak = 256 CUs x "
+                                        "2.4e9 cycles/s x 1 wave64 VALU instruction per CU per cycle"}
+    return out
+
+
 def batch_bench(w, args):
-    """The batch workload: all problems in one plan, autotuned grids, iterations
-    replayed as hipGraphs; a step runs T iterations and every extraction."""
+    """The batch workload: all problems in one plan, one launch per kernel per
+    iteration; a step runs T iterations and every problem's extraction."""
     import concurrent.futures as cf
-    import numpy as np
     import torch
     from paper_2403_05775_amd import kdss
     t0 = time.time()
     count = args.batch_graphs or w["graphs"]
-    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+    with cf.ProcessPoolExecutor(max_workers=host_cores()) as ex:
         graphs = list(ex.map(_batch_graph, range(count), chunksize=4))
     log(f"{count} graphs generated ({time.time() - t0:.1f} s), total n={sum(g.n for g in graphs)}")
     t1 = time.time()
     jobs = [(g, k) for g in graphs for k in w["ks"]]
-    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=host_cores()) as ex:
         trees = list(ex.map(lambda gk: kdss.Tree(gk[0], gk[1], threads=1), jobs))
     build_s = time.time() - t1
     L = sum(t.stats().leaves for t in trees)
     M = sum(t.stats().members for t in trees)
+    cks = [t.stats().c_k.value for t in trees]
     log(f"{len(trees)} trees built in {build_s:.1f} s: leaves={L} members={M}")
     T = w["T"]
     t2 = time.time()
-    b = kdss.Batch(trees, T, use_graph=True)
+    b = kdss.Batch(trees, T, use_graph=args.graph, time_kernels=not args.graph)
     plan_s = time.time() - t2
     n_total = b.n
     for t in trees:
         t.close()
     dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
     ws = b.alloc_workspace(dev)
     b.upload(ws)
     r = torch.empty(n_total, dtype=torch.int64, device=dev)
     order = torch.empty(n_total, dtype=torch.int32, device=dev)
-    tune = b.autotune(ws, r, warm=3, iters=3)
-    log(f"plan {plan_s:.1f} s, workspace {b.workspace_bytes / 1e9:.1f} GB, key mode {b.stats().key_mode}; "
-        f"autotune: leaf {tune.best_leaf_blocks} heavy {tune.best_heavy_blocks} gather {tune.best_gather} "
-        f"({tune.best_ms:.3f} ms/iter; masked {tune.gather_ms[0]:.3f}, full {tune.gather_ms[1]:.3f})")
+    tune, cached = tune_launch(b, ws, r, T, args)
+    st = b.stats()
+    log(f"plan {plan_s:.1f} s, workspace {b.workspace_bytes / 1e9:.1f} GB, key mode {st.key_mode}")
     for i in range(args.warmup):
         b.run(ws, T, r, order)
     torch.cuda.synchronize()
+    b.timing(reset=True)
     ts = time.perf_counter()
     for i in range(args.steps):
         res = b.run(ws, T, r, order)
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - ts) / args.steps
-    st = b.stats()
-    step_bytes = T * (4 * M + 4 * L + 8 * n_total + 16 * n_total) + 4 * M + 4 * L
+    tm = b.timing(reset=True)
+    step_bytes = T * (4 * M + 4 * L + 16 * n_total) + (4 * M + 4 * L)
     out = {
         "metric": "SCT-leaf updates/s", "value": L * T / (ms / 1000.0), "unit": "leaf-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": f"batch of {count} Chung-Lu graphs x k in {list(w['ks'])}, T={T}",
+        "config": {"workload": f"batch-512: {count} Chung-Lu graphs (n in [1000, 50000], average degree 8-40, "
+                               f"exponent 2.2-2.8, seeds 1000+g) x k in {list(w['ks'])}, T={T}",
                    "problems": len(jobs), "n_total": n_total, "leaves": L, "members": M,
-                   "key_mode": st.key_mode, "parallelism": "single GPU, one launch per iteration, hipGraph"},
+                   "key_mode": st.key_mode, "gather": "masked" if st.gather == 1 else "full",
+                   "hot_share": round(st.hot_share, 4),
+                   "parallelism": "single GPU, one launch per kernel per iteration for all problems",
+                   "hip_graph": bool(args.graph)},
         "hbm_gbps_algorithmic": step_bytes / (ms / 1000.0) / 1e9,
         "host_build_s": build_s, "plan_s": plan_s,
-        "autotune": {"leaf_blocks": tune.best_leaf_blocks, "heavy_blocks": tune.best_heavy_blocks,
-                     "ms_per_iter": tune.best_ms, "gather": tune.best_gather,
-                     "gather_ms": {"masked": tune.gather_ms[0], "full": tune.gather_ms[1]},
-                     "hot_share": st.hot_share,
-                     "tried": [[tune.leaf_blocks[i], tune.heavy_blocks[i], tune.ms[i]]
-                               for i in range(min(tune.tried, 32))]},
+        "launch": launch_fields(tune, cached),
+        "size_classes": size_classes(st),
         "densest_sizes_first8": [x.size for x in res[:8]],
     }
+    if not args.graph:
+        rf = rooflines(tm, L, M, n_total)
+        out.update(roofline_fields(rf, "leaf_credit_kernel<KPacked>", "batch-512", "batch-512"))
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_batch(jobs, cks, T)
     print(json.dumps(out))
+
+
+def size_classes(ps):
+    """Leaves, members and lane tiles per size class s = h + p."""
+    return {name: {"leaves": int(ps.leaves[c]), "members": int(ps.members[c]), "tiles": int(ps.tiles[c])}
+            for c, name in enumerate(("s<=8", "s<=16", "s<=32", "s<=64", "s>64"))}
+
+
+def tune_launch(plan, ws, r, T, args):
+    """Grid sizes and gather mode: from the committed tuning cache when it holds
+    this plan's key, else timed on the plan's own data at steady state (T/2
+    untimed iterations from zero loads, then 5 timed) and filed in the cache;
+    always outside the timed region."""
+    if args.no_autotune or T < 8:
+        return None, False
+    warm = max(3, T // 2)
+    iters = min(5, T - warm)
+    cache = args.tune_cache or None
+    if cache:
+        tune, cached = plan.autotune_cached(ws, r, warm=warm, iters=iters, cache_path=cache)
+    else:
+        tune, cached = plan.autotune(ws, r, warm=warm, iters=iters), False
+    log(f"launch: leaf {tune.best_leaf_blocks} heavy {tune.best_heavy_blocks} gather {tune.best_gather} "
+        f"({'tuning cache' if cached else f'tuned, {tune.best_ms * 1000:.2f} us/iter'}; key {plan.tune_key()})")
+    return tune, cached
+
+
+def launch_fields(tune, cached):
+    if tune is None:
+        return "defaults"
+    out = {"leaf_blocks": tune.best_leaf_blocks, "heavy_blocks": tune.best_heavy_blocks,
+           "gather": "masked" if tune.best_gather == 1 else "full", "from_tuning_cache": cached,
+           "tuned_us_per_iter": tune.best_ms * 1000}
+    if not cached:
+        out["gather_us"] = {"masked": tune.gather_ms[0] * 1000, "full": tune.gather_ms[1] * 1000}
+    return out
+
+
+def cpu_baseline_batch(jobs, cks, T, budget_s=15.0):
+    """The oracle (clique listing, then T synchronous iterations and the
+    extraction) on a bounded sample of the batch's problems: problems in a
+    seeded shuffle, skipping those with more than 2e7 k-cliques (listing
+    memory), until budget_s seconds of iterations + extraction; listing
+    excluded as the tree build is on the GPU side."""
+    import numpy as np
+    from oracle import oracle as O
+    O.build()
+    cores = host_cores()
+    rng = np.random.default_rng(2048)
+    idx = [int(q) for q in rng.permutation(len(jobs)) if 0 < cks[int(q)] <= 2e7]
+    leaves_done, secs, listing, probs = 0, 0.0, 0.0, 0
+    from paper_2403_05775_amd import kdss
+    for q in idx:
+        g, k = jobs[q]
+        res = O.solve(g.n, g.row_ptr, g.col, k, T, threads=cores)
+        secs += res["iter_seconds"] + res["extract_seconds"]
+        listing += res["enum_seconds"]
+        leaves_done += kdss.tree_count(g, k).leaves
+        probs += 1
+        if secs >= budget_s:
+            break
+    return dict(value=leaves_done * T / secs, unit="leaf-updates/s", cores=cores, kind="oracle",
+                cpu=cpu_model(),
+                sample=f"{probs} of the {len(jobs)} problems (seeded shuffle, c_k <= 2e7), each {T} synchronous "
+                       f"iterations + extraction ({secs:.1f} s); leaves counted as the GPU plan's; the oracle's "
+                       f"k-clique listing ({listing:.1f} s) excluded", seconds=secs)
 
 
 def _within(K, i, K_ref, i_ref, gap):
@@ -428,15 +576,20 @@ def sctbuild_bench(w, args):
     print(json.dumps(out))
 
 
-def counter_traffic(workload, launch_bytes):
-    """HBM bytes per leaf-credit launch from committed rocprofv3 counter runs,
-    only while they describe the current kernel source."""
-    if not os.path.exists(COUNTERS):
+def counters_file(workload):
+    return os.path.join(PROFILES, f"leaf_credit_{workload}_counters.txt")
+
+
+def counter_field(workload, field):
+    """A per-launch figure of the leaf-credit kernel from the committed
+    rocprofv3 counter runs, only while they describe the current kernel source."""
+    path = counters_file(workload)
+    if not os.path.exists(path):
         return None
-    c = json.load(open(COUNTERS))
+    c = json.load(open(path))
     if c.get("kernel_sha256_16") != kernel_hash() or c.get("workload") != workload:
         return None
-    return c.get("hbm_bytes_per_launch")
+    return c.get(field)
 
 
 def cpu_baseline_pb(g, w, tree, L, sample_T):
@@ -447,7 +600,7 @@ def cpu_baseline_pb(g, w, tree, L, sample_T):
     h, p, mem = tree.export()
     res = O.pb_run(g.n, h, p, mem, w["k"], sample_T, True)
     secs = res["seconds"]
-    return dict(value=L * sample_T / secs, unit="leaf-updates/s", cores=1, kind="oracle",
+    return dict(value=L * sample_T / secs, unit="leaf-updates/s", cores=1, kind="oracle", cpu=cpu_model(),
                 sample=f"same graph, k and pairs, {sample_T} synchronous PBUpdate iterations ({secs:.2f} s), "
                        f"one thread", seconds=secs)
 
@@ -457,41 +610,66 @@ def cpu_baseline(g, w, L, sample_T):
     sample_T iterations; listing excluded like the tree build on the GPU side."""
     from oracle import oracle as O
     O.build()
-    res = O.solve(g.n, g.row_ptr, g.col, w["k"], sample_T)
+    res = O.solve(g.n, g.row_ptr, g.col, w["k"], sample_T, threads=host_cores())
     secs = res["iter_seconds"] + res["extract_seconds"]
     return dict(value=L * sample_T / secs, unit="leaf-updates/s", cores=res["threads"], kind="oracle",
+                cpu=cpu_model(),
                 sample=f"same graph and k, {sample_T} iterations + extraction ({secs:.2f} s); "
                        f"its k-clique listing ({res['enum_seconds']:.1f} s, c_k={res['c_k']}) excluded",
                 seconds=secs, listing_seconds=res["enum_seconds"])
 
 
-def tune_plan(plan, ws, r, T, args):
-    """Grid sizes and gather mode timed on the plan's own data (outside any
-    timed region), as the default workload runs them."""
-    if args.no_autotune or T < 8:
-        return None
-    tune = plan.autotune(ws, r, warm=3, iters=5)
-    log(f"autotune: leaf {tune.best_leaf_blocks} heavy {tune.best_heavy_blocks} gather {tune.best_gather} "
-        f"({tune.best_ms * 1000:.2f} us/iter; masked {tune.gather_ms[0] * 1000:.2f}, "
-        f"full {tune.gather_ms[1] * 1000:.2f})")
-    return tune
+def cpu_baseline_full(g, w, L, budget_s=5.0):
+    """A workload the oracle finishes in milliseconds: the whole run (listing,
+    T iterations, extraction), repeated for about budget_s seconds, on one
+    core and on all of the machine's cores."""
+    from oracle import oracle as O
+    O.build()
+    out = {}
+    for label, threads in (("single_core", 1), ("all_cores", host_cores())):
+        reps, secs = 0, 0.0
+        while secs < budget_s or reps < 3:
+            s0 = time.perf_counter()
+            O.solve(g.n, g.row_ptr, g.col, w["k"], w["T"], threads=threads)
+            secs += time.perf_counter() - s0
+            reps += 1
+        out[label] = dict(value=L * w["T"] * reps / secs, ms_per_run=1000.0 * secs / reps, cores=threads, runs=reps)
+    best = out["all_cores"]
+    return dict(value=best["value"], unit="leaf-updates/s", cores=best["cores"], kind="oracle", cpu=cpu_model(),
+                sample=f"the whole workload (listing, {w['T']} iterations, extraction), {best['runs']} runs",
+                seconds=best["ms_per_run"] / 1000.0, single_core=out["single_core"], all_cores=out["all_cores"])
 
 
 def counters_mode(w, args):
-    """A short run for rocprofv3 counter passes: the tuning of the bench run,
-    then 20 iterations of the workload (the last 20 leaf-credit dispatches),
-    then a plain 1 GiB device copy (three times) that calibrates the counters."""
+    """A short run for rocprofv3 counter passes: the bench's launch (tuning
+    cache), then 20 iterations of the workload (the last 20 leaf-credit
+    dispatches), then a plain 1 GiB device copy (three times) that calibrates
+    the byte counters."""
     import torch
     from paper_2403_05775_amd import kdss
-    g = make_graph(w)
-    tree = kdss.Tree(g, w["k"])
-    plan = kdss.Plan(tree, w["T"])
+    if w["kind"] == "batch":
+        import concurrent.futures as cf
+        count = args.batch_graphs or w["graphs"]
+        with cf.ProcessPoolExecutor(max_workers=host_cores()) as ex:
+            graphs = list(ex.map(_batch_graph, range(count), chunksize=4))
+        jobs = [(g, k) for g in graphs for k in w["ks"]]
+        with cf.ThreadPoolExecutor(max_workers=host_cores()) as ex:
+            trees = list(ex.map(lambda gk: kdss.Tree(gk[0], gk[1], threads=1), jobs))
+        plan = kdss.Batch(trees, w["T"])
+        n = plan.n
+    else:
+        g = make_graph(w)
+        plan = kdss.Plan(kdss.Tree(g, w["k"]), w["T"])
+        n = g.n
     ws = plan.alloc_workspace("cuda:0")
     plan.upload(ws)
-    r = plan.alloc_loads("cuda:0")
-    order = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
-    tune_plan(plan, ws, r, w["T"], args)
-    plan.run(ws, 20, r, order)
+    r = torch.empty(max(n, 1) * (2 if plan.width == 128 else 1), dtype=torch.int64, device="cuda:0")
+    order = torch.empty(max(n, 1), dtype=torch.int32, device="cuda:0")
+    tune_launch(plan, ws, r, w["T"], args)
+    if w["kind"] == "batch":
+        plan.run(ws, 20, r, order)
+    else:
+        plan.run(ws, 20, r, order)
     a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
     b = torch.empty_like(a)
     torch.cuda.synchronize()
@@ -513,23 +691,31 @@ def _db_rows(db):
     return per
 
 
-def summarize_counters(workload, fetch_db, write_db, command):
+def summarize_counters(workload, fetch_db, write_db, valu_db, command):
     """Per-launch HBM bytes of the leaf-credit kernel from FETCH_SIZE / WRITE_SIZE
-    runs, each divided by the factor the same counter shows for a 1 GiB copy."""
+    runs, each divided by the factor the same counter shows for a 1 GiB copy,
+    and its VALU wave-instructions (SQ_INSTS_VALU) per launch."""
     out = {"workload": workload, "kernel_sha256_16": kernel_hash(), "command": command}
-    for name, db in (("fetch", fetch_db), ("write", write_db)):
+
+    def leaf_values(db):
         per = _db_rows(db)
         # the last 20 dispatches: the run after the tuning launches
         leaf = [v for (k, d), v in sorted(per.items(), key=lambda kv: kv[0][1])
                 if "leaf_credit_kernel" in k and "KPacked" in k][-20:]
         other = [v for (k, d), v in per.items() if "anonymous namespace" not in k]
-        copy = max(other) if other else None
+        return leaf, (max(other) if other else None)
+
+    for name, db in (("fetch", fetch_db), ("write", write_db)):
+        leaf, copy = leaf_values(db)
         leaf_kib = sum(leaf) / len(leaf)
         factor = copy * 1024.0 / COPY_BYTES if copy else None
         out[name] = {"leaf_kib_per_dispatch": leaf_kib, "dispatches": len(leaf), "copy_kib": copy,
                      "copy_bytes": COPY_BYTES, "factor": factor,
                      "bytes_per_launch": leaf_kib * 1024.0 / factor if factor else None}
     out["hbm_bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    if valu_db:
+        leaf, _ = leaf_values(valu_db)
+        out["valu_insts_per_launch"] = sum(leaf) / len(leaf)
     return out
 
 
@@ -555,63 +741,60 @@ def summarize_trace(db, command):
 COPY_BYTES = 1 << 30
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="chung-lu-1m", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=20)
-    ap.add_argument("--graph", action="store_true", help="replay iterations as hipGraphs")
-    ap.add_argument("--no-autotune", action="store_true", help="default grid sizes and gather mode")
-    ap.add_argument("--mode", default="bench", choices=["bench", "counters"],
-                    help="counters: short run for rocprofv3 --pmc passes (with a copy calibration)")
-    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
-    ap.add_argument("--summarize-trace", metavar="DB")
-    ap.add_argument("--command", default="", help="command line recorded in a summary")
-    ap.add_argument("--out", default="")
-    ap.add_argument("--batch-graphs", type=int, default=0, help="graphs in the batch workload (default 512)")
-    ap.add_argument("--gnn-untrained", action="store_true", help="warm start from a randomly initialised model")
-    args = ap.parse_args()
-    if args.summarize_counters:
-        res = summarize_counters(args.workload, *args.summarize_counters, args.command)
-        with open(args.out or COUNTERS, "w") as f:
-            json.dump(res, f, indent=1)
-        print(json.dumps(res))
-        return
-    if args.summarize_trace:
-        md = summarize_trace(args.summarize_trace, args.command)
-        if args.out:
-            open(args.out, "w").write(md)
-        print(md)
-        return
-    if args.mode == "counters":
-        counters_mode(WORKLOADS[args.workload], args)
-        return
-    if WORKLOADS[args.workload]["kind"] in ("batch", "gnn", "sample", "sctbuild"):
-        if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-            sys.exit(2)
-        kind = WORKLOADS[args.workload]["kind"]
-        if kind == "batch":
-            batch_bench(WORKLOADS[args.workload], args)
-        elif kind == "sample":
-            sample_bench(WORKLOADS[args.workload], args)
-        elif kind == "sctbuild":
-            sctbuild_bench(WORKLOADS[args.workload], args)
-        else:
-            gnn_bench(WORKLOADS[args.workload], args)
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
+def tree_growth(args):
+    """Sizes of the k-pruned clique tree of R-MAT graphs (a, b, c) = (0.57, 0.19,
+    0.19), edge factor 8, seed 0, over a range of scales, counted without
+    building the tree (kdss_sct_count, host threads); a log-linear fit of leaves,
+    members and c_k per scale step extrapolates to scale 27, where the leaf
+    stream (4 B per member + 4 B per leaf, read by every iteration) is compared
+    with one GPU's 288 GB of HBM."""
+    import math
+    from paper_2403_05775_amd import kdss, synth
+    lo, hi = (int(x) for x in args.scales.split("-"))
+    rows = []
+    for sc in range(lo, hi + 1):
+        t0 = time.time()
+        g = synth.rmat(sc, 8, seed=0)
+        gen_s = time.time() - t0
+        st = kdss.tree_count(g, args.k)
+        row = dict(scale=sc, n=g.n, m=g.m, leaves=st.leaves, members=st.members, s_max=st.s_max,
+                   degeneracy=st.degeneracy, c_k=st.c_k.value, count_s=round(st.build_seconds, 2),
+                   generate_s=round(gen_s, 2))
+        rows.append(row)
+        log(json.dumps(row))
 
-    import numpy as np
+    def fit(key):
+        pts = [(r["scale"], math.log(r[key])) for r in rows if r[key] > 0][-3:]
+        xs, ys = [p[0] for p in pts], [p[1] for p in pts]
+        xm, ym = sum(xs) / len(xs), sum(ys) / len(ys)
+        b = sum((x - xm) * (y - ym) for x, y in pts) / max(1e-12, sum((x - xm) ** 2 for x in xs))
+        return math.exp(b), (lambda sc: math.exp(ym + b * (sc - xm)))
+
+    out = {"mode": "tree-growth", "k": args.k, "graph": "R-MAT (0.57, 0.19, 0.19), edge factor 8, seed 0",
+           "rows": rows, "fit_on_scales": [r["scale"] for r in rows][-3:]}
+    target = 27
+    ext = {}
+    for key in ("leaves", "members", "c_k"):
+        f, at = fit(key)
+        ext[key] = {"growth_per_scale": f, "at_scale_27": at(target)}
+    stream_bytes = 4 * ext["members"]["at_scale_27"] + 4 * ext["leaves"]["at_scale_27"]
+    out["extrapolated"] = ext
+    out["scale_27_leaf_stream_bytes"] = stream_bytes
+    out["hbm_bytes"] = 288e9
+    out["scale_27_fits_one_gpu"] = stream_bytes < 288e9
+    out["largest_scale_fitting_288GB"] = max(
+        (sc for sc in range(lo, target + 1)
+         if 4 * fit("members")[1](sc) + 4 * fit("leaves")[1](sc) < 288e9), default=None)
+    print(json.dumps(out))
+
+
+def single_bench(w, args):
+    """One plan (one graph, one k): a step is start loads + T iterations + the
+    extraction on inputs resident in HBM.  The timed steps run with
+    kernel-attached HIP events on every iteration kernel, which give the
+    per-launch durations of the roofline fields."""
     import torch
     from paper_2403_05775_amd import kdss
-
-    w = WORKLOADS[args.workload]
     t0 = time.time()
     g = make_graph(w)
     log(f"graph {g.name}: n={g.n} m={g.m} ({time.time() - t0:.1f} s)")
@@ -621,61 +804,34 @@ def main():
         f"c_k={ts.c_k.value} build={ts.build_seconds:.2f} s")
     T = w["T"]
     update = w.get("update", 0)
-    plan = kdss.Plan(tree, T, use_graph=args.graph, update=update)
+    plan = kdss.Plan(tree, T, use_graph=args.graph, time_kernels=not args.graph, update=update)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
     ws = plan.alloc_workspace(dev)
     plan.upload(ws)
     r = plan.alloc_loads(dev)
     order = torch.empty(g.n, dtype=torch.int32, device=dev)
-    tune = tune_plan(plan, ws, r, T, args)
+    tune, cached = tune_launch(plan, ws, r, T, args)
     ps = plan.stats()
-    # the same launch configuration with hipEvents around every launch
-    tplan = kdss.Plan(tree, T, time_kernels=True, gather=ps.gather, update=update)
-    if tune is not None:
-        tplan.set_launch(tune.best_leaf_blocks, tune.best_heavy_blocks)
-
     for i in range(args.warmup):
         res, _ = plan.run(ws, T, r, order)
         log(f"warmup {i + 1}/{args.warmup}: size={res.size} density={res.density:.3f}")
     torch.cuda.synchronize()
+    plan.timing(reset=True)
     t_start = time.perf_counter()
     for i in range(args.steps):
         res, _ = plan.run(ws, T, r, order)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    tm = plan.timing(reset=True)
     ms_per_step = 1000.0 * elapsed / args.steps
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; i*={res.size} "
         f"density={res.dens_num.value}/{res.size}={res.density:.4f} ub={res.upper_bound:.4f}")
-
-    # per-launch duration of the leaf-credit kernel, from hipEvents on its stream
-    ws2 = tplan.alloc_workspace(dev)
-    tplan.upload(ws2)
-    r2 = tplan.alloc_loads(dev)
-    for i in range(max(1, args.steps)):
-        tplan.run(ws2, T, r2, order)
-    tm = tplan.timing()
-    nl = max(1, tm.leaf_launches)
-    leaf_us = 1000.0 * tm.leaf_ms / nl
-    heavy_us = 1000.0 * tm.heavy_ms / nl
-    reduce_us = 1000.0 * tm.reduce_ms / nl
-    heavy_per_iter = tm.heavy_leaves / nl
-    apply_us = 1000.0 * tm.apply_ms / max(1, tm.apply_launches)
-    pass_us = leaf_us + heavy_us + (reduce_us if ps.width == 128 else 0.0)
-    del ws2
-    # algorithmic bytes of one leaf-credit launch: the leaf stream (4 B per member,
-    # 4 B per leaf header) and one 8-byte key per node
-    leaf_bytes = 4 * ts.members + 4 * ts.leaves + 8 * g.n
-    achieved = leaf_bytes / (leaf_us * 1e-6) / 1e9
-    traffic = counter_traffic(args.workload, leaf_bytes)
-    # algorithmic bytes of one step: T iterations (leaf pass + 16 B per node load
-    # update) and the extraction's second leaf-stream pass
-    step_bytes = T * (leaf_bytes + 16 * g.n) + (4 * ts.members + 4 * ts.leaves)
-    value = ts.leaves * T / (ms_per_step / 1000.0)
+    L, M, n = ts.leaves, ts.members, g.n
+    step_bytes = T * (4 * M + 4 * L + 16 * n) + (4 * M + 4 * L)
     out = {
         "metric": "SCT-leaf updates/s",
-        "value": value,
+        "value": L * T / (ms_per_step / 1000.0),
         "unit": "leaf-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -686,8 +842,8 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {g.name}, k={w['k']}, T={T}", "n": g.n, "m": g.m,
-                   "k": w["k"], "T": T, "leaves": ts.leaves, "members": ts.members, "c_k": ts.c_k.value,
+        "config": {"workload": f"{args.workload}: {g.name}, k={w['k']}, T={T}", "n": n, "m": g.m,
+                   "k": w["k"], "T": T, "leaves": L, "members": M, "c_k": ts.c_k.value,
                    "parallelism": "single GPU", "hip_graph": bool(args.graph),
                    "gather": "masked" if ps.gather == 1 else "full", "hot_share": round(ps.hot_share, 4),
                    "update": "PBUpdate (synchronous)" if update else "Frank-Wolfe"},
@@ -699,34 +855,89 @@ def main():
                              "kind": "top-s" if res.bound_kind == 1 else "max load",
                              "certified_optimal": bool(res.certified),
                              "gap": (res.bound - res.density) / res.bound if res.bound else 0.0}},
-        # with 64-bit loads the hot-node reduction is part of the load update
-        "kernel_us": {"leaf_credit": leaf_us, "heavy_leaf": heavy_us,
-                      "hot_reduce": reduce_us if ps.width == 128 else None, "apply": apply_us},
-        "heavy_leaves_per_iteration": heavy_per_iter,
-        # leaves, members and lane tiles per size class s = h + p
-        "size_classes": {name: {"leaves": int(ps.leaves[c]), "members": int(ps.members[c]), "tiles": int(ps.tiles[c])}
-                         for c, name in enumerate(("s<=8", "s<=16", "s<=32", "s<=64", "s>64"))},
-        "launch": ({"leaf_blocks": tune.best_leaf_blocks, "heavy_blocks": tune.best_heavy_blocks,
-                    "gather": tune.best_gather, "us_per_iter": tune.best_ms * 1000,
-                    "gather_us": {"masked": tune.gather_ms[0] * 1000, "full": tune.gather_ms[1] * 1000}}
-                   if tune is not None else "defaults"),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "pb_kernel" if update else "leaf_credit_kernel<KPacked>",
-                     "bytes_per_launch": leaf_bytes},
-        "credit_pass": {"kernels": "leaf_credit + heavy_leaf" + (" + hot_reduce" if ps.width == 128 else ""),
-                        "us": pass_us,
-                        "achieved": leaf_bytes / (pass_us * 1e-6) / 1e9,
-                        "frac": leaf_bytes / (pass_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
+        "size_classes": size_classes(ps),
+        "launch": launch_fields(tune, cached),
         "cpu_baseline": None,
     }
+    if not args.graph:
+        if kernel_time_sum(tm) > elapsed * 1000.0 * 1.001:
+            raise SystemExit("kernel durations exceed the timed region")
+        rf = rooflines(tm, L, M, n, ps.width)
+        kname = "pb_kernel" if update else "leaf_credit_kernel<KPacked>"
+        out.update(roofline_fields(rf, kname, args.workload, args.workload))
+        out["kernel_ms_per_step"] = kernel_time_sum(tm) / args.steps
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         if update:
-            out["cpu_baseline"] = cpu_baseline_pb(g, w, tree, ts.leaves, w.get("cpu_iters", args.cpu_sample_iters))
+            out["cpu_baseline"] = cpu_baseline_pb(g, w, tree, L, w.get("cpu_iters", args.cpu_sample_iters))
+        elif w.get("cpu_full"):
+            out["cpu_baseline"] = cpu_baseline_full(g, w, L)
         else:
-            out["cpu_baseline"] = cpu_baseline(g, w, ts.leaves, w.get("cpu_iters", args.cpu_sample_iters))
+            out["cpu_baseline"] = cpu_baseline(g, w, L, w.get("cpu_iters", args.cpu_sample_iters))
     print(json.dumps(out))
+
+
+def kernel_time_sum(tm):
+    return tm.leaf_ms + tm.heavy_ms + tm.reduce_ms + tm.apply_ms
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batch-512", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=20)
+    ap.add_argument("--graph", action="store_true", help="replay iterations as hipGraphs (no kernel timing)")
+    ap.add_argument("--no-autotune", action="store_true", help="default grid sizes and gather mode")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2403_05775_amd", "tune_cache.txt"),
+                    help="tuning cache file ('' to tune without one)")
+    ap.add_argument("--scales", default="12-20", help="tree-growth mode: R-MAT scales lo-hi")
+    ap.add_argument("--k", type=int, default=6, help="tree-growth mode: clique size")
+    ap.add_argument("--mode", default="bench", choices=["bench", "counters", "tree-growth"],
+                    help="counters: short run for rocprofv3 --pmc passes (with a copy calibration)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "VALU_DB"))
+    ap.add_argument("--summarize-trace", metavar="DB")
+    ap.add_argument("--command", default="", help="command line recorded in a summary")
+    ap.add_argument("--out", default="")
+    ap.add_argument("--batch-graphs", type=int, default=0, help="graphs in the batch workload (default 512)")
+    ap.add_argument("--gnn-untrained", action="store_true", help="warm start from a randomly initialised model")
+    args = ap.parse_args()
+    if args.summarize_counters:
+        res = summarize_counters(args.workload, *args.summarize_counters, args.command)
+        with open(args.out or counters_file(args.workload), "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res))
+        return
+    if args.summarize_trace:
+        md = summarize_trace(args.summarize_trace, args.command)
+        if args.out:
+            open(args.out, "w").write(md)
+        print(md)
+        return
+    if args.mode == "tree-growth":
+        tree_growth(args)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+    w = WORKLOADS[args.workload]
+    if args.mode == "counters":
+        counters_mode(w, args)
+        return
+    kind = w["kind"]
+    if kind == "batch":
+        batch_bench(w, args)
+    elif kind == "sample":
+        sample_bench(w, args)
+    elif kind == "sctbuild":
+        sctbuild_bench(w, args)
+    elif kind == "gnn":
+        gnn_bench(w, args)
+    else:
+        single_bench(w, args)
 
 
 if __name__ == "__main__":

@@ -206,6 +206,14 @@ int kdss_sct_build_gpu(const kdss_csr *g, uint32_t k, void *stream, kdss_sct **o
 
 int kdss_sct_info(const kdss_sct *s, kdss_tree_stats *out);
 
+/* Sizes the k-pruned tree of g before (or instead of) building it: the same
+ * search as kdss_sct_build (Sec. 2 "Succinct Clique Tree", Lemmas 3-5, the
+ * same leaves), keeping only the counts.  out (host) receives k, n, the kept
+ * leaves |P_k|, their members, s_max, the degeneracy, c_k = |C_k(V)| (Lemma
+ * 5) and the seconds taken (build_seconds).  Host memory stays O(n + m)
+ * whatever the tree's size.  Errors as kdss_sct_build. */
+int kdss_sct_count(const kdss_csr *g, uint32_t k, uint32_t threads, kdss_tree_stats *out);
+
 /* Copies the kept leaves to host arrays: h[i], p[i] per leaf and the members
  * (leaf by leaf, its h hold nodes first, then its p pivot nodes).
  * KDSS_ERANGE if a capacity is too small. */
@@ -388,6 +396,23 @@ int kdss_plan_set_launch(kdss_plan *p, uint32_t leaf_blocks, uint32_t heavy_bloc
  * warm + iters must not exceed T_max.  Synchronises the stream. */
 int kdss_plan_autotune(kdss_plan *p, void *d_ws, size_t ws_bytes, uint64_t *d_r, uint32_t warm, uint32_t iters,
                        kdss_tune_result *out, void *stream);
+
+/* The key under which kdss_plan_autotune_cached files a plan's tuning (host
+ * string, NUL-terminated, into buf[cap]): the current device's architecture,
+ * the kernel variant (load width, key mode, update, gather option), the
+ * problems' clique sizes, and half-octave buckets of the problem count, node
+ * count and leaves per size class.  KDSS_ERANGE if cap is too small. */
+int kdss_plan_tune_key(const kdss_plan *p, char *buf, size_t cap);
+
+/* kdss_plan_autotune through a tuning cache: a text file (cache_path, host)
+ * of lines "key leaf_blocks heavy_blocks gather ms".  When the file holds the
+ * plan's key (the last such line wins) its launch is applied without timing
+ * anything (*from_cache = 1; out carries only the best_* fields); otherwise the
+ * plan is tuned as by kdss_plan_autotune and a line is appended (*from_cache =
+ * 0).  Errors as kdss_plan_autotune. */
+int kdss_plan_autotune_cached(kdss_plan *p, void *d_ws, size_t ws_bytes, uint64_t *d_r, uint32_t warm,
+                              uint32_t iters, const char *cache_path, int *from_cache, kdss_tune_result *out,
+                              void *stream);
 
 /* ---- batches: many problems (graph, k) in one launch per iteration ----
  * (each problem is exactly the problem of

@@ -113,6 +113,15 @@ int kdss_sct_build(const kdss_csr* g, uint32_t k, uint32_t threads, kdss_sct** o
   return KDSS_OK;
 }
 
+int kdss_sct_count(const kdss_csr* g, uint32_t k, uint32_t threads, kdss_tree_stats* out) {
+  if (!out) return fail(KDSS_EINVAL, "null output");
+  try {
+    return count_sct(g, k, threads, out);
+  } catch (const std::bad_alloc&) {
+    return fail(KDSS_ENOMEM, "host memory exhausted while counting the clique tree");
+  }
+}
+
 int kdss_sct_info(const kdss_sct* s, kdss_tree_stats* out) {
   if (!s || !out) return fail(KDSS_EINVAL, "null argument");
   std::memset(out, 0, sizeof(*out));

@@ -72,6 +72,9 @@ struct Sct {
 };
 
 int build_sct(const kdss_csr* g, uint32_t k, uint32_t threads, Sct* out);
+// The same search, keeping only the counts (leaves, members, s_max, c_k).
+int count_sct(const kdss_csr* g, uint32_t k, uint32_t threads, kdss_tree_stats* stats);
+int build_sct_impl(const kdss_csr* g, uint32_t k, uint32_t threads, Sct* out, kdss_tree_stats* stats);
 
 // Binomial coefficient C(a, b) in 128 bits, saturating at 2^128 - 1.
 u128 binom128(uint64_t a, uint64_t b);
@@ -216,5 +219,6 @@ struct kdss_plan {
   void* graph_r = nullptr;
   void* capture_stream = nullptr;
   std::vector<void*> events;           // hipEvent_t pool for kernel timing
+  std::vector<uint32_t> ev_used;       // per iteration: which kernels stamped their events
   kdss_timing timing{};
 };

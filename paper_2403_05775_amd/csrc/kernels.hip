@@ -1,9 +1,14 @@
 // Device side of kdss for gfx950 (CDNA4, 64-lane wavefronts): the leaf-credit
 // pass, the load update, and the extraction (radix sort, prefix clique counts,
 // exact best-prefix search), plus the C-ABI entry points that launch them.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 
 #include "kdss_internal.h"
 
@@ -1661,14 +1666,6 @@ uint32_t grid_for(size_t n, uint32_t threads = 256, uint32_t cap = 16384) {
   return (uint32_t)b;
 }
 
-// r_t = r_{t-1} + delta: the pair kernel when the caller's loads are 16-byte aligned.
-void launch_apply64(uint64_t* r, uint64_t* delta, uint32_t n, hipStream_t st) {
-  if ((reinterpret_cast<uintptr_t>(r) & 15u) == 0)
-    apply64_pairs_kernel<<<grid_for(n / 2 + 1), 256, 0, st>>>(r, delta, n);
-  else
-    apply64_kernel<<<grid_for(n), 256, 0, st>>>(r, delta, n);
-}
-
 uint32_t bit_length128(u128 x) {
   uint32_t b = 0;
   while (x) { ++b; x >>= 1; }
@@ -1681,14 +1678,31 @@ struct WsView {
   T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 
+// Timed launches: kernel-attached events.  ev[0] and ev[1] receive the
+// kernel's own start and end (the dispatch's timestamps, hipExtLaunchKernel),
+// so no marker packet sits between kernels and the elapsed time is the
+// kernel's execution alone.  Without events: a plain launch.
+template <typename... Formals, typename... Actuals>
+void launch_timed(void (*k)(Formals...), uint32_t grid, uint32_t block, uint32_t shm, hipStream_t st,
+                  hipEvent_t* ev, Actuals... a) {
+  if (ev)
+    hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, ev[0], ev[1], 0u, a...);
+  else
+    hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, a...);
+}
+
+// Per-iteration event slots of a timed run (start, end of each kernel).
+constexpr int kEvLeaf = 0, kEvHeavy = 2, kEvReduce = 4, kEvApply = 6, kEvPerIter = 8;
+
 // mode: 0 packed FW keys, 1 full u64 loads, 2 full u128 loads, 3 extraction ranks
-// ev (nullable): four events recorded before the leaf kernel, after it, after
-// the heavy-leaf kernel and after the hot-node reduction.
+// ev (nullable): the iteration's kEvPerIter events; the leaf-credit, heavy-leaf
+// and hot-node reduction kernels stamp their slots; used (when ev is given)
+// receives a bit per slot pair that ran.
 // hot_published: the hot keys at these loads are in the load update's table
 // (64-bit Frank-Wolfe passes); otherwise every workgroup computes them.
 int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& src, uint64_t* out,
                 hipStream_t st, hipEvent_t* ev = nullptr, uint32_t* qlog = nullptr, bool reduce_hot = true,
-                bool hot_published = false) {
+                bool hot_published = false, uint32_t* used = nullptr) {
   const uint32_t ntiles = (uint32_t)P->tiles.size();
   if (ntiles == 0) return KDSS_OK;
   const uint32_t blocks = P->leaf_blocks;
@@ -1704,19 +1718,20 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   uint32_t* qcount = ws.at<uint32_t>(P->off_qcount);
   const uint32_t nbinom = (uint32_t)P->binom.size();
   const size_t table_off = hot_published ? P->off_hotkey_fw : P->off_hotkey;
-  if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
+  hipEvent_t* ev_leaf = ev ? ev + kEvLeaf : nullptr;
+  hipEvent_t* ev_heavy = ev ? ev + kEvHeavy : nullptr;
 #define KDSS_LEAF(KT)                                                                                           \
   if (P->gather == 2)                                                                                            \
-    leaf_credit_kernel<KT, false><<<blocks, kLeafThreads, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src, \
-                                                          out, hot, hot_base, nhot, scratch, queue, qcount,      \
-                                                          ws.at<KT>(table_off), hot_published);                  \
+    launch_timed(leaf_credit_kernel<KT, false>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members,   \
+                 hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,              \
+                 ws.at<KT>(table_off), hot_published);                                                          \
   else                                                                                                           \
-    leaf_credit_kernel<KT, true><<<blocks, kLeafThreads, 0, st>>>(tiles, ntiles, members, hdr, binom, nbinom, P->k1, src,  \
-                                                         out, hot, hot_base, nhot, scratch, queue, qcount,       \
-                                                         ws.at<KT>(table_off), hot_published);                   \
-  if (ev) HIP_TRY(hipEventRecord(ev[1], st), "event record");                                                    \
-  heavy_kernel<KT><<<P->heavy_blocks, 256, 0, st>>>(members, binom, P->k1, src, out, nhot, scratch, queue,      \
-                                                    qcount, ws.at<KT>(table_off), nbinom)
+    launch_timed(leaf_credit_kernel<KT, true>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members,    \
+                 hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,              \
+                 ws.at<KT>(table_off), hot_published);                                                          \
+  launch_timed(heavy_kernel<KT>, P->heavy_blocks, 256, 0, st, ev_heavy, members, binom, P->k1, src, out, nhot,  \
+               scratch, (const uint4*)queue, (const uint32_t*)qcount, (const KT*)ws.at<KT>(table_off), nbinom)
+  if (used) *used |= 1u | 2u;
   switch (mode) {
     case 0: KDSS_LEAF(KPacked); break;
     case 1: KDSS_LEAF(KFull); break;
@@ -1727,12 +1742,12 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   HIP_TRY(hipGetLastError(), "leaf credit launch");
   // hot-node totals over the slot entries (cleared again); also empties the queue
   const uint32_t grid = std::max(1u, (nhot + 3) / 4);   // a wavefront per hot node; block 0 empties the queue
-  if (ev) HIP_TRY(hipEventRecord(ev[2], st), "event record");
   if (reduce_hot) {
-    hot_reduce_kernel<<<grid, 256, 0, st>>>(scratch, hot, nhot, out, qcount, qlog);
+    launch_timed(hot_reduce_kernel, grid, 256, 0, st, ev ? ev + kEvReduce : nullptr, scratch, hot, nhot, out,
+                 qcount, qlog);
     HIP_TRY(hipGetLastError(), "hot reduce launch");
+    if (used) *used |= 4u;
   }
-  if (ev) HIP_TRY(hipEventRecord(ev[3], st), "event record");
   return KDSS_OK;
 }
 
@@ -1742,9 +1757,8 @@ int fw_mode(const kdss_plan* P) { return P->width == 128 ? 2 : (P->key_mode == 0
 // totals go to the slot entries that the load update sums.  Events as for the
 // leaf-credit pass (the last three mark its end).
 int launch_pb(const kdss_plan* P, const WsView& ws, const void* d_r, uint64_t* out, hipStream_t st,
-              hipEvent_t* ev) {
+              hipEvent_t* ev, uint32_t* used) {
   const uint32_t ntiles = (uint32_t)P->tiles.size();
-  if (ev) HIP_TRY(hipEventRecord(ev[0], st), "event record");
   const uint32_t split = P->pb_split, nhot = (uint32_t)P->hot.size();
   // big leaves and lane tiles of more than kPbRegRows rows, staged in LDS, in
   // one launch: one workgroup per tile of more than kPbMidRows rows, then
@@ -1753,22 +1767,24 @@ int launch_pb(const kdss_plan* P, const WsView& ws, const void* d_r, uint64_t* o
     const uint32_t nbig = P->pb_mid, nmid = split - nbig;
     const uint32_t mid_blocks = nmid ? std::min<uint32_t>((nmid + 3) / 4, P->leaf_blocks) : 0u;
     const size_t rows = std::max<size_t>((size_t)4 * P->pb_rows_lo, nbig ? P->pb_rows : 0);
-    pb_kernel<<<nbig + mid_blocks, 256, rows * 64 * 8, st>>>(
-        ws.at<Tile>(P->off_tiles), nbig, split, ws.at<uint32_t>(P->off_members), ws.at<uint32_t>(P->off_hdr),
-        ws.at<uint64_t>(P->off_binom), P->k1, static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot), nhot,
-        out, ws.at<uint64_t>(P->off_scratch), P->pb_rows_lo);
+    launch_timed(pb_kernel, nbig + mid_blocks, 256, (uint32_t)(rows * 64 * 8), st, ev ? ev + kEvLeaf : nullptr,
+                 (const Tile*)ws.at<Tile>(P->off_tiles), nbig, split, (const uint32_t*)ws.at<uint32_t>(P->off_members),
+                 (const uint32_t*)ws.at<uint32_t>(P->off_hdr), (const uint64_t*)ws.at<uint64_t>(P->off_binom), P->k1,
+                 static_cast<const uint64_t*>(d_r), (const uint32_t*)ws.at<uint32_t>(P->off_hot), nhot, out,
+                 ws.at<uint64_t>(P->off_scratch), P->pb_rows_lo);
     HIP_TRY(hipGetLastError(), "PBUpdate launch");
+    if (used) *used |= 1u;
   }
   if (split < ntiles) {   // the other lane tiles, from registers
     const uint32_t blocks = std::min<uint32_t>((ntiles - split + 3) / 4, P->leaf_blocks);
-    pb_reg_kernel<<<blocks, 256, 0, st>>>(ws.at<Tile>(P->off_tiles), split, ntiles, ws.at<uint32_t>(P->off_members),
-                                          ws.at<uint32_t>(P->off_hdr), ws.at<uint64_t>(P->off_binom), P->k1,
-                                          static_cast<const uint64_t*>(d_r), ws.at<uint32_t>(P->off_hot), nhot, out,
-                                          ws.at<uint64_t>(P->off_scratch));
+    launch_timed(pb_reg_kernel, blocks, 256, 0, st, ev ? ev + kEvHeavy : nullptr,
+                 (const Tile*)ws.at<Tile>(P->off_tiles), split, ntiles, (const uint32_t*)ws.at<uint32_t>(P->off_members),
+                 (const uint32_t*)ws.at<uint32_t>(P->off_hdr), (const uint64_t*)ws.at<uint64_t>(P->off_binom), P->k1,
+                 static_cast<const uint64_t*>(d_r), (const uint32_t*)ws.at<uint32_t>(P->off_hot), nhot, out,
+                 ws.at<uint64_t>(P->off_scratch));
     HIP_TRY(hipGetLastError(), "PBUpdate launch");
+    if (used) *used |= 2u;
   }
-  if (ev)
-    for (int i = 1; i < 4; ++i) HIP_TRY(hipEventRecord(ev[i], st), "event record");
   return KDSS_OK;
 }
 
@@ -1786,26 +1802,31 @@ KeySrc fw_src(const kdss_plan* P, const WsView& ws, const void* d_r) {
 // fill -- then r_t = r_{t-1} + delta.  With 64-bit loads the hot-node
 // reduction is part of the update kernel.
 int launch_fw_step(const kdss_plan* P, const WsView& ws, void* d_r, hipStream_t st, hipEvent_t* ev,
-                   uint32_t* qlog) {
+                   uint32_t* qlog, uint32_t* used = nullptr) {
   uint64_t* delta = ws.at<uint64_t>(P->off_delta);
   const bool fused = P->width == 64 && !P->tiles.empty();
-  int rc = P->opts.update == 1 ? launch_pb(P, ws, d_r, delta, st, ev)
-                               : launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev, qlog, !fused, fused);
+  int rc = P->opts.update == 1
+               ? launch_pb(P, ws, d_r, delta, st, ev, used)
+               : launch_leaf(P, ws, fw_mode(P), fw_src(P, ws, d_r), delta, st, ev, qlog, !fused, fused, used);
   if (rc) return rc;
+  hipEvent_t* ev_apply = ev ? ev + kEvApply : nullptr;
+  uint64_t* r = static_cast<uint64_t*>(d_r);
   if (P->width == 128) {
-    apply128_kernel<<<grid_for(P->n), 256, 0, st>>>(static_cast<uint64_t*>(d_r), delta, P->n);
+    launch_timed(apply128_kernel, grid_for(P->n), 256, 0, st, ev_apply, r, delta, P->n);
   } else if (fused) {
     const uint32_t nhot = (uint32_t)P->hot.size();
     const uint32_t hot_blocks = std::max(1u, (nhot + 3) / 4);   // block 0 also empties the queue
-    apply64_hot_kernel<<<hot_blocks + grid_for(P->n / 2 + 1), 256, 0, st>>>(
-        static_cast<uint64_t*>(d_r), delta, P->n, ws.at<uint64_t>(P->off_scratch), ws.at<uint32_t>(P->off_hot),
-        ws.at<uint32_t>(P->off_hot_base), nhot, hot_blocks, ws.at<uint32_t>(P->off_qcount), qlog, P->key_mode,
-        P->id_bits, ws.at<uint64_t>(P->off_hotkey_fw));
+    launch_timed(apply64_hot_kernel, hot_blocks + grid_for(P->n / 2 + 1), 256, 0, st, ev_apply, r, delta, P->n,
+                 ws.at<uint64_t>(P->off_scratch), (const uint32_t*)ws.at<uint32_t>(P->off_hot),
+                 (const uint32_t*)ws.at<uint32_t>(P->off_hot_base), nhot, hot_blocks, ws.at<uint32_t>(P->off_qcount),
+                 qlog, P->key_mode, P->id_bits, ws.at<uint64_t>(P->off_hotkey_fw));
+  } else if ((reinterpret_cast<uintptr_t>(r) & 15u) == 0) {
+    launch_timed(apply64_pairs_kernel, grid_for(P->n / 2 + 1), 256, 0, st, ev_apply, r, delta, P->n);
   } else {
-    launch_apply64(static_cast<uint64_t*>(d_r), delta, P->n, st);
+    launch_timed(apply64_kernel, grid_for(P->n), 256, 0, st, ev_apply, r, delta, P->n);
   }
   HIP_TRY(hipGetLastError(), "apply launch");
-  if (ev) HIP_TRY(hipEventRecord(ev[4], st), "event record");
+  if (used) *used |= 8u;
   return KDSS_OK;
 }
 
@@ -2150,7 +2171,8 @@ int start_run(kdss_plan* P, const WsView& ws, const uint64_t* d_r0, void* d_r, u
     HIP_TRY(hipGetLastError(), "hot keys launch");
   }
   if (P->opts.time_kernels) {
-    while (P->events.size() < 5ull * T) {
+    P->ev_used.assign(T, 0u);
+    while (P->events.size() < (size_t)kEvPerIter * T) {
       hipEvent_t e;
       HIP_TRY(hipEventCreate(&e), "event create");
       P->events.push_back(e);
@@ -2162,8 +2184,8 @@ int start_run(kdss_plan* P, const WsView& ws, const uint64_t* d_r0, void* d_r, u
 // Iteration t (1-based): timed launches, a graph replay, or plain launches.
 int iterate(kdss_plan* P, const WsView& ws, void* d_r, uint32_t t, hipStream_t st) {
   if (P->opts.time_kernels) {
-    hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data()) + 5ull * (t - 1);
-    return launch_fw_step(P, ws, d_r, st, ev, ws.at<uint32_t>(P->off_qlog) + (t - 1));
+    hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data()) + (size_t)kEvPerIter * (t - 1);
+    return launch_fw_step(P, ws, d_r, st, ev, ws.at<uint32_t>(P->off_qlog) + (t - 1), &P->ev_used[t - 1]);
   }
   if (P->opts.use_graph) {
     int rc = ensure_graph(P, ws, d_r);
@@ -2181,19 +2203,18 @@ int collect_timing(kdss_plan* P, const WsView& ws, uint32_t T) {
   HIP_TRY(hipMemcpy(q.data(), ws.at<uint32_t>(P->off_qlog), (size_t)T * 4, hipMemcpyDeviceToHost), "queue log");
   for (uint32_t v : q) P->timing.heavy_leaves += v;
   hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data());
-  for (uint32_t t = 0; t < T; ++t) {
-    float a = 0.f, b = 0.f, c = 0.f, d = 0.f;
-    HIP_TRY(hipEventElapsedTime(&a, ev[5 * t], ev[5 * t + 1]), "event elapsed");
-    HIP_TRY(hipEventElapsedTime(&b, ev[5 * t + 1], ev[5 * t + 2]), "event elapsed");
-    HIP_TRY(hipEventElapsedTime(&c, ev[5 * t + 2], ev[5 * t + 3]), "event elapsed");
-    HIP_TRY(hipEventElapsedTime(&d, ev[5 * t + 3], ev[5 * t + 4]), "event elapsed");
-    P->timing.leaf_ms += a;
-    P->timing.heavy_ms += b;
-    P->timing.reduce_ms += c;
-    P->timing.apply_ms += d;
+  double* dst[4] = {&P->timing.leaf_ms, &P->timing.heavy_ms, &P->timing.reduce_ms, &P->timing.apply_ms};
+  for (uint32_t t = 0; t < T && t < P->ev_used.size(); ++t) {
+    for (int q = 0; q < 4; ++q) {
+      if (!(P->ev_used[t] & (1u << q))) continue;
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ev[(size_t)kEvPerIter * t + 2 * q], ev[(size_t)kEvPerIter * t + 2 * q + 1]),
+              "event elapsed");
+      *dst[q] += ms;
+    }
+    if (P->ev_used[t] & 1u) P->timing.leaf_launches += 1;
+    if (P->ev_used[t] & 8u) P->timing.apply_launches += 1;
   }
-  P->timing.leaf_launches += T;
-  P->timing.apply_launches += T;
   return KDSS_OK;
 }
 
@@ -2519,6 +2540,76 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
   P->leaf_blocks = out->best_leaf_blocks;
   P->heavy_blocks = out->best_heavy_blocks;
   drop_graph(P);
+  return KDSS_OK;
+}
+
+int kdss_plan_tune_key(const kdss_plan* P, char* buf, size_t cap) {
+  if (!P || !buf || cap == 0) return fail(KDSS_EINVAL, "null argument");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  // what the best launch depends on: the device, the kernel variant (load
+  // width, key mode, update, gather option), the clique sizes, and the shape
+  // of the work: leaves per size class and nodes in half-octave buckets
+  auto bucket = [](double x) { return x < 1 ? 0 : (int)std::lround(2.0 * std::log2(x)); };
+  std::vector<uint32_t> ks(P->prob_k.begin(), P->prob_k.end());
+  std::sort(ks.begin(), ks.end());
+  ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+  std::string key = arch + "|w" + std::to_string(P->width) + "|km" + std::to_string(P->key_mode) + "|u" +
+                    std::to_string(P->opts.update) + "|g" + std::to_string(P->opts.gather) + "|k";
+  for (size_t i = 0; i < ks.size(); ++i) key += (i ? "," : "") + std::to_string(ks[i]);
+  key += "|q" + std::to_string(bucket((double)(P->node_off.size() - 1))) + "|n" + std::to_string(bucket(P->n)) +
+         "|L";
+  for (int c = 0; c < kNumClasses; ++c) key += (c ? "," : "") + std::to_string(bucket((double)P->class_leaves[c]));
+  if (key.size() + 1 > cap) return fail(KDSS_ERANGE, "key buffer too small");
+  std::memcpy(buf, key.c_str(), key.size() + 1);
+  return KDSS_OK;
+}
+
+int kdss_plan_autotune_cached(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r, uint32_t warm,
+                              uint32_t iters, const char* cache_path, int* from_cache, kdss_tune_result* out,
+                              void* stream) {
+  if (!P || !d_r || !out || !cache_path || !from_cache) return fail(KDSS_EINVAL, "null argument");
+  *from_cache = 0;
+  char key[512];
+  int rc = kdss_plan_tune_key(P, key, sizeof(key));
+  if (rc) return rc;
+  if (FILE* f = std::fopen(cache_path, "r")) {
+    char line[1024];
+    while (std::fgets(line, sizeof(line), f)) {
+      char k2[512];
+      unsigned lb = 0, hb = 0;
+      int g = 0;
+      double ms = 0.0;
+      if (std::sscanf(line, "%511s %u %u %d %lf", k2, &lb, &hb, &g, &ms) == 5 && std::strcmp(k2, key) == 0 &&
+          lb >= 1 && lb <= kLeafBlocksMax && hb >= 1 && hb <= kHeavyBlocks && (g == 1 || g == 2)) {
+        std::memset(out, 0, sizeof(*out));
+        out->best_leaf_blocks = lb;
+        out->best_heavy_blocks = hb;
+        out->best_gather = g;
+        out->best_ms = ms;
+        *from_cache = 1;
+      }
+    }
+    std::fclose(f);
+  }
+  if (*from_cache) {
+    P->leaf_blocks = out->best_leaf_blocks;
+    P->heavy_blocks = out->best_heavy_blocks;
+    P->gather = out->best_gather;
+    drop_graph(P);
+    return KDSS_OK;
+  }
+  rc = kdss_plan_autotune(P, d_ws, ws_bytes, d_r, warm, iters, out, stream);
+  if (rc) return rc;
+  if (FILE* f = std::fopen(cache_path, "a")) {
+    std::fprintf(f, "%s %u %u %d %.6f\n", key, out->best_leaf_blocks, out->best_heavy_blocks, out->best_gather,
+                 out->best_ms);
+    std::fclose(f);
+  }
   return KDSS_OK;
 }
 

@@ -141,6 +141,9 @@ struct LeafBuf {
   std::vector<uint32_t> p;
   u128 c_k = 0;
   uint32_t s_max = 0;
+  bool count_only = false;      // keep only the counts below, not the leaves
+  bool ck_wrapped = false;      // c_k passed 2^128 - 1
+  uint64_t leaves = 0, nmembers = 0;
 };
 
 // Per-thread search state for the subtree of one root.
@@ -196,6 +199,15 @@ class RootSearch {
   void emit(bool drop_pivots) {
     const uint32_t h = (uint32_t)H_.size();
     const uint32_t p = drop_pivots ? 0 : (uint32_t)P_.size();
+    if (out_->count_only) {
+      const u128 before = out_->c_k;
+      out_->c_k += binom_[(size_t)p * (k_ + 1) + (k_ - h)];
+      if (out_->c_k < before) out_->ck_wrapped = true;
+      out_->leaves += 1;
+      out_->nmembers += h + p;
+      out_->s_max = std::max(out_->s_max, h + p);
+      return;
+    }
     out_->members.insert(out_->members.end(), H_.begin(), H_.end());
     for (uint32_t i = 0; i < p; ++i) out_->members.push_back(nodes_[P_[i]]);
     out_->h.push_back((uint8_t)h);
@@ -296,6 +308,17 @@ class RootSearch {
 }  // namespace
 
 int build_sct(const kdss_csr* g, uint32_t k, uint32_t threads, Sct* out) {
+  return build_sct_impl(g, k, threads, out, nullptr);
+}
+
+int count_sct(const kdss_csr* g, uint32_t k, uint32_t threads, kdss_tree_stats* stats) {
+  Sct tmp;
+  return build_sct_impl(g, k, threads, &tmp, stats);
+}
+
+// With stats != nullptr only the counts are kept (out receives the degeneracy
+// order and nothing else).
+int build_sct_impl(const kdss_csr* g, uint32_t k, uint32_t threads, Sct* out, kdss_tree_stats* stats) {
   auto t0 = std::chrono::steady_clock::now();
   if (!g || !out) return fail(KDSS_EINVAL, "null argument");
   if (k < 2) return fail(KDSS_EINVAL, "k must be at least 2");
@@ -333,6 +356,7 @@ int build_sct(const kdss_csr* g, uint32_t k, uint32_t threads, Sct* out) {
   const uint32_t chunk = 256;
   const uint32_t nchunks = (n + chunk - 1) / chunk;
   std::vector<LeafBuf> bufs(nchunks);
+  for (auto& b : bufs) b.count_only = stats != nullptr;
   std::atomic<uint32_t> next{0};
   std::atomic<bool> oom{false};
   auto worker = [&]() {
@@ -352,6 +376,26 @@ int build_sct(const kdss_csr* g, uint32_t k, uint32_t threads, Sct* out) {
   for (unsigned t = 0; t < nt; ++t) pool.emplace_back(worker);
   for (auto& t : pool) t.join();
   if (oom) return fail(KDSS_ENOMEM, "host memory exhausted while building the clique tree");
+
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    u128 ck = 0;
+    for (auto& b : bufs) {
+      const u128 before = ck;
+      ck += b.c_k;
+      if (b.ck_wrapped || ck < before) return fail(KDSS_EOVERFLOW, "k-clique count exceeds 2^128");
+      stats->leaves += b.leaves;
+      stats->members += b.nmembers;
+      stats->s_max = std::max(stats->s_max, b.s_max);
+    }
+    stats->k = k;
+    stats->n = n;
+    stats->degeneracy = out->deg.degeneracy;
+    stats->c_k.lo = (uint64_t)ck;
+    stats->c_k.hi = (uint64_t)(ck >> 64);
+    stats->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return KDSS_OK;
+  }
 
   uint64_t L = 0, M = 0;
   for (auto& b : bufs) { L += b.h.size(); M += b.members.size(); }

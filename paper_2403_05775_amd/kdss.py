@@ -90,8 +90,11 @@ EXPORTS = [
     "kdss_plan_free", "kdss_plan_upload", "kdss_run", "kdss_leaf_credit", "kdss_extract", "kdss_plan_timing",
     "kdss_batch_create", "kdss_batch_offsets", "kdss_batch_run", "kdss_plan_set_launch", "kdss_plan_autotune",
     "kdss_sample_build", "kdss_sct_build_gpu", "kdss_workspace_size", "kdss_solve", "kdss_run_resume",
-    "kdss_extract_counts", "kdss_batch_free", "kdss_run_static",
+    "kdss_extract_counts", "kdss_batch_free", "kdss_run_static", "kdss_sct_count", "kdss_plan_tune_key",
+    "kdss_plan_autotune_cached",
 ]
+
+TUNE_CACHE = os.path.join(_HERE, "tune_cache.txt")   # launches tuned on MI355X, keyed by plan shape
 
 STATIC_WORKSPACE_BYTES = 64 << 20   # KDSS_STATIC_WORKSPACE_BYTES
 
@@ -117,6 +120,7 @@ def lib():
     L.kdss_csr_validate.argtypes = [C.POINTER(Csr)]
     L.kdss_sct_build.argtypes = [C.POINTER(Csr), C.c_uint32, C.c_uint32, C.POINTER(vp)]
     L.kdss_sct_info.argtypes = [vp, C.POINTER(TreeStats)]
+    L.kdss_sct_count.argtypes = [C.POINTER(Csr), C.c_uint32, C.c_uint32, C.POINTER(TreeStats)]
     L.kdss_sct_export.argtypes = [vp, p32, p32, p32, C.c_uint64, C.c_uint64]
     L.kdss_sct_core_numbers.argtypes = [vp, p32, C.c_uint32]
     L.kdss_sct_free.argtypes = [vp]
@@ -139,6 +143,9 @@ def lib():
     L.kdss_batch_run.argtypes = [vp, vp, C.c_size_t, C.c_uint32, vp, vp, vp, C.POINTER(Result), C.c_uint32, vp]
     L.kdss_plan_set_launch.argtypes = [vp, C.c_uint32, C.c_uint32]
     L.kdss_plan_autotune.argtypes = [vp, vp, C.c_size_t, vp, C.c_uint32, C.c_uint32, C.POINTER(TuneResult), vp]
+    L.kdss_plan_tune_key.argtypes = [vp, C.c_char_p, C.c_size_t]
+    L.kdss_plan_autotune_cached.argtypes = [vp, vp, C.c_size_t, vp, C.c_uint32, C.c_uint32, C.c_char_p,
+                                            C.POINTER(C.c_int), C.POINTER(TuneResult), vp]
     L.kdss_extract.argtypes = [vp, vp, C.c_size_t, vp, vp, C.c_uint32, vp, C.POINTER(Result), vp]
     L.kdss_extract_counts.argtypes = [vp, vp, C.c_size_t, vp, vp, C.c_uint32, vp, vp, C.POINTER(Result), vp]
     L.kdss_workspace_size.argtypes = [vp, C.c_uint32, C.c_uint64, C.POINTER(Opts), C.POINTER(C.c_size_t)]
@@ -172,6 +179,14 @@ def _csr(graph):
 def validate(graph) -> int:
     c, keep = _csr(graph)
     return lib().kdss_csr_validate(C.byref(c))
+
+
+def tree_count(graph, k: int, threads: int = 0) -> TreeStats:
+    """The k-pruned tree's sizes without building it (kdss_sct_count)."""
+    c, keep = _csr(graph)
+    s = TreeStats()
+    _check(lib().kdss_sct_count(C.byref(c), k, threads, C.byref(s)), "kdss_sct_count")
+    return s
 
 
 class Tree:
@@ -296,6 +311,20 @@ class Plan:
         _check(lib().kdss_plan_autotune(self._h, _ptr(ws), ws.numel(), _ptr(r), warm, iters, C.byref(out),
                                         _stream(stream)), "kdss_plan_autotune")
         return out
+
+    def tune_key(self) -> str:
+        buf = C.create_string_buffer(512)
+        _check(lib().kdss_plan_tune_key(self._h, buf, 512), "kdss_plan_tune_key")
+        return buf.value.decode()
+
+    def autotune_cached(self, ws, r, warm: int, iters: int, cache_path: str = TUNE_CACHE, stream=None):
+        """Tuned launch from the cache file, or tuned now and filed there; returns (result, from_cache)."""
+        out = TuneResult()
+        hit = C.c_int(0)
+        _check(lib().kdss_plan_autotune_cached(self._h, _ptr(ws), ws.numel(), _ptr(r), warm, iters,
+                                               cache_path.encode(), C.byref(hit), C.byref(out), _stream(stream)),
+               "kdss_plan_autotune_cached")
+        return out, bool(hit.value)
 
     def timing(self, reset: bool = False) -> Timing:
         t = Timing()

@@ -352,3 +352,15 @@ def test_resume_and_counts_reject_bad_arguments_before_device_work():
                                  None) == kdss.EUNSUPPORTED               # batch plans: no prefix counts
     b.close()
     L.kdss_batch_free(None)
+
+
+@pytest.mark.parametrize("k", [3, 5, 6])
+def test_tree_count_equals_build(k):
+    """kdss_sct_count sizes the same tree kdss_sct_build keeps."""
+    for g in (synth.chung_lu(3000, 30000, 2.3, seed=8, planted=30), synth.rmat(11, 8, seed=0)):
+        t = kdss.Tree(g, k)
+        a, b = t.stats(), kdss.tree_count(g, k)
+        for f in ("k", "n", "leaves", "members", "s_max", "degeneracy"):
+            assert getattr(a, f) == getattr(b, f), f
+        assert a.c_k.value == b.c_k.value
+        assert kdss.tree_count(g, k, threads=1).leaves == a.leaves

@@ -212,3 +212,51 @@ def test_one_shot_solve(K, oracle_mod, width):
     assert [int(x) for x in r] == [int(x) for x in ref["r"]]
     assert np.array_equal(order, ref["order"])
     assert (res.size, res.dens_num.value, res.ub_num.value) == (ref["size"], ref["dens_num"], ref["ub_num"])
+
+
+def test_timed_run_matches_untimed(K, oracle_mod):
+    """Kernel-attached events (time_kernels) change nothing in the results and
+    give one leaf-credit and one load-update duration per iteration."""
+    g = synth.chung_lu(5000, 40000, 2.3, seed=34, planted=25)
+    tree = K.Tree(g, 4)
+    T = 12
+    plain = K.Plan(tree, T)
+    timed = K.Plan(tree, T, time_kernels=True)
+    outs = []
+    for plan in (plain, timed):
+        ws = plan.alloc_workspace()
+        plan.upload(ws)
+        res, _, r, order = _run(K, plan, ws, T, g.n)
+        outs.append((res, host_u64(r, g.n), order.cpu().numpy()))
+    say("timed run")
+    assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][2], outs[1][2])
+    assert (outs[0][0].size, outs[0][0].dens_num.value) == (outs[1][0].size, outs[1][0].dens_num.value)
+    tm = timed.timing(reset=True)
+    assert tm.leaf_launches == T and tm.apply_launches == T
+    assert tm.leaf_ms > 0 and tm.heavy_ms > 0 and tm.apply_ms > 0 and tm.reduce_ms == 0
+    assert timed.timing().leaf_launches == 0
+    ref = oracle_mod.solve(g.n, g.row_ptr, g.col, 4, T)
+    assert np.array_equal(outs[1][1], ref["r"])
+
+
+def test_tuning_cache(K, tmp_path):
+    """A tuned launch is filed under the plan's key and applied from the file."""
+    g = synth.chung_lu(5000, 40000, 2.3, seed=35, planted=25)
+    tree = K.Tree(g, 4)
+    plan = K.Plan(tree, 16)
+    ws = plan.alloc_workspace()
+    plan.upload(ws)
+    r = plan.alloc_loads()
+    key = plan.tune_key()
+    assert key.startswith("gfx") and "|k4|" in key
+    cache = str(tmp_path / "tune.txt")
+    say("tuning cache: tune and file")
+    a, hit = plan.autotune_cached(ws, r, warm=3, iters=2, cache_path=cache)
+    assert not hit and a.tried >= 20
+    line = open(cache).read().split()
+    assert line[0] == key and int(line[1]) == a.best_leaf_blocks and int(line[2]) == a.best_heavy_blocks
+    plan2 = K.Plan(tree, 16)
+    b, hit = plan2.autotune_cached(ws, r, warm=3, iters=2, cache_path=cache)
+    assert hit and (b.best_leaf_blocks, b.best_heavy_blocks, b.best_gather) == \
+        (a.best_leaf_blocks, a.best_heavy_blocks, a.best_gather)
+    assert plan2.stats().gather == a.best_gather
