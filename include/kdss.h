@@ -82,8 +82,8 @@ typedef struct {
     int use_graph;            /* 1: replay the iterations as a hipGraph         */
     uint32_t extract_every;   /* 0: extract after iteration T only; e > 0: also
                                  after every e-th iteration, into the trace     */
-    int time_kernels;         /* 1: bracket every leaf-credit and load-update
-                                 launch of kdss_run with hipEvents (plain
+    int time_kernels;         /* 1: time every iteration kernel of kdss_run
+                                 with kernel-attached hipEvents (plain
                                  launches, no graph); see kdss_plan_timing    */
     int gather;               /* key gathers of the leaf-credit pass:
                                  0: choose (masked when hot nodes hold at least
@@ -107,6 +107,21 @@ typedef struct {
                                     not depend on the pair order.  64-bit loads
                                     only.  The result's upper bound is certified
                                     only for update 0.                         */
+    int schedule;             /* which tiles a workgroup of the persistent
+                                 leaf-credit grid takes:
+                                 0: choose (strided; autotune may switch);
+                                 1: strided: wavefront w takes tiles w,
+                                    w + W, w + 2W, .. of the whole list;
+                                 2: XCD ranges: the tile list is cut into 8
+                                    ranges of equal work, and the workgroups
+                                    b = x, x + 8, .. take range x in strides,
+                                    so each of the 8 XCDs (which run the
+                                    workgroups with b mod 8 = x) walks one
+                                    contiguous range and its L2 holds that
+                                    range's keys.  Batches of Frank-Wolfe
+                                    problems list their tiles problem by
+                                    problem.  Grids under 8 workgroups run
+                                    strided.                                  */
 } kdss_opts;
 
 typedef struct {              /* accumulated by kdss_run when time_kernels = 1  */
@@ -132,6 +147,7 @@ typedef struct {
     uint64_t members[5];
     int gather;               /* gather mode of later runs: 1 masked, 2 full   */
     int update;               /* 0 Frank-Wolfe, 1 PBUpdate (synchronous)       */
+    int schedule;             /* tile schedule of later runs: 1 strided, 2 XCD ranges */
     uint32_t hot_nodes;       /* nodes whose keys and credits live in LDS       */
     double hot_share;         /* their share of all member occurrences          */
 } kdss_plan_stats;
@@ -277,8 +293,14 @@ int kdss_workspace_size(const kdss_sct *s, uint32_t T_max, uint64_t r0_max, cons
                         size_t *bytes);
 
 /* Kernel durations gathered by kdss_run with opts.time_kernels = 1 since the
- * plan was created or the last reset (reset != 0 clears them after copying). */
+ * plan was created or the last reset (reset != 0 clears them after copying).
+ * Each duration is the kernel's own execution span: the runtime stamps the
+ * dispatch's start and end into the launch's events (hipExtLaunchKernel), so
+ * no marker packet sits between the kernels of a timed run. */
 int kdss_plan_timing(kdss_plan *p, kdss_timing *out, int reset);
+
+/* Switches the plan's kernel timing (opts.time_kernels) on or off for later runs. */
+int kdss_plan_set_timing(kdss_plan *p, int on);
 void kdss_plan_free(kdss_plan *p);
 
 /* Copies the leaf stream, tile table and binomial table into the device
@@ -384,6 +406,9 @@ typedef struct {
     int best_gather;              /* gather mode kept (1 masked, 2 full)       */
     double gather_ms[2];          /* per iteration at the best grid sizes with
                                      masked / full gathers (0: not timed)      */
+    int best_schedule;            /* tile schedule kept (1 strided, 2 XCD ranges) */
+    double schedule_ms[2];        /* per iteration with each schedule at the
+                                     best grid sizes and gather (0: not timed) */
 } kdss_tune_result;
 
 /* Sets the grid sizes (leaf-credit 1..2048, heavy-leaf 1..1024 workgroups) used by later runs. */
@@ -391,8 +416,9 @@ int kdss_plan_set_launch(kdss_plan *p, uint32_t leaf_blocks, uint32_t heavy_bloc
 
 /* Times `iters` iterations after `warm` untimed ones (from zero loads) for each
  * candidate pair of grid sizes on the plan's own data, keeps the fastest and
- * reports all (out, host).  When the plan's options left the gather mode to the
- * library, the other mode is then timed at the best sizes and kept if faster.  d_r (device, the plan's load width) is scratch.
+ * reports all (out, host).  When the plan's options left the gather mode (or
+ * the tile schedule) to the library, the other mode (schedule) is then timed at
+ * the best sizes and kept if faster.  d_r (device, the plan's load width) is scratch.
  * warm + iters must not exceed T_max.  Synchronises the stream. */
 int kdss_plan_autotune(kdss_plan *p, void *d_ws, size_t ws_bytes, uint64_t *d_r, uint32_t warm, uint32_t iters,
                        kdss_tune_result *out, void *stream);
@@ -405,7 +431,7 @@ int kdss_plan_autotune(kdss_plan *p, void *d_ws, size_t ws_bytes, uint64_t *d_r,
 int kdss_plan_tune_key(const kdss_plan *p, char *buf, size_t cap);
 
 /* kdss_plan_autotune through a tuning cache: a text file (cache_path, host)
- * of lines "key leaf_blocks heavy_blocks gather ms".  When the file holds the
+ * of lines "key leaf_blocks heavy_blocks gather schedule ms".  When the file holds the
  * plan's key (the last such line wins) its launch is applied without timing
  * anything (*from_cache = 1; out carries only the best_* fields); otherwise the
  * plan is tuned as by kdss_plan_autotune and a line is appended (*from_cache =

@@ -234,6 +234,24 @@ static void layout_workspace(kdss_plan* P) {
   P->off_hotkey_fw = take((size_t)kHotMax * 32);  // hot-node keys at the current loads (64-bit runs)
   P->off_qcount = take(64);
   P->off_qlog = take((size_t)P->T_max * 4);
+  // XCD ranges: cut points of equal work (a lane tile costs its 64-member rows,
+  // a big tile its members)
+  {
+    std::vector<uint64_t> cum(P->tiles.size() + 1, 0);
+    for (size_t i = 0; i < P->tiles.size(); ++i) {
+      const Tile& tl = P->tiles[i];
+      const uint64_t rows = tl.info >> 16;
+      const uint32_t hd = P->hdr[tl.lbase];
+      const uint64_t big = (hd & 31u) + (hd >> 10);
+      cum[i + 1] = cum[i] + ((tl.info & 7u) == kTileLane ? 64 * rows : big) + 64;
+    }
+    for (uint32_t x = 0; x <= kXcds; ++x) {
+      const uint64_t want = cum.back() * x / kXcds;
+      P->xcd_bounds[x] = (uint32_t)(std::lower_bound(cum.begin(), cum.end(), want) - cum.begin());
+    }
+    P->xcd_bounds[kXcds] = (uint32_t)P->tiles.size();
+  }
+  P->off_xcd = take(sizeof(P->xcd_bounds));
   // batch extraction: prefix sums, per-problem results and node offsets
   P->off_prefix = take(n * 8);
   P->off_pres = take(nprob * sizeof(DevResult));
@@ -296,6 +314,11 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
       delete P;
       return fail(KDSS_EINVAL, "update must be 0 (Frank-Wolfe) or 1 (PBUpdate)");
     }
+    if (P->opts.schedule < 0 || P->opts.schedule > 2) {
+      delete P;
+      return fail(KDSS_EINVAL, "schedule must be 0, 1 or 2");
+    }
+    P->sched = P->opts.schedule == 2 ? 2 : 1;
     if (P->opts.update == 1 && (P->opts.width == 128 || !fits64)) {
       delete P;
       return fail(KDSS_EINVAL, "PBUpdate runs with 64-bit loads only");
@@ -494,6 +517,13 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
       delete P;
       return fail(KDSS_ERANGE, "more than 2^26 tiles");
     }
+    // Frank-Wolfe batches list their tiles problem by problem (each problem's
+    // in the order above): a contiguous range of tiles then touches the keys
+    // of few problems.  (PBUpdate keeps the size-class order its launch split
+    // relies on.)
+    if (trees.size() > 1 && P->opts.update == 0)
+      std::stable_sort(P->tiles.begin(), P->tiles.end(),
+                       [](const Tile& a, const Tile& b) { return a.nbase < b.nbase; });
     if (P->hdr.size() > 0xFFFFFFFFull) {
       delete P;
       return fail(KDSS_ERANGE, "more than 2^32 - 1 leaves");
@@ -610,6 +640,7 @@ int kdss_plan_info(const kdss_plan* P, kdss_plan_stats* out) {
   out->T_max = P->T_max;
   out->gather = P->gather;
   out->update = P->opts.update;
+  out->schedule = P->sched;
   out->hot_nodes = (uint32_t)P->hot.size();
   out->hot_share = P->hot_share;
   for (int c = 0; c < kNumClasses; ++c) {

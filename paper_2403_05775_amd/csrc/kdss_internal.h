@@ -130,6 +130,7 @@ constexpr uint32_t kHotSlots = 256;              // credit slots per hot node, s
 constexpr double kMaskedGatherShare = 0.5;       // hot share from which masked gathers are the default
 constexpr uint32_t kPbRegRows = 16;              // PBUpdate: lane tiles up to this many rows run from registers
 constexpr uint32_t kPbMidRows = 32;              // PBUpdate: lane tiles up to this many rows share 4-wave workgroups
+constexpr uint32_t kXcds = 8;                    // accelerator dies; workgroup b runs on die b mod 8
 
 // Copies a plan's leaf stream and tables into the device workspace d_ws and
 // empties its queue and hot-node slots (with kernels when fill_by_kernel, else
@@ -173,6 +174,8 @@ struct kdss_plan {
   int width = 64;          // load width
   int key_mode = 0;        // 0 packed, 1 full
   int gather = 1;          // leaf-pass key gathers: 1 masked, 2 full
+  int sched = 1;           // leaf-pass tile schedule: 1 strided, 2 XCD ranges
+  uint32_t xcd_bounds[9] = {};   // XCD x takes tiles [xcd_bounds[x], xcd_bounds[x + 1])
   uint32_t pb_split = 0;   // PBUpdate: tiles [0, pb_split) are staged in LDS, the rest (lane tiles of
                            // at most kPbRegRows rows) kept in registers
   uint32_t pb_rows = 0;    // PBUpdate: staged rows of 64 members (largest tile or big leaf before pb_mid)
@@ -198,6 +201,7 @@ struct kdss_plan {
   std::vector<uint32_t> hot_base;      // first node id of each hot node's problem
   size_t off_hot = 0, off_hot_base = 0, off_scratch = 0, off_dbase = 0, off_queue = 0, off_qcount = 0;
   size_t off_qlog = 0;
+  size_t off_xcd = 0;                  // the nine XCD range bounds (u32)
   size_t off_hotkey = 0;               // hot-node keys published by a leaf pass for its heavy pass
   size_t off_hotkey_fw = 0;            // hot-node keys at the current loads, kept by the load update
   uint32_t heavy_blocks = 0;           // grid of the heavy-leaf kernel

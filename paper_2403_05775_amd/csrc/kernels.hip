@@ -458,7 +458,7 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
                                                           const uint32_t* __restrict__ hot_base, uint32_t nhot,
                                                           uint64_t* __restrict__ scratch, uint4* __restrict__ queue,
                                                           uint32_t* __restrict__ qcount, KT* __restrict__ hotkey,
-                                                          bool hot_published) {
+                                                          bool hot_published, const uint32_t* __restrict__ xcd) {
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kBinomLds];
@@ -467,9 +467,19 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
   uint32_t* lcol = lowslot + threadIdx.x;
   for (uint32_t i = 0; i < 4; ++i) lcol[i * kLeafThreads] = 0u;   // node 0 until a lane writes its own
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const uint32_t stride = gridDim.x * 4u;
-  uint32_t tile = blockIdx.x * 4u + w;
-  Tile t = tile < ntiles ? tiles[tile] : Tile{};   // in flight during the LDS set-up
+  // strided: every wavefront of the grid walks the whole list; XCD ranges
+  // (xcd != null, grid of 8 or more workgroups): the workgroups with
+  // blockIdx mod 8 = x walk range x = [xcd[x], xcd[x + 1]) in strides of
+  // their own wavefront count, so every tile is still taken exactly once
+  uint32_t tile = blockIdx.x * 4u + w, stride = gridDim.x * 4u, tend = ntiles;
+  if (xcd && gridDim.x >= kXcds) {
+    const uint32_t x = blockIdx.x % kXcds;
+    tile = xcd[x] + (blockIdx.x / kXcds) * 4u + w;
+    stride = ((gridDim.x - x + kXcds - 1) / kXcds) * 4u;
+    tend = xcd[x + 1];
+  }
+  const uint32_t first = tile;
+  Tile t = tile < tend ? tiles[tile] : Tile{};   // in flight during the LDS set-up
   if (hot_published) {
     // the hot keys at these loads were written by the previous load update
     for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
@@ -492,8 +502,8 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
   const uint64_t* bt = lds_binom ? sbinom : binom;
   Sink sink{hcnt, out, 0u, 0ull};
   WaveQueue hq{qslice[w], 0u};
-  for (; tile < ntiles; tile += stride) {
-    if (tile >= blockIdx.x * 4u + w + stride) t = tiles[tile];   // the first one is loaded
+  for (; tile < tend; tile += stride) {
+    if (tile != first) t = tiles[tile];   // the first one is loaded
     KeySrc ts = src;
     ts.base = t.nbase;
     if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k1, ts, hkey, sink);
@@ -1718,17 +1728,18 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   uint32_t* qcount = ws.at<uint32_t>(P->off_qcount);
   const uint32_t nbinom = (uint32_t)P->binom.size();
   const size_t table_off = hot_published ? P->off_hotkey_fw : P->off_hotkey;
+  const uint32_t* xcd = P->sched == 2 ? ws.at<uint32_t>(P->off_xcd) : nullptr;
   hipEvent_t* ev_leaf = ev ? ev + kEvLeaf : nullptr;
   hipEvent_t* ev_heavy = ev ? ev + kEvHeavy : nullptr;
 #define KDSS_LEAF(KT)                                                                                           \
   if (P->gather == 2)                                                                                            \
     launch_timed(leaf_credit_kernel<KT, false>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members,   \
                  hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,              \
-                 ws.at<KT>(table_off), hot_published);                                                          \
+                 ws.at<KT>(table_off), hot_published, xcd);                                                     \
   else                                                                                                           \
     launch_timed(leaf_credit_kernel<KT, true>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members,    \
                  hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,              \
-                 ws.at<KT>(table_off), hot_published);                                                          \
+                 ws.at<KT>(table_off), hot_published, xcd);                                                     \
   launch_timed(heavy_kernel<KT>, P->heavy_blocks, 256, 0, st, ev_heavy, members, binom, P->k1, src, out, nhot,  \
                scratch, (const uint4*)queue, (const uint32_t*)qcount, (const KT*)ws.at<KT>(table_off), nbinom)
   if (used) *used |= 1u | 2u;
@@ -2265,6 +2276,8 @@ int upload_plan(kdss_plan* P, void* d_ws, size_t ws_bytes, void* stream, bool fi
   }
   HIP_TRY(hipMemcpyAsync(ws.at<uint64_t>(P->off_nodeoff), P->node_off.data(), P->node_off.size() * 8,
                          hipMemcpyHostToDevice, st), "upload node offsets");
+  HIP_TRY(hipMemcpyAsync(ws.at<uint32_t>(P->off_xcd), P->xcd_bounds, sizeof(P->xcd_bounds), hipMemcpyHostToDevice,
+                         st), "upload XCD ranges");
   // the heavy-leaf queue and the hot-node slot entries start empty; every leaf
   // pass leaves them empty again
   if (fill_by_kernel) {
@@ -2450,6 +2463,12 @@ int kdss_batch_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const 
   return KDSS_OK;
 }
 
+int kdss_plan_set_timing(kdss_plan* P, int on) {
+  if (!P) return fail(KDSS_EINVAL, "null argument");
+  P->opts.time_kernels = on ? 1 : 0;
+  return KDSS_OK;
+}
+
 int kdss_plan_set_launch(kdss_plan* P, uint32_t leaf_blocks, uint32_t heavy_blocks) {
   if (!P) return fail(KDSS_EINVAL, "null argument");
   if (leaf_blocks == 0 || leaf_blocks > kLeafBlocksMax || heavy_blocks == 0 || heavy_blocks > kHeavyBlocks)
@@ -2513,8 +2532,10 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
     if (rc) break;
   }
   out->best_gather = P->gather;
+  out->best_schedule = P->sched;
   if (!rc) {
     out->gather_ms[P->gather - 1] = out->best_ms;
+    out->schedule_ms[P->sched - 1] = out->best_ms;
     if (saved.gather == 0) {   // the mode was left to the library: try the other one at the best sizes
       const int current = P->gather;
       P->leaf_blocks = out->best_leaf_blocks;
@@ -2531,6 +2552,24 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
         }
       }
       P->gather = out->best_gather;
+    }
+    if (!rc) out->schedule_ms[P->sched - 1] = out->best_ms;
+    if (!rc && saved.schedule == 0 && P->tiles.size() > 0) {   // the schedule was left to the library
+      const int current = P->sched;
+      P->leaf_blocks = out->best_leaf_blocks;
+      P->heavy_blocks = out->best_heavy_blocks;
+      P->sched = 3 - current;
+      float ms = 0.f;
+      rc = time_config(&ms);
+      if (!rc) {
+        ++out->tried;
+        out->schedule_ms[P->sched - 1] = ms;
+        if (ms < out->best_ms) {
+          out->best_ms = ms;
+          out->best_schedule = P->sched;
+        }
+      }
+      P->sched = out->best_schedule;
     }
   }
   hipEventDestroy(e0);
@@ -2559,7 +2598,8 @@ int kdss_plan_tune_key(const kdss_plan* P, char* buf, size_t cap) {
   std::sort(ks.begin(), ks.end());
   ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
   std::string key = arch + "|w" + std::to_string(P->width) + "|km" + std::to_string(P->key_mode) + "|u" +
-                    std::to_string(P->opts.update) + "|g" + std::to_string(P->opts.gather) + "|k";
+                    std::to_string(P->opts.update) + "|g" + std::to_string(P->opts.gather) + "|s" +
+                    std::to_string(P->opts.schedule) + "|k";
   for (size_t i = 0; i < ks.size(); ++i) key += (i ? "," : "") + std::to_string(ks[i]);
   key += "|q" + std::to_string(bucket((double)(P->node_off.size() - 1))) + "|n" + std::to_string(bucket(P->n)) +
          "|L";
@@ -2582,14 +2622,16 @@ int kdss_plan_autotune_cached(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_
     while (std::fgets(line, sizeof(line), f)) {
       char k2[512];
       unsigned lb = 0, hb = 0;
-      int g = 0;
+      int g = 0, sc = 0;
       double ms = 0.0;
-      if (std::sscanf(line, "%511s %u %u %d %lf", k2, &lb, &hb, &g, &ms) == 5 && std::strcmp(k2, key) == 0 &&
-          lb >= 1 && lb <= kLeafBlocksMax && hb >= 1 && hb <= kHeavyBlocks && (g == 1 || g == 2)) {
+      if (std::sscanf(line, "%511s %u %u %d %d %lf", k2, &lb, &hb, &g, &sc, &ms) == 6 &&
+          std::strcmp(k2, key) == 0 && lb >= 1 && lb <= kLeafBlocksMax && hb >= 1 && hb <= kHeavyBlocks &&
+          (g == 1 || g == 2) && (sc == 1 || sc == 2)) {
         std::memset(out, 0, sizeof(*out));
         out->best_leaf_blocks = lb;
         out->best_heavy_blocks = hb;
         out->best_gather = g;
+        out->best_schedule = sc;
         out->best_ms = ms;
         *from_cache = 1;
       }
@@ -2600,14 +2642,15 @@ int kdss_plan_autotune_cached(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_
     P->leaf_blocks = out->best_leaf_blocks;
     P->heavy_blocks = out->best_heavy_blocks;
     P->gather = out->best_gather;
+    P->sched = out->best_schedule;
     drop_graph(P);
     return KDSS_OK;
   }
   rc = kdss_plan_autotune(P, d_ws, ws_bytes, d_r, warm, iters, out, stream);
   if (rc) return rc;
   if (FILE* f = std::fopen(cache_path, "a")) {
-    std::fprintf(f, "%s %u %u %d %.6f\n", key, out->best_leaf_blocks, out->best_heavy_blocks, out->best_gather,
-                 out->best_ms);
+    std::fprintf(f, "%s %u %u %d %d %.6f\n", key, out->best_leaf_blocks, out->best_heavy_blocks, out->best_gather,
+                 out->best_schedule, out->best_ms);
     std::fclose(f);
   }
   return KDSS_OK;

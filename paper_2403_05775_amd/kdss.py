@@ -46,7 +46,7 @@ class TreeStats(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("width", C.c_int), ("use_graph", C.c_int), ("extract_every", C.c_uint32),
-                ("time_kernels", C.c_int), ("gather", C.c_int), ("update", C.c_int)]
+                ("time_kernels", C.c_int), ("gather", C.c_int), ("update", C.c_int), ("schedule", C.c_int)]
 
 
 class Timing(C.Structure):
@@ -58,14 +58,16 @@ class Timing(C.Structure):
 class TuneResult(C.Structure):
     _fields_ = [("tried", C.c_uint32), ("best_leaf_blocks", C.c_uint32), ("best_heavy_blocks", C.c_uint32),
                 ("best_ms", C.c_double), ("leaf_blocks", C.c_uint32 * 32), ("heavy_blocks", C.c_uint32 * 32),
-                ("ms", C.c_double * 32), ("best_gather", C.c_int), ("gather_ms", C.c_double * 2)]
+                ("ms", C.c_double * 32), ("best_gather", C.c_int), ("gather_ms", C.c_double * 2),
+                ("best_schedule", C.c_int), ("schedule_ms", C.c_double * 2)]
 
 
 class PlanStats(C.Structure):
     _fields_ = [("workspace_bytes", C.c_uint64), ("stream_bytes", C.c_uint64), ("width", C.c_int),
                 ("key_mode", C.c_int), ("id_bits", C.c_uint32), ("T_max", C.c_uint32),
                 ("tiles", C.c_uint64 * 5), ("leaves", C.c_uint64 * 5), ("members", C.c_uint64 * 5),
-                ("gather", C.c_int), ("update", C.c_int), ("hot_nodes", C.c_uint32), ("hot_share", C.c_double)]
+                ("gather", C.c_int), ("update", C.c_int), ("schedule", C.c_int), ("hot_nodes", C.c_uint32),
+                ("hot_share", C.c_double)]
 
 
 class SampleInfo(C.Structure):
@@ -91,7 +93,7 @@ EXPORTS = [
     "kdss_batch_create", "kdss_batch_offsets", "kdss_batch_run", "kdss_plan_set_launch", "kdss_plan_autotune",
     "kdss_sample_build", "kdss_sct_build_gpu", "kdss_workspace_size", "kdss_solve", "kdss_run_resume",
     "kdss_extract_counts", "kdss_batch_free", "kdss_run_static", "kdss_sct_count", "kdss_plan_tune_key",
-    "kdss_plan_autotune_cached",
+    "kdss_plan_autotune_cached", "kdss_plan_set_timing",
 ]
 
 TUNE_CACHE = os.path.join(_HERE, "tune_cache.txt")   # launches tuned on MI355X, keyed by plan shape
@@ -144,6 +146,7 @@ def lib():
     L.kdss_plan_set_launch.argtypes = [vp, C.c_uint32, C.c_uint32]
     L.kdss_plan_autotune.argtypes = [vp, vp, C.c_size_t, vp, C.c_uint32, C.c_uint32, C.POINTER(TuneResult), vp]
     L.kdss_plan_tune_key.argtypes = [vp, C.c_char_p, C.c_size_t]
+    L.kdss_plan_set_timing.argtypes = [vp, C.c_int]
     L.kdss_plan_autotune_cached.argtypes = [vp, vp, C.c_size_t, vp, C.c_uint32, C.c_uint32, C.c_char_p,
                                             C.POINTER(C.c_int), C.POINTER(TuneResult), vp]
     L.kdss_extract.argtypes = [vp, vp, C.c_size_t, vp, vp, C.c_uint32, vp, C.POINTER(Result), vp]
@@ -286,8 +289,9 @@ class Plan:
     """Device layout of a tree; owns nothing on the device."""
 
     def __init__(self, tree: Tree, T_max: int, r0_max: int = 0, width: int = 0, use_graph: bool = False,
-                 extract_every: int = 0, time_kernels: bool = False, gather: int = 0, update: int = 0):
-        o = Opts(width, 1 if use_graph else 0, extract_every, 1 if time_kernels else 0, gather, update)
+                 extract_every: int = 0, time_kernels: bool = False, gather: int = 0, update: int = 0,
+                 schedule: int = 0):
+        o = Opts(width, 1 if use_graph else 0, extract_every, 1 if time_kernels else 0, gather, update, schedule)
         h = C.c_void_p()
         _check(lib().kdss_plan_create(tree._h, T_max, r0_max, C.byref(o), C.byref(h)), "kdss_plan_create")
         self._h = h
@@ -325,6 +329,9 @@ class Plan:
                                                cache_path.encode(), C.byref(hit), C.byref(out), _stream(stream)),
                "kdss_plan_autotune_cached")
         return out, bool(hit.value)
+
+    def set_timing(self, on: bool):
+        _check(lib().kdss_plan_set_timing(self._h, 1 if on else 0), "kdss_plan_set_timing")
 
     def timing(self, reset: bool = False) -> Timing:
         t = Timing()
@@ -410,8 +417,8 @@ class Batch(Plan):
     covers every problem; each problem's result equals its solo run."""
 
     def __init__(self, trees, T_max: int, r0_max: int = 0, use_graph: bool = False, time_kernels: bool = False,
-                 gather: int = 0, update: int = 0):
-        o = Opts(0, 1 if use_graph else 0, 0, 1 if time_kernels else 0, gather, update)
+                 gather: int = 0, update: int = 0, schedule: int = 0):
+        o = Opts(0, 1 if use_graph else 0, 0, 1 if time_kernels else 0, gather, update, schedule)
         arr = (C.c_void_p * len(trees))(*[t._h for t in trees])
         h = C.c_void_p()
         _check(lib().kdss_batch_create(arr, len(trees), T_max, r0_max, C.byref(o), C.byref(h)), "kdss_batch_create")
@@ -476,13 +483,13 @@ class Solution:
 
 
 def solve(graph, k: int, T: int, r0=None, width: int = 0, use_graph: bool = False, extract_every: int = 0,
-          threads: int = 0, device="cuda", gather: int = 0, update: int = 0) -> Solution:
+          threads: int = 0, device="cuda", gather: int = 0, update: int = 0, schedule: int = 0) -> Solution:
     """Build the tree, lay it out, run T iterations and the extraction on the GPU."""
     import torch
     tree = Tree(graph, k, threads)
     r0_max = 0 if r0 is None else int(np.max(np.asarray(r0, dtype=np.uint64))) if graph.n else 0
     plan = Plan(tree, T, r0_max, width=width, use_graph=use_graph, extract_every=extract_every, gather=gather,
-                update=update)
+                update=update, schedule=schedule)
     ws = plan.alloc_workspace(device)
     plan.upload(ws)
     r = plan.alloc_loads(device)

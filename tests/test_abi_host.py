@@ -364,3 +364,15 @@ def test_tree_count_equals_build(k):
             assert getattr(a, f) == getattr(b, f), f
         assert a.c_k.value == b.c_k.value
         assert kdss.tree_count(g, k, threads=1).leaves == a.leaves
+
+
+def test_schedule_option():
+    g = synth.chung_lu(2000, 20000, 2.3, seed=5, planted=30)
+    t = kdss.Tree(g, 4)
+    assert kdss.Plan(t, 10).stats().schedule == 1
+    assert kdss.Plan(t, 10, schedule=1).stats().schedule == 1
+    assert kdss.Plan(t, 10, schedule=2).stats().schedule == 2
+    for bad in (-1, 3):
+        with pytest.raises(kdss.KdssError) as e:
+            kdss.Plan(t, 10, schedule=bad)
+        assert e.value.status == kdss.EINVAL

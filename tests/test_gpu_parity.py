@@ -220,3 +220,46 @@ def test_small_leaf_grids(K, oracle_mod, leaf_blocks):
     assert np.array_equal(r.cpu().numpy().view(np.uint64)[: g.n], want["r"])
     assert np.array_equal(order.cpu().numpy().view(np.uint32), want["order"])
     assert (res.size, res.dens_num.value, res.ub_num.value) == (want["size"], want["dens_num"], want["ub_num"])
+
+
+@pytest.mark.parametrize("leaf_blocks", [5, 8, 13, 64, 2048])
+def test_xcd_range_schedule(K, oracle_mod, leaf_blocks):
+    """The XCD-range tile schedule: every tile once whatever the grid (under 8
+    workgroups it runs strided; 13 gives the dies uneven workgroup counts), on
+    a single problem with big leaves and on a batch listed problem by problem."""
+    from paper_2403_05775_amd import kdss
+    g = synth.erdos_renyi(300, 0.1, seed=9, planted_clique=70)
+    T = 5
+    tree = kdss.Tree(g, 4)
+    plan = kdss.Plan(tree, T, schedule=2)
+    assert plan.stats().schedule == 2
+    plan.set_launch(leaf_blocks, 7)
+    ws = plan.alloc_workspace()
+    plan.upload(ws)
+    r = plan.alloc_loads()
+    order = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    print(f"xcd schedule, grid {leaf_blocks}, single", flush=True)
+    res, _ = plan.run(ws, T, r, order)
+    torch.cuda.synchronize()
+    want = ref(oracle_mod, g, 4, T)
+    assert np.array_equal(r.cpu().numpy().view(np.uint64)[: g.n], want["r"])
+    assert (res.size, res.dens_num.value) == (want["size"], want["dens_num"])
+    probs = [(synth.chung_lu(400 + 90 * i, 3000 + 500 * i, 2.3, seed=50 + i, planted=12), 3 + i % 4)
+             for i in range(6)]
+    b = kdss.Batch([kdss.Tree(gq, kq) for gq, kq in probs], T, schedule=2)
+    b.set_launch(leaf_blocks, 5)
+    wsb = b.alloc_workspace()
+    b.upload(wsb)
+    rb = torch.empty(b.n, dtype=torch.int64, device="cuda")
+    ob = torch.empty(b.n, dtype=torch.int32, device="cuda")
+    print(f"xcd schedule, grid {leaf_blocks}, batch", flush=True)
+    resb = b.run(wsb, T, rb, ob)
+    torch.cuda.synchronize()
+    rr = rb.cpu().numpy().view(np.uint64)
+    oo = ob.cpu().numpy().view(np.uint32)
+    for q, (gq, kq) in enumerate(probs):
+        want = ref(oracle_mod, gq, kq, T)
+        lo, hi = int(b.node_off[q]), int(b.node_off[q + 1])
+        assert np.array_equal(rr[lo:hi], want["r"]), q
+        assert np.array_equal(oo[lo:hi], want["order"]), q
+        assert (resb[q].size, resb[q].dens_num.value) == (want["size"], want["dens_num"]), q
