@@ -210,15 +210,29 @@ int kdss_sct_build(const kdss_csr *g, uint32_t k, uint32_t threads, kdss_sct **o
  * bitsets of its later neighbours (built once, kept in a device store), the
  * root pivot and the root's children; one thread per root child runs the
  * pivoting recursion below it with an explicit stack, heaviest start nodes
- * first; a counting pass and a writing pass over chunks of children (scratch
- * up to 8 GiB per chunk).  The leaves may differ from kdss_sct_build's
- * (another valid tree: every k-clique in exactly one kept leaf), so every
- * result computed on it is the same.  Device memory is allocated and freed
- * inside the call, which synchronises the stream (once per peeling sub-round
- * too); build_seconds covers the whole call.
+ * first; a counting pass and a writing pass over chunks of children.  The
+ * leaves may differ from kdss_sct_build's (another valid tree: every k-clique
+ * in exactly one kept leaf), so every result computed on it is the same.
+ * Device memory is the caller's workspace d_ws (ws_bytes): the graph, the
+ * order, the oriented lists, the root bitsets and tasks, one chunk's recursion
+ * scratch (at most half of what is left, at most 8 GiB) and, in the rest, a
+ * staging window through which each chunk's leaves are copied back to the host.
+ * The call synchronises the stream (once per peeling sub-round too);
+ * build_seconds covers the whole call.
  * Errors: as kdss_sct_build, plus KDSS_EUNSUPPORTED (degeneracy above 256,
- * found by the peeling) and KDSS_EHIP. */
-int kdss_sct_build_gpu(const kdss_csr *g, uint32_t k, void *stream, kdss_sct **out);
+ * found by the peeling), KDSS_EWORKSPACE (d_ws NULL, too small for the fixed
+ * parts, or one root child's leaves larger than the staging window) and
+ * KDSS_EHIP. */
+int kdss_sct_build_gpu(const kdss_csr *g, uint32_t k, void *d_ws, size_t ws_bytes, void *stream,
+                       kdss_sct **out);
+
+/* A workspace size (bytes) with which kdss_sct_build_gpu runs g at k: the
+ * fixed parts bounded from n and nnz (the bitsets by nnz / 2 later neighbours
+ * times ceil(degeneracy / 64) words, the degeneracy from a host peeling), one
+ * chunk of recursion scratch, and a 512 MiB staging window.  Host only.
+ * Errors: as kdss_sct_build_gpu's argument and graph checks, and
+ * KDSS_EUNSUPPORTED for degeneracy above 256. */
+int kdss_sct_build_gpu_workspace(const kdss_csr *g, uint32_t k, size_t *bytes);
 
 int kdss_sct_info(const kdss_sct *s, kdss_tree_stats *out);
 
@@ -257,12 +271,15 @@ void kdss_sct_free(kdss_sct *s);
  * returned tree: a plan and kdss_run on it run Algorithm 4's loop (here
  * synchronous) over the sample set and its extraction by
  * rho'_k(V_i) = |C_k(V_i) with sampled C| / i.  The path counts and walks run
- * on the current device on `stream` (device memory is allocated and freed
- * inside the call, which synchronises the stream); colouring and the
- * de-duplication run on the host.
+ * on the current device on `stream`, in the caller's device workspace d_ws of
+ * ws_bytes >= kdss_sample_workspace(n, nnz, k, t) bytes (the graph, the path
+ * counts P_1..P_k and their prefix sums in 128 bits, the draws and the walks;
+ * NULL when that size is 0); the call synchronises the stream.  Colouring and
+ * the de-duplication run on the host.
  * Errors: KDSS_EINVAL (k < 2, null draws with t > 0), KDSS_EGRAPH,
- * KDSS_ERANGE (k > 31), KDSS_EOVERFLOW (2^128 or more paths), KDSS_ENOMEM,
- * KDSS_EHIP. */
+ * KDSS_ERANGE (k > 31), KDSS_EOVERFLOW (2^128 or more paths, seen as a
+ * wrapped path count, block sum or running total), KDSS_EWORKSPACE,
+ * KDSS_ENOMEM, KDSS_EHIP. */
 typedef struct {
     uint64_t samples;         /* t                                             */
     uint64_t cliques;         /* samples that are k-cliques                    */
@@ -273,8 +290,12 @@ typedef struct {
     double host_seconds;      /* colouring, uploads, de-duplication, the tree  */
 } kdss_sample_info;
 
-int kdss_sample_build(const kdss_csr *g, uint32_t k, uint64_t t, const uint64_t *h_draws, void *stream,
-                      kdss_sample_info *info, kdss_sct **out);
+int kdss_sample_build(const kdss_csr *g, uint32_t k, uint64_t t, const uint64_t *h_draws, void *d_ws,
+                      size_t ws_bytes, void *stream, kdss_sample_info *info, kdss_sct **out);
+
+/* Device workspace (bytes) of kdss_sample_build for n nodes, nnz directed
+ * edges, clique size k and t samples (0 when n or t is 0).  Host only. */
+int kdss_sample_workspace(uint32_t n, uint64_t nnz, uint32_t k, uint64_t t, size_t *bytes);
 
 /* Lays out s for the GPU, for runs of at most T_max iterations whose start
  * loads r0 are all <= r0_max.  Chooses the load width (u64 when
@@ -411,7 +432,7 @@ typedef struct {
                                      best grid sizes and gather (0: not timed) */
 } kdss_tune_result;
 
-/* Sets the grid sizes (leaf-credit 1..2048, heavy-leaf 1..1024 workgroups) used by later runs. */
+/* Sets the grid sizes (leaf-credit 1..2048, heavy-leaf 1..2048 workgroups) used by later runs. */
 int kdss_plan_set_launch(kdss_plan *p, uint32_t leaf_blocks, uint32_t heavy_blocks);
 
 /* Times `iters` iterations after `warm` untimed ones (from zero loads) for each

@@ -57,30 +57,43 @@ __global__ __launch_bounds__(256) void path_count_kernel(const uint64_t* __restr
 
 // inclusive prefix sums of a[0..n) (u128): block sums, one-thread scan of the
 // block sums, then each block's prefixes
+// Sums that wrap past 2^128 - 1 set *ovf (a carry shows as s + v < s).
+__device__ __forceinline__ void add_checked(u128& s, u128 v, bool& wrapped) {
+  const u128 t = s + v;
+  wrapped |= t < s;
+  s = t;
+}
+
 __global__ __launch_bounds__(kSampleThreads) void prefix_blocksum_kernel(const u128* __restrict__ a, uint32_t n,
-                                                                         u128* __restrict__ bs) {
+                                                                         u128* __restrict__ bs, int* ovf) {
   __shared__ u128 part[kSampleThreads];
   const uint32_t base = blockIdx.x * kSampleTile + threadIdx.x * kSampleItems;
   u128 s = 0;
+  bool wrapped = false;
   for (uint32_t q = 0; q < kSampleItems; ++q)
-    if (base + q < n) s += a[base + q];
+    if (base + q < n) add_checked(s, a[base + q], wrapped);
   part[threadIdx.x] = s;
+  if (wrapped) atomicOr(ovf, 1);
   __syncthreads();
   if (threadIdx.x == 0) {
     u128 t = 0;
-    for (uint32_t i = 0; i < kSampleThreads; ++i) t += part[i];
+    bool w2 = false;
+    for (uint32_t i = 0; i < kSampleThreads; ++i) add_checked(t, part[i], w2);
     bs[blockIdx.x] = t;
+    if (w2) atomicOr(ovf, 1);
   }
 }
 
-__global__ void prefix_scan_kernel(u128* __restrict__ bs, uint32_t nb) {
+__global__ void prefix_scan_kernel(u128* __restrict__ bs, uint32_t nb, int* ovf) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   u128 run = 0;
+  bool wrapped = false;
   for (uint32_t b = 0; b < nb; ++b) {
     const u128 v = bs[b];
     bs[b] = run;
-    run += v;
+    add_checked(run, v, wrapped);
   }
+  if (wrapped) atomicOr(ovf, 1);
 }
 
 __global__ __launch_bounds__(kSampleThreads) void prefix_write_kernel(const u128* __restrict__ a, uint32_t n,
@@ -191,32 +204,67 @@ uint32_t greedy_colour(const kdss_csr* g, std::vector<uint32_t>& color) {
   return used;
 }
 
-struct DeviceBuffers {
-  std::vector<void*> ptrs;
-  ~DeviceBuffers() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
+// Device buffers carved from the caller's workspace (256-byte aligned pieces).
+struct Carve {
+  char* base;
+  size_t cap, used;
   template <class T>
-  int alloc(T** p, size_t count) {
-    void* q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
-      return kdss::fail(KDSS_ENOMEM, "device memory for the sampler");
-    ptrs.push_back(q);
-    *p = static_cast<T*>(q);
+  int take(T** p, size_t count) {
+    const size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) & ~(size_t)255;
+    if (base && used + bytes <= cap) *p = reinterpret_cast<T*>(base + used);
+    used += bytes;
     return KDSS_OK;
   }
 };
 
+// The pieces of one sampling call; with c.base == nullptr only the size is summed.
+template <class F>
+void sample_pieces(Carve& c, uint32_t n, uint64_t nnz, uint32_t k, uint64_t t, F&& bind) {
+  const uint32_t nb = (n + kSampleTile - 1) / kSampleTile;
+  uint64_t* rp = nullptr;
+  uint32_t *col = nullptr, *dcolor = nullptr, *dout = nullptr;
+  u128 *P = nullptr, *pre = nullptr, *bs = nullptr;
+  uint64_t* draws = nullptr;
+  uint8_t* dvalid = nullptr;
+  int* ovf = nullptr;
+  c.take(&rp, (size_t)n + 1);
+  c.take(&col, nnz);
+  c.take(&dcolor, n);
+  c.take(&P, (size_t)(k + 1) * n);
+  c.take(&pre, n);
+  c.take(&bs, nb);
+  c.take(&draws, (size_t)2 * t * k);
+  c.take(&dout, (size_t)t * k);
+  c.take(&dvalid, t);
+  c.take(&ovf, 1);
+  bind(rp, col, dcolor, P, pre, bs, draws, dout, dvalid, ovf, nb);
+}
+
 }  // namespace
 
-extern "C" int kdss_sample_build(const kdss_csr* g, uint32_t k, uint64_t t, const uint64_t* h_draws, void* stream,
-                                 kdss_sample_info* info, kdss_sct** out) {
+extern "C" int kdss_sample_workspace(uint32_t n, uint64_t nnz, uint32_t k, uint64_t t, size_t* bytes) {
+  if (!bytes) return kdss::fail(KDSS_EINVAL, "null argument");
+  if (k < 2) return kdss::fail(KDSS_EINVAL, "k must be at least 2");
+  if (k > kdss::kMaxK) return kdss::fail(KDSS_ERANGE, "k above 31");
+  Carve c{nullptr, 0, 0};
+  if (n > 0 && t > 0) sample_pieces(c, n, nnz, k, t, [](auto...) {});
+  *bytes = c.used;
+  return KDSS_OK;
+}
+
+extern "C" int kdss_sample_build(const kdss_csr* g, uint32_t k, uint64_t t, const uint64_t* h_draws, void* d_ws,
+                                 size_t ws_bytes, void* stream, kdss_sample_info* info, kdss_sct** out) {
   using clock = std::chrono::steady_clock;
   if (!g || !out || (t && !h_draws)) return kdss::fail(KDSS_EINVAL, "null argument");
   if (k < 2) return kdss::fail(KDSS_EINVAL, "k must be at least 2");
   if (k > kdss::kMaxK) return kdss::fail(KDSS_ERANGE, "k above 31");
   int rc = kdss::validate_csr(g);
   if (rc) return rc;
+  size_t need = 0;
+  rc = kdss_sample_workspace(g->n, g->nnz, k, t, &need);
+  if (rc) return rc;
+  if (need > 0 && (!d_ws || ws_bytes < need))
+    return kdss::fail(KDSS_EWORKSPACE, "sampler workspace smaller than kdss_sample_workspace() reports");
   const auto t0 = clock::now();
   hipStream_t st = static_cast<hipStream_t>(stream);
   const uint32_t n = g->n;
@@ -229,19 +277,19 @@ extern "C" int kdss_sample_build(const kdss_csr* g, uint32_t k, uint64_t t, cons
   std::vector<uint8_t> valid(t);
   double dev_s = 0.0;
   if (n > 0 && t > 0) {
-    DeviceBuffers B;
     uint64_t* rp = nullptr;
     uint32_t *col = nullptr, *dcolor = nullptr, *dout = nullptr;
     u128 *P = nullptr, *pre = nullptr, *bs = nullptr;
     uint64_t* draws = nullptr;
     uint8_t* dvalid = nullptr;
     int* ovf = nullptr;
-    const uint32_t nb = (n + kSampleTile - 1) / kSampleTile;
-    if ((rc = B.alloc(&rp, (size_t)n + 1)) || (rc = B.alloc(&col, g->nnz)) || (rc = B.alloc(&dcolor, n)) ||
-        (rc = B.alloc(&P, (size_t)(k + 1) * n)) || (rc = B.alloc(&pre, n)) || (rc = B.alloc(&bs, nb)) ||
-        (rc = B.alloc(&draws, (size_t)2 * t * k)) || (rc = B.alloc(&dout, (size_t)t * k)) ||
-        (rc = B.alloc(&dvalid, t)) || (rc = B.alloc(&ovf, 1)))
-      return rc;
+    uint32_t nb = 0;
+    Carve c{static_cast<char*>(d_ws), ws_bytes, 0};
+    sample_pieces(c, n, g->nnz, k, t, [&](auto rp_, auto col_, auto dcolor_, auto P_, auto pre_, auto bs_,
+                                          auto draws_, auto dout_, auto dvalid_, auto ovf_, uint32_t nb_) {
+      rp = rp_; col = col_; dcolor = dcolor_; P = P_; pre = pre_; bs = bs_; draws = draws_; dout = dout_;
+      dvalid = dvalid_; ovf = ovf_; nb = nb_;
+    });
     SAMPLE_TRY(hipMemcpyAsync(rp, g->row_ptr, ((size_t)n + 1) * 8, hipMemcpyHostToDevice, st), "upload graph");
     if (g->nnz) SAMPLE_TRY(hipMemcpyAsync(col, g->col, g->nnz * 4, hipMemcpyHostToDevice, st), "upload graph");
     SAMPLE_TRY(hipMemcpyAsync(dcolor, color.data(), (size_t)n * 4, hipMemcpyHostToDevice, st), "upload colours");
@@ -254,8 +302,8 @@ extern "C" int kdss_sample_build(const kdss_csr* g, uint32_t k, uint64_t t, cons
     const uint32_t grid = std::min<uint32_t>((n + 255) / 256, 8192);
     for (uint32_t j = 2; j <= k; ++j)
       path_count_kernel<<<grid, 256, 0, st>>>(rp, col, dcolor, n, P + (size_t)(j - 1) * n, P + (size_t)j * n, ovf);
-    prefix_blocksum_kernel<<<nb, kSampleThreads, 0, st>>>(P + (size_t)k * n, n, bs);
-    prefix_scan_kernel<<<1, 64, 0, st>>>(bs, nb);
+    prefix_blocksum_kernel<<<nb, kSampleThreads, 0, st>>>(P + (size_t)k * n, n, bs, ovf);
+    prefix_scan_kernel<<<1, 64, 0, st>>>(bs, nb, ovf);
     prefix_write_kernel<<<nb, kSampleThreads, 0, st>>>(P + (size_t)k * n, n, bs, pre);
     SAMPLE_TRY(hipGetLastError(), "path count launch");
     u128 total = 0;
@@ -263,7 +311,7 @@ extern "C" int kdss_sample_build(const kdss_csr* g, uint32_t k, uint64_t t, cons
     SAMPLE_TRY(hipMemcpyAsync(&total, pre + (n - 1), 16, hipMemcpyDeviceToHost, st), "read total");
     SAMPLE_TRY(hipMemcpyAsync(&overflow, ovf, sizeof(int), hipMemcpyDeviceToHost, st), "read flag");
     SAMPLE_TRY(hipStreamSynchronize(st), "stream synchronize");
-    // the prefix sums wrap past 2^128 only if a path count did or the total does
+    // a path count, a block sum or the running total of the block sums wrapped
     if (overflow) return kdss::fail(KDSS_EOVERFLOW, "2^128 or more colour-increasing paths");
     inf.paths.lo = (uint64_t)total;
     inf.paths.hi = (uint64_t)(total >> 64);

@@ -438,7 +438,60 @@ void launch_task(hipStream_t st, const uint64_t* orp, const uint32_t* ocol, cons
 
 }  // namespace
 
-extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, kdss_sct** out) {
+// The build's device buffers are carved, 256-byte aligned, from the caller's
+// workspace in the order they are needed; the leaves are written through a
+// staging window (what is left at the end) chunk by chunk.
+struct WsCarve {
+  char* base;
+  size_t cap, used;
+  size_t left() const { return used < cap ? cap - used : 0; }
+  int take(void** p, size_t bytes) {
+    const size_t b = (std::max<size_t>(bytes, 8) + 255) & ~(size_t)255;
+    if (used + b > cap)
+      return kdss::fail(KDSS_EWORKSPACE, "GPU tree build workspace too small (" + std::to_string(used + b) +
+                                             " bytes needed so far, " + std::to_string(cap) + " given)");
+    *p = base + used;
+    used += b;
+    return KDSS_OK;
+  }
+};
+
+constexpr size_t kSctStaging = size_t(512) << 20;   // suggested staging window for the leaves
+
+// Per task thread: the recursion's scratch plus its count and offset entries.
+inline size_t sct_task_bytes(uint32_t D, uint32_t W) { return sct_words64(D, W) * 8 + sct_words32(D) * 4 + 32; }
+
+extern "C" int kdss_sct_build_gpu_workspace(const kdss_csr* g, uint32_t k, size_t* bytes) {
+  if (!g || !bytes) return kdss::fail(KDSS_EINVAL, "null argument");
+  if (k < 2) return kdss::fail(KDSS_EINVAL, "k must be at least 2");
+  if (k > kdss::kMaxK) return kdss::fail(KDSS_ERANGE, "k must be at most 31");
+  int rc = kdss::validate_csr(g);
+  if (rc) return rc;
+  kdss::Degeneracy deg;
+  kdss::degeneracy_order(g, &deg);   // the device peeling reaches the same degeneracy
+  const uint32_t D = deg.degeneracy;
+  if (D > kSctMaxLocal) return kdss::fail(KDSS_EUNSUPPORTED, "the GPU tree build handles degeneracy up to 256");
+  const uint32_t W = std::max<uint32_t>(1, (D + 63) / 64);
+  const uint64_t n = g->n, nnz = g->nnz;
+  auto al = [](size_t b) { return (std::max<size_t>(b, 8) + 255) & ~(size_t)255; };
+  const uint64_t ntile = (n + kPeelTile - 1) / kPeelTile;
+  size_t sz = al((n + 1) * 8) + al(nnz * 4) + 3 * al(n * 4) + al((n + 1) * 8) + al(nnz / 2 * 4) + al(n * 4) + al(4) +
+              3 * al(n * 4) + 2 * al(ntile * 4);
+  // roots: bitsets of the later neighbours (out-degrees sum to nnz / 2), offsets, pivots, task counts
+  sz += al(nnz / 2 * W * 8) + al((n + 1) * 8) + 2 * al(n * 4) + al((n + 1) * 8);
+  // tasks: at most one per later neighbour plus the pivot child of each start node
+  const uint64_t ntask = nnz / 2 + n;
+  sz += al(ntask * 8);
+  const uint64_t chunk = std::max<uint64_t>(64, std::min<uint64_t>(std::max<uint64_t>(ntask, 1),
+                                                                     kSctScratchBudget / sct_task_bytes(D, W)));
+  sz += 5 * 256 + chunk * sct_task_bytes(D, W);
+  sz += kSctStaging;
+  *bytes = sz;
+  return KDSS_OK;
+}
+
+extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* d_ws, size_t ws_bytes, void* stream,
+                                  kdss_sct** out) {
   using clock = std::chrono::steady_clock;
   if (!g || !out) return kdss::fail(KDSS_EINVAL, "null argument");
   if (k < 2) return kdss::fail(KDSS_EINVAL, "k must be at least 2");
@@ -446,6 +499,7 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
   const auto t0 = clock::now();   // the build time includes the graph check, as the host build's does
   int rc = kdss::validate_csr(g);
   if (rc) return rc;
+  if (!d_ws) return kdss::fail(KDSS_EWORKSPACE, "null workspace (see kdss_sct_build_gpu_workspace)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   kdss_sct* s = new (std::nothrow) kdss_sct();
   if (!s) return kdss::fail(KDSS_ENOMEM, "cannot allocate the tree handle");
@@ -454,15 +508,9 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
   T.n = n;
   T.k = k;
   uint32_t D = 0, W = 1;   // the degeneracy and the bitset words, known after the peeling
-  std::vector<void*> bufs;
-  auto cleanup = [&]() {
-    for (void* p : bufs) (void)hipFree(p);
-  };
-  auto alloc = [&](void** p, size_t bytes) -> int {
-    if (hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) return kdss::fail(KDSS_ENOMEM, "device memory");
-    bufs.push_back(*p);
-    return KDSS_OK;
-  };
+  WsCarve carve{static_cast<char*>(d_ws), ws_bytes, 0};
+  auto cleanup = [&]() {};
+  auto alloc = [&](void** p, size_t bytes) -> int { return carve.take(p, bytes); };
   auto run = [&]() -> int {
     uint64_t *rp = nullptr, *orp = nullptr;
     uint32_t *col = nullptr, *rank = nullptr, *ocnt = nullptr, *ocol = nullptr, *perm = nullptr;
@@ -596,10 +644,12 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
     if ((r = alloc((void**)&tasks, ntask * 8))) return r;
     SCT_TRY(hipMemcpyAsync(toff, to.data(), ((size_t)active + 1) * 8, hipMemcpyHostToDevice, st), "upload offsets");
     SCT_TRY(roots(1), "tree root launch");
-    // scratch for one chunk of tasks
-    const size_t per_thread = sct_words64(D, W) * 8 + sct_words32(D) * 4;
+    // scratch for one chunk of tasks: up to half of what is left (the rest
+    // stages the leaves), at least 64 tasks
+    const size_t per_task = sct_task_bytes(D, W);
+    const uint64_t fit = carve.left() > 6 * 256 ? (carve.left() / 2 - 6 * 256) / per_task : 0;
     const uint32_t chunk = (uint32_t)std::max<uint64_t>(
-        64, std::min<uint64_t>(std::max<uint64_t>(ntask, 1), kSctScratchBudget / per_thread));
+        64, std::min<uint64_t>({std::max<uint64_t>(ntask, 1), kSctScratchBudget / per_task, fit}));
     uint64_t *s64 = nullptr, *dcounts = nullptr, *loff = nullptr, *moff = nullptr;
     uint32_t *s32 = nullptr, *dhp = nullptr, *dmem = nullptr;
     if ((r = alloc((void**)&s64, (size_t)chunk * sct_words64(D, W) * 8)) ||
@@ -634,20 +684,39 @@ extern "C" int kdss_sct_build_gpu(const kdss_csr* g, uint32_t k, void* stream, k
     }
     const uint64_t L = lo[ntask], M = mo[ntask];
     if (L >= (1ull << 40)) return kdss::fail(KDSS_ERANGE, "more than 2^40 leaves");
-    if ((r = alloc((void**)&dhp, L * 4)) || (r = alloc((void**)&dmem, M * 4))) return r;
-    // pass 2: the leaves at their offsets (offsets of the chunk's tasks)
-    for (uint64_t v0 = 0; v0 < ntask; v0 += chunk) {
-      const uint32_t c = (uint32_t)std::min<uint64_t>(chunk, ntask - v0);
-      SCT_TRY(hipMemcpyAsync(loff, lo.data() + v0, (size_t)c * 8, hipMemcpyHostToDevice, st), "upload offsets");
-      SCT_TRY(hipMemcpyAsync(moff, mo.data() + v0, (size_t)c * 8, hipMemcpyHostToDevice, st), "upload offsets");
-      SCT_TRY(launch(v0, c, 1, dhp, dmem), "tree write launch");
-      SCT_TRY(hipStreamSynchronize(st), "stream synchronize");   // the device offset buffers are reused
-    }
+    // pass 2: chunks of tasks whose leaves fit the staging window write them
+    // there (offsets relative to the chunk's first task); each chunk is then
+    // copied to its place in the host arrays
+    char* stage = carve.base + carve.used;
+    const size_t stage_bytes = carve.left();
     std::vector<uint32_t> hpv(L);
     T.members.resize(M);
-    if (L) SCT_TRY(hipMemcpyAsync(hpv.data(), dhp, L * 4, hipMemcpyDeviceToHost, st), "read leaves");
-    if (M) SCT_TRY(hipMemcpyAsync(T.members.data(), dmem, M * 4, hipMemcpyDeviceToHost, st), "read leaves");
-    SCT_TRY(hipStreamSynchronize(st), "stream synchronize");
+    std::vector<uint64_t> rl(chunk), rm(chunk);
+    for (uint64_t v0 = 0; v0 < ntask;) {
+      uint64_t v1 = v0;
+      auto need = [&](uint64_t e) { return ((lo[e] - lo[v0]) * 4 + 255) / 256 * 256 + (mo[e] - mo[v0]) * 4; };
+      while (v1 < ntask && v1 - v0 < chunk && need(v1 + 1) <= stage_bytes) ++v1;
+      if (v1 == v0)
+        return kdss::fail(KDSS_EWORKSPACE, "GPU tree build workspace too small: one root child's leaves need " +
+                                               std::to_string(need(v0 + 1)) + " staging bytes, " +
+                                               std::to_string(stage_bytes) + " left");
+      const uint32_t c = (uint32_t)(v1 - v0);
+      const uint64_t dl = lo[v1] - lo[v0], dm = mo[v1] - mo[v0];
+      dhp = reinterpret_cast<uint32_t*>(stage);
+      dmem = reinterpret_cast<uint32_t*>(stage + (dl * 4 + 255) / 256 * 256);
+      for (uint32_t x = 0; x < c; ++x) {
+        rl[x] = lo[v0 + x] - lo[v0];
+        rm[x] = mo[v0 + x] - mo[v0];
+      }
+      SCT_TRY(hipMemcpyAsync(loff, rl.data(), (size_t)c * 8, hipMemcpyHostToDevice, st), "upload offsets");
+      SCT_TRY(hipMemcpyAsync(moff, rm.data(), (size_t)c * 8, hipMemcpyHostToDevice, st), "upload offsets");
+      SCT_TRY(launch(v0, c, 1, dhp, dmem), "tree write launch");
+      if (dl) SCT_TRY(hipMemcpyAsync(hpv.data() + lo[v0], dhp, dl * 4, hipMemcpyDeviceToHost, st), "read leaves");
+      if (dm)
+        SCT_TRY(hipMemcpyAsync(T.members.data() + mo[v0], dmem, dm * 4, hipMemcpyDeviceToHost, st), "read leaves");
+      SCT_TRY(hipStreamSynchronize(st), "stream synchronize");   // offsets and staging are reused
+      v0 = v1;
+    }
     T.h.resize(L);
     T.p.resize(L);
     T.off.resize(L + 1);

@@ -93,7 +93,7 @@ EXPORTS = [
     "kdss_batch_create", "kdss_batch_offsets", "kdss_batch_run", "kdss_plan_set_launch", "kdss_plan_autotune",
     "kdss_sample_build", "kdss_sct_build_gpu", "kdss_workspace_size", "kdss_solve", "kdss_run_resume",
     "kdss_extract_counts", "kdss_batch_free", "kdss_run_static", "kdss_sct_count", "kdss_plan_tune_key",
-    "kdss_plan_autotune_cached", "kdss_plan_set_timing",
+    "kdss_plan_autotune_cached", "kdss_plan_set_timing", "kdss_sample_workspace", "kdss_sct_build_gpu_workspace",
 ]
 
 TUNE_CACHE = os.path.join(_HERE, "tune_cache.txt")   # launches tuned on MI355X, keyed by plan shape
@@ -126,9 +126,11 @@ def lib():
     L.kdss_sct_export.argtypes = [vp, p32, p32, p32, C.c_uint64, C.c_uint64]
     L.kdss_sct_core_numbers.argtypes = [vp, p32, C.c_uint32]
     L.kdss_sct_free.argtypes = [vp]
-    L.kdss_sct_build_gpu.argtypes = [C.POINTER(Csr), C.c_uint32, vp, C.POINTER(vp)]
-    L.kdss_sample_build.argtypes = [C.POINTER(Csr), C.c_uint32, C.c_uint64, p64, vp, C.POINTER(SampleInfo),
-                                    C.POINTER(vp)]
+    L.kdss_sct_build_gpu.argtypes = [C.POINTER(Csr), C.c_uint32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.kdss_sct_build_gpu_workspace.argtypes = [C.POINTER(Csr), C.c_uint32, C.POINTER(C.c_size_t)]
+    L.kdss_sample_build.argtypes = [C.POINTER(Csr), C.c_uint32, C.c_uint64, p64, vp, C.c_size_t, vp,
+                                    C.POINTER(SampleInfo), C.POINTER(vp)]
+    L.kdss_sample_workspace.argtypes = [C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint64, C.POINTER(C.c_size_t)]
     L.kdss_sct_free.restype = None
     L.kdss_plan_create.argtypes = [vp, C.c_uint32, C.c_uint64, C.POINTER(Opts), C.POINTER(vp)]
     L.kdss_plan_info.argtypes = [vp, C.POINTER(PlanStats)]
@@ -244,14 +246,21 @@ class Tree:
 
 
 class GpuTree(Tree):
-    """The k-pruned succinct clique tree built on the GPU (kdss_sct_build_gpu)."""
+    """The k-pruned succinct clique tree built on the GPU (kdss_sct_build_gpu),
+    in a workspace of ws_bytes (default: kdss_sct_build_gpu_workspace's size)."""
 
-    def __init__(self, graph, k: int, stream=None):
+    def __init__(self, graph, k: int, stream=None, ws_bytes: int | None = None):
+        import torch
         c, keep = _csr(graph)
         h = C.c_void_p()
-        _check(lib().kdss_sct_build_gpu(C.byref(c), k, _stream(stream) if stream is not None else None,
-                                        C.byref(h)),
+        need = C.c_size_t(0)
+        _check(lib().kdss_sct_build_gpu_workspace(C.byref(c), k, C.byref(need)), "kdss_sct_build_gpu_workspace")
+        nbytes = need.value if ws_bytes is None else ws_bytes
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+        _check(lib().kdss_sct_build_gpu(C.byref(c), k, _ptr(ws), nbytes,
+                                        _stream(stream) if stream is not None else None, C.byref(h)),
                "kdss_sct_build_gpu")
+        del ws
         self._h = h
         self.n, self.k = graph.n, k
 
@@ -267,8 +276,15 @@ class SampleTree(Tree):
         t = d.shape[0] if d.size else 0
         h = C.c_void_p()
         info = SampleInfo()
+        need = C.c_size_t(0)
+        _check(lib().kdss_sample_workspace(graph.n, int(c.nnz), k, t, C.byref(need)), "kdss_sample_workspace")
+        ws = None
+        if need.value:
+            import torch
+            ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
         _check(lib().kdss_sample_build(C.byref(c), k, t, d.ctypes.data_as(C.POINTER(C.c_uint64)) if t else None,
-                                       _stream(stream) if t else None, C.byref(info), C.byref(h)),
+                                       _ptr(ws), need.value, _stream(stream) if t else None, C.byref(info),
+                                       C.byref(h)),
                "kdss_sample_build")
         self._h = h
         self.n, self.k = graph.n, k

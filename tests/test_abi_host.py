@@ -239,9 +239,20 @@ def test_sample_build_arguments_and_empty_sample():
     c, keep = kdss._csr(g)
     L = kdss.lib()
     h = C.c_void_p()
-    assert L.kdss_sample_build(C.byref(c), 4, 5, None, None, None, C.byref(h)) == kdss.EINVAL   # no draws
-    assert L.kdss_sample_build(C.byref(c), 1, 0, None, None, None, C.byref(h)) == kdss.EINVAL   # k < 2
-    assert L.kdss_sample_build(C.byref(c), 32, 0, None, None, None, C.byref(h)) == kdss.ERANGE  # k > 31
+    assert L.kdss_sample_build(C.byref(c), 4, 5, None, None, 0, None, None, C.byref(h)) == kdss.EINVAL  # no draws
+    assert L.kdss_sample_build(C.byref(c), 1, 0, None, None, 0, None, None, C.byref(h)) == kdss.EINVAL  # k < 2
+    assert L.kdss_sample_build(C.byref(c), 32, 0, None, None, 0, None, None, C.byref(h)) == kdss.ERANGE  # k > 31
+    # the workspace: graph, k + 1 rows of 128-bit path counts, prefix sums, draws, walks
+    need = C.c_size_t(0)
+    assert L.kdss_sample_workspace(g.n, int(c.nnz), 4, 5, C.byref(need)) == 0
+    al = lambda b: (b + 255) // 256 * 256
+    n, nnz, nb = g.n, int(c.nnz), (g.n + 1023) // 1024
+    assert need.value == sum(al(x) for x in (8 * (n + 1), 4 * nnz, 4 * n, 16 * 5 * n, 16 * n, 16 * nb,
+                                             16 * 5 * 4, 4 * 5 * 4, 5, 4))
+    assert L.kdss_sample_workspace(g.n, int(c.nnz), 4, 0, C.byref(need)) == 0 and need.value == 0
+    draws = np.ones(5 * 4 * 2, dtype=np.uint64)
+    assert L.kdss_sample_build(C.byref(c), 4, 5, draws.ctypes.data_as(C.POINTER(C.c_uint64)), None, 0, None, None,
+                               C.byref(h)) == kdss.EWORKSPACE
     # no samples: no device work, an empty tree with no core numbers
     t = kdss.SampleTree(g, 4, np.zeros((0, 4, 2), dtype=np.uint64))
     st = t.stats()

@@ -4,8 +4,8 @@
   whole problem (its clique listing fits in memory), so loads, order, density,
   upper bound and every prefix count K_i are compared bit for bit.
 * The 2048-problem batch (512 Chung-Lu graphs x k in {3, 4, 6, 8}, T = 64, one
-  plan, autotuned grids, hipGraph iterations): eight sampled problems, each
-  solved by the oracle on its own.
+  plan, the bench's tuned launch): every problem equals its solo run, and the
+  oracle on every problem with at most 2e5 k-cliques (about 750).
 * The warm-start evaluation graph (n = 2,000,000, m = 40,000,000, k = 6) and
   R-MAT scale 16 (k = 6): too many cliques for the oracle, so properties that
   hold at any size are checked: Lemma 6 (the loads grow by exactly T c_k),
@@ -93,7 +93,11 @@ def test_chung_lu_1m_bit_exact(K, oracle_mod):
     tree.close()
 
 
-def test_batch_512_sampled(K, oracle_mod):
+def test_batch_512_every_problem(K, oracle_mod):
+    """The full batch in the bench's launch (tuning cache), every one of its
+    2048 problems against its own solo run (loads, order, i*, K_{i*}, upper
+    bound), and against the oracle on every problem with at most 2e5 k-cliques
+    (about 750 problems; the oracle finishes each in a fraction of a second)."""
     from paper_2403_05775_amd import gnn
     say("batch 512 x 4: generating")
     graphs = gnn.generate(512, base_seed=1000, n_lo=1000, n_hi=50000, workers=16, log=lambda *_: None)
@@ -101,33 +105,45 @@ def test_batch_512_sampled(K, oracle_mod):
     trees = [K.Tree(g, k) for g, k in jobs]
     T = 64
     say("batch 512 x 4: plan and run")
-    b = K.Batch(trees, T, use_graph=True)
+    b = K.Batch(trees, T)
     ws = b.alloc_workspace()
     b.upload(ws)
     r = torch.empty(b.n, dtype=torch.int64, device="cuda")
     order = torch.empty(b.n, dtype=torch.int32, device="cuda")
-    b.autotune(ws, r, warm=2, iters=2)
+    b.autotune_cached(ws, r, warm=T // 2, iters=5)
     res = b.run(ws, T, r, order)
     torch.cuda.synchronize()
     rr = r.cpu().numpy().view(np.uint64)
     oo = order.cpu().numpy().view(np.uint32)
     off = b.node_off.astype(np.int64)
-    # eight problems the oracle finishes in seconds: for each k, the smallest
-    # and the largest clique count up to 2e7
-    ck = np.array([t.stats().c_k.value for t in trees], dtype=np.float64)
-    picks = []
-    for k in (3, 4, 6, 8):
-        idx = [q for q, (_, kk) in enumerate(jobs) if kk == k and 0 < ck[q] <= 2e7]
-        idx.sort(key=lambda q: ck[q])
-        picks += [idx[0], idx[-1]]
-    for q in picks:
-        g, k = jobs[q]
-        say(f"batch problem {q} (n={g.n}, k={k}, c_k={int(ck[q])}): oracle")
-        ref = oracle_mod.solve(g.n, g.row_ptr, g.col, k, T)
-        assert rr[off[q]:off[q + 1]].tolist() == loads(ref["r"]), q
-        assert np.array_equal(oo[off[q]:off[q + 1]], ref["order"]), q
-        assert (res[q].size, res[q].dens_num.value, res[q].ub_num.value) == (ref["size"], ref["dens_num"],
-                                                                              ref["ub_num"]), q
+    del ws
+    b.close()
+    torch.cuda.empty_cache()
+    ck = [t.stats().c_k.value for t in trees]
+    checked = 0
+    for q, (g, k) in enumerate(jobs):
+        if q % 256 == 0:
+            say(f"batch problem {q}: solo runs")
+        plan = K.Plan(trees[q], T)
+        pws = plan.alloc_workspace()
+        plan.upload(pws)
+        pr = plan.alloc_loads()
+        po = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda")
+        sres, _ = plan.run(pws, T, pr, po)
+        torch.cuda.synchronize()
+        assert np.array_equal(rr[off[q]:off[q + 1]], pr.cpu().numpy().view(np.uint64)[: g.n]), q
+        assert np.array_equal(oo[off[q]:off[q + 1]], po.cpu().numpy().view(np.uint32)[: g.n]), q
+        assert (res[q].size, res[q].dens_num.value, res[q].ub_num.value) == \
+            (sres.size, sres.dens_num.value, sres.ub_num.value), q
+        plan.close()
+        if 0 < ck[q] <= 200_000:
+            ref = oracle_mod.solve(g.n, g.row_ptr, g.col, k, T, threads=16)
+            assert rr[off[q]:off[q + 1]].tolist() == loads(ref["r"]), q
+            assert (res[q].size, res[q].dens_num.value, res[q].ub_num.value) == \
+                (ref["size"], ref["dens_num"], ref["ub_num"]), q
+            checked += 1
+    say(f"batch: {len(jobs)} problems equal their solo runs; {checked} also equal the oracle")
+    assert checked >= 500
     for t in trees:
         t.close()
 

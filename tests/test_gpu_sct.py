@@ -166,3 +166,35 @@ def test_gpu_tree_core_numbers(K, seed):
     assert gpu.stats().c_k.value == host.stats().c_k.value
     host.close()
     gpu.close()
+
+
+def test_gpu_tree_small_workspace_stages_in_chunks(K):
+    """Workspaces far below the suggested size (about 7 MB of fixed parts here,
+    3.9 MB of leaves): the recursion runs in smaller chunks and the leaves come
+    back through a small staging window in several chunks; every tree built
+    equals the one built with the suggested size.  Sizes too small for the fixed
+    parts or for one root child's leaves are refused with KDSS_EWORKSPACE."""
+    g = synth.chung_lu(20000, 200000, 2.3, seed=61, planted=30)
+    k = 4
+    big = K.GpuTree(g, k)
+    hb, pb, mb = big.export()
+    ck = big.stats().c_k.value
+    ok = 0
+    for mib in (12, 10, 9, 8, 7.5, 7):
+        nbytes = int(mib * (1 << 20))
+        print(f"gpu tree with {nbytes} workspace bytes", flush=True)
+        try:
+            small = K.GpuTree(g, k, ws_bytes=nbytes)
+        except K.KdssError as e:
+            assert e.status == K.EWORKSPACE
+            continue
+        hs, ps, ms = small.export()
+        assert np.array_equal(hs, hb) and np.array_equal(ps, pb) and np.array_equal(ms, mb)
+        assert small.stats().c_k.value == ck
+        small.close()
+        ok += 1
+    assert ok >= 2
+    with pytest.raises(K.KdssError) as e:
+        K.GpuTree(g, k, ws_bytes=1 << 16)
+    assert e.value.status == K.EWORKSPACE
+    big.close()
