@@ -362,7 +362,8 @@ def gnn_bench(w, args):
 
     # warm traces: the model's start and the start taken from the reference loads
     dg = gnn.DeviceGraph.resident(n, rp, col, nnz)
-    dg.x0 = gnn.features(tree, rp, col, nnz)
+    fset = int(meta.get("meta_feature_set", 0))
+    dg.x0 = gnn.features(tree, rp, col, nnz, fset)
     r0, rmax = model.warm_start(dg, t0)
     r0_ideal = torch.from_numpy(ideal.view(np.int64)).to(dev)
     pw = kdss.Plan(tree, Tref, r0_max=max(rmax, int(ideal.max())), extract_every=1)
@@ -405,7 +406,7 @@ def gnn_bench(w, args):
 
     def warm_once(split=False):
         ev[0].record()
-        dg.x0 = gnn.features(tree, rp, col, nnz)
+        dg.x0 = gnn.features(tree, rp, col, nnz, fset)
         ev[1].record()
         r0w, _ = model.warm_start(dg, t0, sync=False)
         ev[2].record()

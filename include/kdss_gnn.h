@@ -14,7 +14,8 @@
  *   h3 = ReLU([h2 | mean_N(h2)] W3 + b3)      (K = 128)
  *   y  = h3 w + b                             (FP32)
  * Every product runs on the matrix cores with BF16 operands and FP32
- * accumulation (v_mfma_f32_32x32x8_bf16); FP32 -> BF16 rounds to nearest even.
+ * accumulation (gfx950's v_mfma_f32_32x32x16_bf16, 16 k per instruction);
+ * FP32 -> BF16 rounds to nearest even.
  *
  * Conventions as in kdss.h: device pointers are caller-owned, work is
  * enqueued on `stream` (a hipStream_t), status codes are kdss.h's.  Row-major
@@ -35,7 +36,9 @@ extern "C" {
 int kdss_gnn_features_workspace(uint32_t n, uint64_t nnz, size_t *bytes);
 
 /* x0 (device, n x 8 BF16) = [log1p(degree), log1p(core number),
- * log1p(triangles through the node), 0, ...] for the tree's graph, n = the
+ * log1p(triangles through the node), 0, ...] for the tree's graph (feature_set
+ * 0), or the same with the triangle column 0 and no triangle counting
+ * (feature_set 1), n = the
  * tree's node count.  d_row_ptr (u64[n + 1]) and d_col (u32[nnz]) are that
  * graph's CSR on the device; edges past nnz and ids >= n are ignored.  Core
  * numbers and the degeneracy order come from the tree's host build and are
@@ -43,7 +46,7 @@ int kdss_gnn_features_workspace(uint32_t n, uint64_t nnz, size_t *bytes);
  * with out-degree <= degeneracy), the DAG's row offsets are scanned, and the
  * triangles are counted by intersecting out-neighbour lists.  Enqueued only. */
 int kdss_gnn_features(const kdss_sct *s, const uint64_t *d_row_ptr, const uint32_t *d_col, uint64_t nnz,
-                      uint16_t *d_x0, void *d_ws, size_t ws_bytes, void *stream);
+                      int feature_set, uint16_t *d_x0, void *d_ws, size_t ws_bytes, void *stream);
 
 /* out[u] = mean over neighbours v of h[v] (F = 8, 16, 32 or 64 columns; 0 for isolated nodes). */
 int kdss_gnn_aggregate(uint32_t n, const uint64_t *d_row_ptr, const uint32_t *d_col, const uint16_t *d_h,
@@ -56,8 +59,9 @@ int kdss_gnn_aggregate_backward(uint32_t n, const uint64_t *d_row_ptr, const uin
                                 uint16_t *d_out, void *stream);
 
 /* Y[M x 64] (leading dim ldy) = act([A1 | A2] Bt^T + bias): A1 has K1 columns,
- * A2 K2 (multiples of 8, K1 + K2 <= 128), Bt is 64 x (K1 + K2) BF16, bias
- * (nullable) 64 FP32, act = ReLU when relu != 0. */
+ * A2 K2 (multiples of 8, K1 + K2 a multiple of 16 and at most 128; leading
+ * dims multiples of 8; A1, A2 and Bt 16-byte aligned), Bt is 64 x (K1 + K2)
+ * BF16, bias (nullable) 64 FP32, act = ReLU when relu != 0. */
 int kdss_gnn_linear(uint32_t M, const uint16_t *d_a1, uint32_t K1, uint32_t lda1, const uint16_t *d_a2,
                     uint32_t K2, uint32_t lda2, const uint16_t *d_bt, const float *d_bias, int relu,
                     uint16_t *d_y, uint32_t ldy, void *stream);
@@ -91,6 +95,48 @@ int kdss_gnn_pack_weights(uint32_t K, const float *d_w32, uint16_t *d_w, uint16_
  * (clear *d_rmax first). */
 int kdss_gnn_warm_start(uint32_t n, const float *d_pred, double t0, uint64_t cap, uint64_t *d_r0,
                         uint64_t *d_rmax, void *stream);
+
+/* ---- the whole model in one call (the start loads of Algorithm 2's
+ * "initialize r(u)"; Frank-Wolfe itself is unchanged) ----
+ * Parameters: one FP32 array of KDSS_GNN_PARAMS values (device, caller-owned):
+ * W1 (16 x 64, row k = input column k: 8 self then 8 neighbour-mean columns),
+ * b1, W2 (128 x 64), b2, W3 (128 x 64), b3, then the head w (64) and its bias. */
+#define KDSS_GNN_W1 0
+#define KDSS_GNN_B1 1024
+#define KDSS_GNN_W2 1088
+#define KDSS_GNN_B2 9280
+#define KDSS_GNN_W3 9344
+#define KDSS_GNN_B3 17536
+#define KDSS_GNN_HEAD 17600
+#define KDSS_GNN_PARAMS 17665
+
+/* Device workspace (bytes) of kdss_gnn_infer (train = 0) or
+ * kdss_gnn_train_step (train != 0) on n nodes: BF16 weight copies, per layer
+ * the neighbour means and outputs, the prediction, and for training the
+ * target, the activation gradients and the parameter gradient. */
+int kdss_gnn_model_workspace(uint32_t n, int train, size_t *bytes);
+
+/* Forward pass and warm start: y = head(h3), h_l = ReLU([h_{l-1} | mean_N(h_{l-1})] W_l + b_l),
+ * h0 = x0 (n x 8 BF16, 16-byte aligned, from kdss_gnn_features), then
+ * r0[u] = round(t0 * expm1(y[u])) clamped to [0, cap] into d_r0 (u64[n]) and
+ * max(*d_rmax, max r0) into *d_rmax.  d_pred (nullable, FP32[n]) receives y.
+ * d_ws (256-byte aligned) of kdss_gnn_model_workspace(n, 0) bytes.  Enqueued only.
+ * Errors: KDSS_EINVAL, KDSS_EWORKSPACE, KDSS_EHIP. */
+int kdss_gnn_infer(uint32_t n, const uint64_t *d_row_ptr, const uint32_t *d_col, const uint16_t *d_x0,
+                   const float *d_params, double t0, uint64_t cap, void *d_ws, size_t ws_bytes, float *d_pred,
+                   uint64_t *d_r0, uint64_t *d_rmax, void *stream);
+
+/* One training step on one graph: the target y = log1p(r / T) from a cold
+ * run's loads d_r (u64[n], T iterations), the forward pass, the mean squared
+ * error over the nodes (added into *d_loss, device FP32), the backward pass
+ * through the head, the three layers and the mean aggregation, and one Adam
+ * step (lr, betas 0.9 / 0.999, eps 1e-8, bias correction at `step` >= 1) on
+ * the KDSS_GNN_PARAMS parameters with moments d_m, d_v (device FP32, zero
+ * before step 1).  d_ws of kdss_gnn_model_workspace(n, 1) bytes.  Enqueued
+ * only.  Errors: KDSS_EINVAL, KDSS_EWORKSPACE, KDSS_EHIP. */
+int kdss_gnn_train_step(uint32_t n, const uint64_t *d_row_ptr, const uint32_t *d_col, const uint16_t *d_x0,
+                        const uint64_t *d_r, uint32_t T, float *d_params, float *d_m, float *d_v, uint32_t step,
+                        float lr, void *d_ws, size_t ws_bytes, float *d_loss, void *stream);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,6 @@
 // Warm-start model for the Frank-Wolfe loads: a small message-passing network
 // whose kernels run on gfx950 with BF16 operands and FP32 accumulation on the
-// matrix cores (v_mfma_f32_32x32x8_bf16).  The model only chooses the integer
+// matrix cores (v_mfma_f32_32x32x16_bf16).  The model only chooses the integer
 // start loads r0; the method's arithmetic is unchanged (a warm start is just
 // Algorithm 2's "initialize r(u)").
 //
@@ -21,8 +21,15 @@ using namespace kdss;
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// One 32x32 BF16 product step over 16 k on gfx950's matrix cores (FP32 accumulate).
+__device__ __forceinline__ f32x16 mfma16(s16x8 a, s16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
 
 // IEEE binary32 -> bfloat16, round to nearest, ties to even; NaN stays a quiet NaN.
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -386,10 +393,13 @@ __global__ __launch_bounds__(256) void aggregate_backward_kernel(uint32_t n, con
 
 // Y[row][c] = act(sum_k X[row][k] * Bt[c][k] + bias[c]), c < 64, where
 // X = [A1 (K1 columns, leading dim lda1) | A2 (K2 columns, lda2)], K = K1 + K2
-// <= 128, K1 and K2 multiples of 8.  A workgroup computes 128 rows; wavefront
-// w computes rows 32 w .. 32 w + 31 as two 32x32 tiles, 8 k per instruction.
-// Lane l holds A[l % 32][k0 + 4 (l / 32) .. + 3] and Bt[j0 + l % 32][k0 + 4 (l / 32) .. + 3];
-// accumulator v of lane l is row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
+// <= 128 a multiple of 16, K1 and K2 multiples of 8.  A workgroup computes 128
+// rows; wavefront w computes rows 32 w .. 32 w + 31 as two 32x32 tiles, 16 k
+// per instruction (v_mfma_f32_32x32x16_bf16).  Lane l holds
+// A[l % 32][k0 + 8 (l / 32) .. + 7] and Bt[j0 + l % 32][k0 + 8 (l / 32) .. + 7]
+// (one 16-byte load each; K1 is a multiple of 8, so a lane's eight k never
+// straddle A1 and A2); accumulator v of lane l is row 8 (v / 4) + 4 (l / 32) +
+// v % 4, column l % 32.
 __global__ __launch_bounds__(256) void gemm_bt_kernel(uint32_t M, const uint16_t* __restrict__ A1, uint32_t K1,
                                                       uint32_t lda1, const uint16_t* __restrict__ A2, uint32_t K2,
                                                       uint32_t lda2, const uint16_t* __restrict__ Bt,
@@ -400,20 +410,21 @@ __global__ __launch_bounds__(256) void gemm_bt_kernel(uint32_t M, const uint16_t
   for (uint32_t i = threadIdx.x; i < 64u * K; i += blockDim.x) sB[i] = Bt[i];
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  const uint32_t li = lane & 31u, kq = (lane >> 5) * 4u;
+  const uint32_t li = lane & 31u, kq = (lane >> 5) * 8u;
   const uint32_t row = blockIdx.x * 128u + w * 32u + li;
   const bool rv = row < M;
   f32x16 acc0 = {}, acc1 = {};
-  for (uint32_t k0 = 0; k0 < K; k0 += 8) {
-    bf16x4 a = {0, 0, 0, 0};
+  for (uint32_t k0 = 0; k0 < K; k0 += 16) {
+    const uint32_t kk = k0 + kq;
+    s16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
     if (rv) {
-      const uint16_t* src = k0 < K1 ? A1 + (size_t)row * lda1 + k0 + kq : A2 + (size_t)row * lda2 + (k0 - K1) + kq;
-      a = *reinterpret_cast<const bf16x4*>(src);
+      const uint16_t* src = kk < K1 ? A1 + (size_t)row * lda1 + kk : A2 + (size_t)row * lda2 + (kk - K1);
+      a = *reinterpret_cast<const s16x8*>(src);
     }
-    const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(&sB[li * K + k0 + kq]);
-    const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(&sB[(32u + li) * K + k0 + kq]);
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b0, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b1, acc1, 0, 0, 0);
+    const s16x8 b0 = *reinterpret_cast<const s16x8*>(&sB[li * K + kk]);
+    const s16x8 b1 = *reinterpret_cast<const s16x8*>(&sB[(32u + li) * K + kk]);
+    acc0 = mfma16(a, b0, acc0);
+    acc1 = mfma16(a, b1, acc1);
   }
   const uint32_t rbase = blockIdx.x * 128u + w * 32u;
 #pragma unroll
@@ -433,8 +444,9 @@ __global__ __launch_bounds__(256) void gemm_bt_kernel(uint32_t M, const uint16_t
 
 // dW[k][c] += sum_rows X[row][k] * dY[row][c];  db[c] += sum_rows dY[row][c].
 // Each workgroup takes a band of rows in chunks of 32 staged in LDS; the four
-// wavefronts own the K/32 x 2 output tiles; reduction over rows, 8 per MFMA:
-// A[i][r] = X[r][i0 + i], B[r][j] = dY[r][j0 + j].
+// wavefronts own the K/32 x 2 output tiles; reduction over rows, 16 per MFMA:
+// A[i][r] = X[r][i0 + i], B[r][j] = dY[r][j0 + j]; lane l supplies rows
+// r = kk + 8 (l / 32) .. + 7 of column i0 + l % 32 (and of dY column j0 + l % 32).
 __global__ __launch_bounds__(256) void gemm_wgrad_kernel(uint32_t M, const uint16_t* __restrict__ A1, uint32_t K1,
                                                          uint32_t lda1, const uint16_t* __restrict__ A2, uint32_t K2,
                                                          uint32_t lda2, const uint16_t* __restrict__ dY,
@@ -443,7 +455,7 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(uint32_t M, const uint1
   __shared__ __align__(16) uint16_t sD[32 * 64];
   const uint32_t K = K1 + K2;
   const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-  const uint32_t li = lane & 31u, rq = (lane >> 5) * 4u;
+  const uint32_t li = lane & 31u, rq = (lane >> 5) * 8u, vq = (lane >> 5) * 4u;
   const uint32_t ntile = ((K + 31u) / 32u) * 2u;   // 32-row tiles, the last one zero-padded
   f32x16 acc[2] = {{}, {}};
   float bsum = 0.f;
@@ -469,14 +481,14 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(uint32_t M, const uint1
       const uint32_t tile = w * 2u + t;
       if (tile >= ntile) continue;
       const uint32_t i0 = (tile >> 1) * 32u, j0 = (tile & 1u) * 32u;
-      for (uint32_t kk = 0; kk < 32; kk += 8) {
-        bf16x4 a, b;
+      for (uint32_t kk = 0; kk < 32; kk += 16) {
+        s16x8 a, b;
 #pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) {
+        for (uint32_t q = 0; q < 8; ++q) {
           a[q] = i0 + li < K ? (short)sX[(kk + rq + q) * K + i0 + li] : (short)0;
           b[q] = (short)sD[(kk + rq + q) * 64u + j0 + li];
         }
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[t], 0, 0, 0);
+        acc[t] = mfma16(a, b, acc[t]);
       }
     }
   }
@@ -487,7 +499,7 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(uint32_t M, const uint1
     const uint32_t i0 = (tile >> 1) * 32u, j0 = (tile & 1u) * 32u;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const uint32_t i = i0 + 8u * (v / 4) + rq + (v % 4);
+      const uint32_t i = i0 + 8u * (v / 4) + vq + (v % 4);
       if (i < K) atomicAdd(dW + (size_t)i * 64u + j0 + li, acc[t][v]);
     }
   }
@@ -599,6 +611,17 @@ __global__ __launch_bounds__(256) void warm_start_kernel(uint32_t n, const float
   if ((threadIdx.x & 63u) == 0 && mx) atomicMax(rmax, mx);
 }
 
+// Training target y[u] = log1p(r[u] / T) from a cold run's 64-bit loads.
+__global__ __launch_bounds__(256) void label_kernel(uint32_t n, const uint64_t* __restrict__ r, double T,
+                                                    float* __restrict__ y) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x)
+    y[u] = (float)log1p((double)r[u] / T);
+}
+
+__global__ __launch_bounds__(256) void zero_f32_kernel(float* __restrict__ a, uint32_t count) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) a[i] = 0.f;
+}
+
 }  // namespace
 
 extern "C" {
@@ -614,8 +637,9 @@ int kdss_gnn_features_workspace(uint32_t n, uint64_t nnz, size_t* bytes) {
 }
 
 int kdss_gnn_features(const kdss_sct* s, const uint64_t* d_row_ptr, const uint32_t* d_col, uint64_t nnz,
-                      uint16_t* d_x0, void* d_ws, size_t ws_bytes, void* stream) {
+                      int feature_set, uint16_t* d_x0, void* d_ws, size_t ws_bytes, void* stream) {
   if (!s || !d_row_ptr || !d_x0 || !d_ws || (nnz && !d_col)) return fail(KDSS_EINVAL, "null argument");
+  if (feature_set != 0 && feature_set != 1) return fail(KDSS_EINVAL, "feature_set must be 0 or 1");
   const uint32_t n = s->s.n;
   size_t need = 0;
   kdss_gnn_features_workspace(n, nnz, &need);
@@ -637,12 +661,14 @@ int kdss_gnn_features(const kdss_sct* s, const uint64_t* d_row_ptr, const uint32
   HIP_TRY(hipMemsetAsync(d_tri, 0, (size_t)n * 4, st), "clear triangles");
   HIP_TRY(hipMemsetAsync(d_orp, 0, 8, st), "clear offsets");
   const uint32_t wave_grid = blocks_for(n, 4, 16384);
-  orient_count_kernel<<<wave_grid, 256, 0, st>>>(n, nnz, d_row_ptr, d_col, d_rank, d_orp + 1);
-  scan_chunks_kernel<<<parts, 256, 0, st>>>(d_orp + 1, n, d_part);
-  scan_parts_kernel<<<1, 256, 0, st>>>(d_part, parts);
-  scan_add_kernel<<<parts, 256, 0, st>>>(d_orp + 1, n, d_part);
-  orient_fill_kernel<<<wave_grid, 256, 0, st>>>(n, nnz, d_row_ptr, d_col, d_rank, d_orp, d_ocol);
-  triangle_kernel<<<wave_grid, 256, 0, st>>>(n, d_orp, d_ocol, d_tri);
+  if (feature_set == 0) {   // triangles through every node (feature set 1 leaves the column 0)
+    orient_count_kernel<<<wave_grid, 256, 0, st>>>(n, nnz, d_row_ptr, d_col, d_rank, d_orp + 1);
+    scan_chunks_kernel<<<parts, 256, 0, st>>>(d_orp + 1, n, d_part);
+    scan_parts_kernel<<<1, 256, 0, st>>>(d_part, parts);
+    scan_add_kernel<<<parts, 256, 0, st>>>(d_orp + 1, n, d_part);
+    orient_fill_kernel<<<wave_grid, 256, 0, st>>>(n, nnz, d_row_ptr, d_col, d_rank, d_orp, d_ocol);
+    triangle_kernel<<<wave_grid, 256, 0, st>>>(n, d_orp, d_ocol, d_tri);
+  }
   features_kernel<<<blocks_for((size_t)n * kFeatureCols, 256, 16384), 256, 0, st>>>(n, d_row_ptr, d_core, d_tri, d_x0);
   HIP_TRY(hipGetLastError(), "features launch");
   return KDSS_OK;
@@ -692,9 +718,11 @@ int kdss_gnn_linear(uint32_t M, const uint16_t* d_a1, uint32_t K1, uint32_t lda1
                     uint32_t lda2, const uint16_t* d_bt, const float* d_bias, int relu, uint16_t* d_y, uint32_t ldy,
                     void* stream) {
   if (!d_a1 || !d_bt || !d_y || (K2 && !d_a2)) return fail(KDSS_EINVAL, "null argument");
-  if (K1 % 8 || K2 % 8 || K1 + K2 == 0 || K1 + K2 > 128 || lda1 < K1 || (K2 && lda2 < K2) || ldy < 64 ||
-      lda1 % 4 || lda2 % 4)
-    return fail(KDSS_EINVAL, "K1, K2 multiples of 8 with K1 + K2 <= 128; leading dims >= widths, multiples of 4");
+  auto a16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+  if (K1 % 8 || K2 % 8 || (K1 + K2) % 16 || K1 + K2 == 0 || K1 + K2 > 128 || lda1 < K1 || (K2 && lda2 < K2) ||
+      ldy < 64 || lda1 % 8 || (K2 && lda2 % 8) || !a16(d_a1) || (K2 && !a16(d_a2)) || !a16(d_bt))
+    return fail(KDSS_EINVAL, "K1, K2 multiples of 8 with K1 + K2 a multiple of 16, at most 128; leading dims >= "
+                             "widths and multiples of 8; A1, A2 and Bt 16-byte aligned");
   gemm_bt_kernel<<<blocks_for(M, 128, 1u << 30), 256, 0, static_cast<hipStream_t>(stream)>>>(
       M, d_a1, K1, lda1, d_a2, K2, lda2, d_bt, d_bias, relu, d_y, ldy);
   HIP_TRY(hipGetLastError(), "linear launch");
@@ -753,6 +781,145 @@ int kdss_gnn_pack_weights(uint32_t K, const float* d_w32, uint16_t* d_w, uint16_
       K, d_w32, d_w, d_wt);
   HIP_TRY(hipGetLastError(), "pack weights launch");
   return KDSS_OK;
+}
+
+// ---- the whole model: parameters in one FP32 array, workspace from the caller ----
+namespace {
+
+constexpr uint32_t kHidden = 64, kF0 = 8;
+constexpr uint32_t kLayerK[3] = {2 * kF0, 2 * kHidden, 2 * kHidden};
+constexpr size_t kOffW[3] = {KDSS_GNN_W1, KDSS_GNN_W2, KDSS_GNN_W3};
+constexpr size_t kOffB[3] = {KDSS_GNN_B1, KDSS_GNN_B2, KDSS_GNN_B3};
+
+struct ModelWs {   // byte layout of kdss_gnn_model_workspace
+  uint16_t *w16[3], *wt16[3];   // BF16 weights K x 64 and 64 x K
+  uint16_t *agg[3], *y[3];      // per layer: neighbour mean (n x F) and output (n x 64)
+  float* pred;                  // n
+  float* target;                // n (training)
+  uint16_t *dy, *dx, *dh;       // n x 64, n x 128, n x 64 (training)
+  float* grad;                  // KDSS_GNN_PARAMS (training)
+  size_t bytes;
+};
+
+ModelWs model_layout(char* base, uint32_t n, int train) {
+  ModelWs m{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    char* p = base ? base + o : nullptr;
+    o += al256(std::max<size_t>(b, 4));
+    return p;
+  };
+  for (int l = 0; l < 3; ++l) {
+    m.w16[l] = reinterpret_cast<uint16_t*>(take((size_t)kLayerK[l] * kHidden * 2));
+    m.wt16[l] = reinterpret_cast<uint16_t*>(take((size_t)kLayerK[l] * kHidden * 2));
+  }
+  const uint32_t F[3] = {kF0, kHidden, kHidden};
+  for (int l = 0; l < 3; ++l) {
+    m.agg[l] = reinterpret_cast<uint16_t*>(take((size_t)n * F[l] * 2));
+    m.y[l] = reinterpret_cast<uint16_t*>(take((size_t)n * kHidden * 2));
+  }
+  m.pred = reinterpret_cast<float*>(take((size_t)n * 4));
+  if (train) {
+    m.target = reinterpret_cast<float*>(take((size_t)n * 4));
+    m.dy = reinterpret_cast<uint16_t*>(take((size_t)n * kHidden * 2));
+    m.dx = reinterpret_cast<uint16_t*>(take((size_t)n * 2 * kHidden * 2));
+    m.dh = reinterpret_cast<uint16_t*>(take((size_t)n * kHidden * 2));
+    m.grad = reinterpret_cast<float*>(take((size_t)KDSS_GNN_PARAMS * 4));
+  }
+  m.bytes = o;
+  return m;
+}
+
+// BF16 copies of the three weights, then the forward pass into m.pred.
+int model_forward(const ModelWs& m, uint32_t n, const uint64_t* rp, const uint32_t* col, const uint16_t* x0,
+                  const float* params, void* stream) {
+  for (int l = 0; l < 3; ++l) {
+    int rc = kdss_gnn_pack_weights(kLayerK[l], params + kOffW[l], m.w16[l], m.wt16[l], stream);
+    if (rc) return rc;
+  }
+  const uint16_t* h = x0;
+  uint32_t F = kF0;
+  for (int l = 0; l < 3; ++l) {
+    int rc = kdss_gnn_aggregate(n, rp, col, h, F, m.agg[l], stream);
+    if (!rc) rc = kdss_gnn_linear(n, h, F, F, m.agg[l], F, F, m.wt16[l], params + kOffB[l], 1, m.y[l], kHidden, stream);
+    if (rc) return rc;
+    h = m.y[l];
+    F = kHidden;
+  }
+  return kdss_gnn_head(n, m.y[2], params + KDSS_GNN_HEAD, m.pred, stream);
+}
+
+int check_model_args(uint32_t n, const uint64_t* rp, const uint32_t* col, const uint16_t* x0, const void* params,
+                     void* d_ws, size_t ws_bytes, int train) {
+  if (!rp || !x0 || !params || !d_ws || (n && !col)) return fail(KDSS_EINVAL, "null argument");
+  if (n == 0) return fail(KDSS_EINVAL, "the graph has no nodes");
+  if ((reinterpret_cast<uintptr_t>(x0) & 15u) || (reinterpret_cast<uintptr_t>(d_ws) & 255u))
+    return fail(KDSS_EINVAL, "x0 must be 16-byte and the workspace 256-byte aligned");
+  if (ws_bytes < model_layout(nullptr, n, train).bytes)
+    return fail(KDSS_EWORKSPACE, "model workspace smaller than kdss_gnn_model_workspace() reports");
+  return KDSS_OK;
+}
+
+}  // namespace
+
+int kdss_gnn_model_workspace(uint32_t n, int train, size_t* bytes) {
+  if (!bytes) return fail(KDSS_EINVAL, "null argument");
+  *bytes = model_layout(nullptr, n, train ? 1 : 0).bytes;
+  return KDSS_OK;
+}
+
+int kdss_gnn_infer(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint16_t* d_x0,
+                   const float* d_params, double t0, uint64_t cap, void* d_ws, size_t ws_bytes, float* d_pred,
+                   uint64_t* d_r0, uint64_t* d_rmax, void* stream) {
+  int rc = check_model_args(n, d_row_ptr, d_col, d_x0, d_params, d_ws, ws_bytes, 0);
+  if (rc) return rc;
+  if (!d_r0 || !d_rmax) return fail(KDSS_EINVAL, "null argument");
+  const ModelWs m = model_layout(static_cast<char*>(d_ws), n, 0);
+  rc = model_forward(m, n, d_row_ptr, d_col, d_x0, d_params, stream);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (d_pred) HIP_TRY(hipMemcpyAsync(d_pred, m.pred, (size_t)n * 4, hipMemcpyDeviceToDevice, st), "copy prediction");
+  return kdss_gnn_warm_start(n, m.pred, t0, cap, d_r0, d_rmax, stream);
+}
+
+int kdss_gnn_train_step(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint16_t* d_x0,
+                        const uint64_t* d_r, uint32_t T, float* d_params, float* d_m, float* d_v, uint32_t step,
+                        float lr, void* d_ws, size_t ws_bytes, float* d_loss, void* stream) {
+  int rc = check_model_args(n, d_row_ptr, d_col, d_x0, d_params, d_ws, ws_bytes, 1);
+  if (rc) return rc;
+  if (!d_r || !d_m || !d_v || !d_loss) return fail(KDSS_EINVAL, "null argument");
+  if (T == 0 || step == 0) return fail(KDSS_EINVAL, "T and step must be at least 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const ModelWs m = model_layout(static_cast<char*>(d_ws), n, 1);
+  label_kernel<<<blocks_for(n, 256, 4096), 256, 0, st>>>(n, d_r, (double)T, m.target);
+  zero_f32_kernel<<<blocks_for(KDSS_GNN_PARAMS, 256, 64), 256, 0, st>>>(m.grad, KDSS_GNN_PARAMS);
+  HIP_TRY(hipGetLastError(), "label launch");
+  rc = model_forward(m, n, d_row_ptr, d_col, d_x0, d_params, stream);
+  if (rc) return rc;
+  // loss and the head's gradient, then each layer back to front
+  rc = kdss_gnn_head_backward(n, m.y[2], d_params + KDSS_GNN_HEAD, m.pred, m.target, m.dy, m.grad + KDSS_GNN_HEAD,
+                              d_loss, stream);
+  if (rc) return rc;
+  const uint32_t F[3] = {kF0, kHidden, kHidden};
+  uint16_t *dy = m.dy, *next = m.dh;   // the gradient at a layer's output, and the buffer for its input's
+  for (int l = 2; l >= 0; --l) {
+    const uint16_t* h = l ? m.y[l - 1] : d_x0;
+    rc = kdss_gnn_relu_backward((uint64_t)n * kHidden, m.y[l], dy, stream);
+    if (!rc) rc = kdss_gnn_linear_wgrad(n, h, F[l], F[l], m.agg[l], F[l], F[l], dy, m.grad + kOffW[l],
+                                        m.grad + kOffB[l], stream);
+    if (rc) return rc;
+    if (l == 0) break;
+    // dX = dY W^T: the self half into columns 0..f-1, the neighbour half into f..2f-1;
+    // the input's gradient is the self half plus the mean's transpose of the other
+    const uint32_t f = F[l];
+    rc = kdss_gnn_linear(n, dy, kHidden, kHidden, nullptr, 0, 0, m.w16[l], nullptr, 0, m.dx, 2 * f, stream);
+    if (!rc) rc = kdss_gnn_linear(n, dy, kHidden, kHidden, nullptr, 0, 0, m.w16[l] + (size_t)f * kHidden, nullptr, 0,
+                                  m.dx + f, 2 * f, stream);
+    if (!rc) rc = kdss_gnn_aggregate_backward(n, d_row_ptr, d_col, m.dx + f, m.dx, f, 2 * f, next, stream);
+    if (rc) return rc;
+    std::swap(dy, next);
+  }
+  return kdss_gnn_adam(KDSS_GNN_PARAMS, d_params, m.grad, d_m, d_v, lr, 0.9f, 0.999f, 1e-8f, step, stream);
 }
 
 int kdss_gnn_warm_start(uint32_t n, const float* d_pred, double t0, uint64_t cap, uint64_t* d_r0, uint64_t* d_rmax,

@@ -22,6 +22,7 @@ HIDDEN = 64
 F0 = 8           # feature columns (3 used, padded to one 8-wide matrix-core step)
 LAYERS = [(F0, F0), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN)]   # (self columns, neighbour columns)
 WEIGHTS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gnn_weights.npz")
+PARAMS = 17665   # KDSS_GNN_PARAMS
 
 _bound = False
 
@@ -32,7 +33,11 @@ def _lib():
     if not _bound:
         vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
         L.kdss_gnn_features_workspace.argtypes = [u32, u64, C.POINTER(C.c_size_t)]
-        L.kdss_gnn_features.argtypes = [vp, vp, vp, u64, vp, vp, C.c_size_t, vp]
+        L.kdss_gnn_features.argtypes = [vp, vp, vp, u64, C.c_int, vp, vp, C.c_size_t, vp]
+        L.kdss_gnn_model_workspace.argtypes = [u32, C.c_int, C.POINTER(C.c_size_t)]
+        L.kdss_gnn_infer.argtypes = [u32, vp, vp, vp, vp, C.c_double, u64, vp, C.c_size_t, vp, vp, vp, vp]
+        L.kdss_gnn_train_step.argtypes = [u32, vp, vp, vp, vp, u32, vp, vp, vp, u32, C.c_float, vp, C.c_size_t,
+                                          vp, vp]
         L.kdss_gnn_aggregate.argtypes = [u32, vp, vp, vp, u32, vp, vp]
         L.kdss_gnn_aggregate_backward.argtypes = [u32, vp, vp, vp, vp, u32, u32, vp, vp]
         L.kdss_gnn_linear.argtypes = [u32, vp, u32, u32, vp, u32, u32, vp, vp, C.c_int, vp, u32, vp]
@@ -63,7 +68,7 @@ def _ck(status, where):
 class DeviceGraph:
     """A graph's CSR on the device, its features and (optionally) labels."""
 
-    def __init__(self, graph, tree=None, device="cuda"):
+    def __init__(self, graph, tree=None, device="cuda", feature_set=0):
         import torch
         self.n = graph.n
         self.row_ptr = torch.from_numpy(graph.row_ptr.astype(np.int64)).to(device)
@@ -72,10 +77,12 @@ class DeviceGraph:
         own = tree is None
         tree = tree or kdss.Tree(graph, 3)
         self.nnz = int(graph.row_ptr[graph.n])
-        self.x0 = features(tree, self.row_ptr, self.col, self.nnz)
+        self.x0 = features(tree, self.row_ptr, self.col, self.nnz, feature_set)
         if own:
             tree.close()
         self.target = None
+        self.loads = None     # a cold run's loads (u64 as int64, device) and its T, for training
+        self.T = 0
 
     @classmethod
     def resident(cls, n, row_ptr, col, nnz):
@@ -87,15 +94,16 @@ class DeviceGraph:
         return self
 
 
-def features(tree, d_row_ptr, d_col, nnz):
-    """x0 (n x 8 BF16 as int16) = log1p of degree, core number, triangle count, then zeros."""
+def features(tree, d_row_ptr, d_col, nnz, feature_set=0):
+    """x0 (n x 8 BF16 as int16) = log1p of degree, core number, triangle count
+    (feature set 0; set 1 leaves the triangle column 0), then zeros."""
     import torch
     nbytes = C.c_size_t(0)
     _ck(_lib().kdss_gnn_features_workspace(tree.n, nnz, C.byref(nbytes)), "kdss_gnn_features_workspace")
     ws = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=d_row_ptr.device)
     x0 = torch.empty((max(tree.n, 1), F0), dtype=torch.int16, device=d_row_ptr.device)
-    _ck(_lib().kdss_gnn_features(tree._h, _p(d_row_ptr), _p(d_col), nnz, _p(x0), _p(ws), ws.numel(), _s()),
-        "kdss_gnn_features")
+    _ck(_lib().kdss_gnn_features(tree._h, _p(d_row_ptr), _p(d_col), nnz, feature_set, _p(x0), _p(ws), ws.numel(),
+                                 _s()), "kdss_gnn_features")
     return x0[: tree.n]
 
 
@@ -120,19 +128,34 @@ class Model:
         import torch
         self.device = device
         rs = synth.Stream(seed, 77)
-        self.params = []
+        host = []
         for (ks, kn) in LAYERS:
             K = ks + kn
             scale = math.sqrt(6.0 / (K + HIDDEN))
-            w = ((rs.uniform(K * HIDDEN) * 2 - 1) * scale).astype(np.float32).reshape(K, HIDDEN)
-            self.params.append(torch.from_numpy(w).to(device))
-            self.params.append(torch.zeros(HIDDEN, dtype=torch.float32, device=device))
+            host.append(((rs.uniform(K * HIDDEN) * 2 - 1) * scale).astype(np.float32).reshape(K, HIDDEN))
+            host.append(np.zeros(HIDDEN, dtype=np.float32))
         head = ((rs.uniform(HIDDEN + 1) * 2 - 1) * math.sqrt(6.0 / (HIDDEN + 1))).astype(np.float32)
         head[HIDDEN] = 0.0
-        self.params.append(torch.from_numpy(head).to(device))
-        self.grads = [torch.zeros_like(p) for p in self.params]
-        self.m = [torch.zeros_like(p) for p in self.params]
-        self.v = [torch.zeros_like(p) for p in self.params]
+        host.append(head)
+        # one flat FP32 array in the library's layout (W1 b1 W2 b2 W3 b3 head);
+        # params, grads and the Adam moments are views into flat arrays
+        self.flat = torch.from_numpy(np.concatenate([h.reshape(-1) for h in host])).to(device)
+        assert self.flat.numel() == PARAMS
+        self.flat_grad = torch.zeros_like(self.flat)
+        self.flat_m = torch.zeros_like(self.flat)
+        self.flat_v = torch.zeros_like(self.flat)
+
+        def views(t):
+            out, at = [], 0
+            for h in host:
+                out.append(t[at:at + h.size].view(h.shape))
+                at += h.size
+            return out
+        self.params = views(self.flat)
+        self.grads = views(self.flat_grad)
+        self.m = views(self.flat_m)
+        self.v = views(self.flat_v)
+        self._ws = {}
         self.w16 = [torch.empty(p.shape, dtype=torch.int16, device=device) for p in self.params[0:6:2]]
         self.wt16 = [torch.empty((HIDDEN, p.shape[0]), dtype=torch.int16, device=device) for p in self.params[0:6:2]]
         self.step_count = 0
@@ -213,35 +236,48 @@ class Model:
                 "adam")
         self.pack()
 
-    def warm_start(self, dg, t0, cap=1 << 62, sync=True):
-        """r0 (device uint64 as int64) and its maximum (an int when sync, else the
-        device scalar), from a forward pass."""
+    def workspace(self, n, train):
         import torch
-        pred, _ = self.forward(dg)
+        key = (n, bool(train))
+        if key not in self._ws:
+            b = C.c_size_t(0)
+            _ck(_lib().kdss_gnn_model_workspace(n, 1 if train else 0, C.byref(b)), "kdss_gnn_model_workspace")
+            self._ws = {key: torch.empty(b.value, dtype=torch.uint8, device=self.device)}
+        return self._ws[key]
+
+    def warm_start(self, dg, t0, cap=1 << 62, sync=True, pred=None):
+        """r0 (device uint64 as int64) and its maximum (an int when sync, else the
+        device scalar): the forward pass and the rounding in one library call."""
+        import torch
+        ws = self.workspace(dg.n, False)
         r0 = torch.empty(dg.n, dtype=torch.int64, device=self.device)
         rmax = torch.zeros(1, dtype=torch.int64, device=self.device)
-        _ck(_lib().kdss_gnn_warm_start(dg.n, _p(pred), float(t0), cap, _p(r0), _p(rmax), _s()), "warm start")
+        _ck(_lib().kdss_gnn_infer(dg.n, _p(dg.row_ptr), _p(dg.col), _p(dg.x0), _p(self.flat), float(t0), cap, _p(ws),
+                                  ws.numel(), _p(pred), _p(r0), _p(rmax), _s()), "kdss_gnn_infer")
         return r0, (int(rmax.item()) if sync else rmax)
 
+    def train_step(self, dg, lr, loss):
+        """One Adam step on one graph (library call: label, forward, backward, Adam);
+        the graph's mean squared error is added into loss (device FP32 [1])."""
+        self.step_count += 1
+        ws = self.workspace(dg.n, True)
+        _ck(_lib().kdss_gnn_train_step(dg.n, _p(dg.row_ptr), _p(dg.col), _p(dg.x0), _p(dg.loads), dg.T,
+                                       _p(self.flat), _p(self.flat_m), _p(self.flat_v), self.step_count, lr, _p(ws),
+                                       ws.numel(), _p(loss), _s()), "kdss_gnn_train_step")
 
-def label(graph, tree, T, device="cuda"):
-    """Cold-run label y = log1p(r_T / T) (FP32) for a graph's tree."""
+
+def cold_loads(graph, tree, T, device="cuda"):
+    """A cold run's loads r_T (u64 as int64 on the device) for a graph's tree;
+    the training step turns them into the target log1p(r_T / T)."""
     import torch
-    plan = kdss.Plan(tree, T)
+    plan = kdss.Plan(tree, T, width=64)
     ws = plan.alloc_workspace(device)
     plan.upload(ws)
     r = plan.alloc_loads(device)
     order = torch.empty(max(graph.n, 1), dtype=torch.int32, device=device)
     plan.run(ws, T, r, order)
-    def unsigned(w):
-        w = w.to(torch.float64)
-        return torch.where(w < 0, w + 2.0 ** 64, w)
-    if plan.width == 64:
-        rr = unsigned(r[:graph.n])
-    else:   # (lo, hi) word pairs
-        rr = unsigned(r[0:2 * graph.n:2]) + unsigned(r[1:2 * graph.n:2]) * 2.0 ** 64
     plan.close()
-    return torch.log1p(rr / T).to(torch.float32)
+    return r[:graph.n]
 
 
 def generate(count, base_seed=10000, n_lo=10_000, n_hi=200_000, workers=6, first=0, log=print):
@@ -256,17 +292,22 @@ def generate(count, base_seed=10000, n_lo=10_000, n_hi=200_000, workers=6, first
     return graphs
 
 
-def prepare(graphs, k=6, T=200, device="cuda", log=print):
-    """Features and cold-run labels at (k, T) on the device; the host graphs are
+def prepare(graphs, k=6, T=200, device="cuda", log=print, feature_set=0):
+    """Features and cold-run loads at (k, T) on the device; the host graphs are
     released as they are consumed."""
+    import torch
     out = []
     t1 = time.time()
     for i in range(len(graphs)):
         g = graphs[i]
         graphs[i] = None
         tree = kdss.Tree(g, k)
-        dg = DeviceGraph(g, tree, device)
-        dg.target = label(g, tree, T, device)
+        dg = DeviceGraph(g, tree, device, feature_set)
+        dg.loads = cold_loads(g, tree, T, device)
+        dg.T = T
+        # the target as the training step computes it (for the kernel-level path)
+        w = dg.loads.to(torch.float64)
+        dg.target = torch.log1p(torch.where(w < 0, w + 2.0 ** 64, w) / T).to(torch.float32)
         tree.close()
         out.append(dg)
         if len(out) % 25 == 0 or len(out) == len(graphs):
@@ -275,9 +316,9 @@ def prepare(graphs, k=6, T=200, device="cuda", log=print):
 
 
 def training_set(count, k=6, T=200, base_seed=10000, n_lo=10_000, n_hi=200_000, workers=6, device="cuda",
-                 first=0, log=print):
+                 first=0, log=print, feature_set=0):
     """generate() then prepare()."""
-    return prepare(generate(count, base_seed, n_lo, n_hi, workers, first, log), k, T, device, log)
+    return prepare(generate(count, base_seed, n_lo, n_hi, workers, first, log), k, T, device, log, feature_set)
 
 
 def _member(args):
@@ -286,32 +327,31 @@ def _member(args):
 
 
 def evaluate(model, data):
-    """Mean loss over graphs (the gradients it accumulates are discarded)."""
+    """Mean loss over graphs: the forward pass in the library, the mean squared
+    error against log1p(r / T)."""
+    import torch
     tot = 0.0
     for dg in data:
-        model.zero_grad()
-        pred, acts = model.forward(dg)
-        tot += float(model.backward(dg, pred, acts, dg.target).item())
-    model.zero_grad()
+        pred = torch.empty(dg.n, dtype=torch.float32, device=model.device)
+        model.warm_start(dg, 1.0, pred=pred)
+        tot += float(((pred - dg.target) ** 2).mean().item())
     return tot / max(1, len(data))
 
 
 def train(model, data, epochs=3, lr=1e-3, seed=0, val=None, log=print):
-    """One Adam step per graph (MSE over its nodes), graphs in a seeded shuffled
-    order each epoch.  Returns the mean training loss of each epoch."""
+    """One Adam step per graph (MSE over its nodes; one kdss_gnn_train_step
+    call), graphs in a seeded shuffled order each epoch.  Returns the mean
+    training loss of each epoch."""
+    import torch
     rs = synth.Stream(seed, 78)
     hist = []
+    loss = torch.zeros(1, dtype=torch.float32, device=model.device)
     for ep in range(epochs):
         order = rs.shuffle_order(len(data))
-        tot = 0.0
+        loss.zero_()
         for i in order:
-            dg = data[int(i)]
-            model.zero_grad()
-            pred, acts = model.forward(dg)
-            loss = model.backward(dg, pred, acts, dg.target)
-            model.adam(lr)
-            tot += float(loss.item())
-        hist.append(tot / len(data))
+            model.train_step(data[int(i)], lr, loss)
+        hist.append(float(loss.item()) / len(data))
         msg = f"epoch {ep + 1}: mean loss {hist[-1]:.4f}"
         if val:
             msg += f", held-out {evaluate(model, val):.4f}"
@@ -332,6 +372,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--workers", type=int, default=6, help="graph generator processes")
     ap.add_argument("--out", default=WEIGHTS_FILE)
+    ap.add_argument("--feature-set", type=int, default=0, help="0: degree, core, triangles; 1: degree, core")
+    ap.add_argument("--curve", default="", help="graph counts for a held-out loss curve, e.g. 50,100,200,300")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -340,15 +382,25 @@ def main(argv=None):
     t0 = time.time()
     g_val = generate(args.held_out, base_seed=20000, workers=args.workers, log=log)
     g_train = generate(args.graphs, workers=args.workers, log=log)
-    val = prepare(g_val, k=args.k, T=args.T, log=log)
-    data = prepare(g_train, k=args.k, T=args.T, log=log)
+    val = prepare(g_val, k=args.k, T=args.T, log=log, feature_set=args.feature_set)
+    data = prepare(g_train, k=args.k, T=args.T, log=log, feature_set=args.feature_set)
     log(f"data ready in {time.time() - t0:.0f} s")
+    if args.curve:
+        # held-out loss after training on the first c graphs, for each c
+        curve = {}
+        for c in (int(x) for x in args.curve.split(",")):
+            m = Model(seed=0)
+            train(m, data[:c], epochs=args.epochs, lr=args.lr, log=lambda *_: None)
+            curve[c] = evaluate(m, val)
+            log(f"curve: {c} graphs -> held-out loss {curve[c]:.5f}")
+        print("CURVE " + " ".join(f"{c}:{v:.6f}" for c, v in curve.items()), flush=True)
     model = Model(seed=0)
     hist = train(model, data, epochs=args.epochs, lr=args.lr, val=val, log=log)
     state = model.state()
     state.update(meta_graphs=np.int64(args.graphs), meta_k=np.int64(args.k), meta_T=np.int64(args.T),
                  meta_epochs=np.int64(args.epochs), meta_train_loss=np.float64(hist[-1]),
-                 meta_held_out_loss=np.float64(evaluate(model, val)))
+                 meta_held_out_loss=np.float64(evaluate(model, val)),
+                 meta_feature_set=np.int64(args.feature_set))
     np.savez(args.out, **state)
     log(f"saved {args.out} ({time.time() - t0:.0f} s)")
 

@@ -204,7 +204,9 @@ def test_training_reduces_loss_and_warm_start(G, oracle_mod):
     for g in graphs:
         tree = kdss.Tree(g, 4)
         dg = G.DeviceGraph(g, tree)
-        dg.target = G.label(g, tree, 30)
+        dg.loads, dg.T = G.cold_loads(g, tree, 30), 30
+        w = dg.loads.to(torch.float64)
+        dg.target = torch.log1p(w / 30).to(torch.float32)
         data.append(dg)
     model = G.Model(seed=1)
     hist = G.train(model, data, epochs=12, lr=3e-3, log=lambda *_: None)
@@ -218,3 +220,55 @@ def test_training_reduces_loss_and_warm_start(G, oracle_mod):
     sol = kdss.solve(g, 4, 9, r0=r0h)
     ref = oracle_mod.solve(g.n, g.row_ptr, g.col, 4, 9, r0=r0h)
     assert np.array_equal(sol.r, ref["r"]) and (sol.size, sol.dens_num) == (ref["size"], ref["dens_num"])
+
+
+def test_library_step_equals_kernel_by_kernel_step(G):
+    """kdss_gnn_train_step (label, forward, backward, Adam in one call) against
+    the same kernels called one by one: the label transform log1p(r / T) is
+    compared with float64, the loss and parameters after the step within the
+    float atomics' reordering, and kdss_gnn_infer's prediction and integer
+    start loads with the forward pass and kdss_gnn_warm_start bit for bit."""
+    from paper_2403_05775_amd import kdss
+    g = synth.chung_lu(3000, 24000, 2.3, seed=44, planted=15)
+    tree = kdss.Tree(g, 4)
+    dg = G.DeviceGraph(g, tree)
+    dg.loads, dg.T = G.cold_loads(g, tree, 25), 25
+    r = dg.loads.cpu().numpy().view(np.uint64).astype(np.float64)
+    dg.target = torch.from_numpy(np.log1p(r / 25).astype(np.float32)).cuda()
+    a, b = G.Model(seed=5), G.Model(seed=5)
+    # library step
+    loss_a = torch.zeros(1, dtype=torch.float32, device="cuda")
+    a.train_step(dg, 2e-3, loss_a)
+    # kernel by kernel
+    b.zero_grad()
+    pred, acts = b.forward(dg)
+    loss_b = b.backward(dg, pred, acts, dg.target)
+    b.adam(2e-3)
+    torch.cuda.synchronize()
+    assert abs(float(loss_a.item()) - float(loss_b.item())) <= 1e-5 * float(loss_b.item())
+    assert torch.allclose(a.flat, b.flat, rtol=1e-4, atol=1e-6)
+    # inference: the same forward kernels, so the same bits
+    pa = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    r0a, ma = a.warm_start(dg, 40, pred=pa)
+    a.pack()   # the kernel-level forward reads the BF16 copies of the current weights
+    pb, _ = a.forward(dg)
+    r0b = torch.empty(g.n, dtype=torch.int64, device="cuda")
+    mb = torch.zeros(1, dtype=torch.int64, device="cuda")
+    G._ck(G._lib().kdss_gnn_warm_start(g.n, G._p(pb), 40.0, 1 << 62, G._p(r0b), G._p(mb), G._s()), "warm start")
+    torch.cuda.synchronize()
+    assert torch.equal(pa, pb) and torch.equal(r0a, r0b) and ma == int(mb.item())
+
+
+def test_feature_set_without_triangles(G):
+    """Feature set 1 keeps degree and core number and leaves the triangle column 0."""
+    from paper_2403_05775_amd import kdss
+    g = small_graph()
+    tree = kdss.Tree(g, 3)
+    rp = torch.from_numpy(g.row_ptr.astype(np.int64)).cuda()
+    col = torch.from_numpy(g.col.view(np.int32)).cuda()
+    nnz = int(g.row_ptr[-1])
+    x0 = G.features(tree, rp, col, nnz, 0)
+    x1 = G.features(tree, rp, col, nnz, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(x0[:, :2], x1[:, :2]) and torch.equal(x0[:, 3:], x1[:, 3:])
+    assert int((x1[:, 2] != 0).sum()) == 0 and int((x0[:, 2] != 0).sum()) > 0
