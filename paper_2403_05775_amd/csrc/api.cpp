@@ -154,7 +154,7 @@ int kdss_sct_core_numbers(const kdss_sct* s, uint32_t* core, uint32_t n) {
   if (!s || !core) return fail(KDSS_EINVAL, "null argument");
   if (n != s->s.n) return fail(KDSS_ERANGE, "n does not match the tree");
   if (s->s.deg.core.size() != n) return fail(KDSS_EUNSUPPORTED, "a tree of sampled cliques has no core numbers");
-  std::memcpy(core, s->s.deg.core.data(), sizeof(uint32_t) * n);
+  if (n) std::memcpy(core, s->s.deg.core.data(), sizeof(uint32_t) * n);
   return KDSS_OK;
 }
 

@@ -411,7 +411,8 @@ int build_sct_impl(const kdss_csr* g, uint32_t k, uint32_t threads, Sct* out, kd
   u128 ck = 0;
   uint32_t smax = 0;
   for (auto& b : bufs) {
-    std::memcpy(out->members.data() + mi, b.members.data(), b.members.size() * sizeof(uint32_t));
+    if (!b.members.empty())
+      std::memcpy(out->members.data() + mi, b.members.data(), b.members.size() * sizeof(uint32_t));
     for (size_t i = 0; i < b.h.size(); ++i) {
       out->off[li] = mi;
       out->h[li] = b.h[i];
