@@ -60,6 +60,11 @@ WORKLOADS = {
     # at scale 16: the scale-27 graph's clique tree is far beyond host memory
     # (members grow about 28x per two scales); the oracle samples 1 iteration
     "rmat-16": dict(kind="rmat", scale=16, edge_factor=8, seed=0, k=6, T=100, cpu_iters=1),
+    # the same family at scale 18 (262,144 nodes, 1,969,522 edges): the largest
+    # scale whose k = 6 clique tree (8.3e8 leaves, 1.02e10 members, a 44 GB
+    # leaf stream) one GPU holds; scale 19 needs about 200 GB of stream plus a
+    # 61 GB heavy-leaf queue, and scale 27 about 10^19 members (tree-growth mode)
+    "rmat-18": dict(kind="rmat", scale=18, edge_factor=8, seed=0, k=6, T=100, cpu_iters=0),
     # warm start vs cold start on an unseen Chung-Lu graph, n = 2M, m = 40M,
     # exponent 2.5, seed 90000; k = 6; the reference density is the best over a
     # 4T cold run with an extraction after every iteration
@@ -200,7 +205,7 @@ def batch_bench(w, args):
                    "key_mode": st.key_mode, "gather": "masked" if st.gather == 1 else "full",
                    "hot_share": round(st.hot_share, 4),
                    "parallelism": "single GPU, one launch per kernel per iteration for all problems",
-                   "hip_graph": bool(args.graph)},
+                   "hip_graph_iterations": args.graph},
         "hbm_gbps_algorithmic": step_bytes / (ms / 1000.0) / 1e9,
         "host_build_s": build_s, "plan_s": plan_s,
         "launch": launch_fields(tune, cached),
@@ -325,10 +330,11 @@ def gnn_bench(w, args):
     nnz = int(g.row_ptr[-1])
     n = g.n
     model = gnn.Model(device=dev)
-    trained = os.path.exists(gnn.WEIGHTS_FILE) and not args.gnn_untrained
+    wfile = args.gnn_weights or gnn.WEIGHTS_FILE
+    trained = os.path.exists(wfile) and not args.gnn_untrained
     meta = {}
     if trained:
-        with np.load(gnn.WEIGHTS_FILE) as z:
+        with np.load(wfile) as z:
             model.load(z)
             meta = {x: z[x].item() for x in z.files if x.startswith("meta_")}
     log(f"model: {'trained ' + str(meta) if trained else 'untrained (random init)'}")
@@ -856,7 +862,7 @@ def single_bench(w, args):
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {g.name}, k={w['k']}, T={T}", "n": n, "m": g.m,
                    "k": w["k"], "T": T, "leaves": L, "members": M, "c_k": ts.c_k.value,
-                   "parallelism": "single GPU", "hip_graph": bool(args.graph),
+                   "parallelism": "single GPU", "hip_graph_iterations": args.graph,
                    "gather": "masked" if ps.gather == 1 else "full", "hot_share": round(ps.hot_share, 4),
                    "update": "PBUpdate (synchronous)" if update else "Frank-Wolfe"},
         "hbm_gbps_algorithmic": step_bytes / (ms_per_step / 1000.0) / 1e9,
@@ -885,6 +891,10 @@ def single_bench(w, args):
             out["cpu_baseline"] = cpu_baseline_pb(g, w, tree, L, w.get("cpu_iters", args.cpu_sample_iters))
         elif w.get("cpu_full"):
             out["cpu_baseline"] = cpu_baseline_full(g, w, L)
+        elif w.get("cpu_iters") == 0:
+            out["cpu_baseline"] = None
+            out["cpu_baseline_skipped"] = (f"the oracle would list all {ts.c_k.value} k-cliques for every iteration "
+                                           f"(about 1.5e7 per second on 16 threads: over half an hour per iteration)")
         else:
             out["cpu_baseline"] = cpu_baseline(g, w, L, w.get("cpu_iters", args.cpu_sample_iters))
     print(json.dumps(out))
@@ -900,10 +910,9 @@ def profiled_steps(plan, step, args):
     the runtime stamps each dispatch's own start and end, so the durations are
     the kernels' execution spans (what rocprofv3's kernel trace reports).  The
     events cost time between kernels, so the step time comes from the plain
-    steps before."""
+    steps before (timed steps launch plainly, also when the plain steps replay
+    graphs)."""
     import torch
-    if args.graph:
-        return None
     plan.set_timing(True)
     plan.timing(reset=True)
     for _ in range(args.steps):
@@ -922,7 +931,8 @@ def main():
     ap.add_argument("--workload", default="batch-512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=20)
-    ap.add_argument("--graph", action="store_true", help="replay iterations as hipGraphs (no kernel timing)")
+    ap.add_argument("--graph", type=int, default=0, metavar="G",
+                    help="replay the iterations as hipGraphs of G iterations (0: plain launches)")
     ap.add_argument("--no-autotune", action="store_true", help="default grid sizes and gather mode")
     ap.add_argument("--launch", default="", help="LEAF,HEAVY,GATHER: a given launch instead of the tuned one")
     ap.add_argument("--schedule", type=int, default=0, help="tile schedule: 0 tuned, 1 strided, 2 XCD ranges")
@@ -938,6 +948,7 @@ def main():
     ap.add_argument("--out", default="")
     ap.add_argument("--batch-graphs", type=int, default=0, help="graphs in the batch workload (default 512)")
     ap.add_argument("--gnn-untrained", action="store_true", help="warm start from a randomly initialised model")
+    ap.add_argument("--gnn-weights", default="", help="warm-start weights (.npz; default: the package's)")
     args = ap.parse_args()
     if args.summarize_counters:
         res = summarize_counters(args.workload, *args.summarize_counters, args.command)

@@ -79,7 +79,9 @@ typedef struct {
 
 typedef struct {
     int width;                /* 0: choose; 64 or 128: force the load width     */
-    int use_graph;            /* 1: replay the iterations as a hipGraph         */
+    int use_graph;            /* G >= 1: replay the iterations as a hipGraph of
+                                 G iterations (captured on first use; with
+                                 extract_every, one iteration per replay)     */
     uint32_t extract_every;   /* 0: extract after iteration T only; e > 0: also
                                  after every e-th iteration, into the trace     */
     int time_kernels;         /* 1: time every iteration kernel of kdss_run

@@ -14,6 +14,8 @@ CSRC = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(CSRC)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libkdss.so")
+# a test build whose checked HIP calls can be made to fail on request
+OUT_FI = os.path.join(PKG, "libkdss_fi.so")
 BUILD = os.path.join(PKG, "_build")
 ARCH = "gfx950"
 
@@ -28,10 +30,10 @@ HIP_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", 
              "-munsafe-fp-atomics"]
 
 
-def _compile(src: str, obj: str, device: bool) -> None:
+def _compile(src: str, obj: str, device: bool, defines=()) -> None:
     path = os.path.join(CSRC, src)
     if device:
-        cmd = [HIPCC] + COMMON + HIP_FLAGS + ["-c", path, "-o", obj]
+        cmd = [HIPCC] + COMMON + HIP_FLAGS + list(defines) + ["-c", path, "-o", obj]
     else:
         cmd = ["g++"] + COMMON + ["-pthread", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,17 +46,23 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = [(s, os.path.join(BUILD, s + ".o"), False) for s in HOST_SOURCES]
     jobs += [(s, os.path.join(BUILD, s + ".o"), True) for s in DEVICE_SOURCES]
-    with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
-        for f in [ex.submit(_compile, *j) for j in jobs]:
+    fi_obj = os.path.join(BUILD, "kernels_fi.hip.o")
+    with cf.ThreadPoolExecutor(max_workers=len(jobs) + 1) as ex:
+        futs = [ex.submit(_compile, *j) for j in jobs]
+        futs.append(ex.submit(_compile, "kernels.hip", fi_obj, True, ["-DKDSS_FAULT_INJECTION"]))
+        for f in futs:
             f.result()
-    tmp = OUT + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + [j[1] for j in jobs] + ["-pthread"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
-    if verbose:
-        print("built", OUT)
+    objs = [j[1] for j in jobs]
+    fi_objs = [fi_obj if o.endswith(os.sep + "kernels.hip.o") else o for o in objs]
+    for out, ob in ((OUT, objs), (OUT_FI, fi_objs)):
+        tmp = out + ".tmp"
+        cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + ob + ["-pthread"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, out)
+        if verbose:
+            print("built", out)
     return OUT
 
 

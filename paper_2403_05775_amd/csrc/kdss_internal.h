@@ -221,6 +221,7 @@ struct kdss_plan {
   void* graph_exec = nullptr;          // hipGraphExec_t of one iteration
   void* graph_ws = nullptr;
   void* graph_r = nullptr;
+  uint32_t graph_iters = 0;            // iterations the captured graph holds
   void* capture_stream = nullptr;
   std::vector<void*> events;           // hipEvent_t pool for kernel timing
   std::vector<uint32_t> ev_used;       // per iteration: which kernels stamped their events

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1660,13 +1661,32 @@ __global__ __launch_bounds__(256) void segment_best_kernel(const uint64_t* __res
 // Host-side launch helpers.
 // ----------------------------------------------------------------------------
 int hip_fail(hipError_t e, const char* what) {
+#ifdef KDSS_FAULT_INJECTION
+  if (e == hipErrorLaunchFailure) return fail(KDSS_EHIP, std::string(what) + ": injected failure");
+#endif
   return fail(KDSS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(call, what)                 \
-  do {                                      \
-    hipError_t e_ = (call);                 \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
+#ifdef KDSS_FAULT_INJECTION
+// Test builds only: after kdss_debug_inject_hip_failure(k), the k-th checked
+// HIP call from then on reports a failure (the call itself has run), so every
+// error path of the run can be driven from the host.
+std::atomic<long> g_inject{-1};
+hipError_t injected_failure() {
+  long v = g_inject.load();
+  while (v > 0 && !g_inject.compare_exchange_weak(v, v - 1)) {
+  }
+  return v == 1 ? hipErrorLaunchFailure : hipSuccess;
+}
+#else
+constexpr hipError_t injected_failure() { return hipSuccess; }
+#endif
+
+#define HIP_TRY(call, what)                              \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ == hipSuccess) e_ = injected_failure();       \
+    if (e_ != hipSuccess) return hip_fail(e_, what);     \
   } while (0)
 
 uint32_t grid_for(size_t n, uint32_t threads = 256, uint32_t cap = 16384) {
@@ -2123,10 +2143,11 @@ void drop_graph(kdss_plan* P) {
   P->graph_r = nullptr;
 }
 
-// Captures one iteration into a graph on a private stream (the caller's
-// stream may be the null stream, which cannot be captured).
+// Captures use_graph consecutive iterations into one graph on a private
+// stream (the caller's stream may be the null stream, which cannot be captured).
 int ensure_graph(kdss_plan* P, const WsView& ws, void* d_r) {
-  if (P->graph_exec && P->graph_ws == ws.base && P->graph_r == d_r) return KDSS_OK;
+  const uint32_t G = (uint32_t)P->opts.use_graph;
+  if (P->graph_exec && P->graph_ws == ws.base && P->graph_r == d_r && P->graph_iters == G) return KDSS_OK;
   drop_graph(P);
   if (!P->capture_stream) {
     hipStream_t s;
@@ -2135,7 +2156,8 @@ int ensure_graph(kdss_plan* P, const WsView& ws, void* d_r) {
   }
   hipStream_t cs = static_cast<hipStream_t>(P->capture_stream);
   HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
-  int rc = launch_iteration(P, ws, d_r, cs);
+  int rc = KDSS_OK;
+  for (uint32_t i = 0; i < G && !rc; ++i) rc = launch_iteration(P, ws, d_r, cs);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &g);
   if (rc) {
@@ -2150,6 +2172,7 @@ int ensure_graph(kdss_plan* P, const WsView& ws, void* d_r) {
   P->graph_exec = ex;
   P->graph_ws = ws.base;
   P->graph_r = d_r;
+  P->graph_iters = G;
   return KDSS_OK;
 }
 
@@ -2192,19 +2215,37 @@ int start_run(kdss_plan* P, const WsView& ws, const uint64_t* d_r0, void* d_r, u
   return KDSS_OK;
 }
 
-// Iteration t (1-based): timed launches, a graph replay, or plain launches.
+// Iteration t (1-based): timed launches, a one-iteration graph replay, or plain launches.
 int iterate(kdss_plan* P, const WsView& ws, void* d_r, uint32_t t, hipStream_t st) {
   if (P->opts.time_kernels) {
     hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(P->events.data()) + (size_t)kEvPerIter * (t - 1);
     return launch_fw_step(P, ws, d_r, st, ev, ws.at<uint32_t>(P->off_qlog) + (t - 1), &P->ev_used[t - 1]);
   }
-  if (P->opts.use_graph) {
+  if (P->opts.use_graph == 1) {
     int rc = ensure_graph(P, ws, d_r);
     if (rc) return rc;
     HIP_TRY(hipGraphLaunch(static_cast<hipGraphExec_t>(P->graph_exec), st), "graph launch");
     return KDSS_OK;
   }
   return launch_iteration(P, ws, d_r, st);
+}
+
+// Iterations t0 .. t0 + count - 1 with nothing between them: with use_graph
+// = G > 1, as replays of one graph of G iterations, the rest one by one.
+int iterate_span(kdss_plan* P, const WsView& ws, void* d_r, uint32_t t0, uint32_t count, hipStream_t st) {
+  const uint32_t G = P->opts.time_kernels ? 0u : (uint32_t)std::max(0, P->opts.use_graph);
+  uint32_t t = t0;
+  if (G > 1 && count >= G) {
+    int rc = ensure_graph(P, ws, d_r);
+    if (rc) return rc;
+    for (; t + G <= t0 + count; t += G)
+      HIP_TRY(hipGraphLaunch(static_cast<hipGraphExec_t>(P->graph_exec), st), "graph launch");
+  }
+  for (; t < t0 + count; ++t) {
+    int rc = G > 1 ? launch_iteration(P, ws, d_r, st) : iterate(P, ws, d_r, t, st);
+    if (rc) return rc;
+  }
+  return KDSS_OK;
 }
 
 // After the stream is synchronised: add the timed kernel durations of T iterations.
@@ -2232,6 +2273,11 @@ int collect_timing(kdss_plan* P, const WsView& ws, uint32_t T) {
 }  // namespace
 
 extern "C" {
+
+#ifdef KDSS_FAULT_INJECTION
+// after > 0: the after-th checked HIP call from now on fails; after <= 0: none.
+void kdss_debug_inject_hip_failure(long after) { g_inject.store(after > 0 ? after : -1); }
+#endif
 
 void kdss_plan_free(kdss_plan* P) {
   if (!P) return;
@@ -2322,7 +2368,11 @@ int run_impl(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, uint32_t t_o
   const uint32_t every = P->opts.extract_every;
   const uint32_t T_all = t_offset + T;
   uint32_t rows = 0;
-  for (uint32_t t = 1; t <= T; ++t) {
+  if (!every || !h_trace) {
+    rc = iterate_span(P, ws, d_r, 1, T, st);
+    if (rc) return rc;
+  }
+  for (uint32_t t = 1; every && h_trace && t <= T; ++t) {
     rc = iterate(P, ws, d_r, t, st);
     if (rc) return rc;
     if (every && (t_offset + t) % every == 0 && t < T && h_trace && rows < trace_cap) {
@@ -2406,10 +2456,8 @@ int kdss_batch_run(kdss_plan* P, void* d_ws, size_t ws_bytes, uint32_t T, const 
   WsView ws{static_cast<char*>(d_ws)};
   rc = start_run(P, ws, d_r0, d_r, T, st);
   if (rc) return rc;
-  for (uint32_t t = 1; t <= T; ++t) {
-    rc = iterate(P, ws, d_r, t, st);
-    if (rc) return rc;
-  }
+  rc = iterate_span(P, ws, d_r, 1, T, st);
+  if (rc) return rc;
   // segmented extraction
   const uint32_t n = P->n;
   const uint64_t* off = ws.at<uint64_t>(P->off_nodeoff);

@@ -114,7 +114,17 @@ def lib():
     # one libkdss binds to, so it is loaded first (a second runtime loaded
     # beside it finds no device)
     import torch  # noqa: F401
-    L = C.CDLL(LIB_PATH)
+    _lib = _bind(C.CDLL(LIB_PATH))
+    return _lib
+
+
+def lib_at(path: str):
+    """Another build of the library (e.g. the fault-injection test build), bound the same way."""
+    import torch  # noqa: F401
+    return _bind(C.CDLL(path))
+
+
+def _bind(L):
     vp, p64, p32 = C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)
     L.kdss_status_string.restype = C.c_char_p
     L.kdss_status_string.argtypes = [C.c_int]
@@ -161,7 +171,6 @@ def lib():
     L.kdss_run_static.argtypes = [vp, C.c_uint32, vp, vp, vp, C.POINTER(Result), vp]
     L.kdss_batch_free.argtypes = [vp]
     L.kdss_batch_free.restype = None
-    _lib = L
     return L
 
 
@@ -307,7 +316,7 @@ class Plan:
     def __init__(self, tree: Tree, T_max: int, r0_max: int = 0, width: int = 0, use_graph: bool = False,
                  extract_every: int = 0, time_kernels: bool = False, gather: int = 0, update: int = 0,
                  schedule: int = 0):
-        o = Opts(width, 1 if use_graph else 0, extract_every, 1 if time_kernels else 0, gather, update, schedule)
+        o = Opts(width, int(use_graph), extract_every, 1 if time_kernels else 0, gather, update, schedule)
         h = C.c_void_p()
         _check(lib().kdss_plan_create(tree._h, T_max, r0_max, C.byref(o), C.byref(h)), "kdss_plan_create")
         self._h = h
@@ -434,7 +443,7 @@ class Batch(Plan):
 
     def __init__(self, trees, T_max: int, r0_max: int = 0, use_graph: bool = False, time_kernels: bool = False,
                  gather: int = 0, update: int = 0, schedule: int = 0):
-        o = Opts(0, 1 if use_graph else 0, 0, 1 if time_kernels else 0, gather, update, schedule)
+        o = Opts(0, int(use_graph), 0, 1 if time_kernels else 0, gather, update, schedule)
         arr = (C.c_void_p * len(trees))(*[t._h for t in trees])
         h = C.c_void_p()
         _check(lib().kdss_batch_create(arr, len(trees), T_max, r0_max, C.byref(o), C.byref(h)), "kdss_batch_create")
