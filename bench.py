@@ -299,9 +299,9 @@ def cpu_baseline_batch(jobs, cks, T, budget_s=15.0):
 
 
 def _within(K, i, K_ref, i_ref, gap):
-    """K / i >= (1 - gap) K_ref / i_ref, exactly (gap given in hundredths)."""
-    h = round(gap * 100)
-    return 100 * K * i_ref >= (100 - h) * K_ref * i
+    """K / i >= (1 - gap) K_ref / i_ref, exactly (gap rounded to ten-thousandths)."""
+    h = round(gap * 10000)
+    return 10000 * K * i_ref >= (10000 - h) * K_ref * i
 
 
 def gnn_bench(w, args):
@@ -316,7 +316,7 @@ def gnn_bench(w, args):
     import numpy as np
     import torch
     from paper_2403_05775_amd import gnn, kdss, synth
-    k, T, t0, gap = w["k"], w["T"], w["t0"], w["gap"]
+    k, T, t0, gap = w["k"], w["T"], w["t0"], (args.gap or w["gap"])
     t_start = time.time()
     g = synth.chung_lu(w["n"], w["m"], w["beta"], seed=w["seed"])
     log(f"graph {g.name}: n={g.n} m={g.m} ({time.time() - t_start:.1f} s)")
@@ -453,7 +453,7 @@ def gnn_bench(w, args):
         "value": warm_ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": warm_ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64 loads; bf16 model with fp32 accumulation", "data": "synthetic",
-        "config": {"workload": f"gnn-warm-2m: {g.name}, k={k}, gap {gap:.0%}", "n": n, "m": g.m, "k": k,
+        "config": {"workload": f"gnn-warm-2m: {g.name}, k={k}, gap {gap:.1%}", "n": n, "m": g.m, "k": k,
                    "leaves": ts.leaves, "members": ts.members, "c_k": ts.c_k.value, "t0": t0,
                    "reference_iterations": Tref, "parallelism": "single GPU"},
         "cold_ms": cold_ms, "speedup": (cold_ms / warm_ms) if warm_ms else None,
@@ -949,6 +949,7 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=0, help="graphs in the batch workload (default 512)")
     ap.add_argument("--gnn-untrained", action="store_true", help="warm start from a randomly initialised model")
     ap.add_argument("--gnn-weights", default="", help="warm-start weights (.npz; default: the package's)")
+    ap.add_argument("--gap", type=float, default=0.0, help="warm-start workload: density gap (default 0.01)")
     args = ap.parse_args()
     if args.summarize_counters:
         res = summarize_counters(args.workload, *args.summarize_counters, args.command)

@@ -20,7 +20,7 @@
  * Conventions as in kdss.h: device pointers are caller-owned, work is
  * enqueued on `stream` (a hipStream_t), status codes are kdss.h's.  Row-major
  * BF16 buffers are uint16_t; leading dimensions count elements and must be
- * multiples of 4 (even for the aggregation); buffers must be 8-byte aligned.
+ * multiples of 8; buffers must be 16-byte aligned.
  */
 #ifndef KDSS_GNN_H
 #define KDSS_GNN_H

@@ -303,17 +303,27 @@ __global__ __launch_bounds__(256) void features_kernel(uint32_t n, const uint64_
 // Mean aggregation over neighbours and its transpose
 // ---------------------------------------------------------------------------
 
-// One wavefront per node.  A row of F BF16 values is read as F / 2 words by a
-// group of F / 2 lanes; the G = 128 / F groups of a wavefront take every G-th
-// neighbour, up to eight loads in flight per lane, and are summed across groups at
-// the end.  Neighbour ids (and, for the transpose, 1 / deg) are loaded 64 at a
-// time, one per lane, and broadcast with shuffles.
+// One wavefront per node.  A row of F BF16 values is read in 16-byte pieces
+// (eight values) by a group of F / 8 lanes; the G = 512 / F groups of a
+// wavefront take every G-th neighbour, U = min(4, 64 / G) pieces in flight per
+// lane, and are summed across groups at the end.  Neighbour ids (and, for the
+// transpose, 1 / deg) are loaded 64 at a time, one per lane, and broadcast
+// with shuffles.  Rows and row strides are multiples of 16 bytes.
+__device__ __forceinline__ void add8(float (&s)[8], const uint4& w, float sc) {
+  const uint32_t x[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    s[2 * i] += bf2f((uint16_t)(x[i] & 0xFFFFu)) * sc;
+    s[2 * i + 1] += bf2f((uint16_t)(x[i] >> 16)) * sc;
+  }
+}
+
 template <uint32_t F, bool kTranspose>
 __device__ __forceinline__ void aggregate_row(uint32_t u, uint32_t lane, const uint64_t* __restrict__ row_ptr,
-                                              const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
-                                              uint32_t ld_words, float& s0, float& s1) {
-  constexpr uint32_t LPR = F / 2, G = 64 / LPR;
-  constexpr uint32_t U = G >= 8 ? 64 / G : 8;   // loads in flight per lane
+                                              const uint32_t* __restrict__ col, const uint4* __restrict__ src,
+                                              uint32_t ld_vec, float (&s)[8]) {
+  constexpr uint32_t LPR = F / 8, G = 64 / LPR;
+  constexpr uint32_t U = G >= 16 ? 64 / G : 4;   // pieces in flight per lane
   const uint32_t g = lane / LPR, q = lane % LPR;
   const uint64_t b = row_ptr[u], e = row_ptr[u + 1];
   for (uint64_t c0 = b; c0 < e; c0 += 64) {
@@ -325,42 +335,46 @@ __device__ __forceinline__ void aggregate_row(uint32_t u, uint32_t lane, const u
       if (kTranspose) myw = 1.f / (float)(row_ptr[my + 1] - row_ptr[my]);
     }
     for (uint32_t j0 = 0; j0 < cnt; j0 += U * G) {
-      uint32_t w[U];
+      uint4 w[U];
       float sc[U];
 #pragma unroll
       for (uint32_t t = 0; t < U; ++t) {
         const uint32_t j = j0 + t * G + g;
         const uint32_t v = __shfl(my, (int)(j & 63u));
         sc[t] = kTranspose ? __shfl(myw, (int)(j & 63u)) : 1.f;
-        w[t] = j < cnt ? src[(size_t)v * ld_words + q] : 0u;
+        w[t] = j < cnt ? src[(size_t)v * ld_vec + q] : make_uint4(0u, 0u, 0u, 0u);
       }
 #pragma unroll
-      for (uint32_t t = 0; t < U; ++t) {
-        s0 += bf2f((uint16_t)(w[t] & 0xFFFFu)) * sc[t];
-        s1 += bf2f((uint16_t)(w[t] >> 16)) * sc[t];
-      }
+      for (uint32_t t = 0; t < U; ++t) add8(s, w[t], sc[t]);
     }
   }
-  for (uint32_t d = LPR; d < 64; d <<= 1) {
-    s0 += __shfl_xor(s0, (int)d);
-    s1 += __shfl_xor(s1, (int)d);
-  }
+#pragma unroll
+  for (uint32_t d = LPR; d < 64; d <<= 1)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i] += __shfl_xor(s[i], (int)d);
+}
+
+__device__ __forceinline__ uint4 pack8(const float (&s)[8], float scale) {
+  uint32_t x[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    x[i] = (uint32_t)f2bf(s[2 * i] * scale) | ((uint32_t)f2bf(s[2 * i + 1] * scale) << 16);
+  return make_uint4(x[0], x[1], x[2], x[3]);
 }
 
 template <uint32_t F>
 __global__ __launch_bounds__(256) void aggregate_kernel(uint32_t n, const uint64_t* __restrict__ row_ptr,
                                                         const uint32_t* __restrict__ col,
-                                                        const uint32_t* __restrict__ h, uint32_t* __restrict__ out) {
+                                                        const uint4* __restrict__ h, uint4* __restrict__ out) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
   const uint32_t nw = gridDim.x * 4u;
   for (uint32_t u = wave; u < n; u += nw) {
-    float s0 = 0.f, s1 = 0.f;
-    aggregate_row<F, false>(u, lane, row_ptr, col, h, F / 2, s0, s1);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    aggregate_row<F, false>(u, lane, row_ptr, col, h, F / 8, s);
     const uint64_t deg = row_ptr[u + 1] - row_ptr[u];
     const float inv = deg ? 1.f / (float)deg : 0.f;
-    if (lane < F / 2)
-      out[(size_t)u * (F / 2) + lane] = (uint32_t)f2bf(s0 * inv) | ((uint32_t)f2bf(s1 * inv) << 16);
+    if (lane < F / 8) out[(size_t)u * (F / 8) + lane] = pack8(s, inv);
   }
 }
 
@@ -369,20 +383,18 @@ __global__ __launch_bounds__(256) void aggregate_kernel(uint32_t n, const uint64
 template <uint32_t F>
 __global__ __launch_bounds__(256) void aggregate_backward_kernel(uint32_t n, const uint64_t* __restrict__ row_ptr,
                                                                  const uint32_t* __restrict__ col,
-                                                                 const uint32_t* __restrict__ dagg,
-                                                                 const uint32_t* __restrict__ dself,
-                                                                 uint32_t ld_words, uint32_t* __restrict__ out) {
+                                                                 const uint4* __restrict__ dagg,
+                                                                 const uint4* __restrict__ dself,
+                                                                 uint32_t ld_vec, uint4* __restrict__ out) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
   const uint32_t nw = gridDim.x * 4u;
   for (uint32_t v = wave; v < n; v += nw) {
-    float s0 = 0.f, s1 = 0.f;
-    aggregate_row<F, true>(v, lane, row_ptr, col, dagg, ld_words, s0, s1);
-    if (lane < F / 2) {
-      const uint32_t d = dself[(size_t)v * ld_words + lane];
-      s0 += bf2f((uint16_t)(d & 0xFFFFu));
-      s1 += bf2f((uint16_t)(d >> 16));
-      out[(size_t)v * (F / 2) + lane] = (uint32_t)f2bf(s0) | ((uint32_t)f2bf(s1) << 16);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    aggregate_row<F, true>(v, lane, row_ptr, col, dagg, ld_vec, s);
+    if (lane < F / 8) {
+      add8(s, dself[(size_t)v * ld_vec + lane], 1.f);
+      out[(size_t)v * (F / 8) + lane] = pack8(s, 1.f);
     }
   }
 }
@@ -679,9 +691,11 @@ int kdss_gnn_aggregate(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_
   if (!d_row_ptr || (!d_col && n) || !d_h || !d_out) return fail(KDSS_EINVAL, "null argument");
   if (F != 8 && F != 16 && F != 32 && F != 64) return fail(KDSS_EINVAL, "F must be 8, 16, 32 or 64");
   if (n == 0) return KDSS_OK;
+  if ((reinterpret_cast<uintptr_t>(d_h) | reinterpret_cast<uintptr_t>(d_out)) & 15u)
+    return fail(KDSS_EINVAL, "h and out must be 16-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const uint32_t* h = reinterpret_cast<const uint32_t*>(d_h);
-  uint32_t* out = reinterpret_cast<uint32_t*>(d_out);
+  const uint4* h = reinterpret_cast<const uint4*>(d_h);
+  uint4* out = reinterpret_cast<uint4*>(d_out);
   const uint32_t grid = blocks_for(n, 4, 16384);
   switch (F) {
     case 8: aggregate_kernel<8><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, h, out); break;
@@ -696,19 +710,22 @@ int kdss_gnn_aggregate(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_
 int kdss_gnn_aggregate_backward(uint32_t n, const uint64_t* d_row_ptr, const uint32_t* d_col, const uint16_t* d_dagg,
                                 const uint16_t* d_dself, uint32_t F, uint32_t ld, uint16_t* d_out, void* stream) {
   if (!d_row_ptr || (!d_col && n) || !d_dagg || !d_dself || !d_out) return fail(KDSS_EINVAL, "null argument");
-  if ((F != 8 && F != 16 && F != 32 && F != 64) || ld < F || ld % 2)
-    return fail(KDSS_EINVAL, "F must be 8, 16, 32 or 64; ld >= F and even");
+  if ((F != 8 && F != 16 && F != 32 && F != 64) || ld < F || ld % 8)
+    return fail(KDSS_EINVAL, "F must be 8, 16, 32 or 64; ld >= F and a multiple of 8");
+  if ((reinterpret_cast<uintptr_t>(d_dagg) | reinterpret_cast<uintptr_t>(d_dself) |
+       reinterpret_cast<uintptr_t>(d_out)) & 15u)
+    return fail(KDSS_EINVAL, "dagg, dself and out must be 16-byte aligned");
   if (n == 0) return KDSS_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const uint32_t* da = reinterpret_cast<const uint32_t*>(d_dagg);
-  const uint32_t* ds = reinterpret_cast<const uint32_t*>(d_dself);
-  uint32_t* out = reinterpret_cast<uint32_t*>(d_out);
+  const uint4* da = reinterpret_cast<const uint4*>(d_dagg);
+  const uint4* ds = reinterpret_cast<const uint4*>(d_dself);
+  uint4* out = reinterpret_cast<uint4*>(d_out);
   const uint32_t grid = blocks_for(n, 4, 16384);
   switch (F) {
-    case 8: aggregate_backward_kernel<8><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out); break;
-    case 16: aggregate_backward_kernel<16><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out); break;
-    case 32: aggregate_backward_kernel<32><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out); break;
-    default: aggregate_backward_kernel<64><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 2, out); break;
+    case 8: aggregate_backward_kernel<8><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 8, out); break;
+    case 16: aggregate_backward_kernel<16><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 8, out); break;
+    case 32: aggregate_backward_kernel<32><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 8, out); break;
+    default: aggregate_backward_kernel<64><<<grid, 256, 0, st>>>(n, d_row_ptr, d_col, da, ds, ld / 8, out); break;
   }
   HIP_TRY(hipGetLastError(), "aggregate backward launch");
   return KDSS_OK;

@@ -385,17 +385,22 @@ def main(argv=None):
     val = prepare(g_val, k=args.k, T=args.T, log=log, feature_set=args.feature_set)
     data = prepare(g_train, k=args.k, T=args.T, log=log, feature_set=args.feature_set)
     log(f"data ready in {time.time() - t0:.0f} s")
+    model = None
     if args.curve:
-        # held-out loss after training on the first c graphs, for each c
+        # held-out loss after training on the first c graphs, for each c (the
+        # run on all graphs, when listed last, is the saved model)
         curve = {}
         for c in (int(x) for x in args.curve.split(",")):
             m = Model(seed=0)
-            train(m, data[:c], epochs=args.epochs, lr=args.lr, log=lambda *_: None)
+            hist = train(m, data[:c], epochs=args.epochs, lr=args.lr, log=lambda *_: None)
             curve[c] = evaluate(m, val)
-            log(f"curve: {c} graphs -> held-out loss {curve[c]:.5f}")
+            log(f"curve: {c} graphs -> held-out loss {curve[c]:.5f} (last epoch's training loss {hist[-1]:.5f})")
+            if c >= len(data):
+                model = m
         print("CURVE " + " ".join(f"{c}:{v:.6f}" for c, v in curve.items()), flush=True)
-    model = Model(seed=0)
-    hist = train(model, data, epochs=args.epochs, lr=args.lr, val=val, log=log)
+    if model is None:
+        model = Model(seed=0)
+        hist = train(model, data, epochs=args.epochs, lr=args.lr, val=val, log=log)
     state = model.state()
     state.update(meta_graphs=np.int64(args.graphs), meta_k=np.int64(args.k), meta_T=np.int64(args.T),
                  meta_epochs=np.int64(args.epochs), meta_train_loss=np.float64(hist[-1]),
