@@ -2137,7 +2137,7 @@ int read_result(const kdss_plan* P, const WsView& ws, hipStream_t st, DevResult*
 }
 
 void drop_graph(kdss_plan* P) {
-  if (P->graph_exec) hipGraphExecDestroy(static_cast<hipGraphExec_t>(P->graph_exec));
+  if (P->graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(P->graph_exec));
   P->graph_exec = nullptr;
   P->graph_ws = nullptr;
   P->graph_r = nullptr;
@@ -2161,13 +2161,13 @@ int ensure_graph(kdss_plan* P, const WsView& ws, void* d_r) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &g);
   if (rc) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) return hip_fail(e, "end capture");
   hipGraphExec_t ex = nullptr;
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) return hip_fail(e, "graph instantiate");
   P->graph_exec = ex;
   P->graph_ws = ws.base;
@@ -2282,8 +2282,8 @@ void kdss_debug_inject_hip_failure(long after) { g_inject.store(after > 0 ? afte
 void kdss_plan_free(kdss_plan* P) {
   if (!P) return;
   drop_graph(P);
-  for (void* e : P->events) hipEventDestroy(static_cast<hipEvent_t>(e));
-  if (P->capture_stream) hipStreamDestroy(static_cast<hipStream_t>(P->capture_stream));
+  for (void* e : P->events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+  if (P->capture_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(P->capture_stream));
   delete P;
 }
 
@@ -2620,8 +2620,8 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
       P->sched = out->best_schedule;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   P->opts = saved;
   if (rc) return rc;
   P->leaf_blocks = out->best_leaf_blocks;
