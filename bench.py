@@ -809,9 +809,9 @@ def tree_growth(args):
 
 def single_bench(w, args):
     """One plan (one graph, one k): a step is start loads + T iterations + the
-    extraction on inputs resident in HBM.  The timed steps run with
-    kernel-attached HIP events on every iteration kernel, which give the
-    per-launch durations of the roofline fields."""
+    extraction on inputs resident in HBM.  The timed steps launch plainly; the
+    same number of steps after them, with kernel-attached HIP events on every
+    iteration kernel, give the per-launch durations of the roofline fields."""
     import torch
     from paper_2403_05775_amd import kdss
     t0 = time.time()

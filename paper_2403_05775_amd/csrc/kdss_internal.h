@@ -115,6 +115,7 @@ constexpr uint32_t kSortThreads = 256, kSortItems = 8, kSortTile = kSortThreads 
 constexpr uint32_t kScanThreads = 256, kScanItems = 4, kScanTile = kScanThreads * kScanItems;
 constexpr uint32_t kRedThreads = 256, kRedTile = 4096;
 constexpr uint32_t kBinomLds = 512;              // binomial tables up to this size live in LDS
+constexpr uint32_t kHeavyBinomLds = 1024;        // ... in the heavy-leaf pass (s_max 64 at k <= 14)
 // Hot nodes: the nodes that occur in the most leaves.  Their member ids carry
 // kHotFlag | index into the hot table; every workgroup keeps their keys and
 // credits in LDS and adds its nonzero credit totals, at its end, into one of

@@ -535,13 +535,13 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
 
 // Heavy leaves (more than four pivot members below the hold minimum), queued
 // by the leaf-credit kernel as 16-byte entries: one leaf per wavefront, one
-// member per lane, four leaves per batch so their loads overlap.  The hold
+// member per lane, four leaves per batch, the batches pipelined.  The hold
 // minimum m is recomputed; the rank of a low member among the low members is
 // counted with wavefront ballots.  Hot members' keys come from the table the
 // leaf pass published; their credits add up in LDS and reach the nodes' slot
 // entries (slot blockIdx.x % kHotSlots) once per workgroup.  Workgroups past the queue
 // return at once.
-template <class KT>
+template <class KT, bool kLdsBinom>
 __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__ members,
                                                     const uint64_t* __restrict__ binom, uint32_t k1, KeySrc src,
                                                     uint64_t* __restrict__ out, uint32_t nhot,
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__
   constexpr uint32_t B = 4;
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
-  __shared__ uint64_t sbinom[kBinomLds];
+  __shared__ uint64_t sbinom[kLdsBinom ? kHeavyBinomLds : 1];
   __shared__ KT lowk[4][B][64];   // per wavefront and queued leaf: its low members' keys, compacted
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -560,35 +560,55 @@ __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__
   if ((blockIdx.x * 4u) * B >= total) return;   // no entries for this workgroup (uniform)
   // member x of the queued leaf: its first word + 64 x
   const uint64_t xoff = (uint64_t)64 * lane;
-  uint32_t hq[B], sq[B], jq[B], ra[B], nb[B];
-  // headers and member ids of the batch of entries e0 .. e0 + B - 1
-  auto fetch = [&](uint32_t e0) {
+  const uint32_t stride = nw * B;
+  // The batches of a wavefront form a three-stage pipeline: while batch i's
+  // keys are gathered and ranked, batch i + 1's member words and batch i + 2's
+  // entries are in flight.  Lane q loads entry q of a batch (one vector load
+  // per batch) and the fields are broadcast from it; lanes past a leaf read
+  // the leaf's first word (in bounds) and drop it.  Batches past the queue
+  // read its last entry and are not credited.
+  auto entries = [&](uint32_t e0) -> uint4 {
+    return queue[min(min(e0, total - 1) + min(lane, B - 1), total - 1)];
+  };
+  uint32_t hq1[B], sq1[B], jq1[B], nb1[B], wd1[B];
+  auto words = [&](const uint4& ent) {
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
-      const uint4 ent = queue[min(e0 + q, total - 1)];
-      const uint64_t mw = ((uint64_t)ent.y << 32) | ent.x;
-      const uint32_t hd = ent.z;
-      nb[q] = ent.w;
-      hq[q] = hd & 31u;
-      jq[q] = (hd >> 5) & 31u;
-      sq[q] = hq[q] + (hd >> 10);
-      ra[q] = lane < sq[q] ? members[mw + xoff] : 0u;
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)ent.x, q);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)ent.y, q);
+      const uint32_t hd = (uint32_t)__builtin_amdgcn_readlane((int)ent.z, q);
+      nb1[q] = (uint32_t)__builtin_amdgcn_readlane((int)ent.w, q);
+      const uint64_t mw = ((uint64_t)hi << 32) | lo;
+      hq1[q] = hd & 31u;
+      jq1[q] = (hd >> 5) & 31u;
+      sq1[q] = hq1[q] + (hd >> 10);
+      wd1[q] = members[mw + (lane < sq1[q] ? xoff : 0ull)];
     }
   };
   const uint32_t first = (blockIdx.x * 4u + w) * B;
-  if (first < total) fetch(first);   // in flight during the LDS set-up
+  uint4 ent2 = make_uint4(0u, 0u, 0u, 0u);
+  if (first < total) {   // in flight during the LDS set-up
+    words(entries(first));
+    ent2 = entries(first + stride);
+  }
   for (uint32_t i = threadIdx.x; i < nhot; i += blockDim.x) {
     hkey[i] = hotkey[i];
     hcnt[i] = 0;
   }
-  const bool lds_binom = nbinom <= kBinomLds;
-  if (lds_binom)
+  if (kLdsBinom)
     for (uint32_t i = threadIdx.x; i < nbinom; i += blockDim.x) sbinom[i] = binom[i];
   __syncthreads();
-  const uint64_t* bt = lds_binom ? sbinom : binom;
   Sink sink{hcnt, out, 0u, 0ull};
-  for (uint32_t e0 = first; e0 < total; e0 += nw * B) {
-    if (e0 != first) fetch(e0);
+  for (uint32_t e0 = first; e0 < total; e0 += stride) {
+    uint32_t hq[B], sq[B], jq[B], ra[B], nb[B];
+#pragma unroll
+    for (uint32_t q = 0; q < B; ++q) {
+      hq[q] = hq1[q];
+      sq[q] = sq1[q];
+      jq[q] = jq1[q];
+      nb[q] = nb1[q];
+      ra[q] = lane < sq[q] ? wd1[q] : 0u;
+    }
     // every lane gathers (a hot member's hot index and a missing member's 0
     // are node ids too), so the four gathers are in flight together; the LDS
     // key, or the maximum past the leaf, is selected afterwards
@@ -599,6 +619,11 @@ __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__
       ts.base = nb[q];
       ka[q] = KT::load(ts, ra[q] & ~kHotFlag);
     }
+    // the next batch's member words, and the entries of the one after (also
+    // past the queue, unconditionally, so the wait for this batch's keys
+    // below leaves them in flight)
+    words(ent2);
+    ent2 = entries(e0 + 2 * stride);
 #pragma unroll
     for (uint32_t q = 0; q < B; ++q) {
       ka[q] = KT::pick((ra[q] & kHotFlag) != 0, hkey[ra[q] & (kHotMax - 1)], ka[q]);
@@ -638,7 +663,11 @@ __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__
       for (uint32_t i = 0; i < nlow[q]; ++i) below += lowk[w][q][i].lt(ka[q]) ? 1u : 0u;
       const uint32_t p = sq[q] - hq[q], j = jq[q];
       if (low[q] && j >= 1) {
-        const uint64_t c = bt[(size_t)(p - 1 - below) * k1 + (j - 1)];
+        // the table from LDS or from memory, chosen at compile time (a
+        // pointer chosen at run time would make a flat load, whose wait would
+        // also drain the next batches' loads)
+        const size_t bi = (size_t)(p - 1 - below) * k1 + (j - 1);
+        const uint64_t c = kLdsBinom ? sbinom[bi] : binom[bi];
         if (c) sink.add(ra[q], c);
       }
     }
@@ -1760,8 +1789,9 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
     launch_timed(leaf_credit_kernel<KT, true>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members,    \
                  hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,              \
                  ws.at<KT>(table_off), hot_published, xcd);                                                     \
-  launch_timed(heavy_kernel<KT>, P->heavy_blocks, 256, 0, st, ev_heavy, members, binom, P->k1, src, out, nhot,  \
-               scratch, (const uint4*)queue, (const uint32_t*)qcount, (const KT*)ws.at<KT>(table_off), nbinom)
+  launch_timed(nbinom <= kHeavyBinomLds ? heavy_kernel<KT, true> : heavy_kernel<KT, false>, P->heavy_blocks, 256, 0, \
+               st, ev_heavy, members, binom, P->k1, src, out, nhot, scratch, (const uint4*)queue,                  \
+               (const uint32_t*)qcount, (const KT*)ws.at<KT>(table_off), nbinom)
   if (used) *used |= 1u | 2u;
   switch (mode) {
     case 0: KDSS_LEAF(KPacked); break;
