@@ -277,6 +277,18 @@ struct WaveQueue {
 // with more go to the heavy-leaf queue.  Keys are gathered only for members
 // inside the lane's leaf that are not hot (hot keys come from LDS).
 constexpr uint32_t kLeafThreads = 256;   // leaf-credit workgroup size (LDS slot stride)
+
+// A tile descriptor's fields (and one padding word, see the leaf-credit loop).
+__device__ __forceinline__ Tile load_tile(const Tile* __restrict__ tiles, uint32_t i) {
+  const uint4 a = reinterpret_cast<const uint4*>(tiles + i)[0];
+  Tile t{};
+  t.mbase = ((uint64_t)a.y << 32) | a.x;
+  t.lbase = a.z;
+  t.info = a.w;
+  t.nbase = reinterpret_cast<const uint32_t*>(tiles + i)[4];
+  t.pad[0] = reinterpret_cast<const uint32_t*>(tiles + i)[5];
+  return t;
+}
 template <class KT, bool kMasked>
 __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, const uint32_t* __restrict__ members,
                                           const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k1,
@@ -285,17 +297,19 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
   constexpr uint32_t U = kLaneBatch;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nl = (t.info >> 3) & 0x1FFFu, smax = t.info >> 16;
-  const uint32_t hd = lane < nl ? hdr[t.lbase + lane] : 0u;   // a missing leaf reads as empty
-  const uint32_t h = hd & 31u, j = (hd >> 5) & 31u, p = hd >> 10, s = h + p;
   const uint32_t* __restrict__ col = members + t.mbase + lane;
-  KT km = KT::mx();
-  uint32_t mraw = 0, nlow = 0;
   // rows past the tile repeat its last; each batch's rows are requested
   // during the batch before, right after that batch's key gathers, so waiting
-  // for those keys leaves the rows in flight
+  // for those keys leaves the rows in flight.  The first batch's rows go out
+  // before the headers, so the two requests overlap.
   uint32_t nxt[U];
 #pragma unroll
   for (uint32_t u = 0; u < U; ++u) nxt[u] = col[(size_t)min(u, smax - 1) * 64];
+  __builtin_amdgcn_sched_barrier(0);
+  const uint32_t hd = lane < nl ? hdr[t.lbase + lane] : 0u;   // a missing leaf reads as empty
+  const uint32_t h = hd & 31u, j = (hd >> 5) & 31u, p = hd >> 10, s = h + p;
+  KT km = KT::mx();
+  uint32_t mraw = 0, nlow = 0;
   for (uint32_t x0 = 0; x0 < smax; x0 += U) {
     uint32_t raw[U];
     KT key[U], hk[U];
@@ -479,7 +493,6 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
     stride = ((gridDim.x - x + kXcds - 1) / kXcds) * 4u;
     tend = xcd[x + 1];
   }
-  const uint32_t first = tile;
   Tile t = tile < tend ? tiles[tile] : Tile{};   // in flight during the LDS set-up
   if (hot_published) {
     // the hot keys at these loads were written by the previous load update
@@ -504,11 +517,16 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
   Sink sink{hcnt, out, 0u, 0ull};
   WaveQueue hq{qslice[w], 0u};
   for (; tile < tend; tile += stride) {
-    if (tile != first) t = tiles[tile];   // the first one is loaded
+    // the next tile's descriptor, in flight during this tile (scalar loads)
+    const Tile tn = load_tile(tiles, min(tile + stride, tend - 1));
     KeySrc ts = src;
     ts.base = t.nbase;
     if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k1, ts, hkey, sink);
     else tile_lane<KT, kMasked>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq, lcol);
+    // the descriptor's last loaded word is kept alive to here, so its register
+    // is not reused (and the load not waited for) while this tile runs
+    asm volatile("" ::"s"(tn.pad[0]));
+    t = tn;
   }
   sink.flush();
   // the heavy entries the four wavefronts still stage: one counter atomic for
