@@ -738,8 +738,10 @@ def summarize_counters(workload, fetch_db, write_db, valu_db, command):
     return out
 
 
-def summarize_trace(db, command):
-    """Kernel-trace statistics (rocprofv3 --kernel-trace --stats) as markdown."""
+def summarize_trace(db, command, bench_json=None):
+    """Kernel-trace statistics (rocprofv3 --kernel-trace --stats) as markdown;
+    with the JSON line the traced bench printed, also its launch and its own
+    (kernel-attached event) per-launch durations, to compare."""
     import sqlite3
     c = sqlite3.connect(db)
     lines = ["# Kernel trace: " + command, "",
@@ -754,6 +756,17 @@ def summarize_trace(db, command):
         short = name.replace("(anonymous namespace)::", "").split("(")[0]
         lines.append(f"| {short} | {wg} | {calls} | {tot / 1e3:.1f} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | "
                      f"{mx / 1e3:.2f} |")
+    if bench_json:
+        try:
+            line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        except (OSError, ValueError, IndexError):
+            line = None
+        if line:
+            lines += ["", "The traced bench's own line (same run):", "",
+                      f"- launch: {json.dumps(line.get('launch'))}",
+                      f"- per-launch durations from kernel-attached events, us: {json.dumps(line.get('kernel_us'))}",
+                      f"- ms_per_step {line.get('ms_per_step'):.3f} (under the profiler), roofline frac "
+                      f"{(line.get('roofline') or {}).get('frac')}"]
     return "\n".join(lines) + "\n"
 
 
@@ -944,6 +957,7 @@ def main():
                     help="counters: short run for rocprofv3 --pmc passes (with a copy calibration)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "VALU_DB"))
     ap.add_argument("--summarize-trace", metavar="DB")
+    ap.add_argument("--bench-json", default="", help="summarize-trace: the traced bench's JSON output")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
     ap.add_argument("--out", default="")
     ap.add_argument("--batch-graphs", type=int, default=0, help="graphs in the batch workload (default 512)")
@@ -958,7 +972,7 @@ def main():
         print(json.dumps(res))
         return
     if args.summarize_trace:
-        md = summarize_trace(args.summarize_trace, args.command)
+        md = summarize_trace(args.summarize_trace, args.command, args.bench_json or None)
         if args.out:
             open(args.out, "w").write(md)
         print(md)
