@@ -156,9 +156,17 @@ struct Sink {
   }
 };
 
+// A member's key: from the hot table in LDS or from the loads in memory, each
+// by its own unconditional load and the key chosen afterwards (a load in each
+// arm of a choice becomes one flat load through a chosen pointer, and the
+// wait for a flat load drains every load in flight).  A hot member reads the
+// problem's first node (in bounds) and drops it.
 template <class KT>
 __device__ __forceinline__ KT member_key(const KeySrc& src, const KT* hkey, uint32_t raw) {
-  return (raw & kHotFlag) ? hkey[raw & ~kHotFlag] : KT::load(src, raw);
+  const bool hot = (raw & kHotFlag) != 0;
+  const KT g = KT::load(src, hot ? src.base : raw);
+  const KT hk = hkey[raw & (kHotMax - 1)];
+  return KT::pick(hot, hk, g);
 }
 
 // Gather modes of the lane-tile pass (every lane gathers a key for every row,
@@ -366,20 +374,26 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
     // the low members' keys again (unused slots hold the maximum key), and
     // the rank of each among the low members
     const uint32_t r0 = lcol[0], r1 = lcol[kLeafThreads], r2 = lcol[2 * kLeafThreads], r3 = lcol[3 * kLeafThreads];
+    // (all four read together; a slot past nlow holds a valid member word,
+    // of this tile or an earlier one, and its key is replaced by the maximum)
     const KT l0 = member_key<KT>(src, hkey, r0);
-    KT l1 = KT::mx(), l2 = KT::mx(), l3 = KT::mx();
-    if (nlow > 1) l1 = member_key<KT>(src, hkey, r1);
-    if (nlow > 2) l2 = member_key<KT>(src, hkey, r2);
-    if (nlow > 3) l3 = member_key<KT>(src, hkey, r3);
+    const KT l1 = KT::pick(nlow > 1, member_key<KT>(src, hkey, r1), KT::mx());
+    const KT l2 = KT::pick(nlow > 2, member_key<KT>(src, hkey, r2), KT::mx());
+    const KT l3 = KT::pick(nlow > 3, member_key<KT>(src, hkey, r3), KT::mx());
     const uint32_t b0 = (l1.lt(l0) ? 1u : 0u) + (l2.lt(l0) ? 1u : 0u) + (l3.lt(l0) ? 1u : 0u);
     const uint32_t b1 = (l0.lt(l1) ? 1u : 0u) + (l2.lt(l1) ? 1u : 0u) + (l3.lt(l1) ? 1u : 0u);
     const uint32_t b2 = (l0.lt(l2) ? 1u : 0u) + (l1.lt(l2) ? 1u : 0u) + (l3.lt(l2) ? 1u : 0u);
     const uint32_t b3 = (l0.lt(l3) ? 1u : 0u) + (l1.lt(l3) ? 1u : 0u) + (l2.lt(l3) ? 1u : 0u);
+    // the four binomials read together (an unused slot reads row 0)
     const uint64_t* row = binom + (j - 1);
-    sink.add(r0, row[(size_t)(p - 1 - b0) * k1]);
-    if (nlow > 1) sink.add(r1, row[(size_t)(p - 1 - b1) * k1]);
-    if (nlow > 2) sink.add(r2, row[(size_t)(p - 1 - b2) * k1]);
-    if (nlow > 3) sink.add(r3, row[(size_t)(p - 1 - b3) * k1]);
+    const uint64_t c0 = row[(size_t)(p - 1 - b0) * k1];
+    const uint64_t c1 = row[(size_t)(nlow > 1 ? p - 1 - b1 : 0u) * k1];
+    const uint64_t c2 = row[(size_t)(nlow > 2 ? p - 1 - b2 : 0u) * k1];
+    const uint64_t c3 = row[(size_t)(nlow > 3 ? p - 1 - b3 : 0u) * k1];
+    sink.add(r0, c0);
+    if (nlow > 1) sink.add(r1, c1);
+    if (nlow > 2) sink.add(r2, c2);
+    if (nlow > 3) sink.add(r3, c3);
   }
   // Leaves with more than four low members go to the heavy-leaf queue (through
   // the wavefront's LDS buffer); the heavy kernel spreads them over the grid.
@@ -463,7 +477,7 @@ __device__ __forceinline__ void tile_big(const Tile& t, const uint32_t* __restri
 // Eight wavefronts per SIMD (<= 64 VGPRs, 18 KB of LDS per workgroup): the
 // pass is latency-bound, and occupancy hides more of it than wider row
 // batches do.
-template <class KT, bool kMasked>
+template <class KT, bool kMasked, bool kLdsBinom>
 __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restrict__ tiles, uint32_t ntiles,
                                                           const uint32_t* __restrict__ members,
                                                           const uint32_t* __restrict__ hdr,
@@ -476,7 +490,7 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
                                                           bool hot_published, const uint32_t* __restrict__ xcd) {
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
-  __shared__ uint64_t sbinom[kBinomLds];
+  __shared__ uint64_t sbinom[kLdsBinom ? kBinomLds : 1];
   __shared__ uint4 qslice[4][kQueueBuf];
   __shared__ uint32_t lowslot[4 * kLeafThreads];   // four low-member slots per lane
   uint32_t* lcol = lowslot + threadIdx.x;
@@ -509,11 +523,12 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
       if (blockIdx.x == 0) hotkey[i] = hkey[i];   // for the heavy pass
     }
   }
-  const bool lds_binom = nbinom <= kBinomLds;
-  if (lds_binom)
+  if (kLdsBinom)
     for (uint32_t i = threadIdx.x; i < nbinom; i += blockDim.x) sbinom[i] = binom[i];
   __syncthreads();
-  const uint64_t* bt = lds_binom ? sbinom : binom;
+  // the binomial table's memory space fixed at compile time (a pointer chosen
+  // at run time would make flat loads, whose waits drain every load in flight)
+  const uint64_t* bt = kLdsBinom ? sbinom : binom;
   Sink sink{hcnt, out, 0u, 0ull};
   WaveQueue hq{qslice[w], 0u};
   for (; tile < tend; tile += stride) {
@@ -732,6 +747,18 @@ __device__ __forceinline__ uint64_t pb_level_sum(const uint64_t* lr, uint32_t st
   return S;
 }
 
+// A member's load: from the hot table in LDS or the load array in memory,
+// each by its own unconditional load and the value chosen afterwards (a load
+// in each arm of a choice becomes one flat load through a chosen pointer,
+// whose wait drains every load in flight).  Hot members read r[0] (in bounds)
+// and drop it.
+__device__ __forceinline__ uint64_t pb_member_load(const uint64_t* __restrict__ r, const uint64_t* hr, uint32_t raw) {
+  const bool hot = (raw & kHotFlag) != 0;
+  const uint64_t g = r[hot ? 0u : raw];
+  const uint64_t hv = hr[raw & (kHotMax - 1)];
+  return hot ? hv : g;
+}
+
 __device__ __forceinline__ uint32_t pb_node_id(uint32_t raw, const uint32_t* hid) {
   return (raw & kHotFlag) ? hid[raw & (kHotMax - 1)] : raw;
 }
@@ -900,7 +927,7 @@ __global__ __launch_bounds__(256) void pb_kernel(const Tile* __restrict__ tiles,
       wave_lds_sync();   // the previous tile's reads are done
       for (uint32_t x = lane; x < sz; x += 64) {
         const uint32_t raw = lm[x];
-        lr[x] = (raw & kHotFlag) ? hr[raw & (kHotMax - 1)] : r[raw];
+        lr[x] = pb_member_load(r, hr, raw);
       }
       wave_lds_sync();
       const uint64_t nC = binom[(size_t)p * k1 + j], cp = j ? binom[(size_t)(p - 1) * k1 + (j - 1)] : 0ull;
@@ -913,7 +940,7 @@ __global__ __launch_bounds__(256) void pb_kernel(const Tile* __restrict__ tiles,
       wave_lds_sync();
       for (uint32_t x = 0; x < smax; ++x) {
         const uint32_t raw = col[(size_t)x * 64];
-        lr[(size_t)x * 64 + lane] = (raw & kHotFlag) ? hr[raw & (kHotMax - 1)] : r[raw];
+        lr[(size_t)x * 64 + lane] = pb_member_load(r, hr, raw);
       }
       const uint64_t nC = hd ? binom[(size_t)p * k1 + j] : 0ull;
       const uint64_t cp = (hd && j) ? binom[(size_t)(p - 1) * k1 + (j - 1)] : 0ull;
@@ -958,7 +985,7 @@ __device__ __forceinline__ void pb_tile_reg(const Tile& t, const uint32_t* __res
 #pragma unroll
   for (int x = 0; x < SM; ++x) raw[x] = (uint32_t)x < smax ? col[(size_t)x * 64] : 0u;
 #pragma unroll
-  for (int x = 0; x < SM; ++x) rv[x] = (raw[x] & kHotFlag) ? hr[raw[x] & (kHotMax - 1)] : r[raw[x]];
+  for (int x = 0; x < SM; ++x) rv[x] = pb_member_load(r, hr, raw[x]);
   const uint64_t nC = hd ? binom[(size_t)p * k1 + j] : 0ull;
   const uint64_t cp = (hd && j) ? binom[(size_t)(p - 1) * k1 + (j - 1)] : 0ull;
   if (s == 0 || nC == 0) return;
@@ -1798,15 +1825,18 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   const uint32_t* xcd = P->sched == 2 ? ws.at<uint32_t>(P->off_xcd) : nullptr;
   hipEvent_t* ev_leaf = ev ? ev + kEvLeaf : nullptr;
   hipEvent_t* ev_heavy = ev ? ev + kEvHeavy : nullptr;
+#define KDSS_LEAF_V(KT, MASKED, LDSB)                                                                           \
+  launch_timed(leaf_credit_kernel<KT, MASKED, LDSB>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members, \
+               hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,                \
+               ws.at<KT>(table_off), hot_published, xcd)
 #define KDSS_LEAF(KT)                                                                                           \
-  if (P->gather == 2)                                                                                            \
-    launch_timed(leaf_credit_kernel<KT, false>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members,   \
-                 hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,              \
-                 ws.at<KT>(table_off), hot_published, xcd);                                                     \
-  else                                                                                                           \
-    launch_timed(leaf_credit_kernel<KT, true>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members,    \
-                 hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,              \
-                 ws.at<KT>(table_off), hot_published, xcd);                                                     \
+  if (nbinom <= kBinomLds) {                                                                                     \
+    if (P->gather == 2) KDSS_LEAF_V(KT, false, true);                                                            \
+    else KDSS_LEAF_V(KT, true, true);                                                                            \
+  } else {                                                                                                       \
+    if (P->gather == 2) KDSS_LEAF_V(KT, false, false);                                                           \
+    else KDSS_LEAF_V(KT, true, false);                                                                           \
+  }                                                                                                              \
   launch_timed(nbinom <= kHeavyBinomLds ? heavy_kernel<KT, true> : heavy_kernel<KT, false>, P->heavy_blocks, 256, 0, \
                st, ev_heavy, members, binom, P->k1, src, out, nhot, scratch, (const uint4*)queue,                  \
                (const uint32_t*)qcount, (const KT*)ws.at<KT>(table_off), nbinom)
@@ -1818,6 +1848,7 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
     default: KDSS_LEAF(KRank); break;
   }
 #undef KDSS_LEAF
+#undef KDSS_LEAF_V
   HIP_TRY(hipGetLastError(), "leaf credit launch");
   // hot-node totals over the slot entries (cleared again); also empties the queue
   const uint32_t grid = std::max(1u, (nhot + 3) / 4);   // a wavefront per hot node; block 0 empties the queue
