@@ -7,11 +7,14 @@
   plan, the bench's tuned launch): every problem equals its solo run, and the
   oracle on every problem with at most 2e5 k-cliques (about 750).
 * The warm-start evaluation graph (n = 2,000,000, m = 40,000,000, k = 6) and
-  R-MAT scale 16 (k = 6): too many cliques for the oracle, so properties that
-  hold at any size are checked: Lemma 6 (the loads grow by exactly T c_k),
-  the order is the sort of the loads (descending, ties by ascending id), and
-  density <= upper bound.  R-MAT scale 12 is compared with the oracle bit for
-  bit at both load widths.
+  R-MAT scale 16 (k = 6): too many cliques for the oracle's listing, so
+  properties that hold at any size are checked: Lemma 6 (the loads grow by
+  exactly T c_k), the order is the sort of the loads (descending, ties by
+  ascending id), and density <= upper bound; and one credit pass at seeded,
+  tied loads is compared on sampled nodes with a per-node count (the
+  (k - 1)-cliques among the neighbours above the node, by the oracle's
+  counter).  R-MAT scale 12 is compared with the oracle bit for bit at both
+  load widths.
 """
 from __future__ import annotations
 
@@ -35,6 +38,16 @@ def K():
 
 def say(msg):
     print(msg, flush=True)
+
+
+_graphs = {}
+
+
+def warm_start_graph():
+    """The 2M / 40M evaluation graph, generated once for the module's tests."""
+    if "2m" not in _graphs:
+        _graphs["2m"] = synth.chung_lu(2_000_000, 40_000_000, 2.5, seed=90000)
+    return _graphs["2m"]
 
 
 def loads(x):
@@ -148,10 +161,69 @@ def test_batch_512_every_problem(K, oracle_mod):
         t.close()
 
 
+def _local_credit(oracle_mod, g, k, r, u):
+    """The k-cliques whose minimum (load, id) member is u, counted one node at a
+    time: the (k - 1)-cliques among u's neighbours w with (r[w], w) > (r[u], u),
+    by the oracle's own counter on that induced subgraph."""
+    nb = g.col[g.row_ptr[u]:g.row_ptr[u + 1]].astype(np.int64)
+    sel = nb[(r[nb] > r[u]) | ((r[nb] == r[u]) & (nb > u))]
+    if k == 2:
+        return len(sel)
+    mark = np.full(g.n, -1, dtype=np.int64)
+    mark[sel] = np.arange(len(sel))
+    edges = []
+    for i, w in enumerate(sel):
+        j = mark[g.col[g.row_ptr[w]:g.row_ptr[w + 1]]]
+        j = j[j > i]
+        edges.extend((i, int(x)) for x in j)
+    sub = synth.from_edge_list(len(sel), edges)
+    return oracle_mod.count(sub.n, sub.row_ptr, sub.col, k - 1) if sub.n else 0
+
+
+def _sampled_credits(K, oracle_mod, g, k, seed, samples=48, max_degree=400):
+    """One credit pass on the GPU at seeded loads with many ties, compared on
+    sampled nodes (degree at most max_degree, so each count stays small) with
+    the per-node count, and the total with c_k (every clique credits exactly
+    one member)."""
+    tree = K.Tree(g, k)
+    plan = K.Plan(tree, 1)
+    ws = plan.alloc_workspace()
+    plan.upload(ws)
+    rs = synth.Stream(seed, 83)
+    r = (rs.u64(g.n) % np.uint64(4)).astype(np.uint64)
+    rt = torch.from_numpy(r.view(np.int64).copy()).cuda()
+    out = torch.empty(g.n, dtype=torch.int64, device="cuda")
+    plan.leaf_credit(ws, rt, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint64)
+    assert int(got.astype(object).sum()) == tree.stats().c_k.value
+    deg = np.diff(g.row_ptr.astype(np.int64))
+    cand = np.nonzero((deg > 0) & (deg <= max_degree))[0]
+    picks = cand[(rs.u64(samples) % np.uint64(len(cand))).astype(np.int64)]
+    big = cand[np.argsort(deg[cand])[-4:]]   # and the four largest neighbourhoods allowed
+    for u in np.concatenate([picks, big]):
+        assert int(got[u]) == _local_credit(oracle_mod, g, k, r, int(u)), int(u)
+    plan.close()
+    tree.close()
+
+
+def test_warm_start_graph_sampled_credits(K, oracle_mod):
+    """The 2M / 40M graph at k = 6 (2.1e10 cliques, too many for the oracle's
+    listing): one credit pass at tied loads, sampled node by node."""
+    say("chung-lu 2M m=40M k=6: sampled credits")
+    g = warm_start_graph()
+    _sampled_credits(K, oracle_mod, g, 6, seed=5)
+
+
+def test_rmat_16_sampled_credits(K, oracle_mod):
+    say("rmat 16 k=6: sampled credits")
+    _sampled_credits(K, oracle_mod, synth.rmat(16, 8, seed=0), 6, seed=6, max_degree=200)
+
+
 def test_warm_start_graph_properties(K):
     from paper_2403_05775_amd import gnn
     say("chung-lu 2M m=40M k=6: generating")
-    g = synth.chung_lu(2_000_000, 40_000_000, 2.5, seed=90000)
+    g = warm_start_graph()
     tree = K.Tree(g, 6)
     dev = torch.device("cuda:0")
     dg = gnn.DeviceGraph(g, tree, dev)
