@@ -13,8 +13,8 @@
   ascending id), and density <= upper bound; and one credit pass at seeded,
   tied loads is compared on sampled nodes with a per-node count (the
   (k - 1)-cliques among the neighbours above the node, by the oracle's
-  counter).  R-MAT scale 12 is compared with the oracle bit for bit at both
-  load widths.
+  counter); the same sampled pass on R-MAT scale 18.  R-MAT scale 12 is
+  compared with the oracle bit for bit at both load widths.
 """
 from __future__ import annotations
 
@@ -218,6 +218,13 @@ def test_warm_start_graph_sampled_credits(K, oracle_mod):
 def test_rmat_16_sampled_credits(K, oracle_mod):
     say("rmat 16 k=6: sampled credits")
     _sampled_credits(K, oracle_mod, synth.rmat(16, 8, seed=0), 6, seed=6, max_degree=200)
+
+
+def test_rmat_18_sampled_credits(K, oracle_mod):
+    """R-MAT scale 18 at k = 6, the largest R-MAT graph one GPU holds (8.3e8
+    leaves, a 41 GB leaf stream): one credit pass, sampled node by node."""
+    say("rmat 18 k=6: sampled credits (tree build about a minute)")
+    _sampled_credits(K, oracle_mod, synth.rmat(18, 8, seed=0), 6, seed=7, samples=32, max_degree=150)
 
 
 def test_warm_start_graph_properties(K):
