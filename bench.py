@@ -171,7 +171,8 @@ def batch_bench(w, args):
     log(f"{len(trees)} trees built in {build_s:.1f} s: leaves={L} members={M}")
     T = w["T"]
     t2 = time.time()
-    b = kdss.Batch(trees, T, use_graph=args.graph, schedule=args.schedule, gather=launch_gather(args))
+    b = kdss.Batch(trees, T, use_graph=args.graph, schedule=args.schedule, gather=launch_gather(args),
+                   heavy=args.heavy)
     plan_s = time.time() - t2
     n_total = b.n
     for t in trees:
@@ -203,7 +204,7 @@ def batch_bench(w, args):
                                f"exponent 2.2-2.8, seeds 1000+g) x k in {list(w['ks'])}, T={T}",
                    "problems": len(jobs), "n_total": n_total, "leaves": L, "members": M,
                    "key_mode": st.key_mode, "gather": "masked" if st.gather == 1 else "full",
-                   "hot_share": round(st.hot_share, 4),
+                   "hot_share": round(st.hot_share, 4), "heavy_leaves": heavy_name(st.heavy),
                    "parallelism": "single GPU, one launch per kernel per iteration for all problems",
                    "hip_graph_iterations": args.graph},
         "hbm_gbps_algorithmic": step_bytes / (ms / 1000.0) / 1e9,
@@ -255,16 +256,23 @@ def launch_gather(args):
     return int(args.launch.split(",")[2]) if args.launch else 0
 
 
+def heavy_name(mode):
+    """Where leaves with more than four low members are credited."""
+    return "queued for the heavy kernel" if mode == 1 else "in place, by the tile's wavefront"
+
+
 def launch_fields(tune, cached):
     if tune is None:
         return "defaults"
     out = {"leaf_blocks": tune.best_leaf_blocks, "heavy_blocks": tune.best_heavy_blocks,
            "gather": "masked" if tune.best_gather == 1 else "full",
-           "schedule": "strided" if tune.best_schedule == 1 else "XCD ranges", "from_tuning_cache": cached,
+           "schedule": "strided" if tune.best_schedule == 1 else "XCD ranges",
+           "heavy_leaves": "queue" if tune.best_heavy == 1 else "in place", "from_tuning_cache": cached,
            "tuned_us_per_iter": tune.best_ms * 1000}
     if not cached:
         out["gather_us"] = {"masked": tune.gather_ms[0] * 1000, "full": tune.gather_ms[1] * 1000}
         out["schedule_us"] = {"strided": tune.schedule_ms[0] * 1000, "XCD ranges": tune.schedule_ms[1] * 1000}
+        out["heavy_us"] = {"queue": tune.heavy_ms[0] * 1000, "in place": tune.heavy_ms[1] * 1000}
     return out
 
 
@@ -836,7 +844,8 @@ def single_bench(w, args):
         f"c_k={ts.c_k.value} build={ts.build_seconds:.2f} s")
     T = w["T"]
     update = w.get("update", 0)
-    plan = kdss.Plan(tree, T, use_graph=args.graph, update=update, schedule=args.schedule, gather=launch_gather(args))
+    plan = kdss.Plan(tree, T, use_graph=args.graph, update=update, schedule=args.schedule, gather=launch_gather(args),
+                     heavy=args.heavy)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ws = plan.alloc_workspace(dev)
@@ -877,6 +886,7 @@ def single_bench(w, args):
                    "k": w["k"], "T": T, "leaves": L, "members": M, "c_k": ts.c_k.value,
                    "parallelism": "single GPU", "hip_graph_iterations": args.graph,
                    "gather": "masked" if ps.gather == 1 else "full", "hot_share": round(ps.hot_share, 4),
+                   "heavy_leaves": heavy_name(ps.heavy),
                    "update": "PBUpdate (synchronous)" if update else "Frank-Wolfe"},
         "hbm_gbps_algorithmic": step_bytes / (ms_per_step / 1000.0) / 1e9,
         "sct_build_s": ts.build_seconds,
@@ -949,6 +959,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="default grid sizes and gather mode")
     ap.add_argument("--launch", default="", help="LEAF,HEAVY,GATHER: a given launch instead of the tuned one")
     ap.add_argument("--schedule", type=int, default=0, help="tile schedule: 0 tuned, 1 strided, 2 XCD ranges")
+    ap.add_argument("--heavy", type=int, default=0,
+                    help="heavy leaves: 0 tuned, 1 queued for the heavy kernel, 2 in place by the tile's wavefront")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2403_05775_amd", "tune_cache.txt"),
                     help="tuning cache file ('' to tune without one)")
     ap.add_argument("--scales", default="12-20", help="tree-growth mode: R-MAT scales lo-hi")

@@ -124,6 +124,19 @@ typedef struct {
                                     problems list their tiles problem by
                                     problem.  Grids under 8 workgroups run
                                     strided.                                  */
+    int heavy;                /* leaves with more than four pivot members
+                                 below their hold minimum ("heavy"):
+                                 0: choose (queue; autotune may switch);
+                                 1: queue: the leaf-credit kernel queues them
+                                    and a second kernel spreads them over its
+                                    grid, one leaf per wavefront;
+                                 2: in place: the wavefront that finds them
+                                    takes them up at once, four at a time,
+                                    while its tile's rows are still cached,
+                                    and no second kernel runs (faster when
+                                    heavy leaves are spread over many tiles
+                                    and the loads fit in the caches; slower
+                                    when they crowd into a few tiles)        */
 } kdss_opts;
 
 typedef struct {              /* accumulated by kdss_run when time_kernels = 1  */
@@ -152,6 +165,7 @@ typedef struct {
     int schedule;             /* tile schedule of later runs: 1 strided, 2 XCD ranges */
     uint32_t hot_nodes;       /* nodes whose keys and credits live in LDS       */
     double hot_share;         /* their share of all member occurrences          */
+    int heavy;                /* heavy leaves of later runs: 1 queue, 2 in place */
 } kdss_plan_stats;
 
 typedef struct {
@@ -432,6 +446,9 @@ typedef struct {
     int best_schedule;            /* tile schedule kept (1 strided, 2 XCD ranges) */
     double schedule_ms[2];        /* per iteration with each schedule at the
                                      best grid sizes and gather (0: not timed) */
+    int best_heavy;               /* heavy leaves kept (1 queue, 2 in place)   */
+    double heavy_ms[2];           /* per iteration with each heavy-leaf mode at
+                                     the best launch otherwise (0: not timed)  */
 } kdss_tune_result;
 
 /* Sets the grid sizes (leaf-credit 1..2048, heavy-leaf 1..2048 workgroups) used by later runs. */
@@ -439,22 +456,22 @@ int kdss_plan_set_launch(kdss_plan *p, uint32_t leaf_blocks, uint32_t heavy_bloc
 
 /* Times `iters` iterations after `warm` untimed ones (from zero loads) for each
  * candidate pair of grid sizes on the plan's own data, keeps the fastest and
- * reports all (out, host).  When the plan's options left the gather mode (or
- * the tile schedule) to the library, the other mode (schedule) is then timed at
- * the best sizes and kept if faster.  d_r (device, the plan's load width) is scratch.
+ * reports all (out, host).  Then each choice the plan's options left to the
+ * library (the gather mode, then the heavy-leaf mode, then the tile schedule)
+ * has its other value timed at the best launch so far, kept if faster.  d_r (device, the plan's load width) is scratch.
  * warm + iters must not exceed T_max.  Synchronises the stream. */
 int kdss_plan_autotune(kdss_plan *p, void *d_ws, size_t ws_bytes, uint64_t *d_r, uint32_t warm, uint32_t iters,
                        kdss_tune_result *out, void *stream);
 
 /* The key under which kdss_plan_autotune_cached files a plan's tuning (host
  * string, NUL-terminated, into buf[cap]): the current device's architecture,
- * the kernel variant (load width, key mode, update, gather option), the
- * problems' clique sizes, and half-octave buckets of the problem count, node
- * count and leaves per size class.  KDSS_ERANGE if cap is too small. */
+ * the kernel variant (load width, key mode, update, gather, schedule and
+ * heavy-leaf options), the problems' clique sizes, and half-octave buckets of
+ * the problem count, node count and leaves per size class.  KDSS_ERANGE if cap is too small. */
 int kdss_plan_tune_key(const kdss_plan *p, char *buf, size_t cap);
 
 /* kdss_plan_autotune through a tuning cache: a text file (cache_path, host)
- * of lines "key leaf_blocks heavy_blocks gather schedule ms".  When the file holds the
+ * of lines "key leaf_blocks heavy_blocks gather schedule heavy ms".  When the file holds the
  * plan's key (the last such line wins) its launch is applied without timing
  * anything (*from_cache = 1; out carries only the best_* fields); otherwise the
  * plan is tuned as by kdss_plan_autotune and a line is appended (*from_cache =

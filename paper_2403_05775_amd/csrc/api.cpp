@@ -319,6 +319,11 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
       return fail(KDSS_EINVAL, "schedule must be 0, 1 or 2");
     }
     P->sched = P->opts.schedule == 2 ? 2 : 1;
+    if (P->opts.heavy < 0 || P->opts.heavy > 2) {
+      delete P;
+      return fail(KDSS_EINVAL, "heavy must be 0, 1 or 2");
+    }
+    P->heavy = P->opts.heavy == 2 ? 2 : 1;
     if (P->opts.update == 1 && (P->opts.width == 128 || !fits64)) {
       delete P;
       return fail(KDSS_EINVAL, "PBUpdate runs with 64-bit loads only");
@@ -641,6 +646,7 @@ int kdss_plan_info(const kdss_plan* P, kdss_plan_stats* out) {
   out->gather = P->gather;
   out->update = P->opts.update;
   out->schedule = P->sched;
+  out->heavy = P->heavy;
   out->hot_nodes = (uint32_t)P->hot.size();
   out->hot_share = P->hot_share;
   for (int c = 0; c < kNumClasses; ++c) {

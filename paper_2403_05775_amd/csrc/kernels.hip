@@ -297,11 +297,74 @@ __device__ __forceinline__ Tile load_tile(const Tile* __restrict__ tiles, uint32
   t.pad[0] = reinterpret_cast<const uint32_t*>(tiles + i)[5];
   return t;
 }
+// The heavy leaves of a lane tile (more than four pivot members below the
+// hold minimum; heavy has bit c set for column c), taken by the whole
+// wavefront up to four at a time: one member per lane (member x of column c
+// is tile word c + 64 x), the hold minimum by a reduction over lanes 0..31
+// (hold members come first, h <= 31), and each low member's rank among the
+// low members by broadcasting their keys one at a time.  Only the low members
+// are credited here; the lane tile credits the hold minimum.
+template <class KT>
+__device__ __forceinline__ void tile_heavy(uint64_t heavy, uint64_t mbase, uint32_t hd,
+                                           const uint32_t* __restrict__ members, const uint64_t* binom, uint32_t k1,
+                                           const KeySrc& src, const KT* hkey, Sink& sink) {
+  constexpr uint32_t B = sizeof(KT) > 16 ? 2 : 4;   // 128-bit loads: two at a time (registers)
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t xoff = (uint64_t)64 * lane;
+  while (heavy) {
+    // a slot past the last heavy leaf reads column 0's first word and has
+    // no members
+    uint32_t hq[B], sq[B], jq[B], ra[B];
+#pragma unroll
+    for (uint32_t q = 0; q < B; ++q) {
+      const uint32_t c = heavy ? (uint32_t)__builtin_ctzll(heavy) : 0u;
+      const uint32_t hdq = heavy ? readlane32(hd, (int)c) : 0u;
+      heavy &= heavy - 1ull;
+      hq[q] = hdq & 31u;
+      jq[q] = (hdq >> 5) & 31u;
+      sq[q] = hq[q] + (hdq >> 10);
+      ra[q] = members[mbase + c + (lane < sq[q] ? xoff : 0ull)];
+    }
+    KT ka[B], kh[B];
+#pragma unroll
+    for (uint32_t q = 0; q < B; ++q) ka[q] = member_key<KT>(src, hkey, ra[q]);
+#pragma unroll
+    for (uint32_t q = 0; q < B; ++q) {
+      ka[q] = KT::pick(lane < sq[q], ka[q], KT::mx());
+      kh[q] = KT::pick(lane < hq[q], ka[q], KT::mx());
+    }
+#pragma unroll
+    for (int d = 16; d >= 1; d >>= 1) {
+#pragma unroll
+      for (uint32_t q = 0; q < B; ++q) {
+        const KT o = kh[q].sx(d);
+        kh[q] = KT::pick(o.lt(kh[q]), o, kh[q]);
+      }
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < B; ++q) {
+      const KT m = kh[q].rl(0);
+      const bool low = lane < sq[q] && lane >= hq[q] && ka[q].lt(m);
+      uint32_t below = 0;
+      for (uint64_t bm = __ballot(low); bm; bm &= bm - 1ull) {
+        const KT kt = ka[q].rl(__builtin_ctzll(bm));
+        below += kt.lt(ka[q]) ? 1u : 0u;
+      }
+      const uint32_t p = sq[q] - hq[q], j = jq[q];
+      if (low && j >= 1) {
+        const uint64_t c = binom[(size_t)(p - 1 - below) * k1 + (j - 1)];
+        if (c) sink.add(ra[q], c);
+      }
+    }
+  }
+}
+
 template <class KT, bool kMasked>
 __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, const uint32_t* __restrict__ members,
                                           const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k1,
                                           const KeySrc& src, const KT* hkey, Sink& sink, uint4* __restrict__ queue,
-                                          uint32_t* __restrict__ qcount, WaveQueue& hq, uint32_t* lcol) {
+                                          uint32_t* __restrict__ qcount, WaveQueue& hq, uint32_t* lcol,
+                                          uint32_t inline_max) {
   constexpr uint32_t U = kLaneBatch;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nl = (t.info >> 3) & 0x1FFFu, smax = t.info >> 16;
@@ -395,24 +458,31 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
     if (nlow > 2) sink.add(r2, c2);
     if (nlow > 3) sink.add(r3, c3);
   }
-  // Leaves with more than four low members go to the heavy-leaf queue (through
-  // the wavefront's LDS buffer); the heavy kernel spreads them over the grid.
+  // Leaves with more than four low members: a tile with at most inline_max
+  // of them has the whole wavefront take them up right away (its rows are
+  // still in the caches); a tile with more sends them to the heavy-leaf queue
+  // (through the wavefront's LDS buffer), which the heavy kernel spreads over
+  // the grid.
   const uint64_t heavy = __ballot(nlow > 4);
   if (heavy) {
     const uint32_t cnt = (uint32_t)__popcll(heavy);
-    const uint32_t below = (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull));
-    const uint64_t mw = t.mbase + lane;
-    const uint4 entry = make_uint4((uint32_t)mw, (uint32_t)(mw >> 32), hd, t.nbase);
-    if (hq.n + cnt > kQueueBuf) hq.flush(queue, qcount);
-    if (cnt > kQueueBuf) {
-      // more than the slice holds: this tile's entries go to the queue at once
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(qcount, cnt);
-      base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-      if (nlow > 4) queue[base + below] = entry;
+    if (cnt <= inline_max) {
+      tile_heavy<KT>(heavy, t.mbase, hd, members, binom, k1, src, hkey, sink);
     } else {
-      if (nlow > 4) hq.buf[hq.n + below] = entry;
-      hq.n += cnt;
+      const uint32_t below = (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull));
+      const uint64_t mw = t.mbase + lane;
+      const uint4 entry = make_uint4((uint32_t)mw, (uint32_t)(mw >> 32), hd, t.nbase);
+      if (hq.n + cnt > kQueueBuf) hq.flush(queue, qcount);
+      if (cnt > kQueueBuf) {
+        // more than the slice holds: this tile's entries go to the queue at once
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(qcount, cnt);
+        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+        if (nlow > 4) queue[base + below] = entry;
+      } else {
+        if (nlow > 4) hq.buf[hq.n + below] = entry;
+        hq.n += cnt;
+      }
     }
   }
   const uint64_t cm = h ? binom[(size_t)(p - nlow) * k1 + j] : 0ull;
@@ -487,7 +557,8 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
                                                           const uint32_t* __restrict__ hot_base, uint32_t nhot,
                                                           uint64_t* __restrict__ scratch, uint4* __restrict__ queue,
                                                           uint32_t* __restrict__ qcount, KT* __restrict__ hotkey,
-                                                          bool hot_published, const uint32_t* __restrict__ xcd) {
+                                                          bool hot_published, const uint32_t* __restrict__ xcd,
+                                                          uint32_t inline_max) {
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kLdsBinom ? kBinomLds : 1];
@@ -537,7 +608,7 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
     KeySrc ts = src;
     ts.base = t.nbase;
     if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k1, ts, hkey, sink);
-    else tile_lane<KT, kMasked>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq, lcol);
+    else tile_lane<KT, kMasked>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq, lcol, inline_max);
     // the descriptor's last loaded word is kept alive to here, so its register
     // is not reused (and the load not waited for) while this tile runs
     asm volatile("" ::"s"(tn.pad[0]));
@@ -1825,10 +1896,13 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   const uint32_t* xcd = P->sched == 2 ? ws.at<uint32_t>(P->off_xcd) : nullptr;
   hipEvent_t* ev_leaf = ev ? ev + kEvLeaf : nullptr;
   hipEvent_t* ev_heavy = ev ? ev + kEvHeavy : nullptr;
+  // in place: every tile takes up its own heavy leaves; queue: none does
+  const bool in_place = P->heavy == 2;
+  const uint32_t inline_max = in_place ? 64u : 0u;
 #define KDSS_LEAF_V(KT, MASKED, LDSB)                                                                           \
   launch_timed(leaf_credit_kernel<KT, MASKED, LDSB>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members, \
                hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,                \
-               ws.at<KT>(table_off), hot_published, xcd)
+               ws.at<KT>(table_off), hot_published, xcd, inline_max)
 #define KDSS_LEAF(KT)                                                                                           \
   if (nbinom <= kBinomLds) {                                                                                     \
     if (P->gather == 2) KDSS_LEAF_V(KT, false, true);                                                            \
@@ -1837,10 +1911,11 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
     if (P->gather == 2) KDSS_LEAF_V(KT, false, false);                                                           \
     else KDSS_LEAF_V(KT, true, false);                                                                           \
   }                                                                                                              \
-  launch_timed(nbinom <= kHeavyBinomLds ? heavy_kernel<KT, true> : heavy_kernel<KT, false>, P->heavy_blocks, 256, 0, \
-               st, ev_heavy, members, binom, P->k1, src, out, nhot, scratch, (const uint4*)queue,                  \
-               (const uint32_t*)qcount, (const KT*)ws.at<KT>(table_off), nbinom)
-  if (used) *used |= 1u | 2u;
+  if (!in_place)                                                                                                 \
+    launch_timed(nbinom <= kHeavyBinomLds ? heavy_kernel<KT, true> : heavy_kernel<KT, false>, P->heavy_blocks, 256, \
+                 0, st, ev_heavy, members, binom, P->k1, src, out, nhot, scratch, (const uint4*)queue,             \
+                 (const uint32_t*)qcount, (const KT*)ws.at<KT>(table_off), nbinom)
+  if (used) *used |= in_place ? 1u : 1u | 2u;
   switch (mode) {
     case 0: KDSS_LEAF(KPacked); break;
     case 1: KDSS_LEAF(KFull); break;
@@ -2660,6 +2735,7 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
   }
   out->best_gather = P->gather;
   out->best_schedule = P->sched;
+  out->best_heavy = P->heavy;
   if (!rc) {
     out->gather_ms[P->gather - 1] = out->best_ms;
     out->schedule_ms[P->sched - 1] = out->best_ms;
@@ -2679,6 +2755,24 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
         }
       }
       P->gather = out->best_gather;
+    }
+    if (!rc) out->heavy_ms[P->heavy - 1] = out->best_ms;
+    if (!rc && saved.heavy == 0 && P->tiles.size() > 0) {   // the heavy-leaf mode was left to the library
+      const int current = P->heavy;
+      P->leaf_blocks = out->best_leaf_blocks;
+      P->heavy_blocks = out->best_heavy_blocks;
+      P->heavy = 3 - current;
+      float ms = 0.f;
+      rc = time_config(&ms);
+      if (!rc) {
+        ++out->tried;
+        out->heavy_ms[P->heavy - 1] = ms;
+        if (ms < out->best_ms) {
+          out->best_ms = ms;
+          out->best_heavy = P->heavy;
+        }
+      }
+      P->heavy = out->best_heavy;
     }
     if (!rc) out->schedule_ms[P->sched - 1] = out->best_ms;
     if (!rc && saved.schedule == 0 && P->tiles.size() > 0) {   // the schedule was left to the library
@@ -2718,15 +2812,16 @@ int kdss_plan_tune_key(const kdss_plan* P, char* buf, size_t cap) {
   std::string arch(prop.gcnArchName);
   arch = arch.substr(0, arch.find(':'));
   // what the best launch depends on: the device, the kernel variant (load
-  // width, key mode, update, gather option), the clique sizes, and the shape
-  // of the work: leaves per size class and nodes in half-octave buckets
+  // width, key mode, update; gather, schedule and heavy-leaf options), the
+  // clique sizes, and the shape of the work: leaves per size class and nodes
+  // in half-octave buckets
   auto bucket = [](double x) { return x < 1 ? 0 : (int)std::lround(2.0 * std::log2(x)); };
   std::vector<uint32_t> ks(P->prob_k.begin(), P->prob_k.end());
   std::sort(ks.begin(), ks.end());
   ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
   std::string key = arch + "|w" + std::to_string(P->width) + "|km" + std::to_string(P->key_mode) + "|u" +
                     std::to_string(P->opts.update) + "|g" + std::to_string(P->opts.gather) + "|s" +
-                    std::to_string(P->opts.schedule) + "|k";
+                    std::to_string(P->opts.schedule) + "|h" + std::to_string(P->opts.heavy) + "|k";
   for (size_t i = 0; i < ks.size(); ++i) key += (i ? "," : "") + std::to_string(ks[i]);
   key += "|q" + std::to_string(bucket((double)(P->node_off.size() - 1))) + "|n" + std::to_string(bucket(P->n)) +
          "|L";
@@ -2749,16 +2844,17 @@ int kdss_plan_autotune_cached(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_
     while (std::fgets(line, sizeof(line), f)) {
       char k2[512];
       unsigned lb = 0, hb = 0;
-      int g = 0, sc = 0;
+      int g = 0, sc = 0, hm = 0;
       double ms = 0.0;
-      if (std::sscanf(line, "%511s %u %u %d %d %lf", k2, &lb, &hb, &g, &sc, &ms) == 6 &&
+      if (std::sscanf(line, "%511s %u %u %d %d %d %lf", k2, &lb, &hb, &g, &sc, &hm, &ms) == 7 &&
           std::strcmp(k2, key) == 0 && lb >= 1 && lb <= kLeafBlocksMax && hb >= 1 && hb <= kHeavyBlocks &&
-          (g == 1 || g == 2) && (sc == 1 || sc == 2)) {
+          (g == 1 || g == 2) && (sc == 1 || sc == 2) && (hm == 1 || hm == 2)) {
         std::memset(out, 0, sizeof(*out));
         out->best_leaf_blocks = lb;
         out->best_heavy_blocks = hb;
         out->best_gather = g;
         out->best_schedule = sc;
+        out->best_heavy = hm;
         out->best_ms = ms;
         *from_cache = 1;
       }
@@ -2770,14 +2866,15 @@ int kdss_plan_autotune_cached(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_
     P->heavy_blocks = out->best_heavy_blocks;
     P->gather = out->best_gather;
     P->sched = out->best_schedule;
+    P->heavy = out->best_heavy;
     drop_graph(P);
     return KDSS_OK;
   }
   rc = kdss_plan_autotune(P, d_ws, ws_bytes, d_r, warm, iters, out, stream);
   if (rc) return rc;
   if (FILE* f = std::fopen(cache_path, "a")) {
-    std::fprintf(f, "%s %u %u %d %d %.6f\n", key, out->best_leaf_blocks, out->best_heavy_blocks, out->best_gather,
-                 out->best_schedule, out->best_ms);
+    std::fprintf(f, "%s %u %u %d %d %d %.6f\n", key, out->best_leaf_blocks, out->best_heavy_blocks,
+                 out->best_gather, out->best_schedule, out->best_heavy, out->best_ms);
     std::fclose(f);
   }
   return KDSS_OK;

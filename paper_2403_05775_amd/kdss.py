@@ -46,7 +46,8 @@ class TreeStats(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("width", C.c_int), ("use_graph", C.c_int), ("extract_every", C.c_uint32),
-                ("time_kernels", C.c_int), ("gather", C.c_int), ("update", C.c_int), ("schedule", C.c_int)]
+                ("time_kernels", C.c_int), ("gather", C.c_int), ("update", C.c_int), ("schedule", C.c_int),
+                ("heavy", C.c_int)]
 
 
 class Timing(C.Structure):
@@ -59,7 +60,8 @@ class TuneResult(C.Structure):
     _fields_ = [("tried", C.c_uint32), ("best_leaf_blocks", C.c_uint32), ("best_heavy_blocks", C.c_uint32),
                 ("best_ms", C.c_double), ("leaf_blocks", C.c_uint32 * 32), ("heavy_blocks", C.c_uint32 * 32),
                 ("ms", C.c_double * 32), ("best_gather", C.c_int), ("gather_ms", C.c_double * 2),
-                ("best_schedule", C.c_int), ("schedule_ms", C.c_double * 2)]
+                ("best_schedule", C.c_int), ("schedule_ms", C.c_double * 2), ("best_heavy", C.c_int),
+                ("heavy_ms", C.c_double * 2)]
 
 
 class PlanStats(C.Structure):
@@ -67,7 +69,7 @@ class PlanStats(C.Structure):
                 ("key_mode", C.c_int), ("id_bits", C.c_uint32), ("T_max", C.c_uint32),
                 ("tiles", C.c_uint64 * 5), ("leaves", C.c_uint64 * 5), ("members", C.c_uint64 * 5),
                 ("gather", C.c_int), ("update", C.c_int), ("schedule", C.c_int), ("hot_nodes", C.c_uint32),
-                ("hot_share", C.c_double)]
+                ("hot_share", C.c_double), ("heavy", C.c_int)]
 
 
 class SampleInfo(C.Structure):
@@ -315,8 +317,8 @@ class Plan:
 
     def __init__(self, tree: Tree, T_max: int, r0_max: int = 0, width: int = 0, use_graph: bool = False,
                  extract_every: int = 0, time_kernels: bool = False, gather: int = 0, update: int = 0,
-                 schedule: int = 0):
-        o = Opts(width, int(use_graph), extract_every, 1 if time_kernels else 0, gather, update, schedule)
+                 schedule: int = 0, heavy: int = 0):
+        o = Opts(width, int(use_graph), extract_every, 1 if time_kernels else 0, gather, update, schedule, heavy)
         h = C.c_void_p()
         _check(lib().kdss_plan_create(tree._h, T_max, r0_max, C.byref(o), C.byref(h)), "kdss_plan_create")
         self._h = h
@@ -442,8 +444,8 @@ class Batch(Plan):
     covers every problem; each problem's result equals its solo run."""
 
     def __init__(self, trees, T_max: int, r0_max: int = 0, use_graph: bool = False, time_kernels: bool = False,
-                 gather: int = 0, update: int = 0, schedule: int = 0):
-        o = Opts(0, int(use_graph), 0, 1 if time_kernels else 0, gather, update, schedule)
+                 gather: int = 0, update: int = 0, schedule: int = 0, heavy: int = 0):
+        o = Opts(0, int(use_graph), 0, 1 if time_kernels else 0, gather, update, schedule, heavy)
         arr = (C.c_void_p * len(trees))(*[t._h for t in trees])
         h = C.c_void_p()
         _check(lib().kdss_batch_create(arr, len(trees), T_max, r0_max, C.byref(o), C.byref(h)), "kdss_batch_create")
@@ -508,13 +510,14 @@ class Solution:
 
 
 def solve(graph, k: int, T: int, r0=None, width: int = 0, use_graph: bool = False, extract_every: int = 0,
-          threads: int = 0, device="cuda", gather: int = 0, update: int = 0, schedule: int = 0) -> Solution:
+          threads: int = 0, device="cuda", gather: int = 0, update: int = 0, schedule: int = 0,
+          heavy: int = 0) -> Solution:
     """Build the tree, lay it out, run T iterations and the extraction on the GPU."""
     import torch
     tree = Tree(graph, k, threads)
     r0_max = 0 if r0 is None else int(np.max(np.asarray(r0, dtype=np.uint64))) if graph.n else 0
     plan = Plan(tree, T, r0_max, width=width, use_graph=use_graph, extract_every=extract_every, gather=gather,
-                update=update, schedule=schedule)
+                update=update, schedule=schedule, heavy=heavy)
     ws = plan.alloc_workspace(device)
     plan.upload(ws)
     r = plan.alloc_loads(device)

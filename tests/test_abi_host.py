@@ -234,6 +234,20 @@ def test_update_option():
         assert e.value.status == kdss.EINVAL, kw
 
 
+def test_heavy_leaf_option():
+    """Heavy leaves: queued unless in place is asked for; other values refused."""
+    g = synth.chung_lu(2000, 20000, 2.3, seed=5, planted=30)
+    t = kdss.Tree(g, 4)
+    assert kdss.Plan(t, 10).stats().heavy == 1
+    assert kdss.Plan(t, 10, heavy=1).stats().heavy == 1
+    assert kdss.Plan(t, 10, heavy=2).stats().heavy == 2
+    assert kdss.Batch([t], 10, heavy=2).stats().heavy == 2
+    for h in (3, -1):
+        with pytest.raises(kdss.KdssError) as e:
+            kdss.Plan(t, 10, heavy=h)
+        assert e.value.status == kdss.EINVAL, h
+
+
 def test_sample_build_arguments_and_empty_sample():
     g = synth.chung_lu(300, 2000, 2.3, seed=4, planted=10)
     c, keep = kdss._csr(g)

@@ -147,6 +147,87 @@ def test_gather_modes(K, oracle_mod, gather):
         assert_same(sol, ref(oracle_mod, g, k, T, r0=r0), T, f"gather={gather} k={k}")
 
 
+@pytest.mark.parametrize("gather", [1, 2])
+def test_heavy_leaves_in_place(K, oracle_mod, gather):
+    """Heavy leaves (more than four pivot members below the hold minimum) taken
+    up in place by the tile's wavefront instead of the queue: packed keys,
+    (load, id) keys and 128-bit loads (two leaves at a time), extraction
+    included; the same graphs queue heavy leaves in the other mode, and in
+    place none is queued and no heavy kernel runs."""
+    g = synth.chung_lu(4000, 30000, 2.2, seed=21, planted=28)
+    rs = synth.Stream(21, 73)
+    ties = (rs.u64(g.n) % np.uint64(3)).astype(np.uint64)
+    high = np.uint64(2**62) + (rs.u64(g.n) % np.uint64(3)).astype(np.uint64)
+    for k, T, r0, width, key_mode in ((4, 25, None, 0, 0), (5, 9, ties, 0, 0), (4, 7, high, 0, 1),
+                                      (6, 5, None, 128, 1)):
+        print(f"heavy in place, gather {gather} k={k} T={T} width={width}", flush=True)
+        sol = K.solve(g, k, T, r0=r0, width=width, gather=gather, heavy=2)
+        assert sol.plan_stats.heavy == 2 and sol.plan_stats.key_mode == key_mode
+        assert_same(sol, ref(oracle_mod, g, k, T, r0=r0), T, f"in place gather={gather} k={k}")
+    tree = K.Tree(g, 5)
+    counts = {}
+    for heavy in (1, 2):
+        plan = K.Plan(tree, 9, time_kernels=True, gather=gather, heavy=heavy)
+        ws = plan.alloc_workspace()
+        plan.upload(ws)
+        r = plan.alloc_loads()
+        order = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        print(f"heavy mode {heavy}: timed run", flush=True)
+        plan.run(ws, 9, r, order)
+        torch.cuda.synchronize()
+        tm = plan.timing()
+        counts[heavy] = (tm.heavy_leaves, tm.heavy_ms)
+        assert np.array_equal(r.cpu().numpy().view(np.uint64)[: g.n], ref(oracle_mod, g, 5, 9)["r"])
+        plan.close()
+    tree.close()
+    assert counts[1][0] > 0 and counts[1][1] > 0
+    assert counts[2] == (0, 0.0)
+
+
+def test_heavy_in_place_credits_at_tied_loads(K, oracle_mod):
+    """One credit pass with heavy leaves in place, at loads with many ties, and
+    a batch of problems with different k: each equals the oracle."""
+    from paper_2403_05775_amd import kdss
+    g = synth.chung_lu(2000, 16000, 2.2, seed=13, planted=30)
+    for k in (3, 5, 7):
+        tree = kdss.Tree(g, k)
+        plan = kdss.Plan(tree, 1, heavy=2)
+        ws = plan.alloc_workspace()
+        plan.upload(ws)
+        for trial in range(2):
+            rs = synth.Stream(200 + trial, 81)
+            r = (rs.u64(g.n) % np.uint64(2 + 5 * trial)).astype(np.uint64)
+            rt = torch.from_numpy(r.view(np.int64).copy()).cuda()
+            out = torch.empty(g.n, dtype=torch.int64, device="cuda")
+            print(f"in-place leaf credit k={k} trial={trial}", flush=True)
+            plan.leaf_credit(ws, rt, out)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle_mod.credits(g.n, g.row_ptr, g.col, k, r))
+        plan.close()
+        tree.close()
+    T = 6
+    probs = [(synth.chung_lu(500 + 150 * i, 4000 + 900 * i, 2.2, seed=60 + i, planted=14 + i), 3 + i % 5)
+             for i in range(6)]
+    b = kdss.Batch([kdss.Tree(gq, kq) for gq, kq in probs], T, heavy=2)
+    assert b.stats().heavy == 2
+    wsb = b.alloc_workspace()
+    b.upload(wsb)
+    rb = torch.empty(b.n, dtype=torch.int64, device="cuda")
+    ob = torch.empty(b.n, dtype=torch.int32, device="cuda")
+    print("in-place heavy leaves, batch", flush=True)
+    resb = b.run(wsb, T, rb, ob)
+    torch.cuda.synchronize()
+    rr = rb.cpu().numpy().view(np.uint64)
+    oo = ob.cpu().numpy().view(np.uint32)
+    for q, (gq, kq) in enumerate(probs):
+        want = ref(oracle_mod, gq, kq, T)
+        lo, hi = int(b.node_off[q]), int(b.node_off[q + 1])
+        assert np.array_equal(rr[lo:hi], want["r"]), q
+        assert np.array_equal(oo[lo:hi], want["order"]), q
+        assert (resb[q].size, resb[q].dens_num.value, resb[q].ub_num.value) == \
+            (want["size"], want["dens_num"], want["ub_num"]), q
+
+
 def test_leaf_credit_with_forced_ties(K, oracle_mod):
     """One credit pass at arbitrary loads with many equal values (ties by id)."""
     from paper_2403_05775_amd import kdss
