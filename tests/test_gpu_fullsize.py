@@ -83,6 +83,10 @@ def test_chung_lu_1m_bit_exact(K, oracle_mod):
     assert np.array_equal(sol.order, ref["order"])
     assert (sol.size, sol.dens_num, sol.ub_num, sol.c_k) == (ref["size"], ref["dens_num"], ref["ub_num"],
                                                             ref["c_k"])
+    say("chung-lu 1M k=5 T=200: GPU, heavy leaves in place")
+    sol2 = K.solve(g, 5, 200, heavy=2)
+    assert loads(sol2.r) == loads(ref["r"]) and np.array_equal(sol2.order, ref["order"])
+    assert (sol2.size, sol2.dens_num, sol2.ub_num) == (ref["size"], ref["dens_num"], ref["ub_num"])
     say("chung-lu 1M: certified bound")
     want = oracle_mod.top_bound(ref["r"], None, 200, 5)
     from fractions import Fraction
@@ -180,30 +184,40 @@ def _local_credit(oracle_mod, g, k, r, u):
     return oracle_mod.count(sub.n, sub.row_ptr, sub.col, k - 1) if sub.n else 0
 
 
-def _sampled_credits(K, oracle_mod, g, k, seed, samples=48, max_degree=400):
+def _sampled_credits(K, oracle_mod, g, k, seed, samples=48, max_degree=400, heavy_modes=(1,)):
     """One credit pass on the GPU at seeded loads with many ties, compared on
     sampled nodes (degree at most max_degree, so each count stays small) with
     the per-node count, and the total with c_k (every clique credits exactly
-    one member)."""
+    one member); once per heavy-leaf mode (1 queue, 2 in place), the two
+    passes equal node for node."""
     tree = K.Tree(g, k)
-    plan = K.Plan(tree, 1)
-    ws = plan.alloc_workspace()
-    plan.upload(ws)
     rs = synth.Stream(seed, 83)
     r = (rs.u64(g.n) % np.uint64(4)).astype(np.uint64)
-    rt = torch.from_numpy(r.view(np.int64).copy()).cuda()
-    out = torch.empty(g.n, dtype=torch.int64, device="cuda")
-    plan.leaf_credit(ws, rt, out)
-    torch.cuda.synchronize()
-    got = out.cpu().numpy().view(np.uint64)
-    assert int(got.astype(object).sum()) == tree.stats().c_k.value
     deg = np.diff(g.row_ptr.astype(np.int64))
     cand = np.nonzero((deg > 0) & (deg <= max_degree))[0]
     picks = cand[(rs.u64(samples) % np.uint64(len(cand))).astype(np.int64)]
     big = cand[np.argsort(deg[cand])[-4:]]   # and the four largest neighbourhoods allowed
-    for u in np.concatenate([picks, big]):
-        assert int(got[u]) == _local_credit(oracle_mod, g, k, r, int(u)), int(u)
-    plan.close()
+    want = {int(u): _local_credit(oracle_mod, g, k, r, int(u)) for u in np.concatenate([picks, big])}
+    first = None
+    for heavy in heavy_modes:
+        say(f"  credit pass, heavy-leaf mode {heavy}")
+        plan = K.Plan(tree, 1, heavy=heavy)
+        ws = plan.alloc_workspace()
+        plan.upload(ws)
+        rt = torch.from_numpy(r.view(np.int64).copy()).cuda()
+        out = torch.empty(g.n, dtype=torch.int64, device="cuda")
+        plan.leaf_credit(ws, rt, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint64)
+        del ws, rt, out
+        plan.close()
+        assert int(got.astype(object).sum()) == tree.stats().c_k.value
+        for u, c in want.items():
+            assert int(got[u]) == c, (heavy, u)
+        if first is None:
+            first = got
+        else:
+            assert np.array_equal(got, first)
     tree.close()
 
 
@@ -217,14 +231,15 @@ def test_warm_start_graph_sampled_credits(K, oracle_mod):
 
 def test_rmat_16_sampled_credits(K, oracle_mod):
     say("rmat 16 k=6: sampled credits")
-    _sampled_credits(K, oracle_mod, synth.rmat(16, 8, seed=0), 6, seed=6, max_degree=200)
+    _sampled_credits(K, oracle_mod, synth.rmat(16, 8, seed=0), 6, seed=6, max_degree=200, heavy_modes=(1, 2))
 
 
 def test_rmat_18_sampled_credits(K, oracle_mod):
     """R-MAT scale 18 at k = 6, the largest R-MAT graph one GPU holds (8.3e8
     leaves, a 41 GB leaf stream): one credit pass, sampled node by node."""
     say("rmat 18 k=6: sampled credits (tree build about a minute)")
-    _sampled_credits(K, oracle_mod, synth.rmat(18, 8, seed=0), 6, seed=7, samples=32, max_degree=150)
+    _sampled_credits(K, oracle_mod, synth.rmat(18, 8, seed=0), 6, seed=7, samples=32, max_degree=150,
+                     heavy_modes=(1, 2))
 
 
 def test_warm_start_graph_properties(K):
@@ -261,7 +276,13 @@ def test_rmat_12_bit_exact(K, oracle_mod, width):
 
 
 def test_rmat_16_properties(K):
+    """The run's invariants, and the same run with heavy leaves in place (the
+    tuned launch for this graph) equal to it bit for bit."""
     g = synth.rmat(16, 8, seed=0)
     say("rmat 16 k=6 T=100")
     sol = K.solve(g, 6, 100)
     assert_properties(g, sol, 100)
+    say("rmat 16 k=6 T=100, heavy leaves in place")
+    sol2 = K.solve(g, 6, 100, heavy=2)
+    assert np.array_equal(sol2.r, sol.r) and np.array_equal(sol2.order, sol.order)
+    assert (sol2.size, sol2.dens_num, sol2.ub_num) == (sol.size, sol.dens_num, sol.ub_num)
