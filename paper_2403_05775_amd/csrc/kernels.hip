@@ -308,7 +308,7 @@ template <class KT>
 __device__ __forceinline__ void tile_heavy(uint64_t heavy, uint64_t mbase, uint32_t hd,
                                            const uint32_t* __restrict__ members, const uint64_t* binom, uint32_t k1,
                                            const KeySrc& src, const KT* hkey, Sink& sink) {
-  constexpr uint32_t B = sizeof(KT) > 16 ? 2 : 4;   // 128-bit loads: two at a time (registers)
+  constexpr uint32_t B = sizeof(KT) > 8 ? 2 : 4;   // (load, id) keys: two at a time (registers)
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t xoff = (uint64_t)64 * lane;
   while (heavy) {

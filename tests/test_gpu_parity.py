@@ -228,6 +228,37 @@ def test_heavy_in_place_credits_at_tied_loads(K, oracle_mod):
             (want["size"], want["dens_num"], want["ub_num"]), q
 
 
+@pytest.mark.parametrize("gather", [1, 2])
+def test_binomial_table_in_memory(K, oracle_mod, gather):
+    """A plan whose binomial table does not fit in LDS (s_max = 130 at k = 3:
+    131 x 4 entries), so every pass reads it from memory.  The graph's lane
+    tiles hold leaves with 1-4, 5-8 and more than 8 low members at the tied
+    loads used (about 100 of each of the last two per trial); one credit pass
+    per trial and heavy-leaf mode, and a run, equal the oracle."""
+    from paper_2403_05775_amd import kdss
+    g = synth.erdos_renyi(400, 0.08, seed=17, planted_clique=130)
+    tree = kdss.Tree(g, 3)
+    assert tree.stats().s_max == 130
+    for heavy in (1, 2):
+        plan = kdss.Plan(tree, 1, gather=gather, heavy=heavy)
+        ws = plan.alloc_workspace()
+        plan.upload(ws)
+        for trial in range(2):
+            rs = synth.Stream(300 + trial, 81)
+            r = (rs.u64(g.n) % np.uint64(2 + 5 * trial)).astype(np.uint64)
+            rt = torch.from_numpy(r.view(np.int64).copy()).cuda()
+            out = torch.empty(g.n, dtype=torch.int64, device="cuda")
+            print(f"binomials in memory: gather {gather} heavy {heavy} trial {trial}", flush=True)
+            plan.leaf_credit(ws, rt, out)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle_mod.credits(g.n, g.row_ptr, g.col, 3, r))
+        plan.close()
+    tree.close()
+    print(f"binomials in memory: gather {gather}, run T=12", flush=True)
+    sol = K.solve(g, 3, 12, gather=gather)
+    assert_same(sol, ref(oracle_mod, g, 3, 12), 12, f"binomials in memory, gather={gather}")
+
+
 def test_leaf_credit_with_forced_ties(K, oracle_mod):
     """One credit pass at arbitrary loads with many equal values (ties by id)."""
     from paper_2403_05775_amd import kdss
