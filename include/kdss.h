@@ -142,11 +142,13 @@ typedef struct {
 typedef struct {              /* accumulated by kdss_run when time_kernels = 1  */
     uint64_t leaf_launches;   /* Frank-Wolfe credit passes timed                */
     double leaf_ms;           /* leaf-credit kernel, summed (hipEvent time)     */
-    double heavy_ms;          /* heavy-leaf kernel that follows it              */
+    double heavy_ms;          /* heavy-leaf kernel that follows it (0 with
+                                 heavy leaves in place: none runs)             */
     double reduce_ms;         /* hot-node reduction that completes the pass     */
     uint64_t apply_launches;
     double apply_ms;          /* load update r += credits                       */
-    uint64_t heavy_leaves;    /* leaves queued for the heavy-leaf kernel, summed */
+    uint64_t heavy_leaves;    /* leaves queued for the heavy-leaf kernel, summed
+                                 (0 with heavy leaves in place)                */
 } kdss_timing;
 
 typedef struct {

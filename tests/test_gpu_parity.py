@@ -377,23 +377,24 @@ def test_xcd_range_schedule(K, oracle_mod, leaf_blocks):
         assert (resb[q].size, resb[q].dens_num.value) == (want["size"], want["dens_num"]), q
 
 
-@pytest.mark.parametrize("G", [4, 8])
-def test_multi_iteration_graphs(K, oracle_mod, G):
+@pytest.mark.parametrize("G,heavy", [(4, 1), (8, 1), (8, 2)])
+def test_multi_iteration_graphs(K, oracle_mod, G, heavy):
     """Iterations replayed as graphs of G iterations (21 = 2 or 5 replays plus
     the rest one by one), three runs in a row with the oracle checked after
-    each; and a batch plan with 4-iteration graphs."""
+    each; and a batch plan with 4-iteration graphs; heavy leaves queued or in
+    place (a graph without the heavy kernel)."""
     from paper_2403_05775_amd import kdss
     g = synth.chung_lu(3000, 20000, 2.3, seed=11, planted=25)
     T = 21
     want = ref(oracle_mod, g, 4, T)
     tree = kdss.Tree(g, 4)
-    plan = kdss.Plan(tree, T, use_graph=G)
+    plan = kdss.Plan(tree, T, use_graph=G, heavy=heavy)
     ws = plan.alloc_workspace()
     plan.upload(ws)
     r = plan.alloc_loads()
     order = torch.empty(g.n, dtype=torch.int32, device="cuda")
     for rep in range(3):
-        print(f"graphs of {G} iterations, run {rep}", flush=True)
+        print(f"graphs of {G} iterations, heavy mode {heavy}, run {rep}", flush=True)
         res, _ = plan.run(ws, T, r, order)
         torch.cuda.synchronize()
         assert np.array_equal(r.cpu().numpy().view(np.uint64)[: g.n], want["r"]), rep
@@ -401,7 +402,7 @@ def test_multi_iteration_graphs(K, oracle_mod, G):
         assert (res.size, res.dens_num.value, res.ub_num.value) == (want["size"], want["dens_num"], want["ub_num"])
     probs = [(synth.chung_lu(400 + 90 * i, 3000 + 500 * i, 2.3, seed=50 + i, planted=12), 3 + i % 4)
              for i in range(4)]
-    b = kdss.Batch([kdss.Tree(gq, kq) for gq, kq in probs], 9, use_graph=4)
+    b = kdss.Batch([kdss.Tree(gq, kq) for gq, kq in probs], 9, use_graph=4, heavy=heavy)
     wsb = b.alloc_workspace()
     b.upload(wsb)
     rb = torch.empty(b.n, dtype=torch.int64, device="cuda")
