@@ -77,8 +77,10 @@ def test_random_graphs(K, oracle_mod, seed):
         r0 = (rs.u64(n) % np.uint64(4)).astype(np.uint64)       # many ties
     elif seed % 3 == 2:
         r0 = (rs.u64(n) % np.uint64(1000)).astype(np.uint64)
-    print(f"random seed={seed} n={n} m={m} k={k} T={T} r0={'yes' if r0 is not None else 'no'}", flush=True)
-    sol = K.solve(g, k, T, r0=r0)
+    heavy = 1 + seed % 2   # heavy leaves queued (odd seeds: in place)
+    print(f"random seed={seed} n={n} m={m} k={k} T={T} r0={'yes' if r0 is not None else 'no'} heavy={heavy}",
+          flush=True)
+    sol = K.solve(g, k, T, r0=r0, heavy=heavy)
     assert_same(sol, ref(oracle_mod, g, k, T, r0=r0), T, f"seed={seed}")
 
 
@@ -89,10 +91,12 @@ def test_every_size_class(K, oracle_mod, k, planted):
     g = synth.erdos_renyi(260, 0.12, seed=7, planted_clique=planted)
     T = 6
     print(f"size classes k={k} planted={planted}", flush=True)
-    sol = K.solve(g, k, T)
-    if planted > 64:
-        assert sol.plan_stats.leaves[4] > 0
-    assert_same(sol, ref(oracle_mod, g, k, T), T, f"k={k}")
+    want = ref(oracle_mod, g, k, T)
+    for heavy in (1, 2):
+        sol = K.solve(g, k, T, heavy=heavy)
+        if planted > 64:
+            assert sol.plan_stats.leaves[4] > 0
+        assert_same(sol, want, T, f"k={k} heavy={heavy}")
 
 
 def test_graph_replay_and_determinism(K, oracle_mod):
