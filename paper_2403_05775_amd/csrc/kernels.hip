@@ -364,7 +364,7 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
                                           const uint32_t* __restrict__ hdr, const uint64_t* binom, uint32_t k1,
                                           const KeySrc& src, const KT* hkey, Sink& sink, uint4* __restrict__ queue,
                                           uint32_t* __restrict__ qcount, WaveQueue& hq, uint32_t* lcol,
-                                          uint32_t inline_max) {
+                                          bool in_place) {
   constexpr uint32_t U = kLaneBatch;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nl = (t.info >> 3) & 0x1FFFu, smax = t.info >> 16;
@@ -458,17 +458,16 @@ __device__ __forceinline__ void tile_lane(const Tile& t, uint32_t tile_idx, cons
     if (nlow > 2) sink.add(r2, c2);
     if (nlow > 3) sink.add(r3, c3);
   }
-  // Leaves with more than four low members: a tile with at most inline_max
-  // of them has the whole wavefront take them up right away (its rows are
-  // still in the caches); a tile with more sends them to the heavy-leaf queue
-  // (through the wavefront's LDS buffer), which the heavy kernel spreads over
-  // the grid.
+  // Leaves with more than four low members: in place, the whole wavefront
+  // takes them up right away (the tile's rows are still in the caches);
+  // otherwise they go to the heavy-leaf queue (through the wavefront's LDS
+  // buffer), which the heavy kernel spreads over the grid.
   const uint64_t heavy = __ballot(nlow > 4);
   if (heavy) {
-    const uint32_t cnt = (uint32_t)__popcll(heavy);
-    if (cnt <= inline_max) {
+    if (in_place) {
       tile_heavy<KT>(heavy, t.mbase, hd, members, binom, k1, src, hkey, sink);
     } else {
+      const uint32_t cnt = (uint32_t)__popcll(heavy);
       const uint32_t below = (uint32_t)__popcll(heavy & ((1ull << lane) - 1ull));
       const uint64_t mw = t.mbase + lane;
       const uint4 entry = make_uint4((uint32_t)mw, (uint32_t)(mw >> 32), hd, t.nbase);
@@ -558,7 +557,7 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
                                                           uint64_t* __restrict__ scratch, uint4* __restrict__ queue,
                                                           uint32_t* __restrict__ qcount, KT* __restrict__ hotkey,
                                                           bool hot_published, const uint32_t* __restrict__ xcd,
-                                                          uint32_t inline_max) {
+                                                          bool in_place) {
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kLdsBinom ? kBinomLds : 1];
@@ -608,7 +607,7 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
     KeySrc ts = src;
     ts.base = t.nbase;
     if ((t.info & 7u) == kTileBig) tile_big<KT>(t, members, hdr, bt, k1, ts, hkey, sink);
-    else tile_lane<KT, kMasked>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq, lcol, inline_max);
+    else tile_lane<KT, kMasked>(t, tile, members, hdr, bt, k1, ts, hkey, sink, queue, qcount, hq, lcol, in_place);
     // the descriptor's last loaded word is kept alive to here, so its register
     // is not reused (and the load not waited for) while this tile runs
     asm volatile("" ::"s"(tn.pad[0]));
@@ -1898,11 +1897,10 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   hipEvent_t* ev_heavy = ev ? ev + kEvHeavy : nullptr;
   // in place: every tile takes up its own heavy leaves; queue: none does
   const bool in_place = P->heavy == 2;
-  const uint32_t inline_max = in_place ? 64u : 0u;
 #define KDSS_LEAF_V(KT, MASKED, LDSB)                                                                           \
   launch_timed(leaf_credit_kernel<KT, MASKED, LDSB>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members, \
                hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,                \
-               ws.at<KT>(table_off), hot_published, xcd, inline_max)
+               ws.at<KT>(table_off), hot_published, xcd, in_place)
 #define KDSS_LEAF(KT)                                                                                           \
   if (nbinom <= kBinomLds) {                                                                                     \
     if (P->gather == 2) KDSS_LEAF_V(KT, false, true);                                                            \
