@@ -282,8 +282,9 @@ struct WaveQueue {
 // of the first low members go to the lane's four LDS slots (lcol[i * 256],
 // written only by lanes that find one, so a row costs no register selects);
 // lanes with at most four rank them from their keys, looked up again; leaves
-// with more go to the heavy-leaf queue.  Keys are gathered only for members
-// inside the lane's leaf that are not hot (hot keys come from LDS).
+// with more go to the heavy-leaf queue, or are taken up in place by the whole
+// wavefront.  Keys are gathered for every row (a hot or padding member reads a
+// harmless address, see the gather modes); hot keys come from LDS.
 constexpr uint32_t kLeafThreads = 256;   // leaf-credit workgroup size (LDS slot stride)
 
 // A tile descriptor's fields (and one padding word, see the leaf-credit loop).
@@ -639,11 +640,11 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
 // Heavy leaves (more than four pivot members below the hold minimum), queued
 // by the leaf-credit kernel as 16-byte entries: one leaf per wavefront, one
 // member per lane, four leaves per batch, the batches pipelined.  The hold
-// minimum m is recomputed; the rank of a low member among the low members is
-// counted with wavefront ballots.  Hot members' keys come from the table the
-// leaf pass published; their credits add up in LDS and reach the nodes' slot
-// entries (slot blockIdx.x % kHotSlots) once per workgroup.  Workgroups past the queue
-// return at once.
+// minimum m is recomputed; the low members' keys are compacted into LDS and
+// each counts the smaller ones by broadcast reads.  Hot members' keys come
+// from the table the leaf pass published; their credits add up in LDS and
+// reach the nodes' slot entries (slot blockIdx.x % kHotSlots) once per
+// workgroup.  Workgroups past the queue return at once.
 template <class KT, bool kLdsBinom>
 __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__ members,
                                                     const uint64_t* __restrict__ binom, uint32_t k1, KeySrc src,
