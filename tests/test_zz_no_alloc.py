@@ -32,10 +32,10 @@ def fields(res):
             res.bound_num.value, res.bound_den, res.bound_kind, res.certified)
 
 
-def both(K, g, k, T, r0=None, width=0):
+def both(K, g, k, T, r0=None, width=0, heavy=0):
     tree = K.Tree(g, k)
     r0_max = 0 if r0 is None else int(r0.max())
-    plan = K.Plan(tree, T, r0_max=r0_max, width=width, use_graph=True)
+    plan = K.Plan(tree, T, r0_max=r0_max, width=width, use_graph=True, heavy=heavy)
     assert plan.workspace_bytes <= K.STATIC_WORKSPACE_BYTES
     r0_t = None if r0 is None else torch.from_numpy(r0.view(np.int64).copy()).cuda()
     # the static entry point first: nothing of this plan is in any workspace yet
@@ -67,6 +67,16 @@ def test_static_run_twice_second_smaller(K, oracle_mod):
     ref = oracle_mod.solve(small.n, small.row_ptr, small.col, 3, 64)
     assert (b.size, b.dens_num.value, b.ub_num.value) == (ref["size"], ref["dens_num"], ref["ub_num"])
     assert a.n == big.n
+
+
+def test_static_run_heavy_leaves_in_place(K, oracle_mod):
+    """The static entry point with heavy leaves taken up in place (no heavy
+    kernel in the replayed iterations) equals kdss_run and the oracle."""
+    g = synth.chung_lu(6000, 50000, 2.2, seed=43, planted=28)
+    say("static run: 6k-node Chung-Lu, k=5, T=20, heavy leaves in place")
+    got = both(K, g, 5, 20, heavy=2)
+    ref = oracle_mod.solve(g.n, g.row_ptr, g.col, 5, 20)
+    assert (got.size, got.dens_num.value, got.ub_num.value) == (ref["size"], ref["dens_num"], ref["ub_num"])
 
 
 def test_static_run_start_loads_and_wide(K):
