@@ -94,12 +94,13 @@ def host_cores():
     return min(16, os.cpu_count() or 1)
 
 
-def rooflines(tm, L, M, n, width=64):
+def rooflines(tm, L, M, n, width=64, concurrent=False):
     """HBM roofline fractions from the kernel durations of the timed region
     (kernel-attached HIP events; averages per launch), with the algorithmic
     bytes of one iteration: the leaf stream (4 B per member, 4 B per leaf
     header) and w B per node to read the loads, plus w B per node to write them
-    in the load update (w = 8 for 64-bit loads)."""
+    in the load update (w = 8 for 64-bit loads).  concurrent: the pass's two
+    kernels run side by side (PBUpdate), so the pass takes the longer of them."""
     nl = max(1, tm.leaf_launches)
     leaf_us = 1000.0 * tm.leaf_ms / nl
     heavy_us = 1000.0 * tm.heavy_ms / nl
@@ -108,7 +109,7 @@ def rooflines(tm, L, M, n, width=64):
     w = width // 8
     pass_bytes = 4 * M + 4 * L + w * n
     iter_bytes = pass_bytes + w * n
-    pass_us = leaf_us + heavy_us + reduce_us
+    pass_us = (max(leaf_us, heavy_us) if concurrent else leaf_us + heavy_us) + reduce_us
     iter_us = pass_us + apply_us
 
     def frac(b, us):
@@ -131,7 +132,9 @@ def roofline_fields(rf, kernel, workload, counters_key):
                         "frac": rf["leaf"][1], "traffic": traffic, "kernel": kernel,
                         "bytes_per_launch": rf["pass_bytes"], "us_per_launch": rf["leaf_us"],
                         "timing": "kernel-attached HIP events (hipExtLaunchKernel) over the timed steps"},
-           "credit_pass": {"kernels": "leaf_credit + heavy_leaf" + (" + hot_reduce" if rf["reduce_us"] else ""),
+           "credit_pass": {"kernels": ("pb_kernel beside pb_reg_kernel (two streams; the longer counts)"
+                                       if kernel == "pb_kernel" else "leaf_credit + heavy_leaf")
+                                      + (" + hot_reduce" if rf["reduce_us"] else ""),
                            "us": rf["credit_pass"][2], "achieved": rf["credit_pass"][0], "frac": rf["credit_pass"][1]},
            "iteration": {"kernels": "credit pass + load update", "us": rf["iteration"][2],
                          "bytes": rf["iter_bytes"], "achieved": rf["iteration"][0], "frac": rf["iteration"][1]},
@@ -903,11 +906,12 @@ def single_bench(w, args):
     if tm is not None:
         # the kernels of a step fit inside it (a profiler attached to the run
         # can stretch the event-stamped steps; the line then says so)
-        out["kernel_time_within_step"] = kernel_time_sum(tm) / args.steps <= ms_per_step * 1.001
-        rf = rooflines(tm, L, M, n, ps.width)
+        # (PBUpdate's two pass kernels run side by side: the longer one counts)
+        out["kernel_time_within_step"] = kernel_time_sum(tm, bool(update)) / args.steps <= ms_per_step * 1.001
+        rf = rooflines(tm, L, M, n, ps.width, concurrent=bool(update))
         kname = "pb_kernel" if update else "leaf_credit_kernel<KPacked>"
         out.update(roofline_fields(rf, kname, args.workload, args.workload))
-        out["kernel_ms_per_step"] = kernel_time_sum(tm) / args.steps
+        out["kernel_ms_per_step"] = kernel_time_sum(tm, bool(update)) / args.steps
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         if update:
@@ -923,8 +927,11 @@ def single_bench(w, args):
     print(json.dumps(out))
 
 
-def kernel_time_sum(tm):
-    return tm.leaf_ms + tm.heavy_ms + tm.reduce_ms + tm.apply_ms
+def kernel_time_sum(tm, concurrent=False):
+    """Kernel time of the timed steps; with concurrent pass kernels (PBUpdate)
+    the pass counts as the longer of its two kernels."""
+    pass_ms = max(tm.leaf_ms, tm.heavy_ms) if concurrent else tm.leaf_ms + tm.heavy_ms
+    return pass_ms + tm.reduce_ms + tm.apply_ms
 
 
 def profiled_steps(plan, step, args):

@@ -225,6 +225,12 @@ struct kdss_plan {
   void* graph_r = nullptr;
   uint32_t graph_iters = 0;            // iterations the captured graph holds
   void* capture_stream = nullptr;
+  // PBUpdate's register-tile kernel runs beside its LDS-tile kernel: a second
+  // stream of the default priority and the fork / join events (made on first use)
+  mutable void* side_stream = nullptr;
+  mutable void* ev_fork = nullptr;
+  mutable void* ev_join = nullptr;
+  bool one_stream = false;   // set for the duration of a static run: no stream or event is made
   std::vector<void*> events;           // hipEvent_t pool for kernel timing
   std::vector<uint32_t> ev_used;       // per iteration: which kernels stamped their events
   kdss_timing timing{};

@@ -1944,6 +1944,43 @@ int launch_pb(const kdss_plan* P, const WsView& ws, const void* d_r, uint64_t* o
               hipEvent_t* ev, uint32_t* used) {
   const uint32_t ntiles = (uint32_t)P->tiles.size();
   const uint32_t split = P->pb_split, nhot = (uint32_t)P->hot.size();
+  // The two kernels read r_{t-1} and only add credits, so they run side by
+  // side: the register kernel on a second stream forked from st and joined
+  // back before the load update (captured graphs keep the fork and join).
+  hipStream_t reg_st = st;
+  const bool both = split && split < ntiles && !P->one_stream;
+  if (both) {
+    if (!P->side_stream) {   // all three or none
+      hipStream_t s2 = nullptr;
+      hipEvent_t e1 = nullptr, e2 = nullptr;
+      hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&e2, hipEventDisableTiming);
+      if (e == hipSuccess) e = injected_failure();
+      if (e != hipSuccess) {
+        if (e2) (void)hipEventDestroy(e2);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s2) (void)hipStreamDestroy(s2);
+        return hip_fail(e, "PBUpdate side stream");
+      }
+      P->side_stream = s2;
+      P->ev_fork = e1;
+      P->ev_join = e2;
+    }
+    reg_st = static_cast<hipStream_t>(P->side_stream);
+    HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P->ev_fork), st), "PBUpdate fork");
+    HIP_TRY(hipStreamWaitEvent(reg_st, static_cast<hipEvent_t>(P->ev_fork), 0), "PBUpdate fork");
+  }
+  if (split < ntiles) {   // the lane tiles of at most kPbRegRows rows, from registers
+    const uint32_t blocks = std::min<uint32_t>((ntiles - split + 3) / 4, P->leaf_blocks);
+    launch_timed(pb_reg_kernel, blocks, 256, 0, reg_st, ev ? ev + kEvHeavy : nullptr,
+                 (const Tile*)ws.at<Tile>(P->off_tiles), split, ntiles, (const uint32_t*)ws.at<uint32_t>(P->off_members),
+                 (const uint32_t*)ws.at<uint32_t>(P->off_hdr), (const uint64_t*)ws.at<uint64_t>(P->off_binom), P->k1,
+                 static_cast<const uint64_t*>(d_r), (const uint32_t*)ws.at<uint32_t>(P->off_hot), nhot, out,
+                 ws.at<uint64_t>(P->off_scratch));
+    HIP_TRY(hipGetLastError(), "PBUpdate launch");
+    if (used) *used |= 2u;
+  }
   // big leaves and lane tiles of more than kPbRegRows rows, staged in LDS, in
   // one launch: one workgroup per tile of more than kPbMidRows rows, then
   // four wavefronts per workgroup for the rest
@@ -1959,15 +1996,9 @@ int launch_pb(const kdss_plan* P, const WsView& ws, const void* d_r, uint64_t* o
     HIP_TRY(hipGetLastError(), "PBUpdate launch");
     if (used) *used |= 1u;
   }
-  if (split < ntiles) {   // the other lane tiles, from registers
-    const uint32_t blocks = std::min<uint32_t>((ntiles - split + 3) / 4, P->leaf_blocks);
-    launch_timed(pb_reg_kernel, blocks, 256, 0, st, ev ? ev + kEvHeavy : nullptr,
-                 (const Tile*)ws.at<Tile>(P->off_tiles), split, ntiles, (const uint32_t*)ws.at<uint32_t>(P->off_members),
-                 (const uint32_t*)ws.at<uint32_t>(P->off_hdr), (const uint64_t*)ws.at<uint64_t>(P->off_binom), P->k1,
-                 static_cast<const uint64_t*>(d_r), (const uint32_t*)ws.at<uint32_t>(P->off_hot), nhot, out,
-                 ws.at<uint64_t>(P->off_scratch));
-    HIP_TRY(hipGetLastError(), "PBUpdate launch");
-    if (used) *used |= 2u;
+  if (both) {
+    HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(P->ev_join), reg_st), "PBUpdate join");
+    HIP_TRY(hipStreamWaitEvent(st, static_cast<hipEvent_t>(P->ev_join), 0), "PBUpdate join");
   }
   return KDSS_OK;
 }
@@ -2437,6 +2468,9 @@ void kdss_plan_free(kdss_plan* P) {
   drop_graph(P);
   for (void* e : P->events) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
   if (P->capture_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(P->capture_stream));
+  if (P->side_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(P->side_stream));
+  if (P->ev_fork) (void)hipEventDestroy(static_cast<hipEvent_t>(P->ev_fork));
+  if (P->ev_join) (void)hipEventDestroy(static_cast<hipEvent_t>(P->ev_join));
   delete P;
 }
 

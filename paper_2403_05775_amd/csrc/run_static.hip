@@ -59,13 +59,16 @@ int kdss_run_static(kdss_plan* p, uint32_t T, const uint64_t* d_r0, void* d_r, u
   // memset), and the run itself starts from cleared credits and results
   rc = kdss::upload_plan(p, ws, kStaticWorkspaceBytes, stream, true);
   if (rc) return rc;
-  // plain launches only: no graph instantiation and no timing events
+  // plain launches on the caller's stream only: no graph instantiation, no
+  // timing events, no second stream
   const kdss_opts saved = p->opts;
   p->opts.use_graph = 0;
   p->opts.time_kernels = 0;
   p->opts.extract_every = 0;
+  p->one_stream = true;
   rc = kdss::run_plan(p, ws, kStaticWorkspaceBytes, T, d_r0, d_r, d_order, h_res, stream);
   p->opts = saved;
+  p->one_stream = false;
   return rc;
 }
 

@@ -32,10 +32,10 @@ def fields(res):
             res.bound_num.value, res.bound_den, res.bound_kind, res.certified)
 
 
-def both(K, g, k, T, r0=None, width=0, heavy=0):
+def both(K, g, k, T, r0=None, width=0, heavy=0, update=0):
     tree = K.Tree(g, k)
     r0_max = 0 if r0 is None else int(r0.max())
-    plan = K.Plan(tree, T, r0_max=r0_max, width=width, use_graph=True, heavy=heavy)
+    plan = K.Plan(tree, T, r0_max=r0_max, width=width, use_graph=True, heavy=heavy, update=update)
     assert plan.workspace_bytes <= K.STATIC_WORKSPACE_BYTES
     r0_t = None if r0 is None else torch.from_numpy(r0.view(np.int64).copy()).cuda()
     # the static entry point first: nothing of this plan is in any workspace yet
@@ -77,6 +77,21 @@ def test_static_run_heavy_leaves_in_place(K, oracle_mod):
     got = both(K, g, 5, 20, heavy=2)
     ref = oracle_mod.solve(g.n, g.row_ptr, g.col, 5, 20)
     assert (got.size, got.dens_num.value, got.ub_num.value) == (ref["size"], ref["dens_num"], ref["ub_num"])
+
+
+def test_static_run_pbupdate(K, oracle_mod):
+    """PBUpdate through the static entry point (its two pass kernels one after
+    the other on the caller's stream) equals kdss_run (side by side on two
+    streams, replayed as a graph) and the oracle's synchronous pass."""
+    g = synth.chung_lu(6000, 50000, 2.2, seed=44, planted=28)
+    say("static run: 6k-node Chung-Lu, k=4, T=15, PBUpdate")
+    got = both(K, g, 4, 15, update=1)
+    tree = K.Tree(g, 4)
+    h, p, mem = tree.export()
+    tree.close()
+    r = oracle_mod.pb_run(g.n, h, p, mem, 4, 15, True)["r"]
+    ex = oracle_mod.extract(g.n, g.row_ptr, g.col, 4, r)
+    assert (got.size, got.dens_num.value) == (ex["size"], ex["dens_num"])
 
 
 def test_static_run_start_loads_and_wide(K):
