@@ -51,6 +51,20 @@ def test_rooflines_arithmetic(bench):
     assert rf["heavy_per_iter"] == pytest.approx(100.0)
 
 
+def test_rooflines_concurrent_pass(bench):
+    """PBUpdate's two pass kernels run side by side: the pass counts as the
+    longer of them, in the roofline scopes and in the step's kernel time."""
+    tm = types.SimpleNamespace(leaf_launches=10, leaf_ms=1.7, heavy_ms=1.6, reduce_ms=0.0, apply_launches=10,
+                               apply_ms=0.05, heavy_leaves=0)
+    L, M, n = 1_000_000, 12_000_000, 1_000_000
+    rf = bench.rooflines(tm, L, M, n, concurrent=True)
+    assert rf["credit_pass"][2] == pytest.approx(170.0) and rf["iteration"][2] == pytest.approx(175.0)
+    assert bench.kernel_time_sum(tm, True) == pytest.approx(1.75)
+    assert bench.kernel_time_sum(tm) == pytest.approx(3.35)
+    fields = bench.roofline_fields(rf, "pb_kernel", "pbupdate-1m", "pbupdate-1m")
+    assert "beside" in fields["credit_pass"]["kernels"]
+
+
 def _counter_db(path, rows):
     c = sqlite3.connect(path)
     c.execute("create table counters_collection (dispatch_id integer, kernel_name text, counter_name text, "
