@@ -259,9 +259,13 @@ def launch_gather(args):
     return int(args.launch.split(",")[2]) if args.launch else 0
 
 
+HEAVY_MODES = {1: "queue", 2: "in place", 3: "queue, eight per batch"}
+
+
 def heavy_name(mode):
     """Where leaves with more than four low members are credited."""
-    return "queued for the heavy kernel" if mode == 1 else "in place, by the tile's wavefront"
+    return {1: "queued for the heavy kernel (four per batch)", 2: "in place, by the tile's wavefront",
+            3: "queued for the heavy kernel (eight per batch)"}[mode]
 
 
 def launch_fields(tune, cached):
@@ -270,12 +274,12 @@ def launch_fields(tune, cached):
     out = {"leaf_blocks": tune.best_leaf_blocks, "heavy_blocks": tune.best_heavy_blocks,
            "gather": "masked" if tune.best_gather == 1 else "full",
            "schedule": "strided" if tune.best_schedule == 1 else "XCD ranges",
-           "heavy_leaves": "queue" if tune.best_heavy == 1 else "in place", "from_tuning_cache": cached,
+           "heavy_leaves": HEAVY_MODES[tune.best_heavy], "from_tuning_cache": cached,
            "tuned_us_per_iter": tune.best_ms * 1000}
     if not cached:
         out["gather_us"] = {"masked": tune.gather_ms[0] * 1000, "full": tune.gather_ms[1] * 1000}
         out["schedule_us"] = {"strided": tune.schedule_ms[0] * 1000, "XCD ranges": tune.schedule_ms[1] * 1000}
-        out["heavy_us"] = {"queue": tune.heavy_ms[0] * 1000, "in place": tune.heavy_ms[1] * 1000}
+        out["heavy_us"] = {HEAVY_MODES[m]: tune.heavy_ms[m - 1] * 1000 for m in (1, 2, 3)}
     return out
 
 
@@ -967,7 +971,8 @@ def main():
     ap.add_argument("--launch", default="", help="LEAF,HEAVY,GATHER: a given launch instead of the tuned one")
     ap.add_argument("--schedule", type=int, default=0, help="tile schedule: 0 tuned, 1 strided, 2 XCD ranges")
     ap.add_argument("--heavy", type=int, default=0,
-                    help="heavy leaves: 0 tuned, 1 queued for the heavy kernel, 2 in place by the tile's wavefront")
+                    help="heavy leaves: 0 tuned, 1 queued for the heavy kernel, 2 in place by the tile's wavefront, "
+                         "3 queued, eight per heavy-kernel batch")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2403_05775_amd", "tune_cache.txt"),
                     help="tuning cache file ('' to tune without one)")
     ap.add_argument("--scales", default="12-20", help="tree-growth mode: R-MAT scales lo-hi")

@@ -129,14 +129,19 @@ typedef struct {
                                  0: choose (queue; autotune may switch);
                                  1: queue: the leaf-credit kernel queues them
                                     and a second kernel spreads them over its
-                                    grid, one leaf per wavefront;
+                                    grid, one leaf per wavefront, four per
+                                    batch;
                                  2: in place: the wavefront that finds them
                                     takes them up at once, four at a time,
                                     while its tile's rows are still cached,
                                     and no second kernel runs (faster when
                                     heavy leaves are spread over many tiles
                                     and the loads fit in the caches; slower
-                                    when they crowd into a few tiles)        */
+                                    when they crowd into a few tiles);
+                                 3: queue, eight leaves per batch (64-bit
+                                    keys; four otherwise): more in flight per
+                                    wavefront, faster on queues of millions,
+                                    slower on short ones                    */
 } kdss_opts;
 
 typedef struct {              /* accumulated by kdss_run when time_kernels = 1  */
@@ -167,7 +172,8 @@ typedef struct {
     int schedule;             /* tile schedule of later runs: 1 strided, 2 XCD ranges */
     uint32_t hot_nodes;       /* nodes whose keys and credits live in LDS       */
     double hot_share;         /* their share of all member occurrences          */
-    int heavy;                /* heavy leaves of later runs: 1 queue, 2 in place */
+    int heavy;                /* heavy leaves of later runs: 1 queue, 2 in place,
+                                 3 queue with eight per batch                 */
 } kdss_plan_stats;
 
 typedef struct {
@@ -448,8 +454,9 @@ typedef struct {
     int best_schedule;            /* tile schedule kept (1 strided, 2 XCD ranges) */
     double schedule_ms[2];        /* per iteration with each schedule at the
                                      best grid sizes and gather (0: not timed) */
-    int best_heavy;               /* heavy leaves kept (1 queue, 2 in place)   */
-    double heavy_ms[2];           /* per iteration with each heavy-leaf mode at
+    int best_heavy;               /* heavy leaves kept (1 queue, 2 in place,
+                                     3 queue with eight per batch)             */
+    double heavy_ms[3];           /* per iteration with each heavy-leaf mode at
                                      the best launch otherwise (0: not timed)  */
 } kdss_tune_result;
 
@@ -460,7 +467,7 @@ int kdss_plan_set_launch(kdss_plan *p, uint32_t leaf_blocks, uint32_t heavy_bloc
  * candidate pair of grid sizes on the plan's own data, keeps the fastest and
  * reports all (out, host).  Then each choice the plan's options left to the
  * library (the gather mode, then the heavy-leaf mode, then the tile schedule)
- * has its other value timed at the best launch so far, kept if faster.  d_r (device, the plan's load width) is scratch.
+ * has its other values timed at the best launch so far, the fastest kept.  d_r (device, the plan's load width) is scratch.
  * warm + iters must not exceed T_max.  Synchronises the stream. */
 int kdss_plan_autotune(kdss_plan *p, void *d_ws, size_t ws_bytes, uint64_t *d_r, uint32_t warm, uint32_t iters,
                        kdss_tune_result *out, void *stream);

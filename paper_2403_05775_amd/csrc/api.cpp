@@ -319,11 +319,11 @@ static int build_plan(const std::vector<const Sct*>& trees, uint32_t T_max, uint
       return fail(KDSS_EINVAL, "schedule must be 0, 1 or 2");
     }
     P->sched = P->opts.schedule == 2 ? 2 : 1;
-    if (P->opts.heavy < 0 || P->opts.heavy > 2) {
+    if (P->opts.heavy < 0 || P->opts.heavy > 3) {
       delete P;
-      return fail(KDSS_EINVAL, "heavy must be 0, 1 or 2");
+      return fail(KDSS_EINVAL, "heavy must be 0, 1, 2 or 3");
     }
-    P->heavy = P->opts.heavy == 2 ? 2 : 1;
+    P->heavy = P->opts.heavy ? P->opts.heavy : 1;
     if (P->opts.update == 1 && (P->opts.width == 128 || !fits64)) {
       delete P;
       return fail(KDSS_EINVAL, "PBUpdate runs with 64-bit loads only");

@@ -176,7 +176,7 @@ struct kdss_plan {
   int key_mode = 0;        // 0 packed, 1 full
   int gather = 1;          // leaf-pass key gathers: 1 masked, 2 full
   int sched = 1;           // leaf-pass tile schedule: 1 strided, 2 XCD ranges
-  int heavy = 1;           // heavy leaves: 1 queued for the heavy kernel, 2 taken up in place
+  int heavy = 1;           // heavy leaves: 1 queued (heavy kernel, four per batch), 2 in place, 3 queued (eight)
   uint32_t xcd_bounds[9] = {};   // XCD x takes tiles [xcd_bounds[x], xcd_bounds[x + 1])
   uint32_t pb_split = 0;   // PBUpdate: tiles [0, pb_split) are staged in LDS, the rest (lane tiles of
                            // at most kPbRegRows rows) kept in registers

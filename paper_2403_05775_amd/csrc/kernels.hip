@@ -639,20 +639,23 @@ __global__ __launch_bounds__(256, 8) void leaf_credit_kernel(const Tile* __restr
 
 // Heavy leaves (more than four pivot members below the hold minimum), queued
 // by the leaf-credit kernel as 16-byte entries: one leaf per wavefront, one
-// member per lane, four leaves per batch, the batches pipelined.  The hold
+// member per lane, four leaves per batch (eight with kEight and 64-bit or
+// smaller keys: more leaves in flight per wavefront at five wavefronts per
+// SIMD instead of six, faster on queues of millions and slower on short ones,
+// where fewer wavefronts then share the work), the batches pipelined.  The hold
 // minimum m is recomputed; the low members' keys are compacted into LDS and
 // each counts the smaller ones by broadcast reads.  Hot members' keys come
 // from the table the leaf pass published; their credits add up in LDS and
 // reach the nodes' slot entries (slot blockIdx.x % kHotSlots) once per
 // workgroup.  Workgroups past the queue return at once.
-template <class KT, bool kLdsBinom>
+template <class KT, bool kLdsBinom, bool kEight>
 __global__ __launch_bounds__(256) void heavy_kernel(const uint32_t* __restrict__ members,
                                                     const uint64_t* __restrict__ binom, uint32_t k1, KeySrc src,
                                                     uint64_t* __restrict__ out, uint32_t nhot,
                                                     uint64_t* __restrict__ scratch, const uint4* __restrict__ queue,
                                                     const uint32_t* __restrict__ qcount,
                                                     const KT* __restrict__ hotkey, uint32_t nbinom) {
-  constexpr uint32_t B = 4;
+  constexpr uint32_t B = (kEight && sizeof(KT) <= 8) ? 8 : 4;
   __shared__ KT hkey[kHotMax];
   __shared__ unsigned long long hcnt[kHotMax];
   __shared__ uint64_t sbinom[kLdsBinom ? kHeavyBinomLds : 1];
@@ -1898,6 +1901,7 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
   hipEvent_t* ev_heavy = ev ? ev + kEvHeavy : nullptr;
   // in place: every tile takes up its own heavy leaves; queue: none does
   const bool in_place = P->heavy == 2;
+  const bool eight = P->heavy == 3;
 #define KDSS_LEAF_V(KT, MASKED, LDSB)                                                                           \
   launch_timed(leaf_credit_kernel<KT, MASKED, LDSB>, blocks, kLeafThreads, 0, st, ev_leaf, tiles, ntiles, members, \
                hdr, binom, nbinom, P->k1, src, out, hot, hot_base, nhot, scratch, queue, qcount,                \
@@ -1911,7 +1915,9 @@ int launch_leaf(const kdss_plan* P, const WsView& ws, int mode, const KeySrc& sr
     else KDSS_LEAF_V(KT, true, false);                                                                           \
   }                                                                                                              \
   if (!in_place)                                                                                                 \
-    launch_timed(nbinom <= kHeavyBinomLds ? heavy_kernel<KT, true> : heavy_kernel<KT, false>, P->heavy_blocks, 256, \
+    launch_timed(nbinom <= kHeavyBinomLds ? (eight ? heavy_kernel<KT, true, true> : heavy_kernel<KT, true, false>)   \
+                                          : (eight ? heavy_kernel<KT, false, true> : heavy_kernel<KT, false, false>), \
+                 P->heavy_blocks, 256,                                                                           \
                  0, st, ev_heavy, members, binom, P->k1, src, out, nhot, scratch, (const uint4*)queue,             \
                  (const uint32_t*)qcount, (const KT*)ws.at<KT>(table_off), nbinom)
   if (used) *used |= in_place ? 1u : 1u | 2u;
@@ -2794,15 +2800,18 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
       const int current = P->heavy;
       P->leaf_blocks = out->best_leaf_blocks;
       P->heavy_blocks = out->best_heavy_blocks;
-      P->heavy = 3 - current;
-      float ms = 0.f;
-      rc = time_config(&ms);
-      if (!rc) {
-        ++out->tried;
-        out->heavy_ms[P->heavy - 1] = ms;
-        if (ms < out->best_ms) {
-          out->best_ms = ms;
-          out->best_heavy = P->heavy;
+      for (int m = 1; m <= 3 && !rc; ++m) {
+        if (m == current) continue;
+        P->heavy = m;
+        float ms = 0.f;
+        rc = time_config(&ms);
+        if (!rc) {
+          ++out->tried;
+          out->heavy_ms[m - 1] = ms;
+          if (ms < out->best_ms) {
+            out->best_ms = ms;
+            out->best_heavy = m;
+          }
         }
       }
       P->heavy = out->best_heavy;
@@ -2881,7 +2890,7 @@ int kdss_plan_autotune_cached(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_
       double ms = 0.0;
       if (std::sscanf(line, "%511s %u %u %d %d %d %lf", k2, &lb, &hb, &g, &sc, &hm, &ms) == 7 &&
           std::strcmp(k2, key) == 0 && lb >= 1 && lb <= kLeafBlocksMax && hb >= 1 && hb <= kHeavyBlocks &&
-          (g == 1 || g == 2) && (sc == 1 || sc == 2) && (hm == 1 || hm == 2)) {
+          (g == 1 || g == 2) && (sc == 1 || sc == 2) && hm >= 1 && hm <= 3) {
         std::memset(out, 0, sizeof(*out));
         out->best_leaf_blocks = lb;
         out->best_heavy_blocks = hb;

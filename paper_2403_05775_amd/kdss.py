@@ -61,7 +61,7 @@ class TuneResult(C.Structure):
                 ("best_ms", C.c_double), ("leaf_blocks", C.c_uint32 * 32), ("heavy_blocks", C.c_uint32 * 32),
                 ("ms", C.c_double * 32), ("best_gather", C.c_int), ("gather_ms", C.c_double * 2),
                 ("best_schedule", C.c_int), ("schedule_ms", C.c_double * 2), ("best_heavy", C.c_int),
-                ("heavy_ms", C.c_double * 2)]
+                ("heavy_ms", C.c_double * 3)]
 
 
 class PlanStats(C.Structure):

@@ -235,14 +235,16 @@ def test_update_option():
 
 
 def test_heavy_leaf_option():
-    """Heavy leaves: queued unless in place is asked for; other values refused."""
+    """Heavy leaves: queued (four per heavy-kernel batch) unless in place or
+    eight per batch is asked for; other values refused."""
     g = synth.chung_lu(2000, 20000, 2.3, seed=5, planted=30)
     t = kdss.Tree(g, 4)
     assert kdss.Plan(t, 10).stats().heavy == 1
     assert kdss.Plan(t, 10, heavy=1).stats().heavy == 1
     assert kdss.Plan(t, 10, heavy=2).stats().heavy == 2
+    assert kdss.Plan(t, 10, heavy=3).stats().heavy == 3
     assert kdss.Batch([t], 10, heavy=2).stats().heavy == 2
-    for h in (3, -1):
+    for h in (4, -1):
         with pytest.raises(kdss.KdssError) as e:
             kdss.Plan(t, 10, heavy=h)
         assert e.value.status == kdss.EINVAL, h

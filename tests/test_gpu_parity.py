@@ -77,7 +77,7 @@ def test_random_graphs(K, oracle_mod, seed):
         r0 = (rs.u64(n) % np.uint64(4)).astype(np.uint64)       # many ties
     elif seed % 3 == 2:
         r0 = (rs.u64(n) % np.uint64(1000)).astype(np.uint64)
-    heavy = 1 + seed % 2   # heavy leaves queued (odd seeds: in place)
+    heavy = 1 + seed % 3   # heavy leaves queued, in place, or queued eight per batch
     print(f"random seed={seed} n={n} m={m} k={k} T={T} r0={'yes' if r0 is not None else 'no'} heavy={heavy}",
           flush=True)
     sol = K.solve(g, k, T, r0=r0, heavy=heavy)
@@ -92,7 +92,7 @@ def test_every_size_class(K, oracle_mod, k, planted):
     T = 6
     print(f"size classes k={k} planted={planted}", flush=True)
     want = ref(oracle_mod, g, k, T)
-    for heavy in (1, 2):
+    for heavy in (1, 2, 3):
         sol = K.solve(g, k, T, heavy=heavy)
         if planted > 64:
             assert sol.plan_stats.leaves[4] > 0
@@ -170,7 +170,7 @@ def test_heavy_leaves_in_place(K, oracle_mod, gather):
         assert_same(sol, ref(oracle_mod, g, k, T, r0=r0), T, f"in place gather={gather} k={k}")
     tree = K.Tree(g, 5)
     counts = {}
-    for heavy in (1, 2):
+    for heavy in (1, 2, 3):
         plan = K.Plan(tree, 9, time_kernels=True, gather=gather, heavy=heavy)
         ws = plan.alloc_workspace()
         plan.upload(ws)
@@ -186,6 +186,7 @@ def test_heavy_leaves_in_place(K, oracle_mod, gather):
     tree.close()
     assert counts[1][0] > 0 and counts[1][1] > 0
     assert counts[2] == (0, 0.0)
+    assert counts[3][0] == counts[1][0] and counts[3][1] > 0   # the same queue, eight per batch
 
 
 def test_heavy_in_place_credits_at_tied_loads(K, oracle_mod):
@@ -381,7 +382,7 @@ def test_xcd_range_schedule(K, oracle_mod, leaf_blocks):
         assert (resb[q].size, resb[q].dens_num.value) == (want["size"], want["dens_num"]), q
 
 
-@pytest.mark.parametrize("G,heavy", [(4, 1), (8, 1), (8, 2)])
+@pytest.mark.parametrize("G,heavy", [(4, 1), (8, 1), (8, 2), (4, 3)])
 def test_multi_iteration_graphs(K, oracle_mod, G, heavy):
     """Iterations replayed as graphs of G iterations (21 = 2 or 5 replays plus
     the rest one by one), three runs in a row with the oracle checked after
