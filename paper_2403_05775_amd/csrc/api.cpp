@@ -198,7 +198,7 @@ static void layout_workspace(kdss_plan* P) {
   P->off_dres = take(sizeof(DevResult));
   P->off_tb_binom = take(P->tb_binom.size() * 8);
   P->leaf_blocks = (uint32_t)std::min<uint64_t>(kLeafBlocksDefault, std::max<uint64_t>(1, (P->tiles.size() + 3) / 4));
-  P->heavy_blocks = kHeavyBlocks;
+  P->heavy_blocks = kHeavyBlocksDefault;
   P->off_hot = take(P->hot.size() * 4);
   P->off_hot_base = take(P->hot.size() * 4);
   // hot-node credit slots, hot-node-major (kept zero between passes)

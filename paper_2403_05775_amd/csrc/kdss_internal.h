@@ -126,7 +126,8 @@ constexpr uint32_t kHotMinOccurrences = 32;
 constexpr uint32_t kHotFlag = 0x80000000u;
 constexpr uint32_t kLeafBlocksMax = 2048;        // persistent leaf-credit grid, largest
 constexpr uint32_t kLeafBlocksDefault = 2048;    // eight workgroups per CU
-constexpr uint32_t kHeavyBlocks = 2048;          // largest grid of the heavy-leaf kernel
+constexpr uint32_t kHeavyBlocks = 16384;         // largest grid of the heavy-leaf kernel
+constexpr uint32_t kHeavyBlocksDefault = 2048;   // its grid until set or tuned
 constexpr uint32_t kHotSlots = 256;              // credit slots per hot node, shared by workgroups
 constexpr double kMaskedGatherShare = 0.5;       // hot share from which masked gathers are the default
 constexpr uint32_t kPbRegRows = 16;              // PBUpdate: lane tiles up to this many rows run from registers

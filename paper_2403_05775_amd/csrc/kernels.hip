@@ -2713,7 +2713,7 @@ int kdss_plan_set_timing(kdss_plan* P, int on) {
 int kdss_plan_set_launch(kdss_plan* P, uint32_t leaf_blocks, uint32_t heavy_blocks) {
   if (!P) return fail(KDSS_EINVAL, "null argument");
   if (leaf_blocks == 0 || leaf_blocks > kLeafBlocksMax || heavy_blocks == 0 || heavy_blocks > kHeavyBlocks)
-    return fail(KDSS_ERANGE, "grid sizes must be in 1..2048 (leaf and heavy)");
+    return fail(KDSS_ERANGE, "grid sizes must be in 1..2048 (leaf) and 1..16384 (heavy)");
   if (P->leaf_blocks != leaf_blocks || P->heavy_blocks != heavy_blocks) drop_graph(P);
   P->leaf_blocks = leaf_blocks;
   P->heavy_blocks = heavy_blocks;
@@ -2735,7 +2735,9 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
   HIP_TRY(hipEventCreate(&e0), "event create");
   HIP_TRY(hipEventCreate(&e1), "event create");
   const uint32_t leaf_c[] = {512, 1024, 1536, 1792, 2048};
-  const uint32_t heavy_c[] = {256, 512, 1024, 2048};
+  // heavy grids beyond what stays resident let the dispatcher balance the
+  // queue's tail: new workgroups start as others finish
+  const uint32_t heavy_c[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
   std::memset(out, 0, sizeof(*out));
   out->best_ms = 1e30;
   // per-iteration time of the plan's current launch configuration
