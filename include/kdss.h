@@ -448,7 +448,7 @@ typedef struct {
     double best_ms;               /* per iteration, best configuration         */
     uint32_t leaf_blocks[32], heavy_blocks[32];
     double ms[32];                /* per iteration, each grid-size pair (the
-                                     first 32 of the 35 timed)                 */
+                                     first 32 of the 49 timed)                 */
     int best_gather;              /* gather mode kept (1 masked, 2 full)       */
     double gather_ms[2];          /* per iteration at the best grid sizes with
                                      masked / full gathers (0: not timed)      */
@@ -461,7 +461,7 @@ typedef struct {
                                      the best launch otherwise (0: not timed)  */
 } kdss_tune_result;
 
-/* Sets the grid sizes (leaf-credit 1..2048, heavy-leaf 1..16384 workgroups) used by later runs. */
+/* Sets the grid sizes (leaf-credit 1..8192, heavy-leaf 1..16384 workgroups) used by later runs. */
 int kdss_plan_set_launch(kdss_plan *p, uint32_t leaf_blocks, uint32_t heavy_blocks);
 
 /* Times `iters` iterations after `warm` untimed ones (from zero loads) for each

@@ -124,7 +124,7 @@ constexpr uint32_t kHeavyBinomLds = 1024;        // ... in the heavy-leaf pass (
 constexpr uint32_t kHotMax = 512;
 constexpr uint32_t kHotMinOccurrences = 32;
 constexpr uint32_t kHotFlag = 0x80000000u;
-constexpr uint32_t kLeafBlocksMax = 2048;        // persistent leaf-credit grid, largest
+constexpr uint32_t kLeafBlocksMax = 8192;        // leaf-credit grid, largest (2048 stay resident)
 constexpr uint32_t kLeafBlocksDefault = 2048;    // eight workgroups per CU
 constexpr uint32_t kHeavyBlocks = 16384;         // largest grid of the heavy-leaf kernel
 constexpr uint32_t kHeavyBlocksDefault = 2048;   // its grid until set or tuned

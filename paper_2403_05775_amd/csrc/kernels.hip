@@ -541,8 +541,10 @@ __device__ __forceinline__ void tile_big(const Tile& t, const uint32_t* __restri
   }
 }
 
-// Persistent grid: wave w of the grid takes tiles w, w + 4 * gridDim.x, ...
-// Each workgroup adds its nonzero hot-node credit totals into one of
+// Strided grid: wave w of the grid takes tiles w, w + 4 * gridDim.x, ...
+// (grids larger than the 2048 workgroups that stay resident shorten each
+// wave's walk, and workgroups that start as others finish even out the
+// tail).  Each workgroup adds its nonzero hot-node credit totals into one of
 // kHotSlots scratch rows (row blockIdx.x % kHotSlots).
 // Eight wavefronts per SIMD (<= 64 VGPRs, 18 KB of LDS per workgroup): the
 // pass is latency-bound, and occupancy hides more of it than wider row
@@ -2713,7 +2715,7 @@ int kdss_plan_set_timing(kdss_plan* P, int on) {
 int kdss_plan_set_launch(kdss_plan* P, uint32_t leaf_blocks, uint32_t heavy_blocks) {
   if (!P) return fail(KDSS_EINVAL, "null argument");
   if (leaf_blocks == 0 || leaf_blocks > kLeafBlocksMax || heavy_blocks == 0 || heavy_blocks > kHeavyBlocks)
-    return fail(KDSS_ERANGE, "grid sizes must be in 1..2048 (leaf) and 1..16384 (heavy)");
+    return fail(KDSS_ERANGE, "grid sizes must be in 1..8192 (leaf) and 1..16384 (heavy)");
   if (P->leaf_blocks != leaf_blocks || P->heavy_blocks != heavy_blocks) drop_graph(P);
   P->leaf_blocks = leaf_blocks;
   P->heavy_blocks = heavy_blocks;
@@ -2734,7 +2736,9 @@ int kdss_plan_autotune(kdss_plan* P, void* d_ws, size_t ws_bytes, uint64_t* d_r,
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "event create");
   HIP_TRY(hipEventCreate(&e1), "event create");
-  const uint32_t leaf_c[] = {512, 1024, 1536, 1792, 2048};
+  // leaf grids beyond the 2048 workgroups that stay resident balance the
+  // strided tile walk's tail the same way
+  const uint32_t leaf_c[] = {512, 1024, 1536, 1792, 2048, 4096, 8192};
   // heavy grids beyond what stays resident let the dispatcher balance the
   // queue's tail: new workgroups start as others finish
   const uint32_t heavy_c[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
